@@ -1,0 +1,117 @@
+/*
+ * CPU oracle for unidirectional Monte Carlo path tracing of triangle scenes.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the slow, plain reference that the HIP
+ * renderer is checked against.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark load it.  It shares no code with the HIP
+ * library.
+ *
+ * What it computes (paper, Sec. 2.1-2.2, Eq. 1-3 and the five-step forward
+ * path-tracing loop): for every requested pixel p the estimator
+ *     I(p) = (1/spp) * sum_{s<spp} L(p, s)
+ * where L(p, s) is one camera path traced vertex by vertex: extend by the
+ * closest hit, add emitted radiance times the path throughput, sample a new
+ * direction and multiply the throughput by f |n . w| / p.  Next-event
+ * estimation with the power heuristic and Russian roulette are options.  All
+ * random numbers come from a counter-based Philox4x64-10 generator keyed by
+ * (pixel, sample, bounce, job), so any path can be replayed exactly.
+ *
+ * Precision: the path arithmetic is IEEE binary32 with no contraction
+ * (compiled with -ffp-contract=off), so every decision taken on a float
+ * (closest hit, light pick, roulette, lobe) is taken in the renderer's
+ * precision.  Gradients (orc_backward) are accumulated in binary64.
+ */
+#ifndef PTMI_ORACLE_H
+#define PTMI_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct orc_scene orc_scene;
+
+/* Material types of the material table (type, roughness, ior, unused). */
+enum { ORC_LAMBERT = 0, ORC_CONDUCTOR = 1, ORC_DIELECTRIC = 2 };
+
+/* Build a scene from indexed triangles.  Arrays are copied.  build_bvh != 0
+ * also builds the oracle's own binary BVH (object-median splits).
+ * Returns NULL on invalid input (out-of-range index, non-finite value). */
+orc_scene* orc_scene_create(int32_t nv, const float* pos, int32_t nt, const int32_t* idx,
+                            const int32_t* tri_mat, int32_t nm, const float* mats,
+                            const float* albedo, const float* emission, const float* sky,
+                            int32_t build_bvh);
+void orc_scene_destroy(orc_scene* s);
+/* Replace albedo / emission (nt*3 each).  The light set stays the one fixed
+ * at creation (triangles with some emission channel > 0). */
+void orc_scene_set_params(orc_scene* s, const float* albedo, const float* emission);
+int32_t orc_scene_num_lights(const orc_scene* s);
+/* BVH statistics: node count and maximum depth (0 if no BVH). */
+void orc_scene_bvh_stats(const orc_scene* s, int32_t* nodes, int32_t* depth);
+
+/* Pinhole camera constants: out = E[3], R[3], U[3], F[3] (binary32). */
+void orc_camera(const double eye[3], const double target[3], const double up[3],
+                double vfov_deg, int32_t width, int32_t height, float out[12]);
+
+/* Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC 2011). */
+void orc_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+
+/* Render the listed pixels.  out: n*3 floats, the per-pixel mean over spp.
+ * fragile (may be NULL): n bytes, nonzero where some decision along one of
+ * the pixel's paths was within rounding distance of flipping.
+ * per_sample (may be NULL): n*spp*3 floats, L of each sample.
+ * use_bvh: 0 = brute force, 1 = oracle BVH.  rr_start < 0 disables roulette.
+ * Returns 0 or a negative error code. */
+int32_t orc_render(const orc_scene* s, const float cam[12], int32_t width, int32_t height,
+                   const int32_t* pixels, int32_t n, int32_t spp, int32_t max_depth,
+                   uint64_t seed, uint32_t frame, uint32_t job, int32_t nee, int32_t rr_start,
+                   int32_t use_bvh, int32_t threads, float* out, uint8_t* fragile,
+                   float* per_sample);
+
+/* Gradient of sum_p sum_c d_image[p,c] * I(p,c) with respect to per-triangle
+ * albedo and emission, for the fixed-sample estimator (same seed/frame).
+ * Binary64 accumulation; outputs are overwritten (nt*3 each).  abs_* (may be
+ * NULL) receive the sum of absolute values of the individual terms.
+ * Roulette must be off (its survival probability depends on albedo). */
+int32_t orc_backward(const orc_scene* s, const float cam[12], int32_t width, int32_t height,
+                     const int32_t* pixels, int32_t n, int32_t spp, int32_t max_depth,
+                     uint64_t seed, uint32_t frame, uint32_t job, int32_t nee, int32_t use_bvh,
+                     int32_t threads, const float* d_image, double* g_albedo,
+                     double* g_emission, double* abs_albedo, double* abs_emission);
+
+/* Closest hit (mode 0 brute force, 1 BVH) for n rays o[3n], d[3n] with
+ * t in (0, tmax).  prim = -1 on a miss. */
+int32_t orc_closest(const orc_scene* s, int32_t n, const float* o, const float* d, float tmax,
+                    int32_t mode, float* t, int32_t* prim, float* b1, float* b2);
+/* Any hit in (0, tmax): occluded[i] = 0/1. */
+int32_t orc_anyhit(const orc_scene* s, int32_t n, const float* o, const float* d, float tmax,
+                   int32_t mode, uint8_t* occluded);
+
+/* Single-triangle watertight test (for pins): returns 1 on a hit. */
+int32_t orc_tri_test(const float o[3], const float d[3], const float v0[3], const float v1[3],
+                     const float v2[3], float* t, float* b1, float* b2);
+
+/* BSDF pieces, for pins.  n is the unit surface normal on the side of wo
+ * (for the dielectric: the outside normal).  eval writes f[3] and *pdf
+ * (solid angle).  sample writes wi, the weight f|n.wi|/pdf and *pdf and
+ * returns 0 when the sample is rejected. */
+void orc_bsdf_eval(int32_t type, float rough, const float alb[3], const float n[3],
+                   const float wo[3], const float wi[3], float f[3], float* pdf);
+int32_t orc_bsdf_sample(int32_t type, float rough, float ior, const float alb[3],
+                        const float n[3], const float wo[3], float u4, float u5, float u6,
+                        float wi[3], float weight[3], float* pdf);
+
+/* Uniform point on a triangle from (u1, u2); out = point. */
+void orc_sample_triangle(const float v0[3], const float v1[3], const float v2[3], float u1,
+                         float u2, float out[3]);
+/* Self-intersection offset of p along n. */
+void orc_offset(const float p[3], const float n[3], float out[3]);
+/* Light pick: index of the light chosen by raw word w (-1 if no lights). */
+int32_t orc_pick_light(const orc_scene* s, uint32_t w);
+/* u32 -> [0,1) conversion used for every uniform variate. */
+float orc_unif(uint32_t w);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

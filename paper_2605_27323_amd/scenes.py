@@ -1,0 +1,379 @@
+"""Seeded synthetic scene and camera generators.
+
+This module only produces input arrays (geometry, per-triangle parameters,
+material table, camera).  It holds none of the rendering arithmetic, so both
+the HIP renderer and the CPU oracle can be fed from it.
+
+A scene is a dict of NumPy arrays:
+    positions  float32 [nv, 3]
+    indices    int32   [nt, 3]   counter-clockwise (v0, v1, v2) = front side
+    tri_mat    int32   [nt]      index into ``materials``
+    materials  float32 [nm, 4]   (type, roughness, ior, 0)
+    albedo     float32 [nt, 3]
+    emission   float32 [nt, 3]   one-sided, front face only
+    sky        float32 [3]       constant radiance of escaped rays
+A camera is a dict {eye, target, up, vfov_deg, width, height}.
+
+The paper's own benchmark asset is not available; the procedural scenes
+below stand in for it with the sizes and material mix of the workloads
+(icospheres and tessellated boxes on a ground plane under quad lights).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+LAMBERT = 0
+CONDUCTOR = 1
+DIELECTRIC = 2
+
+
+def _pack(pos_list, idx_list, mat_list, alb_list, emi_list, materials, sky=(0.0, 0.0, 0.0)):
+    offs = 0
+    idx_all = []
+    for p, i in zip(pos_list, idx_list):
+        idx_all.append(i + offs)
+        offs += p.shape[0]
+    return {
+        "positions": np.ascontiguousarray(np.concatenate(pos_list).astype(np.float32)),
+        "indices": np.ascontiguousarray(np.concatenate(idx_all).astype(np.int32)),
+        "tri_mat": np.ascontiguousarray(np.concatenate(mat_list).astype(np.int32)),
+        "materials": np.ascontiguousarray(np.asarray(materials, dtype=np.float32).reshape(-1, 4)),
+        "albedo": np.ascontiguousarray(np.concatenate(alb_list).astype(np.float32)),
+        "emission": np.ascontiguousarray(np.concatenate(emi_list).astype(np.float32)),
+        "sky": np.asarray(sky, dtype=np.float32),
+    }
+
+
+def quad(p0, p1, p2, p3):
+    """Two triangles (p0,p1,p2), (p0,p2,p3); front side given by CCW order."""
+    pos = np.array([p0, p1, p2, p3], dtype=np.float64)
+    idx = np.array([[0, 1, 2], [0, 2, 3]], dtype=np.int32)
+    return pos, idx
+
+
+def box_mesh(lo, hi, n=1, outward=True):
+    """Axis-aligned box with an n x n grid of quads per face (12 n^2 triangles).
+
+    Vertices live on one (n+1)^3 lattice so that shared edges use the very same
+    coordinates (needed for a watertight mesh)."""
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    g = np.arange(n + 1, dtype=np.float64) / n
+    coords = [lo[a] + (hi[a] - lo[a]) * g for a in range(3)]
+    for a in range(3):
+        coords[a][0], coords[a][-1] = lo[a], hi[a]
+
+    def vid(i, j, k):
+        return (i * (n + 1) + j) * (n + 1) + k
+
+    X, Y, Z = np.meshgrid(coords[0], coords[1], coords[2], indexing="ij")
+    lattice = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    tris = []
+    r = np.arange(n)
+    A, B = np.meshgrid(r, r, indexing="ij")
+    A = A.ravel()
+    B = B.ravel()
+    # for each face: fixed axis, fixed side, and the two varying axes (u, v)
+    # chosen so that u x v points along the outward normal.
+    faces = [
+        (0, 0, 2, 1), (0, n, 1, 2),
+        (1, 0, 0, 2), (1, n, 2, 0),
+        (2, 0, 1, 0), (2, n, 0, 1),
+    ]
+    for axis, side, ua, va in faces:
+        def idx3(a, b):
+            ijk = [None, None, None]
+            ijk[axis] = np.full_like(a, side)
+            ijk[ua] = a
+            ijk[va] = b
+            return vid(ijk[0], ijk[1], ijk[2])
+        q0 = idx3(A, B)
+        q1 = idx3(A + 1, B)
+        q2 = idx3(A + 1, B + 1)
+        q3 = idx3(A, B + 1)
+        t1 = np.stack([q0, q1, q2], axis=1)
+        t2 = np.stack([q0, q2, q3], axis=1)
+        tris.append(np.concatenate([t1, t2]))
+    idx = np.concatenate(tris).astype(np.int64)
+    # compact the lattice to used vertices
+    used, inv = np.unique(idx.ravel(), return_inverse=True)
+    pos = lattice[used]
+    idx = inv.reshape(-1, 3).astype(np.int32)
+    # orient: make every normal point away from the centre (or towards it)
+    c = 0.5 * (lo + hi)
+    v0, v1, v2 = pos[idx[:, 0]], pos[idx[:, 1]], pos[idx[:, 2]]
+    nrm = np.cross(v1 - v0, v2 - v0)
+    ctr = (v0 + v1 + v2) / 3.0 - c
+    flip = (np.einsum("ij,ij->i", nrm, ctr) < 0) == outward
+    idx[flip] = idx[flip][:, [0, 2, 1]]
+    return pos, idx
+
+
+_ICO_CACHE: dict = {}
+
+
+def icosphere_unit(level):
+    """Unit icosphere; level 1 = icosahedron (20 faces), each level x4 faces."""
+    if level in _ICO_CACHE:
+        return _ICO_CACHE[level]
+    t = (1.0 + 5.0 ** 0.5) / 2.0
+    v = np.array([[-1, t, 0], [1, t, 0], [-1, -t, 0], [1, -t, 0],
+                  [0, -1, t], [0, 1, t], [0, -1, -t], [0, 1, -t],
+                  [t, 0, -1], [t, 0, 1], [-t, 0, -1], [-t, 0, 1]], dtype=np.float64)
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    f = np.array([[0, 11, 5], [0, 5, 1], [0, 1, 7], [0, 7, 10], [0, 10, 11],
+                  [1, 5, 9], [5, 11, 4], [11, 10, 2], [10, 7, 6], [7, 1, 8],
+                  [3, 9, 4], [3, 4, 2], [3, 2, 6], [3, 6, 8], [3, 8, 9],
+                  [4, 9, 5], [2, 4, 11], [6, 2, 10], [8, 6, 7], [9, 8, 1]], dtype=np.int64)
+    for _ in range(level - 1):
+        e = np.concatenate([f[:, [0, 1]], f[:, [1, 2]], f[:, [2, 0]]])
+        e.sort(axis=1)
+        ue, inv = np.unique(e, axis=0, return_inverse=True)
+        inv = inv.ravel()
+        mid = v[ue[:, 0]] + v[ue[:, 1]]
+        mid /= np.linalg.norm(mid, axis=1, keepdims=True)
+        base = v.shape[0]
+        v = np.concatenate([v, mid])
+        nf = f.shape[0]
+        a = base + inv[:nf]
+        b = base + inv[nf:2 * nf]
+        c = base + inv[2 * nf:]
+        f = np.concatenate([
+            np.stack([f[:, 0], a, c], 1), np.stack([f[:, 1], b, a], 1),
+            np.stack([f[:, 2], c, b], 1), np.stack([a, b, c], 1)])
+    # outward orientation check
+    v0, v1, v2 = v[f[:, 0]], v[f[:, 1]], v[f[:, 2]]
+    n = np.cross(v1 - v0, v2 - v0)
+    flip = np.einsum("ij,ij->i", n, v0 + v1 + v2) < 0
+    f[flip] = f[flip][:, [0, 2, 1]]
+    _ICO_CACHE[level] = (v, f.astype(np.int32))
+    return _ICO_CACHE[level]
+
+
+def _tri_params(nt, alb, emi, mat):
+    return (np.repeat(np.asarray(mat, np.int32)[None], nt, 0).reshape(nt),
+            np.repeat(np.asarray(alb, np.float64)[None], nt, 0),
+            np.repeat(np.asarray(emi, np.float64)[None], nt, 0))
+
+
+# --------------------------------------------------------------------------
+# Cornell-style room: 5 walls, two boxes, one quad light (36 triangles)
+# --------------------------------------------------------------------------
+def cornell():
+    white = (0.73, 0.73, 0.73)
+    red = (0.63, 0.06, 0.05)
+    green = (0.14, 0.45, 0.09)
+    P, I, M, A, E = [], [], [], [], []
+
+    def add(pos, idx, alb, emi=(0, 0, 0), mat=0):
+        P.append(pos)
+        I.append(idx)
+        m, a, e = _tri_params(idx.shape[0], alb, emi, mat)
+        M.append(m)
+        A.append(a)
+        E.append(e)
+
+    # floor y=0 facing +y, ceiling y=2 facing -y, back wall z=-1 facing +z
+    add(*quad((-1, 0, -1), (-1, 0, 1), (1, 0, 1), (1, 0, -1)), white)
+    add(*quad((-1, 2, -1), (1, 2, -1), (1, 2, 1), (-1, 2, 1)), white)
+    add(*quad((-1, 0, -1), (1, 0, -1), (1, 2, -1), (-1, 2, -1)), white)
+    # left wall x=-1 facing +x (red), right wall x=+1 facing -x (green)
+    add(*quad((-1, 0, -1), (-1, 2, -1), (-1, 2, 1), (-1, 0, 1)), red)
+    add(*quad((1, 0, -1), (1, 0, 1), (1, 2, 1), (1, 2, -1)), green)
+    add(*box_mesh((-0.7, 0.0, -0.7), (-0.1, 1.2, -0.1), 1), white)
+    add(*box_mesh((0.1, 0.0, -0.2), (0.7, 0.6, 0.4), 1), white)
+    # light at y=1.999 facing -y
+    add(*quad((-0.25, 1.999, -0.25), (0.25, 1.999, -0.25), (0.25, 1.999, 0.25), (-0.25, 1.999, 0.25)),
+        (0.0, 0.0, 0.0), (15.0, 15.0, 15.0))
+    scene = _pack(P, I, M, A, E, [(LAMBERT, 1.0, 1.5, 0.0)])
+    cam = dict(eye=(0.0, 1.0, 3.6), target=(0.0, 1.0, 0.0), up=(0.0, 1.0, 0.0),
+               vfov_deg=40.0, width=128, height=128)
+    return scene, cam
+
+
+def furnace(albedo=0.5, le=1.0, n=2, width=16, height=16):
+    """Closed cube [-1,1]^3 with inward-facing triangles, every triangle
+    Lambertian with the same albedo and the same inward emission; camera at
+    the centre."""
+    pos, idx = box_mesh((-1, -1, -1), (1, 1, 1), n, outward=False)
+    m, a, e = _tri_params(idx.shape[0], (albedo,) * 3, (le,) * 3, 0)
+    scene = _pack([pos], [idx], [m], [a], [e], [(LAMBERT, 1.0, 1.5, 0.0)])
+    cam = dict(eye=(0.0, 0.0, 0.0), target=(0.3, 0.2, 1.0), up=(0.0, 1.0, 0.0),
+               vfov_deg=90.0, width=width, height=height)
+    return scene, cam
+
+
+def plane_under_sky(albedo=0.6, sky=1.0, half=1.0, width=16, height=16, height_cam=3.0):
+    """Two-triangle square at y=0 facing +y under a constant sky; camera above
+    looking straight down (the square fills only part of the view)."""
+    pos, idx = quad((-half, 0, -half), (-half, 0, half), (half, 0, half), (half, 0, -half))
+    m, a, e = _tri_params(2, (albedo,) * 3, (0, 0, 0), 0)
+    scene = _pack([pos], [idx], [m], [a], [e], [(LAMBERT, 1.0, 1.5, 0.0)], sky=(sky,) * 3)
+    cam = dict(eye=(0.0, height_cam, 0.0), target=(0.0, 0.0, 0.0), up=(0.0, 0.0, 1.0),
+               vfov_deg=60.0, width=width, height=height)
+    return scene, cam
+
+
+def plane_under_light(albedo=0.5, le=4.0, light_half=0.5, light_h=1.0, half=4.0,
+                      width=16, height=16):
+    """Diffuse square at y=0 under one downward-facing quad light (for the
+    polygon-irradiance closed form)."""
+    p0, i0 = quad((-half, 0, -half), (-half, 0, half), (half, 0, half), (half, 0, -half))
+    s = light_half
+    p1, i1 = quad((-s, light_h, -s), (s, light_h, -s), (s, light_h, s), (-s, light_h, s))
+    m0, a0, e0 = _tri_params(2, (albedo,) * 3, (0, 0, 0), 0)
+    m1, a1, e1 = _tri_params(2, (0, 0, 0), (le,) * 3, 0)
+    scene = _pack([p0, p1], [i0, i1], [m0, m1], [a0, a1], [e0, e1], [(LAMBERT, 1.0, 1.5, 0.0)])
+    cam = dict(eye=(0.0, 0.5, -3.0), target=(0.0, 0.0, 0.0), up=(0.0, 1.0, 0.0),
+               vfov_deg=45.0, width=width, height=height)
+    return scene, cam
+
+
+# --------------------------------------------------------------------------
+# Procedural scenes: icospheres + tessellated boxes on a ground plane
+# --------------------------------------------------------------------------
+def procedural(seed=2, n_objects=2000, width=1920, height=1080, material_mode="lambert_conductor",
+               n_material_ids=64, ground_albedo=0.5, light_le=20.0):
+    """Half icospheres (level 3 or 4: 320 or 1280 faces), half boxes with an
+    n x n grid per face (n in {3,4,5}: 108..300 triangles): expected
+    1000 triangles per object on average.  Centres uniform in
+    [-50,50] x [0,100] x [-50,50], scale log-uniform in [0.1, 5], a 400 x 400
+    ground quad at y = 0 and 16 downward 10 x 10 quad lights at y = 120.
+
+    material_mode:
+      "lambert_conductor": per mesh, 50% Lambertian (albedo U[0.1,0.9]^3),
+          50% GGX conductor (F0 U[0.1,0.9]^3, roughness U[0.05,0.8]).
+      "divergence": per mesh one of ``n_material_ids`` ids drawn uniformly;
+          ids in the first quarter are Lambertian, second conductor, third
+          rough dielectric (ior U[1.3,1.8]), last quarter emissive Lambertian
+          (albedo 0, emission 5 * U[0.2,1]^3).
+    """
+    rng = np.random.default_rng(seed)
+    n_ico = n_objects // 2
+    n_box = n_objects - n_ico
+    P, I, M, A, E = [], [], [], [], []
+    materials = [(LAMBERT, 1.0, 1.5, 0.0)]  # material 0: ground and lights
+
+    if material_mode == "divergence":
+        q = n_material_ids // 4
+        mat_alb = rng.uniform(0.1, 0.9, size=(n_material_ids, 3))
+        mat_emi = np.zeros((n_material_ids, 3))
+        for mid in range(n_material_ids):
+            if mid < q:
+                materials.append((LAMBERT, 1.0, 1.5, 0.0))
+            elif mid < 2 * q:
+                materials.append((CONDUCTOR, float(rng.uniform(0.05, 0.8)), 1.5, 0.0))
+            elif mid < 3 * q:
+                materials.append((DIELECTRIC, float(rng.uniform(0.05, 0.8)), float(rng.uniform(1.3, 1.8)), 0.0))
+            else:
+                materials.append((LAMBERT, 1.0, 1.5, 0.0))
+                mat_alb[mid] = 0.0
+                mat_emi[mid] = 5.0 * rng.uniform(0.2, 1.0, size=3)
+
+    def obj_material():
+        if material_mode == "divergence":
+            mid = int(rng.integers(0, n_material_ids))
+            return mid + 1, mat_alb[mid], mat_emi[mid]
+        if rng.uniform() < 0.5:
+            alb = rng.uniform(0.1, 0.9, size=3)
+            return 0, alb, np.zeros(3)
+        alb = rng.uniform(0.1, 0.9, size=3)
+        rough = float(rng.uniform(0.05, 0.8))
+        materials.append((CONDUCTOR, rough, 1.5, 0.0))
+        return len(materials) - 1, alb, np.zeros(3)
+
+    centres = np.stack([rng.uniform(-50, 50, n_objects), rng.uniform(0, 100, n_objects),
+                        rng.uniform(-50, 50, n_objects)], 1)
+    scales = np.exp(rng.uniform(np.log(0.1), np.log(5.0), n_objects))
+    kinds = np.array([0] * n_ico + [1] * n_box)
+    rng.shuffle(kinds)
+    for o in range(n_objects):
+        c = centres[o]
+        s = scales[o]
+        if kinds[o] == 0:
+            lvl = int(rng.integers(3, 5))
+            up, ui = icosphere_unit(lvl)
+            pos = c + s * up
+            idx = ui
+        else:
+            n = int(rng.integers(3, 6))
+            ext = s * rng.uniform(0.5, 1.0, size=3)
+            pos, idx = box_mesh(c - ext, c + ext, n)
+        mat, alb, emi = obj_material()
+        P.append(pos)
+        I.append(idx)
+        m, a, e = _tri_params(idx.shape[0], alb, emi, mat)
+        M.append(m)
+        A.append(a)
+        E.append(e)
+
+    # ground
+    gp, gi = quad((-200, 0, -200), (-200, 0, 200), (200, 0, 200), (200, 0, -200))
+    m, a, e = _tri_params(2, (ground_albedo,) * 3, (0, 0, 0), 0)
+    P.append(gp); I.append(gi); M.append(m); A.append(a); E.append(e)
+    # 16 lights: 4 x 4 grid of 10 x 10 quads over [-45,45]^2 at y=120, facing -y
+    for gx in np.linspace(-45, 45, 4):
+        for gz in np.linspace(-45, 45, 4):
+            lp, li = quad((gx - 5, 120, gz - 5), (gx + 5, 120, gz - 5), (gx + 5, 120, gz + 5), (gx - 5, 120, gz + 5))
+            m, a, e = _tri_params(2, (0, 0, 0), (light_le,) * 3, 0)
+            P.append(lp); I.append(li); M.append(m); A.append(a); E.append(e)
+    scene = _pack(P, I, M, A, E, materials)
+    cam = dict(eye=(0.0, 50.0, -130.0), target=(0.0, 40.0, 0.0), up=(0.0, 1.0, 0.0),
+               vfov_deg=50.0, width=width, height=height)
+    return scene, cam
+
+
+def random_soup(seed, n_tris, extent=1.0, emissive_frac=0.1, materials=None):
+    """Random triangle soup in [-extent, extent]^3 (tiny scenes for
+    intersection and parity tests), with shared edges from a small vertex
+    pool so that edge and vertex hits occur."""
+    rng = np.random.default_rng(seed)
+    nv = max(3, n_tris // 2 + 3)
+    pos = rng.uniform(-extent, extent, size=(nv, 3))
+    # snap some coordinates onto a coarse grid to create axis-aligned and
+    # coplanar configurations
+    snap = rng.uniform(size=pos.shape) < 0.3
+    pos[snap] = np.round(pos[snap] * 4) / 4
+    idx = np.empty((n_tris, 3), np.int32)
+    for t in range(n_tris):
+        idx[t] = rng.choice(nv, 3, replace=False)
+    mats = materials if materials is not None else [(LAMBERT, 1.0, 1.5, 0.0)]
+    tri_mat = rng.integers(0, len(mats), n_tris).astype(np.int32)
+    alb = rng.uniform(0.1, 0.9, size=(n_tris, 3))
+    emi = np.zeros((n_tris, 3))
+    ne = int(round(emissive_frac * n_tris))
+    if ne:
+        sel = rng.choice(n_tris, ne, replace=False)
+        emi[sel] = rng.uniform(0.5, 5.0, size=(ne, 3))
+    return _pack([pos], [idx], [tri_mat], [alb], [emi], mats)
+
+
+def batch_jobs(seed=4, n_jobs=64, tri_lo=1e4, tri_hi=2e6):
+    """Job list of the batched workload: per job a scene seed, a triangle
+    count T drawn log-uniform in [tri_lo, tri_hi] (objects = T / 1000 with the
+    procedural mix), a resolution from {256^2, 512^2, 1024^2, 1920x1080} and
+    1..8 spp."""
+    rng = np.random.default_rng(seed)
+    res = [(256, 256), (512, 512), (1024, 1024), (1920, 1080)]
+    jobs = []
+    for j in range(n_jobs):
+        t = float(np.exp(rng.uniform(np.log(tri_lo), np.log(tri_hi))))
+        w, h = res[int(rng.integers(0, 4))]
+        spp = int(rng.integers(1, 9))
+        jobs.append(dict(scene_seed=1000 + j, n_objects=max(2, int(round(t / 1000.0))),
+                         width=w, height=h, spp=spp))
+    return jobs
+
+
+def perturb_albedo(albedo, seed=5, sigma=0.05, lo=0.02, hi=0.95):
+    """Per-triangle albedo + N(0, sigma), clipped to [lo, hi]."""
+    rng = np.random.default_rng(seed)
+    out = albedo.astype(np.float64) + rng.normal(0.0, sigma, size=albedo.shape)
+    return np.clip(out, lo, hi).astype(np.float32)
+
+
+def pixel_subset(width, height, n, seed=1234):
+    """Sorted seeded subset of pixel ids (py * width + px)."""
+    rng = np.random.default_rng(seed)
+    n = min(n, width * height)
+    return np.sort(rng.choice(width * height, n, replace=False)).astype(np.int32)
