@@ -1,0 +1,216 @@
+/*
+ * ptmi: megakernel and wavefront Monte Carlo path tracing of triangle
+ * scenes on AMD Instinct MI355X (gfx950), as a C-ABI shared library.
+ *
+ * What is computed (paper Sec. 2.1-2.3, Eq. 1-3): for every pixel p of a
+ * W x H pinhole camera, the estimator
+ *     I(p) = (1/spp) * sum_{s<spp} L(p, s)
+ * of the light transport equation, where L(p, s) is one camera path traced
+ * vertex by vertex (extend to the closest hit, add emitted radiance times
+ * the throughput, sample a new direction and update the throughput, up to
+ * max_depth scattering vertices).  Next-event estimation with the power
+ * heuristic and Russian roulette are options.  Random numbers come from
+ * Philox4x64-10 keyed by (pixel, frame * spp + s, bounce, job) under key
+ * (seed, 0), so a path can be replayed exactly (the adjoint relies on it).
+ *
+ * Two schedules compute bit-identical images (paper Sec. 2.2-2.3, 3.1):
+ *   PT_MODE_MEGA  one kernel; each thread traces its pixel's paths to the end.
+ *   PT_MODE_WAVE  per bounce, separate extend / shade / shadow kernels over
+ *                 structure-of-arrays path state in device memory, with the
+ *                 live paths compacted into a queue after every bounce.
+ *
+ * Conventions
+ *   - Every call returns a pt_status; 0 is success.  pt_last_error() gives
+ *     a message for the calling thread.  No C++ exception crosses the ABI.
+ *   - Host arrays passed in are copied; the caller keeps ownership.
+ *   - All device memory is owned by the caller and passed as plain device
+ *     pointers (for example from torch tensors); the library never
+ *     allocates device memory.  Work is enqueued on the caller's HIP stream
+ *     (a hipStream_t passed as void*; NULL = the null stream) and is
+ *     asynchronous unless stated otherwise.
+ *   - Asynchronous device errors surface at the next call or at pt_sync.
+ *   - A context may be used by one host thread at a time.
+ */
+#ifndef PTMI_H
+#define PTMI_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pt_status;
+enum {
+    PT_OK = 0,
+    PT_EINVAL = -1,      /* bad argument */
+    PT_ENOMEM = -2,      /* buffer or workspace too small */
+    PT_EHIP = -3,        /* HIP runtime error or no GPU */
+    PT_ESTATE = -4,      /* wrong call order (e.g. render before bind) */
+    PT_EOVERFLOW = -5,   /* a device-side capacity was exceeded */
+    PT_EUNSUPPORTED = -6 /* option not supported */
+};
+
+enum { PT_LAMBERT = 0, PT_CONDUCTOR = 1, PT_DIELECTRIC = 2 };
+enum { PT_MODE_MEGA = 0, PT_MODE_WAVE = 1 };
+
+/* Render flags (pt_render_args.flags). */
+enum {
+    PT_FLAG_PROFILE = 1,       /* time every stage launch with HIP events */
+    PT_FLAG_NO_COMPACT = 2,    /* wavefront: no compaction, dispatch every path each bounce */
+    PT_FLAG_SORT_MATERIAL = 4, /* wavefront: counting-sort each shade queue by material type */
+    PT_FLAG_COUNT_RAYS = 8     /* keep per-bounce queue counts readable via pt_frame_stats */
+};
+
+typedef struct pt_ctx pt_ctx;
+
+/* Triangle scene (paper Sec. 3: scene data packed on the CPU).
+ * positions  float[nv*3]; indices int32[nt*3], counter-clockwise (v0,v1,v2)
+ * faces the front; tri_material int32[nt] indexes materials float[nm*4]
+ * = (type, roughness, ior, unused); albedo and emission float[nt*3] per
+ * triangle (emission is one-sided, front face only); sky float[3] is the
+ * radiance of escaped rays.  Triangles with some emission channel > 0 at
+ * load time form the fixed light set of next-event estimation (picked in
+ * proportion to area).  Non-finite values or out-of-range indices give
+ * PT_EINVAL. */
+typedef struct {
+    int32_t nv, nt, nm;
+    const float* positions;
+    const int32_t* indices;
+    const int32_t* tri_material;
+    const float* materials;
+    const float* albedo;
+    const float* emission;
+    float sky[3];
+} pt_scene_desc;
+
+/* BVH build options (NULL = defaults). */
+typedef struct {
+    int32_t max_leaf;  /* triangles per leaf, 1..8 (default 4) */
+    int32_t threads;   /* host threads for the build (0 = hardware concurrency) */
+} pt_bvh_opts;
+
+/* Filled by pt_build_bvh: sizes of the device buffers of pt_scene_buffers. */
+typedef struct {
+    int64_t node_count, node_bytes;  /* BVH4 nodes, 128 B each */
+    int64_t tri_bytes;               /* 48 B per triangle, leaf order */
+    int64_t light_count, light_bytes;/* 8 B per light (index + CDF word) */
+    int64_t material_bytes;          /* 16 B per material */
+    int32_t depth;                   /* BVH4 levels */
+    int32_t stack_entries;           /* traversal stack entries needed */
+    double build_seconds;
+} pt_bvh_info;
+
+/* Caller-allocated device buffers, each at least the size pt_build_bvh
+ * reported and 256-byte aligned.  nodes/tris/lights/materials are written
+ * by pt_bind_scene (upload on the stream).  albedo and emission are
+ * float[nt*3] device arrays in input triangle order that the kernels read
+ * at every render: they are the differentiable parameters; pt_bind_scene
+ * fills them from the loaded scene when upload_params != 0. */
+typedef struct {
+    void* nodes;
+    void* tris;
+    void* lights;
+    void* materials;
+    float* albedo;
+    float* emission;
+    int32_t upload_params;
+} pt_scene_buffers;
+
+/* Pinhole camera: eye, target, up, vertical field of view (degrees),
+ * image size.  Row py = 0 is the top of the image. */
+typedef struct {
+    double eye[3], target[3], up[3];
+    double vfov_deg;
+    int32_t width, height;
+} pt_camera;
+
+/* Per-render arguments.  max_depth = number of scattering vertices
+ * (emission found after the last one is still counted); rr_start < 0
+ * disables Russian roulette, else it applies from that vertex on.
+ * block = threads per workgroup (64..256, multiple of 64; 0 = default);
+ * grid_mult = persistent workgroups per compute unit (0 = default). */
+typedef struct {
+    int32_t spp, max_depth;
+    uint64_t seed;
+    uint32_t frame;
+    uint32_t job;
+    int32_t nee, rr_start;
+    int32_t mode;
+    int32_t flags;
+    int32_t block, grid_mult;
+} pt_render_args;
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int32_t pt_version(void);
+/* Message of the last failing call on this thread ("" if none). */
+const char* pt_last_error(void);
+
+/* Create a context on HIP device `device`; device < 0 creates a host-only
+ * context (scene load and BVH build only; rendering returns PT_ESTATE).
+ * PT_EHIP if the device does not exist or HIP is unavailable. */
+pt_status pt_create(pt_ctx** out, int32_t device);
+pt_status pt_destroy(pt_ctx* ctx);
+
+/* Copy and validate the scene (replaces any previous one). */
+pt_status pt_load_scene(pt_ctx* ctx, const pt_scene_desc* scene);
+
+/* CPU build of the acceleration structure (paper Sec. 3 builds BLAS/TLAS
+ * through the driver; here a binned-SAH binary BVH collapsed to a 4-wide
+ * BVH with 128-byte nodes), the leaf-order triangle array and the
+ * area-proportional light CDF.  Synchronous, host only. */
+pt_status pt_build_bvh(pt_ctx* ctx, const pt_bvh_opts* opts, pt_bvh_info* info);
+
+/* Host copies of the built buffers (each may be NULL), sizes as reported. */
+pt_status pt_get_bvh(pt_ctx* ctx, void* nodes, void* tris, void* lights, void* materials);
+
+/* Upload the built buffers into the caller's device buffers on `stream`
+ * and remember the pointers for later renders.  The buffers must stay
+ * allocated while the context renders with them. */
+pt_status pt_bind_scene(pt_ctx* ctx, const pt_scene_buffers* buffers, void* stream);
+
+pt_status pt_set_camera(pt_ctx* ctx, const pt_camera* camera);
+
+/* Device workspace (bytes) a render with these arguments needs, for the
+ * camera currently set: wavefront path state, queues and counters, and
+ * the traversal stack overflow area. */
+pt_status pt_workspace_size(pt_ctx* ctx, const pt_render_args* args, uint64_t* bytes);
+
+/* Render one frame (paper Sec. 2.2 megakernel / Sec. 2.3 wavefront).
+ * image_out: float[H][W][3] device, this frame's per-pixel mean over spp.
+ * accum_inout (may be NULL): float[H][W][3] device running average
+ * (paper Sec. 2.3 accumulation): frame 0 stores the frame, frame n > 0
+ * stores acc + (I - acc) / (n + 1).
+ * workspace: device memory of at least pt_workspace_size bytes. */
+pt_status pt_render_frame(pt_ctx* ctx, const pt_render_args* args, float* image_out,
+                          float* accum_inout, void* workspace, uint64_t workspace_bytes,
+                          void* stream);
+
+/* Path-replay adjoint of one frame: ACCUMULATES (+=) into d_albedo and
+ * d_emission (float[nt*3] device, input triangle order) the gradient of
+ * sum_p sum_c d_image[p][c] * I[p][c] for the fixed-sample estimator defined
+ * by (seed, frame, spp, job).  Each path is replayed twice from its random
+ * numbers (radiance first, then gradients), nothing is stored per path.
+ * PT_EINVAL if Russian roulette is on (its survival probability depends on
+ * the albedo). */
+pt_status pt_render_backward(pt_ctx* ctx, const pt_render_args* args, const float* d_image,
+                             float* d_albedo, float* d_emission, void* workspace,
+                             uint64_t workspace_bytes, void* stream);
+
+/* Statistics of the last frame rendered with PT_FLAG_PROFILE or
+ * PT_FLAG_COUNT_RAYS (synchronises the stream): stage_ms[k] per stage
+ * (0 raygen, 1 extend, 2 shade, 3 shadow, 4 accumulate, 5 megakernel,
+ * 6 sort, 7 adjoint), launches[k], extension and shadow ray counts. */
+typedef struct {
+    double stage_ms[8];
+    int64_t launches[8];
+    int64_t extension_rays, shadow_rays;
+} pt_frame_stats;
+pt_status pt_frame_stats_get(pt_ctx* ctx, pt_frame_stats* stats);
+
+/* Wait for all work the context enqueued on `stream`. */
+pt_status pt_sync(pt_ctx* ctx, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

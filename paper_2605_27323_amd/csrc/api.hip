@@ -1,0 +1,478 @@
+// C-ABI entry points of libptmi (declared in include/ptmi.h).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "bvh_build.h"
+#include "kernels.h"
+
+using namespace ptmi;
+
+namespace {
+
+thread_local std::string g_err;
+
+pt_status fail(pt_status code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+pt_status hip_fail(hipError_t e, const char* what) {
+    return fail(PT_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define PT_HIP(call, what)                            \
+    do {                                              \
+        hipError_t e_ = (call);                       \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+constexpr int kDefaultBlock = 128;
+constexpr int kDefaultGridMult = 8;
+constexpr int kStackLds = 16;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+struct StageTimer {
+    int stage;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct pt_ctx {
+    int device = -1;
+    int num_cu = 256;
+    // scene (host copy)
+    bool loaded = false, built = false, bound = false, cam_set = false;
+    int32_t nt = 0, nm = 0;
+    std::vector<float> tri_v, albedo, emission, mats;
+    std::vector<int32_t> tri_mat;
+    float sky[3] = {0, 0, 0};
+    BuildResult bvh;
+    SceneView view{};
+    CamView cam{};
+    // profiling
+    std::vector<StageTimer> timers;
+    std::vector<hipEvent_t> event_pool;
+    size_t event_next = 0;
+    uint32_t* last_counts = nullptr;  // device counters of the last frame
+    int last_ncounts = 0, last_D = 0, last_mode = 0;
+    bool last_valid = false;
+};
+
+namespace {
+
+int stack_lds_for(const pt_ctx* c) {
+    int need = c->bvh.stack_entries;
+    if (need <= 8) return 8;
+    return kStackLds;
+}
+
+struct Launch {
+    int block, grid;
+    int lds;
+    int gcap;
+    uint32_t nlanes;
+};
+
+pt_status launch_config(const pt_ctx* c, const pt_render_args* a, Launch& L) {
+    L.block = a->block > 0 ? a->block : kDefaultBlock;
+    int mult = a->grid_mult > 0 ? a->grid_mult : kDefaultGridMult;
+    if (L.block < 64 || L.block > 256 || (L.block % 64) != 0) return fail(PT_EINVAL, "block must be a multiple of 64 in [64, 256]");
+    if (mult < 1 || mult > 64) return fail(PT_EINVAL, "grid_mult must be in [1, 64]");
+    L.grid = c->num_cu * mult;
+    L.lds = stack_lds_for(c);
+    L.gcap = std::max(0, c->bvh.stack_entries - L.lds);
+    L.nlanes = (uint32_t)L.grid * (uint32_t)L.block;
+    return PT_OK;
+}
+
+struct WsLayout {
+    size_t counts, ovf, wave[11], total;
+    int ncounts;
+};
+
+// workspace: counters | traversal overflow stack | wavefront state
+WsLayout layout(const pt_ctx* c, const pt_render_args* a, const Launch& L) {
+    WsLayout w{};
+    const size_t npaths = (size_t)c->cam.W * c->cam.H * a->spp;
+    w.ncounts = (a->max_depth + 2) + (a->max_depth + 1) + 4;
+    size_t off = 0;
+    w.counts = off;
+    off = align_up(off + sizeof(uint32_t) * w.ncounts);
+    w.ovf = off;
+    off = align_up(off + sizeof(uint2) * (size_t)L.gcap * L.nlanes);
+    for (int i = 0; i < 11; ++i) {
+        w.wave[i] = off;
+        if (a->mode == PT_MODE_WAVE) off = align_up(off + sizeof(float4) * npaths);
+    }
+    w.total = off;
+    return w;
+}
+
+pt_status check_args(const pt_ctx* c, const pt_render_args* a) {
+    if (!c) return fail(PT_EINVAL, "null context");
+    if (!a) return fail(PT_EINVAL, "null args");
+    if (c->device < 0) return fail(PT_ESTATE, "host-only context cannot render");
+    if (!c->bound) return fail(PT_ESTATE, "scene not bound (pt_bind_scene)");
+    if (!c->cam_set) return fail(PT_ESTATE, "camera not set (pt_set_camera)");
+    if (a->spp < 1 || a->spp > 65536) return fail(PT_EINVAL, "spp must be in [1, 65536]");
+    if (a->max_depth < 0 || a->max_depth > 1000) return fail(PT_EINVAL, "max_depth must be in [0, 1000]");
+    if (a->mode != PT_MODE_MEGA && a->mode != PT_MODE_WAVE) return fail(PT_EINVAL, "unknown mode");
+    const uint64_t npaths = (uint64_t)c->cam.W * c->cam.H * a->spp;
+    if (npaths >= 0xFFFFFFFFull) return fail(PT_EINVAL, "width * height * spp must be < 2^32 - 1");
+    return PT_OK;
+}
+
+hipEvent_t next_event(pt_ctx* c) {
+    if (c->event_next == c->event_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->event_pool.push_back(e);
+    }
+    return c->event_pool[c->event_next++];
+}
+
+// run `fn` (a launch) bracketed by events when profiling
+template <typename F>
+hipError_t timed(pt_ctx* c, bool prof, int stage, hipStream_t s, F fn) {
+    if (!prof) return fn();
+    StageTimer t{stage, next_event(c), next_event(c)};
+    if (!t.a || !t.b) return hipErrorOutOfMemory;
+    (void)hipEventRecord(t.a, s);
+    hipError_t e = fn();
+    (void)hipEventRecord(t.b, s);
+    c->timers.push_back(t);
+    return e;
+}
+
+SceneView make_view(const pt_ctx* c, const pt_scene_buffers* b) {
+    SceneView v{};
+    v.nodes = reinterpret_cast<const float4*>(b->nodes);
+    v.tris = reinterpret_cast<const float4*>(b->tris);
+    v.lights = reinterpret_cast<const LightEntry*>(b->lights);
+    v.mats = reinterpret_cast<const float4*>(b->materials);
+    v.albedo = b->albedo;
+    v.emission = b->emission;
+    v.nl = (int32_t)c->bvh.lights.size();
+    v.nt = c->nt;
+    v.n_nodes = (int32_t)c->bvh.nodes.size();
+    v.area_total = c->bvh.area_total;
+    v.sky0 = c->sky[0];
+    v.sky1 = c->sky[1];
+    v.sky2 = c->sky[2];
+    return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t pt_version(void) { return 10000; }
+
+const char* pt_last_error(void) { return g_err.c_str(); }
+
+pt_status pt_create(pt_ctx** out, int32_t device) {
+    if (!out) return fail(PT_EINVAL, "null output pointer");
+    *out = nullptr;
+    pt_ctx* c = new pt_ctx();
+    if (device >= 0) {
+        int n = 0;
+        hipError_t e = hipGetDeviceCount(&n);
+        if (e != hipSuccess || n == 0) {
+            delete c;
+            return fail(PT_EHIP, std::string("no HIP device: ") + (e != hipSuccess ? hipGetErrorString(e) : "count is 0"));
+        }
+        if (device >= n) {
+            delete c;
+            return fail(PT_EHIP, "device index out of range");
+        }
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, device);
+        if (e != hipSuccess) {
+            delete c;
+            return hip_fail(e, "hipGetDeviceProperties");
+        }
+        c->num_cu = prop.multiProcessorCount;
+        c->device = device;
+    }
+    *out = c;
+    return PT_OK;
+}
+
+pt_status pt_destroy(pt_ctx* c) {
+    if (!c) return PT_OK;
+    if (c->device >= 0) {
+        (void)hipSetDevice(c->device);
+        for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+    }
+    delete c;
+    return PT_OK;
+}
+
+pt_status pt_load_scene(pt_ctx* c, const pt_scene_desc* s) {
+    if (!c || !s) return fail(PT_EINVAL, "null argument");
+    if (s->nv < 0 || s->nt < 0 || s->nm < 1) return fail(PT_EINVAL, "need nv >= 0, nt >= 0, nm >= 1");
+    if (s->nt > 0 && (!s->positions || !s->indices || !s->tri_material || !s->albedo || !s->emission))
+        return fail(PT_EINVAL, "null scene array");
+    if (!s->materials) return fail(PT_EINVAL, "null material table");
+    if ((int64_t)s->nt > kMaxTris) return fail(PT_EINVAL, "too many triangles");
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(s->sky[i])) return fail(PT_EINVAL, "non-finite sky");
+    for (int64_t i = 0; i < 3 * (int64_t)s->nv; ++i)
+        if (!std::isfinite(s->positions[i])) return fail(PT_EINVAL, "non-finite vertex position");
+    for (int i = 0; i < s->nm; ++i) {
+        const float* m = s->materials + 4 * i;
+        int t = (int)m[0];
+        if ((float)t != m[0] || t < PT_LAMBERT || t > PT_DIELECTRIC) return fail(PT_EINVAL, "unknown material type");
+        if (!(m[1] >= 0.f && m[1] <= 1.f)) return fail(PT_EINVAL, "roughness must be in [0, 1]");
+        if (t == PT_DIELECTRIC && !(m[2] > 0.f && std::isfinite(m[2]))) return fail(PT_EINVAL, "bad ior");
+    }
+    c->nt = s->nt;
+    c->nm = s->nm;
+    c->tri_v.resize(9 * (size_t)s->nt);
+    c->tri_mat.assign(s->tri_material, s->tri_material + s->nt);
+    for (int32_t i = 0; i < s->nt; ++i) {
+        for (int k = 0; k < 3; ++k) {
+            int32_t vi = s->indices[3 * (size_t)i + k];
+            if (vi < 0 || vi >= s->nv) return fail(PT_EINVAL, "vertex index out of range");
+            for (int a = 0; a < 3; ++a) c->tri_v[9 * (size_t)i + 3 * k + a] = s->positions[3 * (size_t)vi + a];
+        }
+        if (c->tri_mat[i] < 0 || c->tri_mat[i] >= s->nm) return fail(PT_EINVAL, "material index out of range");
+    }
+    c->albedo.assign(s->albedo, s->albedo + 3 * (size_t)s->nt);
+    c->emission.assign(s->emission, s->emission + 3 * (size_t)s->nt);
+    for (float v : c->albedo)
+        if (!std::isfinite(v)) return fail(PT_EINVAL, "non-finite albedo");
+    for (float v : c->emission)
+        if (!std::isfinite(v) || v < 0.f) return fail(PT_EINVAL, "emission must be finite and >= 0");
+    c->mats.assign(s->materials, s->materials + 4 * (size_t)s->nm);
+    std::memcpy(c->sky, s->sky, sizeof c->sky);
+    c->loaded = true;
+    c->built = false;
+    c->bound = false;
+    return PT_OK;
+}
+
+pt_status pt_build_bvh(pt_ctx* c, const pt_bvh_opts* o, pt_bvh_info* info) {
+    if (!c) return fail(PT_EINVAL, "null context");
+    if (!c->loaded) return fail(PT_ESTATE, "no scene loaded");
+    int max_leaf = o && o->max_leaf > 0 ? o->max_leaf : 4;
+    int threads = o ? o->threads : 0;
+    if (max_leaf > kMaxLeaf) return fail(PT_EINVAL, "max_leaf must be <= 8");
+    auto t0 = std::chrono::steady_clock::now();
+    try {
+        c->bvh = build_scene(c->tri_v, c->tri_mat, c->emission, max_leaf, threads);
+    } catch (const std::exception& e) {
+        return fail(PT_ENOMEM, std::string("BVH build failed: ") + e.what());
+    }
+    double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    c->built = true;
+    c->bound = false;
+    if (info) {
+        info->node_count = (int64_t)c->bvh.nodes.size();
+        info->node_bytes = (int64_t)(c->bvh.nodes.size() * sizeof(Node4));
+        info->tri_bytes = (int64_t)(std::max<size_t>(1, c->bvh.tris.size()) * sizeof(float4));
+        info->light_count = (int64_t)c->bvh.lights.size();
+        info->light_bytes = (int64_t)(std::max<size_t>(1, c->bvh.lights.size()) * sizeof(LightEntry));
+        info->material_bytes = (int64_t)(c->mats.size() * sizeof(float));
+        info->depth = c->bvh.depth;
+        info->stack_entries = c->bvh.stack_entries;
+        info->build_seconds = secs;
+    }
+    return PT_OK;
+}
+
+pt_status pt_get_bvh(pt_ctx* c, void* nodes, void* tris, void* lights, void* materials) {
+    if (!c) return fail(PT_EINVAL, "null context");
+    if (!c->built) return fail(PT_ESTATE, "BVH not built");
+    if (nodes) std::memcpy(nodes, c->bvh.nodes.data(), c->bvh.nodes.size() * sizeof(Node4));
+    if (tris) std::memcpy(tris, c->bvh.tris.data(), c->bvh.tris.size() * sizeof(float4));
+    if (lights) std::memcpy(lights, c->bvh.lights.data(), c->bvh.lights.size() * sizeof(LightEntry));
+    if (materials) std::memcpy(materials, c->mats.data(), c->mats.size() * sizeof(float));
+    return PT_OK;
+}
+
+pt_status pt_bind_scene(pt_ctx* c, const pt_scene_buffers* b, void* stream) {
+    if (!c || !b) return fail(PT_EINVAL, "null argument");
+    if (c->device < 0) return fail(PT_ESTATE, "host-only context cannot bind device buffers");
+    if (!c->built) return fail(PT_ESTATE, "BVH not built (pt_build_bvh)");
+    const void* ptrs[4] = {b->nodes, b->tris, b->lights, b->materials};
+    for (const void* p : ptrs)
+        if (!p || (reinterpret_cast<uintptr_t>(p) % kAlign) != 0) return fail(PT_EINVAL, "scene buffers must be non-null and 256-byte aligned");
+    if (c->nt > 0 && (!b->albedo || !b->emission)) return fail(PT_EINVAL, "null albedo/emission");
+    PT_HIP(hipSetDevice(c->device), "hipSetDevice");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    PT_HIP(hipMemcpyAsync(b->nodes, c->bvh.nodes.data(), c->bvh.nodes.size() * sizeof(Node4), hipMemcpyHostToDevice, s), "upload nodes");
+    if (!c->bvh.tris.empty())
+        PT_HIP(hipMemcpyAsync(b->tris, c->bvh.tris.data(), c->bvh.tris.size() * sizeof(float4), hipMemcpyHostToDevice, s), "upload triangles");
+    if (!c->bvh.lights.empty())
+        PT_HIP(hipMemcpyAsync(b->lights, c->bvh.lights.data(), c->bvh.lights.size() * sizeof(LightEntry), hipMemcpyHostToDevice, s), "upload lights");
+    PT_HIP(hipMemcpyAsync(b->materials, c->mats.data(), c->mats.size() * sizeof(float), hipMemcpyHostToDevice, s), "upload materials");
+    if (b->upload_params && c->nt > 0) {
+        PT_HIP(hipMemcpyAsync(b->albedo, c->albedo.data(), c->albedo.size() * sizeof(float), hipMemcpyHostToDevice, s), "upload albedo");
+        PT_HIP(hipMemcpyAsync(b->emission, c->emission.data(), c->emission.size() * sizeof(float), hipMemcpyHostToDevice, s), "upload emission");
+    }
+    // the host copies above are pageable: make sure they have been consumed
+    PT_HIP(hipStreamSynchronize(s), "upload sync");
+    c->view = make_view(c, b);
+    c->bound = true;
+    return PT_OK;
+}
+
+pt_status pt_set_camera(pt_ctx* c, const pt_camera* cam) {
+    if (!c || !cam) return fail(PT_EINVAL, "null argument");
+    if (cam->width < 1 || cam->height < 1 || cam->width > 65536 || cam->height > 65536)
+        return fail(PT_EINVAL, "image size must be in [1, 65536]");
+    if (!(cam->vfov_deg > 0.0 && cam->vfov_deg < 180.0)) return fail(PT_EINVAL, "vfov must be in (0, 180)");
+    const double* e = cam->eye;
+    const double* t = cam->target;
+    const double* u = cam->up;
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(e[i]) || !std::isfinite(t[i]) || !std::isfinite(u[i])) return fail(PT_EINVAL, "non-finite camera");
+    // binary64 basis, rounded once: F = unit(target - eye), R = unit(F x up)
+    // scaled by tan(vfov / 2) * W / H, U = (R x F) scaled by tan(vfov / 2)
+    double f[3] = {t[0] - e[0], t[1] - e[1], t[2] - e[2]};
+    double fl = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    if (!(fl > 0.0)) return fail(PT_EINVAL, "eye and target coincide");
+    f[0] = f[0] / fl; f[1] = f[1] / fl; f[2] = f[2] / fl;
+    double r[3] = {f[1] * u[2] - f[2] * u[1], f[2] * u[0] - f[0] * u[2], f[0] * u[1] - f[1] * u[0]};
+    double rl = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    if (!(rl > 0.0)) return fail(PT_EINVAL, "up is parallel to the view direction");
+    r[0] = r[0] / rl; r[1] = r[1] / rl; r[2] = r[2] / rl;
+    double v[3] = {r[1] * f[2] - r[2] * f[1], r[2] * f[0] - r[0] * f[2], r[0] * f[1] - r[1] * f[0]};
+    double th = std::tan(0.5 * (cam->vfov_deg * (3.14159265358979323846 / 180.0)));
+    double asp = (double)cam->width / (double)cam->height;
+    for (int i = 0; i < 3; ++i) {
+        c->cam.E[i] = (float)e[i];
+        c->cam.R[i] = (float)(r[i] * (th * asp));
+        c->cam.U[i] = (float)(v[i] * th);
+        c->cam.F[i] = (float)f[i];
+    }
+    c->cam.W = cam->width;
+    c->cam.H = cam->height;
+    c->cam_set = true;
+    return PT_OK;
+}
+
+pt_status pt_workspace_size(pt_ctx* c, const pt_render_args* a, uint64_t* bytes) {
+    if (!c || !a || !bytes) return fail(PT_EINVAL, "null argument");
+    if (!c->built) return fail(PT_ESTATE, "BVH not built");
+    if (!c->cam_set) return fail(PT_ESTATE, "camera not set");
+    if (a->spp < 1 || a->max_depth < 0 || a->max_depth > 1000) return fail(PT_EINVAL, "bad spp or max_depth");
+    Launch L;
+    pt_status st = launch_config(c, a, L);
+    if (st) return st;
+    *bytes = layout(c, a, L).total;
+    return PT_OK;
+}
+
+pt_status pt_render_frame(pt_ctx* c, const pt_render_args* a, float* img, float* acc, void* ws, uint64_t ws_bytes,
+                          void* stream) {
+    pt_status st = check_args(c, a);
+    if (st) return st;
+    if (!img) return fail(PT_EINVAL, "null image");
+    if (!ws) return fail(PT_EINVAL, "null workspace");
+    if ((reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return fail(PT_EINVAL, "workspace must be 256-byte aligned");
+    Launch L;
+    st = launch_config(c, a, L);
+    if (st) return st;
+    WsLayout w = layout(c, a, L);
+    if (ws_bytes < w.total) return fail(PT_ENOMEM, "workspace too small (pt_workspace_size)");
+    PT_HIP(hipSetDevice(c->device), "hipSetDevice");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char* base = static_cast<char*>(ws);
+    uint32_t* counts = reinterpret_cast<uint32_t*>(base + w.counts);
+    uint2* ovf = reinterpret_cast<uint2*>(base + w.ovf);
+    PathParams pp{a->spp, a->max_depth, a->nee ? 1 : 0, a->rr_start, a->seed, a->frame, a->job};
+    const bool prof = (a->flags & PT_FLAG_PROFILE) != 0;
+    c->timers.clear();
+    c->event_next = 0;
+    dim3 grid(L.grid), block(L.block);
+    const uint32_t npaths = (uint32_t)c->cam.W * c->cam.H * a->spp;
+    if (a->mode == PT_MODE_MEGA) {
+        PT_HIP(launch_init_counts(s, counts, w.ncounts, 0u), "init counters");
+        // counters: [0] extension rays, [1] shadow rays, [2] overflow flag
+        PT_HIP(timed(c, prof, 5, s, [&] { return launch_mega(L.lds, grid, block, s, c->view, c->cam, pp, img, acc, ovf, L.gcap, counts); }), "megakernel");
+    } else {
+        WaveBufs wb{};
+        for (int q = 0; q < 2; ++q) {
+            wb.ray_o[q] = reinterpret_cast<float4*>(base + w.wave[0 + q]);
+            wb.ray_d[q] = reinterpret_cast<float4*>(base + w.wave[2 + q]);
+            wb.pst[q] = reinterpret_cast<float4*>(base + w.wave[4 + q]);
+        }
+        wb.hit = reinterpret_cast<float4*>(base + w.wave[6]);
+        wb.sh_o = reinterpret_cast<float4*>(base + w.wave[7]);
+        wb.sh_d = reinterpret_cast<float4*>(base + w.wave[8]);
+        wb.sh_c = reinterpret_cast<float4*>(base + w.wave[9]);
+        wb.L = reinterpret_cast<float4*>(base + w.wave[10]);
+        wb.counts = counts;
+        wb.sh_base = a->max_depth + 2;
+        wb.err_slot = w.ncounts - 1;
+        const int compact = (a->flags & PT_FLAG_NO_COMPACT) ? 0 : 1;
+        PT_HIP(launch_init_counts(s, counts, w.ncounts, npaths), "init counters");
+        PT_HIP(timed(c, prof, 0, s, [&] { return launch_raygen(grid, block, s, c->cam, pp, wb); }), "raygen");
+        for (int b = 0; b <= a->max_depth; ++b) {
+            PT_HIP(timed(c, prof, 1, s, [&] { return launch_extend(L.lds, grid, block, s, c->view, wb, b, ovf, L.gcap); }), "extend");
+            PT_HIP(timed(c, prof, 2, s, [&] { return launch_shade(grid, block, s, c->view, pp, wb, b, compact); }), "shade");
+            if (b < a->max_depth && a->nee)
+                PT_HIP(timed(c, prof, 3, s, [&] { return launch_shadow(L.lds, grid, block, s, c->view, wb, b, ovf, L.gcap); }), "shadow");
+        }
+        PT_HIP(timed(c, prof, 4, s, [&] { return launch_accumulate(grid, block, s, c->cam, pp, wb.L, img, acc); }), "accumulate");
+    }
+    c->last_counts = counts;
+    c->last_ncounts = w.ncounts;
+    c->last_D = a->max_depth;
+    c->last_mode = a->mode;
+    c->last_valid = true;
+    return PT_OK;
+}
+
+pt_status pt_render_backward(pt_ctx* c, const pt_render_args* a, const float* d_image, float* d_albedo,
+                             float* d_emission, void* ws, uint64_t ws_bytes, void* stream) {
+    pt_status st = check_args(c, a);
+    if (st) return st;
+    (void)d_image; (void)d_albedo; (void)d_emission; (void)ws; (void)ws_bytes; (void)stream;
+    return fail(PT_EUNSUPPORTED, "adjoint not built yet");
+}
+
+pt_status pt_frame_stats_get(pt_ctx* c, pt_frame_stats* out) {
+    if (!c || !out) return fail(PT_EINVAL, "null argument");
+    std::memset(out, 0, sizeof *out);
+    if (!c->last_valid) return fail(PT_ESTATE, "no frame rendered");
+    PT_HIP(hipSetDevice(c->device), "hipSetDevice");
+    for (const StageTimer& t : c->timers) {
+        PT_HIP(hipEventSynchronize(t.b), "event sync");
+        float ms = 0.f;
+        PT_HIP(hipEventElapsedTime(&ms, t.a, t.b), "event time");
+        out->stage_ms[t.stage] += (double)ms;
+        out->launches[t.stage] += 1;
+    }
+    std::vector<uint32_t> h(c->last_ncounts);
+    PT_HIP(hipMemcpy(h.data(), c->last_counts, h.size() * sizeof(uint32_t), hipMemcpyDeviceToHost), "read counters");
+    if (c->last_mode == PT_MODE_MEGA) {
+        out->extension_rays = h[0];
+        out->shadow_rays = h[1];
+        if (h[2]) return fail(PT_EOVERFLOW, "traversal stack overflow");
+    } else {
+        for (int b = 0; b <= c->last_D; ++b) out->extension_rays += h[b];
+        for (int b = 0; b <= c->last_D; ++b) out->shadow_rays += h[c->last_D + 2 + b];
+        if (h[c->last_ncounts - 1]) return fail(PT_EOVERFLOW, "traversal stack overflow");
+    }
+    return PT_OK;
+}
+
+pt_status pt_sync(pt_ctx* c, void* stream) {
+    if (!c) return fail(PT_EINVAL, "null context");
+    if (c->device < 0) return PT_OK;
+    PT_HIP(hipSetDevice(c->device), "hipSetDevice");
+    PT_HIP(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)), "hipStreamSynchronize");
+    return PT_OK;
+}
+
+}  // extern "C"

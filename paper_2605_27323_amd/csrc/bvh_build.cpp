@@ -1,0 +1,356 @@
+// Host-side scene packing for libptmi: binned-SAH binary BVH collapsed to a
+// 4-wide BVH with 128-byte nodes, triangles reordered to leaf order, and the
+// area-proportional light CDF.  The paper builds its acceleration
+// structures through the Vulkan driver (Sec. 3); this is the software
+// counterpart for traversal on the compute units.
+#include "bvh_build.h"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <future>
+#include <memory>
+#include <mutex>
+#include <thread>
+
+namespace ptmi {
+namespace {
+
+struct PrimInfo {
+    float lo[3], hi[3], c[3];
+};
+
+struct BNode {
+    float lo[3], hi[3];
+    BNode* kid[2];
+    int32_t first, count;  // count > 0: leaf
+};
+
+struct Arena {
+    std::deque<BNode> nodes;
+    BNode* make() {
+        nodes.emplace_back();
+        return &nodes.back();
+    }
+};
+
+constexpr int kBins = 32;
+
+float area_of(const float lo[3], const float hi[3]) {
+    float dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
+    if (!(dx >= 0.f) || !(dy >= 0.f) || !(dz >= 0.f)) return 0.f;
+    return 2.f * (dx * dy + dy * dz + dz * dx);
+}
+
+class BinaryBuilder {
+   public:
+    BinaryBuilder(const std::vector<PrimInfo>& info, std::vector<int32_t>& order, int max_leaf, int threads)
+        : info_(info), order_(order), max_leaf_(max_leaf), budget_(threads > 1 ? threads - 1 : 0) {}
+
+    BNode* build() {
+        arenas_.emplace_back(new Arena());
+        return rec(0, (int32_t)order_.size(), arenas_.back().get());
+    }
+
+   private:
+    const std::vector<PrimInfo>& info_;
+    std::vector<int32_t>& order_;
+    int max_leaf_;
+    std::atomic<int> budget_;
+    std::mutex mu_;
+    std::vector<std::unique_ptr<Arena>> arenas_;
+
+    Arena* new_arena() {
+        std::lock_guard<std::mutex> g(mu_);
+        arenas_.emplace_back(new Arena());
+        return arenas_.back().get();
+    }
+
+    BNode* leaf(BNode* n, int32_t first, int32_t count) {
+        n->first = first;
+        n->count = count;
+        n->kid[0] = n->kid[1] = nullptr;
+        return n;
+    }
+
+    BNode* rec(int32_t first, int32_t count, Arena* arena) {
+        BNode* n = arena->make();
+        float clo[3], chi[3];
+        for (int a = 0; a < 3; ++a) {
+            n->lo[a] = INFINITY; n->hi[a] = -INFINITY;
+            clo[a] = INFINITY; chi[a] = -INFINITY;
+        }
+        for (int32_t i = first; i < first + count; ++i) {
+            const PrimInfo& p = info_[order_[i]];
+            for (int a = 0; a < 3; ++a) {
+                n->lo[a] = std::min(n->lo[a], p.lo[a]);
+                n->hi[a] = std::max(n->hi[a], p.hi[a]);
+                clo[a] = std::min(clo[a], p.c[a]);
+                chi[a] = std::max(chi[a], p.c[a]);
+            }
+        }
+        if (count <= 1) return leaf(n, first, count);
+
+        // binned SAH over the three axes
+        float best_cost = INFINITY;
+        int best_axis = -1, best_split = -1;
+        for (int a = 0; a < 3; ++a) {
+            float ext = chi[a] - clo[a];
+            if (!(ext > 0.f)) continue;
+            float scale = kBins / ext;
+            int cnt[kBins] = {0};
+            float blo[kBins][3], bhi[kBins][3];
+            for (int b = 0; b < kBins; ++b)
+                for (int k = 0; k < 3; ++k) { blo[b][k] = INFINITY; bhi[b][k] = -INFINITY; }
+            for (int32_t i = first; i < first + count; ++i) {
+                const PrimInfo& p = info_[order_[i]];
+                int b = std::min(kBins - 1, (int)((p.c[a] - clo[a]) * scale));
+                cnt[b]++;
+                for (int k = 0; k < 3; ++k) {
+                    blo[b][k] = std::min(blo[b][k], p.lo[k]);
+                    bhi[b][k] = std::max(bhi[b][k], p.hi[k]);
+                }
+            }
+            float rarea[kBins];
+            int rcnt[kBins];
+            float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+            int c = 0;
+            for (int b = kBins - 1; b > 0; --b) {
+                c += cnt[b];
+                for (int k = 0; k < 3; ++k) { lo[k] = std::min(lo[k], blo[b][k]); hi[k] = std::max(hi[k], bhi[b][k]); }
+                rarea[b] = area_of(lo, hi);
+                rcnt[b] = c;
+            }
+            for (int k = 0; k < 3; ++k) { lo[k] = INFINITY; hi[k] = -INFINITY; }
+            c = 0;
+            for (int b = 0; b < kBins - 1; ++b) {
+                c += cnt[b];
+                for (int k = 0; k < 3; ++k) { lo[k] = std::min(lo[k], blo[b][k]); hi[k] = std::max(hi[k], bhi[b][k]); }
+                if (c == 0 || rcnt[b + 1] == 0) continue;
+                float cost = area_of(lo, hi) * c + rarea[b + 1] * rcnt[b + 1];
+                if (cost < best_cost) { best_cost = cost; best_axis = a; best_split = b + 1; }
+            }
+        }
+        float parea = area_of(n->lo, n->hi);
+        float leaf_cost = (float)count;
+        float split_cost = parea > 0.f ? 1.0f + best_cost / parea : INFINITY;
+        if (count <= max_leaf_ && (best_axis < 0 || leaf_cost <= split_cost)) return leaf(n, first, count);
+
+        int32_t mid;
+        if (best_axis >= 0) {
+            float ext = chi[best_axis] - clo[best_axis];
+            float scale = kBins / ext;
+            int a = best_axis, sb = best_split;
+            float c0 = clo[a];
+            auto it = std::partition(order_.begin() + first, order_.begin() + first + count, [&](int32_t t) {
+                int b = std::min(kBins - 1, (int)((info_[t].c[a] - c0) * scale));
+                return b < sb;
+            });
+            mid = (int32_t)(it - order_.begin());
+            if (mid == first || mid == first + count) mid = first + count / 2;
+        } else {
+            mid = first + count / 2;  // all centroids coincide
+        }
+        int32_t nl = mid - first, nr = count - nl;
+        n->first = -1;
+        n->count = 0;
+        bool spawn = false;
+        if (count > 65536) {
+            spawn = budget_.fetch_sub(1) > 0;
+            if (!spawn) budget_.fetch_add(1);
+        }
+        if (spawn) {
+            Arena* a2 = new_arena();
+            auto fut = std::async(std::launch::async, [this, a2, first, nl]() { return rec(first, nl, a2); });
+            n->kid[1] = rec(mid, nr, arena);
+            n->kid[0] = fut.get();
+            budget_.fetch_add(1);
+        } else {
+            n->kid[0] = rec(first, nl, arena);
+            n->kid[1] = rec(mid, nr, arena);
+        }
+        return n;
+    }
+};
+
+struct Collapser {
+    std::vector<Node4>& out;
+    float pad;
+    int depth = 0;
+
+    static bool is_leaf(const BNode* n) { return n->count > 0 || (n->kid[0] == nullptr); }
+
+    void set_box(Node4& q, int slot, const BNode* c) {
+        float lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::nextafter(c->lo[a] - pad, -INFINITY);
+            hi[a] = std::nextafter(c->hi[a] + pad, INFINITY);
+        }
+        q.lox[slot] = lo[0]; q.hix[slot] = hi[0];
+        q.loy[slot] = lo[1]; q.hiy[slot] = hi[1];
+        q.loz[slot] = lo[2]; q.hiz[slot] = hi[2];
+    }
+
+    static uint32_t leaf_ref(const BNode* n) {
+        return kLeafBit | (uint32_t(n->count - 1) << kLeafCountShift) | uint32_t(n->first);
+    }
+
+    // Writes node `idx` from the binary subtree rooted at internal node n.
+    void emit(uint32_t idx, const BNode* n, int level) {
+        depth = std::max(depth, level);
+        const BNode* kids[4] = {n->kid[0], n->kid[1], nullptr, nullptr};
+        int k = 2;
+        while (k < 4) {
+            int best = -1;
+            float ba = -1.f;
+            for (int i = 0; i < k; ++i) {
+                if (is_leaf(kids[i])) continue;
+                float a = area_of(kids[i]->lo, kids[i]->hi);
+                if (a > ba) { ba = a; best = i; }
+            }
+            if (best < 0) break;
+            const BNode* b = kids[best];
+            kids[best] = b->kid[0];
+            kids[k++] = b->kid[1];
+        }
+        // allocate the internal children first: emplace_back may move `out`
+        uint32_t child_idx[4] = {0, 0, 0, 0};
+        for (int s = 0; s < k; ++s) {
+            if (is_leaf(kids[s])) continue;
+            child_idx[s] = (uint32_t)out.size();
+            out.emplace_back();
+        }
+        Node4& q = out[idx];
+        for (int s = 0; s < 4; ++s) {
+            q.lox[s] = q.hix[s] = q.loy[s] = q.hiy[s] = q.loz[s] = q.hiz[s] = INFINITY;
+            q.ref[s] = kEmptyRef;
+            q.pad[s] = 0;
+        }
+        for (int s = 0; s < k; ++s) {
+            if (is_leaf(kids[s]) && kids[s]->count == 0) continue;  // empty leaf: slot stays empty
+            set_box(q, s, kids[s]);
+            q.ref[s] = is_leaf(kids[s]) ? leaf_ref(kids[s]) : child_idx[s];
+        }
+        for (int s = 0; s < k; ++s)
+            if (!is_leaf(kids[s])) emit(child_idx[s], kids[s], level + 1);
+    }
+};
+
+}  // namespace
+
+BuildResult build_scene(const std::vector<float>& tri_v, const std::vector<int32_t>& tri_mat,
+                        const std::vector<float>& emission, int max_leaf, int threads) {
+    BuildResult r;
+    const int32_t nt = (int32_t)tri_mat.size();
+    max_leaf = std::max(1, std::min(kMaxLeaf, max_leaf));
+    if (threads <= 0) threads = (int)std::max(1u, std::thread::hardware_concurrency());
+
+    std::vector<PrimInfo> info(nt);
+    float M = 0.f;
+    for (int32_t i = 0; i < nt; ++i) {
+        const float* p = &tri_v[9 * (size_t)i];
+        for (int a = 0; a < 3; ++a) {
+            float lo = std::min(p[a], std::min(p[3 + a], p[6 + a]));
+            float hi = std::max(p[a], std::max(p[3 + a], p[6 + a]));
+            info[i].lo[a] = lo;
+            info[i].hi[a] = hi;
+            info[i].c[a] = 0.5f * (lo + hi);
+            M = std::max(M, std::max(std::fabs(lo), std::fabs(hi)));
+        }
+    }
+    // boxes are padded by 2^-18 of the largest coordinate so that the slab
+    // test can never reject a triangle the watertight test accepts
+    const float pad = M * 0x1p-18f;
+
+    std::vector<int32_t> order(nt);
+    for (int32_t i = 0; i < nt; ++i) order[i] = i;
+    r.nodes.reserve(nt / 2 + 1);
+    r.nodes.emplace_back();
+    Collapser col{r.nodes, pad};
+    if (nt == 0) {
+        Node4& q = r.nodes[0];
+        for (int s = 0; s < 4; ++s) {
+            q.lox[s] = q.hix[s] = q.loy[s] = q.hiy[s] = q.loz[s] = q.hiz[s] = INFINITY;
+            q.ref[s] = kEmptyRef;
+            q.pad[s] = 0;
+        }
+        r.depth = 1;
+    } else {
+        BinaryBuilder bb(info, order, max_leaf, threads);
+        BNode* root = bb.build();
+        if (Collapser::is_leaf(root)) {
+            // a single leaf: wrap it in a root node with one child
+            Node4& q = r.nodes[0];
+            for (int s = 0; s < 4; ++s) {
+                q.lox[s] = q.hix[s] = q.loy[s] = q.hiy[s] = q.loz[s] = q.hiz[s] = INFINITY;
+                q.ref[s] = kEmptyRef;
+                q.pad[s] = 0;
+            }
+            col.set_box(q, 0, root);
+            q.ref[0] = Collapser::leaf_ref(root);
+            col.depth = 1;
+        } else {
+            col.emit(0, root, 1);
+        }
+        r.depth = col.depth;
+    }
+    r.stack_entries = 3 * r.depth + 1;
+
+    // triangles in leaf order
+    r.tris.resize(3 * (size_t)nt);
+    std::vector<uint8_t> is_light(nt);
+    for (int32_t i = 0; i < nt; ++i) {
+        const float* e = &emission[3 * (size_t)i];
+        is_light[i] = (e[0] > 0.f || e[1] > 0.f || e[2] > 0.f);
+    }
+    std::vector<uint32_t> leaf_pos(nt);
+    for (int32_t j = 0; j < nt; ++j) {
+        int32_t t = order[j];
+        leaf_pos[t] = (uint32_t)j;
+        const float* p = &tri_v[9 * (size_t)t];
+        uint32_t id = (uint32_t)t;
+        uint32_t mi = (uint32_t)tri_mat[t] | (is_light[t] ? kLightFlag : 0u);
+        float fid, fmi;
+        std::memcpy(&fid, &id, 4);
+        std::memcpy(&fmi, &mi, 4);
+        r.tris[3 * (size_t)j + 0] = make_float4(p[0], p[1], p[2], fid);
+        r.tris[3 * (size_t)j + 1] = make_float4(p[3], p[4], p[5], fmi);
+        r.tris[3 * (size_t)j + 2] = make_float4(p[6], p[7], p[8], 0.f);
+    }
+
+    // light set in input order: fp64 prefix sums of the triangle areas,
+    // quantised to u32 words (last word saturated)
+    std::vector<double> cum;
+    std::vector<uint32_t> ids;
+    double acc = 0.0;
+    for (int32_t i = 0; i < nt; ++i) {
+        if (!is_light[i]) continue;
+        const float* p = &tri_v[9 * (size_t)i];
+        double ax = (double)p[3] - (double)p[0], ay = (double)p[4] - (double)p[1], az = (double)p[5] - (double)p[2];
+        double bx = (double)p[6] - (double)p[0], by = (double)p[7] - (double)p[1], bz = (double)p[8] - (double)p[2];
+        double cx = ay * bz - az * by, cy = az * bx - ax * bz, cz = ax * by - ay * bx;
+        acc += 0.5 * std::sqrt(cx * cx + cy * cy + cz * cz);
+        cum.push_back(acc);
+        ids.push_back((uint32_t)i);
+    }
+    r.area_total = (float)acc;
+    if (acc > 0.0) {
+        r.lights.resize(ids.size());
+        for (size_t j = 0; j < ids.size(); ++j) {
+            uint32_t w;
+            if (j + 1 == ids.size()) {
+                w = 0xFFFFFFFFu;
+            } else {
+                double q = std::floor(cum[j] / acc * 4294967296.0);
+                w = q > 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)q;
+            }
+            r.lights[j].tri = leaf_pos[ids[j]];
+            r.lights[j].cdf = w;
+        }
+    }
+    return r;
+}
+
+}  // namespace ptmi

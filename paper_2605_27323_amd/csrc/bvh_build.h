@@ -1,0 +1,23 @@
+// Host-side scene packing for libptmi (BVH4 build, leaf-order triangles,
+// light CDF).
+#pragma once
+#include <vector>
+
+#include "ptmi_internal.h"
+
+namespace ptmi {
+
+struct BuildResult {
+    std::vector<Node4> nodes;
+    std::vector<float4> tris;        // 3 per triangle, leaf order
+    std::vector<LightEntry> lights;  // input order of the light triangles
+    float area_total = 0.f;
+    int depth = 0;
+    int stack_entries = 0;
+};
+
+// tri_v: nt*9 vertex coordinates (v0, v1, v2) in input order.
+BuildResult build_scene(const std::vector<float>& tri_v, const std::vector<int32_t>& tri_mat,
+                        const std::vector<float>& emission, int max_leaf, int threads);
+
+}  // namespace ptmi

@@ -1,0 +1,824 @@
+// Device functions of the path tracer (gfx950, wave64).
+//
+// Arithmetic is binary32 in source order; the library is compiled with
+// -ffp-contract=off and IEEE division/square root, so every float decision
+// (closest hit, light pick, roulette, lobe) is reproducible on any IEEE
+// machine that evaluates the same expressions.  Formulas follow the paper's
+// estimator (Sec. 2.2, Eq. 3) with the readings fixed in the design notes:
+// Philox4x64-10 random numbers keyed by (pixel, sample, bounce, job),
+// pinhole camera with box-filter jitter, watertight ray/triangle test,
+// Lambertian / GGX conductor / rough dielectric materials, next-event
+// estimation with the power heuristic, roulette after the throughput update.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "ptmi_internal.h"
+
+namespace ptmi {
+
+// Every function here is also compiled for the host, so that the exact
+// kernel arithmetic can be run on the CPU by the test emulator.
+#define PT_DEV __host__ __device__ __forceinline__
+
+PT_DEV uint32_t f2u(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __float_as_uint(x);
+#else
+    uint32_t u;
+    memcpy(&u, &x, 4);
+    return u;
+#endif
+}
+PT_DEV float u2f(uint32_t u) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __uint_as_float(u);
+#else
+    float x;
+    memcpy(&x, &u, 4);
+    return x;
+#endif
+}
+PT_DEV uint64_t mulhi64(uint64_t a, uint64_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __umul64hi(a, b);
+#else
+    return (uint64_t)(((unsigned __int128)a * b) >> 64);
+#endif
+}
+
+constexpr float kPi = (float)3.14159265358979323846;
+constexpr float kInvPi = (float)(1.0 / 3.14159265358979323846);
+constexpr float kShadowTmax = 0.9999f;
+constexpr float kBoxSlack = 1.0f + 0x1p-16f;
+
+struct f3 {
+    float x, y, z;
+};
+PT_DEV f3 mk3(float x, float y, float z) { return f3{x, y, z}; }
+PT_DEV f3 add3(f3 a, f3 b) { return mk3(a.x + b.x, a.y + b.y, a.z + b.z); }
+PT_DEV f3 sub3(f3 a, f3 b) { return mk3(a.x - b.x, a.y - b.y, a.z - b.z); }
+PT_DEV f3 scl3(f3 a, float s) { return mk3(a.x * s, a.y * s, a.z * s); }
+PT_DEV f3 neg3(f3 a) { return mk3(-a.x, -a.y, -a.z); }
+PT_DEV f3 mul3(f3 a, f3 b) { return mk3(a.x * b.x, a.y * b.y, a.z * b.z); }
+PT_DEV float dot3(f3 a, f3 b) { return (a.x * b.x + a.y * b.y) + a.z * b.z; }
+PT_DEV f3 cross3(f3 a, f3 b) {
+    return mk3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+// v * (1 / sqrt(|v|^2)), IEEE division and square root
+PT_DEV f3 normalize3(f3 a) {
+    float s = 1.0f / sqrtf(dot3(a, a));
+    return scl3(a, s);
+}
+PT_DEV float comp3(f3 a, int i) { return i == 0 ? a.x : (i == 1 ? a.y : a.z); }
+PT_DEV f3 xyz(float4 v) { return mk3(v.x, v.y, v.z); }
+PT_DEV float max3c(f3 a) {
+    float m = a.x > a.y ? a.x : a.y;
+    return m > a.z ? m : a.z;
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC 2011)
+// ---------------------------------------------------------------------------
+struct Rng8 {
+    uint32_t w[8];
+};
+
+PT_DEV Rng8 philox8(uint64_t seed, uint32_t pixel, uint32_t sample, uint32_t bounce, uint32_t job) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+    uint64_t c0 = pixel, c1 = sample, c2 = bounce, c3 = job;
+    uint64_t k0 = seed, k1 = 0;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        uint64_t hi0 = mulhi64(M0, c0), lo0 = M0 * c0;
+        uint64_t hi1 = mulhi64(M1, c2), lo1 = M1 * c2;
+        uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    Rng8 r;
+    r.w[0] = (uint32_t)c0; r.w[1] = (uint32_t)(c0 >> 32);
+    r.w[2] = (uint32_t)c1; r.w[3] = (uint32_t)(c1 >> 32);
+    r.w[4] = (uint32_t)c2; r.w[5] = (uint32_t)(c2 >> 32);
+    r.w[6] = (uint32_t)c3; r.w[7] = (uint32_t)(c3 >> 32);
+    return r;
+}
+// top 24 bits scaled by 2^-24: exact, in [0, 1)
+PT_DEV float unif(uint32_t w) { return (float)(w >> 8) * 0x1p-24f; }
+
+// cos and sin of 2 pi u, evaluated in binary64 and rounded once
+PT_DEV void cos_sin_2pi(float u, float& c, float& s) {
+    double ph = (2.0 * 3.14159265358979323846) * (double)u;
+#if defined(__HIP_DEVICE_COMPILE__)
+    double sd, cd;
+    sincos(ph, &sd, &cd);
+#else
+    double sd = ::sin(ph), cd = ::cos(ph);
+#endif
+    c = (float)cd;
+    s = (float)sd;
+}
+
+// ---------------------------------------------------------------------------
+// camera
+// ---------------------------------------------------------------------------
+PT_DEV void camera_ray(const CamView& cam, int px, int py, float u0, float u1, f3& o, f3& d) {
+    float sx = (((float)px + u0) / (float)cam.W) * 2.0f - 1.0f;
+    float sy = 1.0f - (((float)py + u1) / (float)cam.H) * 2.0f;
+    f3 dd = mk3((sx * cam.R[0] + sy * cam.U[0]) + cam.F[0], (sx * cam.R[1] + sy * cam.U[1]) + cam.F[1],
+                (sx * cam.R[2] + sy * cam.U[2]) + cam.F[2]);
+    o = mk3(cam.E[0], cam.E[1], cam.E[2]);
+    d = normalize3(dd);
+}
+
+// ---------------------------------------------------------------------------
+// rays: watertight triangle test (Woop, Benthin, Wald, JCGT 2013)
+// ---------------------------------------------------------------------------
+struct Ray {
+    f3 o, d;
+    f3 inv;  // 1/d for the slab test, zero components replaced by 2^-80
+    int kx, ky, kz;
+    float Sx, Sy, Sz;
+};
+
+PT_DEV Ray make_ray(f3 o, f3 d) {
+    Ray r;
+    r.o = o;
+    r.d = d;
+    r.inv = mk3(1.0f / (d.x != 0.0f ? d.x : 0x1p-80f), 1.0f / (d.y != 0.0f ? d.y : 0x1p-80f),
+                1.0f / (d.z != 0.0f ? d.z : 0x1p-80f));
+    float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
+    int kz = 0;
+    float m = ax;
+    if (ay > m) {
+        kz = 1;
+        m = ay;
+    }
+    if (az > m) kz = 2;
+    int kx = kz == 2 ? 0 : kz + 1;
+    int ky = kx == 2 ? 0 : kx + 1;
+    float dkz = comp3(d, kz);
+    if (dkz < 0.0f) {
+        int t = kx;
+        kx = ky;
+        ky = t;
+    }
+    r.kx = kx;
+    r.ky = ky;
+    r.kz = kz;
+    r.Sx = comp3(d, kx) / dkz;
+    r.Sy = comp3(d, ky) / dkz;
+    r.Sz = 1.0f / dkz;
+    return r;
+}
+
+// Returns true on a hit with t > 0; t and the barycentrics of v1, v2.
+PT_DEV bool tri_intersect(const Ray& r, f3 v0, f3 v1, f3 v2, float& t, float& b1, float& b2) {
+    f3 A = sub3(v0, r.o), B = sub3(v1, r.o), C = sub3(v2, r.o);
+    float Akz = comp3(A, r.kz), Bkz = comp3(B, r.kz), Ckz = comp3(C, r.kz);
+    float Ax = comp3(A, r.kx) - r.Sx * Akz;
+    float Ay = comp3(A, r.ky) - r.Sy * Akz;
+    float Bx = comp3(B, r.kx) - r.Sx * Bkz;
+    float By = comp3(B, r.ky) - r.Sy * Bkz;
+    float Cx = comp3(C, r.kx) - r.Sx * Ckz;
+    float Cy = comp3(C, r.ky) - r.Sy * Ckz;
+    float U = Cx * By - Cy * Bx;
+    float V = Ax * Cy - Ay * Cx;
+    float W = Bx * Ay - By * Ax;
+    if (U == 0.0f || V == 0.0f || W == 0.0f) {
+        // exact binary32 products in binary64, one rounding each
+        U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
+        V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
+        W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
+    }
+    if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return false;
+    float det = (U + V) + W;
+    if (det == 0.0f) return false;
+    float Az = r.Sz * Akz;
+    float Bz = r.Sz * Bkz;
+    float Cz = r.Sz * Ckz;
+    float T = (U * Az + V * Bz) + W * Cz;
+    float tt = T / det;
+    if (!(tt > 0.0f)) return false;
+    t = tt;
+    b1 = V / det;
+    b2 = W / det;
+    return true;
+}
+
+// Conservative slab test of the four children of a node against (0, tlim]:
+// entry <= exit * (1 + 2^-16).  Writes the entry distances; returns a
+// 4-bit hit mask.  Empty slots are masked out by their reference: their
+// +inf boxes alone would pass when every direction component is positive
+// and tlim is +inf (inf <= inf).
+PT_DEV unsigned slab4(const Ray& r, const float4 q[7], float tlim, float tn[4]) {
+    const float* lox = &q[0].x;
+    const float* hix = &q[1].x;
+    const float* loy = &q[2].x;
+    const float* hiy = &q[3].x;
+    const float* loz = &q[4].x;
+    const float* hiz = &q[5].x;
+    unsigned mask = 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        float ax = (lox[c] - r.o.x) * r.inv.x, bx = (hix[c] - r.o.x) * r.inv.x;
+        float ay = (loy[c] - r.o.y) * r.inv.y, by = (hiy[c] - r.o.y) * r.inv.y;
+        float az = (loz[c] - r.o.z) * r.inv.z, bz = (hiz[c] - r.o.z) * r.inv.z;
+        float t0 = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), 0.0f));
+        float t1 = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), tlim));
+        tn[c] = t0;
+        const float cref = c == 0 ? q[6].x : (c == 1 ? q[6].y : (c == 2 ? q[6].z : q[6].w));
+        if (t0 <= t1 * kBoxSlack && f2u(cref) != kEmptyRef) mask |= 1u << c;
+    }
+    return mask;
+}
+
+// ---------------------------------------------------------------------------
+// traversal stack: per-lane entries in LDS (stride = block size), deeper
+// entries spill to a per-lane global area (stride = number of lanes)
+// ---------------------------------------------------------------------------
+template <int LDS>
+struct TravStack {
+    uint32_t* lref;
+    float* lt;
+    uint2* gbl;
+    int lstride;
+    int gstride;
+    int gcap;
+    int sp;
+    bool overflow;
+
+    PT_DEV void push(uint32_t ref, float t) {
+        if (sp < LDS) {
+            lref[sp * lstride] = ref;
+            lt[sp * lstride] = t;
+        } else if (sp - LDS < gcap) {
+            gbl[(sp - LDS) * gstride] = make_uint2(ref, f2u(t));
+        } else {
+            overflow = true;
+            return;
+        }
+        ++sp;
+    }
+    PT_DEV void pop(uint32_t& ref, float& t) {
+        --sp;
+        if (sp < LDS) {
+            ref = lref[sp * lstride];
+            t = lt[sp * lstride];
+        } else {
+            uint2 e = gbl[(sp - LDS) * gstride];
+            ref = e.x;
+            t = u2f(e.y);
+        }
+    }
+};
+
+struct Hit {
+    float t, b1, b2;
+    uint32_t tri;   // leaf-order index, ~0u on a miss
+    uint32_t id;    // input id (tie-break)
+};
+
+PT_DEV void load_node(const float4* __restrict__ nodes, uint32_t idx, float4 q[8]) {
+    const float4* p = nodes + (size_t)idx * 8;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) q[i] = p[i];
+}
+
+// sort up to four (ref, t) pairs by t (ascending), invalid entries last
+PT_DEV void sort4(uint32_t ref[4], float t[4]) {
+#define PT_CSWAP(a, b)                         \
+    if (t[b] < t[a]) {                         \
+        float tt = t[a]; t[a] = t[b]; t[b] = tt; \
+        uint32_t rr = ref[a]; ref[a] = ref[b]; ref[b] = rr; \
+    }
+    PT_CSWAP(0, 1);
+    PT_CSWAP(2, 3);
+    PT_CSWAP(0, 2);
+    PT_CSWAP(1, 3);
+    PT_CSWAP(1, 2);
+#undef PT_CSWAP
+}
+
+// Closest hit in (0, tmax): smallest t, ties to the smaller input id.
+// References outside the node or triangle arrays are skipped, so a damaged
+// BVH cannot make a lane read out of bounds.
+template <int LDS>
+PT_DEV Hit closest_hit(const SceneView& sc, const Ray& r, float tmax, TravStack<LDS>& st) {
+    Hit h;
+    h.t = tmax;
+    h.b1 = 0.0f;
+    h.b2 = 0.0f;
+    h.tri = 0xFFFFFFFFu;
+    h.id = 0xFFFFFFFFu;
+    st.sp = 0;
+    uint32_t ref = 0;  // root
+    while (true) {
+        if (!(ref & kLeafBit)) {
+            if (ref < (uint32_t)sc.n_nodes) {
+                float4 q[8];
+                load_node(sc.nodes, ref, q);
+                float tn[4];
+                unsigned m = slab4(r, q, h.t, tn);
+                if (m) {
+                    uint32_t rr[4];
+                    float tt[4];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        bool hit = (m >> c) & 1u;
+                        const float cref = c == 0 ? q[6].x : (c == 1 ? q[6].y : (c == 2 ? q[6].z : q[6].w));
+                        rr[c] = hit ? f2u(cref) : kEmptyRef;
+                        tt[c] = hit ? tn[c] : INFINITY;
+                    }
+                    sort4(rr, tt);
+                    // push the farther hits (farthest first), descend into the nearest
+                    if (rr[3] != kEmptyRef) st.push(rr[3], tt[3]);
+                    if (rr[2] != kEmptyRef) st.push(rr[2], tt[2]);
+                    if (rr[1] != kEmptyRef) st.push(rr[1], tt[1]);
+                    ref = rr[0];
+                    continue;
+                }
+            }
+        } else {
+            uint32_t first = ref & kLeafFirstMask;
+            uint32_t cnt = ((ref >> kLeafCountShift) & 15u) + 1u;
+            if (first + cnt <= (uint32_t)sc.nt) {
+                for (uint32_t i = first; i < first + cnt; ++i) {
+                    const float4* tp = sc.tris + (size_t)i * 3;
+                    float4 a = tp[0], b = tp[1], c = tp[2];
+                    float t, b1, b2;
+                    if (tri_intersect(r, xyz(a), xyz(b), xyz(c), t, b1, b2) && t < tmax) {
+                        uint32_t id = f2u(a.w);
+                        if (t < h.t || (t == h.t && id < h.id)) {
+                            h.t = t;
+                            h.b1 = b1;
+                            h.b2 = b2;
+                            h.tri = i;
+                            h.id = id;
+                        }
+                    }
+                }
+            }
+        }
+        // pop the next entry that can still hold a closer hit
+        bool found = false;
+        while (st.sp > 0) {
+            float t;
+            st.pop(ref, t);
+            if (t <= h.t * kBoxSlack) {
+                found = true;
+                break;
+            }
+        }
+        if (!found) break;
+    }
+    return h;
+}
+
+// Any hit in (0, tmax).
+template <int LDS>
+PT_DEV bool any_hit(const SceneView& sc, const Ray& r, float tmax, TravStack<LDS>& st) {
+    st.sp = 0;
+    uint32_t ref = 0;
+    while (true) {
+        if (!(ref & kLeafBit)) {
+            if (ref < (uint32_t)sc.n_nodes) {
+                float4 q[8];
+                load_node(sc.nodes, ref, q);
+                float tn[4];
+                unsigned m = slab4(r, q, tmax, tn);
+                if (m) {
+                    // descend into the first hit child, push the others
+                    const uint32_t cr[4] = {f2u(q[6].x), f2u(q[6].y), f2u(q[6].z), f2u(q[6].w)};
+                    uint32_t next = kEmptyRef;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        if (!((m >> c) & 1u)) continue;
+                        if (next == kEmptyRef) next = cr[c];
+                        else st.push(cr[c], tn[c]);
+                    }
+                    ref = next;
+                    continue;
+                }
+            }
+        } else {
+            uint32_t first = ref & kLeafFirstMask;
+            uint32_t cnt = ((ref >> kLeafCountShift) & 15u) + 1u;
+            if (first + cnt <= (uint32_t)sc.nt) {
+                for (uint32_t i = first; i < first + cnt; ++i) {
+                    const float4* tp = sc.tris + (size_t)i * 3;
+                    float4 a = tp[0], b = tp[1], c = tp[2];
+                    float t, b1, b2;
+                    if (tri_intersect(r, xyz(a), xyz(b), xyz(c), t, b1, b2) && t < tmax) return true;
+                }
+            }
+        }
+        if (st.sp == 0) break;
+        float t;
+        st.pop(ref, t);
+    }
+    return false;
+}
+
+// ---------------------------------------------------------------------------
+// geometry helpers
+// ---------------------------------------------------------------------------
+// Self-intersection offset (Waechter and Binder, Ray Tracing Gems ch. 6):
+// move each coordinate by int(256 n) ulps, or by n / 65536 near zero.
+PT_DEV float offset_coord(float p, float n) {
+    int of = (int)(256.0f * n);
+    int bits = (int)f2u(p);
+    bits = bits + (p < 0.0f ? -of : of);
+    float moved = u2f((uint32_t)bits);
+    return fabsf(p) < 0x1p-5f ? p + 0x1p-16f * n : moved;
+}
+PT_DEV f3 offset_point(f3 p, f3 n) {
+    return mk3(offset_coord(p.x, n.x), offset_coord(p.y, n.y), offset_coord(p.z, n.z));
+}
+
+PT_DEV f3 tri_normal(f3 v0, f3 v1, f3 v2) {
+    f3 c = cross3(sub3(v1, v0), sub3(v2, v0));
+    if (dot3(c, c) == 0.0f) return mk3(0.0f, 0.0f, 1.0f);
+    return normalize3(c);
+}
+
+// uniform point: b1 = sqrt(u1)(1-u2), b2 = sqrt(u1) u2 on edges e1, e2
+PT_DEV f3 tri_point(f3 v0, f3 v1, f3 v2, float u1, float u2) {
+    f3 e1 = sub3(v1, v0), e2 = sub3(v2, v0);
+    float su = sqrtf(u1);
+    float b1 = su * (1.0f - u2), b2 = su * u2;
+    return mk3((v0.x + b1 * e1.x) + b2 * e2.x, (v0.y + b1 * e1.y) + b2 * e2.y, (v0.z + b1 * e1.z) + b2 * e2.z);
+}
+
+// Orthonormal basis (Duff et al., JCGT 2017).
+struct Frame {
+    f3 t, b, n;
+};
+PT_DEV Frame make_frame(f3 n) {
+    float sign = copysignf(1.0f, n.z);
+    float a = -1.0f / (sign + n.z);
+    float b = n.x * n.y * a;
+    Frame f;
+    f.t = mk3(1.0f + sign * n.x * n.x * a, sign * b, -sign * n.x);
+    f.b = mk3(b, sign + n.y * n.y * a, -n.y);
+    f.n = n;
+    return f;
+}
+PT_DEV f3 to_local(const Frame& f, f3 w) { return mk3(dot3(f.t, w), dot3(f.b, w), dot3(f.n, w)); }
+PT_DEV f3 to_world(const Frame& f, f3 l) {
+    return mk3((f.t.x * l.x + f.b.x * l.y) + f.n.x * l.z, (f.t.y * l.x + f.b.y * l.y) + f.n.y * l.z,
+               (f.t.z * l.x + f.b.z * l.y) + f.n.z * l.z);
+}
+
+// ---------------------------------------------------------------------------
+// materials
+// ---------------------------------------------------------------------------
+PT_DEV float ggx_alpha(float rough) {
+    float a = rough * rough;
+    return a < 1e-4f ? 1e-4f : a;
+}
+// GGX D for a unit half vector; hx^2 + hy^2 + a2 hz^2 avoids the
+// cancellation of cos^2 (a2 - 1) + 1 near the peak
+PT_DEV float ggx_D(f3 h, float a2) {
+    float den = (h.x * h.x + h.y * h.y) + a2 * (h.z * h.z);
+    return a2 / ((kPi * den) * den);
+}
+PT_DEV float ggx_lambda(f3 w, float a2) {
+    float t2 = (w.x * w.x + w.y * w.y) / (w.z * w.z);
+    return (sqrtf(1.0f + a2 * t2) - 1.0f) * 0.5f;
+}
+// visible-normal sampling (Heitz, JCGT 2018)
+PT_DEV f3 ggx_vndf(f3 wo, float alpha, float u5, float u6) {
+    f3 Vh = normalize3(mk3(alpha * wo.x, alpha * wo.y, wo.z));
+    float lensq = Vh.x * Vh.x + Vh.y * Vh.y;
+    f3 T1 = lensq > 0.0f ? scl3(mk3(-Vh.y, Vh.x, 0.0f), 1.0f / sqrtf(lensq)) : mk3(1.0f, 0.0f, 0.0f);
+    f3 T2 = cross3(Vh, T1);
+    float r = sqrtf(u5), c, s;
+    cos_sin_2pi(u6, c, s);
+    float t1 = r * c, t2 = r * s;
+    float sh = 0.5f * (1.0f + Vh.z);
+    t2 = (1.0f - sh) * sqrtf(1.0f - t1 * t1) + sh * t2;
+    float nz2 = (1.0f - t1 * t1) - t2 * t2;
+    float nz = sqrtf(nz2 > 0.0f ? nz2 : 0.0f);
+    f3 Nh = mk3((t1 * T1.x + t2 * T2.x) + nz * Vh.x, (t1 * T1.y + t2 * T2.y) + nz * Vh.y,
+                (t1 * T1.z + t2 * T2.z) + nz * Vh.z);
+    return normalize3(mk3(alpha * Nh.x, alpha * Nh.y, Nh.z > 0.0f ? Nh.z : 0.0f));
+}
+PT_DEV float pow5(float m) { return ((m * m) * (m * m)) * m; }
+
+// Albedo-free factors of a lobe, kept for the adjoint: f (or the sampling
+// weight) = Lambert: albedo * k; conductor: (albedo + (1 - albedo) m5) * k;
+// dielectric: k, untinted.
+struct Lobe {
+    int type;
+    float m5, k;
+};
+
+// f and the solid-angle pdf of an opaque material, wo and wi in the local
+// frame of the normal on wo's side.
+PT_DEV void eval_opaque(int type, float rough, f3 alb, f3 wo, f3 wi, f3& f, float& pdf, Lobe& lb) {
+    f = mk3(0.0f, 0.0f, 0.0f);
+    pdf = 0.0f;
+    lb.type = type;
+    lb.m5 = 0.0f;
+    lb.k = 0.0f;
+    if (wi.z <= 0.0f || wo.z <= 0.0f) return;
+    if (type == PT_LAMBERT) {
+        f = mk3(alb.x * kInvPi, alb.y * kInvPi, alb.z * kInvPi);
+        pdf = wi.z * kInvPi;
+        lb.k = kInvPi;
+        return;
+    }
+    float alpha = ggx_alpha(rough), a2 = alpha * alpha;
+    f3 h = normalize3(add3(wo, wi));
+    float D = ggx_D(h, a2);
+    float lo = ggx_lambda(wo, a2), li = ggx_lambda(wi, a2);
+    float G1 = 1.0f / (1.0f + lo);
+    float G2 = 1.0f / ((1.0f + lo) + li);
+    float m5 = pow5(1.0f - dot3(wi, h));
+    float k = (D * G2) / ((4.0f * wo.z) * wi.z);
+    f = mk3((alb.x + (1.0f - alb.x) * m5) * k, (alb.y + (1.0f - alb.y) * m5) * k, (alb.z + (1.0f - alb.z) * m5) * k);
+    pdf = (G1 * D) / (4.0f * wo.z);
+    lb.m5 = m5;
+    lb.k = k;
+}
+
+// exact unpolarised Fresnel reflectance, eta = eta_t / eta_i
+PT_DEV float fresnel_dielectric(float ci, float eta) {
+    float s2 = (1.0f - ci * ci) / (eta * eta);
+    if (s2 >= 1.0f) return 1.0f;
+    float ct = sqrtf(1.0f - s2);
+    float rs = (ci - eta * ct) / (ci + eta * ct);
+    float rp = (eta * ci - ct) / (eta * ci + ct);
+    return 0.5f * (rs * rs + rp * rp);
+}
+
+// Sample a continuation direction in the local frame; false = rejected.
+PT_DEV bool sample_local(int type, float rough, float ior, bool entering, f3 alb, f3 wo, float u4, float u5,
+                         float u6, f3& wi, f3& weight, float& pdf, Lobe& lb) {
+    lb.type = type;
+    lb.m5 = 0.0f;
+    lb.k = 0.0f;
+    if (type == PT_LAMBERT) {
+        float r = sqrtf(u5), c, s;
+        cos_sin_2pi(u6, c, s);
+        float z2 = 1.0f - u5;
+        wi = mk3(r * c, r * s, sqrtf(z2 > 0.0f ? z2 : 0.0f));
+        weight = alb;
+        pdf = wi.z * kInvPi;
+        lb.k = 1.0f;
+        return true;
+    }
+    if (wo.z <= 0.0f) return false;
+    float alpha = ggx_alpha(rough), a2 = alpha * alpha;
+    f3 m = ggx_vndf(wo, alpha, u5, u6);
+    float com = dot3(wo, m);
+    float lo = ggx_lambda(wo, a2);
+    float G1 = 1.0f / (1.0f + lo);
+    if (type == PT_CONDUCTOR) {
+        f3 w = mk3((2.0f * com) * m.x - wo.x, (2.0f * com) * m.y - wo.y, (2.0f * com) * m.z - wo.z);
+        if (w.z <= 0.0f) return false;
+        float li = ggx_lambda(w, a2);
+        float G2 = 1.0f / ((1.0f + lo) + li);
+        float g = G2 / G1;
+        float m5 = pow5(1.0f - com);
+        wi = w;
+        weight = mk3((alb.x + (1.0f - alb.x) * m5) * g, (alb.y + (1.0f - alb.y) * m5) * g,
+                     (alb.z + (1.0f - alb.z) * m5) * g);
+        pdf = (G1 * ggx_D(m, a2)) / (4.0f * wo.z);
+        lb.m5 = m5;
+        lb.k = g;
+        return true;
+    }
+    // rough dielectric (Walter et al., EGSR 2007)
+    float eta = entering ? ior : 1.0f / ior;
+    float F = fresnel_dielectric(com, eta);
+    f3 w;
+    float scale;
+    if (u4 < F) {
+        w = mk3((2.0f * com) * m.x - wo.x, (2.0f * com) * m.y - wo.y, (2.0f * com) * m.z - wo.z);
+        if (w.z <= 0.0f) return false;
+        scale = 1.0f;
+    } else {
+        float s2 = (1.0f - com * com) / (eta * eta);
+        float ct = sqrtf(1.0f - s2);
+        float a = com / eta - ct;
+        w = mk3(-wo.x / eta + a * m.x, -wo.y / eta + a * m.y, -wo.z / eta + a * m.z);
+        if (w.z >= 0.0f) return false;
+        scale = 1.0f / (eta * eta);
+    }
+    float li = ggx_lambda(w, a2);
+    float G2 = 1.0f / ((1.0f + lo) + li);
+    float g = (G2 / G1) * scale;
+    wi = w;
+    weight = mk3(g, g, g);
+    pdf = 0.0f;
+    lb.k = g;
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// one path vertex (shared by the megakernel, the wavefront and the adjoint)
+// ---------------------------------------------------------------------------
+struct PathState {
+    f3 beta;
+    f3 L;
+    float p_prev;
+    int prev_smooth;
+};
+
+struct ShadowReq {
+    bool valid;
+    f3 o, d;     // segment origin and unnormalised direction to the light
+    f3 C;        // f Le_y G: contribution per unit throughput if visible
+    f3 contrib;  // beta * C with the throughput arriving at the vertex
+    uint32_t light_id;  // input id of the light triangle
+    float G;
+    Lobe lobe;   // f = lobe(albedo)
+};
+
+struct VertexOut {
+    bool cont;          // the path continues
+    f3 o, d;            // continuation ray
+    uint32_t id;        // input id of the hit triangle (~0u on a miss)
+    bool emitted;       // emission term counted at this vertex
+    float w_emit;       // its MIS weight
+    Lobe scat;          // sampling weight = lobe(albedo) when cont
+};
+
+PT_DEV uint32_t pick_light(const SceneView& sc, uint32_t w) {
+    int lo = 0, hi = sc.nl - 1;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (w <= sc.lights[mid].cdf) hi = mid;
+        else lo = mid + 1;
+    }
+    return (uint32_t)lo;
+}
+
+PT_DEV f3 load3(const float* __restrict__ p, uint32_t i) {
+    return mk3(p[3 * (size_t)i], p[3 * (size_t)i + 1], p[3 * (size_t)i + 2]);
+}
+
+// Shade vertex k of a path: add emission (MIS-weighted after a light-sampled
+// vertex), build the light-sample request, sample the continuation and
+// apply roulette.  ps.L receives the emission; the light-sample
+// contribution beta * C is added by the caller once the segment is found
+// unoccluded (megakernel: at once; wavefront: in the shadow stage).
+PT_DEV VertexOut shade_vertex(const SceneView& sc, const PathParams& pp, uint32_t pixel, uint32_t sample, int k,
+                              f3 rd, const Hit& h, PathState& ps, ShadowReq& sh) {
+    VertexOut out;
+    out.cont = false;
+    out.id = 0xFFFFFFFFu;
+    out.emitted = false;
+    out.w_emit = 0.0f;
+    sh.valid = false;
+    if (h.tri >= (uint32_t)sc.nt) {
+        ps.L = mk3(ps.L.x + ps.beta.x * sc.sky0, ps.L.y + ps.beta.y * sc.sky1, ps.L.z + ps.beta.z * sc.sky2);
+        return out;
+    }
+    const float4* tp = sc.tris + (size_t)h.tri * 3;
+    float4 ta = tp[0], tb = tp[1], tc = tp[2];
+    f3 v0 = xyz(ta), v1 = xyz(tb), v2 = xyz(tc);
+    uint32_t id = f2u(ta.w);
+    uint32_t minfo = f2u(tb.w);
+    out.id = id;
+    f3 e1 = sub3(v1, v0), e2 = sub3(v2, v0);
+    f3 x = mk3((v0.x + h.b1 * e1.x) + h.b2 * e2.x, (v0.y + h.b1 * e1.y) + h.b2 * e2.y,
+               (v0.z + h.b1 * e1.z) + h.b2 * e2.z);
+    f3 ng = tri_normal(v0, v1, v2);
+    f3 wo = neg3(rd);
+    float cos_e = dot3(ng, wo);
+    if (cos_e > 0.0f) {
+        float w = 1.0f;
+        if (k > 1 && pp.nee && ps.prev_smooth && (minfo & kLightFlag) && sc.nl > 0) {
+            float pl = (h.t * h.t) / (sc.area_total * cos_e);
+            w = (ps.p_prev * ps.p_prev) / (ps.p_prev * ps.p_prev + pl * pl);
+        }
+        f3 Le = load3(sc.emission, id);
+        ps.L = mk3(ps.L.x + ps.beta.x * (w * Le.x), ps.L.y + ps.beta.y * (w * Le.y), ps.L.z + ps.beta.z * (w * Le.z));
+        out.emitted = true;
+        out.w_emit = w;
+    }
+    if (k == pp.D + 1) return out;
+    Rng8 rn = philox8(pp.seed, pixel, sample, (uint32_t)k, pp.job);
+    float4 mat = sc.mats[minfo & ~kLightFlag];
+    int type = (int)mat.x;
+    float rough = mat.y, ior = mat.z;
+    f3 alb = load3(sc.albedo, id);
+    bool entering = true;
+    f3 n;
+    if (type == PT_DIELECTRIC) {
+        entering = cos_e > 0.0f;
+        n = entering ? ng : neg3(ng);
+    } else {
+        n = cos_e > 0.0f ? ng : neg3(ng);
+    }
+    Frame fr = make_frame(n);
+    f3 wo_l = to_local(fr, wo);
+    if (pp.nee && sc.nl > 0 && type != PT_DIELECTRIC) {
+        uint32_t j = pick_light(sc, rn.w[0]);
+        uint32_t lt = sc.lights[j].tri;
+        const float4* lp = sc.tris + (size_t)lt * 3;
+        float4 la = lp[0], lb4 = lp[1], lc = lp[2];
+        f3 y = tri_point(xyz(la), xyz(lb4), xyz(lc), unif(rn.w[1]), unif(rn.w[2]));
+        f3 ny = tri_normal(xyz(la), xyz(lb4), xyz(lc));
+        f3 dv = sub3(y, x);
+        float d2 = dot3(dv, dv);
+        if (d2 > 0.0f) {
+            f3 wl = scl3(dv, 1.0f / sqrtf(d2));
+            float cos_y = -dot3(ny, wl);
+            float cos_x = dot3(n, wl);
+            if (cos_y > 0.0f && cos_x > 0.0f) {
+                f3 f;
+                float pb;
+                Lobe lob;
+                eval_opaque(type, rough, alb, wo_l, to_local(fr, wl), f, pb, lob);
+                float pl = d2 / (sc.area_total * cos_y);
+                if (lob.k > 0.0f && pl > 0.0f) {
+                    float wmis = (pl * pl) / (pl * pl + pb * pb);
+                    float G = (cos_x * wmis) / pl;
+                    uint32_t lid = f2u(la.w);
+                    f3 Le = load3(sc.emission, lid);
+                    sh.C = mk3((f.x * Le.x) * G, (f.y * Le.y) * G, (f.z * Le.z) * G);
+                    sh.contrib = mk3(ps.beta.x * sh.C.x, ps.beta.y * sh.C.y, ps.beta.z * sh.C.z);
+                    sh.o = offset_point(x, dot3(ng, wl) > 0.0f ? ng : neg3(ng));
+                    f3 sy = offset_point(y, ny);
+                    sh.d = sub3(sy, sh.o);
+                    sh.valid = true;
+                    sh.light_id = lid;
+                    sh.G = G;
+                    sh.lobe = lob;
+                }
+            }
+        }
+    }
+    f3 wi_l, W;
+    float pb;
+    Lobe lb;
+    bool ok = sample_local(type, rough, ior, entering, alb, wo_l, unif(rn.w[4]), unif(rn.w[5]), unif(rn.w[6]), wi_l,
+                           W, pb, lb);
+    if (!ok) return out;
+    if (W.x == 0.0f && W.y == 0.0f && W.z == 0.0f) return out;
+    if (type != PT_DIELECTRIC && !(pb > 0.0f)) return out;
+    ps.beta = mk3(ps.beta.x * W.x, ps.beta.y * W.y, ps.beta.z * W.z);
+    if (pp.rr_start >= 0 && k >= pp.rr_start) {
+        float q = max3c(ps.beta);
+        q = q < 1.0f ? q : 1.0f;
+        float u7 = unif(rn.w[7]);
+        if (u7 >= q) return out;
+        ps.beta = mk3(ps.beta.x / q, ps.beta.y / q, ps.beta.z / q);
+    }
+    f3 wi = to_world(fr, wi_l);
+    f3 no = dot3(ng, wi) > 0.0f ? ng : neg3(ng);
+    out.o = offset_point(x, no);
+    out.d = wi;
+    out.cont = true;
+    out.scat = lb;
+    ps.p_prev = pb;
+    ps.prev_smooth = type != PT_DIELECTRIC;
+    return out;
+}
+
+// One complete camera path (megakernel body): extend, shade, and trace the
+// light-sample segment at once; counts extension and shadow rays.
+template <int LDS>
+PT_DEV f3 trace_path(const SceneView& sc, const CamView& cam, const PathParams& pp, uint32_t pix, uint32_t sample,
+                     TravStack<LDS>& st, uint32_t& n_ext, uint32_t& n_sh) {
+    Rng8 r0 = philox8(pp.seed, pix, sample, 0u, pp.job);
+    f3 o, d;
+    camera_ray(cam, (int)(pix % (uint32_t)cam.W), (int)(pix / (uint32_t)cam.W), unif(r0.w[0]), unif(r0.w[1]), o, d);
+    PathState ps;
+    ps.beta = mk3(1.f, 1.f, 1.f);
+    ps.L = mk3(0.f, 0.f, 0.f);
+    ps.p_prev = 0.f;
+    ps.prev_smooth = 0;
+    for (int k = 1;; ++k) {
+        Ray ray = make_ray(o, d);
+        Hit h = closest_hit<LDS>(sc, ray, INFINITY, st);
+        ++n_ext;
+        ShadowReq sh;
+        VertexOut vo = shade_vertex(sc, pp, pix, sample, k, d, h, ps, sh);
+        if (sh.valid) {
+            ++n_sh;
+            Ray sr = make_ray(sh.o, sh.d);
+            if (!any_hit<LDS>(sc, sr, kShadowTmax, st))
+                ps.L = mk3(ps.L.x + sh.contrib.x, ps.L.y + sh.contrib.y, ps.L.z + sh.contrib.z);
+        }
+        if (!vo.cont) break;
+        o = vo.o;
+        d = vo.d;
+    }
+    return ps.L;
+}
+
+}  // namespace ptmi

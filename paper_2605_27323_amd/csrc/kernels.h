@@ -1,0 +1,45 @@
+// Kernel launchers of libptmi (definitions in kernels.hip).
+#pragma once
+#include "../../include/ptmi.h"
+#include "device.h"
+
+namespace ptmi {
+
+constexpr uint32_t kDeadPath = 0xFFFFFFFFu;
+
+// Wavefront path state, structure of arrays (one float4 stream per field
+// group, so that a wave's 64 lanes read or write 1 KiB contiguously).
+//   ray_o[q][i] = (origin, path id)     ray_d[q][i] = (direction, last pdf)
+//   pst[q][i]   = (throughput, flags)   hit[i] = (t, b1, b2, leaf-order tri)
+//   sh_o/sh_d/sh_c[i] = shadow segment origin + path id, direction, beta*C
+//   L[path]     = radiance of the path (indexed by path id, not queue slot)
+// q alternates between bounces (ping-pong queues).
+struct WaveBufs {
+    float4* ray_o[2];
+    float4* ray_d[2];
+    float4* pst[2];
+    float4* hit;
+    float4* sh_o;
+    float4* sh_d;
+    float4* sh_c;
+    float4* L;
+    uint32_t* counts;  // [b] live paths at bounce b, [sh_base + b] shadow rays, [err_slot]
+    int sh_base;
+    int err_slot;
+};
+
+hipError_t launch_mega(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const CamView& cam,
+                       const PathParams& pp, float* img, float* acc, uint2* ovf, int gcap, uint32_t* stats);
+hipError_t launch_init_counts(hipStream_t s, uint32_t* counts, int n, uint32_t first);
+hipError_t launch_raygen(dim3 grid, dim3 block, hipStream_t s, const CamView& cam, const PathParams& pp,
+                         const WaveBufs& wb);
+hipError_t launch_extend(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const WaveBufs& wb,
+                         int b, uint2* ovf, int gcap);
+hipError_t launch_shade(dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const PathParams& pp,
+                        const WaveBufs& wb, int b, int compact);
+hipError_t launch_shadow(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const WaveBufs& wb,
+                         int b, uint2* ovf, int gcap);
+hipError_t launch_accumulate(dim3 grid, dim3 block, hipStream_t s, const CamView& cam, const PathParams& pp,
+                             const float4* L, float* img, float* acc);
+
+}  // namespace ptmi

@@ -1,0 +1,227 @@
+// Render kernels of libptmi: the megakernel (paper Sec. 2.2: one thread per
+// pixel traces its paths to the end) and the wavefront stages (Sec. 2.3 and
+// 3.1: raygen, extend, shade, shadow, accumulate over structure-of-arrays
+// path state, live paths compacted into a queue after every bounce).
+#include "wavefront.h"
+
+namespace ptmi {
+
+namespace {
+
+__device__ __forceinline__ uint32_t lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+// position of this lane among the set lanes of a 64-bit ballot below it
+__device__ __forceinline__ uint32_t rank_in(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// one atomic per wave reserves room for the wave's set lanes; every set
+// lane gets base + its rank among them
+__device__ __forceinline__ uint32_t wave_reserve(uint32_t* ctr, uint64_t m) {
+    uint32_t base = 0;
+    if (lane_id() == 0) base = atomicAdd(ctr, (uint32_t)__popcll(m));
+    base = __builtin_amdgcn_readfirstlane(base);
+    return base + rank_in(m);
+}
+
+template <int LDS>
+__device__ __forceinline__ TravStack<LDS> make_stack(uint32_t* smem, uint2* ovf, int gcap, uint32_t gtid,
+                                                     uint32_t nlanes) {
+    TravStack<LDS> st;
+    st.lref = smem + threadIdx.x;
+    st.lt = reinterpret_cast<float*>(smem + LDS * blockDim.x) + threadIdx.x;
+    st.lstride = blockDim.x;
+    st.gbl = ovf + gtid;
+    st.gstride = (int)nlanes;
+    st.gcap = gcap;
+    st.sp = 0;
+    st.overflow = false;
+    return st;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// megakernel
+// ---------------------------------------------------------------------------
+template <int LDS>
+__global__ void __launch_bounds__(256) k_mega(SceneView sc, CamView cam, PathParams pp, float* __restrict__ img,
+                                              float* __restrict__ acc, uint2* __restrict__ ovf, int gcap,
+                                              uint32_t* __restrict__ stats) {
+    extern __shared__ uint32_t smem[];
+    const uint32_t nlanes = gridDim.x * blockDim.x;
+    const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
+    TravStack<LDS> st = make_stack<LDS>(smem, ovf, gcap, gtid, nlanes);
+    const uint32_t npix = (uint32_t)cam.W * (uint32_t)cam.H;
+    // uniform trip count per wave so that the ray counters can use shuffles
+    const uint32_t wave0 = gtid & ~63u;
+    for (uint32_t base = wave0; base < npix; base += nlanes) {
+        const uint32_t pix = base + (gtid & 63u);
+        uint32_t n_ext = 0, n_sh = 0;
+        if (pix < npix) {
+            f3 sum = mk3(0.f, 0.f, 0.f);
+            for (int s = 0; s < pp.spp; ++s) {
+                const uint32_t sample = pp.frame * (uint32_t)pp.spp + (uint32_t)s;
+                f3 L = trace_path<LDS>(sc, cam, pp, pix, sample, st, n_ext, n_sh);
+                sum = s == 0 ? L : add3(sum, L);
+            }
+            const float fs = (float)pp.spp;
+            store_pixel(img, acc, pix, mk3(sum.x / fs, sum.y / fs, sum.z / fs), pp.frame);
+        }
+        uint32_t e = n_ext, sh = n_sh;
+        for (int off = 32; off > 0; off >>= 1) {
+            e += __shfl_xor(e, off);
+            sh += __shfl_xor(sh, off);
+        }
+        if ((gtid & 63u) == 0) {
+            atomicAdd(&stats[0], e);
+            atomicAdd(&stats[1], sh);
+        }
+    }
+    if (st.overflow) atomicOr(&stats[2], 1u);
+}
+
+// ---------------------------------------------------------------------------
+// wavefront stages
+// ---------------------------------------------------------------------------
+__global__ void k_init_counts(uint32_t* __restrict__ counts, int n, uint32_t first) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) counts[i] = i == 0 ? first : 0u;
+}
+
+__global__ void __launch_bounds__(256) k_raygen(CamView cam, PathParams pp, WaveBufs wb) {
+    const uint32_t nlanes = gridDim.x * blockDim.x;
+    const uint32_t npaths = (uint32_t)cam.W * (uint32_t)cam.H * (uint32_t)pp.spp;
+    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < npaths; p += nlanes) raygen_item(cam, pp, wb, p);
+}
+
+template <int LDS>
+__global__ void __launch_bounds__(256) k_extend(SceneView sc, WaveBufs wb, int b, uint2* __restrict__ ovf, int gcap) {
+    extern __shared__ uint32_t smem[];
+    const uint32_t nlanes = gridDim.x * blockDim.x;
+    const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
+    TravStack<LDS> st = make_stack<LDS>(smem, ovf, gcap, gtid, nlanes);
+    const uint32_t count = wb.counts[b];
+    for (uint32_t i = gtid; i < count; i += nlanes) extend_item<LDS>(sc, wb, b, i, st);
+    if (st.overflow) atomicOr(&wb.counts[wb.err_slot], 1u);
+}
+
+__global__ void __launch_bounds__(256) k_shade(SceneView sc, PathParams pp, WaveBufs wb, int b, int compact) {
+    const uint32_t nlanes = gridDim.x * blockDim.x;
+    const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t count = wb.counts[b];
+    const int nxt = (b & 1) ^ 1;
+    uint32_t* next_count = &wb.counts[b + 1];
+    uint32_t* sh_count = &wb.counts[wb.sh_base + b];
+    if (!compact && gtid == 0 && count) atomicMax(next_count, count);
+    // wave-uniform trip count: every lane takes part in the ballots
+    for (uint32_t base = gtid & ~63u; base < count; base += nlanes) {
+        const uint32_t i = base + (gtid & 63u);
+        VertexOut vo;
+        ShadowReq sh;
+        PathState ps;
+        vo.cont = false;
+        sh.valid = false;
+        uint32_t path = kDeadPath;
+        if (i < count) path = shade_item(sc, pp, wb, b, i, vo, sh, ps);
+        if (compact) {
+            const uint64_t mk = __ballot(vo.cont);
+            if (mk) {
+                const uint32_t j = wave_reserve(next_count, mk);
+                if (vo.cont) write_continuation(wb, nxt, j, vo, ps, path);
+            }
+        } else if (i < count) {
+            // no compaction: slots stay in place, finished paths marked dead
+            if (vo.cont) write_continuation(wb, nxt, i, vo, ps, path);
+            else write_dead(wb, nxt, i);
+        }
+        const uint64_t ms = __ballot(sh.valid);
+        if (ms) {
+            const uint32_t j = wave_reserve(sh_count, ms);
+            if (sh.valid) write_shadow(wb, j, sh, path);
+        }
+    }
+}
+
+template <int LDS>
+__global__ void __launch_bounds__(256) k_shadow(SceneView sc, WaveBufs wb, int b, uint2* __restrict__ ovf, int gcap) {
+    extern __shared__ uint32_t smem[];
+    const uint32_t nlanes = gridDim.x * blockDim.x;
+    const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
+    TravStack<LDS> st = make_stack<LDS>(smem, ovf, gcap, gtid, nlanes);
+    const uint32_t count = wb.counts[wb.sh_base + b];
+    for (uint32_t i = gtid; i < count; i += nlanes) shadow_item<LDS>(sc, wb, i, st);
+    if (st.overflow) atomicOr(&wb.counts[wb.err_slot], 1u);
+}
+
+__global__ void __launch_bounds__(256) k_accumulate(CamView cam, PathParams pp, const float4* __restrict__ L,
+                                                    float* __restrict__ img, float* __restrict__ acc) {
+    const uint32_t nlanes = gridDim.x * blockDim.x;
+    const uint32_t npix = (uint32_t)cam.W * (uint32_t)cam.H;
+    for (uint32_t pix = blockIdx.x * blockDim.x + threadIdx.x; pix < npix; pix += nlanes)
+        accumulate_item(pp, L, img, acc, pix);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+#define PT_STACK_CASES(X) X(8) X(16) X(24) X(32)
+
+static size_t stack_lds_bytes(int lds, int block) { return (size_t)lds * 2 * sizeof(uint32_t) * block; }
+
+hipError_t launch_mega(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const CamView& cam,
+                       const PathParams& pp, float* img, float* acc, uint2* ovf, int gcap, uint32_t* stats) {
+    size_t sm = stack_lds_bytes(lds, block.x);
+#define X(N) \
+    if (lds == N) { hipLaunchKernelGGL(k_mega<N>, grid, block, sm, s, sc, cam, pp, img, acc, ovf, gcap, stats); return hipGetLastError(); }
+    PT_STACK_CASES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_init_counts(hipStream_t s, uint32_t* counts, int n, uint32_t first) {
+    hipLaunchKernelGGL(k_init_counts, dim3((n + 255) / 256), dim3(256), 0, s, counts, n, first);
+    return hipGetLastError();
+}
+
+hipError_t launch_raygen(dim3 grid, dim3 block, hipStream_t s, const CamView& cam, const PathParams& pp,
+                         const WaveBufs& wb) {
+    hipLaunchKernelGGL(k_raygen, grid, block, 0, s, cam, pp, wb);
+    return hipGetLastError();
+}
+
+hipError_t launch_extend(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const WaveBufs& wb,
+                         int b, uint2* ovf, int gcap) {
+    size_t sm = stack_lds_bytes(lds, block.x);
+#define X(N) \
+    if (lds == N) { hipLaunchKernelGGL(k_extend<N>, grid, block, sm, s, sc, wb, b, ovf, gcap); return hipGetLastError(); }
+    PT_STACK_CASES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_shade(dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const PathParams& pp,
+                        const WaveBufs& wb, int b, int compact) {
+    hipLaunchKernelGGL(k_shade, grid, block, 0, s, sc, pp, wb, b, compact);
+    return hipGetLastError();
+}
+
+hipError_t launch_shadow(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const WaveBufs& wb,
+                         int b, uint2* ovf, int gcap) {
+    size_t sm = stack_lds_bytes(lds, block.x);
+#define X(N) \
+    if (lds == N) { hipLaunchKernelGGL(k_shadow<N>, grid, block, sm, s, sc, wb, b, ovf, gcap); return hipGetLastError(); }
+    PT_STACK_CASES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_accumulate(dim3 grid, dim3 block, hipStream_t s, const CamView& cam, const PathParams& pp,
+                             const float4* L, float* img, float* acc) {
+    hipLaunchKernelGGL(k_accumulate, grid, block, 0, s, cam, pp, L, img, acc);
+    return hipGetLastError();
+}
+
+}  // namespace ptmi

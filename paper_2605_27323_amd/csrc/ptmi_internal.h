@@ -1,0 +1,63 @@
+// Internal layouts shared by the host code and the HIP kernels of libptmi.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ptmi {
+
+// 4-wide BVH node, one 128-byte line: child boxes as structure of arrays
+// over the four children, then four child references.
+//   ref = index of an internal node            (bit 31 clear)
+//   ref = LEAF | (count - 1) << 27 | first_tri (bit 31 set, 1..16 triangles)
+//   ref = EMPTY (all ones) for an unused slot; its box is +inf..+inf so the
+//   slab test rejects it without a branch.
+struct alignas(128) Node4 {
+    float lox[4], hix[4], loy[4], hiy[4], loz[4], hiz[4];
+    uint32_t ref[4];
+    uint32_t pad[4];
+};
+static_assert(sizeof(Node4) == 128, "node must be one 128-byte line");
+
+constexpr uint32_t kLeafBit = 0x80000000u;
+constexpr uint32_t kEmptyRef = 0xFFFFFFFFu;
+constexpr int kLeafCountShift = 27;
+constexpr uint32_t kLeafFirstMask = (1u << kLeafCountShift) - 1u;
+constexpr int kMaxLeaf = 8;
+constexpr int64_t kMaxTris = int64_t(kLeafFirstMask) + 1;
+
+// Triangle in leaf order, 48 bytes: three float4 = (v0, input id bits),
+// (v1, material index | light flag bit 31), (v2, 0).
+constexpr uint32_t kLightFlag = 0x80000000u;
+
+// Light table entry: leaf-order triangle index and the u32 CDF word.
+struct LightEntry {
+    uint32_t tri;
+    uint32_t cdf;
+};
+
+struct SceneView {
+    const float4* __restrict__ nodes;
+    const float4* __restrict__ tris;
+    const LightEntry* __restrict__ lights;
+    const float4* __restrict__ mats;
+    const float* __restrict__ albedo;    // input order, nt*3
+    const float* __restrict__ emission;  // input order, nt*3
+    int32_t nl;
+    int32_t nt;
+    int32_t n_nodes;
+    float area_total;
+    float sky0, sky1, sky2;
+};
+
+struct CamView {
+    float E[3], R[3], U[3], F[3];
+    int32_t W, H;
+};
+
+struct PathParams {
+    int32_t spp, D, nee, rr_start;
+    uint64_t seed;
+    uint32_t frame, job;
+};
+
+}  // namespace ptmi

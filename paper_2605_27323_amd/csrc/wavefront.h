@@ -1,0 +1,122 @@
+// Per-item bodies of the wavefront stages (paper Sec. 2.3 and 3.1), shared
+// by the HIP kernels and the CPU emulator used in tests.  The kernels add
+// only the grid-stride loops and the wave-level queue compaction.
+#pragma once
+#include "kernels.h"
+
+namespace ptmi {
+
+PT_DEV void store_pixel(float* __restrict__ img, float* __restrict__ acc, uint32_t pix, f3 I, uint32_t frame) {
+    img[3 * (size_t)pix + 0] = I.x;
+    img[3 * (size_t)pix + 1] = I.y;
+    img[3 * (size_t)pix + 2] = I.z;
+    if (acc) {
+        float* a = acc + 3 * (size_t)pix;
+        if (frame == 0) {
+            a[0] = I.x;
+            a[1] = I.y;
+            a[2] = I.z;
+        } else {
+            float n = (float)(frame + 1u);
+            a[0] = a[0] + (I.x - a[0]) / n;
+            a[1] = a[1] + (I.y - a[1]) / n;
+            a[2] = a[2] + (I.z - a[2]) / n;
+        }
+    }
+}
+
+// camera ray and initial state of path p = pixel * spp + s (queue 0 slot p)
+PT_DEV void raygen_item(const CamView& cam, const PathParams& pp, const WaveBufs& wb, uint32_t p) {
+    const uint32_t pix = p / (uint32_t)pp.spp;
+    const uint32_t s = p - pix * (uint32_t)pp.spp;
+    const uint32_t sample = pp.frame * (uint32_t)pp.spp + s;
+    Rng8 r0 = philox8(pp.seed, pix, sample, 0u, pp.job);
+    f3 o, d;
+    camera_ray(cam, (int)(pix % (uint32_t)cam.W), (int)(pix / (uint32_t)cam.W), unif(r0.w[0]), unif(r0.w[1]), o, d);
+    wb.ray_o[0][p] = make_float4(o.x, o.y, o.z, u2f(p));
+    wb.ray_d[0][p] = make_float4(d.x, d.y, d.z, 0.f);
+    wb.pst[0][p] = make_float4(1.f, 1.f, 1.f, u2f(0u));
+    wb.L[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// closest hit of queue slot i of bounce b
+template <int LDS>
+PT_DEV void extend_item(const SceneView& sc, const WaveBufs& wb, int b, uint32_t i, TravStack<LDS>& st) {
+    float4 o4 = wb.ray_o[b & 1][i], d4 = wb.ray_d[b & 1][i];
+    if (f2u(o4.w) == kDeadPath) return;
+    Ray ray = make_ray(xyz(o4), xyz(d4));
+    Hit h = closest_hit<LDS>(sc, ray, INFINITY, st);
+    wb.hit[i] = make_float4(h.t, h.b1, h.b2, u2f(h.tri));
+}
+
+// shade queue slot i of bounce b (vertex k = b + 1); returns the path id
+// (kDeadPath for a dead slot); vo / sh / ps describe what to enqueue
+PT_DEV uint32_t shade_item(const SceneView& sc, const PathParams& pp, const WaveBufs& wb, int b, uint32_t i,
+                           VertexOut& vo, ShadowReq& sh, PathState& ps) {
+    const int cur = b & 1;
+    float4 o4 = wb.ray_o[cur][i];
+    const uint32_t path = f2u(o4.w);
+    vo.cont = false;
+    sh.valid = false;
+    if (path == kDeadPath) return path;
+    float4 d4 = wb.ray_d[cur][i], p4 = wb.pst[cur][i], h4 = wb.hit[i];
+    const uint32_t pix = path / (uint32_t)pp.spp;
+    const uint32_t s = path - pix * (uint32_t)pp.spp;
+    const uint32_t sample = pp.frame * (uint32_t)pp.spp + s;
+    float4 l4 = wb.L[path];
+    ps.beta = xyz(p4);
+    ps.L = xyz(l4);
+    ps.p_prev = d4.w;
+    ps.prev_smooth = (int)f2u(p4.w);
+    Hit h;
+    h.t = h4.x;
+    h.b1 = h4.y;
+    h.b2 = h4.z;
+    h.tri = f2u(h4.w);
+    h.id = 0;
+    vo = shade_vertex(sc, pp, pix, sample, b + 1, xyz(d4), h, ps, sh);
+    if (vo.emitted || h.tri >= (uint32_t)sc.nt) wb.L[path] = make_float4(ps.L.x, ps.L.y, ps.L.z, 0.f);
+    return path;
+}
+
+PT_DEV void write_continuation(const WaveBufs& wb, int nxt, uint32_t j, const VertexOut& vo, const PathState& ps,
+                               uint32_t path) {
+    wb.ray_o[nxt][j] = make_float4(vo.o.x, vo.o.y, vo.o.z, u2f(path));
+    wb.ray_d[nxt][j] = make_float4(vo.d.x, vo.d.y, vo.d.z, ps.p_prev);
+    wb.pst[nxt][j] = make_float4(ps.beta.x, ps.beta.y, ps.beta.z, u2f((uint32_t)ps.prev_smooth));
+}
+
+PT_DEV void write_dead(const WaveBufs& wb, int nxt, uint32_t j) {
+    wb.ray_o[nxt][j] = make_float4(0.f, 0.f, 0.f, u2f(kDeadPath));
+}
+
+PT_DEV void write_shadow(const WaveBufs& wb, uint32_t j, const ShadowReq& sh, uint32_t path) {
+    wb.sh_o[j] = make_float4(sh.o.x, sh.o.y, sh.o.z, u2f(path));
+    wb.sh_d[j] = make_float4(sh.d.x, sh.d.y, sh.d.z, 0.f);
+    wb.sh_c[j] = make_float4(sh.contrib.x, sh.contrib.y, sh.contrib.z, 0.f);
+}
+
+// light-sample segment i: add beta * C to its path when unoccluded
+template <int LDS>
+PT_DEV void shadow_item(const SceneView& sc, const WaveBufs& wb, uint32_t i, TravStack<LDS>& st) {
+    float4 o4 = wb.sh_o[i], d4 = wb.sh_d[i];
+    Ray ray = make_ray(xyz(o4), xyz(d4));
+    if (!any_hit<LDS>(sc, ray, kShadowTmax, st)) {
+        const uint32_t path = f2u(o4.w);
+        float4 c4 = wb.sh_c[i];
+        float4 l4 = wb.L[path];
+        wb.L[path] = make_float4(l4.x + c4.x, l4.y + c4.y, l4.z + c4.z, 0.f);
+    }
+}
+
+// per-pixel mean over its spp paths, summed in sample order
+PT_DEV void accumulate_item(const PathParams& pp, const float4* __restrict__ L, float* __restrict__ img,
+                            float* __restrict__ acc, uint32_t pix) {
+    const float4* l = L + (size_t)pix * (uint32_t)pp.spp;
+    f3 sum = xyz(l[0]);
+    for (int s = 1; s < pp.spp; ++s) sum = add3(sum, xyz(l[s]));
+    const float fs = (float)pp.spp;
+    store_pixel(img, acc, pix, mk3(sum.x / fs, sum.y / fs, sum.z / fs), pp.frame);
+}
+
+}  // namespace ptmi

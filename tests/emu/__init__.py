@@ -1,0 +1,96 @@
+"""CPU emulator of the HIP kernels (tests only): builds libptmi_emu.so from
+the library sources plus emu.hip, compiled for the host."""
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+LIB = os.path.join(HERE, "libptmi_emu.so")
+_L = None
+
+
+def build():
+    from paper_2605_27323_amd import build as B
+    csrc = os.path.join(ROOT, "paper_2605_27323_amd", "csrc")
+    srcs = [os.path.join(HERE, "emu.hip"), os.path.join(csrc, "kernels.hip"), os.path.join(csrc, "bvh_build.cpp")]
+    for extra in ("adjoint.hip", "batch.hip"):
+        p = os.path.join(csrc, extra)
+        if os.path.exists(p):
+            srcs.append(p)
+    cmd = [B.HIPCC, *B.COMMON, "-shared", "-x", "hip", *srcs, "-o", LIB + ".tmp", "-lpthread"]
+    subprocess.run(cmd, check=True)
+    os.replace(LIB + ".tmp", LIB)
+
+
+def lib():
+    global _L
+    if _L is None:
+        from paper_2605_27323_amd import ptmi
+        ptmi.lib()  # torch's HIP runtime first
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        L.emu_render_mega.restype = C.c_int32
+        L.emu_render_mega.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_uint64,
+                                      C.c_uint32, C.c_uint32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]
+        L.emu_render_wave.restype = C.c_int32
+        L.emu_render_wave.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, C.c_uint32, C.c_uint32,
+                                      C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.c_void_p, C.c_void_p]
+        for name, (res, args) in ptmi.SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _L = L
+    return _L
+
+
+class Emu:
+    """Host-only library context (emulator build) with a scene and camera."""
+
+    def __init__(self, scene, cam):
+        from paper_2605_27323_amd import ptmi
+        L = lib()
+        h = C.c_void_p()
+        assert L.pt_create(C.byref(h), -1) == 0
+        self.h = h
+        keep = {k: np.ascontiguousarray(v) for k, v in scene.items()}
+        self._keep = keep
+        d = ptmi.SceneDesc(keep["positions"].shape[0], keep["indices"].shape[0], keep["materials"].shape[0],
+                           keep["positions"].ctypes.data, keep["indices"].ctypes.data, keep["tri_mat"].ctypes.data,
+                           keep["materials"].ctypes.data, keep["albedo"].ctypes.data, keep["emission"].ctypes.data,
+                           (C.c_float * 3)(*np.asarray(keep["sky"], np.float32).tolist()))
+        assert L.pt_load_scene(h, C.byref(d)) == 0, L.pt_last_error()
+        info = ptmi.BvhInfo()
+        assert L.pt_build_bvh(h, None, C.byref(info)) == 0
+        c = ptmi.Camera((C.c_double * 3)(*cam["eye"]), (C.c_double * 3)(*cam["target"]), (C.c_double * 3)(*cam["up"]),
+                        float(cam["vfov_deg"]), int(cam["width"]), int(cam["height"]))
+        assert L.pt_set_camera(h, C.byref(c)) == 0
+        self.W, self.H = int(cam["width"]), int(cam["height"])
+
+    def mega(self, pixels=None, spp=1, max_depth=5, seed=0, frame=0, job=0, nee=True, rr_start=-1):
+        if pixels is None:
+            pixels = np.arange(self.W * self.H, dtype=np.int32)
+        pixels = np.ascontiguousarray(pixels, np.int32)
+        out = np.zeros((pixels.size, 3), np.float32)
+        rays = np.zeros(2, np.uint64)
+        rc = lib().emu_render_mega(self.h, pixels.ctypes.data, pixels.size, spp, max_depth, seed, frame, job,
+                                   int(bool(nee)), rr_start, out.ctypes.data, rays.ctypes.data)
+        assert rc == 0
+        return out, rays
+
+    def wave(self, spp=1, max_depth=5, seed=0, frame=0, job=0, nee=True, rr_start=-1, compact=True, shuffle=0):
+        img = np.zeros((self.W * self.H, 3), np.float32)
+        rays = np.zeros(2, np.uint64)
+        rc = lib().emu_render_wave(self.h, spp, max_depth, seed, frame, job, int(bool(nee)), rr_start,
+                                   int(bool(compact)), shuffle, img.ctypes.data, rays.ctypes.data)
+        assert rc == 0
+        return img, rays
+
+    def __del__(self):
+        try:
+            lib().pt_destroy(self.h)
+        except Exception:
+            pass

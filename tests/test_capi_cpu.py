@@ -1,0 +1,178 @@
+"""CPU checks of the C-ABI library: it loads, exports every function the
+header declares, validates its inputs, and builds a well-formed BVH4 with
+the same light set and CDF as the oracle (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_27323_amd import scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ptmi = pytest.importorskip("paper_2605_27323_amd.ptmi")
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "ptmi.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pt_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_header_function():
+    L = ptmi.lib()
+    names = header_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(L, n), n
+    # the binding declares exactly these
+    assert set(names) == set(ptmi.SIGNATURES)
+
+
+def test_create_without_gpu_reports_hip_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = C.c_void_p()
+    rc = ptmi.lib().pt_create(C.byref(h), 0)
+    assert rc == ptmi.PT_EHIP
+    assert len(ptmi.lib().pt_last_error()) > 0
+
+
+def _desc(scene):
+    keep = {k: np.ascontiguousarray(v) for k, v in scene.items()}
+    d = ptmi.SceneDesc(keep["positions"].shape[0], keep["indices"].shape[0], keep["materials"].shape[0],
+                       keep["positions"].ctypes.data, keep["indices"].ctypes.data, keep["tri_mat"].ctypes.data,
+                       keep["materials"].ctypes.data, keep["albedo"].ctypes.data, keep["emission"].ctypes.data,
+                       (C.c_float * 3)(*keep["sky"].tolist()))
+    return d, keep
+
+
+def test_invalid_inputs_rejected():
+    L = ptmi.lib()
+    h = C.c_void_p()
+    assert L.pt_create(C.byref(h), -1) == 0
+    scene, cam = scenes.cornell()
+    bad = {k: v.copy() for k, v in scene.items()}
+    bad["indices"][3, 1] = 10_000
+    d, keep = _desc(bad)
+    assert L.pt_load_scene(h, C.byref(d)) == ptmi.PT_EINVAL
+    bad = {k: v.copy() for k, v in scene.items()}
+    bad["positions"][5, 2] = np.nan
+    d, keep = _desc(bad)
+    assert L.pt_load_scene(h, C.byref(d)) == ptmi.PT_EINVAL
+    bad = {k: v.copy() for k, v in scene.items()}
+    bad["materials"] = np.array([[7, 0.5, 1.5, 0]], np.float32)
+    d, keep = _desc(bad)
+    assert L.pt_load_scene(h, C.byref(d)) == ptmi.PT_EINVAL
+    bad = {k: v.copy() for k, v in scene.items()}
+    bad["emission"][0, 0] = -1
+    d, keep = _desc(bad)
+    assert L.pt_load_scene(h, C.byref(d)) == ptmi.PT_EINVAL
+    # build before load, render on a host-only context, null pointers
+    info = ptmi.BvhInfo()
+    assert L.pt_build_bvh(h, None, C.byref(info)) == ptmi.PT_ESTATE
+    d, keep = _desc(scene)
+    assert L.pt_load_scene(h, C.byref(d)) == 0
+    assert L.pt_build_bvh(h, None, C.byref(info)) == 0
+    a = ptmi.RenderArgs(1, 1, 0, 0, 0, 1, -1, 0, 0, 0, 0)
+    assert L.pt_render_frame(h, C.byref(a), None, None, None, 0, None) == ptmi.PT_ESTATE
+    assert L.pt_load_scene(h, None) == ptmi.PT_EINVAL
+    camd = ptmi.Camera((C.c_double * 3)(0, 0, 0), (C.c_double * 3)(0, 0, 0), (C.c_double * 3)(0, 1, 0), 40.0, 8, 8)
+    assert L.pt_set_camera(h, C.byref(camd)) == ptmi.PT_EINVAL  # eye == target
+    camd = ptmi.Camera((C.c_double * 3)(0, 0, 0), (C.c_double * 3)(0, 0, 1), (C.c_double * 3)(0, 1, 0), 200.0, 8, 8)
+    assert L.pt_set_camera(h, C.byref(camd)) == ptmi.PT_EINVAL  # fov
+    opts = ptmi.BvhOpts(9, 0)
+    assert L.pt_build_bvh(h, C.byref(opts), C.byref(info)) == ptmi.PT_EINVAL
+    assert L.pt_destroy(h) == 0
+
+
+def _walk(nodes, nt):
+    """Decode the BVH4 (test-side reader of the node layout): returns
+    leaf ranges and, per leaf, the chain of ancestor boxes."""
+    f = nodes.view(np.float32).reshape(-1, 32)
+    u = nodes.view(np.uint32).reshape(-1, 32)
+    leaves = []
+    depth = 0
+    stack = [(0, [], 1)]
+    while stack:
+        ni, boxes, lvl = stack.pop()
+        depth = max(depth, lvl)
+        for c in range(4):
+            ref = int(u[ni, 24 + c])
+            lo = np.array([f[ni, 0 + c], f[ni, 8 + c], f[ni, 16 + c]])
+            hi = np.array([f[ni, 4 + c], f[ni, 12 + c], f[ni, 20 + c]])
+            if ref == 0xFFFFFFFF:
+                assert np.isinf(lo).all()
+                continue
+            if ref & 0x80000000:
+                first = ref & ((1 << 27) - 1)
+                cnt = ((ref >> 27) & 15) + 1
+                leaves.append((first, cnt, boxes + [(lo, hi)]))
+            else:
+                assert 0 < ref < nodes.shape[0]
+                stack.append((ref, boxes + [(lo, hi)], lvl + 1))
+    return leaves, depth
+
+
+@pytest.mark.parametrize("which", ["cornell", "procedural", "soup", "single", "empty"])
+def test_bvh4_structure(which):
+    if which == "cornell":
+        scene, _ = scenes.cornell()
+    elif which == "procedural":
+        scene, _ = scenes.procedural(seed=3, n_objects=30)
+    elif which == "soup":
+        scene = scenes.random_soup(5, 300, emissive_frac=0.2)
+    elif which == "single":
+        scene = scenes.random_soup(6, 1, emissive_frac=1.0)
+    else:
+        scene = scenes.random_soup(7, 1)
+        scene = dict(scene, indices=np.zeros((0, 3), np.int32), tri_mat=np.zeros(0, np.int32),
+                     albedo=np.zeros((0, 3), np.float32), emission=np.zeros((0, 3), np.float32))
+    ctx = ptmi.Context(scene, device=-1)
+    nodes, tris, lights = ctx.host_bvh()
+    nt = scene["indices"].shape[0]
+    leaves, depth = _walk(nodes, nt)
+    assert depth == ctx.info.depth
+    assert ctx.info.stack_entries == 3 * depth + 1
+    covered = np.zeros(nt, int)
+    ids = tris[:, 3].view(np.uint32) if nt else np.zeros(0, np.uint32)
+    pos = scene["positions"]
+    idx = scene["indices"]
+    for first, cnt, boxes in leaves:
+        assert cnt <= 4
+        for j in range(first, first + cnt):
+            covered[j] += 1
+            tid = int(ids[j])
+            v = pos[idx[tid]].astype(np.float32)
+            assert np.array_equal(tris[j, [0, 1, 2]], v[0])
+            assert np.array_equal(tris[j, [4, 5, 6]], v[1])
+            assert np.array_equal(tris[j, [8, 9, 10]], v[2])
+            for lo, hi in boxes:  # every ancestor box encloses the triangle
+                assert (v >= lo).all() and (v <= hi).all()
+    assert (covered == 1).all()
+    if nt:
+        assert sorted(ids.tolist()) == list(range(nt))
+        minfo = tris[:, 7].view(np.uint32)
+        assert np.array_equal(minfo & 0x7FFFFFFF, scene["tri_mat"][ids])
+        is_light = (scene["emission"] > 0).any(1)
+        assert np.array_equal((minfo >> 31).astype(bool), is_light[ids])
+
+
+def test_light_cdf_matches_oracle():
+    scene = scenes.random_soup(11, 200, emissive_frac=0.3)
+    ctx = ptmi.Context(scene, device=-1)
+    _, tris, lights = ctx.host_bvh()
+    S = oracle.Scene(scene, bvh=False)
+    assert lights.shape[0] == S.num_lights
+    ids = tris[:, 3].view(np.uint32)
+    light_ids = ids[lights[:, 0]]
+    assert (np.diff(light_ids.astype(np.int64)) > 0).all()  # input order
+    rng = np.random.default_rng(0)
+    words = np.concatenate([rng.integers(0, 2**32, 5000, dtype=np.uint64),
+                            lights[:, 1].astype(np.uint64), (lights[:-1, 1].astype(np.uint64) + 1)])
+    for w in words:
+        j_lib = int(np.searchsorted(lights[:, 1], np.uint32(w), side="left"))
+        assert j_lib == S.pick_light(int(w))

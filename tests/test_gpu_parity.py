@@ -1,0 +1,189 @@
+"""GPU parity: the HIP megakernel and wavefront (through the C ABI) against
+the CPU oracle, element by element on the same seeded inputs.
+
+Bar (per pixel, all channels): |g - o| <= 1e-4 max(|g|, |o|) + 1e-6 mean(o)
+on at least 99.9% of pixels, every failing pixel flagged fragile by the
+oracle (a float decision within rounding distance of flipping).  The two
+schedules must agree bit for bit with each other.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_27323_amd import scenes
+from tests._parity import assert_parity, image_tolerance_report
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2605_27323_amd import ptmi  # noqa: E402
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def render_both(R, **kw):
+    mega = R.render(mode="mega", **kw).cpu().numpy()
+    wave = R.render(mode="wave", **kw).cpu().numpy()
+    torch.cuda.synchronize()
+    return mega, wave
+
+
+def test_cornell_full_image_mega_wave_vs_oracle():
+    scene, cam = scenes.cornell()
+    log("cornell 128x128 spp4 D5 nee")
+    R = ptmi.Renderer(scene, cam)
+    mega, wave = render_both(R, spp=4, max_depth=5, seed=0)
+    assert np.array_equal(mega.view(np.uint32), wave.view(np.uint32))
+    S = oracle.Scene(scene)
+    ref, frag = S.render(cam, spp=4, max_depth=5, seed=0)
+    nexact = assert_parity(wave, ref, frag, what="cornell")
+    assert nexact >= 0.999 * ref.shape[0]
+
+
+@pytest.mark.parametrize("a,D", [(0.5, 3), (0.9, 8)])
+def test_white_furnace_exact(a, D):
+    le = 1.5
+    scene, cam = scenes.furnace(albedo=a, le=le, n=2, width=19, height=13)
+    log("furnace", a, D)
+    R = ptmi.Renderer(scene, cam)
+    mega, wave = render_both(R, spp=2, max_depth=D, seed=3, nee=False)
+    af = float(np.float32(a))
+    expect = le * sum(af ** k for k in range(D + 1))
+    for img in (mega, wave):
+        assert np.abs(img - expect).max() <= (2 * D + 6) * 2.0 ** -24 * expect
+
+
+def test_plane_under_sky_exact():
+    scene, cam = scenes.plane_under_sky(albedo=0.6, sky=1.25, width=37, height=23)
+    log("plane under sky")
+    R = ptmi.Renderer(scene, cam)
+    S = oracle.Scene(scene)
+    for D in (0, 1, 2):
+        mega, wave = render_both(R, spp=1, max_depth=D, seed=1)
+        ref, frag = S.render(cam, spp=1, max_depth=D, seed=1)
+        assert np.array_equal(wave.reshape(-1, 3), ref)
+        assert np.array_equal(mega.reshape(-1, 3), ref)
+
+
+@pytest.mark.parametrize("cfg", [
+    dict(spp=3, max_depth=8, rr_start=3, nee=True, seed=7, frame=0),
+    dict(spp=1, max_depth=4, rr_start=-1, nee=False, seed=11, frame=2),
+    dict(spp=2, max_depth=0, rr_start=-1, nee=True, seed=5, frame=1),
+])
+def test_procedural_small_all_pixels(cfg):
+    scene, cam = scenes.procedural(seed=21, n_objects=40, width=97, height=61)
+    log("procedural 40 objects", scene["indices"].shape[0], "tris", cfg)
+    R = ptmi.Renderer(scene, cam)
+    mega, wave = render_both(R, **cfg)
+    assert np.array_equal(mega.view(np.uint32), wave.view(np.uint32))
+    S = oracle.Scene(scene)
+    ref, frag = S.render(cam, **cfg)
+    assert_parity(wave, ref, frag, what=f"procedural {cfg}")
+
+
+def test_divergence_materials_with_dielectrics():
+    scene, cam = scenes.procedural(seed=31, n_objects=60, width=80, height=48, material_mode="divergence")
+    log("divergence 60 objects", scene["indices"].shape[0])
+    R = ptmi.Renderer(scene, cam)
+    cfg = dict(spp=2, max_depth=12, rr_start=3, nee=True, seed=9)
+    mega, wave = render_both(R, **cfg)
+    assert np.array_equal(mega.view(np.uint32), wave.view(np.uint32))
+    S = oracle.Scene(scene)
+    ref, frag = S.render(cam, **cfg)
+    assert_parity(wave, ref, frag, what="divergence")
+
+
+def test_full_size_procedural_sampled_pixels():
+    # the benchmark workload: ~1M triangles, 1920x1080, 1 spp, depth 8, roulette from 3
+    scene, cam = scenes.procedural(seed=2, n_objects=2000)
+    log("procedural 1M", scene["indices"].shape[0], "tris 1920x1080")
+    R = ptmi.Renderer(scene, cam)
+    S = oracle.Scene(scene)
+    px = scenes.pixel_subset(1920, 1080, 16384, seed=1234)
+    for frame in (0, 5):
+        cfg = dict(spp=1, max_depth=8, rr_start=3, nee=True, seed=0, frame=frame)
+        mega, wave = render_both(R, **cfg)
+        assert np.array_equal(mega.view(np.uint32), wave.view(np.uint32))
+        ref, frag = S.render(cam, pixels=px, **cfg)
+        assert_parity(wave.reshape(-1, 3)[px], ref, frag, what=f"1M frame {frame}")
+
+
+def test_edge_cases():
+    log("edge cases")
+    # empty scene: every pixel sees the sky
+    base = scenes.random_soup(3, 4)
+    empty = dict(base, indices=np.zeros((0, 3), np.int32), tri_mat=np.zeros(0, np.int32),
+                 albedo=np.zeros((0, 3), np.float32), emission=np.zeros((0, 3), np.float32),
+                 sky=np.array([0.25, 0.5, 1.0], np.float32))
+    cam = dict(eye=(0, 0, -3.0), target=(0, 0, 0), up=(0, 1, 0), vfov_deg=45.0, width=5, height=3)
+    R = ptmi.Renderer(empty, cam)
+    mega, wave = render_both(R, spp=2, max_depth=3)
+    assert (mega == empty["sky"]).all() and (wave == empty["sky"]).all()
+    # single pixel, single triangle, no lights
+    one = scenes.random_soup(4, 1, emissive_frac=0.0)
+    one["sky"] = np.array([1.0, 1.0, 1.0], np.float32)
+    cam1 = dict(eye=(0, 0, -3.0), target=(0, 0, 0), up=(0, 1, 0), vfov_deg=60.0, width=1, height=1)
+    R1 = ptmi.Renderer(one, cam1)
+    S1 = oracle.Scene(one)
+    for spp in (1, 5):
+        mega, wave = render_both(R1, spp=spp, max_depth=2)
+        ref, _ = S1.render(cam1, spp=spp, max_depth=2)
+        assert np.array_equal(wave.reshape(-1, 3), ref) and np.array_equal(mega.reshape(-1, 3), ref)
+
+
+def test_no_compaction_and_launch_shapes_bit_identical():
+    scene, cam = scenes.procedural(seed=41, n_objects=30, width=64, height=40)
+    log("launch shapes")
+    R = ptmi.Renderer(scene, cam)
+    cfg = dict(spp=2, max_depth=6, rr_start=2, seed=3)
+    ref = R.render(mode="wave", **cfg).cpu().numpy()
+    outs = [R.render(mode="wave", flags=ptmi.FLAG_NO_COMPACT, **cfg),
+            R.render(mode="wave", block=64, grid_mult=1, **cfg),
+            R.render(mode="wave", block=256, grid_mult=3, **cfg),
+            R.render(mode="mega", block=64, grid_mult=2, **cfg),
+            R.render(mode="wave", **cfg)]
+    for o in outs:
+        assert np.array_equal(o.cpu().numpy().view(np.uint32), ref.view(np.uint32))
+
+
+def test_progressive_accumulation_and_ray_counts():
+    scene, cam = scenes.cornell()
+    cam = dict(cam, width=33, height=17)
+    log("progressive")
+    R = ptmi.Renderer(scene, cam)
+    S = oracle.Scene(scene)
+    acc = torch.zeros((17, 33, 3), dtype=torch.float32, device="cuda")
+    ref_acc = None
+    for frame in range(4):
+        R.render(mode="wave" if frame % 2 else "mega", accum=acc, spp=2, max_depth=4, frame=frame,
+                 flags=ptmi.FLAG_COUNT_RAYS)
+        I, _ = S.render(cam, spp=2, max_depth=4, frame=frame)
+        if ref_acc is None:
+            ref_acc = I.copy()
+        else:
+            n = np.float32(frame + 1)
+            ref_acc = (ref_acc + (I - ref_acc) / n).astype(np.float32)
+    got = acc.cpu().numpy().reshape(-1, 3)
+    frac, nfail, unexplained, nexact = image_tolerance_report(got, ref_acc, np.zeros(len(ref_acc)))
+    assert nexact >= 0.999 * len(ref_acc)
+    # identical paths => identical ray counts in both schedules
+    R.render(mode="mega", spp=2, max_depth=4, flags=ptmi.FLAG_COUNT_RAYS)
+    sm = R.stats()
+    R.render(mode="wave", spp=2, max_depth=4, flags=ptmi.FLAG_COUNT_RAYS)
+    sw = R.stats()
+    assert sm["extension_rays"] == sw["extension_rays"] > 0
+    assert sm["shadow_rays"] == sw["shadow_rays"] > 0
+
+
+def test_profile_stage_times():
+    scene, cam = scenes.procedural(seed=51, n_objects=20, width=48, height=32)
+    R = ptmi.Renderer(scene, cam)
+    R.render(mode="wave", spp=1, max_depth=5, rr_start=3, flags=ptmi.FLAG_PROFILE)
+    st = R.stats()
+    assert st["launches"]["extend"] == 6 and st["launches"]["shade"] == 6
+    assert all(v >= 0 for v in st["stage_ms"].values())
