@@ -1,0 +1,81 @@
+// Path-replay adjoint of one camera path (Vicini, Speierer, Jakob, "Path
+// Replay Backpropagation", SIGGRAPH 2021), shared by the HIP kernel and the
+// CPU emulator.  With sampling independent of albedo and emission (cosine
+// and visible-normal sampling, area-proportional light picks, no roulette)
+// the path is fixed by its random numbers, so it is replayed twice instead
+// of being stored: replay A recomputes the radiance L of the path, replay B
+// walks it again and, at each vertex x_k with throughput beta_k,
+//   emission w Le(tri_k):      dLe(tri_k)   += delta beta_k w
+//   light sample f Le(y) G:    dLe(tri_y)   += delta beta_k f G
+//                              dalb(tri_k)  += delta beta_k df/dalb G Le(y)
+//   continuation weight W_k:   dalb(tri_k)  += delta (L - L_acc) dW/dalb / W
+// where L_acc is the radiance gathered up to and including x_k's light
+// sample and delta = dLoss/dI(pixel) / spp.  Channels with W = 0 carry no
+// gradient through W (the division of the method).
+#pragma once
+#include "device.h"
+
+namespace ptmi {
+
+template <int LDS, class Acc>
+PT_DEV void adjoint_path(const SceneView& sc, const CamView& cam, const PathParams& pp, uint32_t pix, uint32_t sample,
+                         f3 delta, float* __restrict__ g_alb, float* __restrict__ g_emi, TravStack<LDS>& st,
+                         Acc& acc) {
+    uint32_t ne = 0, ns = 0;
+    const f3 Ltot = trace_path<LDS>(sc, cam, pp, pix, sample, st, ne, ns);
+    Rng8 r0 = philox8(pp.seed, pix, sample, 0u, pp.job);
+    f3 o, d;
+    camera_ray(cam, (int)(pix % (uint32_t)cam.W), (int)(pix / (uint32_t)cam.W), unif(r0.w[0]), unif(r0.w[1]), o, d);
+    PathState ps;
+    ps.beta = mk3(1.f, 1.f, 1.f);
+    ps.L = mk3(0.f, 0.f, 0.f);
+    ps.p_prev = 0.f;
+    ps.prev_smooth = 0;
+    for (int k = 1;; ++k) {
+        Ray ray = make_ray(o, d);
+        Hit h = closest_hit<LDS>(sc, ray, INFINITY, st);
+        const f3 beta = ps.beta;
+        ShadowReq sh;
+        VertexOut vo = shade_vertex(sc, pp, pix, sample, k, d, h, ps, sh);
+        if (vo.id == 0xFFFFFFFFu) break;  // escaped: the sky is not a parameter
+        const uint32_t id = vo.id;
+        if (vo.emitted) {
+            acc.add(g_emi + 3 * (size_t)id + 0, delta.x * (beta.x * vo.w_emit));
+            acc.add(g_emi + 3 * (size_t)id + 1, delta.y * (beta.y * vo.w_emit));
+            acc.add(g_emi + 3 * (size_t)id + 2, delta.z * (beta.z * vo.w_emit));
+        }
+        if (sh.valid) {
+            Ray sr = make_ray(sh.o, sh.d);
+            if (!any_hit<LDS>(sc, sr, kShadowTmax, st)) {
+                ps.L = mk3(ps.L.x + sh.contrib.x, ps.L.y + sh.contrib.y, ps.L.z + sh.contrib.z);
+                const f3 rho = load3(sc.albedo, id);
+                const f3 Le = load3(sc.emission, sh.light_id);
+                const float der = lobe_der(sh.lobe);
+                const uint32_t lid = sh.light_id;
+                acc.add(g_emi + 3 * (size_t)lid + 0, delta.x * (beta.x * (lobe_value(sh.lobe, rho.x) * sh.G)));
+                acc.add(g_emi + 3 * (size_t)lid + 1, delta.y * (beta.y * (lobe_value(sh.lobe, rho.y) * sh.G)));
+                acc.add(g_emi + 3 * (size_t)lid + 2, delta.z * (beta.z * (lobe_value(sh.lobe, rho.z) * sh.G)));
+                if (der != 0.0f) {
+                    acc.add(g_alb + 3 * (size_t)id + 0, delta.x * (beta.x * ((der * sh.G) * Le.x)));
+                    acc.add(g_alb + 3 * (size_t)id + 1, delta.y * (beta.y * ((der * sh.G) * Le.y)));
+                    acc.add(g_alb + 3 * (size_t)id + 2, delta.z * (beta.z * ((der * sh.G) * Le.z)));
+                }
+            }
+        }
+        if (!vo.cont) break;
+        const float der = lobe_der(vo.scat);
+        if (der != 0.0f) {
+            const f3 rho = load3(sc.albedo, id);
+            const float W[3] = {lobe_value(vo.scat, rho.x), lobe_value(vo.scat, rho.y), lobe_value(vo.scat, rho.z)};
+            const float post[3] = {Ltot.x - ps.L.x, Ltot.y - ps.L.y, Ltot.z - ps.L.z};
+            const float dl[3] = {delta.x, delta.y, delta.z};
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                if (W[c] != 0.0f) acc.add(g_alb + 3 * (size_t)id + c, dl[c] * (post[c] * (der / W[c])));
+        }
+        o = vo.o;
+        d = vo.d;
+    }
+}
+
+}  // namespace ptmi

@@ -1,0 +1,62 @@
+// Adjoint kernel of libptmi: one thread per camera path sample, two replays
+// of the path from its random numbers, gradients added with hardware fp32
+// atomics (see adjoint.h for the algorithm).
+#include "adjoint.h"
+#include "kernels.h"
+
+namespace ptmi {
+
+namespace {
+
+struct AtomicAcc {
+    __device__ __forceinline__ void add(float* p, float v) {
+        if (v != 0.0f) unsafeAtomicAdd(p, v);
+    }
+};
+
+}  // namespace
+
+template <int LDS>
+__global__ void __launch_bounds__(256) k_adjoint(SceneView sc, CamView cam, PathParams pp,
+                                                 const float* __restrict__ d_img, float* __restrict__ g_alb,
+                                                 float* __restrict__ g_emi, uint2* __restrict__ ovf, int gcap,
+                                                 uint32_t* __restrict__ stats) {
+    extern __shared__ uint32_t smem[];
+    const uint32_t nlanes = gridDim.x * blockDim.x;
+    const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
+    TravStack<LDS> st;
+    st.lref = smem + threadIdx.x;
+    st.lt = reinterpret_cast<float*>(smem + LDS * blockDim.x) + threadIdx.x;
+    st.lstride = blockDim.x;
+    st.gbl = ovf + gtid;
+    st.gstride = (int)nlanes;
+    st.gcap = gcap;
+    st.sp = 0;
+    st.overflow = false;
+    AtomicAcc acc;
+    const uint32_t npaths = (uint32_t)cam.W * (uint32_t)cam.H * (uint32_t)pp.spp;
+    const float fs = (float)pp.spp;
+    for (uint32_t p = gtid; p < npaths; p += nlanes) {
+        const uint32_t pix = p / (uint32_t)pp.spp;
+        const uint32_t s = p - pix * (uint32_t)pp.spp;
+        const f3 delta = mk3(d_img[3 * (size_t)pix] / fs, d_img[3 * (size_t)pix + 1] / fs, d_img[3 * (size_t)pix + 2] / fs);
+        adjoint_path<LDS>(sc, cam, pp, pix, pp.frame * (uint32_t)pp.spp + s, delta, g_alb, g_emi, st, acc);
+    }
+    if (st.overflow) atomicOr(&stats[2], 1u);
+}
+
+hipError_t launch_adjoint(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const CamView& cam,
+                          const PathParams& pp, const float* d_img, float* g_alb, float* g_emi, uint2* ovf, int gcap,
+                          uint32_t* stats) {
+    size_t sm = (size_t)lds * 2 * sizeof(uint32_t) * block.x;
+#define X(N)                                                                                                  \
+    if (lds == N) {                                                                                           \
+        hipLaunchKernelGGL(k_adjoint<N>, grid, block, sm, s, sc, cam, pp, d_img, g_alb, g_emi, ovf, gcap, stats); \
+        return hipGetLastError();                                                                             \
+    }
+    X(8) X(16) X(24) X(32)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+}  // namespace ptmi

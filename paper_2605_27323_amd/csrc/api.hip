@@ -437,8 +437,38 @@ pt_status pt_render_backward(pt_ctx* c, const pt_render_args* a, const float* d_
                              float* d_emission, void* ws, uint64_t ws_bytes, void* stream) {
     pt_status st = check_args(c, a);
     if (st) return st;
-    (void)d_image; (void)d_albedo; (void)d_emission; (void)ws; (void)ws_bytes; (void)stream;
-    return fail(PT_EUNSUPPORTED, "adjoint not built yet");
+    if (a->rr_start >= 0) return fail(PT_EINVAL, "the adjoint needs Russian roulette off (rr_start < 0)");
+    if (!d_image || !d_albedo || !d_emission) return fail(PT_EINVAL, "null gradient buffer");
+    if (!ws) return fail(PT_EINVAL, "null workspace");
+    if ((reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return fail(PT_EINVAL, "workspace must be 256-byte aligned");
+    pt_render_args am = *a;
+    am.mode = PT_MODE_MEGA;
+    Launch L;
+    st = launch_config(c, &am, L);
+    if (st) return st;
+    WsLayout w = layout(c, &am, L);
+    if (ws_bytes < w.total) return fail(PT_ENOMEM, "workspace too small (pt_workspace_size)");
+    PT_HIP(hipSetDevice(c->device), "hipSetDevice");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char* base = static_cast<char*>(ws);
+    uint32_t* counts = reinterpret_cast<uint32_t*>(base + w.counts);
+    uint2* ovf = reinterpret_cast<uint2*>(base + w.ovf);
+    PathParams pp{a->spp, a->max_depth, a->nee ? 1 : 0, -1, a->seed, a->frame, a->job};
+    const bool prof = (a->flags & PT_FLAG_PROFILE) != 0;
+    c->timers.clear();
+    c->event_next = 0;
+    PT_HIP(launch_init_counts(s, counts, w.ncounts, 0u), "init counters");
+    PT_HIP(timed(c, prof, 7, s, [&] {
+               return launch_adjoint(L.lds, dim3(L.grid), dim3(L.block), s, c->view, c->cam, pp, d_image, d_albedo,
+                                     d_emission, ovf, L.gcap, counts);
+           }),
+           "adjoint");
+    c->last_counts = counts;
+    c->last_ncounts = w.ncounts;
+    c->last_D = a->max_depth;
+    c->last_mode = PT_MODE_MEGA;
+    c->last_valid = true;
+    return PT_OK;
 }
 
 pt_status pt_frame_stats_get(pt_ctx* c, pt_frame_stats* out) {

@@ -15,6 +15,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include "ptmi.h"
 #include "ptmi_internal.h"
 
 namespace ptmi {
@@ -522,6 +523,18 @@ struct Lobe {
     int type;
     float m5, k;
 };
+
+// value and albedo derivative of a lobe at albedo rho (one channel)
+PT_DEV float lobe_value(const Lobe& lb, float rho) {
+    if (lb.type == PT_LAMBERT) return rho * lb.k;
+    if (lb.type == PT_CONDUCTOR) return (rho + (1.0f - rho) * lb.m5) * lb.k;
+    return lb.k;
+}
+PT_DEV float lobe_der(const Lobe& lb) {
+    if (lb.type == PT_LAMBERT) return lb.k;
+    if (lb.type == PT_CONDUCTOR) return (1.0f - lb.m5) * lb.k;
+    return 0.0f;
+}
 
 // f and the solid-angle pdf of an opaque material, wo and wi in the local
 // frame of the normal on wo's side.

@@ -39,6 +39,9 @@ hipError_t launch_shade(dim3 grid, dim3 block, hipStream_t s, const SceneView& s
                         const WaveBufs& wb, int b, int compact);
 hipError_t launch_shadow(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const WaveBufs& wb,
                          int b, uint2* ovf, int gcap);
+hipError_t launch_adjoint(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const CamView& cam,
+                          const PathParams& pp, const float* d_img, float* g_alb, float* g_emi, uint2* ovf, int gcap,
+                          uint32_t* stats);
 hipError_t launch_accumulate(dim3 grid, dim3 block, hipStream_t s, const CamView& cam, const PathParams& pp,
                              const float4* L, float* img, float* acc);
 

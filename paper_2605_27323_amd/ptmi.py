@@ -255,3 +255,44 @@ class Renderer(Context):
 
     def sync(self):
         check(lib().pt_sync(self.h, self._stream()))
+
+
+def _autograd():
+    import torch
+
+    class RenderFn(torch.autograd.Function):
+        """image = render(albedo, emission): forward by the HIP renderer,
+        backward by its path-replay adjoint (same seed/frame/spp, so the
+        gradient is that of the fixed-sample estimator)."""
+
+        @staticmethod
+        def forward(ctx, albedo, emission, renderer, kw):
+            if albedo.data_ptr() != renderer.albedo.data_ptr():
+                renderer.albedo.copy_(albedo.detach())
+            if emission.data_ptr() != renderer.emission.data_ptr():
+                renderer.emission.copy_(emission.detach())
+            ctx.renderer = renderer
+            ctx.kw = dict(kw)
+            return renderer.render(**kw).clone()
+
+        @staticmethod
+        def backward(ctx, grad_image):
+            R = ctx.renderer
+            ga = torch.zeros_like(R.albedo)
+            ge = torch.zeros_like(R.emission)
+            kw = {k: v for k, v in ctx.kw.items() if k != "mode"}
+            R.backward(grad_image.contiguous(), ga, ge, **kw)
+            return ga, ge, None, None
+
+    return RenderFn
+
+
+_RENDER_FN = None
+
+
+def render_differentiable(albedo, emission, renderer, **kw):
+    """Differentiable render: gradients flow to albedo and emission (nt x 3)."""
+    global _RENDER_FN
+    if _RENDER_FN is None:
+        _RENDER_FN = _autograd()
+    return _RENDER_FN.apply(albedo, emission, renderer, kw)

@@ -39,6 +39,9 @@ def lib():
         L.emu_render_wave.restype = C.c_int32
         L.emu_render_wave.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, C.c_uint32, C.c_uint32,
                                       C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.c_void_p, C.c_void_p]
+        L.emu_backward.restype = C.c_int32
+        L.emu_backward.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int32,
+                                   C.c_void_p, C.c_void_p, C.c_void_p]
         for name, (res, args) in ptmi.SIGNATURES.items():
             f = getattr(L, name)
             f.restype = res
@@ -88,6 +91,16 @@ class Emu:
                                    int(bool(compact)), shuffle, img.ctypes.data, rays.ctypes.data)
         assert rc == 0
         return img, rays
+
+    def backward(self, d_image, spp=1, max_depth=5, seed=0, frame=0, job=0, nee=True):
+        d_image = np.ascontiguousarray(d_image, np.float32).reshape(-1, 3)
+        nt = self._keep["indices"].shape[0]
+        ga = np.zeros((max(nt, 1), 3), np.float32)
+        ge = np.zeros((max(nt, 1), 3), np.float32)
+        rc = lib().emu_backward(self.h, spp, max_depth, seed, frame, job, int(bool(nee)), d_image.ctypes.data,
+                                ga.ctypes.data, ge.ctypes.data)
+        assert rc == 0
+        return ga[:nt], ge[:nt]
 
     def __del__(self):
         try:

@@ -9,6 +9,7 @@
 
 #include "../../paper_2605_27323_amd/csrc/api.hip"
 #include "../../paper_2605_27323_amd/csrc/wavefront.h"
+#include "../../paper_2605_27323_amd/csrc/adjoint.h"
 
 namespace {
 
@@ -158,6 +159,28 @@ int32_t emu_render_wave(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32
     for (uint32_t pix = 0; pix < npix; ++pix) accumulate_item(pp, wb.L, img, nullptr, pix);
     rays[0] = ne;
     rays[1] = ns;
+    return hs.st.overflow ? 1 : 0;
+}
+
+// Path-replay adjoint over the whole image (sequential binary32 adds):
+// g_alb, g_emi (nt*3) are accumulated into.
+int32_t emu_backward(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32_t frame, uint32_t job, int32_t nee,
+                     const float* d_img, float* g_alb, float* g_emi) {
+    struct HostAcc {
+        void add(float* p, float v) {
+            if (v != 0.0f) *p += v;
+        }
+    } acc;
+    SceneView sc = host_view(c);
+    PathParams pp{spp, D, nee ? 1 : 0, -1, seed, frame, job};
+    HostStack hs(std::max(0, c->bvh.stack_entries - kL));
+    const uint32_t npaths = (uint32_t)c->cam.W * c->cam.H * (uint32_t)spp;
+    const float fs = (float)spp;
+    for (uint32_t p = 0; p < npaths; ++p) {
+        const uint32_t pix = p / (uint32_t)spp, s = p - pix * (uint32_t)spp;
+        f3 delta = mk3(d_img[3 * (size_t)pix] / fs, d_img[3 * (size_t)pix + 1] / fs, d_img[3 * (size_t)pix + 2] / fs);
+        adjoint_path<kL>(sc, c->cam, pp, pix, frame * (uint32_t)spp + s, delta, g_alb, g_emi, hs.st, acc);
+    }
     return hs.st.overflow ? 1 : 0;
 }
 

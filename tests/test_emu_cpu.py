@@ -90,3 +90,22 @@ def test_full_size_scene_sampled_pixels():
     px = scenes.pixel_subset(1920, 1080, 4096, seed=99)
     E, img, rays, nexact = _check(scene, cam, pixels=px, spp=1, max_depth=8, rr_start=3, seed=0, frame=1)
     assert nexact >= 0.999 * len(px)
+
+
+@pytest.mark.parametrize("which", ["cornell", "conductor"])
+def test_adjoint_matches_oracle(which):
+    scene, cam = scenes.cornell()
+    cam = dict(cam, width=24, height=20)
+    if which == "conductor":
+        scene = {k: v.copy() for k, v in scene.items()}
+        scene["materials"] = np.array([[0, 1.0, 1.5, 0], [1, 0.35, 1.5, 0]], np.float32)
+        scene["tri_mat"][10:22] = 1
+    E = emu.Emu(scene, cam)
+    rng = np.random.default_rng(0)
+    d = rng.normal(size=(cam["width"] * cam["height"], 3)).astype(np.float32)
+    ga, ge = E.backward(d, spp=2, max_depth=4, seed=3)
+    oa, oe, aa, ae = oracle.Scene(scene).backward(cam, d, spp=2, max_depth=4, seed=3)
+    for g, o, a in [(ga, oa, aa), (ge, oe, ae)]:
+        # per entry: 1e-4 of the summed absolute terms plus 1e-7 of the largest gradient
+        assert (np.abs(g - o) <= 1e-4 * a + 1e-7 * np.abs(o).max()).all()
+        assert np.linalg.norm(g - o) <= 1e-4 * np.linalg.norm(o)
