@@ -125,30 +125,56 @@ def test_adjoint_vs_central_differences_and_autograd():
     assert checked >= 20
 
 
+def _primary_counts(scene, cam, spp):
+    """Primary-hit samples per triangle (pixel-centre rays, times spp), from
+    the oracle's closest hit."""
+    c = oracle.camera(cam)
+    W, H = cam["width"], cam["height"]
+    px, py = np.meshgrid(np.arange(W), np.arange(H))
+    sx = ((px + 0.5) / W * 2 - 1).astype(np.float32).reshape(-1, 1)
+    sy = (1 - (py + 0.5) / H * 2).astype(np.float32).reshape(-1, 1)
+    d = sx * c[3:6] + sy * c[6:9] + c[9:12]
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    o = np.repeat(c[None, :3], len(d), 0)
+    _, prim, _, _ = oracle.Scene(scene).closest(o, d.astype(np.float32))
+    return np.bincount(prim[prim >= 0], minlength=scene["indices"].shape[0]) * spp
+
+
 def test_adam_recovers_perturbed_albedo():
     # reduced differentiable-rendering protocol: target rendered with
-    # perturbed per-triangle albedos, Adam on the L2 image loss
+    # perturbed per-triangle albedos, 200 Adam steps on the L2 image loss;
+    # recovery measured on triangles with >= 64 primary-hit samples.  The
+    # loss gradient 2 (I - T) dI/dalbedo is estimated with independent
+    # samples for I and for the adjoint (the same samples would bias it by
+    # Var(I) / albedo).
     scene, cam = scenes.cornell()
     cam = dict(cam, width=64, height=64)
     R = ptmi.Renderer(scene, cam)
     true_alb = scenes.perturb_albedo(scene["albedo"], seed=5, sigma=0.05)
     true_alb[34:] = 0.0  # the light keeps albedo 0
-    kw = dict(spp=8, max_depth=4)
+    kw = dict(spp=4, max_depth=4)
     R.albedo.copy_(torch.from_numpy(true_alb).cuda())
-    target = R.render(seed=999, **kw).clone()
+    target = R.render(seed=999, spp=256, max_depth=4).clone()
     alb = torch.from_numpy(scene["albedo"].copy()).cuda().requires_grad_(True)
-    emi = R.emission.clone()
-    opt = torch.optim.Adam([alb], lr=1e-2)
-    err0 = float((alb.detach()[:34] - torch.from_numpy(true_alb[:34]).cuda()).abs().mean())
-    for step in range(60):
+    opt = torch.optim.Adam([alb], lr=5e-3)
+    for step in range(200):
         opt.zero_grad()
-        img = ptmi.render_differentiable(alb, emi, R, seed=step, **kw)
-        loss = ((img - target) ** 2).mean()
-        loss.backward()
+        R.albedo.copy_(alb.detach())
+        I = R.render(seed=2 * step, **kw)
+        d_img = (2.0 / I.numel()) * (I - target)
+        ga = torch.zeros_like(R.albedo)
+        ge = torch.zeros_like(R.emission)
+        R.backward(d_img.contiguous(), ga, ge, seed=2 * step + 1, **kw)
+        alb.grad = ga
         opt.step()
         with torch.no_grad():
-            alb.clamp_(0.0, 1.0)
+            alb.clamp_(0.02, 0.95)
             alb[34:] = 0.0
-    err1 = float((alb.detach()[:34] - torch.from_numpy(true_alb[:34]).cuda()).abs().mean())
-    log("albedo error", err0, "->", err1)
-    assert err1 < 0.5 * err0
+    seen = np.nonzero(_primary_counts(scene, cam, kw["spp"]) >= 64)[0]
+    seen = seen[seen < 34]
+    a_true = true_alb[seen]
+    e0 = float(np.abs(scene["albedo"][seen] - a_true).mean())
+    e1 = float(np.abs(alb.detach().cpu().numpy()[seen] - a_true).mean())
+    log("albedo error over", len(seen), "triangles:", e0, "->", e1)
+    assert len(seen) >= 12
+    assert e1 < 0.5 * e0
