@@ -128,7 +128,9 @@ typedef struct {
  * (emission found after the last one is still counted); rr_start < 0
  * disables Russian roulette, else it applies from that vertex on.
  * block = threads per workgroup (64..256, multiple of 64; 0 = default);
- * grid_mult = persistent workgroups per compute unit (0 = default). */
+ * grid_mult = persistent workgroups per compute unit (0 = default);
+ * sort_threshold: with PT_FLAG_SORT_MATERIAL, a bounce's shade queue is
+ * sorted by material only when it holds at least this many paths. */
 typedef struct {
     int32_t spp, max_depth;
     uint64_t seed;
@@ -138,6 +140,7 @@ typedef struct {
     int32_t mode;
     int32_t flags;
     int32_t block, grid_mult;
+    uint32_t sort_threshold;
 } pt_render_args;
 
 /* Library version (major * 10000 + minor * 100 + patch). */

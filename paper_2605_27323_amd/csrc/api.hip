@@ -93,7 +93,7 @@ pt_status launch_config(const pt_ctx* c, const pt_render_args* a, Launch& L) {
 }
 
 struct WsLayout {
-    size_t counts, ovf, wave[11], total;
+    size_t counts, ovf, wave[11], sort_key, perm, hist, total;
     int ncounts;
 };
 
@@ -111,6 +111,12 @@ WsLayout layout(const pt_ctx* c, const pt_render_args* a, const Launch& L) {
         w.wave[i] = off;
         if (a->mode == PT_MODE_WAVE) off = align_up(off + sizeof(float4) * npaths);
     }
+    w.sort_key = off;
+    if (a->mode == PT_MODE_WAVE) off = align_up(off + sizeof(uint32_t) * npaths);
+    w.perm = off;
+    if (a->mode == PT_MODE_WAVE) off = align_up(off + sizeof(uint32_t) * npaths);
+    w.hist = off;
+    if (a->mode == PT_MODE_WAVE) off = align_up(off + sizeof(uint32_t) * (2 * kSortBins + 1));
     w.total = off;
     return w;
 }
@@ -414,12 +420,20 @@ pt_status pt_render_frame(pt_ctx* c, const pt_render_args* a, float* img, float*
         wb.counts = counts;
         wb.sh_base = a->max_depth + 2;
         wb.err_slot = w.ncounts - 1;
+        wb.sort_key = reinterpret_cast<uint32_t*>(base + w.sort_key);
+        wb.perm = reinterpret_cast<uint32_t*>(base + w.perm);
+        wb.hist = reinterpret_cast<uint32_t*>(base + w.hist);
         const int compact = (a->flags & PT_FLAG_NO_COMPACT) ? 0 : 1;
+        const int sort = (a->flags & PT_FLAG_SORT_MATERIAL) ? 1 : 0;
+        if (sort && !compact) return fail(PT_EINVAL, "material sort needs compaction");
         PT_HIP(launch_init_counts(s, counts, w.ncounts, npaths), "init counters");
+        if (sort) PT_HIP(launch_init_counts(s, wb.hist, 2 * kSortBins + 1, 0u), "init sort histogram");
         PT_HIP(timed(c, prof, 0, s, [&] { return launch_raygen(grid, block, s, c->cam, pp, wb); }), "raygen");
         for (int b = 0; b <= a->max_depth; ++b) {
             PT_HIP(timed(c, prof, 1, s, [&] { return launch_extend(L.lds, grid, block, s, c->view, wb, b, ovf, L.gcap); }), "extend");
-            PT_HIP(timed(c, prof, 2, s, [&] { return launch_shade(grid, block, s, c->view, pp, wb, b, compact); }), "shade");
+            if (sort)
+                PT_HIP(timed(c, prof, 6, s, [&] { return launch_sort(grid, block, s, c->view, wb, b, a->sort_threshold); }), "sort");
+            PT_HIP(timed(c, prof, 2, s, [&] { return launch_shade(grid, block, s, c->view, pp, wb, b, compact, sort); }), "shade");
             if (b < a->max_depth && a->nee)
                 PT_HIP(timed(c, prof, 3, s, [&] { return launch_shadow(L.lds, grid, block, s, c->view, wb, b, ovf, L.gcap); }), "shadow");
         }

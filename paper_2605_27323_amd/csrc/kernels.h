@@ -26,7 +26,14 @@ struct WaveBufs {
     uint32_t* counts;  // [b] live paths at bounce b, [sh_base + b] shadow rays, [err_slot]
     int sh_base;
     int err_slot;
+    // material sort (optional): keys and permutation per queue slot, 64-bin
+    // histogram / running offsets, flag = 1 when the current queue is sorted
+    uint32_t* sort_key;
+    uint32_t* perm;
+    uint32_t* hist;     // [64] counts, [64..127] running offsets, [128] sorted flag
 };
+
+constexpr int kSortBins = 64;
 
 hipError_t launch_mega(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const CamView& cam,
                        const PathParams& pp, float* img, float* acc, uint2* ovf, int gcap, uint32_t* stats);
@@ -36,7 +43,10 @@ hipError_t launch_raygen(dim3 grid, dim3 block, hipStream_t s, const CamView& ca
 hipError_t launch_extend(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const WaveBufs& wb,
                          int b, uint2* ovf, int gcap);
 hipError_t launch_shade(dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const PathParams& pp,
-                        const WaveBufs& wb, int b, int compact);
+                        const WaveBufs& wb, int b, int compact, int sorted);
+// counting sort of queue b by material key when it holds >= threshold paths
+hipError_t launch_sort(dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const WaveBufs& wb, int b,
+                       uint32_t threshold);
 hipError_t launch_shadow(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const WaveBufs& wb,
                          int b, uint2* ovf, int gcap);
 hipError_t launch_adjoint(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const CamView& cam,

@@ -108,10 +108,12 @@ __global__ void __launch_bounds__(256) k_extend(SceneView sc, WaveBufs wb, int b
     if (st.overflow) atomicOr(&wb.counts[wb.err_slot], 1u);
 }
 
-__global__ void __launch_bounds__(256) k_shade(SceneView sc, PathParams pp, WaveBufs wb, int b, int compact) {
+__global__ void __launch_bounds__(256) k_shade(SceneView sc, PathParams pp, WaveBufs wb, int b, int compact,
+                                               int sorted) {
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t count = wb.counts[b];
+    const uint32_t* perm = (sorted && wb.hist[2 * kSortBins]) ? wb.perm : nullptr;
     const int nxt = (b & 1) ^ 1;
     uint32_t* next_count = &wb.counts[b + 1];
     uint32_t* sh_count = &wb.counts[wb.sh_base + b];
@@ -125,7 +127,7 @@ __global__ void __launch_bounds__(256) k_shade(SceneView sc, PathParams pp, Wave
         vo.cont = false;
         sh.valid = false;
         uint32_t path = kDeadPath;
-        if (i < count) path = shade_item(sc, pp, wb, b, i, vo, sh, ps);
+        if (i < count) path = shade_item(sc, pp, wb, b, i, vo, sh, ps, perm);
         if (compact) {
             const uint64_t mk = __ballot(vo.cont);
             if (mk) {
@@ -154,6 +156,70 @@ __global__ void __launch_bounds__(256) k_shadow(SceneView sc, WaveBufs wb, int b
     const uint32_t count = wb.counts[wb.sh_base + b];
     for (uint32_t i = gtid; i < count; i += nlanes) shadow_item<LDS>(sc, wb, i, st);
     if (st.overflow) atomicOr(&wb.counts[wb.err_slot], 1u);
+}
+
+// ---------------------------------------------------------------------------
+// material sort of a shade queue: histogram, scan, scatter of a permutation
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_sort_hist(SceneView sc, WaveBufs wb, int b, uint32_t threshold) {
+    __shared__ uint32_t h[kSortBins];
+    const uint32_t count = wb.counts[b];
+    if (count < threshold) return;
+    for (int t = threadIdx.x; t < kSortBins; t += blockDim.x) h[t] = 0u;
+    __syncthreads();
+    const uint32_t nlanes = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += nlanes) {
+        const uint32_t key = material_key(sc, wb.hit[i]);
+        wb.sort_key[i] = key;
+        atomicAdd(&h[key], 1u);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < kSortBins; t += blockDim.x)
+        if (h[t]) atomicAdd(&wb.hist[t], h[t]);
+}
+
+// one block of 64 threads: exclusive scan of the histogram into the running
+// offsets, histogram cleared for the next bounce, sorted flag set
+__global__ void k_sort_scan(WaveBufs wb, int b, uint32_t threshold) {
+    __shared__ uint32_t v[kSortBins];
+    const int t = threadIdx.x;
+    const bool active = wb.counts[b] >= threshold;
+    v[t] = active ? wb.hist[t] : 0u;
+    __syncthreads();
+    for (int off = 1; off < kSortBins; off <<= 1) {
+        uint32_t x = t >= off ? v[t - off] : 0u;
+        __syncthreads();
+        v[t] += x;
+        __syncthreads();
+    }
+    wb.hist[kSortBins + t] = t == 0 ? 0u : v[t - 1];
+    wb.hist[t] = 0u;
+    if (t == 0) wb.hist[2 * kSortBins] = active ? 1u : 0u;
+}
+
+// per chunk of blockDim slots: block-local ranks in LDS, one global atomic
+// per non-empty bin, then perm[offset + rank] = slot
+__global__ void __launch_bounds__(256) k_sort_scatter(WaveBufs wb, int b, uint32_t threshold) {
+    __shared__ uint32_t cnt[kSortBins], base[kSortBins];
+    const uint32_t count = wb.counts[b];
+    if (count < threshold) return;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t c0 = blockIdx.x * blockDim.x; c0 < count; c0 += stride) {
+        for (int t = threadIdx.x; t < kSortBins; t += blockDim.x) cnt[t] = 0u;
+        __syncthreads();
+        const uint32_t i = c0 + threadIdx.x;
+        uint32_t key = 0, rank = 0;
+        if (i < count) {
+            key = wb.sort_key[i];
+            rank = atomicAdd(&cnt[key], 1u);
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < kSortBins; t += blockDim.x)
+            if (cnt[t]) base[t] = atomicAdd(&wb.hist[kSortBins + t], cnt[t]);
+        __syncthreads();
+        if (i < count) wb.perm[base[key] + rank] = i;
+        __syncthreads();
+    }
 }
 
 __global__ void __launch_bounds__(256) k_accumulate(CamView cam, PathParams pp, const float4* __restrict__ L,
@@ -203,8 +269,20 @@ hipError_t launch_extend(int lds, dim3 grid, dim3 block, hipStream_t s, const Sc
 }
 
 hipError_t launch_shade(dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const PathParams& pp,
-                        const WaveBufs& wb, int b, int compact) {
-    hipLaunchKernelGGL(k_shade, grid, block, 0, s, sc, pp, wb, b, compact);
+                        const WaveBufs& wb, int b, int compact, int sorted) {
+    hipLaunchKernelGGL(k_shade, grid, block, 0, s, sc, pp, wb, b, compact, sorted);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort(dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const WaveBufs& wb, int b,
+                       uint32_t threshold) {
+    hipLaunchKernelGGL(k_sort_hist, grid, block, 0, s, sc, wb, b, threshold);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(kSortBins), 0, s, wb, b, threshold);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sort_scatter, grid, block, 0, s, wb, b, threshold);
     return hipGetLastError();
 }
 

@@ -49,10 +49,22 @@ PT_DEV void extend_item(const SceneView& sc, const WaveBufs& wb, int b, uint32_t
     wb.hit[i] = make_float4(h.t, h.b1, h.b2, u2f(h.tri));
 }
 
+// 6-bit sort key of a hit: material type in bits 4-5, low bits of the
+// material index in bits 0-3; 63 for a miss
+PT_DEV uint32_t material_key(const SceneView& sc, const float4& h4) {
+    const uint32_t tri = f2u(h4.w);
+    if (tri >= (uint32_t)sc.nt) return 63u;
+    const uint32_t mi = f2u(sc.tris[(size_t)tri * 3 + 1].w) & ~kLightFlag;
+    const uint32_t type = (uint32_t)sc.mats[mi].x;
+    return (type << 4) | (mi & 15u);
+}
+
 // shade queue slot i of bounce b (vertex k = b + 1); returns the path id
-// (kDeadPath for a dead slot); vo / sh / ps describe what to enqueue
+// (kDeadPath for a dead slot); vo / sh / ps describe what to enqueue.  With
+// a material sort the slot's data is read from slot perm[i].
 PT_DEV uint32_t shade_item(const SceneView& sc, const PathParams& pp, const WaveBufs& wb, int b, uint32_t i,
-                           VertexOut& vo, ShadowReq& sh, PathState& ps) {
+                           VertexOut& vo, ShadowReq& sh, PathState& ps, const uint32_t* __restrict__ perm = nullptr) {
+    if (perm) i = perm[i];
     const int cur = b & 1;
     float4 o4 = wb.ray_o[cur][i];
     const uint32_t path = f2u(o4.w);

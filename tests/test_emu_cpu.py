@@ -45,6 +45,8 @@ def test_procedural_scenes(mode, cfg):
     w, rw = E.wave(shuffle=11, **cfg)
     assert np.array_equal(w.view(np.uint32), img.view(np.uint32))
     assert (rw == rays).all()
+    w, rw = E.wave(sort=True, shuffle=3, **cfg)
+    assert np.array_equal(w.view(np.uint32), img.view(np.uint32))
 
 
 def test_furnace_and_sky_exact():

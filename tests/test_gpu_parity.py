@@ -93,6 +93,8 @@ def test_divergence_materials_with_dielectrics():
     cfg = dict(spp=2, max_depth=12, rr_start=3, nee=True, seed=9)
     mega, wave = render_both(R, **cfg)
     assert np.array_equal(mega.view(np.uint32), wave.view(np.uint32))
+    srt = R.render(mode="wave", flags=ptmi.FLAG_SORT_MATERIAL, **cfg).cpu().numpy()
+    assert np.array_equal(srt.view(np.uint32), wave.view(np.uint32))
     S = oracle.Scene(scene)
     ref, frag = S.render(cam, **cfg)
     assert_parity(wave, ref, frag, what="divergence")
@@ -146,6 +148,9 @@ def test_no_compaction_and_launch_shapes_bit_identical():
             R.render(mode="wave", block=64, grid_mult=1, **cfg),
             R.render(mode="wave", block=256, grid_mult=3, **cfg),
             R.render(mode="mega", block=64, grid_mult=2, **cfg),
+            R.render(mode="wave", flags=ptmi.FLAG_SORT_MATERIAL, **cfg),
+            R.render(mode="wave", flags=ptmi.FLAG_SORT_MATERIAL, sort_threshold=1500, **cfg),
+            R.render(mode="wave", flags=ptmi.FLAG_SORT_MATERIAL, block=64, grid_mult=1, **cfg),
             R.render(mode="wave", **cfg)]
     for o in outs:
         assert np.array_equal(o.cpu().numpy().view(np.uint32), ref.view(np.uint32))
