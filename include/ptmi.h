@@ -210,6 +210,44 @@ typedef struct {
 } pt_frame_stats;
 pt_status pt_frame_stats_get(pt_ctx* ctx, pt_frame_stats* stats);
 
+/* Batched rendering (many views and scenes of uneven size in one
+ * persistent wavefront).  Each job names a context (scene bound, camera
+ * set; all on one device), its render arguments (spp, max_depth, seed,
+ * frame, nee, rr_start; args.job keys its random numbers, so a job renders
+ * exactly what pt_render_frame renders with the same arguments) and its
+ * device image float[H][W][3].  All jobs' paths share one pool of
+ * pool_capacity slots refilled every iteration (path regeneration). */
+typedef struct {
+    pt_ctx* ctx;
+    pt_render_args args;
+    float* image_out;
+} pt_job;
+
+typedef struct {
+    uint32_t pool_capacity;  /* path slots (0 = 2^21) */
+    int32_t block, grid_mult;/* as in pt_render_args (0 = defaults) */
+    int32_t iters_per_graph; /* iterations captured per graph launch, even (0 = 8) */
+    int32_t use_graph;       /* 1 = capture and replay a hipGraph, 0 = plain launches */
+} pt_batch_opts;
+
+typedef struct {
+    double seconds;          /* host wall time of the whole batch */
+    int64_t path_samples;    /* sum over jobs of W * H * spp */
+    int64_t iterations;      /* pool iterations that did work */
+    int64_t launches;        /* graph launches (or iterations without a graph) */
+} pt_batch_result;
+
+/* Device workspace of a batch (bytes): job table, control block, pool
+ * state, per-path radiance of every job, traversal stack overflow. */
+pt_status pt_batch_workspace_size(const pt_job* jobs, int32_t n_jobs, const pt_batch_opts* opts,
+                                  uint64_t* bytes);
+
+/* Render all jobs; returns when every image is written (synchronous).
+ * job_ms (may be NULL): per job, device time from the start of the batch
+ * to the moment its last path finished, in milliseconds. */
+pt_status pt_render_batch(const pt_job* jobs, int32_t n_jobs, const pt_batch_opts* opts, void* workspace,
+                          uint64_t workspace_bytes, void* stream, double* job_ms, pt_batch_result* result);
+
 /* Wait for all work the context enqueued on `stream`. */
 pt_status pt_sync(pt_ctx* ctx, void* stream);
 

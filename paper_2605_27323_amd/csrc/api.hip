@@ -6,6 +6,7 @@
 #include <string>
 #include <vector>
 
+#include "batch.h"
 #include "bvh_build.h"
 #include "kernels.h"
 
@@ -507,6 +508,202 @@ pt_status pt_frame_stats_get(pt_ctx* c, pt_frame_stats* out) {
         for (int b = 0; b <= c->last_D; ++b) out->extension_rays += h[b];
         for (int b = 0; b <= c->last_D; ++b) out->shadow_rays += h[c->last_D + 2 + b];
         if (h[c->last_ncounts - 1]) return fail(PT_EOVERFLOW, "traversal stack overflow");
+    }
+    return PT_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct BatchPlan {
+    std::vector<JobDesc> jobs;
+    uint64_t total = 0, total_pix = 0;
+    int device = -1, num_cu = 256, stack_entries = 1;
+    Launch L{};
+    uint32_t capacity = 0;
+    int iters_per_graph = 8, use_graph = 1;
+    // workspace offsets
+    size_t o_jobs = 0, o_ctl = 0, o_rem = 0, o_ts = 0, o_pool = 0, o_L = 0, o_ovf = 0, total_bytes = 0;
+};
+
+pt_status plan_batch(const pt_job* jobs, int32_t n, const pt_batch_opts* o, BatchPlan& P) {
+    if (!jobs || n < 1) return fail(PT_EINVAL, "need at least one job");
+    if (n > 255) return fail(PT_EINVAL, "at most 255 jobs per batch");
+    P.jobs.resize(n);
+    for (int j = 0; j < n; ++j) {
+        const pt_job& jb = jobs[j];
+        pt_status st = check_args(jb.ctx, &jb.args);
+        if (st) return st;
+        if (!jb.image_out) return fail(PT_EINVAL, "null job image");
+        if (P.device < 0) {
+            P.device = jb.ctx->device;
+            P.num_cu = jb.ctx->num_cu;
+        } else if (P.device != jb.ctx->device) {
+            return fail(PT_EINVAL, "all jobs of a batch must be on one device");
+        }
+        JobDesc& d = P.jobs[j];
+        d.sc = jb.ctx->view;
+        d.cam = jb.ctx->cam;
+        d.pp = PathParams{jb.args.spp, jb.args.max_depth, jb.args.nee ? 1 : 0, jb.args.rr_start, jb.args.seed,
+                          jb.args.frame, jb.args.job};
+        d.img = jb.image_out;
+        d.npaths = (uint32_t)((uint64_t)d.cam.W * d.cam.H * jb.args.spp);
+        d.npix = (uint32_t)((uint64_t)d.cam.W * d.cam.H);
+        d.base = (uint32_t)P.total;
+        d.pix_base = (uint32_t)P.total_pix;
+        P.total += d.npaths;
+        P.total_pix += d.npix;
+        if (P.total >= 0xFFFFFFFFull) return fail(PT_EINVAL, "a batch holds fewer than 2^32 - 1 paths");
+        P.stack_entries = std::max(P.stack_entries, jb.ctx->bvh.stack_entries);
+    }
+    pt_batch_opts def{0, 0, 0, 0, 1};
+    if (!o) o = &def;
+    P.capacity = o->pool_capacity ? o->pool_capacity : (1u << 21);
+    if (P.capacity < 64 || P.capacity > (1u << 28)) return fail(PT_EINVAL, "pool_capacity must be in [64, 2^28]");
+    P.iters_per_graph = o->iters_per_graph > 0 ? o->iters_per_graph : 8;
+    if (P.iters_per_graph % 2 || P.iters_per_graph > 256) return fail(PT_EINVAL, "iters_per_graph must be even and <= 256");
+    P.use_graph = o->use_graph;
+    pt_render_args la{};
+    la.block = o->block;
+    la.grid_mult = o->grid_mult;
+    P.L.block = la.block > 0 ? la.block : kDefaultBlock;
+    int mult = la.grid_mult > 0 ? la.grid_mult : kDefaultGridMult;
+    if (P.L.block < 64 || P.L.block > 256 || (P.L.block % 64) != 0) return fail(PT_EINVAL, "block must be a multiple of 64 in [64, 256]");
+    if (mult < 1 || mult > 64) return fail(PT_EINVAL, "grid_mult must be in [1, 64]");
+    P.L.grid = P.num_cu * mult;
+    P.L.lds = P.stack_entries <= 8 ? 8 : kStackLds;
+    P.L.gcap = std::max(0, P.stack_entries - P.L.lds);
+    P.L.nlanes = (uint32_t)P.L.grid * (uint32_t)P.L.block;
+    size_t off = 0;
+    P.o_jobs = off; off = align_up(off + sizeof(JobDesc) * n);
+    P.o_ctl = off; off = align_up(off + sizeof(BatchCtl));
+    P.o_rem = off; off = align_up(off + sizeof(uint32_t) * n);
+    P.o_ts = off; off = align_up(off + sizeof(uint64_t) * n);
+    P.o_pool = off; off = align_up(off + sizeof(float4) * (size_t)P.capacity * 10);
+    P.o_L = off; off = align_up(off + sizeof(float4) * std::max<uint64_t>(P.total, 1));
+    P.o_ovf = off; off = align_up(off + sizeof(uint2) * (size_t)P.L.gcap * P.L.nlanes);
+    P.total_bytes = off;
+    return PT_OK;
+}
+
+BatchBufs batch_bufs(const BatchPlan& P, char* base, int n) {
+    BatchBufs bb{};
+    bb.jobs = reinterpret_cast<JobDesc*>(base + P.o_jobs);
+    bb.njobs = n;
+    bb.capacity = P.capacity;
+    bb.ctl = reinterpret_cast<BatchCtl*>(base + P.o_ctl);
+    bb.remaining = reinterpret_cast<uint32_t*>(base + P.o_rem);
+    bb.done_ts = reinterpret_cast<uint64_t*>(base + P.o_ts);
+    float4* pool = reinterpret_cast<float4*>(base + P.o_pool);
+    const size_t C = P.capacity;
+    bb.ray_o[0] = pool + 0 * C; bb.ray_o[1] = pool + 1 * C;
+    bb.ray_d[0] = pool + 2 * C; bb.ray_d[1] = pool + 3 * C;
+    bb.pst[0] = pool + 4 * C; bb.pst[1] = pool + 5 * C;
+    bb.hit = pool + 6 * C;
+    bb.sh_o = pool + 7 * C; bb.sh_d = pool + 8 * C; bb.sh_c = pool + 9 * C;
+    bb.L = reinterpret_cast<float4*>(base + P.o_L);
+    return bb;
+}
+
+}  // namespace
+
+extern "C" {
+
+pt_status pt_batch_workspace_size(const pt_job* jobs, int32_t n, const pt_batch_opts* o, uint64_t* bytes) {
+    if (!bytes) return fail(PT_EINVAL, "null output");
+    BatchPlan P;
+    pt_status st = plan_batch(jobs, n, o, P);
+    if (st) return st;
+    *bytes = P.total_bytes;
+    return PT_OK;
+}
+
+pt_status pt_render_batch(const pt_job* jobs, int32_t n, const pt_batch_opts* o, void* ws, uint64_t ws_bytes,
+                          void* stream, double* job_ms, pt_batch_result* res) {
+    BatchPlan P;
+    pt_status st = plan_batch(jobs, n, o, P);
+    if (st) return st;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return fail(PT_EINVAL, "workspace must be non-null and 256-byte aligned");
+    if (ws_bytes < P.total_bytes) return fail(PT_ENOMEM, "workspace too small (pt_batch_workspace_size)");
+    PT_HIP(hipSetDevice(P.device), "hipSetDevice");
+    auto t0 = std::chrono::steady_clock::now();
+    char* base = static_cast<char*>(ws);
+    BatchBufs bb = batch_bufs(P, base, n);
+    hipStream_t user = reinterpret_cast<hipStream_t>(stream);
+    // private non-blocking stream (default priority) ordered after the caller's work
+    hipStream_t s = nullptr;
+    hipEvent_t ev = nullptr;
+    PT_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "create stream");
+    struct Cleanup {
+        hipStream_t s;
+        hipEvent_t* ev;
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ge = nullptr;
+        ~Cleanup() {
+            if (ge) (void)hipGraphExecDestroy(ge);
+            if (g) (void)hipGraphDestroy(g);
+            if (*ev) (void)hipEventDestroy(*ev);
+            (void)hipStreamDestroy(s);
+        }
+    } cleanup{s, &ev};
+    PT_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "create event");
+    PT_HIP(hipEventRecord(ev, user), "record");
+    PT_HIP(hipStreamWaitEvent(s, ev, 0), "wait");
+    PT_HIP(hipMemcpyAsync(bb.jobs, P.jobs.data(), sizeof(JobDesc) * n, hipMemcpyHostToDevice, s), "upload jobs");
+    PT_HIP(launch_batch_init(s, bb, (uint32_t)P.total), "batch init");
+    uint2* ovf = reinterpret_cast<uint2*>(base + P.o_ovf);
+    dim3 grid(P.L.grid), block(P.L.block);
+    // an upper bound on iterations: each iteration retires at least one
+    // path vertex of the oldest path in the pool
+    int max_depth = 0;
+    for (const JobDesc& d : P.jobs) max_depth = std::max(max_depth, d.pp.D);
+    const uint64_t cap_iters = (P.total / P.capacity + 2) * (uint64_t)(max_depth + 2) * 2 + 64;
+    uint64_t launches = 0, iters = 0;
+    BatchCtl ctl{};
+    if (P.use_graph) {
+        PT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+        hipError_t ce = hipSuccess;
+        for (int it = 0; it < P.iters_per_graph && ce == hipSuccess; ++it)
+            ce = launch_batch_iteration(P.L.lds, grid, block, s, bb, it & 1, ovf, P.L.gcap);
+        hipError_t ee = hipStreamEndCapture(s, &cleanup.g);
+        if (ce != hipSuccess) return hip_fail(ce, "capture launches");
+        if (ee != hipSuccess) return hip_fail(ee, "end capture");
+        PT_HIP(hipGraphInstantiate(&cleanup.ge, cleanup.g, nullptr, nullptr, 0), "instantiate graph");
+    }
+    while (true) {
+        if (P.use_graph) {
+            PT_HIP(hipGraphLaunch(cleanup.ge, s), "graph launch");
+            iters += P.iters_per_graph;
+        } else {
+            for (int it = 0; it < 2; ++it)
+                PT_HIP(launch_batch_iteration(P.L.lds, grid, block, s, bb, it & 1, ovf, P.L.gcap), "batch iteration");
+            iters += 2;
+        }
+        ++launches;
+        PT_HIP(hipMemcpyAsync(&ctl, bb.ctl, sizeof ctl, hipMemcpyDeviceToHost, s), "read control");
+        PT_HIP(hipStreamSynchronize(s), "batch sync");
+        if (ctl.done || ctl.err) break;
+        if (iters > cap_iters) return fail(PT_EOVERFLOW, "batch did not finish within its iteration bound");
+    }
+    if (ctl.err) return fail(PT_EOVERFLOW, "traversal stack overflow");
+    PT_HIP(launch_batch_accumulate(grid, block, s, bb, (uint32_t)P.total_pix), "batch accumulate");
+    std::vector<uint64_t> ts(n);
+    PT_HIP(hipMemcpyAsync(ts.data(), bb.done_ts, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, s), "read timestamps");
+    PT_HIP(hipStreamSynchronize(s), "batch final sync");
+    PT_HIP(hipEventRecord(ev, s), "record done");
+    PT_HIP(hipStreamWaitEvent(user, ev, 0), "caller waits");
+    if (job_ms) {
+        int rate_khz = 0;
+        PT_HIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, P.device), "wall clock rate");
+        for (int j = 0; j < n; ++j)
+            job_ms[j] = rate_khz > 0 && ts[j] >= ctl.t_start ? (double)(ts[j] - ctl.t_start) / (double)rate_khz : -1.0;
+    }
+    if (res) {
+        res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        res->path_samples = (int64_t)P.total;
+        res->iterations = ctl.iterations;
+        res->launches = (int64_t)launches;
     }
     return PT_OK;
 }

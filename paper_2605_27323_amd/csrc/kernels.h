@@ -55,4 +55,10 @@ hipError_t launch_adjoint(int lds, dim3 grid, dim3 block, hipStream_t s, const S
 hipError_t launch_accumulate(dim3 grid, dim3 block, hipStream_t s, const CamView& cam, const PathParams& pp,
                              const float4* L, float* img, float* acc);
 
+struct BatchBufs;
+hipError_t launch_batch_init(hipStream_t s, const BatchBufs& bb, uint32_t total);
+hipError_t launch_batch_iteration(int lds, dim3 grid, dim3 block, hipStream_t s, const BatchBufs& bb, int q,
+                                  uint2* ovf, int gcap);
+hipError_t launch_batch_accumulate(dim3 grid, dim3 block, hipStream_t s, const BatchBufs& bb, uint32_t total_pix);
+
 }  // namespace ptmi

@@ -66,6 +66,20 @@ class FrameStats(C.Structure):
                 ("shadow_rays", C.c_int64)]
 
 
+class Job(C.Structure):
+    _fields_ = [("ctx", C.c_void_p), ("args", RenderArgs), ("image_out", C.c_void_p)]
+
+
+class BatchOpts(C.Structure):
+    _fields_ = [("pool_capacity", C.c_uint32), ("block", C.c_int32), ("grid_mult", C.c_int32),
+                ("iters_per_graph", C.c_int32), ("use_graph", C.c_int32)]
+
+
+class BatchResult(C.Structure):
+    _fields_ = [("seconds", C.c_double), ("path_samples", C.c_int64), ("iterations", C.c_int64),
+                ("launches", C.c_int64)]
+
+
 # name -> (restype, argtypes); every function of include/ptmi.h
 SIGNATURES = {
     "pt_version": (C.c_int32, []),
@@ -83,6 +97,9 @@ SIGNATURES = {
     "pt_render_backward": (C.c_int32, [C.c_void_p, C.POINTER(RenderArgs), C.c_void_p, C.c_void_p, C.c_void_p,
                                        C.c_void_p, C.c_uint64, C.c_void_p]),
     "pt_frame_stats_get": (C.c_int32, [C.c_void_p, C.POINTER(FrameStats)]),
+    "pt_batch_workspace_size": (C.c_int32, [C.POINTER(Job), C.c_int32, C.POINTER(BatchOpts), C.POINTER(C.c_uint64)]),
+    "pt_render_batch": (C.c_int32, [C.POINTER(Job), C.c_int32, C.POINTER(BatchOpts), C.c_void_p, C.c_uint64, C.c_void_p,
+                                    C.c_void_p, C.POINTER(BatchResult)]),
     "pt_sync": (C.c_int32, [C.c_void_p, C.c_void_p]),
 }
 
@@ -297,3 +314,38 @@ def render_differentiable(albedo, emission, renderer, **kw):
     if _RENDER_FN is None:
         _RENDER_FN = _autograd()
     return _RENDER_FN.apply(albedo, emission, renderer, kw)
+
+
+def render_batch(renderers, job_args, images=None, pool_capacity=0, block=0, grid_mult=0, iters_per_graph=0,
+                 use_graph=True, workspace=None):
+    """Render several jobs in one batched persistent wavefront.
+
+    renderers: Renderer per job (scene bound, camera set, all on one device);
+    job_args: dict of render arguments per job (spp, max_depth, seed, frame,
+    nee, rr_start; `job` defaults to the job's index).  Returns (images,
+    per-job completion ms, result dict)."""
+    import torch
+    n = len(renderers)
+    jobs = (Job * n)()
+    if images is None:
+        images = [torch.empty((R.height, R.width, 3), dtype=torch.float32, device=R.torch_device) for R in renderers]
+    for j, (R, kw) in enumerate(zip(renderers, job_args)):
+        kw = dict(kw)
+        kw.setdefault("job", j)
+        jobs[j].ctx = R.h
+        jobs[j].args = R.args(**kw)
+        jobs[j].image_out = images[j].data_ptr()
+    opts = BatchOpts(int(pool_capacity), int(block), int(grid_mult), int(iters_per_graph), int(bool(use_graph)))
+    need = C.c_uint64()
+    check(lib().pt_batch_workspace_size(jobs, n, C.byref(opts), C.byref(need)))
+    if workspace is None or workspace[1] < need.value:
+        t, p = _aligned_empty(need.value, renderers[0].torch_device)
+        workspace = (t, need.value, p)
+    ms = np.zeros(n, np.float64)
+    res = BatchResult()
+    stream = renderers[0]._stream()
+    check(lib().pt_render_batch(jobs, n, C.byref(opts), workspace[2], workspace[1], stream, ms.ctypes.data,
+                                C.byref(res)))
+    out = {"seconds": res.seconds, "path_samples": res.path_samples, "iterations": res.iterations,
+           "launches": res.launches, "workspace": workspace}
+    return images, ms, out

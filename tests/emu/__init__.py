@@ -39,6 +39,8 @@ def lib():
         L.emu_render_wave.restype = C.c_int32
         L.emu_render_wave.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, C.c_uint32, C.c_uint32,
                                       C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.c_int32, C.c_void_p, C.c_void_p]
+        L.emu_render_batch.restype = C.c_int64
+        L.emu_render_batch.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_uint32, C.c_uint64, C.c_void_p]
         L.emu_backward.restype = C.c_int32
         L.emu_backward.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int32,
                                    C.c_void_p, C.c_void_p, C.c_void_p]
@@ -108,3 +110,26 @@ class Emu:
             lib().pt_destroy(self.h)
         except Exception:
             pass
+
+
+def render_batch(emus, job_args, capacity, shuffle=0):
+    """Emulated batched pool; returns (list of images, iterations)."""
+    from paper_2605_27323_amd import ptmi
+    n = len(emus)
+    ctxs = (C.c_void_p * n)(*[e.h.value for e in emus])
+    args = (ptmi.RenderArgs * n)()
+    total_pix = 0
+    for j, (e, kw) in enumerate(zip(emus, job_args)):
+        a = dict(spp=1, max_depth=5, seed=0, frame=0, job=j, nee=True, rr_start=-1)
+        a.update(kw)
+        args[j] = ptmi.RenderArgs(a["spp"], a["max_depth"], a["seed"], a["frame"], a["job"], int(bool(a["nee"])),
+                                  a["rr_start"], 1, 0, 0, 0, 0)
+        total_pix += e.W * e.H
+    img = np.zeros((total_pix, 3), np.float32)
+    it = lib().emu_render_batch(ctxs, args, n, capacity, shuffle, img.ctypes.data)
+    assert it >= 0, "batch bookkeeping error"
+    out, off = [], 0
+    for e in emus:
+        out.append(img[off:off + e.W * e.H])
+        off += e.W * e.H
+    return out, it

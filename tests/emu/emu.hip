@@ -10,6 +10,7 @@
 #include "../../paper_2605_27323_amd/csrc/api.hip"
 #include "../../paper_2605_27323_amd/csrc/wavefront.h"
 #include "../../paper_2605_27323_amd/csrc/adjoint.h"
+#include "../../paper_2605_27323_amd/csrc/batch.h"
 
 namespace {
 
@@ -197,6 +198,92 @@ int32_t emu_backward(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32_t 
         adjoint_path<kL>(sc, c->cam, pp, pix, frame * (uint32_t)spp + s, delta, g_alb, g_emi, hs.st, acc);
     }
     return hs.st.overflow ? 1 : 0;
+}
+
+// Batched pool over the jobs (host memory copies of the scenes), images
+// written job after job into img (concatenated W*H*3 blocks).  Returns the
+// number of iterations, or -1 on a bookkeeping error.
+int64_t emu_render_batch(pt_ctx** ctxs, const pt_render_args* args, int32_t n, uint32_t capacity, uint64_t shuffle_seed,
+                         float* img) {
+    std::vector<JobDesc> jobs(n);
+    uint64_t total = 0, total_pix = 0;
+    int gcap = 0;
+    for (int j = 0; j < n; ++j) {
+        JobDesc& d = jobs[j];
+        d.sc = host_view(ctxs[j]);
+        d.cam = ctxs[j]->cam;
+        d.pp = PathParams{args[j].spp, args[j].max_depth, args[j].nee ? 1 : 0, args[j].rr_start, args[j].seed,
+                          args[j].frame, args[j].job};
+        d.npix = (uint32_t)d.cam.W * d.cam.H;
+        d.npaths = d.npix * (uint32_t)args[j].spp;
+        d.img = img + 3 * total_pix;
+        d.base = (uint32_t)total;
+        d.pix_base = (uint32_t)total_pix;
+        total += d.npaths;
+        total_pix += d.npix;
+        gcap = std::max(gcap, ctxs[j]->bvh.stack_entries - kL);
+    }
+    std::vector<float4> pool(10 * (size_t)capacity), L(std::max<uint64_t>(total, 1));
+    std::vector<uint32_t> remaining(n);
+    std::vector<uint64_t> done_ts(n);
+    BatchCtl ctl{};
+    BatchBufs bb{};
+    bb.jobs = jobs.data();
+    bb.njobs = n;
+    bb.capacity = capacity;
+    bb.ctl = &ctl;
+    bb.remaining = remaining.data();
+    bb.done_ts = done_ts.data();
+    const size_t C = capacity;
+    bb.ray_o[0] = &pool[0]; bb.ray_o[1] = &pool[C];
+    bb.ray_d[0] = &pool[2 * C]; bb.ray_d[1] = &pool[3 * C];
+    bb.pst[0] = &pool[4 * C]; bb.pst[1] = &pool[5 * C];
+    bb.hit = &pool[6 * C];
+    bb.sh_o = &pool[7 * C]; bb.sh_d = &pool[8 * C]; bb.sh_c = &pool[9 * C];
+    bb.L = L.data();
+    ctl.total = (uint32_t)total;
+    for (int j = 0; j < n; ++j) remaining[j] = jobs[j].npaths;
+    HostStack hs(std::max(0, gcap));
+    std::mt19937_64 rng(shuffle_seed);
+    int64_t it = 0;
+    for (;; ++it) {
+        const int q = (int)(it & 1);
+        batch_schedule(bb, q);
+        if (ctl.done) break;
+        if (it > 100000000) return -1;
+        for (uint32_t i = 0; i < ctl.regen_n; ++i) batch_regen_item(bb, q, i);
+        for (uint32_t i = 0; i < ctl.count; ++i) batch_extend_item<kL>(bb, q, i, hs.st);
+        for (uint32_t i = 0; i < ctl.count; ++i) {
+            VertexOut vo;
+            ShadowReq sh;
+            PathState ps;
+            uint32_t g = 0, meta = 0;
+            bool fin = batch_shade_item(bb, q, i, vo, sh, ps, g, meta);
+            if (fin && remaining[meta >> 24]-- == 0) return -1;
+            if (vo.cont) {
+                if (ctl.live[q ^ 1] >= capacity) return -1;
+                batch_write_continuation(bb, q ^ 1, ctl.live[q ^ 1]++, vo, ps, g, meta);
+            }
+            if (sh.valid) batch_write_shadow(bb, ctl.shadow++, sh, g, meta >> 24, !vo.cont);
+        }
+        if (shuffle_seed) {  // queue order must not matter
+            std::vector<uint32_t> perm(ctl.shadow);
+            for (uint32_t i = 0; i < perm.size(); ++i) perm[i] = i;
+            std::shuffle(perm.begin(), perm.end(), rng);
+            for (float4* f : {bb.sh_o, bb.sh_d, bb.sh_c}) {
+                std::vector<float4> tmp(f, f + perm.size());
+                for (uint32_t i = 0; i < perm.size(); ++i) f[i] = tmp[perm[i]];
+            }
+        }
+        for (uint32_t i = 0; i < ctl.shadow; ++i) {
+            uint32_t job = 0;
+            if (batch_shadow_item<kL>(bb, i, hs.st, job) && remaining[job]-- == 0) return -1;
+        }
+    }
+    for (int j = 0; j < n; ++j)
+        if (remaining[j] != 0) return -1;
+    for (uint32_t gp = 0; gp < total_pix; ++gp) batch_accumulate_item(bb, gp);
+    return it;
 }
 
 }  // extern "C"

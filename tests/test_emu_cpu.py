@@ -111,3 +111,15 @@ def test_adjoint_matches_oracle(which):
         # per entry: 1e-4 of the summed absolute terms plus 1e-7 of the largest gradient
         assert (np.abs(g - o) <= 1e-4 * a + 1e-7 * np.abs(o).max()).all()
         assert np.linalg.norm(g - o) <= 1e-4 * np.linalg.norm(o)
+
+
+@pytest.mark.parametrize("capacity", [64, 333, 100000])
+def test_batch_pool_equals_standalone(capacity):
+    jobs = []
+    for j, (seed, n, w, h, spp) in enumerate([(1000, 8, 33, 21, 2), (1001, 20, 16, 16, 3), (1002, 3, 40, 8, 1)]):
+        s, c = scenes.procedural(seed=seed, n_objects=n, width=w, height=h)
+        jobs.append((emu.Emu(s, c), dict(spp=spp, max_depth=6, rr_start=3, seed=5, frame=1)))
+    imgs, it = emu.render_batch([e for e, _ in jobs], [kw for _, kw in jobs], capacity, shuffle=capacity)
+    for j, (e, kw) in enumerate(jobs):
+        ref, _ = e.mega(job=j, **kw)
+        assert np.array_equal(imgs[j].view(np.uint32), ref.view(np.uint32))
