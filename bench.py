@@ -47,8 +47,9 @@ def measured_traffic(kernel):
 
 
 def cpu_baseline(scene, cam, budget_s=12.0):
-    """The oracle (plain C, all host threads) on successive 65536-pixel
-    chunks of frame 0 until the time budget is spent."""
+    """The oracle (plain C, all host threads) on whole frames 0, 1, 2, ...
+    of the benchmark workload, split in 262144-pixel chunks, until the time
+    budget is spent."""
     import numpy as np
 
     import oracle
@@ -58,16 +59,20 @@ def cpu_baseline(scene, cam, budget_s=12.0):
     build_s = time.perf_counter() - t0
     npix = W * H
     done = 0
+    frame = 0
     t0 = time.perf_counter()
-    chunk = 65536
-    while done < npix and time.perf_counter() - t0 < budget_s:
-        px = np.arange(done, min(npix, done + chunk), dtype=np.int32)
-        S.render(cam, pixels=px, spp=SPP, max_depth=DEPTH, seed=0, frame=0, rr_start=RR, threads=threads)
+    chunk = 262144
+    while time.perf_counter() - t0 < budget_s and frame < 1000:
+        first = done % npix
+        px = np.arange(first, min(npix, first + chunk), dtype=np.int32)
+        S.render(cam, pixels=px, spp=SPP, max_depth=DEPTH, seed=0, frame=frame, rr_start=RR, threads=threads)
         done += px.size
+        if done % npix == 0:
+            frame += 1
     dt = time.perf_counter() - t0
     return {"value": done * SPP / dt, "unit": "path-samples/s", "cores": threads, "kind": "oracle",
-            "sample": f"frame 0 pixels [0, {done}) of {W}x{H} at {SPP} spp (first {done} of {npix}), "
-                      f"{dt:.1f} s render, BVH build {build_s:.1f} s excluded"}
+            "sample": f"{done} paths = {done / npix:.2f} frames of the {W}x{H} 1-spp workload (frames 0..{frame}), "
+                      f"{dt:.1f} s render on {threads} threads, BVH build {build_s:.1f} s excluded"}
 
 
 def main():
@@ -78,6 +83,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--mode", default="both", choices=["both", "wave", "mega"])
+    ap.add_argument("--no-tune", action="store_true", help="default launch parameters instead of the autotuner")
+    ap.add_argument("--batch", action="store_true",
+                    help="batched workload instead: 64 jobs, 10k-2M triangles each, mixed resolutions and spp")
+    ap.add_argument("--divergence", action="store_true",
+                    help="divergence workload instead: ~10M triangles, 64 material ids, 4 spp, depth 16")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -98,8 +108,12 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2605_27323_amd import ptmi, scenes
+    from paper_2605_27323_amd import autotune, ptmi, scenes
 
+    if args.batch:
+        return batch_bench(args)
+    if args.divergence:
+        return divergence_bench(args)
     t0 = time.perf_counter()
     scene, cam = scenes.procedural(seed=2, n_objects=2000, width=W, height=H)
     nt = scene["indices"].shape[0]
@@ -108,13 +122,21 @@ def main():
         f"built in {R.info.build_seconds:.2f} s (setup {time.perf_counter() - t0:.1f} s)")
     kw = dict(spp=SPP, max_depth=DEPTH, rr_start=RR, nee=True, seed=0)
     img = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+    modes = ["wave", "mega"] if args.mode == "both" else [args.mode]
+    tuned = {m: {} for m in modes}
+    if not args.no_tune:
+        for mode in modes:
+            t = time.perf_counter()
+            tuned[mode] = autotune.tune_frame(R, mode=mode, cache=None, log=log, **kw)
+            log(f"autotune {mode}: {tuned[mode]} ({time.perf_counter() - t:.1f} s)")
 
     def run(mode, k, first, flags=0):
+        p = dict(tuned[mode])
+        p["flags"] = p.get("flags", 0) | flags
         for i in range(k):
-            R.render(out=img, mode=mode, frame=first + i, flags=flags, **kw)
+            R.render(out=img, mode=mode, frame=first + i, **kw, **p)
 
     res = {}
-    modes = ["wave", "mega"] if args.mode == "both" else [args.mode]
     for mode in modes:
         run(mode, args.warmup, 0)
         torch.cuda.synchronize()
@@ -131,7 +153,7 @@ def main():
     launches = {}
     rays = [0, 0]
     for i in range(args.steps):
-        R.render(out=img, mode="wave", frame=args.warmup + i, flags=ptmi.FLAG_PROFILE, **kw)
+        run("wave", 1, args.warmup + i, flags=ptmi.FLAG_PROFILE)
         st = R.stats()
         for k, v in st["stage_ms"].items():
             stage_ms[k] = stage_ms.get(k, 0.0) + v
@@ -179,6 +201,7 @@ def main():
         "rays_per_s": ((ext_rays_per_frame + sh_rays_per_frame) / (res["wave"]["ms"] * 1e-3)) if "wave" in res else None,
         "rays_per_frame": {"extension": ext_rays_per_frame, "shadow": sh_rays_per_frame},
         "stage_ms_per_frame": frame_stage_ms,
+        "launch_params": tuned,
         "roofline": roofline,
         "paper_context": "paper reports ~16% (1.138x by its table) wavefront over megakernel on an RTX 3060 Ti "
                          "with RT cores, A Beautiful Game scene",
@@ -190,6 +213,85 @@ def main():
     if not args.no_cpu:
         log("oracle CPU baseline ...")
         out["cpu_baseline"] = cpu_baseline(scene, cam)
+    print(json.dumps(out), flush=True)
+
+
+def batch_bench(args):
+    """64 jobs: per job a procedural scene of T triangles (T log-uniform in
+    [1e4, 2e6]), a resolution from {256^2, 512^2, 1024^2, 1920x1080}, 1..8
+    spp, depth 8, roulette from 3; all in one batched persistent wavefront."""
+    import numpy as np
+    import torch
+
+    from paper_2605_27323_amd import autotune, ptmi, scenes
+    t0 = time.perf_counter()
+    specs = scenes.batch_jobs(seed=4, n_jobs=64)
+    Rs, job_args = [], []
+    ntri = 0
+    for j, sp in enumerate(specs):
+        sc, cam = scenes.procedural(seed=sp["scene_seed"], n_objects=min(2000, sp["n_objects"]), width=sp["width"],
+                                    height=sp["height"])
+        Rs.append(ptmi.Renderer(sc, cam))
+        ntri += sc["indices"].shape[0]
+        job_args.append(dict(spp=sp["spp"], max_depth=DEPTH, rr_start=RR, nee=True, seed=0, job=j))
+    total = sum(R.width * R.height * a["spp"] for R, a in zip(Rs, job_args))
+    log(f"batch: {len(Rs)} jobs, {ntri} triangles, {total} path samples (setup {time.perf_counter() - t0:.1f} s)")
+    opts = {} if args.no_tune else autotune.tune_batch(Rs, job_args, cache=None, log=log)
+    log(f"batch options {opts}")
+    ws = None
+    _, _, r = ptmi.render_batch(Rs, job_args, **opts)
+    ws = r["workspace"]
+    runs = []
+    for _ in range(max(1, args.steps // 16)):
+        _, ms, r = ptmi.render_batch(Rs, job_args, workspace=ws, **opts)
+        runs.append((r["seconds"], ms))
+    sec = min(t for t, _ in runs)
+    ms = [m for t, m in runs if t == sec][0]
+    out = {"metric": "batched path samples/s (64 jobs)", "value": total / sec, "unit": "path-samples/s",
+           "n_gpus": 1, "steps": len(runs), "warmup": 1, "ms_per_step": sec * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"64 jobs, {ntri} triangles in total, {total} path samples, depth {DEPTH}, "
+                                  f"roulette from {RR}, one batched persistent wavefront with a hipGraph loop",
+                      "triangles": ntri, "path_samples": total},
+           "job_latency_ms": {"p50": float(np.percentile(ms, 50)), "p99": float(np.percentile(ms, 99)),
+                              "max": float(np.max(ms))},
+           "iterations": r["iterations"], "graph_launches": r["launches"], "batch_options": opts}
+    print(json.dumps(out), flush=True)
+
+
+def divergence_bench(args):
+    """~10M triangles, 64 material ids (Lambertian, conductor, rough
+    dielectric, emissive), 1920x1080, 4 spp, depth 16, roulette from 3:
+    megakernel, wavefront, wavefront with material sort."""
+    import torch
+
+    from paper_2605_27323_amd import ptmi, scenes
+    t0 = time.perf_counter()
+    scene, cam = scenes.procedural(seed=3, n_objects=20000, width=W, height=H, material_mode="divergence")
+    nt = scene["indices"].shape[0]
+    R = ptmi.Renderer(scene, cam)
+    log(f"divergence scene {nt} triangles, BVH depth {R.info.depth} (setup {time.perf_counter() - t0:.1f} s)")
+    kw = dict(spp=4, max_depth=16, rr_start=3, nee=True, seed=0)
+    img = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+    res = {}
+    k = max(2, args.steps // 8)
+    for name, extra in [("mega", dict(mode="mega")), ("wave", dict(mode="wave")),
+                        ("wave_sorted", dict(mode="wave", flags=ptmi.FLAG_SORT_MATERIAL, sort_threshold=1 << 16))]:
+        R.render(out=img, frame=0, **kw, **extra)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for i in range(k):
+            R.render(out=img, frame=1 + i, **kw, **extra)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / k
+        res[name] = {"ms_per_frame": dt * 1e3, "path_samples_per_s": W * H * 4 / dt}
+        log(f"{name}: {dt * 1e3:.2f} ms/frame")
+    out = {"metric": "path samples/s, divergence workload", "value": res["wave_sorted"]["path_samples_per_s"],
+           "unit": "path-samples/s", "n_gpus": 1, "steps": k, "warmup": 1,
+           "ms_per_step": res["wave_sorted"]["ms_per_frame"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"procedural {nt} triangles, 64 material ids, {W}x{H}, 4 spp, depth 16, "
+                                  f"roulette from 3"}, "schedules": res}
     print(json.dumps(out), flush=True)
 
 

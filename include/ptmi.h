@@ -130,7 +130,9 @@ typedef struct {
  * block = threads per workgroup (64..256, multiple of 64; 0 = default);
  * grid_mult = persistent workgroups per compute unit (0 = default);
  * sort_threshold: with PT_FLAG_SORT_MATERIAL, a bounce's shade queue is
- * sorted by material only when it holds at least this many paths. */
+ * sorted by material only when it holds at least this many paths;
+ * stack_lds: traversal stack entries kept in LDS per lane, 8/16/24/32
+ * (0 = default 16); deeper entries spill to the workspace. */
 typedef struct {
     int32_t spp, max_depth;
     uint64_t seed;
@@ -141,6 +143,7 @@ typedef struct {
     int32_t flags;
     int32_t block, grid_mult;
     uint32_t sort_threshold;
+    int32_t stack_lds;
 } pt_render_args;
 
 /* Library version (major * 10000 + minor * 100 + patch). */
@@ -226,6 +229,7 @@ typedef struct {
 typedef struct {
     uint32_t pool_capacity;  /* path slots (0 = 2^21) */
     int32_t block, grid_mult;/* as in pt_render_args (0 = defaults) */
+    int32_t stack_lds;       /* as in pt_render_args (0 = default) */
     int32_t iters_per_graph; /* iterations captured per graph launch, even (0 = 8) */
     int32_t use_graph;       /* 1 = capture and replay a hipGraph, 0 = plain launches */
 } pt_batch_opts;

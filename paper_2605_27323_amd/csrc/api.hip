@@ -68,10 +68,14 @@ struct pt_ctx {
 
 namespace {
 
-int stack_lds_for(const pt_ctx* c) {
-    int need = c->bvh.stack_entries;
-    if (need <= 8) return 8;
-    return kStackLds;
+// LDS stack entries per lane: requested (8, 16, 24, 32) or the default,
+// never more than the BVH can need
+int stack_lds_for(int requested, int need, int& out) {
+    int lds = requested > 0 ? requested : kStackLds;
+    if (lds != 8 && lds != 16 && lds != 24 && lds != 32) return fail(PT_EINVAL, "stack_lds must be 8, 16, 24 or 32");
+    while (lds > 8 && lds - 8 >= need) lds -= 8;
+    out = lds;
+    return PT_OK;
 }
 
 struct Launch {
@@ -87,7 +91,8 @@ pt_status launch_config(const pt_ctx* c, const pt_render_args* a, Launch& L) {
     if (L.block < 64 || L.block > 256 || (L.block % 64) != 0) return fail(PT_EINVAL, "block must be a multiple of 64 in [64, 256]");
     if (mult < 1 || mult > 64) return fail(PT_EINVAL, "grid_mult must be in [1, 64]");
     L.grid = c->num_cu * mult;
-    L.lds = stack_lds_for(c);
+    pt_status st = stack_lds_for(a->stack_lds, c->bvh.stack_entries, L.lds);
+    if (st) return st;
     L.gcap = std::max(0, c->bvh.stack_entries - L.lds);
     L.nlanes = (uint32_t)L.grid * (uint32_t)L.block;
     return PT_OK;
@@ -557,7 +562,7 @@ pt_status plan_batch(const pt_job* jobs, int32_t n, const pt_batch_opts* o, Batc
         if (P.total >= 0xFFFFFFFFull) return fail(PT_EINVAL, "a batch holds fewer than 2^32 - 1 paths");
         P.stack_entries = std::max(P.stack_entries, jb.ctx->bvh.stack_entries);
     }
-    pt_batch_opts def{0, 0, 0, 0, 1};
+    pt_batch_opts def{0, 0, 0, 0, 0, 1};
     if (!o) o = &def;
     P.capacity = o->pool_capacity ? o->pool_capacity : (1u << 21);
     if (P.capacity < 64 || P.capacity > (1u << 28)) return fail(PT_EINVAL, "pool_capacity must be in [64, 2^28]");
@@ -572,7 +577,8 @@ pt_status plan_batch(const pt_job* jobs, int32_t n, const pt_batch_opts* o, Batc
     if (P.L.block < 64 || P.L.block > 256 || (P.L.block % 64) != 0) return fail(PT_EINVAL, "block must be a multiple of 64 in [64, 256]");
     if (mult < 1 || mult > 64) return fail(PT_EINVAL, "grid_mult must be in [1, 64]");
     P.L.grid = P.num_cu * mult;
-    P.L.lds = P.stack_entries <= 8 ? 8 : kStackLds;
+    pt_status sl = stack_lds_for(o->stack_lds, P.stack_entries, P.L.lds);
+    if (sl) return sl;
     P.L.gcap = std::max(0, P.stack_entries - P.L.lds);
     P.L.nlanes = (uint32_t)P.L.grid * (uint32_t)P.L.block;
     size_t off = 0;

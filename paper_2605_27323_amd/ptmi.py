@@ -58,7 +58,7 @@ class RenderArgs(C.Structure):
     _fields_ = [("spp", C.c_int32), ("max_depth", C.c_int32), ("seed", C.c_uint64), ("frame", C.c_uint32),
                 ("job", C.c_uint32), ("nee", C.c_int32), ("rr_start", C.c_int32), ("mode", C.c_int32),
                 ("flags", C.c_int32), ("block", C.c_int32), ("grid_mult", C.c_int32),
-                ("sort_threshold", C.c_uint32)]
+                ("sort_threshold", C.c_uint32), ("stack_lds", C.c_int32)]
 
 
 class FrameStats(C.Structure):
@@ -72,7 +72,7 @@ class Job(C.Structure):
 
 class BatchOpts(C.Structure):
     _fields_ = [("pool_capacity", C.c_uint32), ("block", C.c_int32), ("grid_mult", C.c_int32),
-                ("iters_per_graph", C.c_int32), ("use_graph", C.c_int32)]
+                ("stack_lds", C.c_int32), ("iters_per_graph", C.c_int32), ("use_graph", C.c_int32)]
 
 
 class BatchResult(C.Structure):
@@ -227,10 +227,10 @@ class Renderer(Context):
         self.width, self.height = int(cam["width"]), int(cam["height"])
 
     def args(self, spp=1, max_depth=5, seed=0, frame=0, job=0, nee=True, rr_start=-1, mode="wave", flags=0,
-             block=0, grid_mult=0, sort_threshold=0):
+             block=0, grid_mult=0, sort_threshold=0, stack_lds=0):
         m = MODE_WAVE if mode in ("wave", MODE_WAVE) else MODE_MEGA
         return RenderArgs(int(spp), int(max_depth), int(seed), int(frame), int(job), int(bool(nee)), int(rr_start), m,
-                          int(flags), int(block), int(grid_mult), int(sort_threshold))
+                          int(flags), int(block), int(grid_mult), int(sort_threshold), int(stack_lds))
 
     def workspace(self, a):
         need = C.c_uint64()
@@ -317,7 +317,7 @@ def render_differentiable(albedo, emission, renderer, **kw):
 
 
 def render_batch(renderers, job_args, images=None, pool_capacity=0, block=0, grid_mult=0, iters_per_graph=0,
-                 use_graph=True, workspace=None):
+                 use_graph=True, workspace=None, stack_lds=0):
     """Render several jobs in one batched persistent wavefront.
 
     renderers: Renderer per job (scene bound, camera set, all on one device);
@@ -335,7 +335,8 @@ def render_batch(renderers, job_args, images=None, pool_capacity=0, block=0, gri
         jobs[j].ctx = R.h
         jobs[j].args = R.args(**kw)
         jobs[j].image_out = images[j].data_ptr()
-    opts = BatchOpts(int(pool_capacity), int(block), int(grid_mult), int(iters_per_graph), int(bool(use_graph)))
+    opts = BatchOpts(int(pool_capacity), int(block), int(grid_mult), int(stack_lds), int(iters_per_graph),
+                     int(bool(use_graph)))
     need = C.c_uint64()
     check(lib().pt_batch_workspace_size(jobs, n, C.byref(opts), C.byref(need)))
     if workspace is None or workspace[1] < need.value:
