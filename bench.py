@@ -229,7 +229,7 @@ def batch_bench(args):
     Rs, job_args = [], []
     ntri = 0
     for j, sp in enumerate(specs):
-        sc, cam = scenes.procedural(seed=sp["scene_seed"], n_objects=min(2000, sp["n_objects"]), width=sp["width"],
+        sc, cam = scenes.procedural(seed=sp["scene_seed"], n_objects=sp["n_objects"], width=sp["width"],
                                     height=sp["height"])
         Rs.append(ptmi.Renderer(sc, cam))
         ntri += sc["indices"].shape[0]

@@ -21,8 +21,8 @@ FRAME_SPACE = {
              "sort_threshold": [None, 1 << 16]},
     "mega": {"block": [64, 128, 256], "grid_mult": [2, 4, 8, 16], "stack_lds": [8, 16]},
 }
-BATCH_SPACE = {"pool_capacity": [1 << 20, 1 << 21, 1 << 22], "block": [128, 256], "grid_mult": [4, 8, 16],
-               "stack_lds": [8, 16], "iters_per_graph": [8, 16]}
+BATCH_SPACE = {"pool_capacity": [1 << 20, 1 << 21, 1 << 22], "block": [128, 256], "grid_mult": [4, 8],
+               "stack_lds": [8, 16]}
 
 
 def _bucket(x):

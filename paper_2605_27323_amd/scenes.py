@@ -350,9 +350,9 @@ def random_soup(seed, n_tris, extent=1.0, emissive_frac=0.1, materials=None):
 
 def batch_jobs(seed=4, n_jobs=64, tri_lo=1e4, tri_hi=2e6):
     """Job list of the batched workload: per job a scene seed, a triangle
-    count T drawn log-uniform in [tri_lo, tri_hi] (objects = T / 1000 with the
-    procedural mix), a resolution from {256^2, 512^2, 1024^2, 1920x1080} and
-    1..8 spp."""
+    count T drawn log-uniform in [tri_lo, tri_hi] (objects = T / 500: the
+    procedural mix averages 500 triangles per object), a resolution from
+    {256^2, 512^2, 1024^2, 1920x1080} and 1..8 spp."""
     rng = np.random.default_rng(seed)
     res = [(256, 256), (512, 512), (1024, 1024), (1920, 1080)]
     jobs = []
@@ -360,7 +360,7 @@ def batch_jobs(seed=4, n_jobs=64, tri_lo=1e4, tri_hi=2e6):
         t = float(np.exp(rng.uniform(np.log(tri_lo), np.log(tri_hi))))
         w, h = res[int(rng.integers(0, 4))]
         spp = int(rng.integers(1, 9))
-        jobs.append(dict(scene_seed=1000 + j, n_objects=max(2, int(round(t / 1000.0))),
+        jobs.append(dict(scene_seed=1000 + j, n_objects=max(2, int(round(t / 500.0))),
                          width=w, height=h, spp=spp))
     return jobs
 
