@@ -132,7 +132,10 @@ typedef struct {
  * sort_threshold: with PT_FLAG_SORT_MATERIAL, a bounce's shade queue is
  * sorted by material only when it holds at least this many paths;
  * stack_lds: traversal stack entries kept in LDS per lane, 8/16/24/32
- * (0 = default 16); deeper entries spill to the workspace. */
+ * (0 = default 16); deeper entries spill to the workspace;
+ * tail_threshold: wavefront hybrid tail, a bounce whose queue holds fewer
+ * than this many paths finishes them in place, megakernel style, inside the
+ * shade stage (0 = off; the image is the same bit for bit). */
 typedef struct {
     int32_t spp, max_depth;
     uint64_t seed;
@@ -144,6 +147,7 @@ typedef struct {
     int32_t block, grid_mult;
     uint32_t sort_threshold;
     int32_t stack_lds;
+    uint32_t tail_threshold;
 } pt_render_args;
 
 /* Library version (major * 10000 + minor * 100 + patch). */

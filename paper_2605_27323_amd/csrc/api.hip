@@ -439,7 +439,11 @@ pt_status pt_render_frame(pt_ctx* c, const pt_render_args* a, float* img, float*
             PT_HIP(timed(c, prof, 1, s, [&] { return launch_extend(L.lds, grid, block, s, c->view, wb, b, ovf, L.gcap); }), "extend");
             if (sort)
                 PT_HIP(timed(c, prof, 6, s, [&] { return launch_sort(grid, block, s, c->view, wb, b, a->sort_threshold); }), "sort");
-            PT_HIP(timed(c, prof, 2, s, [&] { return launch_shade(grid, block, s, c->view, pp, wb, b, compact, sort); }), "shade");
+            PT_HIP(timed(c, prof, 2, s, [&] {
+                       return launch_shade(L.lds, grid, block, s, c->view, pp, wb, b, compact, sort,
+                                           a->tail_threshold, ovf, L.gcap);
+                   }),
+                   "shade");
             if (b < a->max_depth && a->nee)
                 PT_HIP(timed(c, prof, 3, s, [&] { return launch_shadow(L.lds, grid, block, s, c->view, wb, b, ovf, L.gcap); }), "shadow");
         }

@@ -33,8 +33,22 @@ __device__ __forceinline__ TravStack<LDS> stack_b(uint32_t* smem, uint2* ovf, in
     return st;
 }
 
-__device__ __forceinline__ void job_finished(const BatchBufs& bb, uint32_t job) {
-    if (atomicSub(&bb.remaining[job], 1u) == 1u) bb.done_ts[job] = wall_clock64();
+// wave-aggregated job counters: every lane of the wave calls this; lanes
+// with fin set retire one path of job `job`.  One atomic per distinct job in
+// the wave (usually one) instead of one per path; the lane whose
+// subtraction reaches zero stamps the job's completion time.
+__device__ __forceinline__ void jobs_finished(const BatchBufs& bb, bool fin, uint32_t job) {
+    uint64_t m = __ballot(fin);
+    while (m) {
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        const uint32_t j0 = __shfl(job, leader);
+        const uint64_t same = __ballot(fin && job == j0);
+        if ((int)lane_id_b() == leader) {
+            const uint32_t n = (uint32_t)__popcll(same);
+            if (atomicSub(&bb.remaining[j0], n) == n) bb.done_ts[j0] = wall_clock64();
+        }
+        m &= ~same;
+    }
 }
 
 }  // namespace
@@ -91,10 +105,8 @@ __global__ void __launch_bounds__(256) k_batch_shade(BatchBufs bb, int q) {
         sh.valid = false;
         uint32_t g = 0, meta = 0;
         bool finished = false;
-        if (i < count) {
-            finished = batch_shade_item(bb, q, i, vo, sh, ps, g, meta);
-            if (finished) job_finished(bb, meta >> 24);
-        }
+        if (i < count) finished = batch_shade_item(bb, q, i, vo, sh, ps, g, meta);
+        jobs_finished(bb, finished, meta >> 24);
         const uint64_t mk = __ballot(vo.cont);
         if (mk) {
             const uint32_t j = reserve_b(&bb.ctl->live[q ^ 1], mk);
@@ -113,9 +125,15 @@ __global__ void __launch_bounds__(256) k_batch_shadow(BatchBufs bb, uint2* __res
     extern __shared__ uint32_t smem[];
     TravStack<LDS> st = stack_b<LDS>(smem, ovf, gcap);
     const uint32_t count = bb.ctl->shadow;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+    const uint32_t nlanes = gridDim.x * blockDim.x;
+    const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
+    // wave-uniform trip count so that the job counters can be aggregated
+    for (uint32_t base = gtid & ~63u; base < count; base += nlanes) {
+        const uint32_t i = base + (gtid & 63u);
         uint32_t job = 0;
-        if (batch_shadow_item<LDS>(bb, i, st, job)) job_finished(bb, job);
+        bool fin = false;
+        if (i < count) fin = batch_shadow_item<LDS>(bb, i, st, job);
+        jobs_finished(bb, fin, job);
     }
     if (st.overflow) atomicOr(&bb.ctl->err, 1u);
 }

@@ -42,8 +42,9 @@ hipError_t launch_raygen(dim3 grid, dim3 block, hipStream_t s, const CamView& ca
                          const WaveBufs& wb);
 hipError_t launch_extend(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const WaveBufs& wb,
                          int b, uint2* ovf, int gcap);
-hipError_t launch_shade(dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const PathParams& pp,
-                        const WaveBufs& wb, int b, int compact, int sorted);
+// tail > 0: a queue with fewer than `tail` paths is finished in place
+hipError_t launch_shade(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const PathParams& pp,
+                        const WaveBufs& wb, int b, int compact, int sorted, uint32_t tail, uint2* ovf, int gcap);
 // counting sort of queue b by material key when it holds >= threshold paths
 hipError_t launch_sort(dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const WaveBufs& wb, int b,
                        uint32_t threshold);

@@ -91,6 +91,28 @@ __global__ void k_init_counts(uint32_t* __restrict__ counts, int n, uint32_t fir
     if (i < n) counts[i] = i == 0 ? first : 0u;
 }
 
+// hybrid tail: a queue with fewer than `tail` paths is too short to keep
+// the stage kernels busy; each path is shaded and finished in place
+template <int LDS>
+__global__ void __launch_bounds__(256) k_shade_tail(SceneView sc, PathParams pp, WaveBufs wb, int b, int sorted,
+                                                    uint32_t tail, uint2* __restrict__ ovf, int gcap) {
+    const uint32_t count = wb.counts[b];
+    if (!(count < tail)) return;
+    extern __shared__ uint32_t smem[];
+    const uint32_t nlanes = gridDim.x * blockDim.x;
+    const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t* perm = (sorted && wb.hist[2 * kSortBins]) ? wb.perm : nullptr;
+    TravStack<LDS> st = make_stack<LDS>(smem, ovf, gcap, gtid, nlanes);
+    for (uint32_t i = gtid; i < count; i += nlanes) {
+        VertexOut vo;
+        ShadowReq sh;
+        PathState ps;
+        const uint32_t path = shade_item(sc, pp, wb, b, i, vo, sh, ps, perm);
+        finish_path<LDS>(sc, pp, wb, path, b + 1, vo, sh, ps, st);
+    }
+    if (st.overflow) atomicOr(&wb.counts[wb.err_slot], 1u);
+}
+
 __global__ void __launch_bounds__(256) k_raygen(CamView cam, PathParams pp, WaveBufs wb) {
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t npaths = (uint32_t)cam.W * (uint32_t)cam.H * (uint32_t)pp.spp;
@@ -109,10 +131,11 @@ __global__ void __launch_bounds__(256) k_extend(SceneView sc, WaveBufs wb, int b
 }
 
 __global__ void __launch_bounds__(256) k_shade(SceneView sc, PathParams pp, WaveBufs wb, int b, int compact,
-                                               int sorted) {
+                                               int sorted, uint32_t tail) {
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t count = wb.counts[b];
+    if (compact && count < tail) return;  // k_shade_tail finishes this queue
     const uint32_t* perm = (sorted && wb.hist[2 * kSortBins]) ? wb.perm : nullptr;
     const int nxt = (b & 1) ^ 1;
     uint32_t* next_count = &wb.counts[b + 1];
@@ -268,10 +291,20 @@ hipError_t launch_extend(int lds, dim3 grid, dim3 block, hipStream_t s, const Sc
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_shade(dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const PathParams& pp,
-                        const WaveBufs& wb, int b, int compact, int sorted) {
-    hipLaunchKernelGGL(k_shade, grid, block, 0, s, sc, pp, wb, b, compact, sorted);
-    return hipGetLastError();
+hipError_t launch_shade(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const PathParams& pp,
+                        const WaveBufs& wb, int b, int compact, int sorted, uint32_t tail, uint2* ovf, int gcap) {
+    hipLaunchKernelGGL(k_shade, grid, block, 0, s, sc, pp, wb, b, compact, sorted, compact ? tail : 0u);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !tail || !compact) return e;
+    const size_t sm = stack_lds_bytes(lds, block.x);
+#define X(N)                                                                                                 \
+    if (lds == N) {                                                                                          \
+        hipLaunchKernelGGL(k_shade_tail<N>, grid, block, sm, s, sc, pp, wb, b, sorted, tail, ovf, gcap);     \
+        return hipGetLastError();                                                                            \
+    }
+    PT_STACK_CASES(X)
+#undef X
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_sort(dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const WaveBufs& wb, int b,

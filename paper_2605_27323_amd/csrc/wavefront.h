@@ -91,6 +91,32 @@ PT_DEV uint32_t shade_item(const SceneView& sc, const PathParams& pp, const Wave
     return path;
 }
 
+// Hybrid tail: continue a shaded path in place to its end (megakernel
+// order: light sample of the current vertex, then extend and shade the next
+// vertices) and store its final radiance.  Used when a bounce's queue is too
+// short to keep the wavefront stages busy.
+template <int LDS>
+PT_DEV void finish_path(const SceneView& sc, const PathParams& pp, const WaveBufs& wb, uint32_t path, int k,
+                        VertexOut vo, ShadowReq sh, PathState& ps, TravStack<LDS>& st) {
+    const uint32_t pix = path / (uint32_t)pp.spp;
+    const uint32_t s = path - pix * (uint32_t)pp.spp;
+    const uint32_t sample = pp.frame * (uint32_t)pp.spp + s;
+    while (true) {
+        if (sh.valid) {
+            Ray sr = make_ray(sh.o, sh.d);
+            if (!any_hit<LDS>(sc, sr, kShadowTmax, st))
+                ps.L = mk3(ps.L.x + sh.contrib.x, ps.L.y + sh.contrib.y, ps.L.z + sh.contrib.z);
+        }
+        if (!vo.cont) break;
+        ++k;
+        const f3 d = vo.d;
+        Ray ray = make_ray(vo.o, d);
+        Hit h = closest_hit<LDS>(sc, ray, INFINITY, st);
+        vo = shade_vertex(sc, pp, pix, sample, k, d, h, ps, sh);
+    }
+    wb.L[path] = make_float4(ps.L.x, ps.L.y, ps.L.z, 0.f);
+}
+
 PT_DEV void write_continuation(const WaveBufs& wb, int nxt, uint32_t j, const VertexOut& vo, const PathState& ps,
                                uint32_t path) {
     wb.ray_o[nxt][j] = make_float4(vo.o.x, vo.o.y, vo.o.z, u2f(path));

@@ -38,7 +38,8 @@ def lib():
                                       C.c_uint32, C.c_uint32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]
         L.emu_render_wave.restype = C.c_int32
         L.emu_render_wave.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, C.c_uint32, C.c_uint32,
-                                      C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.c_int32, C.c_void_p, C.c_void_p]
+                                      C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.c_int32, C.c_uint32, C.c_void_p,
+                                      C.c_void_p]
         L.emu_render_batch.restype = C.c_int64
         L.emu_render_batch.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_uint32, C.c_uint64, C.c_void_p]
         L.emu_backward.restype = C.c_int32
@@ -87,11 +88,12 @@ class Emu:
         return out, rays
 
     def wave(self, spp=1, max_depth=5, seed=0, frame=0, job=0, nee=True, rr_start=-1, compact=True, shuffle=0,
-             sort=False):
+             sort=False, tail=0):
         img = np.zeros((self.W * self.H, 3), np.float32)
         rays = np.zeros(2, np.uint64)
         rc = lib().emu_render_wave(self.h, spp, max_depth, seed, frame, job, int(bool(nee)), rr_start,
-                                   int(bool(compact)), shuffle, int(bool(sort)), img.ctypes.data, rays.ctypes.data)
+                                   int(bool(compact)), shuffle, int(bool(sort)), int(tail), img.ctypes.data,
+                                   rays.ctypes.data)
         assert rc == 0
         return img, rays
 

@@ -90,8 +90,8 @@ int32_t emu_render_mega(pt_ctx* c, const int32_t* pixels, int32_t n, int32_t spp
 // Wavefront over the whole image: img[W*H*3]; shuffle_seed != 0 permutes
 // every continuation and shadow queue.  compact = 0 keeps dead slots.
 int32_t emu_render_wave(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32_t frame, uint32_t job, int32_t nee,
-                        int32_t rr_start, int32_t compact, uint64_t shuffle_seed, int32_t sort, float* img,
-                        uint64_t* rays) {
+                        int32_t rr_start, int32_t compact, uint64_t shuffle_seed, int32_t sort, uint32_t tail,
+                        float* img, uint64_t* rays) {
     SceneView sc = host_view(c);
     PathParams pp{spp, D, nee ? 1 : 0, rr_start, seed, frame, job};
     const uint32_t npaths = (uint32_t)c->cam.W * c->cam.H * (uint32_t)spp;
@@ -135,11 +135,16 @@ int32_t emu_render_wave(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32
             for (uint32_t i = 1; i < count; ++i)  // keys are non-decreasing along perm
                 if (material_key(sc, wb.hit[perm[i]]) < material_key(sc, wb.hit[perm[i - 1]])) return 2;
         }
+        const bool finish = compact && count < tail;
         for (uint32_t i = 0; i < count; ++i) {
             VertexOut vo;
             ShadowReq sh;
             PathState ps;
             uint32_t path = shade_item(sc, pp, wb, b, i, vo, sh, ps, sort ? perm.data() : nullptr);
+            if (finish) {
+                finish_path<kL>(sc, pp, wb, path, b + 1, vo, sh, ps, hs.st);
+                continue;
+            }
             if (path != kDeadPath) ++ne;
             if (compact) {
                 if (vo.cont) write_continuation(wb, nxt, counts[b + 1]++, vo, ps, path);
