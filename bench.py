@@ -19,6 +19,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# autotuner result on MI355X for the 1M-triangle 1080p workload
+FIXED_PARAMS = {"wave": {"block": 256, "grid_mult": 16, "stack_lds": 8, "tail_threshold": 1 << 18},
+                "mega": {"block": 256, "grid_mult": 16, "stack_lds": 8}}
 W, H, SPP, DEPTH, RR = 1920, 1080, 1, 8, 3
 # algorithmic state bytes per queued ray of the extend stage: read origin +
 # direction (32 B), write the hit record (16 B)
@@ -84,6 +87,9 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--mode", default="both", choices=["both", "wave", "mega"])
     ap.add_argument("--no-tune", action="store_true", help="default launch parameters instead of the autotuner")
+    ap.add_argument("--fixed", action="store_true",
+                    help="launch parameters the autotuner chose on MI355X for this workload, without tuning "
+                         "(for profiled runs)")
     ap.add_argument("--batch", action="store_true",
                     help="batched workload instead: 64 jobs, 10k-2M triangles each, mixed resolutions and spp")
     ap.add_argument("--divergence", action="store_true",
@@ -124,7 +130,9 @@ def main():
     img = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
     modes = ["wave", "mega"] if args.mode == "both" else [args.mode]
     tuned = {m: {} for m in modes}
-    if not args.no_tune:
+    if args.fixed:
+        tuned = {m: dict(FIXED_PARAMS[m]) for m in modes}
+    elif not args.no_tune:
         for mode in modes:
             t = time.perf_counter()
             tuned[mode] = autotune.tune_frame(R, mode=mode, cache=None, log=log, **kw)
