@@ -21,12 +21,11 @@ __global__ void __launch_bounds__(256) k_adjoint(SceneView sc, CamView cam, Path
                                                  const float* __restrict__ d_img, float* __restrict__ g_alb,
                                                  float* __restrict__ g_emi, uint2* __restrict__ ovf, int gcap,
                                                  uint32_t* __restrict__ stats) {
-    extern __shared__ uint32_t smem[];
+    extern __shared__ __align__(8) uint32_t smem[];
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
     TravStack<LDS> st;
-    st.lref = smem + threadIdx.x;
-    st.lt = reinterpret_cast<float*>(smem + LDS * blockDim.x) + threadIdx.x;
+    st.lds = reinterpret_cast<uint2*>(smem) + threadIdx.x;
     st.lstride = blockDim.x;
     st.gbl = ovf + gtid;
     st.gstride = (int)nlanes;

@@ -22,8 +22,7 @@ __device__ __forceinline__ uint32_t reserve_b(uint32_t* ctr, uint64_t m) {
 template <int LDS>
 __device__ __forceinline__ TravStack<LDS> stack_b(uint32_t* smem, uint2* ovf, int gcap) {
     TravStack<LDS> st;
-    st.lref = smem + threadIdx.x;
-    st.lt = reinterpret_cast<float*>(smem + LDS * blockDim.x) + threadIdx.x;
+    st.lds = reinterpret_cast<uint2*>(smem) + threadIdx.x;
     st.lstride = blockDim.x;
     st.gbl = ovf + blockIdx.x * blockDim.x + threadIdx.x;
     st.gstride = (int)(gridDim.x * blockDim.x);
@@ -84,7 +83,7 @@ __global__ void __launch_bounds__(256) k_batch_regen(BatchBufs bb, int q) {
 
 template <int LDS>
 __global__ void __launch_bounds__(256) k_batch_extend(BatchBufs bb, int q, uint2* __restrict__ ovf, int gcap) {
-    extern __shared__ uint32_t smem[];
+    extern __shared__ __align__(8) uint32_t smem[];
     TravStack<LDS> st = stack_b<LDS>(smem, ovf, gcap);
     const uint32_t count = bb.ctl->count;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
@@ -122,7 +121,7 @@ __global__ void __launch_bounds__(256) k_batch_shade(BatchBufs bb, int q) {
 
 template <int LDS>
 __global__ void __launch_bounds__(256) k_batch_shadow(BatchBufs bb, uint2* __restrict__ ovf, int gcap) {
-    extern __shared__ uint32_t smem[];
+    extern __shared__ __align__(8) uint32_t smem[];
     TravStack<LDS> st = stack_b<LDS>(smem, ovf, gcap);
     const uint32_t count = bb.ctl->shadow;
     const uint32_t nlanes = gridDim.x * blockDim.x;

@@ -263,6 +263,7 @@ BuildResult build_scene(const std::vector<float>& tri_v, const std::vector<int32
     // boxes are padded by 2^-18 of the largest coordinate so that the slab
     // test can never reject a triangle the watertight test accepts
     const float pad = M * 0x1p-18f;
+    r.max_coord = M;
 
     std::vector<int32_t> order(nt);
     for (int32_t i = 0; i < nt; ++i) order[i] = i;

@@ -12,6 +12,7 @@ struct BuildResult {
     std::vector<float4> tris;        // 3 per triangle, leaf order
     std::vector<LightEntry> lights;  // input order of the light triangles
     float area_total = 0.f;
+    float max_coord = 0.f;  // largest absolute vertex coordinate
     int depth = 0;
     int stack_entries = 0;
 };

@@ -30,8 +30,7 @@ template <int LDS>
 __device__ __forceinline__ TravStack<LDS> make_stack(uint32_t* smem, uint2* ovf, int gcap, uint32_t gtid,
                                                      uint32_t nlanes) {
     TravStack<LDS> st;
-    st.lref = smem + threadIdx.x;
-    st.lt = reinterpret_cast<float*>(smem + LDS * blockDim.x) + threadIdx.x;
+    st.lds = reinterpret_cast<uint2*>(smem) + threadIdx.x;
     st.lstride = blockDim.x;
     st.gbl = ovf + gtid;
     st.gstride = (int)nlanes;
@@ -50,7 +49,7 @@ template <int LDS>
 __global__ void __launch_bounds__(256) k_mega(SceneView sc, CamView cam, PathParams pp, float* __restrict__ img,
                                               float* __restrict__ acc, uint2* __restrict__ ovf, int gcap,
                                               uint32_t* __restrict__ stats) {
-    extern __shared__ uint32_t smem[];
+    extern __shared__ __align__(8) uint32_t smem[];
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
     TravStack<LDS> st = make_stack<LDS>(smem, ovf, gcap, gtid, nlanes);
@@ -98,7 +97,7 @@ __global__ void __launch_bounds__(256) k_shade_tail(SceneView sc, PathParams pp,
                                                     uint32_t tail, uint2* __restrict__ ovf, int gcap) {
     const uint32_t count = wb.counts[b];
     if (!(count < tail)) return;
-    extern __shared__ uint32_t smem[];
+    extern __shared__ __align__(8) uint32_t smem[];
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t* perm = (sorted && wb.hist[2 * kSortBins]) ? wb.perm : nullptr;
@@ -121,7 +120,7 @@ __global__ void __launch_bounds__(256) k_raygen(CamView cam, PathParams pp, Wave
 
 template <int LDS>
 __global__ void __launch_bounds__(256) k_extend(SceneView sc, WaveBufs wb, int b, uint2* __restrict__ ovf, int gcap) {
-    extern __shared__ uint32_t smem[];
+    extern __shared__ __align__(8) uint32_t smem[];
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
     TravStack<LDS> st = make_stack<LDS>(smem, ovf, gcap, gtid, nlanes);
@@ -172,7 +171,7 @@ __global__ void __launch_bounds__(256) k_shade(SceneView sc, PathParams pp, Wave
 
 template <int LDS>
 __global__ void __launch_bounds__(256) k_shadow(SceneView sc, WaveBufs wb, int b, uint2* __restrict__ ovf, int gcap) {
-    extern __shared__ uint32_t smem[];
+    extern __shared__ __align__(8) uint32_t smem[];
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
     TravStack<LDS> st = make_stack<LDS>(smem, ovf, gcap, gtid, nlanes);

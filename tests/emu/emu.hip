@@ -33,19 +33,18 @@ SceneView host_view(const pt_ctx* c) {
     v.sky0 = c->sky[0];
     v.sky1 = c->sky[1];
     v.sky2 = c->sky[2];
+    v.fused_origin_limit = 32.0f * c->bvh.max_coord;
     return v;
 }
 
 constexpr int kL = 16;
 
 struct HostStack {
-    uint32_t lref[kL];
-    float lt[kL];
+    uint2 l[kL];
     std::vector<uint2> gbl;
     TravStack<kL> st;
     explicit HostStack(int gcap) : gbl(std::max(gcap, 1)) {
-        st.lref = lref;
-        st.lt = lt;
+        st.lds = l;
         st.lstride = 1;
         st.gbl = gbl.data();
         st.gstride = 1;

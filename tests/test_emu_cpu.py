@@ -126,3 +126,13 @@ def test_batch_pool_equals_standalone(capacity):
     for j, (e, kw) in enumerate(jobs):
         ref, _ = e.mega(job=j, **kw)
         assert np.array_equal(imgs[j].view(np.uint32), ref.view(np.uint32))
+
+
+def test_far_camera_uses_unfused_slab_test():
+    # origins beyond 32x the largest scene coordinate take the subtracting
+    # slab form; the image must not change
+    scene = scenes.random_soup(9, 60, emissive_frac=0.2)
+    for dist in (5.0, 400.0):
+        cam = dict(eye=(0.3 * dist, 0.2 * dist, -dist), target=(0, 0, 0), up=(0, 1, 0),
+                   vfov_deg=60.0 * 5.0 / dist, width=16, height=12)
+        _check(scene, cam, spp=2, max_depth=4)
