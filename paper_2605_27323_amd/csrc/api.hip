@@ -178,7 +178,6 @@ SceneView make_view(const pt_ctx* c, const pt_scene_buffers* b) {
     v.sky0 = c->sky[0];
     v.sky1 = c->sky[1];
     v.sky2 = c->sky[2];
-    v.fused_origin_limit = 32.0f * c->bvh.max_coord;
     return v;
 }
 

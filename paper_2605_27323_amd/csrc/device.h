@@ -146,8 +146,7 @@ PT_DEV void camera_ray(const CamView& cam, int px, int py, float u0, float u1, f
 // ---------------------------------------------------------------------------
 struct Ray {
     f3 o, d;
-    f3 inv;   // 1/d for the slab test, zero components replaced by 2^-80
-    f3 oinv;  // o * inv, for the fused slab form
+    f3 inv;  // 1/d for the slab test, zero components replaced by 2^-80
     int kx, ky, kz;
     float Sx, Sy, Sz;
 };
@@ -158,7 +157,6 @@ PT_DEV Ray make_ray(f3 o, f3 d) {
     r.d = d;
     r.inv = mk3(1.0f / (d.x != 0.0f ? d.x : 0x1p-80f), 1.0f / (d.y != 0.0f ? d.y : 0x1p-80f),
                 1.0f / (d.z != 0.0f ? d.z : 0x1p-80f));
-    r.oinv = mul3(o, r.inv);
     float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
     int kz = 0;
     float m = ax;
@@ -219,17 +217,12 @@ PT_DEV bool tri_intersect(const Ray& r, f3 v0, f3 v1, f3 v2, float& t, float& b1
 }
 
 // Conservative slab test of the four children of a node against (0, tlim]:
-// entry <= exit * (1 + 2^-16).  Writes the entry distances; returns a
-// 4-bit hit mask.  Empty slots are masked out by their reference: their
-// +inf boxes alone would pass when every direction component is positive
-// and tlim is +inf (inf <= inf).
-//   fused = true: t = fma(b, 1/d, -o/d), one operation per plane.  Beside
-//   a relative error covered by the 2^-16 slack it carries an absolute
-//   error of about 2^-24 |o| along each axis; boxes are padded by 2^-18 of
-//   the largest scene coordinate, so the test stays conservative for
-//   origins within 32 times that coordinate (the caller checks).
-//   fused = false: t = (b - o) / d, relative error only, any origin.
-PT_DEV unsigned slab4(const Ray& r, const float4 q[7], float tlim, float tn[4], bool fused) {
+// entry <= exit * (1 + 2^-16), with t = (b - o) / d (relative error only,
+// covered by the slack).  Writes the entry distances; returns a 4-bit hit
+// mask.  Empty slots are masked out by their reference: their +inf boxes
+// alone would pass when every direction component is positive and tlim is
+// +inf (inf <= inf).
+PT_DEV unsigned slab4(const Ray& r, const float4 q[7], float tlim, float tn[4]) {
     const float* lox = &q[0].x;
     const float* hix = &q[1].x;
     const float* loy = &q[2].x;
@@ -239,22 +232,9 @@ PT_DEV unsigned slab4(const Ray& r, const float4 q[7], float tlim, float tn[4], 
     unsigned mask = 0;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        float ax, bx, ay, by, az, bz;
-        if (fused) {
-            ax = fmaf(lox[c], r.inv.x, -r.oinv.x);
-            bx = fmaf(hix[c], r.inv.x, -r.oinv.x);
-            ay = fmaf(loy[c], r.inv.y, -r.oinv.y);
-            by = fmaf(hiy[c], r.inv.y, -r.oinv.y);
-            az = fmaf(loz[c], r.inv.z, -r.oinv.z);
-            bz = fmaf(hiz[c], r.inv.z, -r.oinv.z);
-        } else {
-            ax = (lox[c] - r.o.x) * r.inv.x;
-            bx = (hix[c] - r.o.x) * r.inv.x;
-            ay = (loy[c] - r.o.y) * r.inv.y;
-            by = (hiy[c] - r.o.y) * r.inv.y;
-            az = (loz[c] - r.o.z) * r.inv.z;
-            bz = (hiz[c] - r.o.z) * r.inv.z;
-        }
+        float ax = (lox[c] - r.o.x) * r.inv.x, bx = (hix[c] - r.o.x) * r.inv.x;
+        float ay = (loy[c] - r.o.y) * r.inv.y, by = (hiy[c] - r.o.y) * r.inv.y;
+        float az = (loz[c] - r.o.z) * r.inv.z, bz = (hiz[c] - r.o.z) * r.inv.z;
         float t0 = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), 0.0f));
         float t1 = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), tlim));
         tn[c] = t0;
@@ -262,11 +242,6 @@ PT_DEV unsigned slab4(const Ray& r, const float4 q[7], float tlim, float tn[4], 
         if (t0 <= t1 * kBoxSlack && f2u(cref) != kEmptyRef) mask |= 1u << c;
     }
     return mask;
-}
-
-// the fused slab form is conservative for this origin (see slab4)
-PT_DEV bool fused_ok(const SceneView& sc, f3 o) {
-    return fmaxf(fmaxf(fabsf(o.x), fabsf(o.y)), fabsf(o.z)) <= sc.fused_origin_limit;
 }
 
 // ---------------------------------------------------------------------------
@@ -347,7 +322,6 @@ PT_DEV Hit closest_hit(const SceneView& sc, const Ray& r, float tmax, TravStack<
     h.tri = 0xFFFFFFFFu;
     h.id = 0xFFFFFFFFu;
     st.sp = 0;
-    const bool fused = fused_ok(sc, r.o);
     uint32_t ref = 0;  // root
     while (true) {
         if (!(ref & kLeafBit)) {
@@ -355,7 +329,7 @@ PT_DEV Hit closest_hit(const SceneView& sc, const Ray& r, float tmax, TravStack<
                 float4 q[8];
                 load_node(sc.nodes, ref, q);
                 float tn[4];
-                unsigned m = slab4(r, q, h.t, tn, fused);
+                unsigned m = slab4(r, q, h.t, tn);
                 if (m) {
                     uint32_t rr[4];
                     float tt[4];
@@ -415,7 +389,6 @@ PT_DEV Hit closest_hit(const SceneView& sc, const Ray& r, float tmax, TravStack<
 template <int LDS>
 PT_DEV bool any_hit(const SceneView& sc, const Ray& r, float tmax, TravStack<LDS>& st) {
     st.sp = 0;
-    const bool fused = fused_ok(sc, r.o);
     uint32_t ref = 0;
     while (true) {
         if (!(ref & kLeafBit)) {
@@ -423,7 +396,7 @@ PT_DEV bool any_hit(const SceneView& sc, const Ray& r, float tmax, TravStack<LDS
                 float4 q[8];
                 load_node(sc.nodes, ref, q);
                 float tn[4];
-                unsigned m = slab4(r, q, tmax, tn, fused);
+                unsigned m = slab4(r, q, tmax, tn);
                 if (m) {
                     // descend into the first hit child, push the others
                     const uint32_t cr[4] = {f2u(q[6].x), f2u(q[6].y), f2u(q[6].z), f2u(q[6].w)};

@@ -47,7 +47,6 @@ struct SceneView {
     int32_t n_nodes;
     float area_total;
     float sky0, sky1, sky2;
-    float fused_origin_limit;  // 32 x the largest scene coordinate (see slab4)
 };
 
 struct CamView {

@@ -13,7 +13,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libptmi.so")
+LIB_PATH = os.environ.get("PTMI_LIB") or os.path.join(HERE, "libptmi.so")
 
 PT_OK, PT_EINVAL, PT_ENOMEM, PT_EHIP, PT_ESTATE, PT_EOVERFLOW, PT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 MODE_MEGA, MODE_WAVE = 0, 1

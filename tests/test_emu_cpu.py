@@ -128,9 +128,8 @@ def test_batch_pool_equals_standalone(capacity):
         assert np.array_equal(imgs[j].view(np.uint32), ref.view(np.uint32))
 
 
-def test_far_camera_uses_unfused_slab_test():
-    # origins beyond 32x the largest scene coordinate take the subtracting
-    # slab form; the image must not change
+def test_far_camera():
+    # a camera far outside the scene (slab distances from large origins)
     scene = scenes.random_soup(9, 60, emissive_frac=0.2)
     for dist in (5.0, 400.0):
         cam = dict(eye=(0.3 * dist, 0.2 * dist, -dist), target=(0, 0, 0), up=(0, 1, 0),
