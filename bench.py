@@ -23,9 +23,6 @@ HBM_PEAK_GBS = 8000.0
 FIXED_PARAMS = {"wave": {"block": 256, "grid_mult": 16, "stack_lds": 8, "tail_threshold": 1 << 18},
                 "mega": {"block": 256, "grid_mult": 16, "stack_lds": 8}}
 W, H, SPP, DEPTH, RR = 1920, 1080, 1, 8, 3
-# algorithmic state bytes per queued ray of the extend stage: read origin +
-# direction (32 B), write the hit record (16 B)
-EXTEND_BYTES_PER_RAY = 48
 
 
 def log(*a):
@@ -156,9 +153,8 @@ def main():
         log(f"{mode}: {res[mode]['ms']:.3f} ms/frame, {res[mode]['value'] / 1e6:.1f} M path-samples/s")
 
     # per-stage times with HIP events on the render stream, over the same
-    # number of frames, plus ray counts
-    stage_ms = {}
-    launches = {}
+    # number of frames, plus ray counts, work items and algorithmic bytes
+    stage_ms, launches, items, nbytes = {}, {}, {}, {}
     rays = [0, 0]
     for i in range(args.steps):
         run("wave", 1, args.warmup + i, flags=ptmi.FLAG_PROFILE)
@@ -166,26 +162,35 @@ def main():
         for k, v in st["stage_ms"].items():
             stage_ms[k] = stage_ms.get(k, 0.0) + v
             launches[k] = launches.get(k, 0) + st["launches"][k]
+        for k, v in st["items"].items():
+            items[k] = items.get(k, 0) + v
+            nbytes[k] = nbytes.get(k, 0.0) + st["bytes"][k]
         rays[0] += st["extension_rays"]
         rays[1] += st["shadow_rays"]
     frame_stage_ms = {k: v / args.steps for k, v in stage_ms.items()}
     log("wavefront stage ms/frame: " + ", ".join(f"{k} {v:.3f}" for k, v in frame_stage_ms.items()))
-    dom = max(stage_ms, key=stage_ms.get)
-    dom_avg_ms = stage_ms[dom] / launches[dom]
     ext_rays_per_frame = rays[0] / args.steps
     sh_rays_per_frame = rays[1] / args.steps
-    # extend: algorithmic state bytes per launch = 48 B x queued rays
-    if dom == "extend":
-        per_launch_bytes = EXTEND_BYTES_PER_RAY * rays[0] / launches["extend"]
-    else:
-        per_launch_bytes = None
-    roofline = None
-    if per_launch_bytes is not None:
-        achieved = per_launch_bytes / (dom_avg_ms * 1e-3) / 1e9
-        roofline = {"bound": "hbm", "kernel": "k_extend", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                    "traffic": measured_traffic("ptmi::k_extend<16>"),
-                    "avg_launch_ms": dom_avg_ms, "bytes_per_launch": per_launch_bytes}
+    # roofline of the stage kernel with the largest share of the frame: its
+    # algorithmic path-state bytes per launch over its mean launch time
+    dom = max(stage_ms, key=stage_ms.get)
+    lds = tuned["wave"].get("stack_lds", 16)
+    kname = {"extend": f"ptmi::k_extend<{lds}>", "shade": "ptmi::k_shade", "shadow": f"ptmi::k_shadow<{lds}>",
+             "tail": f"ptmi::k_shade_tail<{lds}>", "raygen": "ptmi::k_raygen", "accumulate": "ptmi::k_accumulate",
+             "sort": "ptmi::k_sort_*"}[dom]
+    dom_avg_ms = stage_ms[dom] / launches[dom]
+    per_launch_bytes = nbytes.get(dom, 0.0) / launches[dom]
+    achieved = per_launch_bytes / (dom_avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname),
+                "avg_launch_ms": dom_avg_ms, "bytes_per_launch": per_launch_bytes,
+                "launches_per_frame": launches[dom] / args.steps,
+                "items_per_frame": items.get(dom, 0) / args.steps,
+                "stage_share": stage_ms[dom] / sum(stage_ms.values())}
+    state_bytes = sum(nbytes.values()) / args.steps
+    state_floor = {"bytes_per_frame": state_bytes,
+                   "frac_of_frame": (state_bytes / (res["wave"]["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS)
+                   if "wave" in res else None}
 
     out = {
         "metric": "path samples/s wavefront vs megakernel @1080p, 1M tris; adjoint samples/s",
@@ -211,6 +216,8 @@ def main():
         "stage_ms_per_frame": frame_stage_ms,
         "launch_params": tuned,
         "roofline": roofline,
+        "state_traffic": state_floor,
+        "stage_items_per_frame": {k: v / args.steps for k, v in items.items()},
         "paper_context": "paper reports ~16% (1.138x by its table) wavefront over megakernel on an RTX 3060 Ti "
                          "with RT cores, A Beautiful Game scene",
     }

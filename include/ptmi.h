@@ -206,13 +206,27 @@ pt_status pt_render_backward(pt_ctx* ctx, const pt_render_args* args, const floa
                              float* d_albedo, float* d_emission, void* workspace,
                              uint64_t workspace_bytes, void* stream);
 
-/* Statistics of the last frame rendered with PT_FLAG_PROFILE or
- * PT_FLAG_COUNT_RAYS (synchronises the stream): stage_ms[k] per stage
- * (0 raygen, 1 extend, 2 shade, 3 shadow, 4 accumulate, 5 megakernel,
- * 6 sort, 7 adjoint), launches[k], extension and shadow ray counts. */
+/* Statistics of the last frame rendered (synchronises the stream).
+ * Stages (index k): 0 raygen, 1 extend, 2 shade, 3 shadow, 4 accumulate,
+ * 5 megakernel, 6 sort, 7 adjoint, 8 hybrid tail.
+ *   stage_ms[k], launches[k]: HIP-event time and launch count per stage,
+ *     filled only when the frame ran with PT_FLAG_PROFILE (else 0).
+ *   stage_items[k]: work items the stage's launches processed (paths for
+ *     raygen, accumulate pixels, queued rays for extend / shade / shadow /
+ *     tail, paths for the megakernel and the adjoint); always filled.
+ *   stage_bytes[k]: the stage's algorithmic path-state bytes (reads +
+ *     writes of queue records, radiance and image buffers a stage must move;
+ *     scene data excluded; conditional radiance updates of shade and shadow
+ *     excluded, so a lower bound there); always filled.
+ *   extension_rays, shadow_rays: rays traced by the frame (wavefront stages
+ *   and hybrid tail, or megakernel, or adjoint replays).
+ * PT_EOVERFLOW if a traversal stack overflowed during the frame. */
+#define PT_NSTAGES 9
 typedef struct {
-    double stage_ms[8];
-    int64_t launches[8];
+    double stage_ms[PT_NSTAGES];
+    int64_t launches[PT_NSTAGES];
+    int64_t stage_items[PT_NSTAGES];
+    double stage_bytes[PT_NSTAGES];
     int64_t extension_rays, shadow_rays;
 } pt_frame_stats;
 pt_status pt_frame_stats_get(pt_ctx* ctx, pt_frame_stats* stats);

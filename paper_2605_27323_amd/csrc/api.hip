@@ -61,8 +61,14 @@ struct pt_ctx {
     std::vector<StageTimer> timers;
     std::vector<hipEvent_t> event_pool;
     size_t event_next = 0;
-    uint32_t* last_counts = nullptr;  // device counters of the last frame
-    int last_ncounts = 0, last_D = 0, last_mode = 0;
+    // last frame: device counters and what is needed to turn them into
+    // per-stage work items and bytes
+    uint32_t* last_counts = nullptr;
+    int last_ncounts = 0, last_D = 0, last_kind = 0;  // kind: 0 megakernel, 1 wavefront, 2 adjoint
+    int last_spp = 1, last_nee = 1, last_compact = 1, last_sort = 0;
+    uint32_t last_tail = 0, last_sort_threshold = 0;
+    uint64_t last_npix = 0;
+    bool last_acc = false;
     bool last_valid = false;
 };
 
@@ -133,6 +139,7 @@ pt_status check_args(const pt_ctx* c, const pt_render_args* a) {
     if (c->device < 0) return fail(PT_ESTATE, "host-only context cannot render");
     if (!c->bound) return fail(PT_ESTATE, "scene not bound (pt_bind_scene)");
     if (!c->cam_set) return fail(PT_ESTATE, "camera not set (pt_set_camera)");
+    if (a->flags & ~(PT_FLAG_PROFILE | PT_FLAG_NO_COMPACT | PT_FLAG_SORT_MATERIAL)) return fail(PT_EINVAL, "unknown flag");
     if (a->spp < 1 || a->spp > 65536) return fail(PT_EINVAL, "spp must be in [1, 65536]");
     if (a->max_depth < 0 || a->max_depth > 1000) return fail(PT_EINVAL, "max_depth must be in [0, 1000]");
     if (a->mode != PT_MODE_MEGA && a->mode != PT_MODE_WAVE) return fail(PT_EINVAL, "unknown mode");
@@ -161,6 +168,22 @@ hipError_t timed(pt_ctx* c, bool prof, int stage, hipStream_t s, F fn) {
     (void)hipEventRecord(t.b, s);
     c->timers.push_back(t);
     return e;
+}
+
+void remember_frame(pt_ctx* c, const pt_render_args* a, uint32_t* counts, int ncounts, int kind, bool acc) {
+    c->last_counts = counts;
+    c->last_ncounts = ncounts;
+    c->last_D = a->max_depth;
+    c->last_kind = kind;
+    c->last_spp = a->spp;
+    c->last_nee = a->nee ? 1 : 0;
+    c->last_compact = (a->flags & PT_FLAG_NO_COMPACT) ? 0 : 1;
+    c->last_sort = (a->flags & PT_FLAG_SORT_MATERIAL) ? 1 : 0;
+    c->last_tail = a->tail_threshold;
+    c->last_sort_threshold = a->sort_threshold;
+    c->last_npix = (uint64_t)c->cam.W * (uint64_t)c->cam.H;
+    c->last_acc = acc;
+    c->last_valid = true;
 }
 
 SceneView make_view(const pt_ctx* c, const pt_scene_buffers* b) {
@@ -425,6 +448,7 @@ pt_status pt_render_frame(pt_ctx* c, const pt_render_args* a, float* img, float*
         wb.L = reinterpret_cast<float4*>(base + w.wave[10]);
         wb.counts = counts;
         wb.sh_base = a->max_depth + 2;
+        wb.tail_slot = 2 * a->max_depth + 3;
         wb.err_slot = w.ncounts - 1;
         wb.sort_key = reinterpret_cast<uint32_t*>(base + w.sort_key);
         wb.perm = reinterpret_cast<uint32_t*>(base + w.perm);
@@ -439,21 +463,19 @@ pt_status pt_render_frame(pt_ctx* c, const pt_render_args* a, float* img, float*
             PT_HIP(timed(c, prof, 1, s, [&] { return launch_extend(L.lds, grid, block, s, c->view, wb, b, ovf, L.gcap); }), "extend");
             if (sort)
                 PT_HIP(timed(c, prof, 6, s, [&] { return launch_sort(grid, block, s, c->view, wb, b, a->sort_threshold); }), "sort");
-            PT_HIP(timed(c, prof, 2, s, [&] {
-                       return launch_shade(L.lds, grid, block, s, c->view, pp, wb, b, compact, sort,
-                                           a->tail_threshold, ovf, L.gcap);
-                   }),
-                   "shade");
+            PT_HIP(timed(c, prof, 2, s, [&] { return launch_shade(grid, block, s, c->view, pp, wb, b, compact, sort, a->tail_threshold); }), "shade");
+            if (compact && a->tail_threshold)
+                PT_HIP(timed(c, prof, 8, s, [&] {
+                           return launch_tail(L.lds, grid, block, s, c->view, pp, wb, b, sort, a->tail_threshold, ovf,
+                                              L.gcap);
+                       }),
+                       "hybrid tail");
             if (b < a->max_depth && a->nee)
                 PT_HIP(timed(c, prof, 3, s, [&] { return launch_shadow(L.lds, grid, block, s, c->view, wb, b, ovf, L.gcap); }), "shadow");
         }
         PT_HIP(timed(c, prof, 4, s, [&] { return launch_accumulate(grid, block, s, c->cam, pp, wb.L, img, acc); }), "accumulate");
     }
-    c->last_counts = counts;
-    c->last_ncounts = w.ncounts;
-    c->last_D = a->max_depth;
-    c->last_mode = a->mode;
-    c->last_valid = true;
+    remember_frame(c, a, counts, w.ncounts, a->mode == PT_MODE_WAVE ? 1 : 0, acc != nullptr);
     return PT_OK;
 }
 
@@ -487,11 +509,7 @@ pt_status pt_render_backward(pt_ctx* c, const pt_render_args* a, const float* d_
                                      d_emission, ovf, L.gcap, counts);
            }),
            "adjoint");
-    c->last_counts = counts;
-    c->last_ncounts = w.ncounts;
-    c->last_D = a->max_depth;
-    c->last_mode = PT_MODE_MEGA;
-    c->last_valid = true;
+    remember_frame(c, a, counts, w.ncounts, 2, false);
     return PT_OK;
 }
 
@@ -509,15 +527,57 @@ pt_status pt_frame_stats_get(pt_ctx* c, pt_frame_stats* out) {
     }
     std::vector<uint32_t> h(c->last_ncounts);
     PT_HIP(hipMemcpy(h.data(), c->last_counts, h.size() * sizeof(uint32_t), hipMemcpyDeviceToHost), "read counters");
-    if (c->last_mode == PT_MODE_MEGA) {
+    const uint64_t npix = c->last_npix, npaths = npix * (uint64_t)c->last_spp;
+    const double img_bytes = 12.0 + (c->last_acc ? 24.0 : 0.0);  // image write (+ running average RMW)
+    if (c->last_kind != 1) {
+        // megakernel / adjoint: [0] extension rays, [1] shadow rays, [2] overflow
         out->extension_rays = h[0];
         out->shadow_rays = h[1];
+        const int k = c->last_kind == 0 ? 5 : 7;
+        out->stage_items[k] = (int64_t)npaths;
+        // path state lives in registers: only the image (megakernel) or
+        // the image adjoint (read once per pixel) touches memory
+        out->stage_bytes[k] = (double)npix * (c->last_kind == 0 ? img_bytes : 12.0);
         if (h[2]) return fail(PT_EOVERFLOW, "traversal stack overflow");
-    } else {
-        for (int b = 0; b <= c->last_D; ++b) out->extension_rays += h[b];
-        for (int b = 0; b <= c->last_D; ++b) out->shadow_rays += h[c->last_D + 2 + b];
-        if (h[c->last_ncounts - 1]) return fail(PT_EOVERFLOW, "traversal stack overflow");
+        return PT_OK;
     }
+    const int D = c->last_D;
+    const uint32_t* cnt = h.data();
+    const uint32_t* shc = h.data() + D + 2;
+    const uint32_t tail = c->last_compact ? c->last_tail : 0u;
+    // per queued path: raygen writes ray_o, ray_d, pst, L (64 B); extend
+    // reads ray_o, ray_d, writes hit (48 B); shade reads ray_o, ray_d, pst,
+    // hit, L (80 B) and writes 48 B per continuation and per shadow record;
+    // shadow reads 48 B per record; the tail reads a shade record (80 B) and
+    // writes the final L (16 B); the sort reads hit, writes the key, reads
+    // the key, writes the permutation (28 B)
+    out->stage_items[0] = (int64_t)npaths;
+    out->stage_bytes[0] = 64.0 * (double)npaths;
+    for (int b = 0; b <= D; ++b) {
+        out->extension_rays += cnt[b];
+        out->stage_items[1] += cnt[b];
+        if (c->last_sort && cnt[b] >= c->last_sort_threshold) out->stage_items[6] += cnt[b];
+        if (tail && cnt[b] < tail) {
+            out->stage_items[8] += cnt[b];
+        } else {
+            out->stage_items[2] += cnt[b];
+            out->stage_bytes[2] += 48.0 * ((double)cnt[b + 1] + (double)shc[b]);
+        }
+        if (b < D && c->last_nee) {
+            out->shadow_rays += shc[b];
+            out->stage_items[3] += shc[b];
+        }
+    }
+    out->extension_rays += h[2 * D + 3];
+    out->shadow_rays += h[2 * D + 4];
+    out->stage_bytes[1] = 48.0 * (double)out->stage_items[1];
+    out->stage_bytes[2] += 80.0 * (double)out->stage_items[2];
+    out->stage_bytes[3] = 48.0 * (double)out->stage_items[3];
+    out->stage_bytes[6] = 28.0 * (double)out->stage_items[6];
+    out->stage_bytes[8] = 96.0 * (double)out->stage_items[8];
+    out->stage_items[4] = (int64_t)npix;
+    out->stage_bytes[4] = (double)npix * (16.0 * c->last_spp + img_bytes);
+    if (h[c->last_ncounts - 1]) return fail(PT_EOVERFLOW, "traversal stack overflow");
     return PT_OK;
 }
 

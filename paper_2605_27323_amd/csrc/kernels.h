@@ -23,8 +23,12 @@ struct WaveBufs {
     float4* sh_d;
     float4* sh_c;
     float4* L;
-    uint32_t* counts;  // [b] live paths at bounce b, [sh_base + b] shadow rays, [err_slot]
+    // [b] live paths at bounce b, [sh_base + b] shadow rays, [tail_slot] and
+    // [tail_slot + 1] extension and shadow rays traced by the hybrid tail,
+    // [err_slot] traversal stack overflow flag
+    uint32_t* counts;
     int sh_base;
+    int tail_slot;
     int err_slot;
     // material sort (optional): keys and permutation per queue slot, 64-bin
     // histogram / running offsets, flag = 1 when the current queue is sorted
@@ -42,9 +46,12 @@ hipError_t launch_raygen(dim3 grid, dim3 block, hipStream_t s, const CamView& ca
                          const WaveBufs& wb);
 hipError_t launch_extend(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const WaveBufs& wb,
                          int b, uint2* ovf, int gcap);
-// tail > 0: a queue with fewer than `tail` paths is finished in place
-hipError_t launch_shade(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const PathParams& pp,
-                        const WaveBufs& wb, int b, int compact, int sorted, uint32_t tail, uint2* ovf, int gcap);
+// tail > 0 (compacted queues only): a queue with fewer than `tail` paths is
+// skipped here and finished in place by launch_tail
+hipError_t launch_shade(dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const PathParams& pp,
+                        const WaveBufs& wb, int b, int compact, int sorted, uint32_t tail);
+hipError_t launch_tail(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const PathParams& pp,
+                       const WaveBufs& wb, int b, int sorted, uint32_t tail, uint2* ovf, int gcap);
 // counting sort of queue b by material key when it holds >= threshold paths
 hipError_t launch_sort(dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const WaveBufs& wb, int b,
                        uint32_t threshold);

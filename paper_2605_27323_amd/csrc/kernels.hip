@@ -102,12 +102,22 @@ __global__ void __launch_bounds__(256) k_shade_tail(SceneView sc, PathParams pp,
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t* perm = (sorted && wb.hist[2 * kSortBins]) ? wb.perm : nullptr;
     TravStack<LDS> st = make_stack<LDS>(smem, ovf, gcap, gtid, nlanes);
+    uint32_t n_ext = 0, n_sh = 0;
     for (uint32_t i = gtid; i < count; i += nlanes) {
         VertexOut vo;
         ShadowReq sh;
         PathState ps;
         const uint32_t path = shade_item(sc, pp, wb, b, i, vo, sh, ps, perm);
-        finish_path<LDS>(sc, pp, wb, path, b + 1, vo, sh, ps, st);
+        finish_path<LDS>(sc, pp, wb, path, b + 1, vo, sh, ps, st, n_ext, n_sh);
+    }
+    // every lane of the wave is here: reduce the ray counts across it
+    for (int off = 32; off > 0; off >>= 1) {
+        n_ext += __shfl_xor(n_ext, off);
+        n_sh += __shfl_xor(n_sh, off);
+    }
+    if (lane_id() == 0 && (n_ext | n_sh)) {
+        atomicAdd(&wb.counts[wb.tail_slot], n_ext);
+        atomicAdd(&wb.counts[wb.tail_slot + 1], n_sh);
     }
     if (st.overflow) atomicOr(&wb.counts[wb.err_slot], 1u);
 }
@@ -290,11 +300,14 @@ hipError_t launch_extend(int lds, dim3 grid, dim3 block, hipStream_t s, const Sc
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_shade(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const PathParams& pp,
-                        const WaveBufs& wb, int b, int compact, int sorted, uint32_t tail, uint2* ovf, int gcap) {
+hipError_t launch_shade(dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const PathParams& pp,
+                        const WaveBufs& wb, int b, int compact, int sorted, uint32_t tail) {
     hipLaunchKernelGGL(k_shade, grid, block, 0, s, sc, pp, wb, b, compact, sorted, compact ? tail : 0u);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !tail || !compact) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_tail(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const PathParams& pp,
+                       const WaveBufs& wb, int b, int sorted, uint32_t tail, uint2* ovf, int gcap) {
     const size_t sm = stack_lds_bytes(lds, block.x);
 #define X(N)                                                                                                 \
     if (lds == N) {                                                                                          \

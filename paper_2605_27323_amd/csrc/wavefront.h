@@ -95,20 +95,24 @@ PT_DEV uint32_t shade_item(const SceneView& sc, const PathParams& pp, const Wave
 // order: light sample of the current vertex, then extend and shade the next
 // vertices) and store its final radiance.  Used when a bounce's queue is too
 // short to keep the wavefront stages busy.
+// n_ext / n_sh count the extension and shadow rays traced here.
 template <int LDS>
 PT_DEV void finish_path(const SceneView& sc, const PathParams& pp, const WaveBufs& wb, uint32_t path, int k,
-                        VertexOut vo, ShadowReq sh, PathState& ps, TravStack<LDS>& st) {
+                        VertexOut vo, ShadowReq sh, PathState& ps, TravStack<LDS>& st, uint32_t& n_ext,
+                        uint32_t& n_sh) {
     const uint32_t pix = path / (uint32_t)pp.spp;
     const uint32_t s = path - pix * (uint32_t)pp.spp;
     const uint32_t sample = pp.frame * (uint32_t)pp.spp + s;
     while (true) {
         if (sh.valid) {
+            ++n_sh;
             Ray sr = make_ray(sh.o, sh.d);
             if (!any_hit<LDS>(sc, sr, kShadowTmax, st))
                 ps.L = mk3(ps.L.x + sh.contrib.x, ps.L.y + sh.contrib.y, ps.L.z + sh.contrib.z);
         }
         if (!vo.cont) break;
         ++k;
+        ++n_ext;
         const f3 d = vo.d;
         Ray ray = make_ray(vo.o, d);
         Hit h = closest_hit<LDS>(sc, ray, INFINITY, st);

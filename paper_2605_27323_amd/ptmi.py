@@ -17,8 +17,8 @@ LIB_PATH = os.environ.get("PTMI_LIB") or os.path.join(HERE, "libptmi.so")
 
 PT_OK, PT_EINVAL, PT_ENOMEM, PT_EHIP, PT_ESTATE, PT_EOVERFLOW, PT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 MODE_MEGA, MODE_WAVE = 0, 1
-FLAG_PROFILE, FLAG_NO_COMPACT, FLAG_SORT_MATERIAL, FLAG_COUNT_RAYS = 1, 2, 4, 8
-STAGES = ["raygen", "extend", "shade", "shadow", "accumulate", "mega", "sort", "adjoint"]
+FLAG_PROFILE, FLAG_NO_COMPACT, FLAG_SORT_MATERIAL = 1, 2, 4
+STAGES = ["raygen", "extend", "shade", "shadow", "accumulate", "mega", "sort", "adjoint", "tail"]
 
 
 class PtError(RuntimeError):
@@ -61,9 +61,13 @@ class RenderArgs(C.Structure):
                 ("sort_threshold", C.c_uint32), ("stack_lds", C.c_int32), ("tail_threshold", C.c_uint32)]
 
 
+NSTAGES = 9
+
+
 class FrameStats(C.Structure):
-    _fields_ = [("stage_ms", C.c_double * 8), ("launches", C.c_int64 * 8), ("extension_rays", C.c_int64),
-                ("shadow_rays", C.c_int64)]
+    _fields_ = [("stage_ms", C.c_double * NSTAGES), ("launches", C.c_int64 * NSTAGES),
+                ("stage_items", C.c_int64 * NSTAGES), ("stage_bytes", C.c_double * NSTAGES),
+                ("extension_rays", C.c_int64), ("shadow_rays", C.c_int64)]
 
 
 class Job(C.Structure):
@@ -268,8 +272,10 @@ class Renderer(Context):
     def stats(self):
         s = FrameStats()
         check(lib().pt_frame_stats_get(self.h, C.byref(s)))
-        return {"stage_ms": {STAGES[k]: s.stage_ms[k] for k in range(8) if s.launches[k]},
-                "launches": {STAGES[k]: s.launches[k] for k in range(8) if s.launches[k]},
+        return {"stage_ms": {STAGES[k]: s.stage_ms[k] for k in range(NSTAGES) if s.launches[k]},
+                "launches": {STAGES[k]: s.launches[k] for k in range(NSTAGES) if s.launches[k]},
+                "items": {STAGES[k]: s.stage_items[k] for k in range(NSTAGES) if s.stage_items[k]},
+                "bytes": {STAGES[k]: s.stage_bytes[k] for k in range(NSTAGES) if s.stage_items[k]},
                 "extension_rays": s.extension_rays, "shadow_rays": s.shadow_rays}
 
     def sync(self):

@@ -109,6 +109,7 @@ int32_t emu_render_wave(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32
     wb.L = buf[10].data();
     wb.counts = counts.data();
     wb.sh_base = D + 2;
+    wb.tail_slot = 2 * D + 3;
     wb.err_slot = (int)counts.size() - 1;
     std::mt19937_64 rng(shuffle_seed);
     HostStack hs(std::max(0, c->bvh.stack_entries - kL));
@@ -139,11 +140,14 @@ int32_t emu_render_wave(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32
             ShadowReq sh;
             PathState ps;
             uint32_t path = shade_item(sc, pp, wb, b, i, vo, sh, ps, sort ? perm.data() : nullptr);
+            if (path != kDeadPath) ++ne;
             if (finish) {
-                finish_path<kL>(sc, pp, wb, path, b + 1, vo, sh, ps, hs.st);
+                uint32_t te = 0, ts = 0;
+                finish_path<kL>(sc, pp, wb, path, b + 1, vo, sh, ps, hs.st, te, ts);
+                ne += te;
+                ns += ts;
                 continue;
             }
-            if (path != kDeadPath) ++ne;
             if (compact) {
                 if (vo.cont) write_continuation(wb, nxt, counts[b + 1]++, vo, ps, path);
             } else {

@@ -48,8 +48,9 @@ def test_procedural_scenes(mode, cfg):
     w, rw = E.wave(sort=True, shuffle=3, **cfg)
     assert np.array_equal(w.view(np.uint32), img.view(np.uint32))
     for tail in (1, 500, 10 ** 9):  # hybrid tail from some bounce on, or from the start
-        w, _ = E.wave(tail=tail, shuffle=tail, **cfg)
+        w, rt = E.wave(tail=tail, shuffle=tail, **cfg)
         assert np.array_equal(w.view(np.uint32), img.view(np.uint32))
+        assert (rt == rays).all()  # the tail's in-place rays are counted too
 
 
 def test_furnace_and_sky_exact():

@@ -168,8 +168,7 @@ def test_progressive_accumulation_and_ray_counts():
     acc = torch.zeros((17, 33, 3), dtype=torch.float32, device="cuda")
     ref_acc = None
     for frame in range(4):
-        R.render(mode="wave" if frame % 2 else "mega", accum=acc, spp=2, max_depth=4, frame=frame,
-                 flags=ptmi.FLAG_COUNT_RAYS)
+        R.render(mode="wave" if frame % 2 else "mega", accum=acc, spp=2, max_depth=4, frame=frame)
         I, _ = S.render(cam, spp=2, max_depth=4, frame=frame)
         if ref_acc is None:
             ref_acc = I.copy()
@@ -180,12 +179,17 @@ def test_progressive_accumulation_and_ray_counts():
     frac, nfail, unexplained, nexact = image_tolerance_report(got, ref_acc, np.zeros(len(ref_acc)))
     assert nexact >= 0.999 * len(ref_acc)
     # identical paths => identical ray counts in both schedules
-    R.render(mode="mega", spp=2, max_depth=4, flags=ptmi.FLAG_COUNT_RAYS)
+    R.render(mode="mega", spp=2, max_depth=4)
     sm = R.stats()
-    R.render(mode="wave", spp=2, max_depth=4, flags=ptmi.FLAG_COUNT_RAYS)
+    R.render(mode="wave", spp=2, max_depth=4)
     sw = R.stats()
     assert sm["extension_rays"] == sw["extension_rays"] > 0
     assert sm["shadow_rays"] == sw["shadow_rays"] > 0
+    # the hybrid tail traces the rest of the paths in place and counts them
+    R.render(mode="wave", spp=2, max_depth=4, tail_threshold=400)
+    st = R.stats()
+    assert st["items"].get("tail", 0) > 0
+    assert (st["extension_rays"], st["shadow_rays"]) == (sm["extension_rays"], sm["shadow_rays"])
 
 
 def test_profile_stage_times():
@@ -195,3 +199,13 @@ def test_profile_stage_times():
     st = R.stats()
     assert st["launches"]["extend"] == 6 and st["launches"]["shade"] == 6
     assert all(v >= 0 for v in st["stage_ms"].values())
+    # work items and algorithmic bytes follow from the queue counts
+    it, by = st["items"], st["bytes"]
+    assert it["raygen"] == 48 * 32 and it["accumulate"] == 48 * 32
+    assert it["extend"] == st["extension_rays"] and it["shadow"] == st["shadow_rays"]
+    assert it["shade"] == it["extend"] and "tail" not in it
+    assert by["extend"] == 48 * it["extend"] and by["shadow"] == 48 * it["shadow"]
+    assert by["shade"] == 80 * it["shade"] + 48 * (it["extend"] - it["raygen"]) + 48 * it["shadow"]
+    R.render(mode="wave", spp=1, max_depth=5, rr_start=3, tail_threshold=1 << 30, flags=ptmi.FLAG_PROFILE)
+    st = R.stats()
+    assert st["launches"]["tail"] == 6 and st["items"]["tail"] == 48 * 32 and "shade" not in st["items"]
