@@ -20,7 +20,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # autotuner result on MI355X for the 1M-triangle 1080p workload
-FIXED_PARAMS = {"wave": {"block": 256, "grid_mult": 16, "stack_lds": 8, "tail_threshold": 1 << 18},
+FIXED_PARAMS = {"wave": {"block": 256, "grid_mult": 8, "stack_lds": 8, "tail_threshold": 1 << 18},
                 "mega": {"block": 256, "grid_mult": 16, "stack_lds": 8}}
 W, H, SPP, DEPTH, RR = 1920, 1080, 1, 8, 3
 
@@ -87,6 +87,8 @@ def main():
     ap.add_argument("--fixed", action="store_true",
                     help="launch parameters the autotuner chose on MI355X for this workload, without tuning "
                          "(for profiled runs)")
+    ap.add_argument("--params", default=None,
+                    help='launch parameters as JSON, e.g. {"wave": {"block": 256, "grid_mult": 8}} (no tuning)')
     ap.add_argument("--batch", action="store_true",
                     help="batched workload instead: 64 jobs, 10k-2M triangles each, mixed resolutions and spp")
     ap.add_argument("--divergence", action="store_true",
@@ -127,7 +129,10 @@ def main():
     img = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
     modes = ["wave", "mega"] if args.mode == "both" else [args.mode]
     tuned = {m: {} for m in modes}
-    if args.fixed:
+    if args.params:
+        given = json.loads(args.params)
+        tuned = {m: dict(given.get(m, FIXED_PARAMS[m])) for m in modes}
+    elif args.fixed:
         tuned = {m: dict(FIXED_PARAMS[m]) for m in modes}
     elif not args.no_tune:
         for mode in modes:

@@ -18,7 +18,7 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ptmi_autotune.j
 
 FRAME_SPACE = {
     "wave": {"block": [64, 128, 256], "grid_mult": [4, 8, 16], "stack_lds": [8, 16],
-             "sort_threshold": [None, 1 << 16], "tail_threshold": [0, 1 << 14, 1 << 16, 1 << 18]},
+             "sort_threshold": [None, 1 << 16], "tail_threshold": [0, 1 << 16, 1 << 18, 1 << 19, 1 << 20]},
     "mega": {"block": [64, 128, 256], "grid_mult": [2, 4, 8, 16], "stack_lds": [8, 16]},
 }
 BATCH_SPACE = {"pool_capacity": [1 << 20, 1 << 21, 1 << 22], "block": [128, 256], "grid_mult": [4, 8],

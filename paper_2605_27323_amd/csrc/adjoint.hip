@@ -24,14 +24,8 @@ __global__ void __launch_bounds__(256) k_adjoint(SceneView sc, CamView cam, Path
     extern __shared__ __align__(8) uint32_t smem[];
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
-    TravStack<LDS> st;
-    st.lds = reinterpret_cast<uint2*>(smem) + threadIdx.x;
-    st.lstride = blockDim.x;
-    st.gbl = ovf + gtid;
-    st.gstride = (int)nlanes;
-    st.gcap = gcap;
-    st.sp = 0;
-    st.overflow = false;
+    TravStack<LDS> st =
+        make_trav_stack<LDS>(reinterpret_cast<uint2*>(smem) + threadIdx.x, (int)blockDim.x, ovf + gtid, (int)nlanes, gcap);
     AtomicAcc acc;
     const uint32_t npaths = (uint32_t)cam.W * (uint32_t)cam.H * (uint32_t)pp.spp;
     const float fs = (float)pp.spp;

@@ -21,15 +21,8 @@ __device__ __forceinline__ uint32_t reserve_b(uint32_t* ctr, uint64_t m) {
 
 template <int LDS>
 __device__ __forceinline__ TravStack<LDS> stack_b(uint32_t* smem, uint2* ovf, int gcap) {
-    TravStack<LDS> st;
-    st.lds = reinterpret_cast<uint2*>(smem) + threadIdx.x;
-    st.lstride = blockDim.x;
-    st.gbl = ovf + blockIdx.x * blockDim.x + threadIdx.x;
-    st.gstride = (int)(gridDim.x * blockDim.x);
-    st.gcap = gcap;
-    st.sp = 0;
-    st.overflow = false;
-    return st;
+    return make_trav_stack<LDS>(reinterpret_cast<uint2*>(smem) + threadIdx.x, (int)blockDim.x,
+                                ovf + blockIdx.x * blockDim.x + threadIdx.x, (int)(gridDim.x * blockDim.x), gcap);
 }
 
 // wave-aggregated job counters: every lane of the wave calls this; lanes

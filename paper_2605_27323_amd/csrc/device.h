@@ -245,12 +245,24 @@ PT_DEV unsigned slab4(const Ray& r, const float4 q[7], float tlim, float tn[4]) 
 }
 
 // ---------------------------------------------------------------------------
-// traversal stack: per-lane entries in LDS (stride = block size), deeper
-// entries spill to a per-lane global area (stride = number of lanes)
+// traversal stack: per-lane entries in LDS (stride = block size, so the 64
+// lanes of a wave hit 64 consecutive 8-byte words), deeper entries spill to
+// a per-lane global area (stride = number of lanes).  The LDS pointer
+// carries the local address space so that pushes and pops compile to
+// ds_write_b64 / ds_read_b64 rather than flat accesses.
 // ---------------------------------------------------------------------------
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef __attribute__((address_space(3))) uint2 lds_uint2;
+// product of two values below 2^24 (full-rate 24-bit multiply on the GPU)
+__device__ __forceinline__ uint32_t mul24(uint32_t a, uint32_t b) { return __umul24(a, b); }
+#else
+typedef uint2 lds_uint2;
+inline uint32_t mul24(uint32_t a, uint32_t b) { return (a & 0xFFFFFFu) * (b & 0xFFFFFFu); }
+#endif
+
 template <int LDS>
 struct TravStack {
-    uint2* lds;  // (reference, entry distance bits), one 64-bit LDS access per push / pop
+    lds_uint2* lds;  // (reference, entry distance bits), one 64-bit LDS access per push / pop
     uint2* gbl;
     int lstride;
     int gstride;
@@ -259,10 +271,11 @@ struct TravStack {
     bool overflow;
 
     PT_DEV void push(uint32_t ref, float t) {
+        const uint2 e = make_uint2(ref, f2u(t));
         if (sp < LDS) {
-            lds[sp * lstride] = make_uint2(ref, f2u(t));
+            lds[mul24((uint32_t)sp, (uint32_t)lstride)] = e;
         } else if (sp - LDS < gcap) {
-            gbl[(sp - LDS) * gstride] = make_uint2(ref, f2u(t));
+            gbl[(size_t)(sp - LDS) * (uint32_t)gstride] = e;
         } else {
             overflow = true;
             return;
@@ -272,16 +285,34 @@ struct TravStack {
     PT_DEV void pop(uint32_t& ref, float& t) {
         --sp;
         if (sp < LDS) {
-            uint2 e = lds[sp * lstride];
+            const uint2 e = lds[mul24((uint32_t)sp, (uint32_t)lstride)];
             ref = e.x;
             t = u2f(e.y);
         } else {
-            uint2 e = gbl[(sp - LDS) * gstride];
-            ref = e.x;
-            t = u2f(e.y);
+            // a distinct load kind keeps the compiler from merging the two
+            // branches into one flat load through a selected pointer
+            const uint64_t e = __builtin_nontemporal_load(
+                reinterpret_cast<const uint64_t*>(gbl + (size_t)(sp - LDS) * (uint32_t)gstride));
+            ref = (uint32_t)e;
+            t = u2f((uint32_t)(e >> 32));
         }
     }
 };
+
+// lds_lane: this lane's first LDS entry (entry k at lds_lane[k * lstride]);
+// gbl_lane: its first spill entry (entry LDS + k at gbl_lane[k * gstride])
+template <int LDS>
+PT_DEV TravStack<LDS> make_trav_stack(uint2* lds_lane, int lstride, uint2* gbl_lane, int gstride, int gcap) {
+    TravStack<LDS> st;
+    st.lds = (lds_uint2*)lds_lane;
+    st.lstride = lstride;
+    st.gbl = gbl_lane;
+    st.gstride = gstride;
+    st.gcap = gcap;
+    st.sp = 0;
+    st.overflow = false;
+    return st;
+}
 
 struct Hit {
     float t, b1, b2;
@@ -295,139 +326,176 @@ PT_DEV void load_node(const float4* __restrict__ nodes, uint32_t idx, float4 q[8
     for (int i = 0; i < 7; ++i) q[i] = p[i];
 }
 
-// sort up to four (ref, t) pairs by t (ascending), invalid entries last
+// sort four (ref, t) pairs by t (ascending), invalid entries (t = +inf)
+// last; a select network, no branches
+PT_DEV void cswap(uint32_t& ra, float& ta, uint32_t& rb, float& tb) {
+    const bool s = tb < ta;
+    const float t0 = s ? tb : ta, t1 = s ? ta : tb;
+    const uint32_t r0 = s ? rb : ra, r1 = s ? ra : rb;
+    ta = t0;
+    tb = t1;
+    ra = r0;
+    rb = r1;
+}
+
 PT_DEV void sort4(uint32_t ref[4], float t[4]) {
-#define PT_CSWAP(a, b)                         \
-    if (t[b] < t[a]) {                         \
-        float tt = t[a]; t[a] = t[b]; t[b] = tt; \
-        uint32_t rr = ref[a]; ref[a] = ref[b]; ref[b] = rr; \
-    }
-    PT_CSWAP(0, 1);
-    PT_CSWAP(2, 3);
-    PT_CSWAP(0, 2);
-    PT_CSWAP(1, 3);
-    PT_CSWAP(1, 2);
-#undef PT_CSWAP
+    cswap(ref[0], t[0], ref[1], t[1]);
+    cswap(ref[2], t[2], ref[3], t[3]);
+    cswap(ref[0], t[0], ref[2], t[2]);
+    cswap(ref[1], t[1], ref[3], t[3]);
+    cswap(ref[1], t[1], ref[2], t[2]);
 }
 
 // Closest hit in (0, tmax): smallest t, ties to the smaller input id.
 // References outside the node or triangle arrays are skipped, so a damaged
 // BVH cannot make a lane read out of bounds.
+//
+// The traversal is written as a resumable step (closest_step), so that a
+// persistent kernel can run one step per loop trip and hand a finished
+// lane a new ray while the others are still traversing.  closest_hit runs
+// the steps to the end.
+
 template <int LDS>
-PT_DEV Hit closest_hit(const SceneView& sc, const Ray& r, float tmax, TravStack<LDS>& st) {
-    Hit h;
+PT_DEV void closest_begin(float tmax, Hit& h, uint32_t& ref, TravStack<LDS>& st) {
     h.t = tmax;
     h.b1 = 0.0f;
     h.b2 = 0.0f;
     h.tri = 0xFFFFFFFFu;
     h.id = 0xFFFFFFFFu;
     st.sp = 0;
-    uint32_t ref = 0;  // root
-    while (true) {
-        if (!(ref & kLeafBit)) {
-            if (ref < (uint32_t)sc.n_nodes) {
-                float4 q[8];
-                load_node(sc.nodes, ref, q);
-                float tn[4];
-                unsigned m = slab4(r, q, h.t, tn);
-                if (m) {
-                    uint32_t rr[4];
-                    float tt[4];
+    ref = 0;  // root
+}
+
+// Visit `ref` (an inner node: push the farther hit children, move to the
+// nearest; a leaf: test its triangles), then pop the next entry that can
+// still hold a closer hit.  Returns false when the traversal is finished.
+template <int LDS>
+PT_DEV bool closest_step(const SceneView& sc, const Ray& r, float tmax, Hit& h, uint32_t& ref, TravStack<LDS>& st) {
+    if (!(ref & kLeafBit)) {
+        if (ref < (uint32_t)sc.n_nodes) {
+            float4 q[8];
+            load_node(sc.nodes, ref, q);
+            float tn[4];
+            unsigned m = slab4(r, q, h.t, tn);
+            if (m) {
+                uint32_t rr[4];
+                float tt[4];
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        bool hit = (m >> c) & 1u;
-                        const float cref = c == 0 ? q[6].x : (c == 1 ? q[6].y : (c == 2 ? q[6].z : q[6].w));
-                        rr[c] = hit ? f2u(cref) : kEmptyRef;
-                        tt[c] = hit ? tn[c] : INFINITY;
-                    }
-                    sort4(rr, tt);
-                    // push the farther hits (farthest first), descend into the nearest
-                    if (rr[3] != kEmptyRef) st.push(rr[3], tt[3]);
-                    if (rr[2] != kEmptyRef) st.push(rr[2], tt[2]);
-                    if (rr[1] != kEmptyRef) st.push(rr[1], tt[1]);
-                    ref = rr[0];
-                    continue;
+                for (int c = 0; c < 4; ++c) {
+                    bool hit = (m >> c) & 1u;
+                    const float cref = c == 0 ? q[6].x : (c == 1 ? q[6].y : (c == 2 ? q[6].z : q[6].w));
+                    rr[c] = hit ? f2u(cref) : kEmptyRef;
+                    tt[c] = hit ? tn[c] : INFINITY;
                 }
+                sort4(rr, tt);
+                // push the farther hits (farthest first), descend into the nearest
+                if (rr[3] != kEmptyRef) st.push(rr[3], tt[3]);
+                if (rr[2] != kEmptyRef) st.push(rr[2], tt[2]);
+                if (rr[1] != kEmptyRef) st.push(rr[1], tt[1]);
+                ref = rr[0];
+                return true;
             }
-        } else {
-            uint32_t first = ref & kLeafFirstMask;
-            uint32_t cnt = ((ref >> kLeafCountShift) & 15u) + 1u;
-            if (first + cnt <= (uint32_t)sc.nt) {
-                for (uint32_t i = first; i < first + cnt; ++i) {
-                    const float4* tp = sc.tris + (size_t)i * 3;
-                    float4 a = tp[0], b = tp[1], c = tp[2];
-                    float t, b1, b2;
-                    if (tri_intersect(r, xyz(a), xyz(b), xyz(c), t, b1, b2) && t < tmax) {
-                        uint32_t id = f2u(a.w);
-                        if (t < h.t || (t == h.t && id < h.id)) {
-                            h.t = t;
-                            h.b1 = b1;
-                            h.b2 = b2;
-                            h.tri = i;
-                            h.id = id;
-                        }
+        }
+    } else {
+        uint32_t first = ref & kLeafFirstMask;
+        uint32_t cnt = ((ref >> kLeafCountShift) & 15u) + 1u;
+        if (first + cnt <= (uint32_t)sc.nt) {
+            for (uint32_t i = first; i < first + cnt; ++i) {
+                const float4* tp = sc.tris + (size_t)i * 3;
+                float4 a = tp[0], b = tp[1], c = tp[2];
+                float t, b1, b2;
+                if (tri_intersect(r, xyz(a), xyz(b), xyz(c), t, b1, b2) && t < tmax) {
+                    uint32_t id = f2u(a.w);
+                    if (t < h.t || (t == h.t && id < h.id)) {
+                        h.t = t;
+                        h.b1 = b1;
+                        h.b2 = b2;
+                        h.tri = i;
+                        h.id = id;
                     }
                 }
             }
         }
-        // pop the next entry that can still hold a closer hit
-        bool found = false;
-        while (st.sp > 0) {
-            float t;
-            st.pop(ref, t);
-            if (t <= h.t * kBoxSlack) {
-                found = true;
-                break;
-            }
-        }
-        if (!found) break;
+    }
+    while (st.sp > 0) {
+        float t;
+        st.pop(ref, t);
+        if (t <= h.t * kBoxSlack) return true;
+    }
+    return false;
+}
+
+template <int LDS>
+PT_DEV Hit closest_hit(const SceneView& sc, const Ray& r, float tmax, TravStack<LDS>& st) {
+    Hit h;
+    uint32_t ref;
+    closest_begin<LDS>(tmax, h, ref, st);
+    while (closest_step<LDS>(sc, r, tmax, h, ref, st)) {
     }
     return h;
 }
 
-// Any hit in (0, tmax).
+// Any hit in (0, tmax), as resumable steps: any_step visits `ref` and pops
+// the next entry; it returns false when the traversal is finished, with
+// `occluded` set if a triangle was hit.
 template <int LDS>
-PT_DEV bool any_hit(const SceneView& sc, const Ray& r, float tmax, TravStack<LDS>& st) {
+PT_DEV void any_begin(uint32_t& ref, TravStack<LDS>& st) {
     st.sp = 0;
-    uint32_t ref = 0;
-    while (true) {
-        if (!(ref & kLeafBit)) {
-            if (ref < (uint32_t)sc.n_nodes) {
-                float4 q[8];
-                load_node(sc.nodes, ref, q);
-                float tn[4];
-                unsigned m = slab4(r, q, tmax, tn);
-                if (m) {
-                    // descend into the first hit child, push the others
-                    const uint32_t cr[4] = {f2u(q[6].x), f2u(q[6].y), f2u(q[6].z), f2u(q[6].w)};
-                    uint32_t next = kEmptyRef;
+    ref = 0;
+}
+
+template <int LDS>
+PT_DEV bool any_step(const SceneView& sc, const Ray& r, float tmax, uint32_t& ref, TravStack<LDS>& st,
+                     bool& occluded) {
+    if (!(ref & kLeafBit)) {
+        if (ref < (uint32_t)sc.n_nodes) {
+            float4 q[8];
+            load_node(sc.nodes, ref, q);
+            float tn[4];
+            unsigned m = slab4(r, q, tmax, tn);
+            if (m) {
+                // descend into the first hit child, push the others
+                const uint32_t cr[4] = {f2u(q[6].x), f2u(q[6].y), f2u(q[6].z), f2u(q[6].w)};
+                uint32_t next = kEmptyRef;
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        if (!((m >> c) & 1u)) continue;
-                        if (next == kEmptyRef) next = cr[c];
-                        else st.push(cr[c], tn[c]);
-                    }
-                    ref = next;
-                    continue;
+                for (int c = 0; c < 4; ++c) {
+                    if (!((m >> c) & 1u)) continue;
+                    if (next == kEmptyRef) next = cr[c];
+                    else st.push(cr[c], tn[c]);
                 }
+                ref = next;
+                return true;
             }
-        } else {
-            uint32_t first = ref & kLeafFirstMask;
-            uint32_t cnt = ((ref >> kLeafCountShift) & 15u) + 1u;
-            if (first + cnt <= (uint32_t)sc.nt) {
-                for (uint32_t i = first; i < first + cnt; ++i) {
-                    const float4* tp = sc.tris + (size_t)i * 3;
-                    float4 a = tp[0], b = tp[1], c = tp[2];
-                    float t, b1, b2;
-                    if (tri_intersect(r, xyz(a), xyz(b), xyz(c), t, b1, b2) && t < tmax) return true;
+        }
+    } else {
+        uint32_t first = ref & kLeafFirstMask;
+        uint32_t cnt = ((ref >> kLeafCountShift) & 15u) + 1u;
+        if (first + cnt <= (uint32_t)sc.nt) {
+            for (uint32_t i = first; i < first + cnt; ++i) {
+                const float4* tp = sc.tris + (size_t)i * 3;
+                float4 a = tp[0], b = tp[1], c = tp[2];
+                float t, b1, b2;
+                if (tri_intersect(r, xyz(a), xyz(b), xyz(c), t, b1, b2) && t < tmax) {
+                    occluded = true;
+                    return false;
                 }
             }
         }
-        if (st.sp == 0) break;
-        float t;
-        st.pop(ref, t);
     }
-    return false;
+    if (st.sp == 0) return false;
+    float t;
+    st.pop(ref, t);
+    return true;
+}
+
+template <int LDS>
+PT_DEV bool any_hit(const SceneView& sc, const Ray& r, float tmax, TravStack<LDS>& st) {
+    uint32_t ref;
+    any_begin<LDS>(ref, st);
+    bool occluded = false;
+    while (any_step<LDS>(sc, r, tmax, ref, st, occluded)) {
+    }
+    return occluded;
 }
 
 // ---------------------------------------------------------------------------

@@ -38,6 +38,9 @@ struct WaveBufs {
 };
 
 constexpr int kSortBins = 64;
+// persistent traversal kernels refill a wave's idle lanes once this many
+// of its 64 lanes are idle
+constexpr uint32_t kRefill = 16;
 
 hipError_t launch_mega(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const CamView& cam,
                        const PathParams& pp, float* img, float* acc, uint2* ovf, int gcap, uint32_t* stats);

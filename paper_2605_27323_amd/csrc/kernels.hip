@@ -29,15 +29,8 @@ __device__ __forceinline__ uint32_t wave_reserve(uint32_t* ctr, uint64_t m) {
 template <int LDS>
 __device__ __forceinline__ TravStack<LDS> make_stack(uint32_t* smem, uint2* ovf, int gcap, uint32_t gtid,
                                                      uint32_t nlanes) {
-    TravStack<LDS> st;
-    st.lds = reinterpret_cast<uint2*>(smem) + threadIdx.x;
-    st.lstride = blockDim.x;
-    st.gbl = ovf + gtid;
-    st.gstride = (int)nlanes;
-    st.gcap = gcap;
-    st.sp = 0;
-    st.overflow = false;
-    return st;
+    return make_trav_stack<LDS>(reinterpret_cast<uint2*>(smem) + threadIdx.x, (int)blockDim.x, ovf + gtid,
+                                (int)nlanes, gcap);
 }
 
 }  // namespace
@@ -128,14 +121,62 @@ __global__ void __launch_bounds__(256) k_raygen(CamView cam, PathParams pp, Wave
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < npaths; p += nlanes) raygen_item(cam, pp, wb, p);
 }
 
+// Persistent traversal: each wave owns a contiguous chunk of the queue and
+// keeps its 64 lanes busy by handing queue entries to lanes whose ray has
+// finished, one traversal step per loop trip, instead of letting finished
+// lanes idle until the slowest ray of the wave is done.  Lanes are refilled
+// when at least `refill` of them are idle (or all are); the chunk cursor is
+// wave-uniform, so no atomics are needed.
+__device__ __forceinline__ void wave_chunk(uint32_t count, uint32_t& next, uint32_t& end) {
+    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t chunk = (uint32_t)(((uint64_t)count + nwaves - 1) / nwaves);
+    next = (uint32_t)min((uint64_t)wave * chunk, (uint64_t)count);
+    end = (uint32_t)min((uint64_t)next + chunk, (uint64_t)count);
+}
+
 template <int LDS>
-__global__ void __launch_bounds__(256) k_extend(SceneView sc, WaveBufs wb, int b, uint2* __restrict__ ovf, int gcap) {
+__global__ void __launch_bounds__(256) k_extend(SceneView sc, WaveBufs wb, int b, uint2* __restrict__ ovf, int gcap,
+                                                uint32_t refill) {
     extern __shared__ __align__(8) uint32_t smem[];
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
     TravStack<LDS> st = make_stack<LDS>(smem, ovf, gcap, gtid, nlanes);
-    const uint32_t count = wb.counts[b];
-    for (uint32_t i = gtid; i < count; i += nlanes) extend_item<LDS>(sc, wb, b, i, st);
+    const int cur = b & 1;
+    uint32_t next, end;
+    wave_chunk(wb.counts[b], next, end);
+    bool live = false;
+    uint32_t item = 0, ref = 0;
+    Ray ray;
+    Hit h;
+    while (true) {
+        const uint64_t idle = __ballot(!live);
+        const uint32_t nidle = (uint32_t)__popcll(idle);
+        if (next < end && (nidle >= refill || nidle == 64u)) {
+            if (!live) {
+                const uint32_t i = next + rank_in(idle);
+                if (i < end) {
+                    const float4 o4 = wb.ray_o[cur][i];
+                    if (f2u(o4.w) != kDeadPath) {  // dead slots (no compaction) need no hit
+                        const float4 d4 = wb.ray_d[cur][i];
+                        ray = make_ray(xyz(o4), xyz(d4));
+                        closest_begin<LDS>(INFINITY, h, ref, st);
+                        item = i;
+                        live = true;
+                    }
+                }
+            }
+            next = min(next + nidle, end);
+        }
+        if (__ballot(live) == 0ull) {
+            if (next < end) continue;
+            break;
+        }
+        if (live && !closest_step<LDS>(sc, ray, INFINITY, h, ref, st)) {
+            wb.hit[item] = make_float4(h.t, h.b1, h.b2, u2f(h.tri));
+            live = false;
+        }
+    }
     if (st.overflow) atomicOr(&wb.counts[wb.err_slot], 1u);
 }
 
@@ -180,13 +221,44 @@ __global__ void __launch_bounds__(256) k_shade(SceneView sc, PathParams pp, Wave
 }
 
 template <int LDS>
-__global__ void __launch_bounds__(256) k_shadow(SceneView sc, WaveBufs wb, int b, uint2* __restrict__ ovf, int gcap) {
+__global__ void __launch_bounds__(256) k_shadow(SceneView sc, WaveBufs wb, int b, uint2* __restrict__ ovf, int gcap,
+                                                uint32_t refill) {
     extern __shared__ __align__(8) uint32_t smem[];
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
     TravStack<LDS> st = make_stack<LDS>(smem, ovf, gcap, gtid, nlanes);
-    const uint32_t count = wb.counts[wb.sh_base + b];
-    for (uint32_t i = gtid; i < count; i += nlanes) shadow_item<LDS>(sc, wb, i, st);
+    uint32_t next, end;
+    wave_chunk(wb.counts[wb.sh_base + b], next, end);
+    bool live = false;
+    uint32_t item = 0, ref = 0;
+    Ray ray;
+    while (true) {
+        const uint64_t idle = __ballot(!live);
+        const uint32_t nidle = (uint32_t)__popcll(idle);
+        if (next < end && (nidle >= refill || nidle == 64u)) {
+            if (!live) {
+                const uint32_t i = next + rank_in(idle);
+                if (i < end) {
+                    ray = make_ray(xyz(wb.sh_o[i]), xyz(wb.sh_d[i]));
+                    any_begin<LDS>(ref, st);
+                    item = i;
+                    live = true;
+                }
+            }
+            next = min(next + nidle, end);
+        }
+        if (__ballot(live) == 0ull) {
+            if (next < end) continue;
+            break;
+        }
+        if (live) {
+            bool occluded = false;
+            if (!any_step<LDS>(sc, ray, kShadowTmax, ref, st, occluded)) {
+                live = false;
+                if (!occluded) shadow_add(wb, item);
+            }
+        }
+    }
     if (st.overflow) atomicOr(&wb.counts[wb.err_slot], 1u);
 }
 
@@ -294,7 +366,7 @@ hipError_t launch_extend(int lds, dim3 grid, dim3 block, hipStream_t s, const Sc
                          int b, uint2* ovf, int gcap) {
     size_t sm = stack_lds_bytes(lds, block.x);
 #define X(N) \
-    if (lds == N) { hipLaunchKernelGGL(k_extend<N>, grid, block, sm, s, sc, wb, b, ovf, gcap); return hipGetLastError(); }
+    if (lds == N) { hipLaunchKernelGGL(k_extend<N>, grid, block, sm, s, sc, wb, b, ovf, gcap, kRefill); return hipGetLastError(); }
     PT_STACK_CASES(X)
 #undef X
     return hipErrorInvalidValue;
@@ -335,7 +407,7 @@ hipError_t launch_shadow(int lds, dim3 grid, dim3 block, hipStream_t s, const Sc
                          int b, uint2* ovf, int gcap) {
     size_t sm = stack_lds_bytes(lds, block.x);
 #define X(N) \
-    if (lds == N) { hipLaunchKernelGGL(k_shadow<N>, grid, block, sm, s, sc, wb, b, ovf, gcap); return hipGetLastError(); }
+    if (lds == N) { hipLaunchKernelGGL(k_shadow<N>, grid, block, sm, s, sc, wb, b, ovf, gcap, kRefill); return hipGetLastError(); }
     PT_STACK_CASES(X)
 #undef X
     return hipErrorInvalidValue;

@@ -138,17 +138,20 @@ PT_DEV void write_shadow(const WaveBufs& wb, uint32_t j, const ShadowReq& sh, ui
     wb.sh_c[j] = make_float4(sh.contrib.x, sh.contrib.y, sh.contrib.z, 0.f);
 }
 
+// unoccluded light-sample segment i: add its beta * C to its path
+PT_DEV void shadow_add(const WaveBufs& wb, uint32_t i) {
+    const uint32_t path = f2u(wb.sh_o[i].w);
+    float4 c4 = wb.sh_c[i];
+    float4 l4 = wb.L[path];
+    wb.L[path] = make_float4(l4.x + c4.x, l4.y + c4.y, l4.z + c4.z, 0.f);
+}
+
 // light-sample segment i: add beta * C to its path when unoccluded
 template <int LDS>
 PT_DEV void shadow_item(const SceneView& sc, const WaveBufs& wb, uint32_t i, TravStack<LDS>& st) {
     float4 o4 = wb.sh_o[i], d4 = wb.sh_d[i];
     Ray ray = make_ray(xyz(o4), xyz(d4));
-    if (!any_hit<LDS>(sc, ray, kShadowTmax, st)) {
-        const uint32_t path = f2u(o4.w);
-        float4 c4 = wb.sh_c[i];
-        float4 l4 = wb.L[path];
-        wb.L[path] = make_float4(l4.x + c4.x, l4.y + c4.y, l4.z + c4.z, 0.f);
-    }
+    if (!any_hit<LDS>(sc, ray, kShadowTmax, st)) shadow_add(wb, i);
 }
 
 // per-pixel mean over its spp paths, summed in sample order

@@ -25,12 +25,25 @@ def build():
     os.replace(LIB + ".tmp", LIB)
 
 
+def _stale():
+    """True when the emulator library is missing or older than a source."""
+    if not os.path.exists(LIB):
+        return True
+    t = os.path.getmtime(LIB)
+    dirs = [HERE, os.path.join(ROOT, "paper_2605_27323_amd", "csrc"), os.path.join(ROOT, "include")]
+    for d in dirs:
+        for f in os.listdir(d):
+            if f.endswith((".h", ".hip", ".cpp")) and os.path.getmtime(os.path.join(d, f)) > t:
+                return True
+    return False
+
+
 def lib():
     global _L
     if _L is None:
         from paper_2605_27323_amd import ptmi
         ptmi.lib()  # torch's HIP runtime first
-        if not os.path.exists(LIB):
+        if _stale():
             build()
         L = C.CDLL(LIB)
         L.emu_render_mega.restype = C.c_int32

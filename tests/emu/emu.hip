@@ -42,15 +42,7 @@ struct HostStack {
     uint2 l[kL];
     std::vector<uint2> gbl;
     TravStack<kL> st;
-    explicit HostStack(int gcap) : gbl(std::max(gcap, 1)) {
-        st.lds = l;
-        st.lstride = 1;
-        st.gbl = gbl.data();
-        st.gstride = 1;
-        st.gcap = gcap;
-        st.sp = 0;
-        st.overflow = false;
-    }
+    explicit HostStack(int gcap) : gbl(std::max(gcap, 1)) { st = make_trav_stack<kL>(l, 1, gbl.data(), 1, gcap); }
 };
 
 }  // namespace
