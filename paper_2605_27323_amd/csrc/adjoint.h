@@ -37,6 +37,7 @@ PT_DEV void adjoint_path(const SceneView& sc, const CamView& cam, const PathPara
         const f3 beta = ps.beta;
         ShadowReq sh;
         VertexOut vo = shade_vertex(sc, pp, pix, sample, k, d, h, ps, sh);
+        add_radiance(ps, vo);
         if (vo.id == 0xFFFFFFFFu) break;  // escaped: the sky is not a parameter
         const uint32_t id = vo.id;
         if (vo.emitted) {

@@ -128,9 +128,8 @@ PT_DEV bool batch_shade_item(const BatchBufs& bb, int q, uint32_t i, VertexOut& 
     const uint32_t pix = local / (uint32_t)jd.pp.spp;
     const uint32_t s = local - pix * (uint32_t)jd.pp.spp;
     const uint32_t sample = jd.pp.frame * (uint32_t)jd.pp.spp + s;
-    const float4 l4 = bb.L[g];
     ps.beta = xyz(p4);
-    ps.L = xyz(l4);
+    ps.L = mk3(0.f, 0.f, 0.f);
     ps.p_prev = d4.w;
     ps.prev_smooth = (int)((m >> 16) & 1u);
     Hit h;
@@ -140,7 +139,11 @@ PT_DEV bool batch_shade_item(const BatchBufs& bb, int q, uint32_t i, VertexOut& 
     h.tri = f2u(h4.w);
     h.id = 0;
     vo = shade_vertex(jd.sc, jd.pp, pix, sample, (int)k, xyz(d4), h, ps, sh);
-    if (vo.emitted || h.tri >= (uint32_t)jd.sc.nt) bb.L[g] = make_float4(ps.L.x, ps.L.y, ps.L.z, 0.f);
+    if (vo.addL) {  // the radiance is read only where this vertex adds to it
+        ps.L = xyz(bb.L[g]);
+        add_radiance(ps, vo);
+        bb.L[g] = make_float4(ps.L.x, ps.L.y, ps.L.z, 0.f);
+    }
     meta = meta_pack(k + 1u, (uint32_t)ps.prev_smooth, job);
     // a path with a pending light sample finishes after the shadow stage;
     // its job counter is decremented there

@@ -349,6 +349,8 @@ BuildResult build_scene(const std::vector<float>& tri_v, const std::vector<int32
             }
             r.lights[j].tri = leaf_pos[ids[j]];
             r.lights[j].cdf = w;
+            r.lights[j].id = ids[j];
+            r.lights[j].pad = 0u;
         }
     }
     return r;

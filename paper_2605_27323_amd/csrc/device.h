@@ -734,14 +734,53 @@ struct VertexOut {
     bool emitted;       // emission term counted at this vertex
     float w_emit;       // its MIS weight
     Lobe scat;          // sampling weight = lobe(albedo) when cont
+    bool addL;          // radiance to add at this vertex (emission or sky) ...
+    f3 Ladd;            // ... this much: L becomes L + Ladd (see add_radiance)
 };
 
-PT_DEV uint32_t pick_light(const SceneView& sc, uint32_t w) {
+// apply a vertex's emission / sky term to the path radiance
+PT_DEV void add_radiance(PathState& ps, const VertexOut& vo) {
+    if (vo.addL) ps.L = mk3(ps.L.x + vo.Ladd.x, ps.L.y + vo.Ladd.y, ps.L.z + vo.Ladd.z);
+}
+
+// Light table staged in LDS by a kernel (CDF words, leaf-order triangle and
+// input indices of the n lights); n = 0: read the table from global memory.
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+#else
+typedef uint32_t lds_u32;
+#endif
+constexpr int kLdsLights = 1024;
+
+struct LightCache {
+    const lds_u32* cdf;
+    const lds_u32* tri;
+    const lds_u32* id;
+    int n;
+};
+
+PT_DEV LightCache no_light_cache() {
+    LightCache lc;
+    lc.cdf = lc.tri = lc.id = nullptr;
+    lc.n = 0;
+    return lc;
+}
+
+// first light whose CDF word is >= w (the last word is 2^32 - 1)
+PT_DEV uint32_t pick_light(const SceneView& sc, const LightCache& lc, uint32_t w) {
     int lo = 0, hi = sc.nl - 1;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (w <= sc.lights[mid].cdf) hi = mid;
-        else lo = mid + 1;
+    if (lc.n) {
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (w <= lc.cdf[mid]) hi = mid;
+            else lo = mid + 1;
+        }
+    } else {
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (w <= sc.lights[mid].cdf) hi = mid;
+            else lo = mid + 1;
+        }
     }
     return (uint32_t)lo;
 }
@@ -752,26 +791,57 @@ PT_DEV f3 load3(const float* __restrict__ p, uint32_t i) {
 
 // Shade vertex k of a path: add emission (MIS-weighted after a light-sampled
 // vertex), build the light-sample request, sample the continuation and
-// apply roulette.  ps.L receives the emission; the light-sample
+// apply roulette.  The emission (or sky) term is returned in out.Ladd for
+// the caller to add to the path radiance (add_radiance), so that the
+// radiance is needed only where it is updated; the light-sample
 // contribution beta * C is added by the caller once the segment is found
 // unoccluded (megakernel: at once; wavefront: in the shadow stage).
+//
+// Memory access order is arranged for latency: the hit triangle, the
+// random numbers, the light choice and the light triangle and emission do
+// not depend on each other, so all their loads are issued before any of
+// them is waited for; only the per-triangle albedo, emission and material
+// wait for the hit triangle.  Values fetched this way are used under the
+// same conditions as before, so the arithmetic is unchanged.
 PT_DEV VertexOut shade_vertex(const SceneView& sc, const PathParams& pp, uint32_t pixel, uint32_t sample, int k,
-                              f3 rd, const Hit& h, PathState& ps, ShadowReq& sh) {
+                              f3 rd, const Hit& h, PathState& ps, ShadowReq& sh,
+                              const LightCache& lc = no_light_cache()) {
     VertexOut out;
     out.cont = false;
     out.id = 0xFFFFFFFFu;
     out.emitted = false;
     out.w_emit = 0.0f;
+    out.addL = false;
     sh.valid = false;
     if (h.tri >= (uint32_t)sc.nt) {
-        ps.L = mk3(ps.L.x + ps.beta.x * sc.sky0, ps.L.y + ps.beta.y * sc.sky1, ps.L.z + ps.beta.z * sc.sky2);
+        out.addL = true;
+        out.Ladd = mk3(ps.beta.x * sc.sky0, ps.beta.y * sc.sky1, ps.beta.z * sc.sky2);
         return out;
     }
     const float4* tp = sc.tris + (size_t)h.tri * 3;
-    float4 ta = tp[0], tb = tp[1], tc = tp[2];
+    const float4 ta = tp[0], tb = tp[1], tc = tp[2];
+    const bool more = k != pp.D + 1;
+    Rng8 rn;
+    float4 la, lb4, lc4;
+    f3 Le_l;
+    const bool nee = more && pp.nee && sc.nl > 0;
+    if (more) rn = philox8(pp.seed, pixel, sample, (uint32_t)k, pp.job);
+    if (nee) {
+        const uint32_t j = pick_light(sc, lc, rn.w[0]);
+        const uint32_t lt = lc.n ? lc.tri[j] : sc.lights[j].tri;
+        const uint32_t lid = lc.n ? lc.id[j] : sc.lights[j].id;
+        const float4* lp = sc.tris + (size_t)lt * 3;
+        la = lp[0];
+        lb4 = lp[1];
+        lc4 = lp[2];
+        Le_l = load3(sc.emission, lid);
+    }
     f3 v0 = xyz(ta), v1 = xyz(tb), v2 = xyz(tc);
     uint32_t id = f2u(ta.w);
     uint32_t minfo = f2u(tb.w);
+    const f3 Le = load3(sc.emission, id);
+    const f3 alb = load3(sc.albedo, id);
+    const float4 mat = sc.mats[minfo & ~kLightFlag];
     out.id = id;
     f3 e1 = sub3(v1, v0), e2 = sub3(v2, v0);
     f3 x = mk3((v0.x + h.b1 * e1.x) + h.b2 * e2.x, (v0.y + h.b1 * e1.y) + h.b2 * e2.y,
@@ -785,17 +855,14 @@ PT_DEV VertexOut shade_vertex(const SceneView& sc, const PathParams& pp, uint32_
             float pl = (h.t * h.t) / (sc.area_total * cos_e);
             w = (ps.p_prev * ps.p_prev) / (ps.p_prev * ps.p_prev + pl * pl);
         }
-        f3 Le = load3(sc.emission, id);
-        ps.L = mk3(ps.L.x + ps.beta.x * (w * Le.x), ps.L.y + ps.beta.y * (w * Le.y), ps.L.z + ps.beta.z * (w * Le.z));
+        out.addL = true;
+        out.Ladd = mk3(ps.beta.x * (w * Le.x), ps.beta.y * (w * Le.y), ps.beta.z * (w * Le.z));
         out.emitted = true;
         out.w_emit = w;
     }
-    if (k == pp.D + 1) return out;
-    Rng8 rn = philox8(pp.seed, pixel, sample, (uint32_t)k, pp.job);
-    float4 mat = sc.mats[minfo & ~kLightFlag];
+    if (!more) return out;
     int type = (int)mat.x;
     float rough = mat.y, ior = mat.z;
-    f3 alb = load3(sc.albedo, id);
     bool entering = true;
     f3 n;
     if (type == PT_DIELECTRIC) {
@@ -806,13 +873,9 @@ PT_DEV VertexOut shade_vertex(const SceneView& sc, const PathParams& pp, uint32_
     }
     Frame fr = make_frame(n);
     f3 wo_l = to_local(fr, wo);
-    if (pp.nee && sc.nl > 0 && type != PT_DIELECTRIC) {
-        uint32_t j = pick_light(sc, rn.w[0]);
-        uint32_t lt = sc.lights[j].tri;
-        const float4* lp = sc.tris + (size_t)lt * 3;
-        float4 la = lp[0], lb4 = lp[1], lc = lp[2];
-        f3 y = tri_point(xyz(la), xyz(lb4), xyz(lc), unif(rn.w[1]), unif(rn.w[2]));
-        f3 ny = tri_normal(xyz(la), xyz(lb4), xyz(lc));
+    if (nee && type != PT_DIELECTRIC) {
+        f3 y = tri_point(xyz(la), xyz(lb4), xyz(lc4), unif(rn.w[1]), unif(rn.w[2]));
+        f3 ny = tri_normal(xyz(la), xyz(lb4), xyz(lc4));
         f3 dv = sub3(y, x);
         float d2 = dot3(dv, dv);
         if (d2 > 0.0f) {
@@ -829,8 +892,7 @@ PT_DEV VertexOut shade_vertex(const SceneView& sc, const PathParams& pp, uint32_
                     float wmis = (pl * pl) / (pl * pl + pb * pb);
                     float G = (cos_x * wmis) / pl;
                     uint32_t lid = f2u(la.w);
-                    f3 Le = load3(sc.emission, lid);
-                    sh.C = mk3((f.x * Le.x) * G, (f.y * Le.y) * G, (f.z * Le.z) * G);
+                    sh.C = mk3((f.x * Le_l.x) * G, (f.y * Le_l.y) * G, (f.z * Le_l.z) * G);
                     sh.contrib = mk3(ps.beta.x * sh.C.x, ps.beta.y * sh.C.y, ps.beta.z * sh.C.z);
                     sh.o = offset_point(x, dot3(ng, wl) > 0.0f ? ng : neg3(ng));
                     f3 sy = offset_point(y, ny);
@@ -874,7 +936,7 @@ PT_DEV VertexOut shade_vertex(const SceneView& sc, const PathParams& pp, uint32_
 // light-sample segment at once; counts extension and shadow rays.
 template <int LDS>
 PT_DEV f3 trace_path(const SceneView& sc, const CamView& cam, const PathParams& pp, uint32_t pix, uint32_t sample,
-                     TravStack<LDS>& st, uint32_t& n_ext, uint32_t& n_sh) {
+                     TravStack<LDS>& st, uint32_t& n_ext, uint32_t& n_sh, const LightCache& lc = no_light_cache()) {
     Rng8 r0 = philox8(pp.seed, pix, sample, 0u, pp.job);
     f3 o, d;
     camera_ray(cam, (int)(pix % (uint32_t)cam.W), (int)(pix / (uint32_t)cam.W), unif(r0.w[0]), unif(r0.w[1]), o, d);
@@ -888,7 +950,8 @@ PT_DEV f3 trace_path(const SceneView& sc, const CamView& cam, const PathParams& 
         Hit h = closest_hit<LDS>(sc, ray, INFINITY, st);
         ++n_ext;
         ShadowReq sh;
-        VertexOut vo = shade_vertex(sc, pp, pix, sample, k, d, h, ps, sh);
+        VertexOut vo = shade_vertex(sc, pp, pix, sample, k, d, h, ps, sh, lc);
+        add_radiance(ps, vo);
         if (sh.valid) {
             ++n_sh;
             Ray sr = make_ray(sh.o, sh.d);

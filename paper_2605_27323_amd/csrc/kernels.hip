@@ -33,19 +33,43 @@ __device__ __forceinline__ TravStack<LDS> make_stack(uint32_t* smem, uint2* ovf,
                                 (int)nlanes, gcap);
 }
 
+// Stage the light table (CDF words, leaf-order and input triangle indices)
+// in the block's LDS so that the light choice is a binary search in LDS.
+// Every thread of the block must call this (it synchronises the block).
+__device__ __forceinline__ LightCache stage_lights(const SceneView& sc, uint32_t* buf) {
+    if (sc.nl <= 0 || sc.nl > kLdsLights) return no_light_cache();
+    for (int j = threadIdx.x; j < sc.nl; j += blockDim.x) {
+        const LightEntry e = sc.lights[j];
+        buf[j] = e.cdf;
+        buf[kLdsLights + j] = e.tri;
+        buf[2 * kLdsLights + j] = e.id;
+    }
+    __syncthreads();
+    LightCache lc;
+    lc.cdf = (const lds_u32*)buf;
+    lc.tri = (const lds_u32*)(buf + kLdsLights);
+    lc.id = (const lds_u32*)(buf + 2 * kLdsLights);
+    lc.n = sc.nl;
+    return lc;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // megakernel
 // ---------------------------------------------------------------------------
+// four waves per SIMD instead of the three the register count would give:
+// a few spilled registers cost less than the lost latency hiding
 template <int LDS>
-__global__ void __launch_bounds__(256) k_mega(SceneView sc, CamView cam, PathParams pp, float* __restrict__ img,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_mega(SceneView sc, CamView cam, PathParams pp, float* __restrict__ img,
                                               float* __restrict__ acc, uint2* __restrict__ ovf, int gcap,
                                               uint32_t* __restrict__ stats) {
     extern __shared__ __align__(8) uint32_t smem[];
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
     TravStack<LDS> st = make_stack<LDS>(smem, ovf, gcap, gtid, nlanes);
+    __shared__ uint32_t light_buf[3 * kLdsLights];
+    const LightCache lc = stage_lights(sc, light_buf);
     const uint32_t npix = (uint32_t)cam.W * (uint32_t)cam.H;
     // uniform trip count per wave so that the ray counters can use shuffles
     const uint32_t wave0 = gtid & ~63u;
@@ -56,7 +80,7 @@ __global__ void __launch_bounds__(256) k_mega(SceneView sc, CamView cam, PathPar
             f3 sum = mk3(0.f, 0.f, 0.f);
             for (int s = 0; s < pp.spp; ++s) {
                 const uint32_t sample = pp.frame * (uint32_t)pp.spp + (uint32_t)s;
-                f3 L = trace_path<LDS>(sc, cam, pp, pix, sample, st, n_ext, n_sh);
+                f3 L = trace_path<LDS>(sc, cam, pp, pix, sample, st, n_ext, n_sh, lc);
                 sum = s == 0 ? L : add3(sum, L);
             }
             const float fs = (float)pp.spp;
@@ -89,8 +113,10 @@ template <int LDS>
 __global__ void __launch_bounds__(256) k_shade_tail(SceneView sc, PathParams pp, WaveBufs wb, int b, int sorted,
                                                     uint32_t tail, uint2* __restrict__ ovf, int gcap) {
     const uint32_t count = wb.counts[b];
-    if (!(count < tail)) return;
+    if (!(count < tail) || count == 0u) return;
     extern __shared__ __align__(8) uint32_t smem[];
+    __shared__ uint32_t light_buf[3 * kLdsLights];
+    const LightCache lc = stage_lights(sc, light_buf);
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t* perm = (sorted && wb.hist[2 * kSortBins]) ? wb.perm : nullptr;
@@ -100,8 +126,8 @@ __global__ void __launch_bounds__(256) k_shade_tail(SceneView sc, PathParams pp,
         VertexOut vo;
         ShadowReq sh;
         PathState ps;
-        const uint32_t path = shade_item(sc, pp, wb, b, i, vo, sh, ps, perm);
-        finish_path<LDS>(sc, pp, wb, path, b + 1, vo, sh, ps, st, n_ext, n_sh);
+        const uint32_t path = shade_item(sc, pp, wb, b, i, vo, sh, ps, perm, lc, true);
+        finish_path<LDS>(sc, pp, wb, path, b + 1, vo, sh, ps, st, n_ext, n_sh, lc);
     }
     // every lane of the wave is here: reduce the ray counts across it
     for (int off = 32; off > 0; off >>= 1) {
@@ -186,6 +212,9 @@ __global__ void __launch_bounds__(256) k_shade(SceneView sc, PathParams pp, Wave
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t count = wb.counts[b];
     if (compact && count < tail) return;  // k_shade_tail finishes this queue
+    if (count == 0u) return;
+    __shared__ uint32_t light_buf[3 * kLdsLights];
+    const LightCache lc = stage_lights(sc, light_buf);
     const uint32_t* perm = (sorted && wb.hist[2 * kSortBins]) ? wb.perm : nullptr;
     const int nxt = (b & 1) ^ 1;
     uint32_t* next_count = &wb.counts[b + 1];
@@ -200,7 +229,7 @@ __global__ void __launch_bounds__(256) k_shade(SceneView sc, PathParams pp, Wave
         vo.cont = false;
         sh.valid = false;
         uint32_t path = kDeadPath;
-        if (i < count) path = shade_item(sc, pp, wb, b, i, vo, sh, ps, perm);
+        if (i < count) path = shade_item(sc, pp, wb, b, i, vo, sh, ps, perm, lc);
         if (compact) {
             const uint64_t mk = __ballot(vo.cont);
             if (mk) {

@@ -29,10 +29,13 @@ constexpr int64_t kMaxTris = int64_t(kLeafFirstMask) + 1;
 // (v1, material index | light flag bit 31), (v2, 0).
 constexpr uint32_t kLightFlag = 0x80000000u;
 
-// Light table entry: leaf-order triangle index and the u32 CDF word.
+// Light table entry, 16 bytes: leaf-order triangle index, the u32 CDF word,
+// the input triangle index (which addresses the emission array), zero.
 struct LightEntry {
     uint32_t tri;
     uint32_t cdf;
+    uint32_t id;
+    uint32_t pad;
 };
 
 struct SceneView {

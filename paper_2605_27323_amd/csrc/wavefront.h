@@ -61,23 +61,31 @@ PT_DEV uint32_t material_key(const SceneView& sc, const float4& h4) {
 
 // shade queue slot i of bounce b (vertex k = b + 1); returns the path id
 // (kDeadPath for a dead slot); vo / sh / ps describe what to enqueue.  With
-// a material sort the slot's data is read from slot perm[i].
+// a material sort the slot's data is read from slot perm[i].  The path
+// radiance L[path] is read only where this vertex adds to it, and updated
+// in place; with for_tail it is always read into ps.L (plus this vertex's
+// term) for finish_path, which stores it at the path's end.
 PT_DEV uint32_t shade_item(const SceneView& sc, const PathParams& pp, const WaveBufs& wb, int b, uint32_t i,
-                           VertexOut& vo, ShadowReq& sh, PathState& ps, const uint32_t* __restrict__ perm = nullptr) {
+                           VertexOut& vo, ShadowReq& sh, PathState& ps, const uint32_t* __restrict__ perm = nullptr,
+                           const LightCache& lc = no_light_cache(), bool for_tail = false) {
     if (perm) i = perm[i];
     const int cur = b & 1;
-    float4 o4 = wb.ray_o[cur][i];
+    // all four records at once (a dead slot's stale records are not used);
+    // the empty asm consumes them before the dead-slot test so that the
+    // compiler cannot sink three of the loads behind it
+    const float4 o4 = wb.ray_o[cur][i], d4 = wb.ray_d[cur][i], p4 = wb.pst[cur][i], h4 = wb.hit[i];
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm volatile("" ::"v"(d4.x), "v"(p4.x), "v"(h4.w));
+#endif
     const uint32_t path = f2u(o4.w);
     vo.cont = false;
     sh.valid = false;
     if (path == kDeadPath) return path;
-    float4 d4 = wb.ray_d[cur][i], p4 = wb.pst[cur][i], h4 = wb.hit[i];
     const uint32_t pix = path / (uint32_t)pp.spp;
     const uint32_t s = path - pix * (uint32_t)pp.spp;
     const uint32_t sample = pp.frame * (uint32_t)pp.spp + s;
-    float4 l4 = wb.L[path];
     ps.beta = xyz(p4);
-    ps.L = xyz(l4);
+    ps.L = mk3(0.f, 0.f, 0.f);
     ps.p_prev = d4.w;
     ps.prev_smooth = (int)f2u(p4.w);
     Hit h;
@@ -86,8 +94,15 @@ PT_DEV uint32_t shade_item(const SceneView& sc, const PathParams& pp, const Wave
     h.b2 = h4.z;
     h.tri = f2u(h4.w);
     h.id = 0;
-    vo = shade_vertex(sc, pp, pix, sample, b + 1, xyz(d4), h, ps, sh);
-    if (vo.emitted || h.tri >= (uint32_t)sc.nt) wb.L[path] = make_float4(ps.L.x, ps.L.y, ps.L.z, 0.f);
+    vo = shade_vertex(sc, pp, pix, sample, b + 1, xyz(d4), h, ps, sh, lc);
+    if (for_tail) {
+        ps.L = xyz(wb.L[path]);
+        add_radiance(ps, vo);
+    } else if (vo.addL) {
+        ps.L = xyz(wb.L[path]);
+        add_radiance(ps, vo);
+        wb.L[path] = make_float4(ps.L.x, ps.L.y, ps.L.z, 0.f);
+    }
     return path;
 }
 
@@ -99,7 +114,7 @@ PT_DEV uint32_t shade_item(const SceneView& sc, const PathParams& pp, const Wave
 template <int LDS>
 PT_DEV void finish_path(const SceneView& sc, const PathParams& pp, const WaveBufs& wb, uint32_t path, int k,
                         VertexOut vo, ShadowReq sh, PathState& ps, TravStack<LDS>& st, uint32_t& n_ext,
-                        uint32_t& n_sh) {
+                        uint32_t& n_sh, const LightCache& lc = no_light_cache()) {
     const uint32_t pix = path / (uint32_t)pp.spp;
     const uint32_t s = path - pix * (uint32_t)pp.spp;
     const uint32_t sample = pp.frame * (uint32_t)pp.spp + s;
@@ -116,7 +131,8 @@ PT_DEV void finish_path(const SceneView& sc, const PathParams& pp, const WaveBuf
         const f3 d = vo.d;
         Ray ray = make_ray(vo.o, d);
         Hit h = closest_hit<LDS>(sc, ray, INFINITY, st);
-        vo = shade_vertex(sc, pp, pix, sample, k, d, h, ps, sh);
+        vo = shade_vertex(sc, pp, pix, sample, k, d, h, ps, sh, lc);
+        add_radiance(ps, vo);
     }
     wb.L[path] = make_float4(ps.L.x, ps.L.y, ps.L.z, 0.f);
 }

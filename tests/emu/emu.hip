@@ -131,7 +131,8 @@ int32_t emu_render_wave(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32
             VertexOut vo;
             ShadowReq sh;
             PathState ps;
-            uint32_t path = shade_item(sc, pp, wb, b, i, vo, sh, ps, sort ? perm.data() : nullptr);
+            uint32_t path = shade_item(sc, pp, wb, b, i, vo, sh, ps, sort ? perm.data() : nullptr, no_light_cache(),
+                                       finish);
             if (path != kDeadPath) ++ne;
             if (finish) {
                 uint32_t te = 0, ts = 0;

@@ -170,6 +170,7 @@ def test_light_cdf_matches_oracle():
     ids = tris[:, 3].view(np.uint32)
     light_ids = ids[lights[:, 0]]
     assert (np.diff(light_ids.astype(np.int64)) > 0).all()  # input order
+    assert np.array_equal(lights[:, 2], light_ids) and not lights[:, 3].any()
     rng = np.random.default_rng(0)
     words = np.concatenate([rng.integers(0, 2**32, 5000, dtype=np.uint64),
                             lights[:, 1].astype(np.uint64), (lights[:-1, 1].astype(np.uint64) + 1)])
