@@ -71,12 +71,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     __shared__ uint32_t light_buf[3 * kLdsLights];
     const LightCache lc = stage_lights(sc, light_buf);
     const uint32_t npix = (uint32_t)cam.W * (uint32_t)cam.H;
-    // uniform trip count per wave so that the ray counters can use shuffles
-    const uint32_t wave0 = gtid & ~63u;
-    for (uint32_t base = wave0; base < npix; base += nlanes) {
-        const uint32_t pix = base + (gtid & 63u);
-        uint32_t n_ext = 0, n_sh = 0;
-        if (pix < npix) {
+    uint32_t n_ext = 0, n_sh = 0;
+    for (uint32_t pix = gtid; pix < npix; pix += nlanes) {
+        {
             f3 sum = mk3(0.f, 0.f, 0.f);
             for (int s = 0; s < pp.spp; ++s) {
                 const uint32_t sample = pp.frame * (uint32_t)pp.spp + (uint32_t)s;
@@ -86,15 +83,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
             const float fs = (float)pp.spp;
             store_pixel(img, acc, pix, mk3(sum.x / fs, sum.y / fs, sum.z / fs), pp.frame);
         }
-        uint32_t e = n_ext, sh = n_sh;
-        for (int off = 32; off > 0; off >>= 1) {
-            e += __shfl_xor(e, off);
-            sh += __shfl_xor(sh, off);
-        }
-        if ((gtid & 63u) == 0) {
-            atomicAdd(&stats[0], e);
-            atomicAdd(&stats[1], sh);
-        }
+    }
+    // ray counts: one atomic per wave for the whole kernel
+    uint32_t e = n_ext, sh = n_sh;
+    for (int off = 32; off > 0; off >>= 1) {
+        e += __shfl_xor(e, off);
+        sh += __shfl_xor(sh, off);
+    }
+    if ((gtid & 63u) == 0 && (e | sh)) {
+        atomicAdd(&stats[0], e);
+        atomicAdd(&stats[1], sh);
     }
     if (st.overflow) atomicOr(&stats[2], 1u);
 }
@@ -220,9 +218,17 @@ __global__ void __launch_bounds__(256) k_shade(SceneView sc, PathParams pp, Wave
     uint32_t* next_count = &wb.counts[b + 1];
     uint32_t* sh_count = &wb.counts[wb.sh_base + b];
     if (!compact && gtid == 0 && count) atomicMax(next_count, count);
-    // wave-uniform trip count: every lane takes part in the ballots
-    for (uint32_t base = gtid & ~63u; base < count; base += nlanes) {
-        const uint32_t i = base + (gtid & 63u);
+    // Queue slots are reserved once per block and trip, not once per wave:
+    // concurrent atomics on one counter are serialised by the memory
+    // system, and the shade stage issues two of them for every 64 paths
+    // otherwise.  Block-uniform trip count (the block synchronises); the
+    // per-wave counts are double-buffered by trip parity.
+    __shared__ uint32_t s_cnt[2][2][4];
+    __shared__ uint32_t s_base[2][2];
+    const uint32_t w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int par = 0;
+    for (uint32_t bbase = blockIdx.x * blockDim.x; bbase < count; bbase += nlanes, par ^= 1) {
+        const uint32_t i = bbase + threadIdx.x;
         VertexOut vo;
         ShadowReq sh;
         PathState ps;
@@ -230,22 +236,32 @@ __global__ void __launch_bounds__(256) k_shade(SceneView sc, PathParams pp, Wave
         sh.valid = false;
         uint32_t path = kDeadPath;
         if (i < count) path = shade_item(sc, pp, wb, b, i, vo, sh, ps, perm, lc);
+        const uint64_t mk = compact ? __ballot(vo.cont) : 0ull;
+        const uint64_t ms = __ballot(sh.valid);
+        if (lane_id() == 0) {
+            s_cnt[par][0][w] = (uint32_t)__popcll(mk);
+            s_cnt[par][1][w] = (uint32_t)__popcll(ms);
+        }
+        __syncthreads();
+        if (threadIdx.x < 2) {
+            uint32_t tot = 0;
+            for (uint32_t k = 0; k < nw; ++k) tot += s_cnt[par][threadIdx.x][k];
+            s_base[par][threadIdx.x] = tot ? atomicAdd(threadIdx.x == 0 ? next_count : sh_count, tot) : 0u;
+        }
+        __syncthreads();
+        uint32_t off_c = s_base[par][0], off_s = s_base[par][1];
+        for (uint32_t k = 0; k < w; ++k) {
+            off_c += s_cnt[par][0][k];
+            off_s += s_cnt[par][1][k];
+        }
         if (compact) {
-            const uint64_t mk = __ballot(vo.cont);
-            if (mk) {
-                const uint32_t j = wave_reserve(next_count, mk);
-                if (vo.cont) write_continuation(wb, nxt, j, vo, ps, path);
-            }
+            if (vo.cont) write_continuation(wb, nxt, off_c + rank_in(mk), vo, ps, path);
         } else if (i < count) {
             // no compaction: slots stay in place, finished paths marked dead
             if (vo.cont) write_continuation(wb, nxt, i, vo, ps, path);
             else write_dead(wb, nxt, i);
         }
-        const uint64_t ms = __ballot(sh.valid);
-        if (ms) {
-            const uint32_t j = wave_reserve(sh_count, ms);
-            if (sh.valid) write_shadow(wb, j, sh, path);
-        }
+        if (sh.valid) write_shadow(wb, off_s + rank_in(ms), sh, path);
     }
 }
 
