@@ -165,6 +165,14 @@ PT_DEV void batch_write_shadow(const BatchBufs& bb, uint32_t j, const ShadowReq&
     bb.sh_c[j] = make_float4(sh.contrib.x, sh.contrib.y, sh.contrib.z, 0.f);
 }
 
+// unoccluded shadow record i: add its beta * C to its path
+PT_DEV void batch_shadow_add(const BatchBufs& bb, uint32_t i) {
+    const uint32_t g = f2u(bb.sh_o[i].w);
+    const float4 c4 = bb.sh_c[i];
+    const float4 l4 = bb.L[g];
+    bb.L[g] = make_float4(l4.x + c4.x, l4.y + c4.y, l4.z + c4.z, 0.f);
+}
+
 // shadow record i: returns true if it ends its path (caller decrements the
 // job counter) and sets job
 template <int LDS>
@@ -173,12 +181,7 @@ PT_DEV bool batch_shadow_item(const BatchBufs& bb, uint32_t i, TravStack<LDS>& s
     const uint32_t tag = f2u(d4.w);
     job = tag & 0x7FFFFFFFu;
     Ray ray = make_ray(xyz(o4), xyz(d4));
-    if (!any_hit<LDS>(bb.jobs[job].sc, ray, kShadowTmax, st)) {
-        const uint32_t g = f2u(o4.w);
-        const float4 c4 = bb.sh_c[i];
-        const float4 l4 = bb.L[g];
-        bb.L[g] = make_float4(l4.x + c4.x, l4.y + c4.y, l4.z + c4.z, 0.f);
-    }
+    if (!any_hit<LDS>(bb.jobs[job].sc, ray, kShadowTmax, st)) batch_shadow_add(bb, i);
     return (tag >> 31) != 0u;
 }
 

@@ -3,21 +3,11 @@
 // The host captures a fixed number of iterations into a hipGraph and replays
 // it until the device control block reports that every path has finished.
 #include "batch.h"
+#include "wave.h"
 
 namespace ptmi {
 
 namespace {
-
-__device__ __forceinline__ uint32_t lane_id_b() {
-    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
-}
-
-__device__ __forceinline__ uint32_t reserve_b(uint32_t* ctr, uint64_t m) {
-    uint32_t base = 0;
-    if (lane_id_b() == 0) base = atomicAdd(ctr, (uint32_t)__popcll(m));
-    base = __builtin_amdgcn_readfirstlane(base);
-    return base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
 
 template <int LDS>
 __device__ __forceinline__ TravStack<LDS> stack_b(uint32_t* smem, uint2* ovf, int gcap) {
@@ -35,7 +25,7 @@ __device__ __forceinline__ void jobs_finished(const BatchBufs& bb, bool fin, uin
         const int leader = __ffsll((unsigned long long)m) - 1;
         const uint32_t j0 = __shfl(job, leader);
         const uint64_t same = __ballot(fin && job == j0);
-        if ((int)lane_id_b() == leader) {
+        if ((int)lane_id() == leader) {
             const uint32_t n = (uint32_t)__popcll(same);
             if (atomicSub(&bb.remaining[j0], n) == n) bb.done_ts[j0] = wall_clock64();
         }
@@ -74,22 +64,59 @@ __global__ void __launch_bounds__(256) k_batch_regen(BatchBufs bb, int q) {
         batch_regen_item(bb, q, i);
 }
 
+// persistent traversal over the pool (see k_extend): each wave owns a chunk
+// of the queue and refills finished lanes from it; a lane's scene is its
+// path's job's scene
 template <int LDS>
-__global__ void __launch_bounds__(256) k_batch_extend(BatchBufs bb, int q, uint2* __restrict__ ovf, int gcap) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
+k_batch_extend(BatchBufs bb, int q, uint2* __restrict__ ovf, int gcap) {
     extern __shared__ __align__(8) uint32_t smem[];
     TravStack<LDS> st = stack_b<LDS>(smem, ovf, gcap);
-    const uint32_t count = bb.ctl->count;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
-        batch_extend_item<LDS>(bb, q, i, st);
+    uint32_t next, end;
+    wave_chunk(bb.ctl->count, next, end);
+    bool live = false;
+    uint32_t item = 0, ref = 0;
+    SceneView sc{};
+    Ray ray;
+    Hit h;
+    while (true) {
+        const uint64_t idle = __ballot(!live);
+        const uint32_t nidle = (uint32_t)__popcll(idle);
+        if (next < end && (nidle >= kRefill || nidle == 64u)) {
+            if (!live) {
+                const uint32_t i = next + rank_in(idle);
+                if (i < end) {
+                    const float4 o4 = bb.ray_o[q][i], d4 = bb.ray_d[q][i];
+                    sc = bb.jobs[f2u(bb.pst[q][i].w) >> 24].sc;
+                    ray = make_ray(xyz(o4), xyz(d4));
+                    closest_begin<LDS>(INFINITY, h, ref, st);
+                    item = i;
+                    live = true;
+                }
+            }
+            next = min(next + nidle, end);
+        }
+        if (__ballot(live) == 0ull) {
+            if (next < end) continue;
+            break;
+        }
+        if (live && !closest_step<LDS>(sc, ray, INFINITY, h, ref, st)) {
+            bb.hit[item] = make_float4(h.t, h.b1, h.b2, u2f(h.tri));
+            live = false;
+        }
+    }
     if (st.overflow) atomicOr(&bb.ctl->err, 1u);
 }
 
+// slots of the next queue and of the shadow queue reserved once per block
+// and trip (see k_shade)
 __global__ void __launch_bounds__(256) k_batch_shade(BatchBufs bb, int q) {
     const uint32_t nlanes = gridDim.x * blockDim.x;
-    const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t count = bb.ctl->count;
-    for (uint32_t base = gtid & ~63u; base < count; base += nlanes) {
-        const uint32_t i = base + (gtid & 63u);
+    __shared__ BlockReserve br;
+    int par = 0;
+    for (uint32_t bbase = blockIdx.x * blockDim.x; bbase < count; bbase += nlanes, par ^= 1) {
+        const uint32_t i = bbase + threadIdx.x;
         VertexOut vo;
         ShadowReq sh;
         PathState ps;
@@ -99,33 +126,59 @@ __global__ void __launch_bounds__(256) k_batch_shade(BatchBufs bb, int q) {
         bool finished = false;
         if (i < count) finished = batch_shade_item(bb, q, i, vo, sh, ps, g, meta);
         jobs_finished(bb, finished, meta >> 24);
-        const uint64_t mk = __ballot(vo.cont);
-        if (mk) {
-            const uint32_t j = reserve_b(&bb.ctl->live[q ^ 1], mk);
-            if (vo.cont) batch_write_continuation(bb, q ^ 1, j, vo, ps, g, meta);
-        }
-        const uint64_t ms = __ballot(sh.valid);
-        if (ms) {
-            const uint32_t j = reserve_b(&bb.ctl->shadow, ms);
-            if (sh.valid) batch_write_shadow(bb, j, sh, g, meta >> 24, !vo.cont);
-        }
+        const uint64_t mk = __ballot(vo.cont), ms = __ballot(sh.valid);
+        uint32_t jc, js;
+        block_reserve2(br, par, &bb.ctl->live[q ^ 1], mk, &bb.ctl->shadow, ms, jc, js);
+        if (vo.cont) batch_write_continuation(bb, q ^ 1, jc, vo, ps, g, meta);
+        if (sh.valid) batch_write_shadow(bb, js, sh, g, meta >> 24, !vo.cont);
     }
 }
 
+// persistent any-hit over the shadow records; the job counters are updated
+// every trip for the lanes whose record ended its path
 template <int LDS>
-__global__ void __launch_bounds__(256) k_batch_shadow(BatchBufs bb, uint2* __restrict__ ovf, int gcap) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
+k_batch_shadow(BatchBufs bb, uint2* __restrict__ ovf, int gcap) {
     extern __shared__ __align__(8) uint32_t smem[];
     TravStack<LDS> st = stack_b<LDS>(smem, ovf, gcap);
-    const uint32_t count = bb.ctl->shadow;
-    const uint32_t nlanes = gridDim.x * blockDim.x;
-    const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
-    // wave-uniform trip count so that the job counters can be aggregated
-    for (uint32_t base = gtid & ~63u; base < count; base += nlanes) {
-        const uint32_t i = base + (gtid & 63u);
-        uint32_t job = 0;
+    uint32_t next, end;
+    wave_chunk(bb.ctl->shadow, next, end);
+    bool live = false;
+    uint32_t item = 0, ref = 0, tag = 0;
+    SceneView sc{};
+    Ray ray;
+    while (true) {
+        const uint64_t idle = __ballot(!live);
+        const uint32_t nidle = (uint32_t)__popcll(idle);
+        if (next < end && (nidle >= kRefill || nidle == 64u)) {
+            if (!live) {
+                const uint32_t i = next + rank_in(idle);
+                if (i < end) {
+                    const float4 o4 = bb.sh_o[i], d4 = bb.sh_d[i];
+                    tag = f2u(d4.w);
+                    sc = bb.jobs[tag & 0x7FFFFFFFu].sc;
+                    ray = make_ray(xyz(o4), xyz(d4));
+                    any_begin<LDS>(ref, st);
+                    item = i;
+                    live = true;
+                }
+            }
+            next = min(next + nidle, end);
+        }
+        if (__ballot(live) == 0ull) {
+            if (next < end) continue;
+            break;
+        }
         bool fin = false;
-        if (i < count) fin = batch_shadow_item<LDS>(bb, i, st, job);
-        jobs_finished(bb, fin, job);
+        if (live) {
+            bool occluded = false;
+            if (!any_step<LDS>(sc, ray, kShadowTmax, ref, st, occluded)) {
+                live = false;
+                if (!occluded) batch_shadow_add(bb, item);
+                fin = (tag >> 31) != 0u;
+            }
+        }
+        jobs_finished(bb, fin, tag & 0x7FFFFFFFu);
     }
     if (st.overflow) atomicOr(&bb.ctl->err, 1u);
 }

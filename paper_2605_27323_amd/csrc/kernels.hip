@@ -3,28 +3,11 @@
 // 3.1: raygen, extend, shade, shadow, accumulate over structure-of-arrays
 // path state, live paths compacted into a queue after every bounce).
 #include "wavefront.h"
+#include "wave.h"
 
 namespace ptmi {
 
 namespace {
-
-__device__ __forceinline__ uint32_t lane_id() {
-    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
-}
-
-// position of this lane among the set lanes of a 64-bit ballot below it
-__device__ __forceinline__ uint32_t rank_in(uint64_t m) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
-
-// one atomic per wave reserves room for the wave's set lanes; every set
-// lane gets base + its rank among them
-__device__ __forceinline__ uint32_t wave_reserve(uint32_t* ctr, uint64_t m) {
-    uint32_t base = 0;
-    if (lane_id() == 0) base = atomicAdd(ctr, (uint32_t)__popcll(m));
-    base = __builtin_amdgcn_readfirstlane(base);
-    return base + rank_in(m);
-}
 
 template <int LDS>
 __device__ __forceinline__ TravStack<LDS> make_stack(uint32_t* smem, uint2* ovf, int gcap, uint32_t gtid,
@@ -151,13 +134,6 @@ __global__ void __launch_bounds__(256) k_raygen(CamView cam, PathParams pp, Wave
 // lanes idle until the slowest ray of the wave is done.  Lanes are refilled
 // when at least `refill` of them are idle (or all are); the chunk cursor is
 // wave-uniform, so no atomics are needed.
-__device__ __forceinline__ void wave_chunk(uint32_t count, uint32_t& next, uint32_t& end) {
-    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const uint32_t chunk = (uint32_t)(((uint64_t)count + nwaves - 1) / nwaves);
-    next = (uint32_t)min((uint64_t)wave * chunk, (uint64_t)count);
-    end = (uint32_t)min((uint64_t)next + chunk, (uint64_t)count);
-}
 
 template <int LDS>
 __global__ void __launch_bounds__(256) k_extend(SceneView sc, WaveBufs wb, int b, uint2* __restrict__ ovf, int gcap,
@@ -223,9 +199,7 @@ __global__ void __launch_bounds__(256) k_shade(SceneView sc, PathParams pp, Wave
     // system, and the shade stage issues two of them for every 64 paths
     // otherwise.  Block-uniform trip count (the block synchronises); the
     // per-wave counts are double-buffered by trip parity.
-    __shared__ uint32_t s_cnt[2][2][4];
-    __shared__ uint32_t s_base[2][2];
-    const uint32_t w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __shared__ BlockReserve br;
     int par = 0;
     for (uint32_t bbase = blockIdx.x * blockDim.x; bbase < count; bbase += nlanes, par ^= 1) {
         const uint32_t i = bbase + threadIdx.x;
@@ -238,30 +212,16 @@ __global__ void __launch_bounds__(256) k_shade(SceneView sc, PathParams pp, Wave
         if (i < count) path = shade_item(sc, pp, wb, b, i, vo, sh, ps, perm, lc);
         const uint64_t mk = compact ? __ballot(vo.cont) : 0ull;
         const uint64_t ms = __ballot(sh.valid);
-        if (lane_id() == 0) {
-            s_cnt[par][0][w] = (uint32_t)__popcll(mk);
-            s_cnt[par][1][w] = (uint32_t)__popcll(ms);
-        }
-        __syncthreads();
-        if (threadIdx.x < 2) {
-            uint32_t tot = 0;
-            for (uint32_t k = 0; k < nw; ++k) tot += s_cnt[par][threadIdx.x][k];
-            s_base[par][threadIdx.x] = tot ? atomicAdd(threadIdx.x == 0 ? next_count : sh_count, tot) : 0u;
-        }
-        __syncthreads();
-        uint32_t off_c = s_base[par][0], off_s = s_base[par][1];
-        for (uint32_t k = 0; k < w; ++k) {
-            off_c += s_cnt[par][0][k];
-            off_s += s_cnt[par][1][k];
-        }
+        uint32_t jc, js;
+        block_reserve2(br, par, next_count, mk, sh_count, ms, jc, js);
         if (compact) {
-            if (vo.cont) write_continuation(wb, nxt, off_c + rank_in(mk), vo, ps, path);
+            if (vo.cont) write_continuation(wb, nxt, jc, vo, ps, path);
         } else if (i < count) {
             // no compaction: slots stay in place, finished paths marked dead
             if (vo.cont) write_continuation(wb, nxt, i, vo, ps, path);
             else write_dead(wb, nxt, i);
         }
-        if (sh.valid) write_shadow(wb, off_s + rank_in(ms), sh, path);
+        if (sh.valid) write_shadow(wb, js, sh, path);
     }
 }
 
