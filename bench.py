@@ -19,6 +19,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+# algorithmic flops of one BVH4 node visit (four slab tests of 26 flops:
+# 6 subtractions, 6 multiplications, 12 min/max, slack multiply, compare)
+# and of one watertight triangle test (51 flops on its full path)
+FLOPS_PER_NODE = 104
+FLOPS_PER_TRI = 51
 # autotuner result on MI355X for the 1M-triangle 1080p workload
 FIXED_PARAMS = {"wave": {"block": 256, "grid_mult": 8, "stack_lds": 8, "tail_threshold": 1 << 18},
                 "mega": {"block": 256, "grid_mult": 16, "stack_lds": 8}}
@@ -38,7 +44,7 @@ def measured_traffic(kernel):
         return None
     prof = json.load(open(path))
     h = hashlib.sha256()
-    for f in ["device.h", "wavefront.h", "kernels.hip", "kernels.h", "ptmi_internal.h"]:
+    for f in ["device.h", "wavefront.h", "wave.h", "kernels.hip", "kernels.h", "ptmi_internal.h"]:
         h.update(open(os.path.join(ROOT, "paper_2605_27323_amd", "csrc", f), "rb").read())
     if h.hexdigest()[:16] != prof["source_hash"]:
         return None
@@ -159,7 +165,7 @@ def main():
 
     # per-stage times with HIP events on the render stream, over the same
     # number of frames, plus ray counts, work items and algorithmic bytes
-    stage_ms, launches, items, nbytes = {}, {}, {}, {}
+    stage_ms, launches, items, nbytes, nodes, tris = {}, {}, {}, {}, {}, {}
     rays = [0, 0]
     for i in range(args.steps):
         run("wave", 1, args.warmup + i, flags=ptmi.FLAG_PROFILE)
@@ -170,14 +176,22 @@ def main():
         for k, v in st["items"].items():
             items[k] = items.get(k, 0) + v
             nbytes[k] = nbytes.get(k, 0.0) + st["bytes"][k]
+        for k, v in st["node_visits"].items():
+            nodes[k] = nodes.get(k, 0) + v
+        for k, v in st["tri_tests"].items():
+            tris[k] = tris.get(k, 0) + v
         rays[0] += st["extension_rays"]
         rays[1] += st["shadow_rays"]
     frame_stage_ms = {k: v / args.steps for k, v in stage_ms.items()}
     log("wavefront stage ms/frame: " + ", ".join(f"{k} {v:.3f}" for k, v in frame_stage_ms.items()))
     ext_rays_per_frame = rays[0] / args.steps
     sh_rays_per_frame = rays[1] / args.steps
-    # roofline of the stage kernel with the largest share of the frame: its
-    # algorithmic path-state bytes per launch over its mean launch time
+    # roofline of the stage kernel with the largest share of the frame.
+    # Traversal kernels (extend, shadow, tail) are bound by vector ALU issue:
+    # achieved = algorithmic flops per launch (FLOPS_PER_NODE per BVH node
+    # visit, FLOPS_PER_TRI per triangle test, counted on the device) over the
+    # mean launch time, against the fp32 vector peak.  The streaming stages
+    # use their algorithmic path-state bytes against the HBM peak.
     dom = max(stage_ms, key=stage_ms.get)
     lds = tuned["wave"].get("stack_lds", 16)
     kname = {"extend": f"ptmi::k_extend<{lds}>", "shade": "ptmi::k_shade", "shadow": f"ptmi::k_shadow<{lds}>",
@@ -185,13 +199,22 @@ def main():
              "sort": "ptmi::k_sort_*"}[dom]
     dom_avg_ms = stage_ms[dom] / launches[dom]
     per_launch_bytes = nbytes.get(dom, 0.0) / launches[dom]
-    achieved = per_launch_bytes / (dom_avg_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname),
-                "avg_launch_ms": dom_avg_ms, "bytes_per_launch": per_launch_bytes,
-                "launches_per_frame": launches[dom] / args.steps,
-                "items_per_frame": items.get(dom, 0) / args.steps,
-                "stage_share": stage_ms[dom] / sum(stage_ms.values())}
+    state_gbs = per_launch_bytes / (dom_avg_ms * 1e-3) / 1e9
+    common = {"kernel": kname, "traffic": measured_traffic(kname), "avg_launch_ms": dom_avg_ms,
+              "launches_per_frame": launches[dom] / args.steps, "items_per_frame": items.get(dom, 0) / args.steps,
+              "stage_share": stage_ms[dom] / sum(stage_ms.values()), "state_bytes_per_launch": per_launch_bytes,
+              "state_gbs": state_gbs}
+    if dom in ("extend", "shadow", "tail"):
+        flops = FLOPS_PER_NODE * nodes.get(dom, 0) + FLOPS_PER_TRI * tris.get(dom, 0)
+        per_launch_flops = flops / launches[dom]
+        achieved = per_launch_flops / (dom_avg_ms * 1e-3) / 1e12
+        roofline = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "flops_per_launch": per_launch_flops,
+                    "node_visits_per_frame": nodes.get(dom, 0) / args.steps,
+                    "tri_tests_per_frame": tris.get(dom, 0) / args.steps, **common}
+    else:
+        roofline = {"bound": "hbm", "achieved": state_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": state_gbs / HBM_PEAK_GBS, "bytes_per_launch": per_launch_bytes, **common}
     state_bytes = sum(nbytes.values()) / args.steps
     state_floor = {"bytes_per_frame": state_bytes,
                    "frac_of_frame": (state_bytes / (res["wave"]["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS)
@@ -223,6 +246,8 @@ def main():
         "roofline": roofline,
         "state_traffic": state_floor,
         "stage_items_per_frame": {k: v / args.steps for k, v in items.items()},
+        "node_visits_per_frame": {k: v / args.steps for k, v in nodes.items()},
+        "tri_tests_per_frame": {k: v / args.steps for k, v in tris.items()},
         "paper_context": "paper reports ~16% (1.138x by its table) wavefront over megakernel on an RTX 3060 Ti "
                          "with RT cores, A Beautiful Game scene",
     }

@@ -218,6 +218,9 @@ pt_status pt_render_backward(pt_ctx* ctx, const pt_render_args* args, const floa
  *     writes of queue records, radiance and image buffers a stage must move;
  *     scene data excluded; conditional radiance updates of shade and shadow
  *     excluded, so a lower bound there); always filled.
+ *   node_visits[k], tri_tests[k]: BVH node visits (four child boxes tested
+ *     each) and ray/triangle tests of the traversal stages (extend, shadow,
+ *     hybrid tail, megakernel, adjoint); always filled.
  *   extension_rays, shadow_rays: rays traced by the frame (wavefront stages
  *   and hybrid tail, or megakernel, or adjoint replays).
  * PT_EOVERFLOW if a traversal stack overflowed during the frame. */
@@ -227,6 +230,7 @@ typedef struct {
     int64_t launches[PT_NSTAGES];
     int64_t stage_items[PT_NSTAGES];
     double stage_bytes[PT_NSTAGES];
+    int64_t node_visits[PT_NSTAGES], tri_tests[PT_NSTAGES];
     int64_t extension_rays, shadow_rays;
 } pt_frame_stats;
 pt_status pt_frame_stats_get(pt_ctx* ctx, pt_frame_stats* stats);

@@ -2,6 +2,7 @@
 // of the path from its random numbers, gradients added with hardware fp32
 // atomics (see adjoint.h for the algorithm).
 #include "adjoint.h"
+#include "wave.h"
 #include "kernels.h"
 
 namespace ptmi {
@@ -20,7 +21,7 @@ template <int LDS>
 __global__ void __launch_bounds__(256) k_adjoint(SceneView sc, CamView cam, PathParams pp,
                                                  const float* __restrict__ d_img, float* __restrict__ g_alb,
                                                  float* __restrict__ g_emi, uint2* __restrict__ ovf, int gcap,
-                                                 uint32_t* __restrict__ stats) {
+                                                 uint32_t* __restrict__ stats, unsigned long long* __restrict__ trav) {
     extern __shared__ __align__(8) uint32_t smem[];
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -35,16 +36,18 @@ __global__ void __launch_bounds__(256) k_adjoint(SceneView sc, CamView cam, Path
         const f3 delta = mk3(d_img[3 * (size_t)pix] / fs, d_img[3 * (size_t)pix + 1] / fs, d_img[3 * (size_t)pix + 2] / fs);
         adjoint_path<LDS>(sc, cam, pp, pix, pp.frame * (uint32_t)pp.spp + s, delta, g_alb, g_emi, st, acc);
     }
+    wave_add_u64(&trav[0], st.nodes);
+    wave_add_u64(&trav[1], st.tris);
     if (st.overflow) atomicOr(&stats[2], 1u);
 }
 
 hipError_t launch_adjoint(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const CamView& cam,
                           const PathParams& pp, const float* d_img, float* g_alb, float* g_emi, uint2* ovf, int gcap,
-                          uint32_t* stats) {
+                          uint32_t* stats, unsigned long long* trav) {
     size_t sm = (size_t)lds * 2 * sizeof(uint32_t) * block.x;
 #define X(N)                                                                                                  \
     if (lds == N) {                                                                                           \
-        hipLaunchKernelGGL(k_adjoint<N>, grid, block, sm, s, sc, cam, pp, d_img, g_alb, g_emi, ovf, gcap, stats); \
+        hipLaunchKernelGGL(k_adjoint<N>, grid, block, sm, s, sc, cam, pp, d_img, g_alb, g_emi, ovf, gcap, stats, trav); \
         return hipGetLastError();                                                                             \
     }
     X(8) X(16) X(24) X(32)

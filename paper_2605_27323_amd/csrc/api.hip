@@ -64,6 +64,7 @@ struct pt_ctx {
     // last frame: device counters and what is needed to turn them into
     // per-stage work items and bytes
     uint32_t* last_counts = nullptr;
+    unsigned long long* last_trav = nullptr;
     int last_ncounts = 0, last_D = 0, last_kind = 0;  // kind: 0 megakernel, 1 wavefront, 2 adjoint
     int last_spp = 1, last_nee = 1, last_compact = 1, last_sort = 0;
     uint32_t last_tail = 0, last_sort_threshold = 0;
@@ -105,9 +106,10 @@ pt_status launch_config(const pt_ctx* c, const pt_render_args* a, Launch& L) {
 }
 
 struct WsLayout {
-    size_t counts, ovf, wave[11], sort_key, perm, hist, total;
+    size_t counts, trav, ovf, wave[11], sort_key, perm, hist, total;
     int ncounts;
 };
+constexpr int kTravWords = 16;  // 8 u64 traversal work counters
 
 // workspace: counters | traversal overflow stack | wavefront state
 WsLayout layout(const pt_ctx* c, const pt_render_args* a, const Launch& L) {
@@ -117,6 +119,8 @@ WsLayout layout(const pt_ctx* c, const pt_render_args* a, const Launch& L) {
     size_t off = 0;
     w.counts = off;
     off = align_up(off + sizeof(uint32_t) * w.ncounts);
+    w.trav = off;
+    off = align_up(off + sizeof(uint32_t) * kTravWords);
     w.ovf = off;
     off = align_up(off + sizeof(uint2) * (size_t)L.gcap * L.nlanes);
     for (int i = 0; i < 11; ++i) {
@@ -423,17 +427,19 @@ pt_status pt_render_frame(pt_ctx* c, const pt_render_args* a, float* img, float*
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     char* base = static_cast<char*>(ws);
     uint32_t* counts = reinterpret_cast<uint32_t*>(base + w.counts);
+    unsigned long long* trav = reinterpret_cast<unsigned long long*>(base + w.trav);
     uint2* ovf = reinterpret_cast<uint2*>(base + w.ovf);
     PathParams pp{a->spp, a->max_depth, a->nee ? 1 : 0, a->rr_start, a->seed, a->frame, a->job};
     const bool prof = (a->flags & PT_FLAG_PROFILE) != 0;
     c->timers.clear();
     c->event_next = 0;
     dim3 grid(L.grid), block(L.block);
+    PT_HIP(launch_init_counts(s, reinterpret_cast<uint32_t*>(trav), kTravWords, 0u), "init work counters");
     const uint32_t npaths = (uint32_t)c->cam.W * c->cam.H * a->spp;
     if (a->mode == PT_MODE_MEGA) {
         PT_HIP(launch_init_counts(s, counts, w.ncounts, 0u), "init counters");
         // counters: [0] extension rays, [1] shadow rays, [2] overflow flag
-        PT_HIP(timed(c, prof, 5, s, [&] { return launch_mega(L.lds, grid, block, s, c->view, c->cam, pp, img, acc, ovf, L.gcap, counts); }), "megakernel");
+        PT_HIP(timed(c, prof, 5, s, [&] { return launch_mega(L.lds, grid, block, s, c->view, c->cam, pp, img, acc, ovf, L.gcap, counts, trav); }), "megakernel");
     } else {
         WaveBufs wb{};
         for (int q = 0; q < 2; ++q) {
@@ -447,6 +453,7 @@ pt_status pt_render_frame(pt_ctx* c, const pt_render_args* a, float* img, float*
         wb.sh_c = reinterpret_cast<float4*>(base + w.wave[9]);
         wb.L = reinterpret_cast<float4*>(base + w.wave[10]);
         wb.counts = counts;
+        wb.trav = trav;
         wb.sh_base = a->max_depth + 2;
         wb.tail_slot = 2 * a->max_depth + 3;
         wb.err_slot = w.ncounts - 1;
@@ -476,6 +483,7 @@ pt_status pt_render_frame(pt_ctx* c, const pt_render_args* a, float* img, float*
         PT_HIP(timed(c, prof, 4, s, [&] { return launch_accumulate(grid, block, s, c->cam, pp, wb.L, img, acc); }), "accumulate");
     }
     remember_frame(c, a, counts, w.ncounts, a->mode == PT_MODE_WAVE ? 1 : 0, acc != nullptr);
+    c->last_trav = trav;
     return PT_OK;
 }
 
@@ -498,18 +506,21 @@ pt_status pt_render_backward(pt_ctx* c, const pt_render_args* a, const float* d_
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     char* base = static_cast<char*>(ws);
     uint32_t* counts = reinterpret_cast<uint32_t*>(base + w.counts);
+    unsigned long long* trav = reinterpret_cast<unsigned long long*>(base + w.trav);
     uint2* ovf = reinterpret_cast<uint2*>(base + w.ovf);
     PathParams pp{a->spp, a->max_depth, a->nee ? 1 : 0, -1, a->seed, a->frame, a->job};
     const bool prof = (a->flags & PT_FLAG_PROFILE) != 0;
     c->timers.clear();
     c->event_next = 0;
     PT_HIP(launch_init_counts(s, counts, w.ncounts, 0u), "init counters");
+    PT_HIP(launch_init_counts(s, reinterpret_cast<uint32_t*>(trav), kTravWords, 0u), "init work counters");
     PT_HIP(timed(c, prof, 7, s, [&] {
                return launch_adjoint(L.lds, dim3(L.grid), dim3(L.block), s, c->view, c->cam, pp, d_image, d_albedo,
-                                     d_emission, ovf, L.gcap, counts);
+                                     d_emission, ovf, L.gcap, counts, trav);
            }),
            "adjoint");
     remember_frame(c, a, counts, w.ncounts, 2, false);
+    c->last_trav = trav;
     return PT_OK;
 }
 
@@ -527,6 +538,8 @@ pt_status pt_frame_stats_get(pt_ctx* c, pt_frame_stats* out) {
     }
     std::vector<uint32_t> h(c->last_ncounts);
     PT_HIP(hipMemcpy(h.data(), c->last_counts, h.size() * sizeof(uint32_t), hipMemcpyDeviceToHost), "read counters");
+    unsigned long long tv[kTravWords / 2];
+    PT_HIP(hipMemcpy(tv, c->last_trav, sizeof tv, hipMemcpyDeviceToHost), "read work counters");
     const uint64_t npix = c->last_npix, npaths = npix * (uint64_t)c->last_spp;
     const double img_bytes = 12.0 + (c->last_acc ? 24.0 : 0.0);  // image write (+ running average RMW)
     if (c->last_kind != 1) {
@@ -535,6 +548,8 @@ pt_status pt_frame_stats_get(pt_ctx* c, pt_frame_stats* out) {
         out->shadow_rays = h[1];
         const int k = c->last_kind == 0 ? 5 : 7;
         out->stage_items[k] = (int64_t)npaths;
+        out->node_visits[k] = (int64_t)tv[0];
+        out->tri_tests[k] = (int64_t)tv[1];
         // path state lives in registers: only the image (megakernel) or
         // the image adjoint (read once per pixel) touches memory
         out->stage_bytes[k] = (double)npix * (c->last_kind == 0 ? img_bytes : 12.0);
@@ -570,6 +585,12 @@ pt_status pt_frame_stats_get(pt_ctx* c, pt_frame_stats* out) {
     }
     out->extension_rays += h[2 * D + 3];
     out->shadow_rays += h[2 * D + 4];
+    out->node_visits[1] = (int64_t)tv[0];
+    out->tri_tests[1] = (int64_t)tv[1];
+    out->node_visits[3] = (int64_t)tv[2];
+    out->tri_tests[3] = (int64_t)tv[3];
+    out->node_visits[8] = (int64_t)tv[4];
+    out->tri_tests[8] = (int64_t)tv[5];
     out->stage_bytes[1] = 48.0 * (double)out->stage_items[1];
     out->stage_bytes[2] += 80.0 * (double)out->stage_items[2];
     out->stage_bytes[3] = 48.0 * (double)out->stage_items[3];

@@ -269,6 +269,7 @@ struct TravStack {
     int gcap;
     int sp;
     bool overflow;
+    uint32_t nodes, tris;  // node visits and triangle tests of this lane (work counters)
 
     PT_DEV void push(uint32_t ref, float t) {
         const uint2 e = make_uint2(ref, f2u(t));
@@ -311,6 +312,7 @@ PT_DEV TravStack<LDS> make_trav_stack(uint2* lds_lane, int lstride, uint2* gbl_l
     st.gcap = gcap;
     st.sp = 0;
     st.overflow = false;
+    st.nodes = st.tris = 0u;
     return st;
 }
 
@@ -373,6 +375,7 @@ template <int LDS>
 PT_DEV bool closest_step(const SceneView& sc, const Ray& r, float tmax, Hit& h, uint32_t& ref, TravStack<LDS>& st) {
     if (!(ref & kLeafBit)) {
         if (ref < (uint32_t)sc.n_nodes) {
+            ++st.nodes;
             float4 q[8];
             load_node(sc.nodes, ref, q);
             float tn[4];
@@ -400,6 +403,7 @@ PT_DEV bool closest_step(const SceneView& sc, const Ray& r, float tmax, Hit& h, 
         uint32_t first = ref & kLeafFirstMask;
         uint32_t cnt = ((ref >> kLeafCountShift) & 15u) + 1u;
         if (first + cnt <= (uint32_t)sc.nt) {
+            st.tris += cnt;
             for (uint32_t i = first; i < first + cnt; ++i) {
                 const float4* tp = sc.tris + (size_t)i * 3;
                 float4 a = tp[0], b = tp[1], c = tp[2];
@@ -449,6 +453,7 @@ PT_DEV bool any_step(const SceneView& sc, const Ray& r, float tmax, uint32_t& re
                      bool& occluded) {
     if (!(ref & kLeafBit)) {
         if (ref < (uint32_t)sc.n_nodes) {
+            ++st.nodes;
             float4 q[8];
             load_node(sc.nodes, ref, q);
             float tn[4];
@@ -472,6 +477,7 @@ PT_DEV bool any_step(const SceneView& sc, const Ray& r, float tmax, uint32_t& re
         uint32_t cnt = ((ref >> kLeafCountShift) & 15u) + 1u;
         if (first + cnt <= (uint32_t)sc.nt) {
             for (uint32_t i = first; i < first + cnt; ++i) {
+                ++st.tris;
                 const float4* tp = sc.tris + (size_t)i * 3;
                 float4 a = tp[0], b = tp[1], c = tp[2];
                 float t, b1, b2;

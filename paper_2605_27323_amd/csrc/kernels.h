@@ -27,6 +27,9 @@ struct WaveBufs {
     // [tail_slot + 1] extension and shadow rays traced by the hybrid tail,
     // [err_slot] traversal stack overflow flag
     uint32_t* counts;
+    // traversal work counters: node visits and triangle tests of the
+    // extend [0, 1], shadow [2, 3] and hybrid-tail [4, 5] kernels
+    unsigned long long* trav;
     int sh_base;
     int tail_slot;
     int err_slot;
@@ -42,8 +45,11 @@ constexpr int kSortBins = 64;
 // of its 64 lanes are idle
 constexpr uint32_t kRefill = 16;
 
+// stats: [0] extension rays, [1] shadow rays, [2] overflow flag; trav:
+// node visits, triangle tests
 hipError_t launch_mega(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const CamView& cam,
-                       const PathParams& pp, float* img, float* acc, uint2* ovf, int gcap, uint32_t* stats);
+                       const PathParams& pp, float* img, float* acc, uint2* ovf, int gcap, uint32_t* stats,
+                       unsigned long long* trav);
 hipError_t launch_init_counts(hipStream_t s, uint32_t* counts, int n, uint32_t first);
 hipError_t launch_raygen(dim3 grid, dim3 block, hipStream_t s, const CamView& cam, const PathParams& pp,
                          const WaveBufs& wb);
@@ -62,7 +68,7 @@ hipError_t launch_shadow(int lds, dim3 grid, dim3 block, hipStream_t s, const Sc
                          int b, uint2* ovf, int gcap);
 hipError_t launch_adjoint(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const CamView& cam,
                           const PathParams& pp, const float* d_img, float* g_alb, float* g_emi, uint2* ovf, int gcap,
-                          uint32_t* stats);
+                          uint32_t* stats, unsigned long long* trav);
 hipError_t launch_accumulate(dim3 grid, dim3 block, hipStream_t s, const CamView& cam, const PathParams& pp,
                              const float4* L, float* img, float* acc);
 

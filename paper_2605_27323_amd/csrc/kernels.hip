@@ -46,7 +46,7 @@ __device__ __forceinline__ LightCache stage_lights(const SceneView& sc, uint32_t
 template <int LDS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_mega(SceneView sc, CamView cam, PathParams pp, float* __restrict__ img,
                                               float* __restrict__ acc, uint2* __restrict__ ovf, int gcap,
-                                              uint32_t* __restrict__ stats) {
+                                              uint32_t* __restrict__ stats, unsigned long long* __restrict__ trav) {
     extern __shared__ __align__(8) uint32_t smem[];
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -77,6 +77,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         atomicAdd(&stats[0], e);
         atomicAdd(&stats[1], sh);
     }
+    wave_add_u64(&trav[0], st.nodes);
+    wave_add_u64(&trav[1], st.tris);
     if (st.overflow) atomicOr(&stats[2], 1u);
 }
 
@@ -119,6 +121,8 @@ __global__ void __launch_bounds__(256) k_shade_tail(SceneView sc, PathParams pp,
         atomicAdd(&wb.counts[wb.tail_slot], n_ext);
         atomicAdd(&wb.counts[wb.tail_slot + 1], n_sh);
     }
+    wave_add_u64(&wb.trav[4], st.nodes);
+    wave_add_u64(&wb.trav[5], st.tris);
     if (st.overflow) atomicOr(&wb.counts[wb.err_slot], 1u);
 }
 
@@ -177,6 +181,8 @@ __global__ void __launch_bounds__(256) k_extend(SceneView sc, WaveBufs wb, int b
             live = false;
         }
     }
+    wave_add_u64(&wb.trav[0], st.nodes);
+    wave_add_u64(&wb.trav[1], st.tris);
     if (st.overflow) atomicOr(&wb.counts[wb.err_slot], 1u);
 }
 
@@ -264,6 +270,8 @@ __global__ void __launch_bounds__(256) k_shadow(SceneView sc, WaveBufs wb, int b
             }
         }
     }
+    wave_add_u64(&wb.trav[2], st.nodes);
+    wave_add_u64(&wb.trav[3], st.tris);
     if (st.overflow) atomicOr(&wb.counts[wb.err_slot], 1u);
 }
 
@@ -347,10 +355,11 @@ __global__ void __launch_bounds__(256) k_accumulate(CamView cam, PathParams pp, 
 static size_t stack_lds_bytes(int lds, int block) { return (size_t)lds * 2 * sizeof(uint32_t) * block; }
 
 hipError_t launch_mega(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const CamView& cam,
-                       const PathParams& pp, float* img, float* acc, uint2* ovf, int gcap, uint32_t* stats) {
+                       const PathParams& pp, float* img, float* acc, uint2* ovf, int gcap, uint32_t* stats,
+                       unsigned long long* trav) {
     size_t sm = stack_lds_bytes(lds, block.x);
 #define X(N) \
-    if (lds == N) { hipLaunchKernelGGL(k_mega<N>, grid, block, sm, s, sc, cam, pp, img, acc, ovf, gcap, stats); return hipGetLastError(); }
+    if (lds == N) { hipLaunchKernelGGL(k_mega<N>, grid, block, sm, s, sc, cam, pp, img, acc, ovf, gcap, stats, trav); return hipGetLastError(); }
     PT_STACK_CASES(X)
 #undef X
     return hipErrorInvalidValue;

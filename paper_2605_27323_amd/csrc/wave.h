@@ -26,6 +26,13 @@ __device__ __forceinline__ uint32_t wave_reserve(uint32_t* ctr, uint64_t m) {
     return base + rank_in(m);
 }
 
+// Sum v over the 64 lanes of the wave (every lane calls this) and add the
+// sum to *dst with one atomic.
+__device__ __forceinline__ void wave_add_u64(unsigned long long* dst, uint32_t v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane_id() == 0 && v) atomicAdd(dst, (unsigned long long)v);
+}
+
 // The contiguous chunk [next, end) of a queue of `count` entries owned by
 // this wave in a persistent kernel (waves of the grid in launch order).
 __device__ __forceinline__ void wave_chunk(uint32_t count, uint32_t& next, uint32_t& end) {

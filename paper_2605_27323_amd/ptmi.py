@@ -67,6 +67,7 @@ NSTAGES = 9
 class FrameStats(C.Structure):
     _fields_ = [("stage_ms", C.c_double * NSTAGES), ("launches", C.c_int64 * NSTAGES),
                 ("stage_items", C.c_int64 * NSTAGES), ("stage_bytes", C.c_double * NSTAGES),
+                ("node_visits", C.c_int64 * NSTAGES), ("tri_tests", C.c_int64 * NSTAGES),
                 ("extension_rays", C.c_int64), ("shadow_rays", C.c_int64)]
 
 
@@ -277,6 +278,8 @@ class Renderer(Context):
                 "launches": {STAGES[k]: s.launches[k] for k in range(NSTAGES) if s.launches[k]},
                 "items": {STAGES[k]: s.stage_items[k] for k in range(NSTAGES) if s.stage_items[k]},
                 "bytes": {STAGES[k]: s.stage_bytes[k] for k in range(NSTAGES) if s.stage_items[k]},
+                "node_visits": {STAGES[k]: s.node_visits[k] for k in range(NSTAGES) if s.node_visits[k]},
+                "tri_tests": {STAGES[k]: s.tri_tests[k] for k in range(NSTAGES) if s.tri_tests[k]},
                 "extension_rays": s.extension_rays, "shadow_rays": s.shadow_rays}
 
     def sync(self):

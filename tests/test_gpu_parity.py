@@ -185,11 +185,17 @@ def test_progressive_accumulation_and_ray_counts():
     sw = R.stats()
     assert sm["extension_rays"] == sw["extension_rays"] > 0
     assert sm["shadow_rays"] == sw["shadow_rays"] > 0
+    # every ray is traversed identically in both schedules: same node visits
+    # and triangle tests in total
+    for key in ("node_visits", "tri_tests"):
+        assert sm[key]["mega"] == sw[key]["extend"] + sw[key]["shadow"] > 0
     # the hybrid tail traces the rest of the paths in place and counts them
     R.render(mode="wave", spp=2, max_depth=4, tail_threshold=400)
     st = R.stats()
     assert st["items"].get("tail", 0) > 0
     assert (st["extension_rays"], st["shadow_rays"]) == (sm["extension_rays"], sm["shadow_rays"])
+    for key in ("node_visits", "tri_tests"):
+        assert sum(st[key].values()) == sm[key]["mega"]
 
 
 def test_profile_stage_times():
