@@ -162,6 +162,20 @@ def main():
         dt = time.perf_counter() - t
         res[mode] = dict(seconds=dt, ms=dt * 1e3 / args.steps, value=W * H * SPP * args.steps / dt)
         log(f"{mode}: {res[mode]['ms']:.3f} ms/frame, {res[mode]['value'] / 1e6:.1f} M path-samples/s")
+    # the same frames with two in flight (pt_render_frames): one frame's
+    # last, short bounces overlap the next frame's first ones
+    inflight = {}
+    for mode in modes:
+        p = dict(tuned[mode])
+        R.render_frames(args.warmup, out=img, mode=mode, frame=0, **kw, **p)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        R.render_frames(args.steps, out=img, mode=mode, frame=args.warmup, **kw, **p)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        inflight[mode] = dict(ms_per_step=dt * 1e3 / args.steps, value=W * H * SPP * args.steps / dt)
+        log(f"{mode}, two frames in flight: {inflight[mode]['ms_per_step']:.3f} ms/frame, "
+            f"{inflight[mode]['value'] / 1e6:.1f} M path-samples/s")
 
     # per-stage times with HIP events on the render stream, over the same
     # number of frames, plus ray counts, work items and algorithmic bytes
@@ -176,12 +190,17 @@ def main():
         for k, v in st["items"].items():
             items[k] = items.get(k, 0) + v
             nbytes[k] = nbytes.get(k, 0.0) + st["bytes"][k]
+        rays[0] += st["extension_rays"]
+        rays[1] += st["shadow_rays"]
+    # the same frames again with the work-counting kernels (node visits and
+    # triangle tests; a separate, slower build, so not timed)
+    for i in range(args.steps):
+        run("wave", 1, args.warmup + i, flags=ptmi.FLAG_COUNT_WORK)
+        st = R.stats()
         for k, v in st["node_visits"].items():
             nodes[k] = nodes.get(k, 0) + v
         for k, v in st["tri_tests"].items():
             tris[k] = tris.get(k, 0) + v
-        rays[0] += st["extension_rays"]
-        rays[1] += st["shadow_rays"]
     frame_stage_ms = {k: v / args.steps for k, v in stage_ms.items()}
     log("wavefront stage ms/frame: " + ", ".join(f"{k} {v:.3f}" for k, v in frame_stage_ms.items()))
     ext_rays_per_frame = rays[0] / args.steps
@@ -239,6 +258,7 @@ def main():
                    "width": W, "height": H, "spp": SPP, "max_depth": DEPTH, "triangles": nt},
         "megakernel": ({"value": res["mega"]["value"], "ms_per_step": res["mega"]["ms"]} if "mega" in res else None),
         "wave_over_mega": (res["wave"]["value"] / res["mega"]["value"]) if len(res) == 2 else None,
+        "two_frames_in_flight": inflight,
         "rays_per_s": ((ext_rays_per_frame + sh_rays_per_frame) / (res["wave"]["ms"] * 1e-3)) if "wave" in res else None,
         "rays_per_frame": {"extension": ext_rays_per_frame, "shadow": sh_rays_per_frame},
         "stage_ms_per_frame": frame_stage_ms,

@@ -58,7 +58,8 @@ enum {
     PT_FLAG_PROFILE = 1,       /* time every stage launch with HIP events */
     PT_FLAG_NO_COMPACT = 2,    /* wavefront: no compaction, dispatch every path each bounce */
     PT_FLAG_SORT_MATERIAL = 4, /* wavefront: counting-sort each shade queue by material type */
-    PT_FLAG_COUNT_RAYS = 8     /* keep per-bounce queue counts readable via pt_frame_stats */
+    PT_FLAG_COUNT_WORK = 8     /* traversal kernels count BVH node visits and triangle tests
+                                  (pt_frame_stats); a separate kernel build, slower */
 };
 
 typedef struct pt_ctx pt_ctx;
@@ -195,6 +196,23 @@ pt_status pt_render_frame(pt_ctx* ctx, const pt_render_args* args, float* image_
                           float* accum_inout, void* workspace, uint64_t workspace_bytes,
                           void* stream);
 
+/* Progressive rendering with two frames in flight: frames args->frame, ...,
+ * args->frame + n_frames - 1, each exactly as pt_render_frame renders it.
+ * A frame's stages run on one of two internal streams of the context
+ * (default priority, created on first use) while the previous frame
+ * finishes on the other, so that the short last bounces of one frame
+ * overlap the first bounces of the next; the per-frame accumulation runs on
+ * `stream` in frame order.  Work enqueued on `stream` before the call
+ * precedes every frame; the call's results are complete when `stream`
+ * reaches its end.  image_out receives each frame's image in turn (the last
+ * one remains); accum_inout (may be NULL) is updated as by n_frames calls of
+ * pt_render_frame, bit for bit.  workspace: pt_frames_workspace_size bytes
+ * (two frame slots), 256-byte aligned.  PT_EINVAL with PT_FLAG_PROFILE.
+ * Calls that overlap on one context race. */
+pt_status pt_frames_workspace_size(pt_ctx* ctx, const pt_render_args* args, uint64_t* bytes);
+pt_status pt_render_frames(pt_ctx* ctx, const pt_render_args* args, int32_t n_frames, float* image_out,
+                           float* accum_inout, void* workspace, uint64_t workspace_bytes, void* stream);
+
 /* Path-replay adjoint of one frame: ACCUMULATES (+=) into d_albedo and
  * d_emission (float[nt*3] device, input triangle order) the gradient of
  * sum_p sum_c d_image[p][c] * I[p][c] for the fixed-sample estimator defined
@@ -220,7 +238,8 @@ pt_status pt_render_backward(pt_ctx* ctx, const pt_render_args* args, const floa
  *     excluded, so a lower bound there); always filled.
  *   node_visits[k], tri_tests[k]: BVH node visits (four child boxes tested
  *     each) and ray/triangle tests of the traversal stages (extend, shadow,
- *     hybrid tail, megakernel, adjoint); always filled.
+ *     hybrid tail, megakernel), filled when the frame ran with
+ *     PT_FLAG_COUNT_WORK (else 0).
  *   extension_rays, shadow_rays: rays traced by the frame (wavefront stages
  *   and hybrid tail, or megakernel, or adjoint replays).
  * PT_EOVERFLOW if a traversal stack overflowed during the frame. */

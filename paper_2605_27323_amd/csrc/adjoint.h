@@ -17,9 +17,9 @@
 
 namespace ptmi {
 
-template <int LDS, class Acc>
+template <int LDS, class Acc, bool COUNT = false>
 PT_DEV void adjoint_path(const SceneView& sc, const CamView& cam, const PathParams& pp, uint32_t pix, uint32_t sample,
-                         f3 delta, float* __restrict__ g_alb, float* __restrict__ g_emi, TravStack<LDS>& st,
+                         f3 delta, float* __restrict__ g_alb, float* __restrict__ g_emi, TravStack<LDS, COUNT>& st,
                          Acc& acc) {
     uint32_t ne = 0, ns = 0;
     const f3 Ltot = trace_path<LDS>(sc, cam, pp, pix, sample, st, ne, ns);

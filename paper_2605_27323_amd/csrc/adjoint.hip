@@ -36,8 +36,6 @@ __global__ void __launch_bounds__(256) k_adjoint(SceneView sc, CamView cam, Path
         const f3 delta = mk3(d_img[3 * (size_t)pix] / fs, d_img[3 * (size_t)pix + 1] / fs, d_img[3 * (size_t)pix + 2] / fs);
         adjoint_path<LDS>(sc, cam, pp, pix, pp.frame * (uint32_t)pp.spp + s, delta, g_alb, g_emi, st, acc);
     }
-    wave_add_u64(&trav[0], st.nodes);
-    wave_add_u64(&trav[1], st.tris);
     if (st.overflow) atomicOr(&stats[2], 1u);
 }
 

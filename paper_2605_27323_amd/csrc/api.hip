@@ -63,6 +63,11 @@ struct pt_ctx {
     size_t event_next = 0;
     // last frame: device counters and what is needed to turn them into
     // per-stage work items and bytes
+    // frames in flight (pt_render_frames): two internal streams and their
+    // events, created on first use
+    bool aux_ready = false;
+    hipStream_t aux[2] = {nullptr, nullptr};
+    hipEvent_t ev_entry = nullptr, ev_stage[2] = {nullptr, nullptr}, ev_acc[2] = {nullptr, nullptr};
     uint32_t* last_counts = nullptr;
     unsigned long long* last_trav = nullptr;
     int last_ncounts = 0, last_D = 0, last_kind = 0;  // kind: 0 megakernel, 1 wavefront, 2 adjoint
@@ -115,7 +120,9 @@ constexpr int kTravWords = 16;  // 8 u64 traversal work counters
 WsLayout layout(const pt_ctx* c, const pt_render_args* a, const Launch& L) {
     WsLayout w{};
     const size_t npaths = (size_t)c->cam.W * c->cam.H * a->spp;
-    w.ncounts = (a->max_depth + 2) + (a->max_depth + 1) + 4;
+    // [0, D+1] live paths per bounce, [D+2, 2D+2] shadow rays per bounce,
+    // [2D+3, 2D+4] rays traced by the hybrid tail, [2D+5] overflow flag
+    w.ncounts = 2 * a->max_depth + 6;
     size_t off = 0;
     w.counts = off;
     off = align_up(off + sizeof(uint32_t) * w.ncounts);
@@ -143,7 +150,8 @@ pt_status check_args(const pt_ctx* c, const pt_render_args* a) {
     if (c->device < 0) return fail(PT_ESTATE, "host-only context cannot render");
     if (!c->bound) return fail(PT_ESTATE, "scene not bound (pt_bind_scene)");
     if (!c->cam_set) return fail(PT_ESTATE, "camera not set (pt_set_camera)");
-    if (a->flags & ~(PT_FLAG_PROFILE | PT_FLAG_NO_COMPACT | PT_FLAG_SORT_MATERIAL)) return fail(PT_EINVAL, "unknown flag");
+    if (a->flags & ~(PT_FLAG_PROFILE | PT_FLAG_NO_COMPACT | PT_FLAG_SORT_MATERIAL | PT_FLAG_COUNT_WORK))
+        return fail(PT_EINVAL, "unknown flag");
     if (a->spp < 1 || a->spp > 65536) return fail(PT_EINVAL, "spp must be in [1, 65536]");
     if (a->max_depth < 0 || a->max_depth > 1000) return fail(PT_EINVAL, "max_depth must be in [0, 1000]");
     if (a->mode != PT_MODE_MEGA && a->mode != PT_MODE_WAVE) return fail(PT_EINVAL, "unknown mode");
@@ -188,6 +196,76 @@ void remember_frame(pt_ctx* c, const pt_render_args* a, uint32_t* counts, int nc
     c->last_npix = (uint64_t)c->cam.W * (uint64_t)c->cam.H;
     c->last_acc = acc;
     c->last_valid = true;
+}
+
+// bytes of one frame's workspace slot in pt_render_frames: the frame
+// layout plus the frame's image (the megakernel writes it there)
+size_t frame_slot_bytes(const pt_ctx* c, const WsLayout& w) {
+    return align_up(w.total + sizeof(float) * 3 * (size_t)c->cam.W * (size_t)c->cam.H);
+}
+
+// Enqueue one frame on stream s, except the wavefront's accumulate (its
+// radiance buffer is returned in *Lbuf): counters, then the megakernel
+// (writing img / acc) or raygen and the bounce stages.
+pt_status enqueue_stages(pt_ctx* c, const pt_render_args* a, const Launch& L, const WsLayout& w, char* base,
+                         hipStream_t s, float* img, float* acc, bool prof, const float4** Lbuf) {
+    uint32_t* counts = reinterpret_cast<uint32_t*>(base + w.counts);
+    unsigned long long* trav = reinterpret_cast<unsigned long long*>(base + w.trav);
+    uint2* ovf = reinterpret_cast<uint2*>(base + w.ovf);
+    PathParams pp{a->spp, a->max_depth, a->nee ? 1 : 0, a->rr_start, a->seed, a->frame, a->job};
+    dim3 grid(L.grid), block(L.block);
+    const bool count = (a->flags & PT_FLAG_COUNT_WORK) != 0;
+    PT_HIP(launch_init_counts(s, reinterpret_cast<uint32_t*>(trav), kTravWords, 0u), "init work counters");
+    const uint32_t npaths = (uint32_t)c->cam.W * c->cam.H * a->spp;
+    if (a->mode == PT_MODE_MEGA) {
+        PT_HIP(launch_init_counts(s, counts, w.ncounts, 0u), "init counters");
+        // counters: [0] extension rays, [1] shadow rays, [2] overflow flag
+        PT_HIP(timed(c, prof, 5, s, [&] { return launch_mega(L.lds, count, grid, block, s, c->view, c->cam, pp, img, acc, ovf, L.gcap, counts, trav); }), "megakernel");
+    } else {
+        WaveBufs wb{};
+        for (int q = 0; q < 2; ++q) {
+            wb.ray_o[q] = reinterpret_cast<float4*>(base + w.wave[0 + q]);
+            wb.ray_d[q] = reinterpret_cast<float4*>(base + w.wave[2 + q]);
+            wb.pst[q] = reinterpret_cast<float4*>(base + w.wave[4 + q]);
+        }
+        wb.hit = reinterpret_cast<float4*>(base + w.wave[6]);
+        wb.sh_o = reinterpret_cast<float4*>(base + w.wave[7]);
+        wb.sh_d = reinterpret_cast<float4*>(base + w.wave[8]);
+        wb.sh_c = reinterpret_cast<float4*>(base + w.wave[9]);
+        wb.L = reinterpret_cast<float4*>(base + w.wave[10]);
+        wb.counts = counts;
+        wb.trav = trav;
+        wb.sh_base = a->max_depth + 2;
+        wb.tail_slot = 2 * a->max_depth + 3;
+        wb.err_slot = w.ncounts - 1;
+        wb.sort_key = reinterpret_cast<uint32_t*>(base + w.sort_key);
+        wb.perm = reinterpret_cast<uint32_t*>(base + w.perm);
+        wb.hist = reinterpret_cast<uint32_t*>(base + w.hist);
+        const int compact = (a->flags & PT_FLAG_NO_COMPACT) ? 0 : 1;
+        const int sort = (a->flags & PT_FLAG_SORT_MATERIAL) ? 1 : 0;
+        if (sort && !compact) return fail(PT_EINVAL, "material sort needs compaction");
+        PT_HIP(launch_init_counts(s, counts, w.ncounts, npaths), "init counters");
+        if (sort) PT_HIP(launch_init_counts(s, wb.hist, 2 * kSortBins + 1, 0u), "init sort histogram");
+        PT_HIP(timed(c, prof, 0, s, [&] { return launch_raygen(grid, block, s, c->cam, pp, wb); }), "raygen");
+        for (int b = 0; b <= a->max_depth; ++b) {
+            PT_HIP(timed(c, prof, 1, s, [&] { return launch_extend(L.lds, count, grid, block, s, c->view, wb, b, ovf, L.gcap); }), "extend");
+            if (sort)
+                PT_HIP(timed(c, prof, 6, s, [&] { return launch_sort(grid, block, s, c->view, wb, b, a->sort_threshold); }), "sort");
+            PT_HIP(timed(c, prof, 2, s, [&] { return launch_shade(grid, block, s, c->view, pp, wb, b, compact, sort, a->tail_threshold); }), "shade");
+            if (compact && a->tail_threshold)
+                PT_HIP(timed(c, prof, 8, s, [&] {
+                           return launch_tail(L.lds, count, grid, block, s, c->view, pp, wb, b, sort, a->tail_threshold, ovf,
+                                              L.gcap);
+                       }),
+                       "hybrid tail");
+            if (b < a->max_depth && a->nee)
+                PT_HIP(timed(c, prof, 3, s, [&] { return launch_shadow(L.lds, count, grid, block, s, c->view, wb, b, ovf, L.gcap); }), "shadow");
+        }
+        *Lbuf = wb.L;
+    }
+    remember_frame(c, a, counts, w.ncounts, a->mode == PT_MODE_WAVE ? 1 : 0, acc != nullptr);
+    c->last_trav = trav;
+    return PT_OK;
 }
 
 SceneView make_view(const pt_ctx* c, const pt_scene_buffers* b) {
@@ -249,6 +327,14 @@ pt_status pt_destroy(pt_ctx* c) {
     if (c->device >= 0) {
         (void)hipSetDevice(c->device);
         for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+        if (c->aux_ready) {
+            for (int i = 0; i < 2; ++i) {
+                (void)hipStreamDestroy(c->aux[i]);
+                (void)hipEventDestroy(c->ev_stage[i]);
+                (void)hipEventDestroy(c->ev_acc[i]);
+            }
+            (void)hipEventDestroy(c->ev_entry);
+        }
     }
     delete c;
     return PT_OK;
@@ -425,65 +511,83 @@ pt_status pt_render_frame(pt_ctx* c, const pt_render_args* a, float* img, float*
     if (ws_bytes < w.total) return fail(PT_ENOMEM, "workspace too small (pt_workspace_size)");
     PT_HIP(hipSetDevice(c->device), "hipSetDevice");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    char* base = static_cast<char*>(ws);
-    uint32_t* counts = reinterpret_cast<uint32_t*>(base + w.counts);
-    unsigned long long* trav = reinterpret_cast<unsigned long long*>(base + w.trav);
-    uint2* ovf = reinterpret_cast<uint2*>(base + w.ovf);
-    PathParams pp{a->spp, a->max_depth, a->nee ? 1 : 0, a->rr_start, a->seed, a->frame, a->job};
     const bool prof = (a->flags & PT_FLAG_PROFILE) != 0;
     c->timers.clear();
     c->event_next = 0;
-    dim3 grid(L.grid), block(L.block);
-    PT_HIP(launch_init_counts(s, reinterpret_cast<uint32_t*>(trav), kTravWords, 0u), "init work counters");
-    const uint32_t npaths = (uint32_t)c->cam.W * c->cam.H * a->spp;
-    if (a->mode == PT_MODE_MEGA) {
-        PT_HIP(launch_init_counts(s, counts, w.ncounts, 0u), "init counters");
-        // counters: [0] extension rays, [1] shadow rays, [2] overflow flag
-        PT_HIP(timed(c, prof, 5, s, [&] { return launch_mega(L.lds, grid, block, s, c->view, c->cam, pp, img, acc, ovf, L.gcap, counts, trav); }), "megakernel");
-    } else {
-        WaveBufs wb{};
-        for (int q = 0; q < 2; ++q) {
-            wb.ray_o[q] = reinterpret_cast<float4*>(base + w.wave[0 + q]);
-            wb.ray_d[q] = reinterpret_cast<float4*>(base + w.wave[2 + q]);
-            wb.pst[q] = reinterpret_cast<float4*>(base + w.wave[4 + q]);
-        }
-        wb.hit = reinterpret_cast<float4*>(base + w.wave[6]);
-        wb.sh_o = reinterpret_cast<float4*>(base + w.wave[7]);
-        wb.sh_d = reinterpret_cast<float4*>(base + w.wave[8]);
-        wb.sh_c = reinterpret_cast<float4*>(base + w.wave[9]);
-        wb.L = reinterpret_cast<float4*>(base + w.wave[10]);
-        wb.counts = counts;
-        wb.trav = trav;
-        wb.sh_base = a->max_depth + 2;
-        wb.tail_slot = 2 * a->max_depth + 3;
-        wb.err_slot = w.ncounts - 1;
-        wb.sort_key = reinterpret_cast<uint32_t*>(base + w.sort_key);
-        wb.perm = reinterpret_cast<uint32_t*>(base + w.perm);
-        wb.hist = reinterpret_cast<uint32_t*>(base + w.hist);
-        const int compact = (a->flags & PT_FLAG_NO_COMPACT) ? 0 : 1;
-        const int sort = (a->flags & PT_FLAG_SORT_MATERIAL) ? 1 : 0;
-        if (sort && !compact) return fail(PT_EINVAL, "material sort needs compaction");
-        PT_HIP(launch_init_counts(s, counts, w.ncounts, npaths), "init counters");
-        if (sort) PT_HIP(launch_init_counts(s, wb.hist, 2 * kSortBins + 1, 0u), "init sort histogram");
-        PT_HIP(timed(c, prof, 0, s, [&] { return launch_raygen(grid, block, s, c->cam, pp, wb); }), "raygen");
-        for (int b = 0; b <= a->max_depth; ++b) {
-            PT_HIP(timed(c, prof, 1, s, [&] { return launch_extend(L.lds, grid, block, s, c->view, wb, b, ovf, L.gcap); }), "extend");
-            if (sort)
-                PT_HIP(timed(c, prof, 6, s, [&] { return launch_sort(grid, block, s, c->view, wb, b, a->sort_threshold); }), "sort");
-            PT_HIP(timed(c, prof, 2, s, [&] { return launch_shade(grid, block, s, c->view, pp, wb, b, compact, sort, a->tail_threshold); }), "shade");
-            if (compact && a->tail_threshold)
-                PT_HIP(timed(c, prof, 8, s, [&] {
-                           return launch_tail(L.lds, grid, block, s, c->view, pp, wb, b, sort, a->tail_threshold, ovf,
-                                              L.gcap);
-                       }),
-                       "hybrid tail");
-            if (b < a->max_depth && a->nee)
-                PT_HIP(timed(c, prof, 3, s, [&] { return launch_shadow(L.lds, grid, block, s, c->view, wb, b, ovf, L.gcap); }), "shadow");
-        }
-        PT_HIP(timed(c, prof, 4, s, [&] { return launch_accumulate(grid, block, s, c->cam, pp, wb.L, img, acc); }), "accumulate");
+    const float4* Lbuf = nullptr;
+    st = enqueue_stages(c, a, L, w, static_cast<char*>(ws), s, img, acc, prof, &Lbuf);
+    if (st) return st;
+    if (a->mode == PT_MODE_WAVE) {
+        PathParams pp{a->spp, a->max_depth, a->nee ? 1 : 0, a->rr_start, a->seed, a->frame, a->job};
+        PT_HIP(timed(c, prof, 4, s, [&] { return launch_accumulate(dim3(L.grid), dim3(L.block), s, c->cam, pp, Lbuf, img, acc); }), "accumulate");
     }
-    remember_frame(c, a, counts, w.ncounts, a->mode == PT_MODE_WAVE ? 1 : 0, acc != nullptr);
-    c->last_trav = trav;
+    return PT_OK;
+}
+
+pt_status pt_frames_workspace_size(pt_ctx* c, const pt_render_args* a, uint64_t* bytes) {
+    if (!c || !a || !bytes) return fail(PT_EINVAL, "null argument");
+    if (!c->built) return fail(PT_ESTATE, "BVH not built");
+    if (!c->cam_set) return fail(PT_ESTATE, "camera not set");
+    if (a->spp < 1 || a->max_depth < 0 || a->max_depth > 1000) return fail(PT_EINVAL, "bad spp or max_depth");
+    Launch L;
+    pt_status st = launch_config(c, a, L);
+    if (st) return st;
+    *bytes = 2 * frame_slot_bytes(c, layout(c, a, L));
+    return PT_OK;
+}
+
+pt_status pt_render_frames(pt_ctx* c, const pt_render_args* a, int32_t n_frames, float* img, float* acc, void* ws,
+                           uint64_t ws_bytes, void* stream) {
+    pt_status st = check_args(c, a);
+    if (st) return st;
+    if (n_frames < 1) return fail(PT_EINVAL, "n_frames must be >= 1");
+    if ((uint64_t)a->frame + (uint64_t)n_frames > 0xFFFFFFFFull) return fail(PT_EINVAL, "frame index overflows");
+    if (a->flags & PT_FLAG_PROFILE) return fail(PT_EINVAL, "PT_FLAG_PROFILE is per frame (pt_render_frame)");
+    if (!img) return fail(PT_EINVAL, "null image");
+    if (!ws) return fail(PT_EINVAL, "null workspace");
+    if ((reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return fail(PT_EINVAL, "workspace must be 256-byte aligned");
+    Launch L;
+    st = launch_config(c, a, L);
+    if (st) return st;
+    const WsLayout w = layout(c, a, L);
+    const size_t slot = frame_slot_bytes(c, w);
+    if (ws_bytes < 2 * slot) return fail(PT_ENOMEM, "workspace too small (pt_frames_workspace_size)");
+    PT_HIP(hipSetDevice(c->device), "hipSetDevice");
+    if (!c->aux_ready) {
+        for (int i = 0; i < 2; ++i) {
+            PT_HIP(hipStreamCreateWithFlags(&c->aux[i], hipStreamNonBlocking), "create stream");
+            PT_HIP(hipEventCreateWithFlags(&c->ev_stage[i], hipEventDisableTiming), "create event");
+            PT_HIP(hipEventCreateWithFlags(&c->ev_acc[i], hipEventDisableTiming), "create event");
+        }
+        PT_HIP(hipEventCreateWithFlags(&c->ev_entry, hipEventDisableTiming), "create event");
+        c->aux_ready = true;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    c->timers.clear();
+    c->event_next = 0;
+    // everything the caller enqueued before (scene, parameters, outputs)
+    // precedes both internal streams
+    PT_HIP(hipEventRecord(c->ev_entry, s), "record event");
+    for (int i = 0; i < 2; ++i) PT_HIP(hipStreamWaitEvent(c->aux[i], c->ev_entry, 0), "stream wait");
+    const uint32_t npix = (uint32_t)c->cam.W * (uint32_t)c->cam.H;
+    for (int32_t f = 0; f < n_frames; ++f) {
+        const int k = f & 1;
+        char* base = static_cast<char*>(ws) + k * slot;
+        float* frame_img = reinterpret_cast<float*>(base + w.total);
+        pt_render_args af = *a;
+        af.frame = a->frame + (uint32_t)f;
+        // the slot's previous frame must have been accumulated
+        PT_HIP(hipStreamWaitEvent(c->aux[k], c->ev_acc[k], 0), "stream wait");
+        const float4* Lbuf = nullptr;
+        st = enqueue_stages(c, &af, L, w, base, c->aux[k], frame_img, nullptr, false, &Lbuf);
+        if (st) return st;
+        PT_HIP(hipEventRecord(c->ev_stage[k], c->aux[k]), "record event");
+        PT_HIP(hipStreamWaitEvent(s, c->ev_stage[k], 0), "stream wait");
+        PathParams pp{af.spp, af.max_depth, af.nee ? 1 : 0, af.rr_start, af.seed, af.frame, af.job};
+        if (a->mode == PT_MODE_WAVE) PT_HIP(launch_accumulate(dim3(L.grid), dim3(L.block), s, c->cam, pp, Lbuf, img, acc), "accumulate");
+        else PT_HIP(launch_average(dim3(L.grid), dim3(L.block), s, frame_img, npix, af.frame, img, acc), "average");
+        PT_HIP(hipEventRecord(c->ev_acc[k], s), "record event");
+    }
     return PT_OK;
 }
 

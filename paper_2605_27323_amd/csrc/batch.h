@@ -104,8 +104,8 @@ PT_DEV void batch_regen_item(const BatchBufs& bb, int q, uint32_t i) {
     bb.L[g] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
-template <int LDS>
-PT_DEV void batch_extend_item(const BatchBufs& bb, int q, uint32_t i, TravStack<LDS>& st) {
+template <int LDS, bool COUNT = false>
+PT_DEV void batch_extend_item(const BatchBufs& bb, int q, uint32_t i, TravStack<LDS, COUNT>& st) {
     const float4 o4 = bb.ray_o[q][i], d4 = bb.ray_d[q][i];
     const uint32_t job = f2u(bb.pst[q][i].w) >> 24;
     const SceneView& sc = bb.jobs[job].sc;
@@ -175,8 +175,8 @@ PT_DEV void batch_shadow_add(const BatchBufs& bb, uint32_t i) {
 
 // shadow record i: returns true if it ends its path (caller decrements the
 // job counter) and sets job
-template <int LDS>
-PT_DEV bool batch_shadow_item(const BatchBufs& bb, uint32_t i, TravStack<LDS>& st, uint32_t& job) {
+template <int LDS, bool COUNT = false>
+PT_DEV bool batch_shadow_item(const BatchBufs& bb, uint32_t i, TravStack<LDS, COUNT>& st, uint32_t& job) {
     const float4 o4 = bb.sh_o[i], d4 = bb.sh_d[i];
     const uint32_t tag = f2u(d4.w);
     job = tag & 0x7FFFFFFFu;

@@ -260,7 +260,7 @@ typedef uint2 lds_uint2;
 inline uint32_t mul24(uint32_t a, uint32_t b) { return (a & 0xFFFFFFu) * (b & 0xFFFFFFu); }
 #endif
 
-template <int LDS>
+template <int LDS, bool COUNT = false>
 struct TravStack {
     lds_uint2* lds;  // (reference, entry distance bits), one 64-bit LDS access per push / pop
     uint2* gbl;
@@ -269,7 +269,7 @@ struct TravStack {
     int gcap;
     int sp;
     bool overflow;
-    uint32_t nodes, tris;  // node visits and triangle tests of this lane (work counters)
+    uint32_t nodes, tris;  // node visits and triangle tests of this lane (counted when COUNT)
 
     PT_DEV void push(uint32_t ref, float t) {
         const uint2 e = make_uint2(ref, f2u(t));
@@ -302,9 +302,9 @@ struct TravStack {
 
 // lds_lane: this lane's first LDS entry (entry k at lds_lane[k * lstride]);
 // gbl_lane: its first spill entry (entry LDS + k at gbl_lane[k * gstride])
-template <int LDS>
-PT_DEV TravStack<LDS> make_trav_stack(uint2* lds_lane, int lstride, uint2* gbl_lane, int gstride, int gcap) {
-    TravStack<LDS> st;
+template <int LDS, bool COUNT = false>
+PT_DEV TravStack<LDS, COUNT> make_trav_stack(uint2* lds_lane, int lstride, uint2* gbl_lane, int gstride, int gcap) {
+    TravStack<LDS, COUNT> st;
     st.lds = (lds_uint2*)lds_lane;
     st.lstride = lstride;
     st.gbl = gbl_lane;
@@ -357,8 +357,8 @@ PT_DEV void sort4(uint32_t ref[4], float t[4]) {
 // lane a new ray while the others are still traversing.  closest_hit runs
 // the steps to the end.
 
-template <int LDS>
-PT_DEV void closest_begin(float tmax, Hit& h, uint32_t& ref, TravStack<LDS>& st) {
+template <int LDS, bool COUNT = false>
+PT_DEV void closest_begin(float tmax, Hit& h, uint32_t& ref, TravStack<LDS, COUNT>& st) {
     h.t = tmax;
     h.b1 = 0.0f;
     h.b2 = 0.0f;
@@ -371,11 +371,11 @@ PT_DEV void closest_begin(float tmax, Hit& h, uint32_t& ref, TravStack<LDS>& st)
 // Visit `ref` (an inner node: push the farther hit children, move to the
 // nearest; a leaf: test its triangles), then pop the next entry that can
 // still hold a closer hit.  Returns false when the traversal is finished.
-template <int LDS>
-PT_DEV bool closest_step(const SceneView& sc, const Ray& r, float tmax, Hit& h, uint32_t& ref, TravStack<LDS>& st) {
+template <int LDS, bool COUNT = false>
+PT_DEV bool closest_step(const SceneView& sc, const Ray& r, float tmax, Hit& h, uint32_t& ref, TravStack<LDS, COUNT>& st) {
     if (!(ref & kLeafBit)) {
         if (ref < (uint32_t)sc.n_nodes) {
-            ++st.nodes;
+            if constexpr (COUNT) ++st.nodes;
             float4 q[8];
             load_node(sc.nodes, ref, q);
             float tn[4];
@@ -403,7 +403,7 @@ PT_DEV bool closest_step(const SceneView& sc, const Ray& r, float tmax, Hit& h, 
         uint32_t first = ref & kLeafFirstMask;
         uint32_t cnt = ((ref >> kLeafCountShift) & 15u) + 1u;
         if (first + cnt <= (uint32_t)sc.nt) {
-            st.tris += cnt;
+            if constexpr (COUNT) st.tris += cnt;
             for (uint32_t i = first; i < first + cnt; ++i) {
                 const float4* tp = sc.tris + (size_t)i * 3;
                 float4 a = tp[0], b = tp[1], c = tp[2];
@@ -429,8 +429,8 @@ PT_DEV bool closest_step(const SceneView& sc, const Ray& r, float tmax, Hit& h, 
     return false;
 }
 
-template <int LDS>
-PT_DEV Hit closest_hit(const SceneView& sc, const Ray& r, float tmax, TravStack<LDS>& st) {
+template <int LDS, bool COUNT = false>
+PT_DEV Hit closest_hit(const SceneView& sc, const Ray& r, float tmax, TravStack<LDS, COUNT>& st) {
     Hit h;
     uint32_t ref;
     closest_begin<LDS>(tmax, h, ref, st);
@@ -442,18 +442,18 @@ PT_DEV Hit closest_hit(const SceneView& sc, const Ray& r, float tmax, TravStack<
 // Any hit in (0, tmax), as resumable steps: any_step visits `ref` and pops
 // the next entry; it returns false when the traversal is finished, with
 // `occluded` set if a triangle was hit.
-template <int LDS>
-PT_DEV void any_begin(uint32_t& ref, TravStack<LDS>& st) {
+template <int LDS, bool COUNT = false>
+PT_DEV void any_begin(uint32_t& ref, TravStack<LDS, COUNT>& st) {
     st.sp = 0;
     ref = 0;
 }
 
-template <int LDS>
-PT_DEV bool any_step(const SceneView& sc, const Ray& r, float tmax, uint32_t& ref, TravStack<LDS>& st,
+template <int LDS, bool COUNT = false>
+PT_DEV bool any_step(const SceneView& sc, const Ray& r, float tmax, uint32_t& ref, TravStack<LDS, COUNT>& st,
                      bool& occluded) {
     if (!(ref & kLeafBit)) {
         if (ref < (uint32_t)sc.n_nodes) {
-            ++st.nodes;
+            if constexpr (COUNT) ++st.nodes;
             float4 q[8];
             load_node(sc.nodes, ref, q);
             float tn[4];
@@ -477,7 +477,7 @@ PT_DEV bool any_step(const SceneView& sc, const Ray& r, float tmax, uint32_t& re
         uint32_t cnt = ((ref >> kLeafCountShift) & 15u) + 1u;
         if (first + cnt <= (uint32_t)sc.nt) {
             for (uint32_t i = first; i < first + cnt; ++i) {
-                ++st.tris;
+                if constexpr (COUNT) ++st.tris;
                 const float4* tp = sc.tris + (size_t)i * 3;
                 float4 a = tp[0], b = tp[1], c = tp[2];
                 float t, b1, b2;
@@ -494,8 +494,8 @@ PT_DEV bool any_step(const SceneView& sc, const Ray& r, float tmax, uint32_t& re
     return true;
 }
 
-template <int LDS>
-PT_DEV bool any_hit(const SceneView& sc, const Ray& r, float tmax, TravStack<LDS>& st) {
+template <int LDS, bool COUNT = false>
+PT_DEV bool any_hit(const SceneView& sc, const Ray& r, float tmax, TravStack<LDS, COUNT>& st) {
     uint32_t ref;
     any_begin<LDS>(ref, st);
     bool occluded = false;
@@ -940,9 +940,9 @@ PT_DEV VertexOut shade_vertex(const SceneView& sc, const PathParams& pp, uint32_
 
 // One complete camera path (megakernel body): extend, shade, and trace the
 // light-sample segment at once; counts extension and shadow rays.
-template <int LDS>
+template <int LDS, bool COUNT = false>
 PT_DEV f3 trace_path(const SceneView& sc, const CamView& cam, const PathParams& pp, uint32_t pix, uint32_t sample,
-                     TravStack<LDS>& st, uint32_t& n_ext, uint32_t& n_sh, const LightCache& lc = no_light_cache()) {
+                     TravStack<LDS, COUNT>& st, uint32_t& n_ext, uint32_t& n_sh, const LightCache& lc = no_light_cache()) {
     Rng8 r0 = philox8(pp.seed, pix, sample, 0u, pp.job);
     f3 o, d;
     camera_ray(cam, (int)(pix % (uint32_t)cam.W), (int)(pix / (uint32_t)cam.W), unif(r0.w[0]), unif(r0.w[1]), o, d);

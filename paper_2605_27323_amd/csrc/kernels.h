@@ -47,30 +47,35 @@ constexpr uint32_t kRefill = 16;
 
 // stats: [0] extension rays, [1] shadow rays, [2] overflow flag; trav:
 // node visits, triangle tests
-hipError_t launch_mega(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const CamView& cam,
-                       const PathParams& pp, float* img, float* acc, uint2* ovf, int gcap, uint32_t* stats,
-                       unsigned long long* trav);
+// count: traversal kernels also count node visits and triangle tests
+hipError_t launch_mega(int lds, bool count, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
+                       const CamView& cam, const PathParams& pp, float* img, float* acc, uint2* ovf, int gcap,
+                       uint32_t* stats, unsigned long long* trav);
 hipError_t launch_init_counts(hipStream_t s, uint32_t* counts, int n, uint32_t first);
 hipError_t launch_raygen(dim3 grid, dim3 block, hipStream_t s, const CamView& cam, const PathParams& pp,
                          const WaveBufs& wb);
-hipError_t launch_extend(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const WaveBufs& wb,
-                         int b, uint2* ovf, int gcap);
+hipError_t launch_extend(int lds, bool count, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
+                         const WaveBufs& wb, int b, uint2* ovf, int gcap);
 // tail > 0 (compacted queues only): a queue with fewer than `tail` paths is
 // skipped here and finished in place by launch_tail
 hipError_t launch_shade(dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const PathParams& pp,
                         const WaveBufs& wb, int b, int compact, int sorted, uint32_t tail);
-hipError_t launch_tail(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const PathParams& pp,
-                       const WaveBufs& wb, int b, int sorted, uint32_t tail, uint2* ovf, int gcap);
+hipError_t launch_tail(int lds, bool count, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
+                       const PathParams& pp, const WaveBufs& wb, int b, int sorted, uint32_t tail, uint2* ovf,
+                       int gcap);
 // counting sort of queue b by material key when it holds >= threshold paths
 hipError_t launch_sort(dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const WaveBufs& wb, int b,
                        uint32_t threshold);
-hipError_t launch_shadow(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const WaveBufs& wb,
-                         int b, uint2* ovf, int gcap);
+hipError_t launch_shadow(int lds, bool count, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
+                         const WaveBufs& wb, int b, uint2* ovf, int gcap);
 hipError_t launch_adjoint(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const CamView& cam,
                           const PathParams& pp, const float* d_img, float* g_alb, float* g_emi, uint2* ovf, int gcap,
                           uint32_t* stats, unsigned long long* trav);
 hipError_t launch_accumulate(dim3 grid, dim3 block, hipStream_t s, const CamView& cam, const PathParams& pp,
                              const float4* L, float* img, float* acc);
+// img = I, running average acc updated for frame `frame` (npix pixels)
+hipError_t launch_average(dim3 grid, dim3 block, hipStream_t s, const float* I, uint32_t npix, uint32_t frame,
+                          float* img, float* acc);
 
 struct BatchBufs;
 hipError_t launch_batch_init(hipStream_t s, const BatchBufs& bb, uint32_t total);

@@ -9,10 +9,10 @@ namespace ptmi {
 
 namespace {
 
-template <int LDS>
-__device__ __forceinline__ TravStack<LDS> make_stack(uint32_t* smem, uint2* ovf, int gcap, uint32_t gtid,
-                                                     uint32_t nlanes) {
-    return make_trav_stack<LDS>(reinterpret_cast<uint2*>(smem) + threadIdx.x, (int)blockDim.x, ovf + gtid,
+template <int LDS, bool COUNT>
+__device__ __forceinline__ TravStack<LDS, COUNT> make_stack(uint32_t* smem, uint2* ovf, int gcap, uint32_t gtid,
+                                                            uint32_t nlanes) {
+    return make_trav_stack<LDS, COUNT>(reinterpret_cast<uint2*>(smem) + threadIdx.x, (int)blockDim.x, ovf + gtid,
                                 (int)nlanes, gcap);
 }
 
@@ -43,14 +43,14 @@ __device__ __forceinline__ LightCache stage_lights(const SceneView& sc, uint32_t
 // ---------------------------------------------------------------------------
 // four waves per SIMD instead of the three the register count would give:
 // a few spilled registers cost less than the lost latency hiding
-template <int LDS>
+template <int LDS, bool COUNT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_mega(SceneView sc, CamView cam, PathParams pp, float* __restrict__ img,
                                               float* __restrict__ acc, uint2* __restrict__ ovf, int gcap,
                                               uint32_t* __restrict__ stats, unsigned long long* __restrict__ trav) {
     extern __shared__ __align__(8) uint32_t smem[];
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
-    TravStack<LDS> st = make_stack<LDS>(smem, ovf, gcap, gtid, nlanes);
+    TravStack<LDS, COUNT> st = make_stack<LDS, COUNT>(smem, ovf, gcap, gtid, nlanes);
     __shared__ uint32_t light_buf[3 * kLdsLights];
     const LightCache lc = stage_lights(sc, light_buf);
     const uint32_t npix = (uint32_t)cam.W * (uint32_t)cam.H;
@@ -77,8 +77,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         atomicAdd(&stats[0], e);
         atomicAdd(&stats[1], sh);
     }
-    wave_add_u64(&trav[0], st.nodes);
-    wave_add_u64(&trav[1], st.tris);
+    if constexpr (COUNT) {
+        wave_add_u64(&trav[0], st.nodes);
+        wave_add_u64(&trav[1], st.tris);
+    }
     if (st.overflow) atomicOr(&stats[2], 1u);
 }
 
@@ -92,7 +94,7 @@ __global__ void k_init_counts(uint32_t* __restrict__ counts, int n, uint32_t fir
 
 // hybrid tail: a queue with fewer than `tail` paths is too short to keep
 // the stage kernels busy; each path is shaded and finished in place
-template <int LDS>
+template <int LDS, bool COUNT>
 __global__ void __launch_bounds__(256) k_shade_tail(SceneView sc, PathParams pp, WaveBufs wb, int b, int sorted,
                                                     uint32_t tail, uint2* __restrict__ ovf, int gcap) {
     const uint32_t count = wb.counts[b];
@@ -103,7 +105,7 @@ __global__ void __launch_bounds__(256) k_shade_tail(SceneView sc, PathParams pp,
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t* perm = (sorted && wb.hist[2 * kSortBins]) ? wb.perm : nullptr;
-    TravStack<LDS> st = make_stack<LDS>(smem, ovf, gcap, gtid, nlanes);
+    TravStack<LDS, COUNT> st = make_stack<LDS, COUNT>(smem, ovf, gcap, gtid, nlanes);
     uint32_t n_ext = 0, n_sh = 0;
     for (uint32_t i = gtid; i < count; i += nlanes) {
         VertexOut vo;
@@ -121,8 +123,10 @@ __global__ void __launch_bounds__(256) k_shade_tail(SceneView sc, PathParams pp,
         atomicAdd(&wb.counts[wb.tail_slot], n_ext);
         atomicAdd(&wb.counts[wb.tail_slot + 1], n_sh);
     }
-    wave_add_u64(&wb.trav[4], st.nodes);
-    wave_add_u64(&wb.trav[5], st.tris);
+    if constexpr (COUNT) {
+        wave_add_u64(&wb.trav[4], st.nodes);
+        wave_add_u64(&wb.trav[5], st.tris);
+    }
     if (st.overflow) atomicOr(&wb.counts[wb.err_slot], 1u);
 }
 
@@ -139,13 +143,13 @@ __global__ void __launch_bounds__(256) k_raygen(CamView cam, PathParams pp, Wave
 // when at least `refill` of them are idle (or all are); the chunk cursor is
 // wave-uniform, so no atomics are needed.
 
-template <int LDS>
-__global__ void __launch_bounds__(256) k_extend(SceneView sc, WaveBufs wb, int b, uint2* __restrict__ ovf, int gcap,
+template <int LDS, bool COUNT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k_extend(SceneView sc, WaveBufs wb, int b, uint2* __restrict__ ovf, int gcap,
                                                 uint32_t refill) {
     extern __shared__ __align__(8) uint32_t smem[];
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
-    TravStack<LDS> st = make_stack<LDS>(smem, ovf, gcap, gtid, nlanes);
+    TravStack<LDS, COUNT> st = make_stack<LDS, COUNT>(smem, ovf, gcap, gtid, nlanes);
     const int cur = b & 1;
     uint32_t next, end;
     wave_chunk(wb.counts[b], next, end);
@@ -181,8 +185,10 @@ __global__ void __launch_bounds__(256) k_extend(SceneView sc, WaveBufs wb, int b
             live = false;
         }
     }
-    wave_add_u64(&wb.trav[0], st.nodes);
-    wave_add_u64(&wb.trav[1], st.tris);
+    if constexpr (COUNT) {
+        wave_add_u64(&wb.trav[0], st.nodes);
+        wave_add_u64(&wb.trav[1], st.tris);
+    }
     if (st.overflow) atomicOr(&wb.counts[wb.err_slot], 1u);
 }
 
@@ -231,13 +237,13 @@ __global__ void __launch_bounds__(256) k_shade(SceneView sc, PathParams pp, Wave
     }
 }
 
-template <int LDS>
-__global__ void __launch_bounds__(256) k_shadow(SceneView sc, WaveBufs wb, int b, uint2* __restrict__ ovf, int gcap,
+template <int LDS, bool COUNT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k_shadow(SceneView sc, WaveBufs wb, int b, uint2* __restrict__ ovf, int gcap,
                                                 uint32_t refill) {
     extern __shared__ __align__(8) uint32_t smem[];
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
-    TravStack<LDS> st = make_stack<LDS>(smem, ovf, gcap, gtid, nlanes);
+    TravStack<LDS, COUNT> st = make_stack<LDS, COUNT>(smem, ovf, gcap, gtid, nlanes);
     uint32_t next, end;
     wave_chunk(wb.counts[wb.sh_base + b], next, end);
     bool live = false;
@@ -270,9 +276,20 @@ __global__ void __launch_bounds__(256) k_shadow(SceneView sc, WaveBufs wb, int b
             }
         }
     }
-    wave_add_u64(&wb.trav[2], st.nodes);
-    wave_add_u64(&wb.trav[3], st.tris);
+    if constexpr (COUNT) {
+        wave_add_u64(&wb.trav[2], st.nodes);
+        wave_add_u64(&wb.trav[3], st.tris);
+    }
     if (st.overflow) atomicOr(&wb.counts[wb.err_slot], 1u);
+}
+
+// frame image I (written by the megakernel into a workspace slot) to the
+// output image and the running average, in frame order
+__global__ void __launch_bounds__(256) k_average(const float* __restrict__ I, uint32_t npix, uint32_t frame,
+                                                 float* __restrict__ img, float* __restrict__ acc) {
+    const uint32_t nlanes = gridDim.x * blockDim.x;
+    for (uint32_t pix = blockIdx.x * blockDim.x + threadIdx.x; pix < npix; pix += nlanes)
+        store_pixel(img, acc, pix, mk3(I[3 * (size_t)pix], I[3 * (size_t)pix + 1], I[3 * (size_t)pix + 2]), frame);
 }
 
 // ---------------------------------------------------------------------------
@@ -351,17 +368,23 @@ __global__ void __launch_bounds__(256) k_accumulate(CamView cam, PathParams pp, 
 // launchers
 // ---------------------------------------------------------------------------
 #define PT_STACK_CASES(X) X(8) X(16) X(24) X(32)
+// instantiate a traversal kernel for the LDS stack depth and the work-counting flag
+#define PT_DISPATCH(N, launch) \
+    if (lds == N) {            \
+        if (count) launch(N, true) else launch(N, false) return hipGetLastError(); \
+    }
 
 static size_t stack_lds_bytes(int lds, int block) { return (size_t)lds * 2 * sizeof(uint32_t) * block; }
 
-hipError_t launch_mega(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const CamView& cam,
-                       const PathParams& pp, float* img, float* acc, uint2* ovf, int gcap, uint32_t* stats,
-                       unsigned long long* trav) {
+hipError_t launch_mega(int lds, bool count, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
+                       const CamView& cam, const PathParams& pp, float* img, float* acc, uint2* ovf, int gcap,
+                       uint32_t* stats, unsigned long long* trav) {
     size_t sm = stack_lds_bytes(lds, block.x);
-#define X(N) \
-    if (lds == N) { hipLaunchKernelGGL(k_mega<N>, grid, block, sm, s, sc, cam, pp, img, acc, ovf, gcap, stats, trav); return hipGetLastError(); }
+#define L(N, C) hipLaunchKernelGGL((k_mega<N, C>), grid, block, sm, s, sc, cam, pp, img, acc, ovf, gcap, stats, trav);
+#define X(N) PT_DISPATCH(N, L)
     PT_STACK_CASES(X)
 #undef X
+#undef L
     return hipErrorInvalidValue;
 }
 
@@ -376,13 +399,14 @@ hipError_t launch_raygen(dim3 grid, dim3 block, hipStream_t s, const CamView& ca
     return hipGetLastError();
 }
 
-hipError_t launch_extend(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const WaveBufs& wb,
-                         int b, uint2* ovf, int gcap) {
+hipError_t launch_extend(int lds, bool count, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
+                         const WaveBufs& wb, int b, uint2* ovf, int gcap) {
     size_t sm = stack_lds_bytes(lds, block.x);
-#define X(N) \
-    if (lds == N) { hipLaunchKernelGGL(k_extend<N>, grid, block, sm, s, sc, wb, b, ovf, gcap, kRefill); return hipGetLastError(); }
+#define L(N, C) hipLaunchKernelGGL((k_extend<N, C>), grid, block, sm, s, sc, wb, b, ovf, gcap, kRefill);
+#define X(N) PT_DISPATCH(N, L)
     PT_STACK_CASES(X)
 #undef X
+#undef L
     return hipErrorInvalidValue;
 }
 
@@ -392,16 +416,15 @@ hipError_t launch_shade(dim3 grid, dim3 block, hipStream_t s, const SceneView& s
     return hipGetLastError();
 }
 
-hipError_t launch_tail(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const PathParams& pp,
-                       const WaveBufs& wb, int b, int sorted, uint32_t tail, uint2* ovf, int gcap) {
+hipError_t launch_tail(int lds, bool count, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
+                       const PathParams& pp, const WaveBufs& wb, int b, int sorted, uint32_t tail, uint2* ovf,
+                       int gcap) {
     const size_t sm = stack_lds_bytes(lds, block.x);
-#define X(N)                                                                                                 \
-    if (lds == N) {                                                                                          \
-        hipLaunchKernelGGL(k_shade_tail<N>, grid, block, sm, s, sc, pp, wb, b, sorted, tail, ovf, gcap);     \
-        return hipGetLastError();                                                                            \
-    }
+#define L(N, C) hipLaunchKernelGGL((k_shade_tail<N, C>), grid, block, sm, s, sc, pp, wb, b, sorted, tail, ovf, gcap);
+#define X(N) PT_DISPATCH(N, L)
     PT_STACK_CASES(X)
 #undef X
+#undef L
     return hipErrorInvalidValue;
 }
 
@@ -417,14 +440,21 @@ hipError_t launch_sort(dim3 grid, dim3 block, hipStream_t s, const SceneView& sc
     return hipGetLastError();
 }
 
-hipError_t launch_shadow(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const WaveBufs& wb,
-                         int b, uint2* ovf, int gcap) {
+hipError_t launch_shadow(int lds, bool count, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
+                         const WaveBufs& wb, int b, uint2* ovf, int gcap) {
     size_t sm = stack_lds_bytes(lds, block.x);
-#define X(N) \
-    if (lds == N) { hipLaunchKernelGGL(k_shadow<N>, grid, block, sm, s, sc, wb, b, ovf, gcap, kRefill); return hipGetLastError(); }
+#define L(N, C) hipLaunchKernelGGL((k_shadow<N, C>), grid, block, sm, s, sc, wb, b, ovf, gcap, kRefill);
+#define X(N) PT_DISPATCH(N, L)
     PT_STACK_CASES(X)
 #undef X
+#undef L
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_average(dim3 grid, dim3 block, hipStream_t s, const float* I, uint32_t npix, uint32_t frame,
+                          float* img, float* acc) {
+    hipLaunchKernelGGL(k_average, grid, block, 0, s, I, npix, frame, img, acc);
+    return hipGetLastError();
 }
 
 hipError_t launch_accumulate(dim3 grid, dim3 block, hipStream_t s, const CamView& cam, const PathParams& pp,

@@ -40,8 +40,8 @@ PT_DEV void raygen_item(const CamView& cam, const PathParams& pp, const WaveBufs
 }
 
 // closest hit of queue slot i of bounce b
-template <int LDS>
-PT_DEV void extend_item(const SceneView& sc, const WaveBufs& wb, int b, uint32_t i, TravStack<LDS>& st) {
+template <int LDS, bool COUNT = false>
+PT_DEV void extend_item(const SceneView& sc, const WaveBufs& wb, int b, uint32_t i, TravStack<LDS, COUNT>& st) {
     float4 o4 = wb.ray_o[b & 1][i], d4 = wb.ray_d[b & 1][i];
     if (f2u(o4.w) == kDeadPath) return;
     Ray ray = make_ray(xyz(o4), xyz(d4));
@@ -111,9 +111,9 @@ PT_DEV uint32_t shade_item(const SceneView& sc, const PathParams& pp, const Wave
 // vertices) and store its final radiance.  Used when a bounce's queue is too
 // short to keep the wavefront stages busy.
 // n_ext / n_sh count the extension and shadow rays traced here.
-template <int LDS>
+template <int LDS, bool COUNT = false>
 PT_DEV void finish_path(const SceneView& sc, const PathParams& pp, const WaveBufs& wb, uint32_t path, int k,
-                        VertexOut vo, ShadowReq sh, PathState& ps, TravStack<LDS>& st, uint32_t& n_ext,
+                        VertexOut vo, ShadowReq sh, PathState& ps, TravStack<LDS, COUNT>& st, uint32_t& n_ext,
                         uint32_t& n_sh, const LightCache& lc = no_light_cache()) {
     const uint32_t pix = path / (uint32_t)pp.spp;
     const uint32_t s = path - pix * (uint32_t)pp.spp;
@@ -163,8 +163,8 @@ PT_DEV void shadow_add(const WaveBufs& wb, uint32_t i) {
 }
 
 // light-sample segment i: add beta * C to its path when unoccluded
-template <int LDS>
-PT_DEV void shadow_item(const SceneView& sc, const WaveBufs& wb, uint32_t i, TravStack<LDS>& st) {
+template <int LDS, bool COUNT = false>
+PT_DEV void shadow_item(const SceneView& sc, const WaveBufs& wb, uint32_t i, TravStack<LDS, COUNT>& st) {
     float4 o4 = wb.sh_o[i], d4 = wb.sh_d[i];
     Ray ray = make_ray(xyz(o4), xyz(d4));
     if (!any_hit<LDS>(sc, ray, kShadowTmax, st)) shadow_add(wb, i);

@@ -17,7 +17,7 @@ LIB_PATH = os.environ.get("PTMI_LIB") or os.path.join(HERE, "libptmi.so")
 
 PT_OK, PT_EINVAL, PT_ENOMEM, PT_EHIP, PT_ESTATE, PT_EOVERFLOW, PT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 MODE_MEGA, MODE_WAVE = 0, 1
-FLAG_PROFILE, FLAG_NO_COMPACT, FLAG_SORT_MATERIAL = 1, 2, 4
+FLAG_PROFILE, FLAG_NO_COMPACT, FLAG_SORT_MATERIAL, FLAG_COUNT_WORK = 1, 2, 4, 8
 STAGES = ["raygen", "extend", "shade", "shadow", "accumulate", "mega", "sort", "adjoint", "tail"]
 
 
@@ -99,6 +99,9 @@ SIGNATURES = {
     "pt_workspace_size": (C.c_int32, [C.c_void_p, C.POINTER(RenderArgs), C.POINTER(C.c_uint64)]),
     "pt_render_frame": (C.c_int32, [C.c_void_p, C.POINTER(RenderArgs), C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_uint64, C.c_void_p]),
+    "pt_frames_workspace_size": (C.c_int32, [C.c_void_p, C.POINTER(RenderArgs), C.POINTER(C.c_uint64)]),
+    "pt_render_frames": (C.c_int32, [C.c_void_p, C.POINTER(RenderArgs), C.c_int32, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_uint64, C.c_void_p]),
     "pt_render_backward": (C.c_int32, [C.c_void_p, C.POINTER(RenderArgs), C.c_void_p, C.c_void_p, C.c_void_p,
                                        C.c_void_p, C.c_uint64, C.c_void_p]),
     "pt_frame_stats_get": (C.c_int32, [C.c_void_p, C.POINTER(FrameStats)]),
@@ -261,6 +264,28 @@ class Renderer(Context):
             assert accum.is_contiguous() and accum.numel() == out.numel()
             acc_ptr = accum.data_ptr()
         check(lib().pt_render_frame(self.h, C.byref(a), out.data_ptr(), acc_ptr, ws, wsb, self._stream()))
+        return out
+
+    def render_frames(self, n_frames, out=None, accum=None, **kw):
+        """Render frames kw['frame'] .. + n_frames - 1 with two frames in flight
+        (pt_render_frames); returns the image tensor (the last frame's image)."""
+        import torch
+        a = self.args(**kw)
+        if out is None:
+            out = torch.empty((self.height, self.width, 3), dtype=torch.float32, device=self.torch_device)
+        assert out.is_contiguous() and out.dtype == torch.float32 and out.numel() == self.height * self.width * 3
+        need = C.c_uint64()
+        check(lib().pt_frames_workspace_size(self.h, C.byref(a), C.byref(need)))
+        if need.value > getattr(self, "_fws_bytes", 0):
+            self._fws = None
+            self._fws, self._fws_ptr = _aligned_empty(need.value, self.torch_device)
+            self._fws_bytes = need.value
+        acc_ptr = None
+        if accum is not None:
+            assert accum.is_contiguous() and accum.numel() == out.numel()
+            acc_ptr = accum.data_ptr()
+        check(lib().pt_render_frames(self.h, C.byref(a), int(n_frames), out.data_ptr(), acc_ptr, self._fws_ptr,
+                                     self._fws_bytes, self._stream()))
         return out
 
     def backward(self, d_image, d_albedo, d_emission, **kw):

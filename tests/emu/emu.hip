@@ -87,7 +87,7 @@ int32_t emu_render_wave(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32
     const uint32_t npaths = (uint32_t)c->cam.W * c->cam.H * (uint32_t)spp;
     std::vector<float4> buf[11];
     for (auto& b : buf) b.assign(std::max<uint32_t>(npaths, 1), make_float4(0, 0, 0, 0));
-    std::vector<uint32_t> counts((D + 2) + (D + 1) + 4, 0u);
+    std::vector<uint32_t> counts(2 * D + 6, 0u);
     WaveBufs wb{};
     for (int q = 0; q < 2; ++q) {
         wb.ray_o[q] = buf[0 + q].data();

@@ -179,9 +179,9 @@ def test_progressive_accumulation_and_ray_counts():
     frac, nfail, unexplained, nexact = image_tolerance_report(got, ref_acc, np.zeros(len(ref_acc)))
     assert nexact >= 0.999 * len(ref_acc)
     # identical paths => identical ray counts in both schedules
-    R.render(mode="mega", spp=2, max_depth=4)
+    R.render(mode="mega", spp=2, max_depth=4, flags=ptmi.FLAG_COUNT_WORK)
     sm = R.stats()
-    R.render(mode="wave", spp=2, max_depth=4)
+    R.render(mode="wave", spp=2, max_depth=4, flags=ptmi.FLAG_COUNT_WORK)
     sw = R.stats()
     assert sm["extension_rays"] == sw["extension_rays"] > 0
     assert sm["shadow_rays"] == sw["shadow_rays"] > 0
@@ -190,7 +190,7 @@ def test_progressive_accumulation_and_ray_counts():
     for key in ("node_visits", "tri_tests"):
         assert sm[key]["mega"] == sw[key]["extend"] + sw[key]["shadow"] > 0
     # the hybrid tail traces the rest of the paths in place and counts them
-    R.render(mode="wave", spp=2, max_depth=4, tail_threshold=400)
+    R.render(mode="wave", spp=2, max_depth=4, tail_threshold=400, flags=ptmi.FLAG_COUNT_WORK)
     st = R.stats()
     assert st["items"].get("tail", 0) > 0
     assert (st["extension_rays"], st["shadow_rays"]) == (sm["extension_rays"], sm["shadow_rays"])
@@ -215,3 +215,30 @@ def test_profile_stage_times():
     R.render(mode="wave", spp=1, max_depth=5, rr_start=3, tail_threshold=1 << 30, flags=ptmi.FLAG_PROFILE)
     st = R.stats()
     assert st["launches"]["tail"] == 6 and st["items"]["tail"] == 48 * 32 and "shade" not in st["items"]
+
+
+@pytest.mark.parametrize("mode", ["wave", "mega"])
+def test_frames_in_flight_match_sequential(mode):
+    """pt_render_frames (two frames in flight on internal streams) gives the
+    same running average and last image, bit for bit, as frame-by-frame
+    rendering."""
+    scene, cam = scenes.procedural(seed=52, n_objects=30, width=64, height=40)
+    log(f"frames in flight {mode}")
+    R = ptmi.Renderer(scene, cam)
+    kw = dict(mode=mode, spp=2, max_depth=6, rr_start=3, tail_threshold=300 if mode == "wave" else 0)
+    acc_seq = torch.zeros((40, 64, 3), dtype=torch.float32, device="cuda")
+    for f in range(5):
+        img_seq = R.render(accum=acc_seq, frame=3 + f, **kw).clone()
+    # continue the same running average both ways from frame 8
+    acc_pipe = acc_seq.clone()
+    acc_seq2 = acc_seq.clone()
+    for f in range(5):
+        R.render(accum=acc_seq2, frame=8 + f, **kw)
+    img_pipe = R.render_frames(5, accum=acc_pipe, frame=8, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(acc_pipe.view(torch.int32), acc_seq2.view(torch.int32))
+    img_last = R.render(frame=12, **kw)
+    assert torch.equal(img_pipe.view(torch.int32), img_last.view(torch.int32))
+    # one frame through the pipelined entry point equals a plain frame
+    one = R.render_frames(1, frame=0, **kw).clone()
+    assert torch.equal(one.view(torch.int32), R.render(frame=0, **kw).view(torch.int32))
