@@ -165,8 +165,14 @@ def main():
     # the same frames with two in flight (pt_render_frames): one frame's
     # last, short bounces overlap the next frame's first ones
     inflight = {}
+    tuned_inflight = {m: dict(tuned[m]) for m in modes}
+    if not args.fixed and not args.no_tune and not args.params:
+        for mode in modes:
+            t = time.perf_counter()
+            tuned_inflight[mode] = autotune.tune_frame(R, mode=mode, cache=None, log=log, in_flight=True, **kw)
+            log(f"autotune {mode}, two frames in flight: {tuned_inflight[mode]} ({time.perf_counter() - t:.1f} s)")
     for mode in modes:
-        p = dict(tuned[mode])
+        p = dict(tuned_inflight[mode])
         R.render_frames(args.warmup, out=img, mode=mode, frame=0, **kw, **p)
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -267,7 +273,7 @@ def main():
                       if "wave" in inflight else None,
         "rays_per_frame": {"extension": ext_rays_per_frame, "shadow": sh_rays_per_frame},
         "stage_ms_per_frame": frame_stage_ms,
-        "launch_params": tuned,
+        "launch_params": {"frame_by_frame": tuned, "two_frames_in_flight": tuned_inflight},
         "roofline": roofline,
         "state_traffic": state_floor,
         "stage_items_per_frame": {k: v / args.steps for k, v in items.items()},

@@ -66,13 +66,14 @@ def _device_name(torch):
     return torch.cuda.get_device_name(0) if torch.cuda.is_available() else "none"
 
 
-def tune_frame(renderer, mode="wave", cache=DEFAULT_CACHE, space=None, log=None, **kw):
-    """Best launch parameters for renderer.render(mode=mode, **kw)."""
+def tune_frame(renderer, mode="wave", cache=DEFAULT_CACHE, space=None, log=None, in_flight=False, **kw):
+    """Best launch parameters for renderer.render(mode=mode, **kw), or with
+    in_flight for renderer.render_frames (two frames in flight)."""
     import torch
 
     from . import ptmi
     key = json.dumps(["frame", _device_name(torch), mode, _bucket(renderer.nt), renderer.width, renderer.height,
-                      kw.get("spp", 1), kw.get("max_depth", 5), kw.get("rr_start", -1)])
+                      kw.get("spp", 1), kw.get("max_depth", 5), kw.get("rr_start", -1), bool(in_flight)])
     hit = _load(cache).get(key) if cache else None
     if hit:
         return hit
@@ -88,12 +89,21 @@ def tune_frame(renderer, mode="wave", cache=DEFAULT_CACHE, space=None, log=None,
         cands.append(c)
     img = torch.empty((renderer.height, renderer.width, 3), dtype=torch.float32, device=renderer.torch_device)
 
+    rest = {k: v for k, v in kw.items() if k != "frame"}
+
     def measure(c, reps):
+        if in_flight:
+            renderer.render_frames(2, out=img, mode=mode, frame=0, **rest, **c)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            renderer.render_frames(reps + 1, out=img, mode=mode, frame=2, **rest, **c)
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t) / (reps + 1)
         renderer.render(out=img, mode=mode, **kw, **c)
         torch.cuda.synchronize()
         t = time.perf_counter()
         for i in range(reps):
-            renderer.render(out=img, mode=mode, frame=1 + i, **{k: v for k, v in kw.items() if k != "frame"}, **c)
+            renderer.render(out=img, mode=mode, frame=1 + i, **rest, **c)
         torch.cuda.synchronize()
         return (time.perf_counter() - t) / reps
 
