@@ -58,8 +58,10 @@ enum {
     PT_FLAG_PROFILE = 1,       /* time every stage launch with HIP events */
     PT_FLAG_NO_COMPACT = 2,    /* wavefront: no compaction, dispatch every path each bounce */
     PT_FLAG_SORT_MATERIAL = 4, /* wavefront: counting-sort each shade queue by material type */
-    PT_FLAG_COUNT_WORK = 8     /* traversal kernels count BVH node visits and triangle tests
+    PT_FLAG_COUNT_WORK = 8,    /* traversal kernels count BVH node visits and triangle tests
                                   (pt_frame_stats); a separate kernel build, slower */
+    PT_FLAG_SORT_RAYS = 16     /* wavefront: counting-sort each extend queue by ray direction octant and
+                                  origin side of the scene centre (coherent waves) */
 };
 
 typedef struct pt_ctx pt_ctx;
@@ -130,8 +132,9 @@ typedef struct {
  * disables Russian roulette, else it applies from that vertex on.
  * block = threads per workgroup (64..256, multiple of 64; 0 = default);
  * grid_mult = persistent workgroups per compute unit (0 = default);
- * sort_threshold: with PT_FLAG_SORT_MATERIAL, a bounce's shade queue is
- * sorted by material only when it holds at least this many paths;
+ * sort_threshold: with PT_FLAG_SORT_MATERIAL (PT_FLAG_SORT_RAYS), a
+ * bounce's shade (extend) queue is sorted only when it holds at least this
+ * many paths;
  * stack_lds: traversal stack entries kept in LDS per lane, 8/16/24/32
  * (0 = default 16); deeper entries spill to the workspace;
  * tail_threshold: wavefront hybrid tail, a bounce whose queue holds fewer

@@ -18,7 +18,8 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ptmi_autotune.j
 
 FRAME_SPACE = {
     "wave": {"block": [64, 128, 256], "grid_mult": [4, 8, 16], "stack_lds": [8, 16],
-             "sort_threshold": [None, 1 << 16], "tail_threshold": [0, 1 << 16, 1 << 18, 1 << 19, 1 << 20]},
+             "sort_threshold": [None, 1 << 16], "ray_sort": [False, True],
+             "tail_threshold": [0, 1 << 16, 1 << 18, 1 << 19, 1 << 20]},
     "mega": {"block": [64, 128, 256], "grid_mult": [2, 4, 8, 16], "stack_lds": [8, 16]},
 }
 BATCH_SPACE = {"pool_capacity": [1 << 20, 1 << 21, 1 << 22], "block": [128, 256], "grid_mult": [4, 8],
@@ -82,10 +83,17 @@ def tune_frame(renderer, mode="wave", cache=DEFAULT_CACHE, space=None, log=None,
     cands = []
     for vals in itertools.product(*(space[n] for n in names)):
         c = dict(zip(names, vals))
+        flags = 0
+        if c.pop("ray_sort", False):
+            flags |= ptmi.FLAG_SORT_RAYS
         if c.get("sort_threshold", None) is None:
             c.pop("sort_threshold", None)
         else:
-            c["flags"] = ptmi.FLAG_SORT_MATERIAL
+            flags |= ptmi.FLAG_SORT_MATERIAL
+        if flags & ptmi.FLAG_SORT_RAYS and "sort_threshold" not in c:
+            c["sort_threshold"] = 1 << 16
+        if flags:
+            c["flags"] = flags
         cands.append(c)
     img = torch.empty((renderer.height, renderer.width, 3), dtype=torch.float32, device=renderer.torch_device)
 

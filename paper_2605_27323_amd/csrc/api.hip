@@ -150,7 +150,7 @@ pt_status check_args(const pt_ctx* c, const pt_render_args* a) {
     if (c->device < 0) return fail(PT_ESTATE, "host-only context cannot render");
     if (!c->bound) return fail(PT_ESTATE, "scene not bound (pt_bind_scene)");
     if (!c->cam_set) return fail(PT_ESTATE, "camera not set (pt_set_camera)");
-    if (a->flags & ~(PT_FLAG_PROFILE | PT_FLAG_NO_COMPACT | PT_FLAG_SORT_MATERIAL | PT_FLAG_COUNT_WORK))
+    if (a->flags & ~(PT_FLAG_PROFILE | PT_FLAG_NO_COMPACT | PT_FLAG_SORT_MATERIAL | PT_FLAG_COUNT_WORK | PT_FLAG_SORT_RAYS))
         return fail(PT_EINVAL, "unknown flag");
     if (a->spp < 1 || a->spp > 65536) return fail(PT_EINVAL, "spp must be in [1, 65536]");
     if (a->max_depth < 0 || a->max_depth > 1000) return fail(PT_EINVAL, "max_depth must be in [0, 1000]");
@@ -190,7 +190,7 @@ void remember_frame(pt_ctx* c, const pt_render_args* a, uint32_t* counts, int nc
     c->last_spp = a->spp;
     c->last_nee = a->nee ? 1 : 0;
     c->last_compact = (a->flags & PT_FLAG_NO_COMPACT) ? 0 : 1;
-    c->last_sort = (a->flags & PT_FLAG_SORT_MATERIAL) ? 1 : 0;
+    c->last_sort = ((a->flags & PT_FLAG_SORT_MATERIAL) ? 1 : 0) + ((a->flags & PT_FLAG_SORT_RAYS) ? 1 : 0);
     c->last_tail = a->tail_threshold;
     c->last_sort_threshold = a->sort_threshold;
     c->last_npix = (uint64_t)c->cam.W * (uint64_t)c->cam.H;
@@ -243,14 +243,17 @@ pt_status enqueue_stages(pt_ctx* c, const pt_render_args* a, const Launch& L, co
         wb.hist = reinterpret_cast<uint32_t*>(base + w.hist);
         const int compact = (a->flags & PT_FLAG_NO_COMPACT) ? 0 : 1;
         const int sort = (a->flags & PT_FLAG_SORT_MATERIAL) ? 1 : 0;
-        if (sort && !compact) return fail(PT_EINVAL, "material sort needs compaction");
+        const int rsort = (a->flags & PT_FLAG_SORT_RAYS) ? 1 : 0;
+        if ((sort || rsort) && !compact) return fail(PT_EINVAL, "sorting needs compaction");
         PT_HIP(launch_init_counts(s, counts, w.ncounts, npaths), "init counters");
-        if (sort) PT_HIP(launch_init_counts(s, wb.hist, 2 * kSortBins + 1, 0u), "init sort histogram");
+        if (sort || rsort) PT_HIP(launch_init_counts(s, wb.hist, 2 * kSortBins + 1, 0u), "init sort histogram");
         PT_HIP(timed(c, prof, 0, s, [&] { return launch_raygen(grid, block, s, c->cam, pp, wb); }), "raygen");
         for (int b = 0; b <= a->max_depth; ++b) {
-            PT_HIP(timed(c, prof, 1, s, [&] { return launch_extend(L.lds, count, grid, block, s, c->view, wb, b, ovf, L.gcap); }), "extend");
+            if (rsort)
+                PT_HIP(timed(c, prof, 6, s, [&] { return launch_sort(grid, block, s, c->view, wb, b, a->sort_threshold, 1); }), "ray sort");
+            PT_HIP(timed(c, prof, 1, s, [&] { return launch_extend(L.lds, count, grid, block, s, c->view, wb, b, ovf, L.gcap, rsort); }), "extend");
             if (sort)
-                PT_HIP(timed(c, prof, 6, s, [&] { return launch_sort(grid, block, s, c->view, wb, b, a->sort_threshold); }), "sort");
+                PT_HIP(timed(c, prof, 6, s, [&] { return launch_sort(grid, block, s, c->view, wb, b, a->sort_threshold, 0); }), "sort");
             PT_HIP(timed(c, prof, 2, s, [&] { return launch_shade(grid, block, s, c->view, pp, wb, b, compact, sort, a->tail_threshold); }), "shade");
             if (compact && a->tail_threshold)
                 PT_HIP(timed(c, prof, 8, s, [&] {
@@ -283,6 +286,9 @@ SceneView make_view(const pt_ctx* c, const pt_scene_buffers* b) {
     v.sky0 = c->sky[0];
     v.sky1 = c->sky[1];
     v.sky2 = c->sky[2];
+    v.cx = c->bvh.center[0];
+    v.cy = c->bvh.center[1];
+    v.cz = c->bvh.center[2];
     return v;
 }
 
@@ -675,7 +681,7 @@ pt_status pt_frame_stats_get(pt_ctx* c, pt_frame_stats* out) {
     for (int b = 0; b <= D; ++b) {
         out->extension_rays += cnt[b];
         out->stage_items[1] += cnt[b];
-        if (c->last_sort && cnt[b] >= c->last_sort_threshold) out->stage_items[6] += cnt[b];
+        if (c->last_sort && cnt[b] >= c->last_sort_threshold) out->stage_items[6] += (int64_t)c->last_sort * cnt[b];
         if (tail && cnt[b] < tail) {
             out->stage_items[8] += cnt[b];
         } else {

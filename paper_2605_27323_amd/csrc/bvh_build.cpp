@@ -264,6 +264,16 @@ BuildResult build_scene(const std::vector<float>& tri_v, const std::vector<int32
     // test can never reject a triangle the watertight test accepts
     const float pad = M * 0x1p-18f;
     r.max_coord = M;
+    if (nt > 0) {
+        for (int a = 0; a < 3; ++a) {
+            float lo = info[0].lo[a], hi = info[0].hi[a];
+            for (int32_t i = 1; i < nt; ++i) {
+                lo = std::min(lo, info[i].lo[a]);
+                hi = std::max(hi, info[i].hi[a]);
+            }
+            r.center[a] = 0.5f * (lo + hi);
+        }
+    }
 
     std::vector<int32_t> order(nt);
     for (int32_t i = 0; i < nt; ++i) order[i] = i;

@@ -13,6 +13,7 @@ struct BuildResult {
     std::vector<LightEntry> lights;  // input order of the light triangles
     float area_total = 0.f;
     float max_coord = 0.f;  // largest absolute vertex coordinate
+    float center[3] = {0.f, 0.f, 0.f};  // centre of the scene's bounding box
     int depth = 0;
     int stack_entries = 0;
 };

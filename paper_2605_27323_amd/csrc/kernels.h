@@ -54,8 +54,9 @@ hipError_t launch_mega(int lds, bool count, dim3 grid, dim3 block, hipStream_t s
 hipError_t launch_init_counts(hipStream_t s, uint32_t* counts, int n, uint32_t first);
 hipError_t launch_raygen(dim3 grid, dim3 block, hipStream_t s, const CamView& cam, const PathParams& pp,
                          const WaveBufs& wb);
+// sorted: a ray sort of queue b precedes (its permutation orders the work)
 hipError_t launch_extend(int lds, bool count, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
-                         const WaveBufs& wb, int b, uint2* ovf, int gcap);
+                         const WaveBufs& wb, int b, uint2* ovf, int gcap, int sorted);
 // tail > 0 (compacted queues only): a queue with fewer than `tail` paths is
 // skipped here and finished in place by launch_tail
 hipError_t launch_shade(dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const PathParams& pp,
@@ -63,9 +64,11 @@ hipError_t launch_shade(dim3 grid, dim3 block, hipStream_t s, const SceneView& s
 hipError_t launch_tail(int lds, bool count, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
                        const PathParams& pp, const WaveBufs& wb, int b, int sorted, uint32_t tail, uint2* ovf,
                        int gcap);
-// counting sort of queue b by material key when it holds >= threshold paths
+// counting sort of queue b by a 6-bit key when it holds >= threshold
+// paths: key_kind 0 = material of the hit (for shade), 1 = ray direction
+// octant and origin side (for extend)
 hipError_t launch_sort(dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const WaveBufs& wb, int b,
-                       uint32_t threshold);
+                       uint32_t threshold, int key_kind);
 hipError_t launch_shadow(int lds, bool count, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
                          const WaveBufs& wb, int b, uint2* ovf, int gcap);
 hipError_t launch_adjoint(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const CamView& cam,

@@ -145,12 +145,14 @@ __global__ void __launch_bounds__(256) k_raygen(CamView cam, PathParams pp, Wave
 
 template <int LDS, bool COUNT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k_extend(SceneView sc, WaveBufs wb, int b, uint2* __restrict__ ovf, int gcap,
-                                                uint32_t refill) {
+                                                uint32_t refill, int sorted) {
     extern __shared__ __align__(8) uint32_t smem[];
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
     TravStack<LDS, COUNT> st = make_stack<LDS, COUNT>(smem, ovf, gcap, gtid, nlanes);
     const int cur = b & 1;
+    // with a ray sort this bounce, position i of the queue is slot perm[i]
+    const uint32_t* perm = (sorted && wb.hist[2 * kSortBins]) ? wb.perm : nullptr;
     uint32_t next, end;
     wave_chunk(wb.counts[b], next, end);
     bool live = false;
@@ -162,8 +164,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
         const uint32_t nidle = (uint32_t)__popcll(idle);
         if (next < end && (nidle >= refill || nidle == 64u)) {
             if (!live) {
-                const uint32_t i = next + rank_in(idle);
-                if (i < end) {
+                const uint32_t pos = next + rank_in(idle);
+                if (pos < end) {
+                    const uint32_t i = perm ? perm[pos] : pos;
                     const float4 o4 = wb.ray_o[cur][i];
                     if (f2u(o4.w) != kDeadPath) {  // dead slots (no compaction) need no hit
                         const float4 d4 = wb.ray_d[cur][i];
@@ -295,15 +298,18 @@ __global__ void __launch_bounds__(256) k_average(const float* __restrict__ I, ui
 // ---------------------------------------------------------------------------
 // material sort of a shade queue: histogram, scan, scatter of a permutation
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_sort_hist(SceneView sc, WaveBufs wb, int b, uint32_t threshold) {
+// key 0: material of the hit (shade queue), 1: ray direction octant and
+// origin side (extend queue)
+__global__ void __launch_bounds__(256) k_sort_hist(SceneView sc, WaveBufs wb, int b, uint32_t threshold, int key_kind) {
     __shared__ uint32_t h[kSortBins];
     const uint32_t count = wb.counts[b];
     if (count < threshold) return;
     for (int t = threadIdx.x; t < kSortBins; t += blockDim.x) h[t] = 0u;
     __syncthreads();
     const uint32_t nlanes = gridDim.x * blockDim.x;
+    const int cur = b & 1;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += nlanes) {
-        const uint32_t key = material_key(sc, wb.hit[i]);
+        const uint32_t key = key_kind ? ray_key(sc, wb.ray_o[cur][i], wb.ray_d[cur][i]) : material_key(sc, wb.hit[i]);
         wb.sort_key[i] = key;
         atomicAdd(&h[key], 1u);
     }
@@ -400,9 +406,9 @@ hipError_t launch_raygen(dim3 grid, dim3 block, hipStream_t s, const CamView& ca
 }
 
 hipError_t launch_extend(int lds, bool count, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
-                         const WaveBufs& wb, int b, uint2* ovf, int gcap) {
+                         const WaveBufs& wb, int b, uint2* ovf, int gcap, int sorted) {
     size_t sm = stack_lds_bytes(lds, block.x);
-#define L(N, C) hipLaunchKernelGGL((k_extend<N, C>), grid, block, sm, s, sc, wb, b, ovf, gcap, kRefill);
+#define L(N, C) hipLaunchKernelGGL((k_extend<N, C>), grid, block, sm, s, sc, wb, b, ovf, gcap, kRefill, sorted);
 #define X(N) PT_DISPATCH(N, L)
     PT_STACK_CASES(X)
 #undef X
@@ -429,8 +435,8 @@ hipError_t launch_tail(int lds, bool count, dim3 grid, dim3 block, hipStream_t s
 }
 
 hipError_t launch_sort(dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const WaveBufs& wb, int b,
-                       uint32_t threshold) {
-    hipLaunchKernelGGL(k_sort_hist, grid, block, 0, s, sc, wb, b, threshold);
+                       uint32_t threshold, int key_kind) {
+    hipLaunchKernelGGL(k_sort_hist, grid, block, 0, s, sc, wb, b, threshold, key_kind);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(kSortBins), 0, s, wb, b, threshold);

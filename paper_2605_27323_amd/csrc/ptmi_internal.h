@@ -50,6 +50,7 @@ struct SceneView {
     int32_t n_nodes;
     float area_total;
     float sky0, sky1, sky2;
+    float cx, cy, cz;  // centre of the scene's bounding box (ray sort key)
 };
 
 struct CamView {

@@ -59,6 +59,14 @@ PT_DEV uint32_t material_key(const SceneView& sc, const float4& h4) {
     return (type << 4) | (mi & 15u);
 }
 
+// 6-bit sort key of a queued ray: direction octant in bits 3-5, the side of
+// the scene centre the origin lies on per axis in bits 0-2; rays with equal
+// keys tend to visit the same BVH nodes
+PT_DEV uint32_t ray_key(const SceneView& sc, const float4& o4, const float4& d4) {
+    return ((d4.x < 0.0f) ? 32u : 0u) | ((d4.y < 0.0f) ? 16u : 0u) | ((d4.z < 0.0f) ? 8u : 0u) |
+           ((o4.x > sc.cx) ? 4u : 0u) | ((o4.y > sc.cy) ? 2u : 0u) | ((o4.z > sc.cz) ? 1u : 0u);
+}
+
 // shade queue slot i of bounce b (vertex k = b + 1); returns the path id
 // (kDeadPath for a dead slot); vo / sh / ps describe what to enqueue.  With
 // a material sort the slot's data is read from slot perm[i].  The path

@@ -33,6 +33,9 @@ SceneView host_view(const pt_ctx* c) {
     v.sky0 = c->sky[0];
     v.sky1 = c->sky[1];
     v.sky2 = c->sky[2];
+    v.cx = c->bvh.center[0];
+    v.cy = c->bvh.center[1];
+    v.cz = c->bvh.center[2];
     return v;
 }
 

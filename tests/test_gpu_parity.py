@@ -154,6 +154,9 @@ def test_no_compaction_and_launch_shapes_bit_identical():
             R.render(mode="wave", tail_threshold=700, **cfg),
             R.render(mode="wave", tail_threshold=1 << 30, stack_lds=8, **cfg),
             R.render(mode="wave", tail_threshold=300, flags=ptmi.FLAG_SORT_MATERIAL, **cfg),
+            R.render(mode="wave", flags=ptmi.FLAG_SORT_RAYS, **cfg),
+            R.render(mode="wave", flags=ptmi.FLAG_SORT_RAYS | ptmi.FLAG_SORT_MATERIAL, sort_threshold=900,
+                     tail_threshold=200, **cfg),
             R.render(mode="wave", **cfg)]
     for o in outs:
         assert np.array_equal(o.cpu().numpy().view(np.uint32), ref.view(np.uint32))
