@@ -162,7 +162,7 @@ def main():
         dt = time.perf_counter() - t
         res[mode] = dict(seconds=dt, ms=dt * 1e3 / args.steps, value=W * H * SPP * args.steps / dt)
         log(f"{mode}: {res[mode]['ms']:.3f} ms/frame, {res[mode]['value'] / 1e6:.1f} M path-samples/s")
-    # the same frames with two in flight (pt_render_frames): one frame's
+    # the same frames with three in flight (pt_render_frames): one frame's
     # last, short bounces overlap the next frame's first ones
     inflight = {}
     tuned_inflight = {m: dict(tuned[m]) for m in modes}
@@ -170,7 +170,7 @@ def main():
         for mode in modes:
             t = time.perf_counter()
             tuned_inflight[mode] = autotune.tune_frame(R, mode=mode, cache=None, log=log, in_flight=True, **kw)
-            log(f"autotune {mode}, two frames in flight: {tuned_inflight[mode]} ({time.perf_counter() - t:.1f} s)")
+            log(f"autotune {mode}, three frames in flight: {tuned_inflight[mode]} ({time.perf_counter() - t:.1f} s)")
     for mode in modes:
         p = dict(tuned_inflight[mode])
         R.render_frames(args.warmup, out=img, mode=mode, frame=0, **kw, **p)
@@ -180,7 +180,7 @@ def main():
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
         inflight[mode] = dict(ms_per_step=dt * 1e3 / args.steps, value=W * H * SPP * args.steps / dt)
-        log(f"{mode}, two frames in flight: {inflight[mode]['ms_per_step']:.3f} ms/frame, "
+        log(f"{mode}, three frames in flight: {inflight[mode]['ms_per_step']:.3f} ms/frame, "
             f"{inflight[mode]['value'] / 1e6:.1f} M path-samples/s")
 
     # per-stage times with HIP events on the render stream, over the same
@@ -262,18 +262,18 @@ def main():
         "config": {"workload": f"procedural scene {nt} triangles (1000 icospheres + 1000 tessellated boxes, "
                                f"ground, 16 quad lights), {W}x{H}, {SPP} spp/frame, max depth {DEPTH}, "
                                f"roulette from {RR}, light sampling on; {head} schedule, progressive frames with "
-                               f"two in flight (bit-identical to frame by frame)",
+                               f"three in flight (bit-identical to frame by frame)",
                    "width": W, "height": H, "spp": SPP, "max_depth": DEPTH, "triangles": nt},
-        "schedules": {m: {"two_frames_in_flight": inflight[m], "frame_by_frame": {"value": res[m]["value"],
+        "schedules": {m: {"frames_in_flight": inflight[m], "frame_by_frame": {"value": res[m]["value"],
                                                                                  "ms_per_step": res[m]["ms"]}}
                       for m in modes},
-        "wave_over_mega": ({"two_frames_in_flight": inflight["wave"]["value"] / inflight["mega"]["value"],
+        "wave_over_mega": ({"frames_in_flight": inflight["wave"]["value"] / inflight["mega"]["value"],
                             "frame_by_frame": res["wave"]["value"] / res["mega"]["value"]} if len(res) == 2 else None),
         "rays_per_s": ((ext_rays_per_frame + sh_rays_per_frame) / (inflight["wave"]["ms_per_step"] * 1e-3))
                       if "wave" in inflight else None,
         "rays_per_frame": {"extension": ext_rays_per_frame, "shadow": sh_rays_per_frame},
         "stage_ms_per_frame": frame_stage_ms,
-        "launch_params": {"frame_by_frame": tuned, "two_frames_in_flight": tuned_inflight},
+        "launch_params": {"frame_by_frame": tuned, "frames_in_flight": tuned_inflight},
         "roofline": roofline,
         "state_traffic": state_floor,
         "stage_items_per_frame": {k: v / args.steps for k, v in items.items()},

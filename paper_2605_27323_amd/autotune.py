@@ -69,7 +69,7 @@ def _device_name(torch):
 
 def tune_frame(renderer, mode="wave", cache=DEFAULT_CACHE, space=None, log=None, in_flight=False, **kw):
     """Best launch parameters for renderer.render(mode=mode, **kw), or with
-    in_flight for renderer.render_frames (two frames in flight)."""
+    in_flight for renderer.render_frames (frames in flight)."""
     import torch
 
     from . import ptmi
@@ -101,12 +101,13 @@ def tune_frame(renderer, mode="wave", cache=DEFAULT_CACHE, space=None, log=None,
 
     def measure(c, reps):
         if in_flight:
+            n = max(6, 2 * reps)  # long enough for the pipeline to fill
             renderer.render_frames(2, out=img, mode=mode, frame=0, **rest, **c)
             torch.cuda.synchronize()
             t = time.perf_counter()
-            renderer.render_frames(reps + 1, out=img, mode=mode, frame=2, **rest, **c)
+            renderer.render_frames(n, out=img, mode=mode, frame=2, **rest, **c)
             torch.cuda.synchronize()
-            return (time.perf_counter() - t) / (reps + 1)
+            return (time.perf_counter() - t) / n
         renderer.render(out=img, mode=mode, **kw, **c)
         torch.cuda.synchronize()
         t = time.perf_counter()

@@ -31,6 +31,8 @@ pt_status hip_fail(hipError_t e, const char* what) {
         if (e_ != hipSuccess) return hip_fail(e_, what); \
     } while (0)
 
+// frames in flight in pt_render_frames (internal streams and workspace slots)
+constexpr int kInFlight = 3;
 constexpr int kDefaultBlock = 128;
 constexpr int kDefaultGridMult = 8;
 constexpr int kStackLds = 16;
@@ -63,11 +65,11 @@ struct pt_ctx {
     size_t event_next = 0;
     // last frame: device counters and what is needed to turn them into
     // per-stage work items and bytes
-    // frames in flight (pt_render_frames): two internal streams and their
+    // frames in flight (pt_render_frames): internal streams and their
     // events, created on first use
     bool aux_ready = false;
-    hipStream_t aux[2] = {nullptr, nullptr};
-    hipEvent_t ev_entry = nullptr, ev_stage[2] = {nullptr, nullptr}, ev_acc[2] = {nullptr, nullptr};
+    hipStream_t aux[kInFlight] = {};
+    hipEvent_t ev_entry = nullptr, ev_stage[kInFlight] = {}, ev_acc[kInFlight] = {};
     uint32_t* last_counts = nullptr;
     unsigned long long* last_trav = nullptr;
     int last_ncounts = 0, last_D = 0, last_kind = 0;  // kind: 0 megakernel, 1 wavefront, 2 adjoint
@@ -334,7 +336,7 @@ pt_status pt_destroy(pt_ctx* c) {
         (void)hipSetDevice(c->device);
         for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
         if (c->aux_ready) {
-            for (int i = 0; i < 2; ++i) {
+            for (int i = 0; i < kInFlight; ++i) {
                 (void)hipStreamDestroy(c->aux[i]);
                 (void)hipEventDestroy(c->ev_stage[i]);
                 (void)hipEventDestroy(c->ev_acc[i]);
@@ -538,7 +540,7 @@ pt_status pt_frames_workspace_size(pt_ctx* c, const pt_render_args* a, uint64_t*
     Launch L;
     pt_status st = launch_config(c, a, L);
     if (st) return st;
-    *bytes = 2 * frame_slot_bytes(c, layout(c, a, L));
+    *bytes = kInFlight * frame_slot_bytes(c, layout(c, a, L));
     return PT_OK;
 }
 
@@ -557,10 +559,10 @@ pt_status pt_render_frames(pt_ctx* c, const pt_render_args* a, int32_t n_frames,
     if (st) return st;
     const WsLayout w = layout(c, a, L);
     const size_t slot = frame_slot_bytes(c, w);
-    if (ws_bytes < 2 * slot) return fail(PT_ENOMEM, "workspace too small (pt_frames_workspace_size)");
+    if (ws_bytes < kInFlight * slot) return fail(PT_ENOMEM, "workspace too small (pt_frames_workspace_size)");
     PT_HIP(hipSetDevice(c->device), "hipSetDevice");
     if (!c->aux_ready) {
-        for (int i = 0; i < 2; ++i) {
+        for (int i = 0; i < kInFlight; ++i) {
             PT_HIP(hipStreamCreateWithFlags(&c->aux[i], hipStreamNonBlocking), "create stream");
             PT_HIP(hipEventCreateWithFlags(&c->ev_stage[i], hipEventDisableTiming), "create event");
             PT_HIP(hipEventCreateWithFlags(&c->ev_acc[i], hipEventDisableTiming), "create event");
@@ -574,10 +576,10 @@ pt_status pt_render_frames(pt_ctx* c, const pt_render_args* a, int32_t n_frames,
     // everything the caller enqueued before (scene, parameters, outputs)
     // precedes both internal streams
     PT_HIP(hipEventRecord(c->ev_entry, s), "record event");
-    for (int i = 0; i < 2; ++i) PT_HIP(hipStreamWaitEvent(c->aux[i], c->ev_entry, 0), "stream wait");
+    for (int i = 0; i < kInFlight; ++i) PT_HIP(hipStreamWaitEvent(c->aux[i], c->ev_entry, 0), "stream wait");
     const uint32_t npix = (uint32_t)c->cam.W * (uint32_t)c->cam.H;
     for (int32_t f = 0; f < n_frames; ++f) {
-        const int k = f & 1;
+        const int k = f % kInFlight;
         char* base = static_cast<char*>(ws) + k * slot;
         float* frame_img = reinterpret_cast<float*>(base + w.total);
         pt_render_args af = *a;

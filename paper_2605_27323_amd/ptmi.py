@@ -267,7 +267,7 @@ class Renderer(Context):
         return out
 
     def render_frames(self, n_frames, out=None, accum=None, **kw):
-        """Render frames kw['frame'] .. + n_frames - 1 with two frames in flight
+        """Render frames kw['frame'] .. + n_frames - 1 with three frames in flight
         (pt_render_frames); returns the image tensor (the last frame's image)."""
         import torch
         a = self.args(**kw)

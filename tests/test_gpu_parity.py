@@ -222,7 +222,7 @@ def test_profile_stage_times():
 
 @pytest.mark.parametrize("mode", ["wave", "mega"])
 def test_frames_in_flight_match_sequential(mode):
-    """pt_render_frames (two frames in flight on internal streams) gives the
+    """pt_render_frames (three frames in flight on internal streams) gives the
     same running average and last image, bit for bit, as frame-by-frame
     rendering."""
     scene, cam = scenes.procedural(seed=52, n_objects=30, width=64, height=40)
