@@ -216,34 +216,6 @@ PT_DEV bool tri_intersect(const Ray& r, f3 v0, f3 v1, f3 v2, float& t, float& b1
     return true;
 }
 
-// Conservative slab test of the four children of a node against (0, tlim]:
-// entry <= exit * (1 + 2^-16), with t = (b - o) / d (relative error only,
-// covered by the slack).  Writes the entry distances; returns a 4-bit hit
-// mask.  Empty slots are masked out by their reference: their +inf boxes
-// alone would pass when every direction component is positive and tlim is
-// +inf (inf <= inf).
-PT_DEV unsigned slab4(const Ray& r, const float4 q[7], float tlim, float tn[4]) {
-    const float* lox = &q[0].x;
-    const float* hix = &q[1].x;
-    const float* loy = &q[2].x;
-    const float* hiy = &q[3].x;
-    const float* loz = &q[4].x;
-    const float* hiz = &q[5].x;
-    unsigned mask = 0;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        float ax = (lox[c] - r.o.x) * r.inv.x, bx = (hix[c] - r.o.x) * r.inv.x;
-        float ay = (loy[c] - r.o.y) * r.inv.y, by = (hiy[c] - r.o.y) * r.inv.y;
-        float az = (loz[c] - r.o.z) * r.inv.z, bz = (hiz[c] - r.o.z) * r.inv.z;
-        float t0 = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), 0.0f));
-        float t1 = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), tlim));
-        tn[c] = t0;
-        const float cref = c == 0 ? q[6].x : (c == 1 ? q[6].y : (c == 2 ? q[6].z : q[6].w));
-        if (t0 <= t1 * kBoxSlack && f2u(cref) != kEmptyRef) mask |= 1u << c;
-    }
-    return mask;
-}
-
 // ---------------------------------------------------------------------------
 // traversal stack: per-lane entries in LDS (stride = block size, so the 64
 // lanes of a wave hit 64 consecutive 8-byte words), deeper entries spill to
@@ -322,11 +294,53 @@ struct Hit {
     uint32_t id;    // input id (tie-break)
 };
 
-PT_DEV void load_node(const float4* __restrict__ nodes, uint32_t idx, float4 q[8]) {
+// load a node with its child planes ordered near/far along the ray:
+// q = near_x, far_x, near_y, far_y, near_z, far_z, refs
+PT_DEV void load_node_nf(const float4* __restrict__ nodes, uint32_t idx, const Ray& r, float4 q[8]) {
     const float4* p = nodes + (size_t)idx * 8;
-#pragma unroll
-    for (int i = 0; i < 7; ++i) q[i] = p[i];
+    const uint32_t sx = f2u(r.inv.x) >> 31, sy = f2u(r.inv.y) >> 31, sz = f2u(r.inv.z) >> 31;
+    q[0] = p[sx];
+    q[1] = p[1u - sx];
+    q[2] = p[2u + sy];
+    q[3] = p[3u - sy];
+    q[4] = p[4u + sz];
+    q[5] = p[5u - sz];
+    q[6] = p[6];
 }
+
+// Conservative slab test of the four children of a node against (0, tlim]:
+// entry <= exit * (1 + 2^-16), with t = (b - o) / d (relative error only,
+// covered by the slack).  Writes the entry distances; returns a 4-bit hit
+// mask.  Empty slots are masked out by their reference: their +inf boxes
+// alone would pass when every direction component is positive and tlim is
+// +inf (inf <= inf).
+// The planes come ordered near/far along the ray (load_node_nf), so the
+// entry and exit distances per axis need no min/max: they are the min and
+// max of the two plane distances.  A NaN distance (a ray lying in a plane
+// with a zero direction component) is ignored by fmaxf / fminf, which keeps
+// the test conservative.
+PT_DEV unsigned slab4_nf(const Ray& r, const float4 q[7], float tlim, float tn[4]) {
+    const float* nx = &q[0].x;
+    const float* fx = &q[1].x;
+    const float* ny = &q[2].x;
+    const float* fy = &q[3].x;
+    const float* nz = &q[4].x;
+    const float* fz = &q[5].x;
+    unsigned mask = 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        float ax = (nx[c] - r.o.x) * r.inv.x, bx = (fx[c] - r.o.x) * r.inv.x;
+        float ay = (ny[c] - r.o.y) * r.inv.y, by = (fy[c] - r.o.y) * r.inv.y;
+        float az = (nz[c] - r.o.z) * r.inv.z, bz = (fz[c] - r.o.z) * r.inv.z;
+        float t0 = fmaxf(fmaxf(ax, ay), fmaxf(az, 0.0f));
+        float t1 = fminf(fminf(bx, by), fminf(bz, tlim));
+        tn[c] = t0;
+        const float cref = c == 0 ? q[6].x : (c == 1 ? q[6].y : (c == 2 ? q[6].z : q[6].w));
+        if (t0 <= t1 * kBoxSlack && f2u(cref) != kEmptyRef) mask |= 1u << c;
+    }
+    return mask;
+}
+
 
 // sort four (ref, t) pairs by t (ascending), invalid entries (t = +inf)
 // last; a select network, no branches
@@ -377,9 +391,9 @@ PT_DEV bool closest_step(const SceneView& sc, const Ray& r, float tmax, Hit& h, 
         if (ref < (uint32_t)sc.n_nodes) {
             if constexpr (COUNT) ++st.nodes;
             float4 q[8];
-            load_node(sc.nodes, ref, q);
+            load_node_nf(sc.nodes, ref, r, q);
             float tn[4];
-            unsigned m = slab4(r, q, h.t, tn);
+            unsigned m = slab4_nf(r, q, h.t, tn);
             if (m) {
                 uint32_t rr[4];
                 float tt[4];
@@ -455,9 +469,9 @@ PT_DEV bool any_step(const SceneView& sc, const Ray& r, float tmax, uint32_t& re
         if (ref < (uint32_t)sc.n_nodes) {
             if constexpr (COUNT) ++st.nodes;
             float4 q[8];
-            load_node(sc.nodes, ref, q);
+            load_node_nf(sc.nodes, ref, r, q);
             float tn[4];
-            unsigned m = slab4(r, q, tmax, tn);
+            unsigned m = slab4_nf(r, q, tmax, tn);
             if (m) {
                 // descend into the first hit child, push the others
                 const uint32_t cr[4] = {f2u(q[6].x), f2u(q[6].y), f2u(q[6].z), f2u(q[6].w)};
