@@ -35,9 +35,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic(kernel):
-    """HBM bytes per dispatch of `kernel` from the committed rocprofv3 counter
-    summary, or None when the kernel sources changed since it was taken."""
+def measured_traffic(kernel, field="hbm_bytes_per_dispatch"):
+    """HBM bytes per dispatch of `kernel` (or another recorded field) from the
+    committed rocprofv3 counter summary, or None when the kernel sources
+    changed since it was taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_extend_procedural1M_1080p.json")
     if not os.path.exists(path):
@@ -49,7 +50,7 @@ def measured_traffic(kernel):
     if h.hexdigest()[:16] != prof["source_hash"]:
         return None
     k = prof["kernels"].get(kernel)
-    return k["hbm_bytes_per_dispatch"] if k else None
+    return k.get(field) if k else None
 
 
 def cpu_baseline(scene, cam, budget_s=12.0):
@@ -235,6 +236,9 @@ def main():
         achieved = per_launch_flops / (dom_avg_ms * 1e-3) / 1e12
         roofline = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "flops_per_launch": per_launch_flops,
+                    # wave64 VALU instructions issued per CU cycle (1.0 = the non-packed issue limit)
+                    "valu_issue_per_cu_cycle": measured_traffic(kname, "valu_per_cu_cycle"),
+                    "l2_hit_rate": measured_traffic(kname, "l2_hit_rate"),
                     "node_visits_per_frame": nodes.get(dom, 0) / args.steps,
                     "tri_tests_per_frame": tris.get(dom, 0) / args.steps, **common}
     else:

@@ -224,7 +224,8 @@ struct Collapser {
         }
         Node4& q = out[idx];
         for (int s = 0; s < 4; ++s) {
-            q.lox[s] = q.hix[s] = q.loy[s] = q.hiy[s] = q.loz[s] = q.hiz[s] = INFINITY;
+            q.lox[s] = q.loy[s] = q.loz[s] = INFINITY;  // empty slot: an inverted box no ray enters
+            q.hix[s] = q.hiy[s] = q.hiz[s] = -INFINITY;
             q.ref[s] = kEmptyRef;
             q.pad[s] = 0;
         }
@@ -283,7 +284,8 @@ BuildResult build_scene(const std::vector<float>& tri_v, const std::vector<int32
     if (nt == 0) {
         Node4& q = r.nodes[0];
         for (int s = 0; s < 4; ++s) {
-            q.lox[s] = q.hix[s] = q.loy[s] = q.hiy[s] = q.loz[s] = q.hiz[s] = INFINITY;
+            q.lox[s] = q.loy[s] = q.loz[s] = INFINITY;  // empty slot: an inverted box no ray enters
+            q.hix[s] = q.hiy[s] = q.hiz[s] = -INFINITY;
             q.ref[s] = kEmptyRef;
             q.pad[s] = 0;
         }
@@ -295,7 +297,8 @@ BuildResult build_scene(const std::vector<float>& tri_v, const std::vector<int32
             // a single leaf: wrap it in a root node with one child
             Node4& q = r.nodes[0];
             for (int s = 0; s < 4; ++s) {
-                q.lox[s] = q.hix[s] = q.loy[s] = q.hiy[s] = q.loz[s] = q.hiz[s] = INFINITY;
+                q.lox[s] = q.loy[s] = q.loz[s] = INFINITY;  // empty slot: an inverted box no ray enters
+                q.hix[s] = q.hiy[s] = q.hiz[s] = -INFINITY;
                 q.ref[s] = kEmptyRef;
                 q.pad[s] = 0;
             }

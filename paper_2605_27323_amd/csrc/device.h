@@ -311,9 +311,9 @@ PT_DEV void load_node_nf(const float4* __restrict__ nodes, uint32_t idx, const R
 // Conservative slab test of the four children of a node against (0, tlim]:
 // entry <= exit * (1 + 2^-16), with t = (b - o) / d (relative error only,
 // covered by the slack).  Writes the entry distances; returns a 4-bit hit
-// mask.  Empty slots are masked out by their reference: their +inf boxes
-// alone would pass when every direction component is positive and tlim is
-// +inf (inf <= inf).
+// mask.  Empty slots hold an inverted box (lo = +inf, hi = -inf: entry
+// +inf, exit -inf for every direction) and are also masked out by their
+// reference.
 // The planes come ordered near/far along the ray (load_node_nf), so the
 // entry and exit distances per axis need no min/max: they are the min and
 // max of the two plane distances.  A NaN distance (a ray lying in a plane
