@@ -60,26 +60,48 @@ def cpu_baseline(scene, cam, budget_s=12.0):
     import numpy as np
 
     import oracle
-    threads = os.cpu_count() or 1
+    # the host's share of cores (at most 16: the GPU machine's CPU share)
+    threads = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()))
     t0 = time.perf_counter()
     S = oracle.Scene(scene)
     build_s = time.perf_counter() - t0
     npix = W * H
-    done = 0
-    frame = 0
-    t0 = time.perf_counter()
-    chunk = 262144
-    while time.perf_counter() - t0 < budget_s and frame < 1000:
-        first = done % npix
-        px = np.arange(first, min(npix, first + chunk), dtype=np.int32)
-        S.render(cam, pixels=px, spp=SPP, max_depth=DEPTH, seed=0, frame=frame, rr_start=RR, threads=threads)
-        done += px.size
-        if done % npix == 0:
-            frame += 1
-    dt = time.perf_counter() - t0
+
+    def run(nthreads, budget, chunk):
+        done, frame = 0, 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget and frame < 1000:
+            first = done % npix
+            px = np.arange(first, min(npix, first + chunk), dtype=np.int32)
+            S.render(cam, pixels=px, spp=SPP, max_depth=DEPTH, seed=0, frame=frame, rr_start=RR, threads=nthreads)
+            done += px.size
+            if done % npix == 0:
+                frame += 1
+        return done, frame, time.perf_counter() - t0
+
+    done, frame, dt = run(threads, budget_s, 262144)
+    done1, _, dt1 = run(1, 3.0, 16384)
     return {"value": done * SPP / dt, "unit": "path-samples/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} paths = {done / npix:.2f} frames of the {W}x{H} 1-spp workload (frames 0..{frame}), "
-                      f"{dt:.1f} s render on {threads} threads, BVH build {build_s:.1f} s excluded"}
+                      f"{dt:.1f} s render on {threads} threads, BVH build {build_s:.1f} s excluded",
+            "single_thread": {"value": done1 * SPP / dt1, "sample": f"first {done1} paths of frame 0, {dt1:.1f} s"}}
+
+
+def copy_ceiling(torch):
+    """Measured device-to-device copy bandwidth (1 GiB read + 1 GiB written
+    per copy): the HBM ceiling the streaming stages can reach."""
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / 5
+    del a, b
+    return {"value": 2 * (1 << 30) / dt / 1e9, "unit": "GB/s", "bytes_per_copy": 2 * (1 << 30)}
 
 
 def main():
@@ -287,6 +309,7 @@ def main():
                          "with RT cores, A Beautiful Game scene",
     }
 
+    out["hbm_copy_ceiling"] = copy_ceiling(torch)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_bench(ptmi, scenes, scene, torch, args)
 
