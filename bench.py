@@ -365,7 +365,8 @@ def batch_bench(args):
 def divergence_bench(args):
     """~10M triangles, 64 material ids (Lambertian, conductor, rough
     dielectric, emissive), 1920x1080, 4 spp, depth 16, roulette from 3:
-    megakernel, wavefront, wavefront with material sort."""
+    megakernel, wavefront, wavefront with the material sort, the ray sort,
+    and the wavefront and megakernel with three frames in flight."""
     import torch
 
     from paper_2605_27323_amd import ptmi, scenes
@@ -378,8 +379,12 @@ def divergence_bench(args):
     img = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
     res = {}
     k = max(2, args.steps // 8)
-    for name, extra in [("mega", dict(mode="mega")), ("wave", dict(mode="wave")),
-                        ("wave_sorted", dict(mode="wave", flags=ptmi.FLAG_SORT_MATERIAL, sort_threshold=1 << 16))]:
+    wave = dict(FIXED_PARAMS["wave"])
+    mega = dict(FIXED_PARAMS["mega"])
+    runs = [("mega", dict(mode="mega", **mega)), ("wave", dict(mode="wave", **wave)),
+            ("wave_material_sort", dict(mode="wave", flags=ptmi.FLAG_SORT_MATERIAL, sort_threshold=1 << 16, **wave)),
+            ("wave_ray_sort", dict(mode="wave", flags=ptmi.FLAG_SORT_RAYS, sort_threshold=1 << 16, **wave))]
+    for name, extra in runs:
         R.render(out=img, frame=0, **kw, **extra)
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -389,12 +394,22 @@ def divergence_bench(args):
         dt = (time.perf_counter() - t) / k
         res[name] = {"ms_per_frame": dt * 1e3, "path_samples_per_s": W * H * 4 / dt}
         log(f"{name}: {dt * 1e3:.2f} ms/frame")
-    out = {"metric": "path samples/s, divergence workload", "value": res["wave_sorted"]["path_samples_per_s"],
+    for name, extra in [("mega_in_flight", dict(mode="mega", **mega)), ("wave_in_flight", dict(mode="wave", **wave))]:
+        R.render_frames(2, out=img, frame=0, **kw, **extra)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        R.render_frames(k, out=img, frame=2, **kw, **extra)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / k
+        res[name] = {"ms_per_frame": dt * 1e3, "path_samples_per_s": W * H * 4 / dt}
+        log(f"{name}: {dt * 1e3:.2f} ms/frame")
+    best = max((r for r in res if r.startswith("wave")), key=lambda r: res[r]["path_samples_per_s"])
+    out = {"metric": "path samples/s, divergence workload", "value": res[best]["path_samples_per_s"],
            "unit": "path-samples/s", "n_gpus": 1, "steps": k, "warmup": 1,
-           "ms_per_step": res["wave_sorted"]["ms_per_frame"], "higher_is_better": True, "scaling": "weak",
+           "ms_per_step": res[best]["ms_per_frame"], "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"procedural {nt} triangles, 64 material ids, {W}x{H}, 4 spp, depth 16, "
-                                  f"roulette from 3"}, "schedules": res}
+                                  f"roulette from 3; best wavefront schedule: {best}"}, "schedules": res}
     print(json.dumps(out), flush=True)
 
 
