@@ -206,70 +206,73 @@ def main():
         log(f"{mode}, three frames in flight: {inflight[mode]['ms_per_step']:.3f} ms/frame, "
             f"{inflight[mode]['value'] / 1e6:.1f} M path-samples/s")
 
-    # per-stage times with HIP events on the render stream, over the same
-    # number of frames, plus ray counts, work items and algorithmic bytes
     stage_ms, launches, items, nbytes, nodes, tris = {}, {}, {}, {}, {}, {}
     rays = [0, 0]
-    for i in range(args.steps):
-        run("wave", 1, args.warmup + i, flags=ptmi.FLAG_PROFILE)
-        st = R.stats()
-        for k, v in st["stage_ms"].items():
-            stage_ms[k] = stage_ms.get(k, 0.0) + v
-            launches[k] = launches.get(k, 0) + st["launches"][k]
-        for k, v in st["items"].items():
-            items[k] = items.get(k, 0) + v
-            nbytes[k] = nbytes.get(k, 0.0) + st["bytes"][k]
-        rays[0] += st["extension_rays"]
-        rays[1] += st["shadow_rays"]
-    # the same frames again with the work-counting kernels (node visits and
-    # triangle tests; a separate, slower build, so not timed)
-    for i in range(args.steps):
-        run("wave", 1, args.warmup + i, flags=ptmi.FLAG_COUNT_WORK)
-        st = R.stats()
-        for k, v in st["node_visits"].items():
-            nodes[k] = nodes.get(k, 0) + v
-        for k, v in st["tri_tests"].items():
-            tris[k] = tris.get(k, 0) + v
-    frame_stage_ms = {k: v / args.steps for k, v in stage_ms.items()}
-    log("wavefront stage ms/frame: " + ", ".join(f"{k} {v:.3f}" for k, v in frame_stage_ms.items()))
-    ext_rays_per_frame = rays[0] / args.steps
-    sh_rays_per_frame = rays[1] / args.steps
-    # roofline of the stage kernel with the largest share of the frame.
-    # Traversal kernels (extend, shadow, tail) are bound by vector ALU issue:
-    # achieved = algorithmic flops per launch (FLOPS_PER_NODE per BVH node
-    # visit, FLOPS_PER_TRI per triangle test, counted on the device) over the
-    # mean launch time, against the fp32 vector peak.  The streaming stages
-    # use their algorithmic path-state bytes against the HBM peak.
-    dom = max(stage_ms, key=stage_ms.get)
-    lds = tuned["wave"].get("stack_lds", 16)
-    kname = {"extend": f"ptmi::k_extend<{lds}, false>", "shade": "ptmi::k_shade",
-             "shadow": f"ptmi::k_shadow<{lds}, false>", "tail": f"ptmi::k_shade_tail<{lds}, false>",
-             "raygen": "ptmi::k_raygen", "accumulate": "ptmi::k_accumulate", "sort": "ptmi::k_sort_*"}[dom]
-    dom_avg_ms = stage_ms[dom] / launches[dom]
-    per_launch_bytes = nbytes.get(dom, 0.0) / launches[dom]
-    state_gbs = per_launch_bytes / (dom_avg_ms * 1e-3) / 1e9
-    common = {"kernel": kname, "traffic": measured_traffic(kname), "avg_launch_ms": dom_avg_ms,
-              "launches_per_frame": launches[dom] / args.steps, "items_per_frame": items.get(dom, 0) / args.steps,
-              "stage_share": stage_ms[dom] / sum(stage_ms.values()), "state_bytes_per_launch": per_launch_bytes,
-              "state_gbs": state_gbs}
-    if dom in ("extend", "shadow", "tail"):
-        flops = FLOPS_PER_NODE * nodes.get(dom, 0) + FLOPS_PER_TRI * tris.get(dom, 0)
-        per_launch_flops = flops / launches[dom]
-        achieved = per_launch_flops / (dom_avg_ms * 1e-3) / 1e12
-        roofline = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "flops_per_launch": per_launch_flops,
-                    # wave64 VALU instructions issued per CU cycle (1.0 = the non-packed issue limit)
-                    "valu_issue_per_cu_cycle": measured_traffic(kname, "valu_per_cu_cycle"),
-                    "l2_hit_rate": measured_traffic(kname, "l2_hit_rate"),
-                    "node_visits_per_frame": nodes.get(dom, 0) / args.steps,
-                    "tri_tests_per_frame": tris.get(dom, 0) / args.steps, **common}
-    else:
-        roofline = {"bound": "hbm", "achieved": state_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": state_gbs / HBM_PEAK_GBS, "bytes_per_launch": per_launch_bytes, **common}
-    state_bytes = sum(nbytes.values()) / args.steps
-    state_floor = {"bytes_per_frame": state_bytes,
-                   "frac_of_frame": (state_bytes / (res["wave"]["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS)
-                   if "wave" in res else None}
+    roofline, state_floor, frame_stage_ms = None, None, {}
+    ext_rays_per_frame = sh_rays_per_frame = 0.0
+    if "wave" in modes:
+        # per-stage times with HIP events on the render stream, over the same
+        # number of frames, plus ray counts, work items and algorithmic bytes
+        for i in range(args.steps):
+            run("wave", 1, args.warmup + i, flags=ptmi.FLAG_PROFILE)
+            st = R.stats()
+            for k, v in st["stage_ms"].items():
+                stage_ms[k] = stage_ms.get(k, 0.0) + v
+                launches[k] = launches.get(k, 0) + st["launches"][k]
+            for k, v in st["items"].items():
+                items[k] = items.get(k, 0) + v
+                nbytes[k] = nbytes.get(k, 0.0) + st["bytes"][k]
+            rays[0] += st["extension_rays"]
+            rays[1] += st["shadow_rays"]
+        # the same frames again with the work-counting kernels (node visits and
+        # triangle tests; a separate, slower build, so not timed)
+        for i in range(args.steps):
+            run("wave", 1, args.warmup + i, flags=ptmi.FLAG_COUNT_WORK)
+            st = R.stats()
+            for k, v in st["node_visits"].items():
+                nodes[k] = nodes.get(k, 0) + v
+            for k, v in st["tri_tests"].items():
+                tris[k] = tris.get(k, 0) + v
+        frame_stage_ms = {k: v / args.steps for k, v in stage_ms.items()}
+        log("wavefront stage ms/frame: " + ", ".join(f"{k} {v:.3f}" for k, v in frame_stage_ms.items()))
+        ext_rays_per_frame = rays[0] / args.steps
+        sh_rays_per_frame = rays[1] / args.steps
+        # roofline of the stage kernel with the largest share of the frame.
+        # Traversal kernels (extend, shadow, tail) are bound by vector ALU issue:
+        # achieved = algorithmic flops per launch (FLOPS_PER_NODE per BVH node
+        # visit, FLOPS_PER_TRI per triangle test, counted on the device) over the
+        # mean launch time, against the fp32 vector peak.  The streaming stages
+        # use their algorithmic path-state bytes against the HBM peak.
+        dom = max(stage_ms, key=stage_ms.get)
+        lds = tuned["wave"].get("stack_lds", 16)
+        kname = {"extend": f"ptmi::k_extend<{lds}, false>", "shade": "ptmi::k_shade",
+                 "shadow": f"ptmi::k_shadow<{lds}, false>", "tail": f"ptmi::k_shade_tail<{lds}, false>",
+                 "raygen": "ptmi::k_raygen", "accumulate": "ptmi::k_accumulate", "sort": "ptmi::k_sort_*"}[dom]
+        dom_avg_ms = stage_ms[dom] / launches[dom]
+        per_launch_bytes = nbytes.get(dom, 0.0) / launches[dom]
+        state_gbs = per_launch_bytes / (dom_avg_ms * 1e-3) / 1e9
+        common = {"kernel": kname, "traffic": measured_traffic(kname), "avg_launch_ms": dom_avg_ms,
+                  "launches_per_frame": launches[dom] / args.steps, "items_per_frame": items.get(dom, 0) / args.steps,
+                  "stage_share": stage_ms[dom] / sum(stage_ms.values()), "state_bytes_per_launch": per_launch_bytes,
+                  "state_gbs": state_gbs}
+        if dom in ("extend", "shadow", "tail"):
+            flops = FLOPS_PER_NODE * nodes.get(dom, 0) + FLOPS_PER_TRI * tris.get(dom, 0)
+            per_launch_flops = flops / launches[dom]
+            achieved = per_launch_flops / (dom_avg_ms * 1e-3) / 1e12
+            roofline = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "flops_per_launch": per_launch_flops,
+                        # wave64 VALU instructions issued per CU cycle (1.0 = the non-packed issue limit)
+                        "valu_issue_per_cu_cycle": measured_traffic(kname, "valu_per_cu_cycle"),
+                        "l2_hit_rate": measured_traffic(kname, "l2_hit_rate"),
+                        "node_visits_per_frame": nodes.get(dom, 0) / args.steps,
+                        "tri_tests_per_frame": tris.get(dom, 0) / args.steps, **common}
+        else:
+            roofline = {"bound": "hbm", "achieved": state_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": state_gbs / HBM_PEAK_GBS, "bytes_per_launch": per_launch_bytes, **common}
+        state_bytes = sum(nbytes.values()) / args.steps
+        state_floor = {"bytes_per_frame": state_bytes,
+                       "frac_of_frame": (state_bytes / (res["wave"]["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS)
+                       if "wave" in res else None}
 
     head = "wave" if "wave" in inflight else "mega"
     out = {

@@ -641,6 +641,9 @@ pt_status pt_frame_stats_get(pt_ctx* c, pt_frame_stats* out) {
     std::memset(out, 0, sizeof *out);
     if (!c->last_valid) return fail(PT_ESTATE, "no frame rendered");
     PT_HIP(hipSetDevice(c->device), "hipSetDevice");
+    // frames in flight ran on the internal streams
+    if (c->aux_ready)
+        for (int i = 0; i < kInFlight; ++i) PT_HIP(hipStreamSynchronize(c->aux[i]), "stream sync");
     for (const StageTimer& t : c->timers) {
         PT_HIP(hipEventSynchronize(t.b), "event sync");
         float ms = 0.f;

@@ -952,37 +952,60 @@ PT_DEV VertexOut shade_vertex(const SceneView& sc, const PathParams& pp, uint32_
     return out;
 }
 
-// One complete camera path (megakernel body): extend, shade, and trace the
-// light-sample segment at once; counts extension and shadow rays.
+// A camera path traced vertex by vertex (megakernel): path_begin generates
+// the camera ray, path_vertex extends it to the next vertex, shades it and
+// traces the light-sample segment at once; it returns false when the path
+// has ended (its radiance is then in pr.ps.L).  Extension and shadow rays
+// are counted in n_ext / n_sh.
+struct PathRun {
+    f3 o, d;
+    PathState ps;
+    int k;
+};
+
+PT_DEV void path_begin(const CamView& cam, const PathParams& pp, uint32_t pix, uint32_t sample, PathRun& pr) {
+    Rng8 r0 = philox8(pp.seed, pix, sample, 0u, pp.job);
+    camera_ray(cam, (int)(pix % (uint32_t)cam.W), (int)(pix / (uint32_t)cam.W), unif(r0.w[0]), unif(r0.w[1]), pr.o,
+               pr.d);
+    pr.ps.beta = mk3(1.f, 1.f, 1.f);
+    pr.ps.L = mk3(0.f, 0.f, 0.f);
+    pr.ps.p_prev = 0.f;
+    pr.ps.prev_smooth = 0;
+    pr.k = 1;
+}
+
+template <int LDS, bool COUNT = false>
+PT_DEV bool path_vertex(const SceneView& sc, const PathParams& pp, uint32_t pix, uint32_t sample, PathRun& pr,
+                        TravStack<LDS, COUNT>& st, uint32_t& n_ext, uint32_t& n_sh,
+                        const LightCache& lc = no_light_cache()) {
+    Ray ray = make_ray(pr.o, pr.d);
+    Hit h = closest_hit<LDS>(sc, ray, INFINITY, st);
+    ++n_ext;
+    ShadowReq sh;
+    VertexOut vo = shade_vertex(sc, pp, pix, sample, pr.k, pr.d, h, pr.ps, sh, lc);
+    add_radiance(pr.ps, vo);
+    if (sh.valid) {
+        ++n_sh;
+        Ray sr = make_ray(sh.o, sh.d);
+        if (!any_hit<LDS>(sc, sr, kShadowTmax, st))
+            pr.ps.L = mk3(pr.ps.L.x + sh.contrib.x, pr.ps.L.y + sh.contrib.y, pr.ps.L.z + sh.contrib.z);
+    }
+    if (!vo.cont) return false;
+    pr.o = vo.o;
+    pr.d = vo.d;
+    ++pr.k;
+    return true;
+}
+
+// One complete camera path: its radiance.
 template <int LDS, bool COUNT = false>
 PT_DEV f3 trace_path(const SceneView& sc, const CamView& cam, const PathParams& pp, uint32_t pix, uint32_t sample,
                      TravStack<LDS, COUNT>& st, uint32_t& n_ext, uint32_t& n_sh, const LightCache& lc = no_light_cache()) {
-    Rng8 r0 = philox8(pp.seed, pix, sample, 0u, pp.job);
-    f3 o, d;
-    camera_ray(cam, (int)(pix % (uint32_t)cam.W), (int)(pix / (uint32_t)cam.W), unif(r0.w[0]), unif(r0.w[1]), o, d);
-    PathState ps;
-    ps.beta = mk3(1.f, 1.f, 1.f);
-    ps.L = mk3(0.f, 0.f, 0.f);
-    ps.p_prev = 0.f;
-    ps.prev_smooth = 0;
-    for (int k = 1;; ++k) {
-        Ray ray = make_ray(o, d);
-        Hit h = closest_hit<LDS>(sc, ray, INFINITY, st);
-        ++n_ext;
-        ShadowReq sh;
-        VertexOut vo = shade_vertex(sc, pp, pix, sample, k, d, h, ps, sh, lc);
-        add_radiance(ps, vo);
-        if (sh.valid) {
-            ++n_sh;
-            Ray sr = make_ray(sh.o, sh.d);
-            if (!any_hit<LDS>(sc, sr, kShadowTmax, st))
-                ps.L = mk3(ps.L.x + sh.contrib.x, ps.L.y + sh.contrib.y, ps.L.z + sh.contrib.z);
-        }
-        if (!vo.cont) break;
-        o = vo.o;
-        d = vo.d;
+    PathRun pr;
+    path_begin(cam, pp, pix, sample, pr);
+    while (path_vertex<LDS>(sc, pp, pix, sample, pr, st, n_ext, n_sh, lc)) {
     }
-    return ps.L;
+    return pr.ps.L;
 }
 
 }  // namespace ptmi

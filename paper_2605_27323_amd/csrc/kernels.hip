@@ -55,16 +55,28 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     const LightCache lc = stage_lights(sc, light_buf);
     const uint32_t npix = (uint32_t)cam.W * (uint32_t)cam.H;
     uint32_t n_ext = 0, n_sh = 0;
-    for (uint32_t pix = gtid; pix < npix; pix += nlanes) {
-        {
-            f3 sum = mk3(0.f, 0.f, 0.f);
-            for (int s = 0; s < pp.spp; ++s) {
-                const uint32_t sample = pp.frame * (uint32_t)pp.spp + (uint32_t)s;
-                f3 L = trace_path<LDS>(sc, cam, pp, pix, sample, st, n_ext, n_sh, lc);
-                sum = s == 0 ? L : add3(sum, L);
-            }
+    // One loop trip = one path vertex.  A lane whose path ends starts its
+    // next sample (or pixel) on the next trip instead of waiting for the
+    // longest path of its wave; a lane's samples still run in order, so the
+    // per-pixel sum is the same.
+    uint32_t pix = gtid, s = 0;
+    f3 sum = mk3(0.f, 0.f, 0.f);
+    PathRun pr;
+    bool started = false;
+    while (pix < npix) {
+        const uint32_t sample = pp.frame * (uint32_t)pp.spp + s;
+        if (!started) {
+            path_begin(cam, pp, pix, sample, pr);
+            started = true;
+        }
+        if (path_vertex<LDS>(sc, pp, pix, sample, pr, st, n_ext, n_sh, lc)) continue;
+        started = false;
+        sum = s == 0 ? pr.ps.L : add3(sum, pr.ps.L);
+        if (++s == (uint32_t)pp.spp) {
             const float fs = (float)pp.spp;
             store_pixel(img, acc, pix, mk3(sum.x / fs, sum.y / fs, sum.z / fs), pp.frame);
+            s = 0;
+            pix += nlanes;
         }
     }
     // ray counts: one atomic per wave for the whole kernel
