@@ -122,6 +122,7 @@ def main():
                     help="batched workload instead: 64 jobs, 10k-2M triangles each, mixed resolutions and spp")
     ap.add_argument("--divergence", action="store_true",
                     help="divergence workload instead: ~10M triangles, 64 material ids, 4 spp, depth 16")
+    ap.add_argument("--max-leaf", type=int, default=4, help="triangles per BVH leaf, 1..8")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -151,7 +152,7 @@ def main():
     t0 = time.perf_counter()
     scene, cam = scenes.procedural(seed=2, n_objects=2000, width=W, height=H)
     nt = scene["indices"].shape[0]
-    R = ptmi.Renderer(scene, cam)
+    R = ptmi.Renderer(scene, cam, max_leaf=args.max_leaf)
     log(f"scene {nt} triangles, BVH {R.info.node_count} nodes depth {R.info.depth}, "
         f"built in {R.info.build_seconds:.2f} s (setup {time.perf_counter() - t0:.1f} s)")
     kw = dict(spp=SPP, max_depth=DEPTH, rr_start=RR, nee=True, seed=0)

@@ -136,7 +136,9 @@ typedef struct {
  * bounce's shade (extend) queue is sorted only when it holds at least this
  * many paths;
  * stack_lds: traversal stack entries kept in LDS per lane, 8/16/24/32
- * (0 = default 16); deeper entries spill to the workspace;
+ * (0 = default 16); deeper entries spill to the workspace; (stack_lds + 1)
+ * x 8 bytes per thread of LDS plus 12 KiB of light table must fit one
+ * workgroup's LDS (PT_EINVAL otherwise);
  * tail_threshold: wavefront hybrid tail, a bounce whose queue holds fewer
  * than this many paths finishes them in place, megakernel style, inside the
  * shade stage (0 = off; the image is the same bit for bit). */

@@ -26,7 +26,7 @@ __global__ void __launch_bounds__(256) k_adjoint(SceneView sc, CamView cam, Path
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
     TravStack<LDS> st =
-        make_trav_stack<LDS>(reinterpret_cast<uint2*>(smem) + threadIdx.x, (int)blockDim.x, ovf + gtid, (int)nlanes, gcap);
+        make_trav_stack<LDS>(reinterpret_cast<uint2*>(smem) + threadIdx.x, (int)blockDim.x, ovf, gtid, (int)nlanes, gcap);
     AtomicAcc acc;
     const uint32_t npaths = (uint32_t)cam.W * (uint32_t)cam.H * (uint32_t)pp.spp;
     const float fs = (float)pp.spp;
@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(256) k_adjoint(SceneView sc, CamView cam, Path
 hipError_t launch_adjoint(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const CamView& cam,
                           const PathParams& pp, const float* d_img, float* g_alb, float* g_emi, uint2* ovf, int gcap,
                           uint32_t* stats, unsigned long long* trav) {
-    size_t sm = (size_t)lds * 2 * sizeof(uint32_t) * block.x;
+    size_t sm = trav_stack_lds_bytes(lds, (int)block.x);
 #define X(N)                                                                                                  \
     if (lds == N) {                                                                                           \
         hipLaunchKernelGGL(k_adjoint<N>, grid, block, sm, s, sc, cam, pp, d_img, g_alb, g_emi, ovf, gcap, stats, trav); \

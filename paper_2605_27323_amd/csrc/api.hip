@@ -50,6 +50,7 @@ struct StageTimer {
 struct pt_ctx {
     int device = -1;
     int num_cu = 256;
+    size_t lds_per_block = 160 * 1024;  // LDS a workgroup may allocate on this device
     // scene (host copy)
     bool loaded = false, built = false, bound = false, cam_set = false;
     int32_t nt = 0, nm = 0;
@@ -83,11 +84,14 @@ struct pt_ctx {
 namespace {
 
 // LDS stack entries per lane: requested (8, 16, 24, 32) or the default,
-// never more than the BVH can need
-int stack_lds_for(int requested, int need, int& out) {
+// never more than the BVH can need; the block's stacks plus the largest
+// static LDS of a traversal kernel (the light table) must fit a workgroup
+int stack_lds_for(int requested, int need, int block, size_t lds_per_block, int& out) {
     int lds = requested > 0 ? requested : kStackLds;
     if (lds != 8 && lds != 16 && lds != 24 && lds != 32) return fail(PT_EINVAL, "stack_lds must be 8, 16, 24 or 32");
     while (lds > 8 && lds - 8 >= need) lds -= 8;
+    if (trav_stack_lds_bytes(lds, block) + 3 * sizeof(uint32_t) * kLdsLights > lds_per_block)
+        return fail(PT_EINVAL, "stack_lds x block exceeds the LDS of a workgroup");
     out = lds;
     return PT_OK;
 }
@@ -105,7 +109,7 @@ pt_status launch_config(const pt_ctx* c, const pt_render_args* a, Launch& L) {
     if (L.block < 64 || L.block > 256 || (L.block % 64) != 0) return fail(PT_EINVAL, "block must be a multiple of 64 in [64, 256]");
     if (mult < 1 || mult > 64) return fail(PT_EINVAL, "grid_mult must be in [1, 64]");
     L.grid = c->num_cu * mult;
-    pt_status st = stack_lds_for(a->stack_lds, c->bvh.stack_entries, L.lds);
+    pt_status st = stack_lds_for(a->stack_lds, c->bvh.stack_entries, L.block, c->lds_per_block, L.lds);
     if (st) return st;
     L.gcap = std::max(0, c->bvh.stack_entries - L.lds);
     L.nlanes = (uint32_t)L.grid * (uint32_t)L.block;
@@ -324,6 +328,7 @@ pt_status pt_create(pt_ctx** out, int32_t device) {
             return hip_fail(e, "hipGetDeviceProperties");
         }
         c->num_cu = prop.multiProcessorCount;
+        c->lds_per_block = prop.sharedMemPerBlock;
         c->device = device;
     }
     *out = c;
@@ -725,6 +730,7 @@ struct BatchPlan {
     std::vector<JobDesc> jobs;
     uint64_t total = 0, total_pix = 0;
     int device = -1, num_cu = 256, stack_entries = 1;
+    size_t lds_per_block = 160 * 1024;
     Launch L{};
     uint32_t capacity = 0;
     int iters_per_graph = 8, use_graph = 1;
@@ -744,6 +750,7 @@ pt_status plan_batch(const pt_job* jobs, int32_t n, const pt_batch_opts* o, Batc
         if (P.device < 0) {
             P.device = jb.ctx->device;
             P.num_cu = jb.ctx->num_cu;
+            P.lds_per_block = jb.ctx->lds_per_block;
         } else if (P.device != jb.ctx->device) {
             return fail(PT_EINVAL, "all jobs of a batch must be on one device");
         }
@@ -777,7 +784,7 @@ pt_status plan_batch(const pt_job* jobs, int32_t n, const pt_batch_opts* o, Batc
     if (P.L.block < 64 || P.L.block > 256 || (P.L.block % 64) != 0) return fail(PT_EINVAL, "block must be a multiple of 64 in [64, 256]");
     if (mult < 1 || mult > 64) return fail(PT_EINVAL, "grid_mult must be in [1, 64]");
     P.L.grid = P.num_cu * mult;
-    pt_status sl = stack_lds_for(o->stack_lds, P.stack_entries, P.L.lds);
+    pt_status sl = stack_lds_for(o->stack_lds, P.stack_entries, P.L.block, P.lds_per_block, P.L.lds);
     if (sl) return sl;
     P.L.gcap = std::max(0, P.stack_entries - P.L.lds);
     P.L.nlanes = (uint32_t)P.L.grid * (uint32_t)P.L.block;

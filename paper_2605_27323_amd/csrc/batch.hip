@@ -11,8 +11,8 @@ namespace {
 
 template <int LDS>
 __device__ __forceinline__ TravStack<LDS> stack_b(uint32_t* smem, uint2* ovf, int gcap) {
-    return make_trav_stack<LDS>(reinterpret_cast<uint2*>(smem) + threadIdx.x, (int)blockDim.x,
-                                ovf + blockIdx.x * blockDim.x + threadIdx.x, (int)(gridDim.x * blockDim.x), gcap);
+    return make_trav_stack<LDS>(reinterpret_cast<uint2*>(smem) + threadIdx.x, (int)blockDim.x, ovf,
+                                blockIdx.x * blockDim.x + threadIdx.x, (int)(gridDim.x * blockDim.x), gcap);
 }
 
 // wave-aggregated job counters: every lane of the wave calls this; lanes
@@ -196,7 +196,7 @@ hipError_t launch_batch_init(hipStream_t s, const BatchBufs& bb, uint32_t total)
 // one iteration of the pool on queue parity q
 hipError_t launch_batch_iteration(int lds, dim3 grid, dim3 block, hipStream_t s, const BatchBufs& bb, int q,
                                   uint2* ovf, int gcap) {
-    const size_t sm = (size_t)lds * 2 * sizeof(uint32_t) * block.x;
+    const size_t sm = trav_stack_lds_bytes(lds, (int)block.x);
     hipLaunchKernelGGL(k_batch_sched, dim3(1), dim3(64), 0, s, bb, q);
     hipLaunchKernelGGL(k_batch_regen, grid, block, 0, s, bb, q);
 #define X(N)                                                                              \

@@ -262,7 +262,9 @@ BuildResult build_scene(const std::vector<float>& tri_v, const std::vector<int32
         }
     }
     // boxes are padded by 2^-18 of the largest coordinate so that the slab
-    // test can never reject a triangle the watertight test accepts
+    // test can never reject a triangle the watertight test accepts: the
+    // padding absorbs the test's absolute rounding (a few ulps of the
+    // coordinates), its relative slack the rest
     const float pad = M * 0x1p-18f;
     r.max_coord = M;
     if (nt > 0) {

@@ -146,17 +146,30 @@ PT_DEV void camera_ray(const CamView& cam, int px, int py, float u0, float u1, f
 // ---------------------------------------------------------------------------
 struct Ray {
     f3 o, d;
-    f3 inv;  // 1/d for the slab test, zero components replaced by 2^-80
-    int kx, ky, kz;
+    f3 inv;  // 1/d for the slab test, components below 2^-80 in magnitude replaced by +-2^-80
+    f3 oi;   // o * inv, rounded: slab distances are p * inv - oi, one fused multiply-add
+    uint32_t k;  // axis permutation of the watertight test: kx | ky << 2 | kz << 4
     float Sx, Sy, Sz;
 };
 
+// The slab test evaluates the distance to a plane at coordinate p as
+// RN(p * inv - RN(o * inv)).  Its error beyond the relative rounding of
+// the result is the rounding of o * inv, at most 2^-24 |o_a inv_a|; with
+// |o_a| <= |p_a - o_a| + |p_a| this is at most 2^-24 of the plane's own
+// distance (relative, covered by kBoxSlack) plus 2^-24 |p_a| in position,
+// far inside the builder's padding of every box by 2^-18 of the largest
+// vertex coordinate.  A direction component below 2^-80 is replaced by
+// +-2^-80: over any hit distance the ray moves far less than the padding
+// along that axis, so the smaller inverse keeps every distance's sign and
+// leaves the test conservative.
 PT_DEV Ray make_ray(f3 o, f3 d) {
     Ray r;
     r.o = o;
     r.d = d;
-    r.inv = mk3(1.0f / (d.x != 0.0f ? d.x : 0x1p-80f), 1.0f / (d.y != 0.0f ? d.y : 0x1p-80f),
-                1.0f / (d.z != 0.0f ? d.z : 0x1p-80f));
+    r.inv = mk3(1.0f / (fabsf(d.x) >= 0x1p-80f ? d.x : copysignf(0x1p-80f, d.x)),
+                1.0f / (fabsf(d.y) >= 0x1p-80f ? d.y : copysignf(0x1p-80f, d.y)),
+                1.0f / (fabsf(d.z) >= 0x1p-80f ? d.z : copysignf(0x1p-80f, d.z)));
+    r.oi = mk3(o.x * r.inv.x, o.y * r.inv.y, o.z * r.inv.z);
     float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
     int kz = 0;
     float m = ax;
@@ -173,9 +186,7 @@ PT_DEV Ray make_ray(f3 o, f3 d) {
         kx = ky;
         ky = t;
     }
-    r.kx = kx;
-    r.ky = ky;
-    r.kz = kz;
+    r.k = (uint32_t)kx | ((uint32_t)ky << 2) | ((uint32_t)kz << 4);
     r.Sx = comp3(d, kx) / dkz;
     r.Sy = comp3(d, ky) / dkz;
     r.Sz = 1.0f / dkz;
@@ -184,14 +195,15 @@ PT_DEV Ray make_ray(f3 o, f3 d) {
 
 // Returns true on a hit with t > 0; t and the barycentrics of v1, v2.
 PT_DEV bool tri_intersect(const Ray& r, f3 v0, f3 v1, f3 v2, float& t, float& b1, float& b2) {
+    const int kx = (int)(r.k & 3u), ky = (int)((r.k >> 2) & 3u), kz = (int)(r.k >> 4);
     f3 A = sub3(v0, r.o), B = sub3(v1, r.o), C = sub3(v2, r.o);
-    float Akz = comp3(A, r.kz), Bkz = comp3(B, r.kz), Ckz = comp3(C, r.kz);
-    float Ax = comp3(A, r.kx) - r.Sx * Akz;
-    float Ay = comp3(A, r.ky) - r.Sy * Akz;
-    float Bx = comp3(B, r.kx) - r.Sx * Bkz;
-    float By = comp3(B, r.ky) - r.Sy * Bkz;
-    float Cx = comp3(C, r.kx) - r.Sx * Ckz;
-    float Cy = comp3(C, r.ky) - r.Sy * Ckz;
+    float Akz = comp3(A, kz), Bkz = comp3(B, kz), Ckz = comp3(C, kz);
+    float Ax = comp3(A, kx) - r.Sx * Akz;
+    float Ay = comp3(A, ky) - r.Sy * Akz;
+    float Bx = comp3(B, kx) - r.Sx * Bkz;
+    float By = comp3(B, ky) - r.Sy * Bkz;
+    float Cx = comp3(C, kx) - r.Sx * Ckz;
+    float Cy = comp3(C, ky) - r.Sy * Ckz;
     float U = Cx * By - Cy * Bx;
     float V = Ax * Cy - Ay * Cx;
     float W = Bx * Ay - By * Ax;
@@ -222,20 +234,38 @@ PT_DEV bool tri_intersect(const Ray& r, f3 v0, f3 v1, f3 v2, float& t, float& b1
 // a per-lane global area (stride = number of lanes).  The LDS pointer
 // carries the local address space so that pushes and pops compile to
 // ds_write_b64 / ds_read_b64 rather than flat accesses.
+//
+// Each lane owns LDS + 1 LDS entries: entry LDS is a discard slot.  A node
+// visit pushes its (up to three) farther children with push3, which writes
+// all three candidates without branches, the invalid ones into the discard
+// slot, as long as no lane of the wave is within three entries of the LDS
+// limit (a wave-uniform test); otherwise it takes the per-entry path that
+// spills to global memory.
 // ---------------------------------------------------------------------------
 #if defined(__HIP_DEVICE_COMPILE__)
 typedef __attribute__((address_space(3))) uint2 lds_uint2;
 // product of two values below 2^24 (full-rate 24-bit multiply on the GPU)
 __device__ __forceinline__ uint32_t mul24(uint32_t a, uint32_t b) { return __umul24(a, b); }
+// true when the condition holds on no active lane of the wave
+__device__ __forceinline__ bool wave_none(bool c) { return __ballot(c) == 0ull; }
 #else
 typedef uint2 lds_uint2;
 inline uint32_t mul24(uint32_t a, uint32_t b) { return (a & 0xFFFFFFu) * (b & 0xFFFFFFu); }
+inline bool wave_none(bool c) { return !c; }
 #endif
+
+// LDS bytes of a block's traversal stacks: LDS entries plus the discard slot
+// per lane, 8 bytes each
+PT_DEV constexpr size_t trav_stack_lds_bytes(int lds, int block) {
+    return (size_t)(lds + 1) * sizeof(uint2) * (size_t)block;
+}
 
 template <int LDS, bool COUNT = false>
 struct TravStack {
+    static_assert(LDS >= 3, "push3 needs at least three LDS entries");
     lds_uint2* lds;  // (reference, entry distance bits), one 64-bit LDS access per push / pop
-    uint2* gbl;
+    uint2* gbl;      // spill area of all lanes (uniform); this lane's entry LDS + k is gbl[glane + k * gstride]
+    uint32_t glane;
     int lstride;
     int gstride;
     int gcap;
@@ -248,38 +278,63 @@ struct TravStack {
         if (sp < LDS) {
             lds[mul24((uint32_t)sp, (uint32_t)lstride)] = e;
         } else if (sp - LDS < gcap) {
-            gbl[(size_t)(sp - LDS) * (uint32_t)gstride] = e;
+            gbl[glane + (size_t)(sp - LDS) * (uint32_t)gstride] = e;
         } else {
             overflow = true;
             return;
         }
         ++sp;
     }
+    // push e0, e1, e2 in this order, each only where its flag is set
+    PT_DEV void push3(uint2 e0, bool v0, uint2 e1, bool v1, uint2 e2, bool v2) {
+        if (wave_none(sp > LDS - 3)) {
+            uint32_t s = (uint32_t)sp;
+            const uint32_t a0 = v0 ? s : (uint32_t)LDS;
+            s += v0 ? 1u : 0u;
+            const uint32_t a1 = v1 ? s : (uint32_t)LDS;
+            s += v1 ? 1u : 0u;
+            const uint32_t a2 = v2 ? s : (uint32_t)LDS;
+            s += v2 ? 1u : 0u;
+            lds[mul24(a0, (uint32_t)lstride)] = e0;
+            lds[mul24(a1, (uint32_t)lstride)] = e1;
+            lds[mul24(a2, (uint32_t)lstride)] = e2;
+            sp = (int)s;
+        } else {
+            if (v0) push(e0.x, u2f(e0.y));
+            if (v1) push(e1.x, u2f(e1.y));
+            if (v2) push(e2.x, u2f(e2.y));
+        }
+    }
     PT_DEV void pop(uint32_t& ref, float& t) {
         --sp;
-        if (sp < LDS) {
-            const uint2 e = lds[mul24((uint32_t)sp, (uint32_t)lstride)];
-            ref = e.x;
-            t = u2f(e.y);
+        uint2 e;
+        if (wave_none(sp >= LDS)) {
+            e = lds[mul24((uint32_t)sp, (uint32_t)lstride)];
+        } else if (sp < LDS) {
+            e = lds[mul24((uint32_t)sp, (uint32_t)lstride)];
         } else {
             // a distinct load kind keeps the compiler from merging the two
             // branches into one flat load through a selected pointer
-            const uint64_t e = __builtin_nontemporal_load(
-                reinterpret_cast<const uint64_t*>(gbl + (size_t)(sp - LDS) * (uint32_t)gstride));
-            ref = (uint32_t)e;
-            t = u2f((uint32_t)(e >> 32));
+            const uint64_t g = __builtin_nontemporal_load(
+                reinterpret_cast<const uint64_t*>(gbl + glane + (size_t)(sp - LDS) * (uint32_t)gstride));
+            e = make_uint2((uint32_t)g, (uint32_t)(g >> 32));
         }
+        ref = e.x;
+        t = u2f(e.y);
     }
 };
 
-// lds_lane: this lane's first LDS entry (entry k at lds_lane[k * lstride]);
-// gbl_lane: its first spill entry (entry LDS + k at gbl_lane[k * gstride])
+// lds_lane: this lane's first LDS entry (entry k at lds_lane[k * lstride],
+// k = 0 .. LDS, the last one the discard slot);
+// gbl: the spill area, where this lane's entry LDS + k is gbl[glane + k * gstride]
 template <int LDS, bool COUNT = false>
-PT_DEV TravStack<LDS, COUNT> make_trav_stack(uint2* lds_lane, int lstride, uint2* gbl_lane, int gstride, int gcap) {
+PT_DEV TravStack<LDS, COUNT> make_trav_stack(uint2* lds_lane, int lstride, uint2* gbl, uint32_t glane, int gstride,
+                                             int gcap) {
     TravStack<LDS, COUNT> st;
     st.lds = (lds_uint2*)lds_lane;
     st.lstride = lstride;
-    st.gbl = gbl_lane;
+    st.gbl = gbl;
+    st.glane = glane;
     st.gstride = gstride;
     st.gcap = gcap;
     st.sp = 0;
@@ -309,16 +364,15 @@ PT_DEV void load_node_nf(const float4* __restrict__ nodes, uint32_t idx, const R
 }
 
 // Conservative slab test of the four children of a node against (0, tlim]:
-// entry <= exit * (1 + 2^-16), with t = (b - o) / d (relative error only,
-// covered by the slack).  Writes the entry distances; returns a 4-bit hit
-// mask.  Empty slots hold an inverted box (lo = +inf, hi = -inf: entry
-// +inf, exit -inf for every direction) and are also masked out by their
-// reference.
+// entry <= exit * (1 + 2^-16), one fused multiply-add per plane (make_ray
+// bounds its error).  Writes the entry
+// distances; returns a 4-bit hit mask.  Empty slots hold an inverted box
+// (lo = +inf, hi = -inf: entry +inf, exit -inf for every direction) and are
+// also masked out by their reference.
 // The planes come ordered near/far along the ray (load_node_nf), so the
 // entry and exit distances per axis need no min/max: they are the min and
-// max of the two plane distances.  A NaN distance (a ray lying in a plane
-// with a zero direction component) is ignored by fmaxf / fminf, which keeps
-// the test conservative.
+// max of the two plane distances.  A NaN distance is ignored by fmaxf /
+// fminf, which keeps the test conservative.
 PT_DEV unsigned slab4_nf(const Ray& r, const float4 q[7], float tlim, float tn[4]) {
     const float* nx = &q[0].x;
     const float* fx = &q[1].x;
@@ -329,9 +383,9 @@ PT_DEV unsigned slab4_nf(const Ray& r, const float4 q[7], float tlim, float tn[4
     unsigned mask = 0;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        float ax = (nx[c] - r.o.x) * r.inv.x, bx = (fx[c] - r.o.x) * r.inv.x;
-        float ay = (ny[c] - r.o.y) * r.inv.y, by = (fy[c] - r.o.y) * r.inv.y;
-        float az = (nz[c] - r.o.z) * r.inv.z, bz = (fz[c] - r.o.z) * r.inv.z;
+        float ax = fmaf(nx[c], r.inv.x, -r.oi.x), bx = fmaf(fx[c], r.inv.x, -r.oi.x);
+        float ay = fmaf(ny[c], r.inv.y, -r.oi.y), by = fmaf(fy[c], r.inv.y, -r.oi.y);
+        float az = fmaf(nz[c], r.inv.z, -r.oi.z), bz = fmaf(fz[c], r.inv.z, -r.oi.z);
         float t0 = fmaxf(fmaxf(ax, ay), fmaxf(az, 0.0f));
         float t1 = fminf(fminf(bx, by), fminf(bz, tlim));
         tn[c] = t0;
@@ -406,9 +460,8 @@ PT_DEV bool closest_step(const SceneView& sc, const Ray& r, float tmax, Hit& h, 
                 }
                 sort4(rr, tt);
                 // push the farther hits (farthest first), descend into the nearest
-                if (rr[3] != kEmptyRef) st.push(rr[3], tt[3]);
-                if (rr[2] != kEmptyRef) st.push(rr[2], tt[2]);
-                if (rr[1] != kEmptyRef) st.push(rr[1], tt[1]);
+                st.push3(make_uint2(rr[3], f2u(tt[3])), rr[3] != kEmptyRef, make_uint2(rr[2], f2u(tt[2])),
+                         rr[2] != kEmptyRef, make_uint2(rr[1], f2u(tt[1])), rr[1] != kEmptyRef);
                 ref = rr[0];
                 return true;
             }
@@ -473,16 +526,12 @@ PT_DEV bool any_step(const SceneView& sc, const Ray& r, float tmax, uint32_t& re
             float tn[4];
             unsigned m = slab4_nf(r, q, tmax, tn);
             if (m) {
-                // descend into the first hit child, push the others
+                // descend into the last hit child, push the other hit ones
                 const uint32_t cr[4] = {f2u(q[6].x), f2u(q[6].y), f2u(q[6].z), f2u(q[6].w)};
-                uint32_t next = kEmptyRef;
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    if (!((m >> c) & 1u)) continue;
-                    if (next == kEmptyRef) next = cr[c];
-                    else st.push(cr[c], tn[c]);
-                }
-                ref = next;
+                const uint32_t last = 31u - (uint32_t)__builtin_clz(m);
+                st.push3(make_uint2(cr[0], f2u(tn[0])), (m & 1u) && last > 0u, make_uint2(cr[1], f2u(tn[1])),
+                         ((m >> 1) & 1u) && last > 1u, make_uint2(cr[2], f2u(tn[2])), ((m >> 2) & 1u) && last > 2u);
+                ref = last == 0u ? cr[0] : (last == 1u ? cr[1] : (last == 2u ? cr[2] : cr[3]));
                 return true;
             }
         }

@@ -12,8 +12,8 @@ namespace {
 template <int LDS, bool COUNT>
 __device__ __forceinline__ TravStack<LDS, COUNT> make_stack(uint32_t* smem, uint2* ovf, int gcap, uint32_t gtid,
                                                             uint32_t nlanes) {
-    return make_trav_stack<LDS, COUNT>(reinterpret_cast<uint2*>(smem) + threadIdx.x, (int)blockDim.x, ovf + gtid,
-                                (int)nlanes, gcap);
+    return make_trav_stack<LDS, COUNT>(reinterpret_cast<uint2*>(smem) + threadIdx.x, (int)blockDim.x, ovf, gtid,
+                                       (int)nlanes, gcap);
 }
 
 // Stage the light table (CDF words, leaf-order and input triangle indices)
@@ -392,7 +392,7 @@ __global__ void __launch_bounds__(256) k_accumulate(CamView cam, PathParams pp, 
         if (count) launch(N, true) else launch(N, false) return hipGetLastError(); \
     }
 
-static size_t stack_lds_bytes(int lds, int block) { return (size_t)lds * 2 * sizeof(uint32_t) * block; }
+static size_t stack_lds_bytes(int lds, int block) { return trav_stack_lds_bytes(lds, block); }
 
 hipError_t launch_mega(int lds, bool count, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
                        const CamView& cam, const PathParams& pp, float* img, float* acc, uint2* ovf, int gcap,

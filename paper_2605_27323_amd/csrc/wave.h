@@ -41,6 +41,9 @@ __device__ __forceinline__ void wave_chunk(uint32_t count, uint32_t& next, uint3
     const uint32_t chunk = (uint32_t)(((uint64_t)count + nwaves - 1) / nwaves);
     next = (uint32_t)min((uint64_t)wave * chunk, (uint64_t)count);
     end = (uint32_t)min((uint64_t)next + chunk, (uint64_t)count);
+    // the same for every lane of the wave: keep them in scalar registers
+    next = __builtin_amdgcn_readfirstlane(next);
+    end = __builtin_amdgcn_readfirstlane(end);
 }
 
 // Block-aggregated reservation on two queue counters: every thread of the

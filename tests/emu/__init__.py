@@ -53,6 +53,9 @@ def lib():
         L.emu_render_wave.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, C.c_uint32, C.c_uint32,
                                       C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.c_int32, C.c_uint32, C.c_void_p,
                                       C.c_void_p]
+        L.emu_closest.restype = C.c_int32
+        L.emu_closest.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_void_p]
         L.emu_render_batch.restype = C.c_int64
         L.emu_render_batch.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_uint32, C.c_uint64, C.c_void_p]
         L.emu_backward.restype = C.c_int32
@@ -88,6 +91,19 @@ class Emu:
                         float(cam["vfov_deg"]), int(cam["width"]), int(cam["height"]))
         assert L.pt_set_camera(h, C.byref(c)) == 0
         self.W, self.H = int(cam["width"]), int(cam["height"])
+
+    def closest(self, o, d):
+        """Closest hit of the library's traversal: t, input id (-1 on a miss), b1, b2."""
+        o = np.ascontiguousarray(o, np.float32).reshape(-1, 3)
+        d = np.ascontiguousarray(d, np.float32).reshape(-1, 3)
+        n = o.shape[0]
+        t = np.zeros(n, np.float32)
+        i = np.zeros(n, np.int32)
+        b1 = np.zeros(n, np.float32)
+        b2 = np.zeros(n, np.float32)
+        assert lib().emu_closest(self.h, n, o.ctypes.data, d.ctypes.data, t.ctypes.data, i.ctypes.data,
+                                 b1.ctypes.data, b2.ctypes.data) == 0
+        return t, i, b1, b2
 
     def mega(self, pixels=None, spp=1, max_depth=5, seed=0, frame=0, job=0, nee=True, rr_start=-1):
         if pixels is None:

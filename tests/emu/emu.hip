@@ -42,10 +42,10 @@ SceneView host_view(const pt_ctx* c) {
 constexpr int kL = 16;
 
 struct HostStack {
-    uint2 l[kL];
+    uint2 l[kL + 1];
     std::vector<uint2> gbl;
     TravStack<kL> st;
-    explicit HostStack(int gcap) : gbl(std::max(gcap, 1)) { st = make_trav_stack<kL>(l, 1, gbl.data(), 1, gcap); }
+    explicit HostStack(int gcap) : gbl(std::max(gcap, 1)) { st = make_trav_stack<kL>(l, 1, gbl.data(), 0u, 1, gcap); }
 };
 
 }  // namespace
@@ -77,6 +77,24 @@ int32_t emu_render_mega(pt_ctx* c, const int32_t* pixels, int32_t n, int32_t spp
     }
     rays[0] = ne;
     rays[1] = ns;
+    return hs.st.overflow ? 1 : 0;
+}
+
+// Closest hit of the library's traversal for n rays o[3n], d[3n] in
+// (0, inf): t, input triangle id (-1 on a miss), barycentrics.  Returns 1
+// if a traversal stack overflowed.
+int32_t emu_closest(pt_ctx* c, int32_t n, const float* o, const float* d, float* t, int32_t* id, float* b1,
+                    float* b2) {
+    SceneView sc = host_view(c);
+    HostStack hs(std::max(0, c->bvh.stack_entries - kL));
+    for (int32_t i = 0; i < n; ++i) {
+        const Ray r = make_ray(mk3(o[3 * i], o[3 * i + 1], o[3 * i + 2]), mk3(d[3 * i], d[3 * i + 1], d[3 * i + 2]));
+        const Hit h = closest_hit<kL>(sc, r, INFINITY, hs.st);
+        t[i] = h.t;
+        id[i] = h.tri == 0xFFFFFFFFu ? -1 : (int32_t)h.id;
+        b1[i] = h.b1;
+        b2[i] = h.b2;
+    }
     return hs.st.overflow ? 1 : 0;
 }
 

@@ -91,6 +91,42 @@ def test_rays_in_all_octants_never_touch_empty_slots():
         _check(scene, cam, spp=2, max_depth=4)
 
 
+@pytest.mark.parametrize("dist,offset", [(1.0, 0.0), (30.0, 0.0), (1e3, 0.0), (1e5, 0.0), (0.5, 3e4), (5.0, -1e6)])
+def test_closest_hit_from_distant_origins_equals_brute_force(dist, offset):
+    # rays aimed at vertices and edge points (where a hit sits on the boundary
+    # of its leaf box) from origins up to 1e5 times the scene's extent, and
+    # from nearby origins in a scene far from the coordinate origin (large
+    # coordinates, short distances): the slab test must stay conservative,
+    # so the closest hit equals the oracle's brute force bit for bit
+    scene = scenes.random_soup(12, 80, emissive_frac=0.1)
+    scene = dict(scene, positions=(scene["positions"] + np.float32(offset)).astype(np.float32))
+    cam = dict(eye=(0, 0, -3.0), target=(0, 0, 0), up=(0, 1, 0), vfov_deg=45.0, width=4, height=4)
+    E = emu.Emu(scene, cam)
+    rng = np.random.default_rng(int(dist))
+    pos, idx = scene["positions"], scene["indices"]
+    v = pos[idx]  # [nt, 3, 3]
+    w = rng.dirichlet([0.2, 0.2, 0.2], size=(600,)).astype(np.float32)
+    w[:200] = np.eye(3, dtype=np.float32)[rng.integers(0, 3, 200)]  # vertices
+    w[200:400, rng.integers(0, 3)] = 0.0  # edges
+    w[200:400] /= w[200:400].sum(1, keepdims=True)
+    tri = rng.integers(0, idx.shape[0], 600)
+    target = np.einsum("nk,nkc->nc", w, v[tri]).astype(np.float32)
+    u = rng.normal(size=(600, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    u[::7] = np.eye(3)[rng.integers(0, 3, len(u[::7]))] * rng.choice([-1, 1], (len(u[::7]), 1))  # axis-parallel
+    o = (target - dist * u).astype(np.float32)
+    assert not np.array_equal(o, target)
+    d = (target - o).astype(np.float64)
+    d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+    t, i, b1, b2 = E.closest(o, d)
+    rt, ri, rb1, rb2 = oracle.Scene(scene).closest(o, d, mode=0)
+    assert (ri >= 0).mean() > 0.5
+    assert np.array_equal(i, ri)
+    hit = ri >= 0
+    for a, r in [(t, rt), (b1, rb1), (b2, rb2)]:
+        assert np.array_equal(a[hit].view(np.uint32), r[hit].view(np.uint32))
+
+
 def test_full_size_scene_sampled_pixels():
     scene, cam = scenes.procedural(seed=2, n_objects=2000)
     px = scenes.pixel_subset(1920, 1080, 4096, seed=99)
