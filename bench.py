@@ -122,7 +122,7 @@ def main():
                     help="batched workload instead: 64 jobs, 10k-2M triangles each, mixed resolutions and spp")
     ap.add_argument("--divergence", action="store_true",
                     help="divergence workload instead: ~10M triangles, 64 material ids, 4 spp, depth 16")
-    ap.add_argument("--max-leaf", type=int, default=4, help="triangles per BVH leaf, 1..8")
+    ap.add_argument("--max-leaf", type=int, default=0, help="triangles per BVH leaf, 1..8 (0 = library default, 1)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -338,7 +338,7 @@ def batch_bench(args):
     for j, sp in enumerate(specs):
         sc, cam = scenes.procedural(seed=sp["scene_seed"], n_objects=sp["n_objects"], width=sp["width"],
                                     height=sp["height"])
-        Rs.append(ptmi.Renderer(sc, cam))
+        Rs.append(ptmi.Renderer(sc, cam, max_leaf=args.max_leaf))
         ntri += sc["indices"].shape[0]
         job_args.append(dict(spp=sp["spp"], max_depth=DEPTH, rr_start=RR, nee=True, seed=0, job=j))
     total = sum(R.width * R.height * a["spp"] for R, a in zip(Rs, job_args))
@@ -377,7 +377,7 @@ def divergence_bench(args):
     t0 = time.perf_counter()
     scene, cam = scenes.procedural(seed=3, n_objects=20000, width=W, height=H, material_mode="divergence")
     nt = scene["indices"].shape[0]
-    R = ptmi.Renderer(scene, cam)
+    R = ptmi.Renderer(scene, cam, max_leaf=args.max_leaf)
     log(f"divergence scene {nt} triangles, BVH depth {R.info.depth} (setup {time.perf_counter() - t0:.1f} s)")
     kw = dict(spp=4, max_depth=16, rr_start=3, nee=True, seed=0)
     img = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
@@ -422,7 +422,7 @@ def adjoint_bench(ptmi, scenes, scene, torch, args):
     cam = dict(eye=(0.0, 50.0, -130.0), target=(0.0, 40.0, 0.0), up=(0.0, 1.0, 0.0), vfov_deg=50.0,
                width=512, height=512)
     try:
-        R = ptmi.Renderer(scene, cam)
+        R = ptmi.Renderer(scene, cam, max_leaf=args.max_leaf)
         kw = dict(spp=8, max_depth=6, rr_start=-1, nee=True, seed=0)
         d_img = torch.ones((512, 512, 3), dtype=torch.float32, device="cuda")
         ga = torch.zeros_like(R.albedo)

@@ -88,7 +88,8 @@ typedef struct {
 
 /* BVH build options (NULL = defaults). */
 typedef struct {
-    int32_t max_leaf;  /* triangles per leaf, 1..8 (default 4) */
+    int32_t max_leaf;  /* triangles per leaf, 1..8 (0 = default 1: one triangle per leaf
+                          keeps the leaf step uniform across a wave) */
     int32_t threads;   /* host threads for the build (0 = hardware concurrency) */
 } pt_bvh_opts;
 

@@ -400,7 +400,7 @@ pt_status pt_load_scene(pt_ctx* c, const pt_scene_desc* s) {
 pt_status pt_build_bvh(pt_ctx* c, const pt_bvh_opts* o, pt_bvh_info* info) {
     if (!c) return fail(PT_EINVAL, "null context");
     if (!c->loaded) return fail(PT_ESTATE, "no scene loaded");
-    int max_leaf = o && o->max_leaf > 0 ? o->max_leaf : 4;
+    int max_leaf = o && o->max_leaf > 0 ? o->max_leaf : 1;
     int threads = o ? o->threads : 0;
     if (max_leaf > kMaxLeaf) return fail(PT_EINVAL, "max_leaf must be <= 8");
     auto t0 = std::chrono::steady_clock::now();

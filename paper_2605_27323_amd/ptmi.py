@@ -143,7 +143,7 @@ def _host(a, dtype):
 class Context:
     """A library context with a loaded scene and its built BVH (host side)."""
 
-    def __init__(self, scene, device=0, max_leaf=4, threads=0):
+    def __init__(self, scene, device=0, max_leaf=0, threads=0):
         L = lib()
         h = C.c_void_p()
         check(L.pt_create(C.byref(h), int(device)))
@@ -202,7 +202,7 @@ def _aligned_empty(nbytes, device):
 class Renderer(Context):
     """Scene bound to device buffers (torch tensors), plus a workspace."""
 
-    def __init__(self, scene, camera=None, device=0, max_leaf=4, threads=0):
+    def __init__(self, scene, camera=None, device=0, max_leaf=0, threads=0):
         import torch
         super().__init__(scene, device=device, max_leaf=max_leaf, threads=threads)
         self.torch_device = torch.device("cuda", device)

@@ -72,7 +72,7 @@ def lib():
 class Emu:
     """Host-only library context (emulator build) with a scene and camera."""
 
-    def __init__(self, scene, cam):
+    def __init__(self, scene, cam, max_leaf=0):
         from paper_2605_27323_amd import ptmi
         L = lib()
         h = C.c_void_p()
@@ -86,7 +86,8 @@ class Emu:
                            (C.c_float * 3)(*np.asarray(keep["sky"], np.float32).tolist()))
         assert L.pt_load_scene(h, C.byref(d)) == 0, L.pt_last_error()
         info = ptmi.BvhInfo()
-        assert L.pt_build_bvh(h, None, C.byref(info)) == 0
+        opts = ptmi.BvhOpts(int(max_leaf), 0)
+        assert L.pt_build_bvh(h, C.byref(opts), C.byref(info)) == 0
         c = ptmi.Camera((C.c_double * 3)(*cam["eye"]), (C.c_double * 3)(*cam["target"]), (C.c_double * 3)(*cam["up"]),
                         float(cam["vfov_deg"]), int(cam["width"]), int(cam["height"]))
         assert L.pt_set_camera(h, C.byref(c)) == 0

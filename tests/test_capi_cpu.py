@@ -117,8 +117,9 @@ def _walk(nodes, nt):
     return leaves, depth
 
 
+@pytest.mark.parametrize("max_leaf", [1, 4, 8])
 @pytest.mark.parametrize("which", ["cornell", "procedural", "soup", "single", "empty"])
-def test_bvh4_structure(which):
+def test_bvh4_structure(which, max_leaf):
     if which == "cornell":
         scene, _ = scenes.cornell()
     elif which == "procedural":
@@ -131,7 +132,7 @@ def test_bvh4_structure(which):
         scene = scenes.random_soup(7, 1)
         scene = dict(scene, indices=np.zeros((0, 3), np.int32), tri_mat=np.zeros(0, np.int32),
                      albedo=np.zeros((0, 3), np.float32), emission=np.zeros((0, 3), np.float32))
-    ctx = ptmi.Context(scene, device=-1)
+    ctx = ptmi.Context(scene, device=-1, max_leaf=max_leaf)
     nodes, tris, lights = ctx.host_bvh()
     nt = scene["indices"].shape[0]
     leaves, depth = _walk(nodes, nt)
@@ -142,7 +143,7 @@ def test_bvh4_structure(which):
     pos = scene["positions"]
     idx = scene["indices"]
     for first, cnt, boxes in leaves:
-        assert cnt <= 4
+        assert cnt <= max_leaf
         for j in range(first, first + cnt):
             covered[j] += 1
             tid = int(ids[j])

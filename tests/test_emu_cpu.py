@@ -82,6 +82,26 @@ def test_empty_and_single_triangle():
     _check(one, cam, spp=3, max_depth=2)
 
 
+@pytest.mark.parametrize("max_leaf", [2, 4, 8])
+def test_leaf_sizes_give_the_same_image(max_leaf):
+    # multi-triangle leaves (the leaf loop) against the default of one
+    # triangle per leaf: the image does not depend on the BVH
+    scene, cam = scenes.procedural(seed=5, n_objects=40, width=40, height=24)
+    cfg = dict(spp=2, max_depth=6, rr_start=2, seed=4)
+    ref, _ = emu.Emu(scene, cam).mega(**cfg)
+    E = emu.Emu(scene, cam, max_leaf=max_leaf)
+    for img in (E.mega(**cfg)[0], E.wave(shuffle=3, **cfg)[0]):
+        assert np.array_equal(img.view(np.uint32), ref.view(np.uint32))
+    o = scenes.random_soup(13, 300)
+    d = np.random.default_rng(max_leaf).normal(size=(400, 3)).astype(np.float32)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    org = np.zeros((400, 3), np.float32)
+    a = emu.Emu(o, cam).closest(org, d)
+    b = emu.Emu(o, cam, max_leaf=max_leaf).closest(org, d)
+    for x, y in zip(a, b):
+        assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
+
+
 def test_rays_in_all_octants_never_touch_empty_slots():
     # nodes with fewer than four children keep +inf boxes in the free slots;
     # rays with every direction component positive used to accept them

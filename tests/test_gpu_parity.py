@@ -167,6 +167,10 @@ def test_no_compaction_and_launch_shapes_bit_identical():
             R.render(mode="wave", flags=ptmi.FLAG_SORT_RAYS | ptmi.FLAG_SORT_MATERIAL, sort_threshold=900,
                      tail_threshold=200, **cfg),
             R.render(mode="wave", **cfg)]
+    # the image does not depend on the BVH either: leaves of up to 4 and 8 triangles
+    for ml in (4, 8):
+        Rl = ptmi.Renderer(scene, cam, max_leaf=ml)
+        outs += [Rl.render(mode="wave", **cfg), Rl.render(mode="mega", **cfg)]
     for o in outs:
         assert np.array_equal(o.cpu().numpy().view(np.uint32), ref.view(np.uint32))
 
