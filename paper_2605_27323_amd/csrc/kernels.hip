@@ -105,9 +105,12 @@ __global__ void k_init_counts(uint32_t* __restrict__ counts, int n, uint32_t fir
 }
 
 // hybrid tail: a queue with fewer than `tail` paths is too short to keep
-// the stage kernels busy; each path is shaded and finished in place
+// the stage kernels busy; each path is shaded and finished in place.
+// Limited to 128 VGPRs (4 waves per SIMD, a few spilled registers): at 148
+// it ran 3 waves per SIMD and kept the next frame's stage kernels off the
+// compute units while it finished the last bounces.
 template <int LDS, bool COUNT>
-__global__ void __launch_bounds__(256) k_shade_tail(SceneView sc, PathParams pp, WaveBufs wb, int b, int sorted,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_shade_tail(SceneView sc, PathParams pp, WaveBufs wb, int b, int sorted,
                                                     uint32_t tail, uint2* __restrict__ ovf, int gcap) {
     const uint32_t count = wb.counts[b];
     if (!(count < tail) || count == 0u) return;
