@@ -26,8 +26,11 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 FLOPS_PER_NODE = 104
 FLOPS_PER_TRI = 51
 # autotuner result on MI355X for the 1M-triangle 1080p workload
-FIXED_PARAMS = {"wave": {"block": 256, "grid_mult": 8, "stack_lds": 8, "tail_threshold": 1 << 18},
-                "mega": {"block": 256, "grid_mult": 16, "stack_lds": 8}}
+FIXED_PARAMS = {"wave": {"block": 256, "grid_mult": 8, "stack_lds": 8, "tail_threshold": 1 << 18, "tail_bounce": 4},
+                "mega": {"block": 256, "grid_mult": 4, "stack_lds": 8}}
+# launch parameters of the divergence workload (4 spp, depth 16)
+DIVERGENCE_PARAMS = {"wave": {"block": 256, "grid_mult": 8, "stack_lds": 8, "tail_threshold": 1 << 18, "tail_bounce": 6},
+                     "mega": {"block": 256, "grid_mult": 4, "stack_lds": 8}}
 W, H, SPP, DEPTH, RR = 1920, 1080, 1, 8, 3
 
 
@@ -383,8 +386,9 @@ def divergence_bench(args):
     img = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
     res = {}
     k = max(2, args.steps // 8)
-    wave = dict(FIXED_PARAMS["wave"])
-    mega = dict(FIXED_PARAMS["mega"])
+    given = json.loads(args.params) if args.params else {}
+    wave = dict(given.get("wave", DIVERGENCE_PARAMS["wave"]))
+    mega = dict(given.get("mega", DIVERGENCE_PARAMS["mega"]))
     runs = [("mega", dict(mode="mega", **mega)), ("wave", dict(mode="wave", **wave)),
             ("wave_material_sort", dict(mode="wave", flags=ptmi.FLAG_SORT_MATERIAL, sort_threshold=1 << 16, **wave)),
             ("wave_ray_sort", dict(mode="wave", flags=ptmi.FLAG_SORT_RAYS, sort_threshold=1 << 16, **wave))]

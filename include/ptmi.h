@@ -142,7 +142,10 @@ typedef struct {
  * workgroup's LDS (PT_EINVAL otherwise);
  * tail_threshold: wavefront hybrid tail, a bounce whose queue holds fewer
  * than this many paths finishes them in place, megakernel style, inside the
- * shade stage (0 = off; the image is the same bit for bit). */
+ * shade stage (0 = off; the image is the same bit for bit);
+ * tail_bounce: when > 0, the hybrid tail finishes every path still running
+ * at bounce tail_bounce (1 .. max_depth) whatever the queue size, and no
+ * stage of a later bounce is enqueued (0 = off; same image bit for bit). */
 typedef struct {
     int32_t spp, max_depth;
     uint64_t seed;
@@ -155,6 +158,7 @@ typedef struct {
     uint32_t sort_threshold;
     int32_t stack_lds;
     uint32_t tail_threshold;
+    int32_t tail_bounce;
 } pt_render_args;
 
 /* Library version (major * 10000 + minor * 100 + patch). */

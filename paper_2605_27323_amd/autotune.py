@@ -22,6 +22,8 @@ FRAME_SPACE = {
              "tail_threshold": [0, 1 << 16, 1 << 18, 1 << 19, 1 << 20]},
     "mega": {"block": [64, 128, 256], "grid_mult": [2, 4, 8, 16], "stack_lds": [8, 16]},
 }
+# tried after the other wave parameters are chosen (0 = off)
+TAIL_BOUNCES = [0, 2, 3, 4, 5, 6]
 BATCH_SPACE = {"pool_capacity": [1 << 20, 1 << 21, 1 << 22], "block": [128, 256], "grid_mult": [4, 8],
                "stack_lds": [8, 16]}
 
@@ -117,6 +119,11 @@ def tune_frame(renderer, mode="wave", cache=DEFAULT_CACHE, space=None, log=None,
         return (time.perf_counter() - t) / reps
 
     best, _ = successive_halving(cands, measure, log=log)
+    if mode == "wave" and space is FRAME_SPACE[mode]:
+        # then the bounce from which the hybrid tail finishes every path
+        depth = kw.get("max_depth", 5)
+        tbs = [t for t in TAIL_BOUNCES if t <= depth]
+        best, _ = successive_halving([dict(best, tail_bounce=t) for t in tbs], measure, reps0=2, log=log)
     if cache:
         _store(cache, key, best)
     return best

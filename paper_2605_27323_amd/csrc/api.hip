@@ -76,6 +76,7 @@ struct pt_ctx {
     int last_ncounts = 0, last_D = 0, last_kind = 0;  // kind: 0 megakernel, 1 wavefront, 2 adjoint
     int last_spp = 1, last_nee = 1, last_compact = 1, last_sort = 0;
     uint32_t last_tail = 0, last_sort_threshold = 0;
+    int last_tail_bounce = 0;
     uint64_t last_npix = 0;
     bool last_acc = false;
     bool last_valid = false;
@@ -160,6 +161,8 @@ pt_status check_args(const pt_ctx* c, const pt_render_args* a) {
         return fail(PT_EINVAL, "unknown flag");
     if (a->spp < 1 || a->spp > 65536) return fail(PT_EINVAL, "spp must be in [1, 65536]");
     if (a->max_depth < 0 || a->max_depth > 1000) return fail(PT_EINVAL, "max_depth must be in [0, 1000]");
+    if (a->tail_bounce < 0 || a->tail_bounce > a->max_depth)
+        return fail(PT_EINVAL, "tail_bounce must be in [0, max_depth]");
     if (a->mode != PT_MODE_MEGA && a->mode != PT_MODE_WAVE) return fail(PT_EINVAL, "unknown mode");
     const uint64_t npaths = (uint64_t)c->cam.W * c->cam.H * a->spp;
     if (npaths >= 0xFFFFFFFFull) return fail(PT_EINVAL, "width * height * spp must be < 2^32 - 1");
@@ -198,6 +201,7 @@ void remember_frame(pt_ctx* c, const pt_render_args* a, uint32_t* counts, int nc
     c->last_compact = (a->flags & PT_FLAG_NO_COMPACT) ? 0 : 1;
     c->last_sort = ((a->flags & PT_FLAG_SORT_MATERIAL) ? 1 : 0) + ((a->flags & PT_FLAG_SORT_RAYS) ? 1 : 0);
     c->last_tail = a->tail_threshold;
+    c->last_tail_bounce = a->tail_bounce;
     c->last_sort_threshold = a->sort_threshold;
     c->last_npix = (uint64_t)c->cam.W * (uint64_t)c->cam.H;
     c->last_acc = acc;
@@ -260,13 +264,17 @@ pt_status enqueue_stages(pt_ctx* c, const pt_render_args* a, const Launch& L, co
             PT_HIP(timed(c, prof, 1, s, [&] { return launch_extend(L.lds, count, grid, block, s, c->view, wb, b, ovf, L.gcap, rsort); }), "extend");
             if (sort)
                 PT_HIP(timed(c, prof, 6, s, [&] { return launch_sort(grid, block, s, c->view, wb, b, a->sort_threshold, 0); }), "sort");
-            PT_HIP(timed(c, prof, 2, s, [&] { return launch_shade(grid, block, s, c->view, pp, wb, b, compact, sort, a->tail_threshold); }), "shade");
-            if (compact && a->tail_threshold)
+            // at bounce tail_bounce the hybrid tail takes whatever is left
+            // (threshold above any queue size); later bounces have nothing
+            const bool last = compact && a->tail_bounce > 0 && b == a->tail_bounce;
+            const uint32_t tail = last ? 0xFFFFFFFFu : a->tail_threshold;
+            PT_HIP(timed(c, prof, 2, s, [&] { return launch_shade(grid, block, s, c->view, pp, wb, b, compact, sort, tail); }), "shade");
+            if (compact && tail)
                 PT_HIP(timed(c, prof, 8, s, [&] {
-                           return launch_tail(L.lds, count, grid, block, s, c->view, pp, wb, b, sort, a->tail_threshold, ovf,
-                                              L.gcap);
+                           return launch_tail(L.lds, count, grid, block, s, c->view, pp, wb, b, sort, tail, ovf, L.gcap);
                        }),
                        "hybrid tail");
+            if (last) break;
             if (b < a->max_depth && a->nee)
                 PT_HIP(timed(c, prof, 3, s, [&] { return launch_shadow(L.lds, count, grid, block, s, c->view, wb, b, ovf, L.gcap); }), "shadow");
         }
@@ -680,6 +688,7 @@ pt_status pt_frame_stats_get(pt_ctx* c, pt_frame_stats* out) {
     const uint32_t* cnt = h.data();
     const uint32_t* shc = h.data() + D + 2;
     const uint32_t tail = c->last_compact ? c->last_tail : 0u;
+    const int tail_bounce = c->last_compact ? c->last_tail_bounce : 0;
     // per queued path: raygen writes ray_o, ray_d, pst, L (64 B); extend
     // reads ray_o, ray_d, writes hit (48 B); shade reads ray_o, ray_d, pst,
     // hit, L (80 B) and writes 48 B per continuation and per shadow record;
@@ -692,7 +701,7 @@ pt_status pt_frame_stats_get(pt_ctx* c, pt_frame_stats* out) {
         out->extension_rays += cnt[b];
         out->stage_items[1] += cnt[b];
         if (c->last_sort && cnt[b] >= c->last_sort_threshold) out->stage_items[6] += (int64_t)c->last_sort * cnt[b];
-        if (tail && cnt[b] < tail) {
+        if ((tail && cnt[b] < tail) || (tail_bounce > 0 && b >= tail_bounce)) {
             out->stage_items[8] += cnt[b];
         } else {
             out->stage_items[2] += cnt[b];

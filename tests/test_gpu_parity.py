@@ -166,6 +166,9 @@ def test_no_compaction_and_launch_shapes_bit_identical():
             R.render(mode="wave", flags=ptmi.FLAG_SORT_RAYS, **cfg),
             R.render(mode="wave", flags=ptmi.FLAG_SORT_RAYS | ptmi.FLAG_SORT_MATERIAL, sort_threshold=900,
                      tail_threshold=200, **cfg),
+            R.render(mode="wave", tail_bounce=1, **cfg),
+            R.render(mode="wave", tail_bounce=3, tail_threshold=300, **cfg),
+            R.render(mode="wave", tail_bounce=6, flags=ptmi.FLAG_SORT_MATERIAL, **cfg),
             R.render(mode="wave", **cfg)]
     # the image does not depend on the BVH either: leaves of up to 4 and 8 triangles
     for ml in (4, 8):
@@ -212,6 +215,13 @@ def test_progressive_accumulation_and_ray_counts():
     assert (st["extension_rays"], st["shadow_rays"]) == (sm["extension_rays"], sm["shadow_rays"])
     for key in ("node_visits", "tri_tests"):
         assert sum(st[key].values()) == sm[key]["mega"]
+    # the same with the tail taking over at bounce 2
+    R.render(mode="wave", spp=2, max_depth=4, tail_bounce=2, flags=ptmi.FLAG_COUNT_WORK)
+    sb = R.stats()
+    assert sb["items"].get("tail", 0) > 0
+    assert (sb["extension_rays"], sb["shadow_rays"]) == (sm["extension_rays"], sm["shadow_rays"])
+    for key in ("node_visits", "tri_tests"):
+        assert sum(sb[key].values()) == sm[key]["mega"]
 
 
 def test_profile_stage_times():
@@ -231,6 +241,10 @@ def test_profile_stage_times():
     R.render(mode="wave", spp=1, max_depth=5, rr_start=3, tail_threshold=1 << 30, flags=ptmi.FLAG_PROFILE)
     st = R.stats()
     assert st["launches"]["tail"] == 6 and st["items"]["tail"] == 48 * 32 and "shade" not in st["items"]
+    # tail_bounce: no stage of a later bounce is launched
+    R.render(mode="wave", spp=1, max_depth=5, rr_start=3, tail_bounce=2, flags=ptmi.FLAG_PROFILE)
+    st = R.stats()
+    assert st["launches"]["extend"] == 3 and st["launches"]["tail"] == 1 and st["launches"]["shadow"] == 2
 
 
 @pytest.mark.parametrize("mode", ["wave", "mega"])
@@ -241,7 +255,8 @@ def test_frames_in_flight_match_sequential(mode):
     scene, cam = scenes.procedural(seed=52, n_objects=30, width=64, height=40)
     log(f"frames in flight {mode}")
     R = ptmi.Renderer(scene, cam)
-    kw = dict(mode=mode, spp=2, max_depth=6, rr_start=3, tail_threshold=300 if mode == "wave" else 0)
+    kw = dict(mode=mode, spp=2, max_depth=6, rr_start=3, tail_threshold=300 if mode == "wave" else 0,
+              tail_bounce=4 if mode == "wave" else 0)
     acc_seq = torch.zeros((40, 64, 3), dtype=torch.float32, device="cuda")
     for f in range(5):
         img_seq = R.render(accum=acc_seq, frame=3 + f, **kw).clone()
