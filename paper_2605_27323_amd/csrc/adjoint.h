@@ -11,7 +11,9 @@
 //   continuation weight W_k:   dalb(tri_k)  += delta (L - L_acc) dW/dalb / W
 // where L_acc is the radiance gathered up to and including x_k's light
 // sample and delta = dLoss/dI(pixel) / spp.  Channels with W = 0 carry no
-// gradient through W (the division of the method).
+// gradient through W (the division of the method).  The accumulator takes
+// add(p, v) (skipping v = 0) and add_light(j, c, p, v) for the emission of
+// light j of the light table, channel c, at p.
 #pragma once
 #include "device.h"
 
@@ -45,6 +47,9 @@ PT_DEV void adjoint_path(const SceneView& sc, const CamView& cam, const PathPara
             acc.add(g_emi + 3 * (size_t)id + 1, delta.y * (beta.y * vo.w_emit));
             acc.add(g_emi + 3 * (size_t)id + 2, delta.z * (beta.z * vo.w_emit));
         }
+        // the albedo gradient of this vertex: light-sample and continuation
+        // terms summed here, one accumulation per channel
+        float ga[3] = {0.0f, 0.0f, 0.0f};
         if (sh.valid) {
             Ray sr = make_ray(sh.o, sh.d);
             if (!any_hit<LDS>(sc, sr, kShadowTmax, st)) {
@@ -53,27 +58,35 @@ PT_DEV void adjoint_path(const SceneView& sc, const CamView& cam, const PathPara
                 const f3 Le = load3(sc.emission, sh.light_id);
                 const float der = lobe_der(sh.lobe);
                 const uint32_t lid = sh.light_id;
-                acc.add(g_emi + 3 * (size_t)lid + 0, delta.x * (beta.x * (lobe_value(sh.lobe, rho.x) * sh.G)));
-                acc.add(g_emi + 3 * (size_t)lid + 1, delta.y * (beta.y * (lobe_value(sh.lobe, rho.y) * sh.G)));
-                acc.add(g_emi + 3 * (size_t)lid + 2, delta.z * (beta.z * (lobe_value(sh.lobe, rho.z) * sh.G)));
+                acc.add_light(sh.light_idx, 0, g_emi + 3 * (size_t)lid + 0,
+                              delta.x * (beta.x * (lobe_value(sh.lobe, rho.x) * sh.G)));
+                acc.add_light(sh.light_idx, 1, g_emi + 3 * (size_t)lid + 1,
+                              delta.y * (beta.y * (lobe_value(sh.lobe, rho.y) * sh.G)));
+                acc.add_light(sh.light_idx, 2, g_emi + 3 * (size_t)lid + 2,
+                              delta.z * (beta.z * (lobe_value(sh.lobe, rho.z) * sh.G)));
                 if (der != 0.0f) {
-                    acc.add(g_alb + 3 * (size_t)id + 0, delta.x * (beta.x * ((der * sh.G) * Le.x)));
-                    acc.add(g_alb + 3 * (size_t)id + 1, delta.y * (beta.y * ((der * sh.G) * Le.y)));
-                    acc.add(g_alb + 3 * (size_t)id + 2, delta.z * (beta.z * ((der * sh.G) * Le.z)));
+                    ga[0] = delta.x * (beta.x * ((der * sh.G) * Le.x));
+                    ga[1] = delta.y * (beta.y * ((der * sh.G) * Le.y));
+                    ga[2] = delta.z * (beta.z * ((der * sh.G) * Le.z));
                 }
             }
         }
-        if (!vo.cont) break;
-        const float der = lobe_der(vo.scat);
-        if (der != 0.0f) {
-            const f3 rho = load3(sc.albedo, id);
-            const float W[3] = {lobe_value(vo.scat, rho.x), lobe_value(vo.scat, rho.y), lobe_value(vo.scat, rho.z)};
-            const float post[3] = {Ltot.x - ps.L.x, Ltot.y - ps.L.y, Ltot.z - ps.L.z};
-            const float dl[3] = {delta.x, delta.y, delta.z};
+        const bool cont = vo.cont;
+        if (cont) {
+            const float der = lobe_der(vo.scat);
+            if (der != 0.0f) {
+                const f3 rho = load3(sc.albedo, id);
+                const float W[3] = {lobe_value(vo.scat, rho.x), lobe_value(vo.scat, rho.y), lobe_value(vo.scat, rho.z)};
+                const float post[3] = {Ltot.x - ps.L.x, Ltot.y - ps.L.y, Ltot.z - ps.L.z};
+                const float dl[3] = {delta.x, delta.y, delta.z};
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-                if (W[c] != 0.0f) acc.add(g_alb + 3 * (size_t)id + c, dl[c] * (post[c] * (der / W[c])));
+                for (int c = 0; c < 3; ++c)
+                    if (W[c] != 0.0f) ga[c] += dl[c] * (post[c] * (der / W[c]));
+            }
         }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc.add(g_alb + 3 * (size_t)id + c, ga[c]);
+        if (!cont) break;
         o = vo.o;
         d = vo.d;
     }

@@ -9,9 +9,23 @@ namespace ptmi {
 
 namespace {
 
+// Gradients go to global memory with hardware fp32 atomics, except the
+// light-sample emission terms of lights in the first kLdsLights entries of
+// the light table: those few addresses receive a term from every visible
+// light sample, so each block sums them in LDS and adds its sums once at
+// the end.
 struct AtomicAcc {
+    float* lds_light;  // 3 floats per light (local memory of the block)
+    uint32_t n_lds;    // lights kept there
     __device__ __forceinline__ void add(float* p, float v) {
         if (v != 0.0f) unsafeAtomicAdd(p, v);
+    }
+    __device__ __forceinline__ void add_light(uint32_t j, int c, float* p, float v) {
+        if (v == 0.0f) return;
+        if (j < n_lds)
+            atomicAdd(&lds_light[3 * j + (uint32_t)c], v);
+        else
+            unsafeAtomicAdd(p, v);
     }
 };
 
@@ -27,7 +41,12 @@ __global__ void __launch_bounds__(256) k_adjoint(SceneView sc, CamView cam, Path
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
     TravStack<LDS> st =
         make_trav_stack<LDS>(reinterpret_cast<uint2*>(smem) + threadIdx.x, (int)blockDim.x, ovf, gtid, (int)nlanes, gcap);
+    __shared__ float light_g[3 * kLdsLights];
     AtomicAcc acc;
+    acc.lds_light = light_g;
+    acc.n_lds = (uint32_t)min(max(sc.nl, 0), kLdsLights);
+    for (uint32_t j = threadIdx.x; j < 3 * acc.n_lds; j += blockDim.x) light_g[j] = 0.0f;
+    __syncthreads();
     const uint32_t npaths = (uint32_t)cam.W * (uint32_t)cam.H * (uint32_t)pp.spp;
     const float fs = (float)pp.spp;
     for (uint32_t p = gtid; p < npaths; p += nlanes) {
@@ -35,6 +54,12 @@ __global__ void __launch_bounds__(256) k_adjoint(SceneView sc, CamView cam, Path
         const uint32_t s = p - pix * (uint32_t)pp.spp;
         const f3 delta = mk3(d_img[3 * (size_t)pix] / fs, d_img[3 * (size_t)pix + 1] / fs, d_img[3 * (size_t)pix + 2] / fs);
         adjoint_path<LDS>(sc, cam, pp, pix, pp.frame * (uint32_t)pp.spp + s, delta, g_alb, g_emi, st, acc);
+    }
+    // every thread of the block is here: add the block's light sums
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < 3 * acc.n_lds; j += blockDim.x) {
+        const float v = light_g[j];
+        if (v != 0.0f) unsafeAtomicAdd(g_emi + 3 * (size_t)sc.lights[j / 3u].id + j % 3u, v);
     }
     if (st.overflow) atomicOr(&stats[2], 1u);
 }

@@ -792,6 +792,7 @@ struct ShadowReq {
     f3 C;        // f Le_y G: contribution per unit throughput if visible
     f3 contrib;  // beta * C with the throughput arriving at the vertex
     uint32_t light_id;  // input id of the light triangle
+    uint32_t light_idx; // its index in the light table
     float G;
     Lobe lobe;   // f = lobe(albedo)
 };
@@ -895,8 +896,10 @@ PT_DEV VertexOut shade_vertex(const SceneView& sc, const PathParams& pp, uint32_
     f3 Le_l;
     const bool nee = more && pp.nee && sc.nl > 0;
     if (more) rn = philox8(pp.seed, pixel, sample, (uint32_t)k, pp.job);
+    uint32_t lj = 0;
     if (nee) {
         const uint32_t j = pick_light(sc, lc, rn.w[0]);
+        lj = j;
         const uint32_t lt = lc.n ? lc.tri[j] : sc.lights[j].tri;
         const uint32_t lid = lc.n ? lc.id[j] : sc.lights[j].id;
         const float4* lp = sc.tris + (size_t)lt * 3;
@@ -968,6 +971,7 @@ PT_DEV VertexOut shade_vertex(const SceneView& sc, const PathParams& pp, uint32_
                     sh.d = sub3(sy, sh.o);
                     sh.valid = true;
                     sh.light_id = lid;
+                    sh.light_idx = lj;
                     sh.G = G;
                     sh.lobe = lob;
                 }

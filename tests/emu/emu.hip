@@ -207,6 +207,7 @@ int32_t emu_backward(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32_t 
         void add(float* p, float v) {
             if (v != 0.0f) *p += v;
         }
+        void add_light(uint32_t, int, float* p, float v) { add(p, v); }
     } acc;
     SceneView sc = host_view(c);
     PathParams pp{spp, D, nee ? 1 : 0, -1, seed, frame, job};
