@@ -111,7 +111,7 @@ PT_DEV void batch_extend_item(const BatchBufs& bb, int q, uint32_t i, TravStack<
     const SceneView& sc = bb.jobs[job].sc;
     Ray ray = make_ray(xyz(o4), xyz(d4));
     Hit h = closest_hit<LDS>(sc, ray, INFINITY, st);
-    bb.hit[i] = make_float4(h.t, h.b1, h.b2, u2f(h.tri));
+    bb.hit[i] = make_float4(h.t, 0.f, 0.f, u2f(h.tri));
 }
 
 // shade slot i of queue q; returns true if the path finished here (the
@@ -134,10 +134,9 @@ PT_DEV bool batch_shade_item(const BatchBufs& bb, int q, uint32_t i, VertexOut& 
     ps.prev_smooth = (int)((m >> 16) & 1u);
     Hit h;
     h.t = h4.x;
-    h.b1 = h4.y;
-    h.b2 = h4.z;
     h.tri = f2u(h4.w);
     h.id = 0;
+    hit_barycentrics(jd.sc, xyz(o4), xyz(d4), h);
     vo = shade_vertex(jd.sc, jd.pp, pix, sample, (int)k, xyz(d4), h, ps, sh);
     if (vo.addL) {  // the radiance is read only where this vertex adds to it
         ps.L = xyz(bb.L[g]);

@@ -101,7 +101,7 @@ k_batch_extend(BatchBufs bb, int q, uint2* __restrict__ ovf, int gcap) {
             break;
         }
         if (live && !closest_step<LDS>(sc, ray, INFINITY, h, ref, st)) {
-            bb.hit[item] = make_float4(h.t, h.b1, h.b2, u2f(h.tri));
+            bb.hit[item] = make_float4(h.t, 0.f, 0.f, u2f(h.tri));
             live = false;
         }
     }

@@ -152,6 +152,8 @@ struct Ray {
     float Sx, Sy, Sz;
 };
 
+PT_DEV void set_shear(Ray& r, f3 d);
+
 // The slab test evaluates the distance to a plane at coordinate p as
 // RN(p * inv - RN(o * inv)).  Its error beyond the relative rounding of
 // the result is the rounding of o * inv, at most 2^-24 |o_a inv_a|; with
@@ -170,6 +172,12 @@ PT_DEV Ray make_ray(f3 o, f3 d) {
                 1.0f / (fabsf(d.y) >= 0x1p-80f ? d.y : copysignf(0x1p-80f, d.y)),
                 1.0f / (fabsf(d.z) >= 0x1p-80f ? d.z : copysignf(0x1p-80f, d.z)));
     r.oi = mk3(o.x * r.inv.x, o.y * r.inv.y, o.z * r.inv.z);
+    set_shear(r, d);
+    return r;
+}
+
+// The watertight test's axis permutation and shear constants of direction d
+PT_DEV void set_shear(Ray& r, f3 d) {
     float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
     int kz = 0;
     float m = ax;
@@ -190,11 +198,12 @@ PT_DEV Ray make_ray(f3 o, f3 d) {
     r.Sx = comp3(d, kx) / dkz;
     r.Sy = comp3(d, ky) / dkz;
     r.Sz = 1.0f / dkz;
-    return r;
 }
 
-// Returns true on a hit with t > 0; t and the barycentrics of v1, v2.
-PT_DEV bool tri_intersect(const Ray& r, f3 v0, f3 v1, f3 v2, float& t, float& b1, float& b2) {
+// Returns true on a hit with t > 0: t, and the barycentrics of v1 and v2
+// undivided, as Vn / det and Wn / det (the traversal divides only for the
+// hit it keeps).
+PT_DEV bool tri_test(const Ray& r, f3 v0, f3 v1, f3 v2, float& t, float& Vn, float& Wn, float& dn) {
     const int kx = (int)(r.k & 3u), ky = (int)((r.k >> 2) & 3u), kz = (int)(r.k >> 4);
     f3 A = sub3(v0, r.o), B = sub3(v1, r.o), C = sub3(v2, r.o);
     float Akz = comp3(A, kz), Bkz = comp3(B, kz), Ckz = comp3(C, kz);
@@ -223,6 +232,16 @@ PT_DEV bool tri_intersect(const Ray& r, f3 v0, f3 v1, f3 v2, float& t, float& b1
     float tt = T / det;
     if (!(tt > 0.0f)) return false;
     t = tt;
+    Vn = V;
+    Wn = W;
+    dn = det;
+    return true;
+}
+
+// Returns true on a hit with t > 0; t and the barycentrics of v1, v2.
+PT_DEV bool tri_intersect(const Ray& r, f3 v0, f3 v1, f3 v2, float& t, float& b1, float& b2) {
+    float V, W, det;
+    if (!tri_test(r, v0, v1, v2, t, V, W, det)) return false;
     b1 = V / det;
     b2 = W / det;
     return true;
@@ -343,11 +362,21 @@ PT_DEV TravStack<LDS, COUNT> make_trav_stack(uint2* lds_lane, int lstride, uint2
     return st;
 }
 
+// During a traversal b1 and b2 hold the undivided barycentrics and det
+// their denominator; closest_hit divides once at the end (hit_finish).
 struct Hit {
     float t, b1, b2;
+    float det;
     uint32_t tri;   // leaf-order index, ~0u on a miss
     uint32_t id;    // input id (tie-break)
 };
+
+PT_DEV void hit_finish(Hit& h) {
+    if (h.tri != 0xFFFFFFFFu) {
+        h.b1 = h.b1 / h.det;
+        h.b2 = h.b2 / h.det;
+    }
+}
 
 // load a node with its child planes ordered near/far along the ray:
 // q = near_x, far_x, near_y, far_y, near_z, far_z, refs
@@ -430,6 +459,7 @@ PT_DEV void closest_begin(float tmax, Hit& h, uint32_t& ref, TravStack<LDS, COUN
     h.t = tmax;
     h.b1 = 0.0f;
     h.b2 = 0.0f;
+    h.det = 1.0f;
     h.tri = 0xFFFFFFFFu;
     h.id = 0xFFFFFFFFu;
     st.sp = 0;
@@ -474,13 +504,14 @@ PT_DEV bool closest_step(const SceneView& sc, const Ray& r, float tmax, Hit& h, 
             for (uint32_t i = first; i < first + cnt; ++i) {
                 const float4* tp = sc.tris + (size_t)i * 3;
                 float4 a = tp[0], b = tp[1], c = tp[2];
-                float t, b1, b2;
-                if (tri_intersect(r, xyz(a), xyz(b), xyz(c), t, b1, b2) && t < tmax) {
+                float t, vn, wn, dn;
+                if (tri_test(r, xyz(a), xyz(b), xyz(c), t, vn, wn, dn) && t < tmax) {
                     uint32_t id = f2u(a.w);
                     if (t < h.t || (t == h.t && id < h.id)) {
                         h.t = t;
-                        h.b1 = b1;
-                        h.b2 = b2;
+                        h.b1 = vn;
+                        h.b2 = wn;
+                        h.det = dn;
                         h.tri = i;
                         h.id = id;
                     }
@@ -503,7 +534,24 @@ PT_DEV Hit closest_hit(const SceneView& sc, const Ray& r, float tmax, TravStack<
     closest_begin<LDS>(tmax, h, ref, st);
     while (closest_step<LDS>(sc, r, tmax, h, ref, st)) {
     }
+    hit_finish(h);
     return h;
+}
+
+// Barycentrics of the closest hit h of the ray (o, d), when the stage that
+// found it kept only t and the triangle (the stage kernels' hit record):
+// the watertight test of that triangle again, on the same inputs, so the
+// values are the ones the traversal had.
+PT_DEV void hit_barycentrics(const SceneView& sc, f3 o, f3 d, Hit& h) {
+    h.b1 = 0.0f;
+    h.b2 = 0.0f;
+    if (h.tri >= (uint32_t)sc.nt) return;
+    Ray r;
+    r.o = o;
+    set_shear(r, d);
+    const float4* tp = sc.tris + (size_t)h.tri * 3;
+    float t;
+    tri_intersect(r, xyz(tp[0]), xyz(tp[1]), xyz(tp[2]), t, h.b1, h.b2);
 }
 
 // Any hit in (0, tmax), as resumable steps: any_step visits `ref` and pops
@@ -543,8 +591,8 @@ PT_DEV bool any_step(const SceneView& sc, const Ray& r, float tmax, uint32_t& re
                 if constexpr (COUNT) ++st.tris;
                 const float4* tp = sc.tris + (size_t)i * 3;
                 float4 a = tp[0], b = tp[1], c = tp[2];
-                float t, b1, b2;
-                if (tri_intersect(r, xyz(a), xyz(b), xyz(c), t, b1, b2) && t < tmax) {
+                float t, vn, wn, dn;
+                if (tri_test(r, xyz(a), xyz(b), xyz(c), t, vn, wn, dn) && t < tmax) {
                     occluded = true;
                     return false;
                 }

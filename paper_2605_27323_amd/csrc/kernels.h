@@ -10,7 +10,8 @@ constexpr uint32_t kDeadPath = 0xFFFFFFFFu;
 // Wavefront path state, structure of arrays (one float4 stream per field
 // group, so that a wave's 64 lanes read or write 1 KiB contiguously).
 //   ray_o[q][i] = (origin, path id)     ray_d[q][i] = (direction, last pdf)
-//   pst[q][i]   = (throughput, flags)   hit[i] = (t, b1, b2, leaf-order tri)
+//   pst[q][i]   = (throughput, flags)   hit[i] = (t, 0, 0, leaf-order tri)
+//   (the shade stage recomputes the hit's barycentrics, hit_barycentrics)
 //   sh_o/sh_d/sh_c[i] = shadow segment origin + path id, direction, beta*C
 //   L[path]     = radiance of the path (indexed by path id, not queue slot)
 // q alternates between bounces (ping-pong queues).

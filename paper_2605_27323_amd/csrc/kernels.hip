@@ -199,7 +199,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
             break;
         }
         if (live && !closest_step<LDS>(sc, ray, INFINITY, h, ref, st)) {
-            wb.hit[item] = make_float4(h.t, h.b1, h.b2, u2f(h.tri));
+            wb.hit[item] = make_float4(h.t, 0.f, 0.f, u2f(h.tri));
             live = false;
         }
     }

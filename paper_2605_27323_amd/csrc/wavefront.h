@@ -46,7 +46,7 @@ PT_DEV void extend_item(const SceneView& sc, const WaveBufs& wb, int b, uint32_t
     if (f2u(o4.w) == kDeadPath) return;
     Ray ray = make_ray(xyz(o4), xyz(d4));
     Hit h = closest_hit<LDS>(sc, ray, INFINITY, st);
-    wb.hit[i] = make_float4(h.t, h.b1, h.b2, u2f(h.tri));
+    wb.hit[i] = make_float4(h.t, 0.f, 0.f, u2f(h.tri));
 }
 
 // 6-bit sort key of a hit: material type in bits 4-5, low bits of the
@@ -98,10 +98,9 @@ PT_DEV uint32_t shade_item(const SceneView& sc, const PathParams& pp, const Wave
     ps.prev_smooth = (int)f2u(p4.w);
     Hit h;
     h.t = h4.x;
-    h.b1 = h4.y;
-    h.b2 = h4.z;
     h.tri = f2u(h4.w);
     h.id = 0;
+    hit_barycentrics(sc, xyz(o4), xyz(d4), h);
     vo = shade_vertex(sc, pp, pix, sample, b + 1, xyz(d4), h, ps, sh, lc);
     if (for_tail) {
         ps.L = xyz(wb.L[path]);
