@@ -214,11 +214,21 @@ def main():
     rays = [0, 0]
     roofline, state_floor, frame_stage_ms = None, None, {}
     ext_rays_per_frame = sh_rays_per_frame = 0.0
+    # stage profile and work counts at the fixed launch parameters, the ones
+    # the committed rocprofv3 profiles were taken with (bench.py --fixed), so
+    # that the roofline's mean launch time is comparable with them
+    prof_params = dict(tuned["wave"]) if (args.params and "wave" in tuned) else dict(FIXED_PARAMS["wave"])
+
+    def run_prof(first, flags):
+        p = dict(prof_params)
+        p["flags"] = p.get("flags", 0) | flags
+        R.render(out=img, mode="wave", frame=first, **kw, **p)
+
     if "wave" in modes:
         # per-stage times with HIP events on the render stream, over the same
         # number of frames, plus ray counts, work items and algorithmic bytes
         for i in range(args.steps):
-            run("wave", 1, args.warmup + i, flags=ptmi.FLAG_PROFILE)
+            run_prof(args.warmup + i, ptmi.FLAG_PROFILE)
             st = R.stats()
             for k, v in st["stage_ms"].items():
                 stage_ms[k] = stage_ms.get(k, 0.0) + v
@@ -231,7 +241,7 @@ def main():
         # the same frames again with the work-counting kernels (node visits and
         # triangle tests; a separate, slower build, so not timed)
         for i in range(args.steps):
-            run("wave", 1, args.warmup + i, flags=ptmi.FLAG_COUNT_WORK)
+            run_prof(args.warmup + i, ptmi.FLAG_COUNT_WORK)
             st = R.stats()
             for k, v in st["node_visits"].items():
                 nodes[k] = nodes.get(k, 0) + v
@@ -248,7 +258,7 @@ def main():
         # mean launch time, against the fp32 vector peak.  The streaming stages
         # use their algorithmic path-state bytes against the HBM peak.
         dom = max(stage_ms, key=stage_ms.get)
-        lds = tuned["wave"].get("stack_lds", 16)
+        lds = prof_params.get("stack_lds", 16)
         kname = {"extend": f"ptmi::k_extend<{lds}, false>", "shade": "ptmi::k_shade",
                  "shadow": f"ptmi::k_shadow<{lds}, false>", "tail": f"ptmi::k_shade_tail<{lds}, false>",
                  "raygen": "ptmi::k_raygen", "accumulate": "ptmi::k_accumulate", "sort": "ptmi::k_sort_*"}[dom]
@@ -258,7 +268,7 @@ def main():
         common = {"kernel": kname, "traffic": measured_traffic(kname), "avg_launch_ms": dom_avg_ms,
                   "launches_per_frame": launches[dom] / args.steps, "items_per_frame": items.get(dom, 0) / args.steps,
                   "stage_share": stage_ms[dom] / sum(stage_ms.values()), "state_bytes_per_launch": per_launch_bytes,
-                  "state_gbs": state_gbs}
+                  "state_gbs": state_gbs, "launch_params": prof_params}
         if dom in ("extend", "shadow", "tail"):
             flops = FLOPS_PER_NODE * nodes.get(dom, 0) + FLOPS_PER_TRI * tris.get(dom, 0)
             per_launch_flops = flops / launches[dom]
