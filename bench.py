@@ -62,7 +62,7 @@ def cpu_baseline(scene, cam, budget_s=12.0):
     budget is spent."""
     import numpy as np
 
-    import oracle
+    # the cores this process may use, at most 16 (the host share of one GPU)
     # the host's share of cores (at most 16: the GPU box's CPU share)
     threads = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()))
     t0 = time.perf_counter()
