@@ -399,9 +399,13 @@ def divergence_bench(args):
     given = json.loads(args.params) if args.params else {}
     wave = dict(given.get("wave", DIVERGENCE_PARAMS["wave"]))
     mega = dict(given.get("mega", DIVERGENCE_PARAMS["mega"]))
+    def sorted_by(flag):
+        return dict(wave, mode="wave", flags=wave.get("flags", 0) | flag,
+                    sort_threshold=wave.get("sort_threshold", 1 << 16))
+
     runs = [("mega", dict(mode="mega", **mega)), ("wave", dict(mode="wave", **wave)),
-            ("wave_material_sort", dict(mode="wave", flags=ptmi.FLAG_SORT_MATERIAL, sort_threshold=1 << 16, **wave)),
-            ("wave_ray_sort", dict(mode="wave", flags=ptmi.FLAG_SORT_RAYS, sort_threshold=1 << 16, **wave))]
+            ("wave_material_sort", sorted_by(ptmi.FLAG_SORT_MATERIAL)),
+            ("wave_ray_sort", sorted_by(ptmi.FLAG_SORT_RAYS))]
     for name, extra in runs:
         R.render(out=img, frame=0, **kw, **extra)
         torch.cuda.synchronize()
