@@ -95,7 +95,7 @@ typedef struct {
 
 /* Filled by pt_build_bvh: sizes of the device buffers of pt_scene_buffers. */
 typedef struct {
-    int64_t node_count, node_bytes;  /* BVH4 nodes, 128 B each */
+    int64_t node_count, node_bytes;  /* BVH4 nodes, 80 B each (half-precision child boxes) */
     int64_t tri_bytes;               /* 48 B per triangle, leaf order */
     int64_t light_count, light_bytes;/* 16 B per light (leaf-order index, CDF word, input index, 0) */
     int64_t material_bytes;          /* 16 B per material */

@@ -175,6 +175,74 @@ class BinaryBuilder {
     }
 };
 
+// binary16 encoding of x >= 0 (finite, below 65504), rounded down or up
+uint16_t half_bits(double x, bool up) {
+    if (!(x > 0.0)) return 0;
+    int k;
+    std::frexp(x, &k);  // x in [2^(k-1), 2^k)
+    int ex = k - 1;
+    double m;
+    uint32_t bits;
+    if (ex < -14) {  // subnormal: multiples of 2^-24
+        m = x * std::ldexp(1.0, 24);
+        double q = up ? std::ceil(m) : std::floor(m);
+        bits = (uint32_t)q;  // 1024 (the smallest normal) when rounded up from the top
+    } else {
+        m = (x / std::ldexp(1.0, ex) - 1.0) * 1024.0;  // fraction in [0, 1024)
+        double q = up ? std::ceil(m) : std::floor(m);
+        bits = ((uint32_t)(ex + 15) << 10) + (uint32_t)q;  // a carry into the exponent stays exact
+    }
+    return (uint16_t)bits;
+}
+
+// Fills a node from its children's boxes (slots with ref == EMPTY unused):
+// per axis the origin is the lowest child plane and the scale the power of
+// two that brings the node's extent to at most 2^15; every plane offset is
+// encoded as binary16, lower planes rounded down and upper planes up (from
+// the exact offset in double), so every decoded box encloses its child's.
+void quantize_node(Node4& q, const float lo[4][3], const float hi[4][3], const uint32_t ref[4]) {
+    q = Node4{};
+    float nlo[3] = {0.f, 0.f, 0.f}, nhi[3] = {0.f, 0.f, 0.f};
+    bool any = false;
+    for (int s = 0; s < 4; ++s) {
+        if (ref[s] == kEmptyRef) continue;
+        for (int a = 0; a < 3; ++a) {
+            nlo[a] = any ? std::min(nlo[a], lo[s][a]) : lo[s][a];
+            nhi[a] = any ? std::max(nhi[a], hi[s][a]) : hi[s][a];
+        }
+        any = true;
+    }
+    uint32_t* planes[3] = {q.x, q.y, q.z};
+    for (int a = 0; a < 3; ++a) {
+        const double ext = (double)nhi[a] - (double)nlo[a];
+        int e = kNodeGridMinExp;
+        if (ext > 0.0) {
+            int k;
+            std::frexp(ext, &k);  // ext < 2^k
+            e = std::max(kNodeGridMinExp, k - 15);
+            while (std::ldexp(32768.0, e) < ext) ++e;
+        }
+        q.o[a] = nlo[a];
+        q.e |= (uint32_t)(e + 128) << (8 * a);
+        const double scale = std::ldexp(1.0, e);
+        uint16_t hl[4], hh[4];
+        for (int s = 0; s < 4; ++s) {
+            if (ref[s] == kEmptyRef) {
+                hl[s] = 0x7C00;  // +inf
+                hh[s] = 0xFC00;  // -inf
+            } else {
+                hl[s] = half_bits(((double)lo[s][a] - (double)nlo[a]) / scale, false);
+                hh[s] = half_bits(((double)hi[s][a] - (double)nlo[a]) / scale, true);
+            }
+        }
+        planes[a][0] = hl[0] | ((uint32_t)hl[1] << 16);
+        planes[a][1] = hl[2] | ((uint32_t)hl[3] << 16);
+        planes[a][2] = hh[0] | ((uint32_t)hh[1] << 16);
+        planes[a][3] = hh[2] | ((uint32_t)hh[3] << 16);
+    }
+    for (int s = 0; s < 4; ++s) q.ref[s] = ref[s];
+}
+
 struct Collapser {
     std::vector<Node4>& out;
     float pad;
@@ -182,15 +250,12 @@ struct Collapser {
 
     static bool is_leaf(const BNode* n) { return n->count > 0 || (n->kid[0] == nullptr); }
 
-    void set_box(Node4& q, int slot, const BNode* c) {
-        float lo[3], hi[3];
+    // padded box of a child
+    void child_box(const BNode* c, float lo[3], float hi[3]) const {
         for (int a = 0; a < 3; ++a) {
             lo[a] = std::nextafter(c->lo[a] - pad, -INFINITY);
             hi[a] = std::nextafter(c->hi[a] + pad, INFINITY);
         }
-        q.lox[slot] = lo[0]; q.hix[slot] = hi[0];
-        q.loy[slot] = lo[1]; q.hiy[slot] = hi[1];
-        q.loz[slot] = lo[2]; q.hiz[slot] = hi[2];
     }
 
     static uint32_t leaf_ref(const BNode* n) {
@@ -222,18 +287,14 @@ struct Collapser {
             child_idx[s] = (uint32_t)out.size();
             out.emplace_back();
         }
-        Node4& q = out[idx];
-        for (int s = 0; s < 4; ++s) {
-            q.lox[s] = q.loy[s] = q.loz[s] = INFINITY;  // empty slot: an inverted box no ray enters
-            q.hix[s] = q.hiy[s] = q.hiz[s] = -INFINITY;
-            q.ref[s] = kEmptyRef;
-            q.pad[s] = 0;
-        }
+        float lo[4][3], hi[4][3];
+        uint32_t ref[4] = {kEmptyRef, kEmptyRef, kEmptyRef, kEmptyRef};
         for (int s = 0; s < k; ++s) {
             if (is_leaf(kids[s]) && kids[s]->count == 0) continue;  // empty leaf: slot stays empty
-            set_box(q, s, kids[s]);
-            q.ref[s] = is_leaf(kids[s]) ? leaf_ref(kids[s]) : child_idx[s];
+            child_box(kids[s], lo[s], hi[s]);
+            ref[s] = is_leaf(kids[s]) ? leaf_ref(kids[s]) : child_idx[s];
         }
+        quantize_node(out[idx], lo, hi, ref);
         for (int s = 0; s < k; ++s)
             if (!is_leaf(kids[s])) emit(child_idx[s], kids[s], level + 1);
     }
@@ -284,28 +345,19 @@ BuildResult build_scene(const std::vector<float>& tri_v, const std::vector<int32
     r.nodes.emplace_back();
     Collapser col{r.nodes, pad};
     if (nt == 0) {
-        Node4& q = r.nodes[0];
-        for (int s = 0; s < 4; ++s) {
-            q.lox[s] = q.loy[s] = q.loz[s] = INFINITY;  // empty slot: an inverted box no ray enters
-            q.hix[s] = q.hiy[s] = q.hiz[s] = -INFINITY;
-            q.ref[s] = kEmptyRef;
-            q.pad[s] = 0;
-        }
+        const float lo[4][3] = {}, hi[4][3] = {};
+        const uint32_t ref[4] = {kEmptyRef, kEmptyRef, kEmptyRef, kEmptyRef};
+        quantize_node(r.nodes[0], lo, hi, ref);
         r.depth = 1;
     } else {
         BinaryBuilder bb(info, order, max_leaf, threads);
         BNode* root = bb.build();
         if (Collapser::is_leaf(root)) {
             // a single leaf: wrap it in a root node with one child
-            Node4& q = r.nodes[0];
-            for (int s = 0; s < 4; ++s) {
-                q.lox[s] = q.loy[s] = q.loz[s] = INFINITY;  // empty slot: an inverted box no ray enters
-                q.hix[s] = q.hiy[s] = q.hiz[s] = -INFINITY;
-                q.ref[s] = kEmptyRef;
-                q.pad[s] = 0;
-            }
-            col.set_box(q, 0, root);
-            q.ref[0] = Collapser::leaf_ref(root);
+            float lo[4][3] = {}, hi[4][3] = {};
+            const uint32_t ref[4] = {Collapser::leaf_ref(root), kEmptyRef, kEmptyRef, kEmptyRef};
+            col.child_box(root, lo[0], hi[0]);
+            quantize_node(r.nodes[0], lo, hi, ref);
             col.depth = 1;
         } else {
             col.emit(0, root, 1);

@@ -154,16 +154,11 @@ struct Ray {
 
 PT_DEV void set_shear(Ray& r, f3 d);
 
-// The slab test evaluates the distance to a plane at coordinate p as
-// RN(p * inv - RN(o * inv)).  Its error beyond the relative rounding of
-// the result is the rounding of o * inv, at most 2^-24 |o_a inv_a|; with
-// |o_a| <= |p_a - o_a| + |p_a| this is at most 2^-24 of the plane's own
-// distance (relative, covered by kBoxSlack) plus 2^-24 |p_a| in position,
-// far inside the builder's padding of every box by 2^-18 of the largest
-// vertex coordinate.  A direction component below 2^-80 is replaced by
-// +-2^-80: over any hit distance the ray moves far less than the padding
-// along that axis, so the smaller inverse keeps every distance's sign and
-// leaves the test conservative.
+// Ray setup: inv = 1/d for the slab test (slab4_q bounds its errors, oi =
+// o * inv rounded is its origin term).  A direction component below 2^-80
+// is replaced by +-2^-80: over any hit distance the ray moves far less than
+// the boxes' padding along that axis, so the smaller inverse keeps every
+// distance's sign and leaves the test conservative.
 PT_DEV Ray make_ray(f3 o, f3 d) {
     Ray r;
     r.o = o;
@@ -378,47 +373,75 @@ PT_DEV void hit_finish(Hit& h) {
     }
 }
 
-// load a node with its child planes ordered near/far along the ray:
-// q = near_x, far_x, near_y, far_y, near_z, far_z, refs
-PT_DEV void load_node_nf(const float4* __restrict__ nodes, uint32_t idx, const Ray& r, float4 q[8]) {
-    const float4* p = nodes + (size_t)idx * 8;
-    const uint32_t sx = f2u(r.inv.x) >> 31, sy = f2u(r.inv.y) >> 31, sz = f2u(r.inv.z) >> 31;
-    q[0] = p[sx];
-    q[1] = p[1u - sx];
-    q[2] = p[2u + sy];
-    q[3] = p[3u - sy];
-    q[4] = p[4u + sz];
-    q[5] = p[5u - sz];
-    q[6] = p[6];
+// load a node: q[0] = (origin, scale exponents), q[1..3] = the x, y, z
+// planes (binary16 pairs), q[4] = child references
+PT_DEV void load_node(const float4* __restrict__ nodes, uint32_t idx, float4 q[5]) {
+    const float4* p = nodes + (size_t)mul24(idx, 5u);
+    q[0] = p[0];
+    q[1] = p[1];
+    q[2] = p[2];
+    q[3] = p[3];
+    q[4] = p[4];
+}
+
+// plane offset c (0..3) of a word pair (w0: children 0, 1; w1: 2, 3) as float
+PT_DEV float half_of(uint32_t w0, uint32_t w1, int c) {
+    const uint32_t w = c < 2 ? w0 : w1;
+    const uint16_t b = (uint16_t)((c & 1) ? (w >> 16) : (w & 0xFFFFu));
+#if defined(__HIP_DEVICE_COMPILE__)
+    return (float)__builtin_bit_cast(_Float16, b);
+#else
+    // binary16 to binary32 (exact)
+    const uint32_t sgn = (uint32_t)(b >> 15) << 31, ex = (b >> 10) & 31u, man = b & 1023u;
+    if (ex == 31u) return u2f(sgn | 0x7F800000u | (man << 13));
+    if (ex == 0u) return man ? (b >> 15 ? -1.0f : 1.0f) * ldexpf((float)man, -24) : u2f(sgn);
+    return u2f(sgn | ((ex + 112u) << 23) | (man << 13));
+#endif
 }
 
 // Conservative slab test of the four children of a node against (0, tlim]:
-// entry <= exit * (1 + 2^-16), one fused multiply-add per plane (make_ray
-// bounds its error).  Writes the entry
-// distances; returns a 4-bit hit mask.  Empty slots hold an inverted box
-// (lo = +inf, hi = -inf: entry +inf, exit -inf for every direction) and are
-// also masked out by their reference.
-// The planes come ordered near/far along the ray (load_node_nf), so the
-// entry and exit distances per axis need no min/max: they are the min and
-// max of the two plane distances.  A NaN distance is ignored by fmaxf /
-// fminf, which keeps the test conservative.
-PT_DEV unsigned slab4_nf(const Ray& r, const float4 q[7], float tlim, float tn[4]) {
-    const float* nx = &q[0].x;
-    const float* fx = &q[1].x;
-    const float* ny = &q[2].x;
-    const float* fy = &q[3].x;
-    const float* nz = &q[4].x;
-    const float* fz = &q[5].x;
+// entry <= exit * (1 + 2^-16).  Writes the entry distances; returns a 4-bit
+// hit mask.
+// A plane at o_a + h 2^e (o_a the node's origin, h a binary16 offset) is at
+// distance h (2^e inv_a) + (o_a inv_a - RN(o inv_a)): one fused
+// multiply-add per plane (the binary16 operand read in place) after three
+// per axis, with 2^e inv_a exact.  Besides the relative rounding of each
+// result (covered by the slack), the errors are the roundings of o inv_a
+// (make_ray) and of the per-axis term, at most 2^-24 of |o_a - o| in
+// position: a part relative to the plane's distance and a part below 2^-23
+// of the scene's largest coordinate, inside the builder's padding of every
+// box.  The encoding only widens the boxes (planes rounded outward).  Per
+// lane the near and far planes of an axis are chosen by the sign of its
+// inverse direction, so the entry and exit distances per axis need no
+// min/max.  Empty slots (planes +inf / -inf) are inverted boxes, also masked
+// out by their reference.  A NaN distance is ignored by fmaxf / fminf,
+// which keeps the test conservative.
+PT_DEV unsigned slab4_q(const Ray& r, const float4 q[5], float tlim, float tn[4]) {
+    const uint32_t e = f2u(q[0].w);
+    const float Ax = ldexpf(r.inv.x, (int)(e & 255u) - 128);
+    const float Ay = ldexpf(r.inv.y, (int)((e >> 8) & 255u) - 128);
+    const float Az = ldexpf(r.inv.z, (int)((e >> 16) & 255u) - 128);
+    const float Bx = fmaf(q[0].x, r.inv.x, -r.oi.x);
+    const float By = fmaf(q[0].y, r.inv.y, -r.oi.y);
+    const float Bz = fmaf(q[0].z, r.inv.z, -r.oi.z);
+    const bool sx = (f2u(r.inv.x) >> 31) != 0u, sy = (f2u(r.inv.y) >> 31) != 0u, sz = (f2u(r.inv.z) >> 31) != 0u;
+    // near / far word pairs per axis: lower planes (words 0, 1) or upper (2, 3)
+    const uint32_t nx0 = f2u(sx ? q[1].z : q[1].x), nx1 = f2u(sx ? q[1].w : q[1].y);
+    const uint32_t fx0 = f2u(sx ? q[1].x : q[1].z), fx1 = f2u(sx ? q[1].y : q[1].w);
+    const uint32_t ny0 = f2u(sy ? q[2].z : q[2].x), ny1 = f2u(sy ? q[2].w : q[2].y);
+    const uint32_t fy0 = f2u(sy ? q[2].x : q[2].z), fy1 = f2u(sy ? q[2].y : q[2].w);
+    const uint32_t nz0 = f2u(sz ? q[3].z : q[3].x), nz1 = f2u(sz ? q[3].w : q[3].y);
+    const uint32_t fz0 = f2u(sz ? q[3].x : q[3].z), fz1 = f2u(sz ? q[3].y : q[3].w);
     unsigned mask = 0;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        float ax = fmaf(nx[c], r.inv.x, -r.oi.x), bx = fmaf(fx[c], r.inv.x, -r.oi.x);
-        float ay = fmaf(ny[c], r.inv.y, -r.oi.y), by = fmaf(fy[c], r.inv.y, -r.oi.y);
-        float az = fmaf(nz[c], r.inv.z, -r.oi.z), bz = fmaf(fz[c], r.inv.z, -r.oi.z);
+        float ax = fmaf(half_of(nx0, nx1, c), Ax, Bx), bx = fmaf(half_of(fx0, fx1, c), Ax, Bx);
+        float ay = fmaf(half_of(ny0, ny1, c), Ay, By), by = fmaf(half_of(fy0, fy1, c), Ay, By);
+        float az = fmaf(half_of(nz0, nz1, c), Az, Bz), bz = fmaf(half_of(fz0, fz1, c), Az, Bz);
         float t0 = fmaxf(fmaxf(ax, ay), fmaxf(az, 0.0f));
         float t1 = fminf(fminf(bx, by), fminf(bz, tlim));
         tn[c] = t0;
-        const float cref = c == 0 ? q[6].x : (c == 1 ? q[6].y : (c == 2 ? q[6].z : q[6].w));
+        const float cref = c == 0 ? q[4].x : (c == 1 ? q[4].y : (c == 2 ? q[4].z : q[4].w));
         if (t0 <= t1 * kBoxSlack && f2u(cref) != kEmptyRef) mask |= 1u << c;
     }
     return mask;
@@ -474,17 +497,17 @@ PT_DEV bool closest_step(const SceneView& sc, const Ray& r, float tmax, Hit& h, 
     if (!(ref & kLeafBit)) {
         if (ref < (uint32_t)sc.n_nodes) {
             if constexpr (COUNT) ++st.nodes;
-            float4 q[8];
-            load_node_nf(sc.nodes, ref, r, q);
+            float4 q[5];
+            load_node(sc.nodes, ref, q);
             float tn[4];
-            unsigned m = slab4_nf(r, q, h.t, tn);
+            unsigned m = slab4_q(r, q, h.t, tn);
             if (m) {
                 uint32_t rr[4];
                 float tt[4];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     bool hit = (m >> c) & 1u;
-                    const float cref = c == 0 ? q[6].x : (c == 1 ? q[6].y : (c == 2 ? q[6].z : q[6].w));
+                    const float cref = c == 0 ? q[4].x : (c == 1 ? q[4].y : (c == 2 ? q[4].z : q[4].w));
                     rr[c] = hit ? f2u(cref) : kEmptyRef;
                     tt[c] = hit ? tn[c] : INFINITY;
                 }
@@ -569,13 +592,13 @@ PT_DEV bool any_step(const SceneView& sc, const Ray& r, float tmax, uint32_t& re
     if (!(ref & kLeafBit)) {
         if (ref < (uint32_t)sc.n_nodes) {
             if constexpr (COUNT) ++st.nodes;
-            float4 q[8];
-            load_node_nf(sc.nodes, ref, r, q);
+            float4 q[5];
+            load_node(sc.nodes, ref, q);
             float tn[4];
-            unsigned m = slab4_nf(r, q, tmax, tn);
+            unsigned m = slab4_q(r, q, tmax, tn);
             if (m) {
                 // descend into the last hit child, push the other hit ones
-                const uint32_t cr[4] = {f2u(q[6].x), f2u(q[6].y), f2u(q[6].z), f2u(q[6].w)};
+                const uint32_t cr[4] = {f2u(q[4].x), f2u(q[4].y), f2u(q[4].z), f2u(q[4].w)};
                 const uint32_t last = 31u - (uint32_t)__builtin_clz(m);
                 st.push3(make_uint2(cr[0], f2u(tn[0])), (m & 1u) && last > 0u, make_uint2(cr[1], f2u(tn[1])),
                          ((m >> 1) & 1u) && last > 1u, make_uint2(cr[2], f2u(tn[2])), ((m >> 2) & 1u) && last > 2u);

@@ -5,18 +5,28 @@
 
 namespace ptmi {
 
-// 4-wide BVH node, one 128-byte line: child boxes as structure of arrays
-// over the four children, then four child references.
+// 4-wide BVH node, 80 bytes (five 16-byte loads per visit): the children's
+// boxes as half-precision offsets from the node's origin, then the four
+// child references.
+//   o[a]      origin on axis a (the node's lower corner)
+//   e         byte a = scale exponent of axis a, biased by 128:
+//             plane = o[a] + h * 2^(e_a - 128), h a binary16 value
+//   x, y, z   per axis four words of binary16 pairs: lower planes of
+//             children (0, 1), (2, 3), then upper planes of (0, 1), (2, 3);
+//             lower planes rounded down, upper planes up, so the decoded
+//             box encloses the child's box
 //   ref = index of an internal node            (bit 31 clear)
 //   ref = LEAF | (count - 1) << 27 | first_tri (bit 31 set, 1..16 triangles)
-//   ref = EMPTY (all ones) for an unused slot; its box is +inf..+inf so the
-//   slab test rejects it without a branch.
-struct alignas(128) Node4 {
-    float lox[4], hix[4], loy[4], hiy[4], loz[4], hiz[4];
+//   ref = EMPTY (all ones) for an unused slot; its planes are +inf (lower)
+//   and -inf (upper), an inverted box the slab test rejects.
+struct alignas(16) Node4 {
+    float o[3];
+    uint32_t e;
+    uint32_t x[4], y[4], z[4];
     uint32_t ref[4];
-    uint32_t pad[4];
 };
-static_assert(sizeof(Node4) == 128, "node must be one 128-byte line");
+static_assert(sizeof(Node4) == 80, "node must be 80 bytes");
+constexpr int kNodeGridMinExp = -100;  // smallest grid step exponent
 
 constexpr uint32_t kLeafBit = 0x80000000u;
 constexpr uint32_t kEmptyRef = 0xFFFFFFFFu;

@@ -172,10 +172,10 @@ class Context:
         self.emission0 = emi.reshape(-1, 3)
 
     def host_bvh(self):
-        """Host copies: nodes (uint8 [n,128]), tris (float32 [nt,12]), lights (uint32 [nl,4]:
+        """Host copies: nodes (uint8 [n,80]), tris (float32 [nt,12]), lights (uint32 [nl,4]:
         leaf-order index, CDF word, input index, 0)."""
         i = self.info
-        nodes = np.zeros((i.node_count, 128), np.uint8)
+        nodes = np.zeros((i.node_count, 80), np.uint8)
         tris = np.zeros((max(self.nt, 1), 12), np.float32)
         lights = np.zeros((max(i.light_count, 1), 4), np.uint32)
         check(lib().pt_get_bvh(self.h, nodes.ctypes.data, tris.ctypes.data, lights.ctypes.data, None))

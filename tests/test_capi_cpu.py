@@ -90,23 +90,30 @@ def test_invalid_inputs_rejected():
 
 
 def _walk(nodes, nt):
-    """Decode the BVH4 (test-side reader of the node layout): returns
-    leaf ranges and, per leaf, the chain of ancestor boxes."""
-    f = nodes.view(np.float32).reshape(-1, 32)
-    u = nodes.view(np.uint32).reshape(-1, 32)
+    """Decode the BVH4 (test-side reader of the node layout: origin, scale
+    exponents, binary16 plane offsets, references): returns leaf ranges and,
+    per leaf, the chain of ancestor boxes, decoded exactly in float64."""
+    f = nodes.view(np.float32).reshape(-1, 20)
+    u = nodes.view(np.uint32).reshape(-1, 20)
+    h = nodes.view(np.float16).reshape(-1, 40)
     leaves = []
     depth = 0
     stack = [(0, [], 1)]
     while stack:
         ni, boxes, lvl = stack.pop()
         depth = max(depth, lvl)
+        org = f[ni, 0:3].astype(np.float64)
+        scale = np.array([2.0 ** (((int(u[ni, 3]) >> (8 * a)) & 255) - 128) for a in range(3)])
         for c in range(4):
-            ref = int(u[ni, 24 + c])
-            lo = np.array([f[ni, 0 + c], f[ni, 8 + c], f[ni, 16 + c]])
-            hi = np.array([f[ni, 4 + c], f[ni, 12 + c], f[ni, 20 + c]])
+            ref = int(u[ni, 16 + c])
+            # axis a: halves 8 + 8a .. 8 + 8a + 7 = lower planes of children 0..3, upper planes of 0..3
+            hl = np.array([h[ni, 8 + 8 * a + c] for a in range(3)], np.float64)
+            hh = np.array([h[ni, 8 + 8 * a + 4 + c] for a in range(3)], np.float64)
             if ref == 0xFFFFFFFF:
-                assert np.isinf(lo).all()
+                assert np.isposinf(hl).all() and np.isneginf(hh).all()
                 continue
+            lo = org + hl * scale
+            hi = org + hh * scale
             if ref & 0x80000000:
                 first = ref & ((1 << 27) - 1)
                 cnt = ((ref >> 27) & 15) + 1
