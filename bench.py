@@ -56,14 +56,14 @@ def measured_traffic(kernel, field="hbm_bytes_per_dispatch"):
     return k.get(field) if k else None
 
 
-def cpu_baseline(scene, cam, budget_s=12.0):
+def cpu_baseline(scene, cam, budget_s=12.0, single_s=3.0):
     """The oracle (plain C, all host threads) on whole frames 0, 1, 2, ...
     of the benchmark workload, split in 262144-pixel chunks, until the time
     budget is spent."""
     import numpy as np
 
+    import oracle
     # the cores this process may use, at most 16 (the host share of one GPU)
-    # the host's share of cores (at most 16: the GPU box's CPU share)
     threads = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()))
     t0 = time.perf_counter()
     S = oracle.Scene(scene)
@@ -83,7 +83,7 @@ def cpu_baseline(scene, cam, budget_s=12.0):
         return done, frame, time.perf_counter() - t0
 
     done, frame, dt = run(threads, budget_s, 262144)
-    done1, _, dt1 = run(1, 3.0, 16384)
+    done1, _, dt1 = run(1, single_s, 16384)
     return {"value": done * SPP / dt, "unit": "path-samples/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} paths = {done / npix:.2f} frames of the {W}x{H} 1-spp workload (frames 0..{frame}), "
                       f"{dt:.1f} s render on {threads} threads, BVH build {build_s:.1f} s excluded",
