@@ -53,6 +53,9 @@ enum {
 enum { PT_LAMBERT = 0, PT_CONDUCTOR = 1, PT_DIELECTRIC = 2 };
 enum { PT_MODE_MEGA = 0, PT_MODE_WAVE = 1 };
 
+/* Camera samplers (pt_render_args.sampler). */
+enum { PT_SAMPLER_PHILOX = 0, PT_SAMPLER_HALTON = 1 };
+
 /* Render flags (pt_render_args.flags). */
 enum {
     PT_FLAG_PROFILE = 1,       /* time every stage launch with HIP events */
@@ -145,7 +148,14 @@ typedef struct {
  * shade stage (0 = off; the image is the same bit for bit);
  * tail_bounce: when > 0, the hybrid tail finishes every path still running
  * at bounce tail_bounce (1 .. max_depth) whatever the queue size, and no
- * stage of a later bounce is enqueued (0 = off; same image bit for bit). */
+ * stage of a later bounce is enqueued (0 = off; same image bit for bit);
+ * sampler: camera jitter, PT_SAMPLER_PHILOX (words of the path's counter)
+ * or PT_SAMPLER_HALTON (the ray generation sampler of Sec. 2.3: the
+ * Halton(2,3) point of the pixel's sample index frame*spp + s, radical
+ * inverses truncated to 24 bits, Cranley-Patterson rotated per pixel by
+ * 24-bit offsets from the Philox block of the reserved sample index
+ * 0xFFFFFFFF, modulo 1); every later dimension of the path stays Philox.
+ * Any other value is PT_EINVAL. */
 typedef struct {
     int32_t spp, max_depth;
     uint64_t seed;
@@ -159,6 +169,7 @@ typedef struct {
     int32_t stack_lds;
     uint32_t tail_threshold;
     int32_t tail_bounce;
+    int32_t sampler;
 } pt_render_args;
 
 /* Library version (major * 10000 + minor * 100 + patch). */

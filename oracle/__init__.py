@@ -43,11 +43,14 @@ def lib():
     L.orc_render.restype = C.c_int32
     L.orc_render.argtypes = [C.c_void_p, f32p, C.c_int32, C.c_int32, i32p, C.c_int32, C.c_int32, C.c_int32,
                              C.c_uint64, C.c_uint32, C.c_uint32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
-                             f32p, C.c_void_p, C.c_void_p]
+                             C.c_int32, f32p, C.c_void_p, C.c_void_p]
     L.orc_backward.restype = C.c_int32
     L.orc_backward.argtypes = [C.c_void_p, f32p, C.c_int32, C.c_int32, i32p, C.c_int32, C.c_int32, C.c_int32,
-                               C.c_uint64, C.c_uint32, C.c_uint32, C.c_int32, C.c_int32, C.c_int32, f32p,
-                               f64p, f64p, C.c_void_p, C.c_void_p]
+                               C.c_uint64, C.c_uint32, C.c_uint32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                               f32p, f64p, f64p, C.c_void_p, C.c_void_p]
+    L.orc_radical_inverse.restype = C.c_float
+    L.orc_radical_inverse.argtypes = [C.c_uint32, C.c_int32]
+    L.orc_halton_jitter.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, f32p]
     L.orc_closest.argtypes = [C.c_void_p, C.c_int32, f32p, f32p, C.c_float, C.c_int32, f32p, i32p, f32p, f32p]
     L.orc_anyhit.argtypes = [C.c_void_p, C.c_int32, f32p, f32p, C.c_float, C.c_int32, u8p]
     L.orc_tri_test.restype = C.c_int32
@@ -129,7 +132,7 @@ class Scene:
         return lib().orc_pick_light(self.ptr, int(w))
 
     def render(self, cam, pixels=None, spp=1, max_depth=5, seed=0, frame=0, job=0, nee=True,
-               rr_start=-1, use_bvh=None, threads=None, per_sample=False):
+               rr_start=-1, use_bvh=None, threads=None, per_sample=False, sampler=0):
         """Returns (rgb [n,3], fragile [n] bool[, per-sample L [n, spp, 3]])."""
         W, H = int(cam["width"]), int(cam["height"])
         if pixels is None:
@@ -144,8 +147,9 @@ class Scene:
         if threads is None:
             threads = os.cpu_count() or 1
         rc = lib().orc_render(self.ptr, camera(cam), W, H, pixels, n, int(spp), int(max_depth), int(seed),
-                              int(frame), int(job), int(bool(nee)), int(rr_start), int(use_bvh), int(threads),
-                              out.reshape(-1), frag.ctypes.data, ps.ctypes.data if ps is not None else None)
+                              int(frame), int(job), int(bool(nee)), int(rr_start), int(sampler), int(use_bvh),
+                              int(threads), out.reshape(-1), frag.ctypes.data,
+                              ps.ctypes.data if ps is not None else None)
         if rc != 0:
             raise ValueError(f"orc_render failed ({rc})")
         if per_sample:
@@ -153,7 +157,7 @@ class Scene:
         return out, frag
 
     def backward(self, cam, d_image, pixels=None, spp=1, max_depth=5, seed=0, frame=0, job=0, nee=True,
-                 use_bvh=None, threads=None):
+                 use_bvh=None, threads=None, sampler=0):
         """Returns (g_albedo [nt,3], g_emission [nt,3], abs_albedo, abs_emission), binary64."""
         W, H = int(cam["width"]), int(cam["height"])
         if pixels is None:
@@ -170,8 +174,8 @@ class Scene:
         if threads is None:
             threads = os.cpu_count() or 1
         rc = lib().orc_backward(self.ptr, camera(cam), W, H, pixels, pixels.size, int(spp), int(max_depth),
-                                int(seed), int(frame), int(job), int(bool(nee)), int(use_bvh), int(threads),
-                                d_image, ga, ge, aa.ctypes.data, ae.ctypes.data)
+                                int(seed), int(frame), int(job), int(bool(nee)), int(sampler), int(use_bvh),
+                                int(threads), d_image, ga, ge, aa.ctypes.data, ae.ctypes.data)
         if rc != 0:
             raise ValueError(f"orc_backward failed ({rc})")
         return ga.reshape(-1, 3), ge.reshape(-1, 3), aa.reshape(-1, 3), ae.reshape(-1, 3)
@@ -194,6 +198,20 @@ class Scene:
         occ = np.zeros(n, np.uint8)
         lib().orc_anyhit(self.ptr, n, o, d, float(tmax), int(mode), occ)
         return occ.astype(bool)
+
+
+def radical_inverse(n, base):
+    """phi_base(n) truncated to 24 bits (base 2 or 3)."""
+    if base not in (2, 3):
+        raise ValueError("the sampler's radical inverse has bases 2 and 3")
+    return lib().orc_radical_inverse(int(n), int(base))
+
+
+def halton_jitter(seed, pixel, sample, job=0):
+    """Camera jitter (u0, u1) of the Halton(2,3) sampler with the pixel's rotation."""
+    out = np.zeros(2, np.float32)
+    lib().orc_halton_jitter(int(seed), int(pixel), int(sample), int(job), out)
+    return float(out[0]), float(out[1])
 
 
 def tri_test(o, d, v0, v1, v2):

@@ -96,6 +96,50 @@ static void rng_words(uint64_t seed, uint32_t pixel, uint32_t sample, uint32_t b
 }
 
 /* ------------------------------------------------------------------------ */
+/* Halton(2,3) camera jitter with a per-pixel Cranley-Patterson rotation     */
+/* (the sampler of the paper's wavefront renderer).  The radical inverse     */
+/* phi_b(n) = sum_i d_i b^-(i+1) of the base-b digits d_i of n, truncated to */
+/* 24 bits: an integer q with q 2^-24 <= phi_b(n) < (q + 1) 2^-24.  The      */
+/* rotation adds 24-bit offsets drawn once per pixel (Philox words 0 and 1   */
+/* of the reserved sample index 0xFFFFFFFF) modulo 1.                        */
+/* ------------------------------------------------------------------------ */
+static uint32_t radical_inverse24(uint32_t n, int base)
+{
+    if (base == 2) {
+        uint32_t rev = 0;
+        for (int i = 0; i < 32; ++i) {  /* bit i of n becomes bit 31 - i */
+            rev = (rev << 1) | (n & 1u);
+            n >>= 1;
+        }
+        return rev >> 8;
+    }
+    /* base 3: R = sum_{i<21} d_i 3^(20-i) (3^21 > 2^32, so every digit of a
+     * 32-bit n is included), phi_3(n) = R / 3^21 exactly */
+    uint64_t R = 0, p21 = 1;
+    for (int i = 0; i < 21; ++i) {
+        R = R * 3u + (n % 3u);
+        n /= 3u;
+        p21 *= 3u;
+    }
+    return (uint32_t)((R << 24) / p21);
+}
+
+float orc_radical_inverse(uint32_t n, int32_t base)
+{
+    return (float)radical_inverse24(n, base == 2 ? 2 : 3) * 0x1p-24f;
+}
+
+void orc_halton_jitter(uint64_t seed, uint32_t pixel, uint32_t sample, uint32_t job, float out[2])
+{
+    uint32_t w[8];
+    rng_words(seed, pixel, 0xFFFFFFFFu, 0, job, w);
+    const uint32_t u0 = (radical_inverse24(sample, 2) + (w[0] >> 8)) & 0xFFFFFFu;
+    const uint32_t u1 = (radical_inverse24(sample, 3) + (w[1] >> 8)) & 0xFFFFFFu;
+    out[0] = (float)u0 * 0x1p-24f;
+    out[1] = (float)u1 * 0x1p-24f;
+}
+
+/* ------------------------------------------------------------------------ */
 /* scene                                                                     */
 /* ------------------------------------------------------------------------ */
 typedef struct {
@@ -906,6 +950,7 @@ typedef struct {
     int W, H, D, nee, rr_start, use_bvh;
     uint64_t seed;
     uint32_t job;
+    int sampler; /* camera jitter: 0 Philox, 1 Halton(2,3) + rotation */
 } pt_args;
 
 static float maxc(v3 a) { float m = a.x > a.y ? a.x : a.y; return m > a.z ? m : a.z; }
@@ -921,7 +966,9 @@ static v3 trace_path(const pt_args* a, int pix, uint32_t sample, int* frag, vrec
     rng_words(a->seed, (uint32_t)pix, sample, 0, a->job, w);
     ray_t r;
     v3 o, d;
-    camera_ray(a->cam, a->W, a->H, px, py, orc_unif(w[0]), orc_unif(w[1]), &o, &d);
+    float jit[2] = {orc_unif(w[0]), orc_unif(w[1])};
+    if (a->sampler == 1) orc_halton_jitter(a->seed, (uint32_t)pix, sample, a->job, jit);
+    camera_ray(a->cam, a->W, a->H, px, py, jit[0], jit[1], &o, &d);
     ray_setup(&r, o, d);
     float p_prev = 0.0f;
     int prev_smooth = 0; /* previous vertex sampled a light (MIS applies) */
@@ -1099,13 +1146,14 @@ static int run_threads(job_t* base, int threads, void* (*fn)(void*))
 int32_t orc_render(const orc_scene* s, const float cam[12], int32_t width, int32_t height,
                    const int32_t* pixels, int32_t n, int32_t spp, int32_t max_depth,
                    uint64_t seed, uint32_t frame, uint32_t job, int32_t nee, int32_t rr_start,
-                   int32_t use_bvh, int32_t threads, float* out, uint8_t* fragile,
+                   int32_t sampler, int32_t use_bvh, int32_t threads, float* out, uint8_t* fragile,
                    float* per_sample)
 {
     if (!s || width <= 0 || height <= 0 || spp <= 0 || max_depth < 0 || n < 0) return -1;
+    if (sampler != 0 && sampler != 1) return -1;
     for (int i = 0; i < n; ++i)
         if (pixels[i] < 0 || pixels[i] >= width * height) return -1;
-    pt_args a = {s, cam, width, height, max_depth, nee, rr_start, use_bvh, seed, job};
+    pt_args a = {s, cam, width, height, max_depth, nee, rr_start, use_bvh, seed, job, sampler};
     job_t b;
     memset(&b, 0, sizeof b);
     b.a = &a; b.pixels = pixels; b.n = n; b.spp = spp; b.frame = frame;
@@ -1211,18 +1259,19 @@ static void* backward_worker(void* p)
 
 int32_t orc_backward(const orc_scene* s, const float cam[12], int32_t width, int32_t height,
                      const int32_t* pixels, int32_t n, int32_t spp, int32_t max_depth,
-                     uint64_t seed, uint32_t frame, uint32_t job, int32_t nee, int32_t use_bvh,
-                     int32_t threads, const float* d_image, double* g_albedo,
+                     uint64_t seed, uint32_t frame, uint32_t job, int32_t nee, int32_t sampler,
+                     int32_t use_bvh, int32_t threads, const float* d_image, double* g_albedo,
                      double* g_emission, double* abs_albedo, double* abs_emission)
 {
     if (!s || width <= 0 || height <= 0 || spp <= 0 || max_depth < 0 || n < 0) return -1;
+    if (sampler != 0 && sampler != 1) return -1;
     if (max_depth + 2 > MAX_VERTS) return -1;
     for (int i = 0; i < n; ++i)
         if (pixels[i] < 0 || pixels[i] >= width * height) return -1;
     if (threads < 1) threads = 1;
     if (threads > 256) threads = 256;
     size_t m = 3 * (size_t)s->nt;
-    pt_args a = {s, cam, width, height, max_depth, nee, -1, use_bvh, seed, job};
+    pt_args a = {s, cam, width, height, max_depth, nee, -1, use_bvh, seed, job, sampler};
     pthread_t th[256];
     job_t jobs[256];
     for (int t = 0; t < threads; ++t) {

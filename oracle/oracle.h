@@ -61,11 +61,14 @@ void orc_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4
  * the pixel's paths was within rounding distance of flipping.
  * per_sample (may be NULL): n*spp*3 floats, L of each sample.
  * use_bvh: 0 = brute force, 1 = oracle BVH.  rr_start < 0 disables roulette.
+ * sampler: camera jitter of sample n of a pixel, 0 = Philox words 0, 1 of
+ * the path's first block, 1 = Halton(2,3) point n with the pixel's
+ * Cranley-Patterson rotation (orc_halton_jitter).
  * Returns 0 or a negative error code. */
 int32_t orc_render(const orc_scene* s, const float cam[12], int32_t width, int32_t height,
                    const int32_t* pixels, int32_t n, int32_t spp, int32_t max_depth,
                    uint64_t seed, uint32_t frame, uint32_t job, int32_t nee, int32_t rr_start,
-                   int32_t use_bvh, int32_t threads, float* out, uint8_t* fragile,
+                   int32_t sampler, int32_t use_bvh, int32_t threads, float* out, uint8_t* fragile,
                    float* per_sample);
 
 /* Gradient of sum_p sum_c d_image[p,c] * I(p,c) with respect to per-triangle
@@ -75,9 +78,16 @@ int32_t orc_render(const orc_scene* s, const float cam[12], int32_t width, int32
  * Roulette must be off (its survival probability depends on albedo). */
 int32_t orc_backward(const orc_scene* s, const float cam[12], int32_t width, int32_t height,
                      const int32_t* pixels, int32_t n, int32_t spp, int32_t max_depth,
-                     uint64_t seed, uint32_t frame, uint32_t job, int32_t nee, int32_t use_bvh,
-                     int32_t threads, const float* d_image, double* g_albedo,
+                     uint64_t seed, uint32_t frame, uint32_t job, int32_t nee, int32_t sampler,
+                     int32_t use_bvh, int32_t threads, const float* d_image, double* g_albedo,
                      double* g_emission, double* abs_albedo, double* abs_emission);
+
+/* Radical inverse of n in base 2 or 3, truncated to 24 bits (exact integer
+ * digit reversal, so the value is q 2^-24 with q 2^-24 <= phi_b(n)). */
+float orc_radical_inverse(uint32_t n, int32_t base);
+/* Camera jitter of sample `sample` of `pixel` with sampler 1: the Halton
+ * (2,3) point of that index rotated by the pixel's offsets, modulo 1. */
+void orc_halton_jitter(uint64_t seed, uint32_t pixel, uint32_t sample, uint32_t job, float out[2]);
 
 /* Closest hit (mode 0 brute force, 1 BVH) for n rays o[3n], d[3n] with
  * t in (0, tmax).  prim = -1 on a miss. */

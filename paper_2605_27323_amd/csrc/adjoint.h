@@ -25,9 +25,8 @@ PT_DEV void adjoint_path(const SceneView& sc, const CamView& cam, const PathPara
                          Acc& acc) {
     uint32_t ne = 0, ns = 0;
     const f3 Ltot = trace_path<LDS>(sc, cam, pp, pix, sample, st, ne, ns);
-    Rng8 r0 = philox8(pp.seed, pix, sample, 0u, pp.job);
     f3 o, d;
-    camera_ray(cam, (int)(pix % (uint32_t)cam.W), (int)(pix / (uint32_t)cam.W), unif(r0.w[0]), unif(r0.w[1]), o, d);
+    camera_sample(cam, pp, pix, sample, o, d);
     PathState ps;
     ps.beta = mk3(1.f, 1.f, 1.f);
     ps.L = mk3(0.f, 0.f, 0.f);

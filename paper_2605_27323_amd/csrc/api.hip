@@ -163,6 +163,8 @@ pt_status check_args(const pt_ctx* c, const pt_render_args* a) {
     if (a->max_depth < 0 || a->max_depth > 1000) return fail(PT_EINVAL, "max_depth must be in [0, 1000]");
     if (a->tail_bounce < 0 || a->tail_bounce > a->max_depth)
         return fail(PT_EINVAL, "tail_bounce must be in [0, max_depth]");
+    if (a->sampler != PT_SAMPLER_PHILOX && a->sampler != PT_SAMPLER_HALTON)
+        return fail(PT_EINVAL, "sampler must be PT_SAMPLER_PHILOX or PT_SAMPLER_HALTON");
     if (a->mode != PT_MODE_MEGA && a->mode != PT_MODE_WAVE) return fail(PT_EINVAL, "unknown mode");
     const uint64_t npaths = (uint64_t)c->cam.W * c->cam.H * a->spp;
     if (npaths >= 0xFFFFFFFFull) return fail(PT_EINVAL, "width * height * spp must be < 2^32 - 1");
@@ -222,7 +224,7 @@ pt_status enqueue_stages(pt_ctx* c, const pt_render_args* a, const Launch& L, co
     uint32_t* counts = reinterpret_cast<uint32_t*>(base + w.counts);
     unsigned long long* trav = reinterpret_cast<unsigned long long*>(base + w.trav);
     uint2* ovf = reinterpret_cast<uint2*>(base + w.ovf);
-    PathParams pp{a->spp, a->max_depth, a->nee ? 1 : 0, a->rr_start, a->seed, a->frame, a->job};
+    PathParams pp{a->spp, a->max_depth, a->nee ? 1 : 0, a->rr_start, a->seed, a->frame, a->job, a->sampler};
     dim3 grid(L.grid), block(L.block);
     const bool count = (a->flags & PT_FLAG_COUNT_WORK) != 0;
     PT_HIP(launch_init_counts(s, reinterpret_cast<uint32_t*>(trav), kTravWords, 0u), "init work counters");
@@ -539,7 +541,7 @@ pt_status pt_render_frame(pt_ctx* c, const pt_render_args* a, float* img, float*
     st = enqueue_stages(c, a, L, w, static_cast<char*>(ws), s, img, acc, prof, &Lbuf);
     if (st) return st;
     if (a->mode == PT_MODE_WAVE) {
-        PathParams pp{a->spp, a->max_depth, a->nee ? 1 : 0, a->rr_start, a->seed, a->frame, a->job};
+        PathParams pp{a->spp, a->max_depth, a->nee ? 1 : 0, a->rr_start, a->seed, a->frame, a->job, a->sampler};
         PT_HIP(timed(c, prof, 4, s, [&] { return launch_accumulate(dim3(L.grid), dim3(L.block), s, c->cam, pp, Lbuf, img, acc); }), "accumulate");
     }
     return PT_OK;
@@ -604,7 +606,7 @@ pt_status pt_render_frames(pt_ctx* c, const pt_render_args* a, int32_t n_frames,
         if (st) return st;
         PT_HIP(hipEventRecord(c->ev_stage[k], c->aux[k]), "record event");
         PT_HIP(hipStreamWaitEvent(s, c->ev_stage[k], 0), "stream wait");
-        PathParams pp{af.spp, af.max_depth, af.nee ? 1 : 0, af.rr_start, af.seed, af.frame, af.job};
+        PathParams pp{af.spp, af.max_depth, af.nee ? 1 : 0, af.rr_start, af.seed, af.frame, af.job, af.sampler};
         if (a->mode == PT_MODE_WAVE) PT_HIP(launch_accumulate(dim3(L.grid), dim3(L.block), s, c->cam, pp, Lbuf, img, acc), "accumulate");
         else PT_HIP(launch_average(dim3(L.grid), dim3(L.block), s, frame_img, npix, af.frame, img, acc), "average");
         PT_HIP(hipEventRecord(c->ev_acc[k], s), "record event");
@@ -633,7 +635,7 @@ pt_status pt_render_backward(pt_ctx* c, const pt_render_args* a, const float* d_
     uint32_t* counts = reinterpret_cast<uint32_t*>(base + w.counts);
     unsigned long long* trav = reinterpret_cast<unsigned long long*>(base + w.trav);
     uint2* ovf = reinterpret_cast<uint2*>(base + w.ovf);
-    PathParams pp{a->spp, a->max_depth, a->nee ? 1 : 0, -1, a->seed, a->frame, a->job};
+    PathParams pp{a->spp, a->max_depth, a->nee ? 1 : 0, -1, a->seed, a->frame, a->job, a->sampler};
     const bool prof = (a->flags & PT_FLAG_PROFILE) != 0;
     c->timers.clear();
     c->event_next = 0;
@@ -767,7 +769,7 @@ pt_status plan_batch(const pt_job* jobs, int32_t n, const pt_batch_opts* o, Batc
         d.sc = jb.ctx->view;
         d.cam = jb.ctx->cam;
         d.pp = PathParams{jb.args.spp, jb.args.max_depth, jb.args.nee ? 1 : 0, jb.args.rr_start, jb.args.seed,
-                          jb.args.frame, jb.args.job};
+                          jb.args.frame, jb.args.job, jb.args.sampler};
         d.img = jb.image_out;
         d.npaths = (uint32_t)((uint64_t)d.cam.W * d.cam.H * jb.args.spp);
         d.npix = (uint32_t)((uint64_t)d.cam.W * d.cam.H);

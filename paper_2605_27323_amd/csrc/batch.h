@@ -94,10 +94,8 @@ PT_DEV void batch_regen_item(const BatchBufs& bb, int q, uint32_t i) {
     const uint32_t pix = local / (uint32_t)jd.pp.spp;
     const uint32_t s = local - pix * (uint32_t)jd.pp.spp;
     const uint32_t sample = jd.pp.frame * (uint32_t)jd.pp.spp + s;
-    Rng8 r0 = philox8(jd.pp.seed, pix, sample, 0u, jd.pp.job);
     f3 o, d;
-    camera_ray(jd.cam, (int)(pix % (uint32_t)jd.cam.W), (int)(pix / (uint32_t)jd.cam.W), unif(r0.w[0]), unif(r0.w[1]),
-               o, d);
+    camera_sample(jd.cam, jd.pp, pix, sample, o, d);
     bb.ray_o[q][slot] = make_float4(o.x, o.y, o.z, u2f(g));
     bb.ray_d[q][slot] = make_float4(d.x, d.y, d.z, 0.f);
     bb.pst[q][slot] = make_float4(1.f, 1.f, 1.f, u2f(meta_pack(1u, 0u, (uint32_t)j)));

@@ -141,6 +141,40 @@ PT_DEV void camera_ray(const CamView& cam, int px, int py, float u0, float u1, f
     d = normalize3(dd);
 }
 
+// Radical inverse phi_b(n) = sum_i d_i b^-(i+1) of the base-b digits of n
+// (b = 2 or 3), truncated to 24 bits: q with q 2^-24 <= phi_b(n).  Base 2
+// reverses the bits; base 3 forms R = sum_{i<21} d_i 3^(20-i) (3^21 > 2^32
+// covers every digit of a 32-bit n), so phi_3(n) = R / 3^21 exactly.
+PT_DEV uint32_t radical_inverse24(uint32_t n, int base) {
+    if (base == 2) return __builtin_bitreverse32(n) >> 8;
+    uint64_t R = 0;
+#pragma unroll
+    for (int i = 0; i < 21; ++i) {
+        R = R * 3u + (n % 3u);
+        n /= 3u;
+    }
+    return (uint32_t)((R << 24) / 10460353203ull);  // 3^21
+}
+
+// Camera ray of sample `sample` of pixel `pix`.  The pixel jitter is Philox
+// words 0, 1 of the path's first block, or with sampler 1 (the paper's
+// wavefront sampler) the Halton(2,3) point of the sample index rotated by
+// the pixel's Cranley-Patterson offsets (words 0, 1 of the reserved sample
+// index 0xFFFFFFFF), modulo 1 on the 2^-24 grid.
+PT_DEV void camera_sample(const CamView& cam, const PathParams& pp, uint32_t pix, uint32_t sample, f3& o, f3& d) {
+    float u0, u1;
+    if (pp.sampler == 1) {
+        const Rng8 c = philox8(pp.seed, pix, 0xFFFFFFFFu, 0u, pp.job);
+        u0 = (float)((radical_inverse24(sample, 2) + (c.w[0] >> 8)) & 0xFFFFFFu) * 0x1p-24f;
+        u1 = (float)((radical_inverse24(sample, 3) + (c.w[1] >> 8)) & 0xFFFFFFu) * 0x1p-24f;
+    } else {
+        const Rng8 r0 = philox8(pp.seed, pix, sample, 0u, pp.job);
+        u0 = unif(r0.w[0]);
+        u1 = unif(r0.w[1]);
+    }
+    camera_ray(cam, (int)(pix % (uint32_t)cam.W), (int)(pix / (uint32_t)cam.W), u0, u1, o, d);
+}
+
 // ---------------------------------------------------------------------------
 // rays: watertight triangle test (Woop, Benthin, Wald, JCGT 2013)
 // ---------------------------------------------------------------------------
@@ -1088,9 +1122,7 @@ struct PathRun {
 };
 
 PT_DEV void path_begin(const CamView& cam, const PathParams& pp, uint32_t pix, uint32_t sample, PathRun& pr) {
-    Rng8 r0 = philox8(pp.seed, pix, sample, 0u, pp.job);
-    camera_ray(cam, (int)(pix % (uint32_t)cam.W), (int)(pix / (uint32_t)cam.W), unif(r0.w[0]), unif(r0.w[1]), pr.o,
-               pr.d);
+    camera_sample(cam, pp, pix, sample, pr.o, pr.d);
     pr.ps.beta = mk3(1.f, 1.f, 1.f);
     pr.ps.L = mk3(0.f, 0.f, 0.f);
     pr.ps.p_prev = 0.f;

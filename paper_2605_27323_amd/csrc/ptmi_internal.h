@@ -72,6 +72,7 @@ struct PathParams {
     int32_t spp, D, nee, rr_start;
     uint64_t seed;
     uint32_t frame, job;
+    int32_t sampler;  // camera jitter: 0 Philox, 1 Halton(2,3) with a per-pixel rotation
 };
 
 }  // namespace ptmi

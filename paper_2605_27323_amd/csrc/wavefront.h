@@ -30,9 +30,8 @@ PT_DEV void raygen_item(const CamView& cam, const PathParams& pp, const WaveBufs
     const uint32_t pix = p / (uint32_t)pp.spp;
     const uint32_t s = p - pix * (uint32_t)pp.spp;
     const uint32_t sample = pp.frame * (uint32_t)pp.spp + s;
-    Rng8 r0 = philox8(pp.seed, pix, sample, 0u, pp.job);
     f3 o, d;
-    camera_ray(cam, (int)(pix % (uint32_t)cam.W), (int)(pix / (uint32_t)cam.W), unif(r0.w[0]), unif(r0.w[1]), o, d);
+    camera_sample(cam, pp, pix, sample, o, d);
     wb.ray_o[0][p] = make_float4(o.x, o.y, o.z, u2f(p));
     wb.ray_d[0][p] = make_float4(d.x, d.y, d.z, 0.f);
     wb.pst[0][p] = make_float4(1.f, 1.f, 1.f, u2f(0u));

@@ -18,6 +18,7 @@ LIB_PATH = os.environ.get("PTMI_LIB") or os.path.join(HERE, "libptmi.so")
 PT_OK, PT_EINVAL, PT_ENOMEM, PT_EHIP, PT_ESTATE, PT_EOVERFLOW, PT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 MODE_MEGA, MODE_WAVE = 0, 1
 FLAG_PROFILE, FLAG_NO_COMPACT, FLAG_SORT_MATERIAL, FLAG_COUNT_WORK, FLAG_SORT_RAYS = 1, 2, 4, 8, 16
+SAMPLER_PHILOX, SAMPLER_HALTON = 0, 1
 STAGES = ["raygen", "extend", "shade", "shadow", "accumulate", "mega", "sort", "adjoint", "tail"]
 
 
@@ -59,7 +60,7 @@ class RenderArgs(C.Structure):
                 ("job", C.c_uint32), ("nee", C.c_int32), ("rr_start", C.c_int32), ("mode", C.c_int32),
                 ("flags", C.c_int32), ("block", C.c_int32), ("grid_mult", C.c_int32),
                 ("sort_threshold", C.c_uint32), ("stack_lds", C.c_int32), ("tail_threshold", C.c_uint32),
-                ("tail_bounce", C.c_int32)]
+                ("tail_bounce", C.c_int32), ("sampler", C.c_int32)]
 
 
 NSTAGES = 9
@@ -237,11 +238,15 @@ class Renderer(Context):
         self.width, self.height = int(cam["width"]), int(cam["height"])
 
     def args(self, spp=1, max_depth=5, seed=0, frame=0, job=0, nee=True, rr_start=-1, mode="wave", flags=0,
-             block=0, grid_mult=0, sort_threshold=0, stack_lds=0, tail_threshold=0, tail_bounce=0):
+             block=0, grid_mult=0, sort_threshold=0, stack_lds=0, tail_threshold=0, tail_bounce=0,
+             sampler="philox"):
         m = MODE_WAVE if mode in ("wave", MODE_WAVE) else MODE_MEGA
+        if sampler not in ("philox", "halton", SAMPLER_PHILOX, SAMPLER_HALTON):
+            raise ValueError(f"unknown sampler {sampler!r} (philox or halton)")
+        smp = SAMPLER_HALTON if sampler in ("halton", SAMPLER_HALTON) else SAMPLER_PHILOX
         return RenderArgs(int(spp), int(max_depth), int(seed), int(frame), int(job), int(bool(nee)), int(rr_start), m,
                           int(flags), int(block), int(grid_mult), int(sort_threshold), int(stack_lds),
-                          int(tail_threshold), int(tail_bounce))
+                          int(tail_threshold), int(tail_bounce), smp)
 
     def workspace(self, a):
         need = C.c_uint64()

@@ -48,11 +48,11 @@ def lib():
         L = C.CDLL(LIB)
         L.emu_render_mega.restype = C.c_int32
         L.emu_render_mega.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_uint64,
-                                      C.c_uint32, C.c_uint32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]
+                                      C.c_uint32, C.c_uint32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32]
         L.emu_render_wave.restype = C.c_int32
         L.emu_render_wave.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, C.c_uint32, C.c_uint32,
                                       C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.c_int32, C.c_uint32, C.c_void_p,
-                                      C.c_void_p]
+                                      C.c_void_p, C.c_int32]
         L.emu_closest.restype = C.c_int32
         L.emu_closest.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_void_p, C.c_void_p]
@@ -60,7 +60,7 @@ def lib():
         L.emu_render_batch.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_uint32, C.c_uint64, C.c_void_p]
         L.emu_backward.restype = C.c_int32
         L.emu_backward.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int32,
-                                   C.c_void_p, C.c_void_p, C.c_void_p]
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]
         for name, (res, args) in ptmi.SIGNATURES.items():
             f = getattr(L, name)
             f.restype = res
@@ -106,34 +106,34 @@ class Emu:
                                  b1.ctypes.data, b2.ctypes.data) == 0
         return t, i, b1, b2
 
-    def mega(self, pixels=None, spp=1, max_depth=5, seed=0, frame=0, job=0, nee=True, rr_start=-1):
+    def mega(self, pixels=None, spp=1, max_depth=5, seed=0, frame=0, job=0, nee=True, rr_start=-1, sampler=0):
         if pixels is None:
             pixels = np.arange(self.W * self.H, dtype=np.int32)
         pixels = np.ascontiguousarray(pixels, np.int32)
         out = np.zeros((pixels.size, 3), np.float32)
         rays = np.zeros(2, np.uint64)
         rc = lib().emu_render_mega(self.h, pixels.ctypes.data, pixels.size, spp, max_depth, seed, frame, job,
-                                   int(bool(nee)), rr_start, out.ctypes.data, rays.ctypes.data)
+                                   int(bool(nee)), rr_start, out.ctypes.data, rays.ctypes.data, int(sampler))
         assert rc == 0
         return out, rays
 
     def wave(self, spp=1, max_depth=5, seed=0, frame=0, job=0, nee=True, rr_start=-1, compact=True, shuffle=0,
-             sort=False, tail=0):
+             sort=False, tail=0, sampler=0):
         img = np.zeros((self.W * self.H, 3), np.float32)
         rays = np.zeros(2, np.uint64)
         rc = lib().emu_render_wave(self.h, spp, max_depth, seed, frame, job, int(bool(nee)), rr_start,
                                    int(bool(compact)), shuffle, int(bool(sort)), int(tail), img.ctypes.data,
-                                   rays.ctypes.data)
+                                   rays.ctypes.data, int(sampler))
         assert rc == 0
         return img, rays
 
-    def backward(self, d_image, spp=1, max_depth=5, seed=0, frame=0, job=0, nee=True):
+    def backward(self, d_image, spp=1, max_depth=5, seed=0, frame=0, job=0, nee=True, sampler=0):
         d_image = np.ascontiguousarray(d_image, np.float32).reshape(-1, 3)
         nt = self._keep["indices"].shape[0]
         ga = np.zeros((max(nt, 1), 3), np.float32)
         ge = np.zeros((max(nt, 1), 3), np.float32)
         rc = lib().emu_backward(self.h, spp, max_depth, seed, frame, job, int(bool(nee)), d_image.ctypes.data,
-                                ga.ctypes.data, ge.ctypes.data)
+                                ga.ctypes.data, ge.ctypes.data, int(sampler))
         assert rc == 0
         return ga[:nt], ge[:nt]
 
@@ -152,10 +152,10 @@ def render_batch(emus, job_args, capacity, shuffle=0):
     args = (ptmi.RenderArgs * n)()
     total_pix = 0
     for j, (e, kw) in enumerate(zip(emus, job_args)):
-        a = dict(spp=1, max_depth=5, seed=0, frame=0, job=j, nee=True, rr_start=-1)
+        a = dict(spp=1, max_depth=5, seed=0, frame=0, job=j, nee=True, rr_start=-1, sampler=0)
         a.update(kw)
         args[j] = ptmi.RenderArgs(a["spp"], a["max_depth"], a["seed"], a["frame"], a["job"], int(bool(a["nee"])),
-                                  a["rr_start"], 1, 0, 0, 0, 0)
+                                  a["rr_start"], 1, 0, 0, 0, 0, sampler=int(a["sampler"]))
         total_pix += e.W * e.H
     img = np.zeros((total_pix, 3), np.float32)
     it = lib().emu_render_batch(ctxs, args, n, capacity, shuffle, img.ctypes.data)

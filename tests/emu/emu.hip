@@ -55,9 +55,10 @@ extern "C" {
 // Megakernel body for the listed pixels: out[n*3].  rays[2] = extension
 // and shadow ray counts.  Returns 0, or 1 if a traversal stack overflowed.
 int32_t emu_render_mega(pt_ctx* c, const int32_t* pixels, int32_t n, int32_t spp, int32_t D, uint64_t seed,
-                        uint32_t frame, uint32_t job, int32_t nee, int32_t rr_start, float* out, uint64_t* rays) {
+                        uint32_t frame, uint32_t job, int32_t nee, int32_t rr_start, float* out, uint64_t* rays,
+                        int32_t sampler) {
     SceneView sc = host_view(c);
-    PathParams pp{spp, D, nee ? 1 : 0, rr_start, seed, frame, job};
+    PathParams pp{spp, D, nee ? 1 : 0, rr_start, seed, frame, job, sampler};
     HostStack hs(std::max(0, c->bvh.stack_entries - kL));
     uint64_t ne = 0, ns = 0;
     for (int32_t i = 0; i < n; ++i) {
@@ -102,9 +103,9 @@ int32_t emu_closest(pt_ctx* c, int32_t n, const float* o, const float* d, float*
 // every continuation and shadow queue.  compact = 0 keeps dead slots.
 int32_t emu_render_wave(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32_t frame, uint32_t job, int32_t nee,
                         int32_t rr_start, int32_t compact, uint64_t shuffle_seed, int32_t sort, uint32_t tail,
-                        float* img, uint64_t* rays) {
+                        float* img, uint64_t* rays, int32_t sampler) {
     SceneView sc = host_view(c);
-    PathParams pp{spp, D, nee ? 1 : 0, rr_start, seed, frame, job};
+    PathParams pp{spp, D, nee ? 1 : 0, rr_start, seed, frame, job, sampler};
     const uint32_t npaths = (uint32_t)c->cam.W * c->cam.H * (uint32_t)spp;
     std::vector<float4> buf[11];
     for (auto& b : buf) b.assign(std::max<uint32_t>(npaths, 1), make_float4(0, 0, 0, 0));
@@ -202,7 +203,7 @@ int32_t emu_render_wave(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32
 // Path-replay adjoint over the whole image (sequential binary32 adds):
 // g_alb, g_emi (nt*3) are accumulated into.
 int32_t emu_backward(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32_t frame, uint32_t job, int32_t nee,
-                     const float* d_img, float* g_alb, float* g_emi) {
+                     const float* d_img, float* g_alb, float* g_emi, int32_t sampler) {
     struct HostAcc {
         void add(float* p, float v) {
             if (v != 0.0f) *p += v;
@@ -210,7 +211,7 @@ int32_t emu_backward(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32_t 
         void add_light(uint32_t, int, float* p, float v) { add(p, v); }
     } acc;
     SceneView sc = host_view(c);
-    PathParams pp{spp, D, nee ? 1 : 0, -1, seed, frame, job};
+    PathParams pp{spp, D, nee ? 1 : 0, -1, seed, frame, job, sampler};
     HostStack hs(std::max(0, c->bvh.stack_entries - kL));
     const uint32_t npaths = (uint32_t)c->cam.W * c->cam.H * (uint32_t)spp;
     const float fs = (float)spp;
@@ -235,7 +236,7 @@ int64_t emu_render_batch(pt_ctx** ctxs, const pt_render_args* args, int32_t n, u
         d.sc = host_view(ctxs[j]);
         d.cam = ctxs[j]->cam;
         d.pp = PathParams{args[j].spp, args[j].max_depth, args[j].nee ? 1 : 0, args[j].rr_start, args[j].seed,
-                          args[j].frame, args[j].job};
+                          args[j].frame, args[j].job, args[j].sampler};
         d.npix = (uint32_t)d.cam.W * d.cam.H;
         d.npaths = d.npix * (uint32_t)args[j].spp;
         d.img = img + 3 * total_pix;

@@ -192,3 +192,26 @@ def test_far_camera():
         cam = dict(eye=(0.3 * dist, 0.2 * dist, -dist), target=(0, 0, 0), up=(0, 1, 0),
                    vfov_deg=60.0 * 5.0 / dist, width=16, height=12)
         _check(scene, cam, spp=2, max_depth=4)
+
+
+def test_halton_sampler_matches_oracle():
+    # the device code's radical inverses and rotation against the oracle's:
+    # same camera rays, so the same images bit for bit; wave = mega; the
+    # adjoint replays the same camera rays; the batch pool carries the sampler
+    scene, cam = scenes.procedural(seed=23, n_objects=30, width=45, height=29)
+    cfg = dict(spp=6, max_depth=5, rr_start=3, seed=3, frame=7, sampler=1)
+    E, img, rays, nexact = _check(scene, cam, **cfg)
+    assert nexact >= 0.999 * img.shape[0]
+    philox, _ = E.mega(**dict(cfg, sampler=0))
+    assert not np.array_equal(img, philox)
+    w, rw = E.wave(shuffle=4, tail=300, **cfg)
+    assert np.array_equal(w.view(np.uint32), img.view(np.uint32))
+    assert (rw == rays).all()
+    rng = np.random.default_rng(1)
+    d = rng.normal(size=(cam["width"] * cam["height"], 3)).astype(np.float32)
+    ga, ge = E.backward(d, spp=2, max_depth=4, seed=3, sampler=1)
+    oa, oe, aa, ae = oracle.Scene(scene).backward(cam, d, spp=2, max_depth=4, seed=3, sampler=1)
+    for g, o, a in [(ga, oa, aa), (ge, oe, ae)]:
+        assert (np.abs(g - o) <= 1e-4 * a + 1e-7 * np.abs(o).max()).all()
+    imgs, _ = emu.render_batch([E], [dict(cfg, job=0)], 500, shuffle=2)
+    assert np.array_equal(imgs[0].view(np.uint32), E.mega(**cfg)[0].view(np.uint32))

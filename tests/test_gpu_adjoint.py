@@ -178,3 +178,17 @@ def test_adam_recovers_perturbed_albedo():
     log("albedo error over", len(seen), "triangles:", e0, "->", e1)
     assert len(seen) >= 12
     assert e1 < 0.5 * e0
+
+
+def test_adjoint_halton_sampler_vs_oracle():
+    scene, cam = scenes.procedural(seed=62, n_objects=25, width=64, height=40)
+    log("adjoint halton")
+    R = ptmi.Renderer(scene, cam)
+    d = np.random.default_rng(2).normal(size=(64 * 40, 3)).astype(np.float32)
+    kw = dict(spp=3, max_depth=5, seed=4, frame=2)
+    ga = torch.zeros_like(R.albedo)
+    ge = torch.zeros_like(R.emission)
+    R.backward(torch.from_numpy(d).cuda(), ga, ge, sampler="halton", **kw)
+    ga, ge = ga.cpu().numpy()[:R.nt], ge.cpu().numpy()[:R.nt]
+    oa, oe, aa, ae = oracle.Scene(scene).backward(cam, d, sampler=1, **kw)
+    _grad_check(ga, ge, oa, oe, aa, ae)

@@ -49,3 +49,15 @@ def test_batch_rejects_bad_options():
         ptmi.render_batch(Rs, args, iters_per_graph=3)
     with pytest.raises(ptmi.PtError):
         ptmi.render_batch(Rs, args, pool_capacity=8)
+
+
+def test_batch_mixed_samplers_equal_standalone():
+    log("batch mixed samplers")
+    Rs, args = _jobs()
+    for j, a in enumerate(args):
+        a["sampler"] = "halton" if j % 2 else "philox"
+    imgs, ms, res = ptmi.render_batch(Rs, args, pool_capacity=500, use_graph=True, iters_per_graph=4)
+    torch.cuda.synchronize()
+    for j, (R, kw) in enumerate(zip(Rs, args)):
+        ref = R.render(mode="wave", job=j, **kw).cpu().numpy()
+        assert np.array_equal(imgs[j].cpu().numpy().view(np.uint32), ref.view(np.uint32)), j
