@@ -120,10 +120,12 @@ def tune_frame(renderer, mode="wave", cache=DEFAULT_CACHE, space=None, log=None,
 
     best, _ = successive_halving(cands, measure, log=log)
     if mode == "wave" and space is FRAME_SPACE[mode]:
-        # then the bounce from which the hybrid tail finishes every path
+        # then the bounce from which the hybrid tail finishes every path;
+        # the candidates differ by a few per cent, so each is timed over
+        # as many frames as the last rounds of the first stage
         depth = kw.get("max_depth", 5)
         tbs = [t for t in TAIL_BOUNCES if t <= depth]
-        best, _ = successive_halving([dict(best, tail_bounce=t) for t in tbs], measure, reps0=2, log=log)
+        best, _ = successive_halving([dict(best, tail_bounce=t) for t in tbs], measure, reps0=32, log=log)
     if cache:
         _store(cache, key, best)
     return best
