@@ -20,6 +20,16 @@ u8p = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
 u64p = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
 
 
+def default_threads():
+    """Host threads of an oracle call: the CPUs this process may run on,
+    capped by OMP_NUM_THREADS when it is set (a shared host's share)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cap = os.environ.get("OMP_NUM_THREADS", "")
+    if cap.isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return max(1, n)
+
+
 def lib():
     global _LIB
     if _LIB is not None:
@@ -145,7 +155,7 @@ class Scene:
         if use_bvh is None:
             use_bvh = self.has_bvh
         if threads is None:
-            threads = os.cpu_count() or 1
+            threads = default_threads()
         rc = lib().orc_render(self.ptr, camera(cam), W, H, pixels, n, int(spp), int(max_depth), int(seed),
                               int(frame), int(job), int(bool(nee)), int(rr_start), int(sampler), int(use_bvh),
                               int(threads), out.reshape(-1), frag.ctypes.data,
@@ -172,7 +182,7 @@ class Scene:
         if use_bvh is None:
             use_bvh = self.has_bvh
         if threads is None:
-            threads = os.cpu_count() or 1
+            threads = default_threads()
         rc = lib().orc_backward(self.ptr, camera(cam), W, H, pixels, pixels.size, int(spp), int(max_depth),
                                 int(seed), int(frame), int(job), int(bool(nee)), int(sampler), int(use_bvh),
                                 int(threads), d_image, ga, ge, aa.ctypes.data, ae.ctypes.data)

@@ -117,11 +117,12 @@ def test_full_size_procedural_sampled_pixels():
         assert_parity(wave.reshape(-1, 3)[px], ref, frag, what=f"1M frame {frame}")
         # the launch configurations the benchmark times: frame by frame, and
         # three frames in flight (the last frame of a run ending at `frame`)
-        tuned = R.render(mode="wave", block=256, grid_mult=8, stack_lds=8, tail_threshold=1 << 18, **cfg)
+        tuned = R.render(mode="wave", block=256, grid_mult=8, stack_lds=8, tail_threshold=1 << 18, tail_bounce=4,
+                         **cfg)
         assert np.array_equal(tuned.cpu().numpy().view(np.uint32), wave.view(np.uint32))
         kw = {k: v for k, v in cfg.items() if k != "frame"}
         inflight = R.render_frames(3, mode="wave", frame=frame - 2 if frame >= 2 else 0, block=256, grid_mult=4,
-                                   stack_lds=8, tail_threshold=1 << 19, **kw)
+                                   stack_lds=8, tail_threshold=1 << 18, tail_bounce=3, **kw)
         if frame >= 2:
             assert np.array_equal(inflight.cpu().numpy().view(np.uint32), wave.view(np.uint32))
 
