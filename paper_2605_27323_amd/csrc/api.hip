@@ -231,7 +231,8 @@ pt_status enqueue_stages(pt_ctx* c, const pt_render_args* a, const Launch& L, co
     const uint32_t npaths = (uint32_t)c->cam.W * c->cam.H * a->spp;
     if (a->mode == PT_MODE_MEGA) {
         PT_HIP(launch_init_counts(s, counts, w.ncounts, 0u), "init counters");
-        // counters: [0] extension rays, [1] shadow rays, [2] overflow flag
+        // counters: [0] extension rays, [1] shadow rays, [2] overflow flag, [4..5] the
+        // megakernel's 64-bit pixel cursor
         PT_HIP(timed(c, prof, 5, s, [&] { return launch_mega(L.lds, count, grid, block, s, c->view, c->cam, pp, img, acc, ovf, L.gcap, counts, trav); }), "megakernel");
     } else {
         WaveBufs wb{};

@@ -41,6 +41,9 @@ __device__ __forceinline__ LightCache stage_lights(const SceneView& sc, uint32_t
 // ---------------------------------------------------------------------------
 // megakernel
 // ---------------------------------------------------------------------------
+// pixels a wave takes from the frame's cursor at a time
+constexpr uint32_t kMegaChunk = 64u;
+
 // four waves per SIMD instead of the three the register count would give:
 // a few spilled registers cost less than the lost latency hiding
 template <int LDS, bool COUNT>
@@ -56,14 +59,52 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     const uint32_t npix = (uint32_t)cam.W * (uint32_t)cam.H;
     uint32_t n_ext = 0, n_sh = 0;
     // One loop trip = one path vertex.  A lane whose path ends starts its
-    // next sample (or pixel) on the next trip instead of waiting for the
-    // longest path of its wave; a lane's samples still run in order, so the
-    // per-pixel sum is the same.
-    uint32_t pix = gtid, s = 0;
+    // next sample on the next trip instead of waiting for the longest path
+    // of its wave; a lane whose pixel is done takes the next pixel of its
+    // wave's chunk, and a wave whose chunk is used up takes the next
+    // kMegaChunk pixels from a global cursor (one atomic per chunk), so
+    // lanes and waves stay busy until the frame is drained.  A pixel's
+    // samples still run in order on one lane, so its sum is the same.
+    unsigned long long* cursor = reinterpret_cast<unsigned long long*>(stats + 4);
+    uint32_t next = 0, end = 0;  // this wave's chunk (wave-uniform)
+    bool drained = false;        // the cursor has passed the last pixel (wave-uniform)
+    bool live = false;
+    uint32_t pix = 0, s = 0;
     f3 sum = mk3(0.f, 0.f, 0.f);
     PathRun pr;
     bool started = false;
-    while (pix < npix) {
+    while (true) {
+        const uint64_t idle = __ballot(!live);
+        if (idle != 0ull && !drained) {
+            if (next >= end) {
+                unsigned long long base = 0ull;
+                if (lane_id() == 0) base = atomicAdd(cursor, (unsigned long long)kMegaChunk);
+                base = wave_broadcast_u64(base);
+                if (base >= (unsigned long long)npix) {
+                    drained = true;
+                } else {
+                    next = (uint32_t)base;
+                    end = (uint32_t)min(base + (unsigned long long)kMegaChunk, (unsigned long long)npix);
+                }
+            }
+            if (!drained) {
+                if (!live) {
+                    const uint32_t pos = next + rank_in(idle);
+                    if (pos < end) {
+                        pix = pos;
+                        s = 0;
+                        started = false;
+                        live = true;
+                    }
+                }
+                next = min(next + (uint32_t)__popcll(idle), end);
+            }
+        }
+        if (__ballot(live) == 0ull) {
+            if (drained) break;
+            continue;
+        }
+        if (!live) continue;
         const uint32_t sample = pp.frame * (uint32_t)pp.spp + s;
         if (!started) {
             path_begin(cam, pp, pix, sample, pr);
@@ -75,8 +116,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         if (++s == (uint32_t)pp.spp) {
             const float fs = (float)pp.spp;
             store_pixel(img, acc, pix, mk3(sum.x / fs, sum.y / fs, sum.z / fs), pp.frame);
-            s = 0;
-            pix += nlanes;
+            live = false;
         }
     }
     // ray counts: one atomic per wave for the whole kernel

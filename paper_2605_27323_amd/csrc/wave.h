@@ -33,6 +33,13 @@ __device__ __forceinline__ void wave_add_u64(unsigned long long* dst, uint32_t v
     if (lane_id() == 0 && v) atomicAdd(dst, (unsigned long long)v);
 }
 
+// lane 0's value, in every lane
+__device__ __forceinline__ unsigned long long wave_broadcast_u64(unsigned long long v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+
 // The contiguous chunk [next, end) of a queue of `count` entries owned by
 // this wave in a persistent kernel (waves of the grid in launch order).
 __device__ __forceinline__ void wave_chunk(uint32_t count, uint32_t& next, uint32_t& end) {
