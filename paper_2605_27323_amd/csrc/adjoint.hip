@@ -49,11 +49,22 @@ __global__ void __launch_bounds__(256) k_adjoint(SceneView sc, CamView cam, Path
     __syncthreads();
     const uint32_t npaths = (uint32_t)cam.W * (uint32_t)cam.H * (uint32_t)pp.spp;
     const float fs = (float)pp.spp;
-    for (uint32_t p = gtid; p < npaths; p += nlanes) {
-        const uint32_t pix = p / (uint32_t)pp.spp;
-        const uint32_t s = p - pix * (uint32_t)pp.spp;
-        const f3 delta = mk3(d_img[3 * (size_t)pix] / fs, d_img[3 * (size_t)pix + 1] / fs, d_img[3 * (size_t)pix + 2] / fs);
-        adjoint_path<LDS>(sc, cam, pp, pix, pp.frame * (uint32_t)pp.spp + s, delta, g_alb, g_emi, st, acc);
+    // a wave takes 64 paths at a time from the cursor, so waves whose paths
+    // were short take more of them and all finish together
+    unsigned long long* cursor = reinterpret_cast<unsigned long long*>(stats + 4);
+    while (true) {
+        unsigned long long base = 0ull;
+        if (lane_id() == 0) base = atomicAdd(cursor, 64ull);
+        base = wave_broadcast_u64(base);
+        if (base >= (unsigned long long)npaths) break;
+        const uint32_t p = (uint32_t)base + lane_id();
+        if (p < npaths) {
+            const uint32_t pix = p / (uint32_t)pp.spp;
+            const uint32_t s = p - pix * (uint32_t)pp.spp;
+            const f3 delta =
+                mk3(d_img[3 * (size_t)pix] / fs, d_img[3 * (size_t)pix + 1] / fs, d_img[3 * (size_t)pix + 2] / fs);
+            adjoint_path<LDS>(sc, cam, pp, pix, pp.frame * (uint32_t)pp.spp + s, delta, g_alb, g_emi, st, acc);
+        }
     }
     // every thread of the block is here: add the block's light sums
     __syncthreads();
