@@ -294,6 +294,9 @@ typedef struct {
     int32_t stack_lds;       /* as in pt_render_args (0 = default) */
     int32_t iters_per_graph; /* iterations captured per graph launch, even (0 = 8) */
     int32_t use_graph;       /* 1 = capture and replay a hipGraph, 0 = plain launches */
+    int32_t pools;           /* pools run concurrently, 1..4 (0 = 1): the jobs are split into
+                                pools of about equal path counts, each with pool_capacity / pools
+                                slots, its own stream and graph; no pool may be left without a job */
 } pt_batch_opts;
 
 typedef struct {

@@ -24,8 +24,8 @@ FRAME_SPACE = {
 }
 # tried after the other wave parameters are chosen (0 = off)
 TAIL_BOUNCES = [0, 2, 3, 4, 5, 6]
-BATCH_SPACE = {"pool_capacity": [1 << 20, 1 << 21, 1 << 22], "block": [128, 256], "grid_mult": [4, 8],
-               "stack_lds": [8, 16]}
+BATCH_SPACE = {"pool_capacity": [1 << 21, 1 << 22, 1 << 23], "block": [128, 256], "grid_mult": [4, 8],
+               "stack_lds": [8, 16], "pools": [1, 2, 3]}
 
 
 def _bucket(x):
@@ -145,6 +145,9 @@ def tune_batch(renderers, job_args, cache=DEFAULT_CACHE, space=None, log=None):
     space = space or BATCH_SPACE
     names = list(space)
     cands = [dict(zip(names, vals)) for vals in itertools.product(*(space[n] for n in names))]
+    # every pool needs a job and 64 slots
+    cands = [c for c in cands if c.get("pools", 1) <= len(renderers)
+             and c.get("pool_capacity", 1 << 21) // max(1, c.get("pools", 1)) >= 64]
     # proxy: the same jobs at 1 spp
     proxy = [dict(a, spp=1) for a in job_args]
     ws = [None]

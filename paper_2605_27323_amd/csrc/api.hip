@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "batch.h"
@@ -39,6 +40,7 @@ constexpr int kStackLds = 16;
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+constexpr int kMaxPools = 4;  // concurrent pools of a batched launch
 
 struct StageTimer {
     int stage;
@@ -740,6 +742,7 @@ namespace {
 
 struct BatchPlan {
     std::vector<JobDesc> jobs;
+    std::vector<int> members;  // caller's job index of each job of this pool
     uint64_t total = 0, total_pix = 0;
     int device = -1, num_cu = 256, stack_entries = 1;
     size_t lds_per_block = 160 * 1024;
@@ -750,12 +753,14 @@ struct BatchPlan {
     size_t o_jobs = 0, o_ctl = 0, o_rem = 0, o_ts = 0, o_pool = 0, o_L = 0, o_ovf = 0, total_bytes = 0;
 };
 
-pt_status plan_batch(const pt_job* jobs, int32_t n, const pt_batch_opts* o, BatchPlan& P) {
-    if (!jobs || n < 1) return fail(PT_EINVAL, "need at least one job");
-    if (n > 255) return fail(PT_EINVAL, "at most 255 jobs per batch");
+// one pool: the jobs `members` of the caller's list, `capacity` path slots
+pt_status plan_batch(const pt_job* jobs, const std::vector<int>& members, const pt_batch_opts* o, uint32_t capacity,
+                     BatchPlan& P) {
+    const int n = (int)members.size();
+    P.members = members;
     P.jobs.resize(n);
     for (int j = 0; j < n; ++j) {
-        const pt_job& jb = jobs[j];
+        const pt_job& jb = jobs[members[j]];
         pt_status st = check_args(jb.ctx, &jb.args);
         if (st) return st;
         if (!jb.image_out) return fail(PT_EINVAL, "null job image");
@@ -781,10 +786,7 @@ pt_status plan_batch(const pt_job* jobs, int32_t n, const pt_batch_opts* o, Batc
         if (P.total >= 0xFFFFFFFFull) return fail(PT_EINVAL, "a batch holds fewer than 2^32 - 1 paths");
         P.stack_entries = std::max(P.stack_entries, jb.ctx->bvh.stack_entries);
     }
-    pt_batch_opts def{0, 0, 0, 0, 0, 1};
-    if (!o) o = &def;
-    P.capacity = o->pool_capacity ? o->pool_capacity : (1u << 21);
-    if (P.capacity < 64 || P.capacity > (1u << 28)) return fail(PT_EINVAL, "pool_capacity must be in [64, 2^28]");
+    P.capacity = capacity;
     P.iters_per_graph = o->iters_per_graph > 0 ? o->iters_per_graph : 8;
     if (P.iters_per_graph % 2 || P.iters_per_graph > 256) return fail(PT_EINVAL, "iters_per_graph must be even and <= 256");
     P.use_graph = o->use_graph;
@@ -809,6 +811,50 @@ pt_status plan_batch(const pt_job* jobs, int32_t n, const pt_batch_opts* o, Batc
     P.o_L = off; off = align_up(off + sizeof(float4) * std::max<uint64_t>(P.total, 1));
     P.o_ovf = off; off = align_up(off + sizeof(uint2) * (size_t)P.L.gcap * P.L.nlanes);
     P.total_bytes = off;
+    return PT_OK;
+}
+
+// The caller's jobs split into `pools` pools of about equal path counts
+// (largest job first into the least loaded pool), each with its share of
+// the path slots and its own workspace slice at offs[k].
+pt_status plan_pools(const pt_job* jobs, int32_t n, const pt_batch_opts* o, std::vector<BatchPlan>& G,
+                     std::vector<size_t>& offs, size_t& total_bytes) {
+    if (!jobs || n < 1) return fail(PT_EINVAL, "need at least one job");
+    if (n > 255) return fail(PT_EINVAL, "at most 255 jobs per batch");
+    pt_batch_opts def{0, 0, 0, 0, 0, 1, 0};
+    if (!o) o = &def;
+    const uint32_t capacity = o->pool_capacity ? o->pool_capacity : (1u << 21);
+    if (capacity < 64 || capacity > (1u << 28)) return fail(PT_EINVAL, "pool_capacity must be in [64, 2^28]");
+    const int K = o->pools > 0 ? o->pools : 1;
+    if (K > kMaxPools) return fail(PT_EINVAL, "pools must be in [0, 4]");
+    if (K > n) return fail(PT_EINVAL, "pools must not exceed the number of jobs");
+    if (K > 1 && capacity / (uint32_t)K < 64) return fail(PT_EINVAL, "pool_capacity / pools must be at least 64");
+    std::vector<uint64_t> size(n);
+    for (int j = 0; j < n; ++j) {
+        if (!jobs[j].ctx) return fail(PT_EINVAL, "null job context");
+        size[j] = (uint64_t)jobs[j].ctx->cam.W * (uint64_t)jobs[j].ctx->cam.H * (uint64_t)std::max(jobs[j].args.spp, 0);
+    }
+    std::vector<int> order(n);
+    for (int j = 0; j < n; ++j) order[j] = j;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return size[a] > size[b]; });
+    std::vector<std::vector<int>> members(K);
+    std::vector<uint64_t> load(K, 0);
+    for (int j : order) {
+        int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        members[k].push_back(j);
+        load[k] += size[j];
+    }
+    G.assign(K, BatchPlan{});
+    offs.assign(K, 0);
+    total_bytes = 0;
+    const uint32_t cap_k = K == 1 ? capacity : (capacity / (uint32_t)K) & ~63u;
+    for (int k = 0; k < K; ++k) {
+        std::sort(members[k].begin(), members[k].end());
+        pt_status st = plan_batch(jobs, members[k], o, cap_k, G[k]);
+        if (st) return st;
+        offs[k] = total_bytes;
+        total_bytes = align_up(total_bytes + G[k].total_bytes);
+    }
     return PT_OK;
 }
 
@@ -837,97 +883,175 @@ extern "C" {
 
 pt_status pt_batch_workspace_size(const pt_job* jobs, int32_t n, const pt_batch_opts* o, uint64_t* bytes) {
     if (!bytes) return fail(PT_EINVAL, "null output");
-    BatchPlan P;
-    pt_status st = plan_batch(jobs, n, o, P);
+    std::vector<BatchPlan> G;
+    std::vector<size_t> offs;
+    size_t total = 0;
+    pt_status st = plan_pools(jobs, n, o, G, offs, total);
     if (st) return st;
-    *bytes = P.total_bytes;
+    *bytes = total;
     return PT_OK;
 }
 
 pt_status pt_render_batch(const pt_job* jobs, int32_t n, const pt_batch_opts* o, void* ws, uint64_t ws_bytes,
                           void* stream, double* job_ms, pt_batch_result* res) {
-    BatchPlan P;
-    pt_status st = plan_batch(jobs, n, o, P);
+    std::vector<BatchPlan> G;
+    std::vector<size_t> offs;
+    size_t total = 0;
+    pt_status st = plan_pools(jobs, n, o, G, offs, total);
     if (st) return st;
     if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return fail(PT_EINVAL, "workspace must be non-null and 256-byte aligned");
-    if (ws_bytes < P.total_bytes) return fail(PT_ENOMEM, "workspace too small (pt_batch_workspace_size)");
-    PT_HIP(hipSetDevice(P.device), "hipSetDevice");
+    if (ws_bytes < total) return fail(PT_ENOMEM, "workspace too small (pt_batch_workspace_size)");
+    const int K = (int)G.size();
+    const int device = G[0].device;
+    for (int k = 1; k < K; ++k)
+        if (G[k].device != device) return fail(PT_EINVAL, "all jobs of a batch must be on one device");
+    PT_HIP(hipSetDevice(device), "hipSetDevice");
     auto t0 = std::chrono::steady_clock::now();
     char* base = static_cast<char*>(ws);
-    BatchBufs bb = batch_bufs(P, base, n);
     hipStream_t user = reinterpret_cast<hipStream_t>(stream);
-    // private non-blocking stream (default priority) ordered after the caller's work
-    hipStream_t s = nullptr;
-    hipEvent_t ev = nullptr;
-    PT_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "create stream");
-    struct Cleanup {
-        hipStream_t s;
-        hipEvent_t* ev;
+    // one private non-blocking stream (default priority) per pool, ordered
+    // after the caller's work; the pools run concurrently
+    struct Pool {
+        hipStream_t s = nullptr;
+        hipEvent_t done = nullptr;  // the pool's last enqueued graph (or iterations) has run
         hipGraph_t g = nullptr;
         hipGraphExec_t ge = nullptr;
+        BatchBufs bb{};
+        BatchCtl ctl{};
+        uint64_t iters = 0, cap_iters = 0;
+        bool active = false;
+    };
+    struct Cleanup {
+        std::vector<Pool> pools;
+        hipEvent_t ev = nullptr;
         ~Cleanup() {
-            if (ge) (void)hipGraphExecDestroy(ge);
-            if (g) (void)hipGraphDestroy(g);
-            if (*ev) (void)hipEventDestroy(*ev);
-            (void)hipStreamDestroy(s);
+            for (Pool& p : pools) {
+                if (p.ge) (void)hipGraphExecDestroy(p.ge);
+                if (p.g) (void)hipGraphDestroy(p.g);
+                if (p.done) (void)hipEventDestroy(p.done);
+                if (p.s) (void)hipStreamDestroy(p.s);
+            }
+            if (ev) (void)hipEventDestroy(ev);
         }
-    } cleanup{s, &ev};
-    PT_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "create event");
-    PT_HIP(hipEventRecord(ev, user), "record");
-    PT_HIP(hipStreamWaitEvent(s, ev, 0), "wait");
-    PT_HIP(hipMemcpyAsync(bb.jobs, P.jobs.data(), sizeof(JobDesc) * n, hipMemcpyHostToDevice, s), "upload jobs");
-    PT_HIP(launch_batch_init(s, bb, (uint32_t)P.total), "batch init");
-    uint2* ovf = reinterpret_cast<uint2*>(base + P.o_ovf);
-    dim3 grid(P.L.grid), block(P.L.block);
-    // an upper bound on iterations: each iteration retires at least one
-    // path vertex of the oldest path in the pool
-    int max_depth = 0;
-    for (const JobDesc& d : P.jobs) max_depth = std::max(max_depth, d.pp.D);
-    const uint64_t cap_iters = (P.total / P.capacity + 2) * (uint64_t)(max_depth + 2) * 2 + 64;
-    uint64_t launches = 0, iters = 0;
-    BatchCtl ctl{};
-    if (P.use_graph) {
-        PT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
-        hipError_t ce = hipSuccess;
-        for (int it = 0; it < P.iters_per_graph && ce == hipSuccess; ++it)
-            ce = launch_batch_iteration(P.L.lds, grid, block, s, bb, it & 1, ovf, P.L.gcap);
-        hipError_t ee = hipStreamEndCapture(s, &cleanup.g);
-        if (ce != hipSuccess) return hip_fail(ce, "capture launches");
-        if (ee != hipSuccess) return hip_fail(ee, "end capture");
-        PT_HIP(hipGraphInstantiate(&cleanup.ge, cleanup.g, nullptr, nullptr, 0), "instantiate graph");
-    }
-    while (true) {
+    } cl;
+    cl.pools.resize(K);
+    PT_HIP(hipEventCreateWithFlags(&cl.ev, hipEventDisableTiming), "create event");
+    PT_HIP(hipEventRecord(cl.ev, user), "record");
+    uint64_t launches = 0;
+    for (int k = 0; k < K; ++k) {
+        Pool& p = cl.pools[k];
+        const BatchPlan& P = G[k];
+        const int nk = (int)P.jobs.size();
+        PT_HIP(hipStreamCreateWithFlags(&p.s, hipStreamNonBlocking), "create stream");
+        PT_HIP(hipEventCreateWithFlags(&p.done, hipEventDisableTiming), "create event");
+        PT_HIP(hipStreamWaitEvent(p.s, cl.ev, 0), "wait");
+        char* pb = base + offs[k];
+        p.bb = batch_bufs(P, pb, nk);
+        PT_HIP(hipMemcpyAsync(p.bb.jobs, P.jobs.data(), sizeof(JobDesc) * nk, hipMemcpyHostToDevice, p.s), "upload jobs");
+        PT_HIP(launch_batch_init(p.s, p.bb, (uint32_t)P.total), "batch init");
+        // an upper bound on iterations: each iteration retires at least one
+        // path vertex of the oldest path in the pool
+        int max_depth = 0;
+        for (const JobDesc& d : P.jobs) max_depth = std::max(max_depth, d.pp.D);
+        p.cap_iters = (P.total / P.capacity + 2) * (uint64_t)(max_depth + 2) * 2 + 64;
         if (P.use_graph) {
-            PT_HIP(hipGraphLaunch(cleanup.ge, s), "graph launch");
-            iters += P.iters_per_graph;
+            uint2* ovf = reinterpret_cast<uint2*>(pb + P.o_ovf);
+            dim3 grid(P.L.grid), block(P.L.block);
+            PT_HIP(hipStreamBeginCapture(p.s, hipStreamCaptureModeThreadLocal), "begin capture");
+            hipError_t ce = hipSuccess;
+            for (int it = 0; it < P.iters_per_graph && ce == hipSuccess; ++it)
+                ce = launch_batch_iteration(P.L.lds, grid, block, p.s, p.bb, it & 1, ovf, P.L.gcap);
+            hipError_t ee = hipStreamEndCapture(p.s, &p.g);
+            if (ce != hipSuccess) return hip_fail(ce, "capture launches");
+            if (ee != hipSuccess) return hip_fail(ee, "end capture");
+            PT_HIP(hipGraphInstantiate(&p.ge, p.g, nullptr, nullptr, 0), "instantiate graph");
+        }
+        p.active = true;
+    }
+    // enqueue the next graph (or two plain iterations) of pool k
+    auto enqueue = [&](int k) -> pt_status {
+        Pool& p = cl.pools[k];
+        const BatchPlan& P = G[k];
+        if (P.use_graph) {
+            PT_HIP(hipGraphLaunch(p.ge, p.s), "graph launch");
+            p.iters += P.iters_per_graph;
         } else {
+            uint2* ovf = reinterpret_cast<uint2*>(base + offs[k] + P.o_ovf);
             for (int it = 0; it < 2; ++it)
-                PT_HIP(launch_batch_iteration(P.L.lds, grid, block, s, bb, it & 1, ovf, P.L.gcap), "batch iteration");
-            iters += 2;
+                PT_HIP(launch_batch_iteration(P.L.lds, dim3(P.L.grid), dim3(P.L.block), p.s, p.bb, it & 1, ovf, P.L.gcap),
+                       "batch iteration");
+            p.iters += 2;
         }
         ++launches;
-        PT_HIP(hipMemcpyAsync(&ctl, bb.ctl, sizeof ctl, hipMemcpyDeviceToHost, s), "read control");
-        PT_HIP(hipStreamSynchronize(s), "batch sync");
-        if (ctl.done || ctl.err) break;
-        if (iters > cap_iters) return fail(PT_EOVERFLOW, "batch did not finish within its iteration bound");
+        PT_HIP(hipEventRecord(p.done, p.s), "record");
+        return PT_OK;
+    };
+    for (int k = 0; k < K; ++k) {
+        st = enqueue(k);
+        if (st) return st;
     }
-    if (ctl.err) return fail(PT_EOVERFLOW, "traversal stack overflow");
-    PT_HIP(launch_batch_accumulate(grid, block, s, bb, (uint32_t)P.total_pix), "batch accumulate");
-    std::vector<uint64_t> ts(n);
-    PT_HIP(hipMemcpyAsync(ts.data(), bb.done_ts, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, s), "read timestamps");
-    PT_HIP(hipStreamSynchronize(s), "batch final sync");
-    PT_HIP(hipEventRecord(ev, s), "record done");
-    PT_HIP(hipStreamWaitEvent(user, ev, 0), "caller waits");
+    // Poll the pools: a pool whose work has run reads its control block and,
+    // unless it has finished, gets its next graph at once, so each stream
+    // stays busy while the others run.
+    int nactive = K;
+    while (nactive > 0) {
+        bool progressed = false;
+        for (int k = 0; k < K; ++k) {
+            Pool& p = cl.pools[k];
+            if (!p.active) continue;
+            hipError_t q = hipEventQuery(p.done);
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) return hip_fail(q, "batch event");
+            progressed = true;
+            PT_HIP(hipMemcpyAsync(&p.ctl, p.bb.ctl, sizeof p.ctl, hipMemcpyDeviceToHost, p.s), "read control");
+            PT_HIP(hipStreamSynchronize(p.s), "batch sync");
+            if (p.ctl.err) return fail(PT_EOVERFLOW, "traversal stack overflow");
+            if (p.ctl.done) {
+                p.active = false;
+                --nactive;
+                continue;
+            }
+            if (p.iters > p.cap_iters) return fail(PT_EOVERFLOW, "batch did not finish within its iteration bound");
+            st = enqueue(k);
+            if (st) return st;
+        }
+        if (!progressed) std::this_thread::yield();
+    }
+    uint64_t t_start = ~0ull;
+    int64_t iterations = 0;
+    std::vector<std::vector<uint64_t>> ts(K);
+    for (int k = 0; k < K; ++k) {
+        Pool& p = cl.pools[k];
+        const BatchPlan& P = G[k];
+        PT_HIP(launch_batch_accumulate(dim3(P.L.grid), dim3(P.L.block), p.s, p.bb, (uint32_t)P.total_pix), "batch accumulate");
+        ts[k].resize(P.jobs.size());
+        PT_HIP(hipMemcpyAsync(ts[k].data(), p.bb.done_ts, sizeof(uint64_t) * P.jobs.size(), hipMemcpyDeviceToHost, p.s),
+               "read timestamps");
+        PT_HIP(hipStreamSynchronize(p.s), "batch final sync");
+        t_start = std::min<uint64_t>(t_start, p.ctl.t_start);
+        iterations += (int64_t)p.ctl.iterations;
+    }
+    // the caller's stream continues after every pool's work
+    for (int k = 0; k < K; ++k) {
+        PT_HIP(hipEventRecord(cl.pools[k].done, cl.pools[k].s), "record done");
+        PT_HIP(hipStreamWaitEvent(user, cl.pools[k].done, 0), "caller waits");
+    }
     if (job_ms) {
         int rate_khz = 0;
-        PT_HIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, P.device), "wall clock rate");
-        for (int j = 0; j < n; ++j)
-            job_ms[j] = rate_khz > 0 && ts[j] >= ctl.t_start ? (double)(ts[j] - ctl.t_start) / (double)rate_khz : -1.0;
+        PT_HIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, device), "wall clock rate");
+        for (int k = 0; k < K; ++k)
+            for (size_t i = 0; i < G[k].members.size(); ++i) {
+                const uint64_t t = ts[k][i];
+                job_ms[G[k].members[i]] =
+                    rate_khz > 0 && t >= t_start ? (double)(t - t_start) / (double)rate_khz : -1.0;
+            }
     }
     if (res) {
         res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        res->path_samples = (int64_t)P.total;
-        res->iterations = ctl.iterations;
+        uint64_t paths = 0;
+        for (const BatchPlan& P : G) paths += P.total;
+        res->path_samples = (int64_t)paths;
+        res->iterations = iterations;
         res->launches = (int64_t)launches;
     }
     return PT_OK;

@@ -79,7 +79,8 @@ class Job(C.Structure):
 
 class BatchOpts(C.Structure):
     _fields_ = [("pool_capacity", C.c_uint32), ("block", C.c_int32), ("grid_mult", C.c_int32),
-                ("stack_lds", C.c_int32), ("iters_per_graph", C.c_int32), ("use_graph", C.c_int32)]
+                ("stack_lds", C.c_int32), ("iters_per_graph", C.c_int32), ("use_graph", C.c_int32),
+                ("pools", C.c_int32)]
 
 
 class BatchResult(C.Structure):
@@ -359,13 +360,14 @@ def render_differentiable(albedo, emission, renderer, **kw):
 
 
 def render_batch(renderers, job_args, images=None, pool_capacity=0, block=0, grid_mult=0, iters_per_graph=0,
-                 use_graph=True, workspace=None, stack_lds=0):
+                 use_graph=True, workspace=None, stack_lds=0, pools=0):
     """Render several jobs in one batched persistent wavefront.
 
     renderers: Renderer per job (scene bound, camera set, all on one device);
     job_args: dict of render arguments per job (spp, max_depth, seed, frame,
-    nee, rr_start; `job` defaults to the job's index).  Returns (images,
-    per-job completion ms, result dict)."""
+    nee, rr_start; `job` defaults to the job's index); pools: pools run
+    concurrently (0 = 1).  Returns (images, per-job completion ms, result
+    dict)."""
     import torch
     n = len(renderers)
     jobs = (Job * n)()
@@ -378,7 +380,7 @@ def render_batch(renderers, job_args, images=None, pool_capacity=0, block=0, gri
         jobs[j].args = R.args(**kw)
         jobs[j].image_out = images[j].data_ptr()
     opts = BatchOpts(int(pool_capacity), int(block), int(grid_mult), int(stack_lds), int(iters_per_graph),
-                     int(bool(use_graph)))
+                     int(bool(use_graph)), int(pools))
     need = C.c_uint64()
     check(lib().pt_batch_workspace_size(jobs, n, C.byref(opts), C.byref(need)))
     if workspace is None or workspace[1] < need.value:

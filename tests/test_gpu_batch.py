@@ -29,11 +29,14 @@ def _jobs():
     return Rs, args
 
 
-@pytest.mark.parametrize("capacity,graph,iters", [(0, True, 0), (256, True, 4), (1000, False, 0), (64, True, 16)])
-def test_batch_equals_standalone(capacity, graph, iters):
-    log("batch", capacity, graph, iters)
+@pytest.mark.parametrize("capacity,graph,iters,pools", [(0, True, 0, 0), (256, True, 4, 1), (1000, False, 0, 1),
+                                                        (64, True, 16, 1), (0, True, 0, 2), (256, True, 4, 4),
+                                                        (1000, False, 0, 3)])
+def test_batch_equals_standalone(capacity, graph, iters, pools):
+    log("batch", capacity, graph, iters, pools)
     Rs, args = _jobs()
-    imgs, ms, res = ptmi.render_batch(Rs, args, pool_capacity=capacity, use_graph=graph, iters_per_graph=iters)
+    imgs, ms, res = ptmi.render_batch(Rs, args, pool_capacity=capacity, use_graph=graph, iters_per_graph=iters,
+                                      pools=pools)
     torch.cuda.synchronize()
     for j, (R, kw) in enumerate(zip(Rs, args)):
         ref = R.render(mode="wave", job=j, **kw).cpu().numpy()
@@ -49,6 +52,12 @@ def test_batch_rejects_bad_options():
         ptmi.render_batch(Rs, args, iters_per_graph=3)
     with pytest.raises(ptmi.PtError):
         ptmi.render_batch(Rs, args, pool_capacity=8)
+    with pytest.raises(ptmi.PtError):
+        ptmi.render_batch(Rs, args, pools=5)  # more than four pools
+    with pytest.raises(ptmi.PtError):
+        ptmi.render_batch(Rs[:2], args[:2], pools=3)  # a pool without a job
+    with pytest.raises(ptmi.PtError):
+        ptmi.render_batch(Rs, args, pool_capacity=128, pools=4)  # 32 slots per pool
 
 
 def test_batch_mixed_samplers_equal_standalone():
