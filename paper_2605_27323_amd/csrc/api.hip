@@ -849,6 +849,7 @@ pt_status plan_pools(const pt_job* jobs, int32_t n, const pt_batch_opts* o, std:
     total_bytes = 0;
     const uint32_t cap_k = K == 1 ? capacity : (capacity / (uint32_t)K) & ~63u;
     for (int k = 0; k < K; ++k) {
+        if (members[k].empty()) return fail(PT_EINVAL, "a pool would hold no job");
         std::sort(members[k].begin(), members[k].end());
         pt_status st = plan_batch(jobs, members[k], o, cap_k, G[k]);
         if (st) return st;
@@ -925,6 +926,9 @@ pt_status pt_render_batch(const pt_job* jobs, int32_t n, const pt_batch_opts* o,
         std::vector<Pool> pools;
         hipEvent_t ev = nullptr;
         ~Cleanup() {
+            // on an early error return no pool may still run on the caller's workspace
+            for (Pool& p : pools)
+                if (p.s) (void)hipStreamSynchronize(p.s);
             for (Pool& p : pools) {
                 if (p.ge) (void)hipGraphExecDestroy(p.ge);
                 if (p.g) (void)hipGraphDestroy(p.g);
