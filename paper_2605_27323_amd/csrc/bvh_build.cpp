@@ -36,7 +36,7 @@ struct Arena {
     }
 };
 
-constexpr int kBins = 32;
+constexpr int kBins = 64;
 
 float area_of(const float lo[3], const float hi[3]) {
     float dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
