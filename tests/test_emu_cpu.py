@@ -215,3 +215,16 @@ def test_halton_sampler_matches_oracle():
         assert (np.abs(g - o) <= 1e-4 * a + 1e-7 * np.abs(o).max()).all()
     imgs, _ = emu.render_batch([E], [dict(cfg, job=0)], 500, shuffle=2)
     assert np.array_equal(imgs[0].view(np.uint32), E.mega(**cfg)[0].view(np.uint32))
+
+
+@pytest.mark.parametrize("only_degenerate_lights", [False, True])
+def test_degenerate_triangles(only_degenerate_lights):
+    # zero-area triangles, emissive ones among them: never hit, never picked
+    # as a light sample (zero area), no NaN; with no light of positive area
+    # the sky alone lights the box
+    from tests._parity import degenerate_scene
+    scene, cam = degenerate_scene(only_degenerate_lights)
+    E, img, rays, nexact = _check(scene, cam, spp=4, max_depth=5, seed=0)
+    assert np.isfinite(img).all() and nexact == img.shape[0]
+    w, _ = E.wave(shuffle=3, spp=4, max_depth=5, seed=0)
+    assert np.array_equal(w.view(np.uint32), img.view(np.uint32))

@@ -150,6 +150,20 @@ def test_edge_cases():
         assert np.array_equal(wave.reshape(-1, 3), ref) and np.array_equal(mega.reshape(-1, 3), ref)
 
 
+@pytest.mark.parametrize("only_degenerate_lights", [False, True])
+def test_degenerate_triangles(only_degenerate_lights):
+    from tests._parity import degenerate_scene
+    scene, cam = degenerate_scene(only_degenerate_lights)
+    log("degenerate triangles", only_degenerate_lights)
+    R = ptmi.Renderer(scene, cam)
+    mega, wave = render_both(R, spp=4, max_depth=5, seed=0)
+    assert np.array_equal(mega.view(np.uint32), wave.view(np.uint32))
+    assert np.isfinite(wave).all()
+    ref, frag = oracle.Scene(scene).render(cam, spp=4, max_depth=5, seed=0)
+    nexact = assert_parity(wave.reshape(-1, 3), ref, frag, what="degenerate")
+    assert nexact == ref.shape[0]
+
+
 def test_no_compaction_and_launch_shapes_bit_identical():
     scene, cam = scenes.procedural(seed=41, n_objects=30, width=64, height=40)
     log("launch shapes")
