@@ -155,7 +155,11 @@ typedef struct {
  * inverses truncated to 24 bits, Cranley-Patterson rotated per pixel by
  * 24-bit offsets from the Philox block of the reserved sample index
  * 0xFFFFFFFF, modulo 1); every later dimension of the path stays Philox.
- * Any other value is PT_EINVAL. */
+ * Any other value is PT_EINVAL.
+ * tail_spread: 1 = the hybrid tail spreads its queue over as many waves as
+ * the device holds at once (partly filled waves, more latency hidden: faster
+ * when a frame runs alone), 0 = full waves (fewer instructions: faster with
+ * frames in flight); same image bit for bit. */
 typedef struct {
     int32_t spp, max_depth;
     uint64_t seed;
@@ -170,6 +174,7 @@ typedef struct {
     uint32_t tail_threshold;
     int32_t tail_bounce;
     int32_t sampler;
+    int32_t tail_spread;
 } pt_render_args;
 
 /* Library version (major * 10000 + minor * 100 + patch). */

@@ -126,6 +126,10 @@ def tune_frame(renderer, mode="wave", cache=DEFAULT_CACHE, space=None, log=None,
         depth = kw.get("max_depth", 5)
         tbs = [t for t in TAIL_BOUNCES if t <= depth]
         best, _ = successive_halving([dict(best, tail_bounce=t) for t in tbs], measure, reps0=32, log=log)
+        if best.get("tail_threshold", 0) or best.get("tail_bounce", 0):
+            # and whether the tail spreads its queue over partly filled waves
+            best, _ = successive_halving([dict(best, tail_spread=v) for v in (False, True)], measure, reps0=32,
+                                         log=log)
     if cache:
         _store(cache, key, best)
     return best

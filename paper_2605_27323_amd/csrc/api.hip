@@ -41,6 +41,7 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 constexpr int kMaxPools = 4;  // concurrent pools of a batched launch
+constexpr uint32_t kTailWavesPerCu = 16;  // the hybrid tail kernel runs 4 waves per SIMD
 
 struct StageTimer {
     int stage;
@@ -165,6 +166,7 @@ pt_status check_args(const pt_ctx* c, const pt_render_args* a) {
     if (a->max_depth < 0 || a->max_depth > 1000) return fail(PT_EINVAL, "max_depth must be in [0, 1000]");
     if (a->tail_bounce < 0 || a->tail_bounce > a->max_depth)
         return fail(PT_EINVAL, "tail_bounce must be in [0, max_depth]");
+    if (a->tail_spread != 0 && a->tail_spread != 1) return fail(PT_EINVAL, "tail_spread must be 0 or 1");
     if (a->sampler != PT_SAMPLER_PHILOX && a->sampler != PT_SAMPLER_HALTON)
         return fail(PT_EINVAL, "sampler must be PT_SAMPLER_PHILOX or PT_SAMPLER_HALTON");
     if (a->mode != PT_MODE_MEGA && a->mode != PT_MODE_WAVE) return fail(PT_EINVAL, "unknown mode");
@@ -276,7 +278,8 @@ pt_status enqueue_stages(pt_ctx* c, const pt_render_args* a, const Launch& L, co
             PT_HIP(timed(c, prof, 2, s, [&] { return launch_shade(grid, block, s, c->view, pp, wb, b, compact, sort, tail); }), "shade");
             if (compact && tail)
                 PT_HIP(timed(c, prof, 8, s, [&] {
-                           return launch_tail(L.lds, count, grid, block, s, c->view, pp, wb, b, sort, tail, ovf, L.gcap);
+                           return launch_tail(L.lds, count, grid, block, s, c->view, pp, wb, b, sort, tail, ovf, L.gcap,
+                                              a->tail_spread ? (uint32_t)c->num_cu * kTailWavesPerCu : 0u);
                        }),
                        "hybrid tail");
             if (last) break;

@@ -62,9 +62,12 @@ hipError_t launch_extend(int lds, bool count, dim3 grid, dim3 block, hipStream_t
 // skipped here and finished in place by launch_tail
 hipError_t launch_shade(dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const PathParams& pp,
                         const WaveBufs& wb, int b, int compact, int sorted, uint32_t tail);
+// resident_waves: 0 = queue entries in full waves; else the waves the
+// device holds at once at the tail kernel's occupancy, over which a short
+// queue is spread
 hipError_t launch_tail(int lds, bool count, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
                        const PathParams& pp, const WaveBufs& wb, int b, int sorted, uint32_t tail, uint2* ovf,
-                       int gcap);
+                       int gcap, uint32_t resident_waves);
 // counting sort of queue b by a 6-bit key when it holds >= threshold
 // paths: key_kind 0 = material of the hit (for shade), 1 = ray direction
 // octant and origin side (for extend)

@@ -151,7 +151,8 @@ __global__ void k_init_counts(uint32_t* __restrict__ counts, int n, uint32_t fir
 // compute units while it finished the last bounces.
 template <int LDS, bool COUNT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_shade_tail(SceneView sc, PathParams pp, WaveBufs wb, int b, int sorted,
-                                                    uint32_t tail, uint2* __restrict__ ovf, int gcap) {
+                                                    uint32_t tail, uint2* __restrict__ ovf, int gcap,
+                                                    uint32_t spread) {
     const uint32_t count = wb.counts[b];
     if (!(count < tail) || count == 0u) return;
     extern __shared__ __align__(8) uint32_t smem[];
@@ -162,7 +163,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     const uint32_t* perm = (sorted && wb.hist[2 * kSortBins]) ? wb.perm : nullptr;
     TravStack<LDS, COUNT> st = make_stack<LDS, COUNT>(smem, ovf, gcap, gtid, nlanes);
     uint32_t n_ext = 0, n_sh = 0;
-    for (uint32_t i = gtid; i < count; i += nlanes) {
+    // spread = 0: entry i goes to thread i (full waves).  spread > 0: entry
+    // i goes to lane i / spread of wave i % spread, so a short queue is
+    // spread over the first `spread` waves (as many as the compute units
+    // hold at once): every SIMD then has several waves whose memory latency
+    // it can overlap, at the price of partly filled waves.  Either way one
+    // lane finishes each path.
+    const uint32_t wave = gtid >> 6;
+    const uint32_t first = spread ? lane_id() * spread + wave : gtid;
+    const uint32_t step = spread ? 64u * spread : nlanes;
+    const bool takes = spread == 0u || wave < spread;
+    for (uint32_t i = first; takes && i < count; i += step) {
         VertexOut vo;
         ShadowReq sh;
         PathState ps;
@@ -479,9 +490,10 @@ hipError_t launch_shade(dim3 grid, dim3 block, hipStream_t s, const SceneView& s
 
 hipError_t launch_tail(int lds, bool count, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
                        const PathParams& pp, const WaveBufs& wb, int b, int sorted, uint32_t tail, uint2* ovf,
-                       int gcap) {
+                       int gcap, uint32_t resident_waves) {
     const size_t sm = stack_lds_bytes(lds, block.x);
-#define L(N, C) hipLaunchKernelGGL((k_shade_tail<N, C>), grid, block, sm, s, sc, pp, wb, b, sorted, tail, ovf, gcap);
+    const uint32_t spread = resident_waves ? std::max(1u, std::min(grid.x * block.x / 64u, resident_waves)) : 0u;
+#define L(N, C) hipLaunchKernelGGL((k_shade_tail<N, C>), grid, block, sm, s, sc, pp, wb, b, sorted, tail, ovf, gcap, spread);
 #define X(N) PT_DISPATCH(N, L)
     PT_STACK_CASES(X)
 #undef X

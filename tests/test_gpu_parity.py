@@ -120,6 +120,9 @@ def test_full_size_procedural_sampled_pixels():
         tuned = R.render(mode="wave", block=256, grid_mult=8, stack_lds=8, tail_threshold=1 << 18, tail_bounce=4,
                          **cfg)
         assert np.array_equal(tuned.cpu().numpy().view(np.uint32), wave.view(np.uint32))
+        spread = R.render(mode="wave", block=256, grid_mult=8, stack_lds=8, tail_threshold=1 << 18, tail_bounce=3,
+                          tail_spread=True, **cfg)
+        assert np.array_equal(spread.cpu().numpy().view(np.uint32), wave.view(np.uint32))
         kw = {k: v for k, v in cfg.items() if k != "frame"}
         inflight = R.render_frames(3, mode="wave", frame=frame - 2 if frame >= 2 else 0, block=256, grid_mult=4,
                                    stack_lds=8, tail_threshold=1 << 18, tail_bounce=3, **kw)
@@ -186,6 +189,9 @@ def test_no_compaction_and_launch_shapes_bit_identical():
             R.render(mode="wave", tail_bounce=1, **cfg),
             R.render(mode="wave", tail_bounce=3, tail_threshold=300, **cfg),
             R.render(mode="wave", tail_bounce=6, flags=ptmi.FLAG_SORT_MATERIAL, **cfg),
+            R.render(mode="wave", tail_bounce=2, tail_spread=True, **cfg),
+            R.render(mode="wave", tail_threshold=1 << 30, tail_spread=True, block=64, grid_mult=1, **cfg),
+            R.render(mode="wave", tail_threshold=500, tail_spread=True, flags=ptmi.FLAG_SORT_MATERIAL, **cfg),
             R.render(mode="wave", **cfg)]
     # the image does not depend on the BVH either: leaves of up to 4 and 8 triangles
     for ml in (4, 8):
