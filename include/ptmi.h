@@ -134,13 +134,13 @@ typedef struct {
 /* Per-render arguments.  max_depth = number of scattering vertices
  * (emission found after the last one is still counted); rr_start < 0
  * disables Russian roulette, else it applies from that vertex on.
- * block = threads per workgroup (64..256, multiple of 64; 0 = default);
- * grid_mult = persistent workgroups per compute unit (0 = default);
+ * block = threads per workgroup (64..256, multiple of 64; 0 = default 256);
+ * grid_mult = persistent workgroups per compute unit (0 = default 8);
  * sort_threshold: with PT_FLAG_SORT_MATERIAL (PT_FLAG_SORT_RAYS), a
  * bounce's shade (extend) queue is sorted only when it holds at least this
  * many paths;
  * stack_lds: traversal stack entries kept in LDS per lane, 8/16/24/32
- * (0 = default 16); deeper entries spill to the workspace; (stack_lds + 1)
+ * (0 = default 8); deeper entries spill to the workspace; (stack_lds + 1)
  * x 8 bytes per thread of LDS plus 12 KiB of light table must fit one
  * workgroup's LDS (PT_EINVAL otherwise);
  * tail_threshold: wavefront hybrid tail, a bounce whose queue holds fewer

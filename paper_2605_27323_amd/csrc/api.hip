@@ -34,9 +34,9 @@ pt_status hip_fail(hipError_t e, const char* what) {
 
 // frames in flight in pt_render_frames (internal streams and workspace slots)
 constexpr int kInFlight = 3;
-constexpr int kDefaultBlock = 128;
+constexpr int kDefaultBlock = 256;
 constexpr int kDefaultGridMult = 8;
-constexpr int kStackLds = 16;
+constexpr int kStackLds = 8;
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
