@@ -100,7 +100,8 @@ typedef struct {
 typedef struct {
     int64_t node_count, node_bytes;  /* BVH4 nodes, 80 B each (half-precision child boxes) */
     int64_t tri_bytes;               /* 48 B per triangle, leaf order */
-    int64_t light_count, light_bytes;/* 16 B per light (leaf-order index, CDF word, input index, 0) */
+    int64_t light_count, light_bytes;/* 16 B per light (leaf-order index, CDF word, input index, 0),
+                                        then the input ids of the 64 largest triangles */
     int64_t material_bytes;          /* 16 B per material */
     int32_t depth;                   /* BVH4 levels */
     int32_t stack_entries;           /* traversal stack entries needed */

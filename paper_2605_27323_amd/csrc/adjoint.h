@@ -12,8 +12,10 @@
 // where L_acc is the radiance gathered up to and including x_k's light
 // sample and delta = dLoss/dI(pixel) / spp.  Channels with W = 0 carry no
 // gradient through W (the division of the method).  The accumulator takes
-// add(p, v) (skipping v = 0) and add_light(j, c, p, v) for the emission of
-// light j of the light table, channel c, at p.
+// add_tri(hot, which, c, p, v) for channel c of the albedo (which = 0) or
+// emission (1) of the hit triangle, at p, hot being its slot among the
+// largest triangles + 1 (0 = none), and add_light(j, c, p, v) for the
+// emission of light j of the light table; both skip v = 0.
 #pragma once
 #include "device.h"
 
@@ -42,9 +44,9 @@ PT_DEV void adjoint_path(const SceneView& sc, const CamView& cam, const PathPara
         if (vo.id == 0xFFFFFFFFu) break;  // escaped: the sky is not a parameter
         const uint32_t id = vo.id;
         if (vo.emitted) {
-            acc.add(g_emi + 3 * (size_t)id + 0, delta.x * (beta.x * vo.w_emit));
-            acc.add(g_emi + 3 * (size_t)id + 1, delta.y * (beta.y * vo.w_emit));
-            acc.add(g_emi + 3 * (size_t)id + 2, delta.z * (beta.z * vo.w_emit));
+            acc.add_tri(vo.hot, 1, 0, g_emi + 3 * (size_t)id + 0, delta.x * (beta.x * vo.w_emit));
+            acc.add_tri(vo.hot, 1, 1, g_emi + 3 * (size_t)id + 1, delta.y * (beta.y * vo.w_emit));
+            acc.add_tri(vo.hot, 1, 2, g_emi + 3 * (size_t)id + 2, delta.z * (beta.z * vo.w_emit));
         }
         // the albedo gradient of this vertex: light-sample and continuation
         // terms summed here, one accumulation per channel
@@ -84,7 +86,7 @@ PT_DEV void adjoint_path(const SceneView& sc, const CamView& cam, const PathPara
             }
         }
 #pragma unroll
-        for (int c = 0; c < 3; ++c) acc.add(g_alb + 3 * (size_t)id + c, ga[c]);
+        for (int c = 0; c < 3; ++c) acc.add_tri(vo.hot, 0, c, g_alb + 3 * (size_t)id + c, ga[c]);
         if (!cont) break;
         o = vo.o;
         d = vo.d;

@@ -9,16 +9,24 @@ namespace ptmi {
 
 namespace {
 
-// Gradients go to global memory with hardware fp32 atomics, except the
-// light-sample emission terms of lights in the first kLdsLights entries of
-// the light table: those few addresses receive a term from every visible
-// light sample, so each block sums them in LDS and adds its sums once at
-// the end.
+// Gradients go to global memory with hardware fp32 atomics, except two
+// kinds of hot spots, which each block sums in LDS and adds once at the
+// end: the light-sample emission terms of lights in the first kLdsLights
+// entries of the light table (every visible light sample adds to one of
+// them), and the albedo and emission terms of the kHotTris largest
+// triangles (a ground plane or an area light is reached by a large share
+// of all paths, and atomics on a few addresses are served one at a time).
 struct AtomicAcc {
     float* lds_light;  // 3 floats per light (local memory of the block)
     uint32_t n_lds;    // lights kept there
-    __device__ __forceinline__ void add(float* p, float v) {
-        if (v != 0.0f) unsafeAtomicAdd(p, v);
+    float* lds_hot;    // [albedo, emission][3 * kHotTris] sums of the largest triangles
+    uint32_t n_hot;
+    __device__ __forceinline__ void add_tri(uint32_t hot, int which, int c, float* p, float v) {
+        if (v == 0.0f) return;
+        if (hot - 1u < n_hot)
+            atomicAdd(&lds_hot[which * 3 * kHotTris + 3 * (hot - 1u) + (uint32_t)c], v);
+        else
+            unsafeAtomicAdd(p, v);
     }
     __device__ __forceinline__ void add_light(uint32_t j, int c, float* p, float v) {
         if (v == 0.0f) return;
@@ -42,10 +50,14 @@ __global__ void __launch_bounds__(256) k_adjoint(SceneView sc, CamView cam, Path
     TravStack<LDS> st =
         make_trav_stack<LDS>(reinterpret_cast<uint2*>(smem) + threadIdx.x, (int)blockDim.x, ovf, gtid, (int)nlanes, gcap);
     __shared__ float light_g[3 * kLdsLights];
+    __shared__ float hot_g[2 * 3 * kHotTris];
     AtomicAcc acc;
     acc.lds_light = light_g;
     acc.n_lds = (uint32_t)min(max(sc.nl, 0), kLdsLights);
+    acc.lds_hot = hot_g;
+    acc.n_hot = (uint32_t)min(max(sc.n_hot, 0), kHotTris);
     for (uint32_t j = threadIdx.x; j < 3 * acc.n_lds; j += blockDim.x) light_g[j] = 0.0f;
+    for (uint32_t j = threadIdx.x; j < 2 * 3 * kHotTris; j += blockDim.x) hot_g[j] = 0.0f;
     __syncthreads();
     const uint32_t npaths = (uint32_t)cam.W * (uint32_t)cam.H * (uint32_t)pp.spp;
     const float fs = (float)pp.spp;
@@ -71,6 +83,12 @@ __global__ void __launch_bounds__(256) k_adjoint(SceneView sc, CamView cam, Path
     for (uint32_t j = threadIdx.x; j < 3 * acc.n_lds; j += blockDim.x) {
         const float v = light_g[j];
         if (v != 0.0f) unsafeAtomicAdd(g_emi + 3 * (size_t)sc.lights[j / 3u].id + j % 3u, v);
+    }
+    for (uint32_t j = threadIdx.x; j < 3 * acc.n_hot; j += blockDim.x) {
+        const size_t at = 3 * (size_t)sc.hot_ids[j / 3u] + j % 3u;
+        const float va = hot_g[j], ve = hot_g[3 * kHotTris + j];
+        if (va != 0.0f) unsafeAtomicAdd(g_alb + at, va);
+        if (ve != 0.0f) unsafeAtomicAdd(g_emi + at, ve);
     }
     if (st.overflow) atomicOr(&stats[2], 1u);
 }

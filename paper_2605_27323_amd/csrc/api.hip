@@ -293,6 +293,9 @@ pt_status enqueue_stages(pt_ctx* c, const pt_render_args* a, const Launch& L, co
     return PT_OK;
 }
 
+// the largest triangles' ids follow the light table in the light buffer
+size_t hot_ids_offset(const pt_ctx* c) { return std::max<size_t>(1, c->bvh.lights.size()) * sizeof(LightEntry); }
+
 SceneView make_view(const pt_ctx* c, const pt_scene_buffers* b) {
     SceneView v{};
     v.nodes = reinterpret_cast<const float4*>(b->nodes);
@@ -311,6 +314,8 @@ SceneView make_view(const pt_ctx* c, const pt_scene_buffers* b) {
     v.cx = c->bvh.center[0];
     v.cy = c->bvh.center[1];
     v.cz = c->bvh.center[2];
+    v.hot_ids = reinterpret_cast<const uint32_t*>(static_cast<const char*>(b->lights) + hot_ids_offset(c));
+    v.n_hot = (int32_t)c->bvh.hot_ids.size();
     return v;
 }
 
@@ -433,7 +438,8 @@ pt_status pt_build_bvh(pt_ctx* c, const pt_bvh_opts* o, pt_bvh_info* info) {
         info->node_bytes = (int64_t)(c->bvh.nodes.size() * sizeof(Node4));
         info->tri_bytes = (int64_t)(std::max<size_t>(1, c->bvh.tris.size()) * sizeof(float4));
         info->light_count = (int64_t)c->bvh.lights.size();
-        info->light_bytes = (int64_t)(std::max<size_t>(1, c->bvh.lights.size()) * sizeof(LightEntry));
+        info->light_bytes = (int64_t)(std::max<size_t>(1, c->bvh.lights.size()) * sizeof(LightEntry) +
+                                      sizeof(LightEntry) * (size_t)((kHotTris + 3) / 4));
         info->material_bytes = (int64_t)(c->mats.size() * sizeof(float));
         info->depth = c->bvh.depth;
         info->stack_entries = c->bvh.stack_entries;
@@ -467,6 +473,10 @@ pt_status pt_bind_scene(pt_ctx* c, const pt_scene_buffers* b, void* stream) {
         PT_HIP(hipMemcpyAsync(b->tris, c->bvh.tris.data(), c->bvh.tris.size() * sizeof(float4), hipMemcpyHostToDevice, s), "upload triangles");
     if (!c->bvh.lights.empty())
         PT_HIP(hipMemcpyAsync(b->lights, c->bvh.lights.data(), c->bvh.lights.size() * sizeof(LightEntry), hipMemcpyHostToDevice, s), "upload lights");
+    if (!c->bvh.hot_ids.empty())
+        PT_HIP(hipMemcpyAsync(static_cast<char*>(b->lights) + hot_ids_offset(c), c->bvh.hot_ids.data(),
+                              c->bvh.hot_ids.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s),
+               "upload hot triangle ids");
     PT_HIP(hipMemcpyAsync(b->materials, c->mats.data(), c->mats.size() * sizeof(float), hipMemcpyHostToDevice, s), "upload materials");
     if (b->upload_params && c->nt > 0) {
         PT_HIP(hipMemcpyAsync(b->albedo, c->albedo.data(), c->albedo.size() * sizeof(float), hipMemcpyHostToDevice, s), "upload albedo");

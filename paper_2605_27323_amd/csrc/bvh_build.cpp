@@ -388,6 +388,32 @@ BuildResult build_scene(const std::vector<float>& tri_v, const std::vector<int32
         r.tris[3 * (size_t)j + 2] = make_float4(p[6], p[7], p[8], 0.f);
     }
 
+    // the kHotTris triangles of largest area (ties to the smaller id), area
+    // above zero: their slot + 1 goes into the w word of their third vertex
+    {
+        std::vector<std::pair<double, int32_t>> ar;
+        ar.reserve(nt);
+        for (int32_t i = 0; i < nt; ++i) {
+            const float* p = &tri_v[9 * (size_t)i];
+            double ax = (double)p[3] - (double)p[0], ay = (double)p[4] - (double)p[1], az = (double)p[5] - (double)p[2];
+            double bx = (double)p[6] - (double)p[0], by = (double)p[7] - (double)p[1], bz = (double)p[8] - (double)p[2];
+            double cx = ay * bz - az * by, cy = az * bx - ax * bz, cz = ax * by - ay * bx;
+            double a2 = cx * cx + cy * cy + cz * cz;
+            if (a2 > 0.0) ar.emplace_back(a2, i);
+        }
+        const size_t h = std::min<size_t>((size_t)kHotTris, ar.size());
+        std::partial_sort(ar.begin(), ar.begin() + (std::ptrdiff_t)h, ar.end(), [](const auto& x, const auto& y) {
+            return x.first > y.first || (x.first == y.first && x.second < y.second);
+        });
+        for (size_t k = 0; k < h; ++k) {
+            const uint32_t id = (uint32_t)ar[k].second, slot1 = (uint32_t)k + 1u;
+            r.hot_ids.push_back(id);
+            float w;
+            std::memcpy(&w, &slot1, 4);
+            r.tris[3 * (size_t)leaf_pos[id] + 2].w = w;
+        }
+    }
+
     // light set in input order: fp64 prefix sums of the triangle areas,
     // quantised to u32 words (last word saturated)
     std::vector<double> cum;

@@ -11,6 +11,7 @@ struct BuildResult {
     std::vector<Node4> nodes;
     std::vector<float4> tris;        // 3 per triangle, leaf order
     std::vector<LightEntry> lights;  // input order of the light triangles
+    std::vector<uint32_t> hot_ids;   // input ids of the largest triangles, by slot (at most kHotTris)
     float area_total = 0.f;
     float max_coord = 0.f;  // largest absolute vertex coordinate
     float center[3] = {0.f, 0.f, 0.f};  // centre of the scene's bounding box

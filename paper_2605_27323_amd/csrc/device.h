@@ -906,6 +906,7 @@ struct VertexOut {
     bool cont;          // the path continues
     f3 o, d;            // continuation ray
     uint32_t id;        // input id of the hit triangle (~0u on a miss)
+    uint32_t hot;       // its slot among the largest triangles + 1 (0 = not one of them)
     bool emitted;       // emission term counted at this vertex
     float w_emit;       // its MIS weight
     Lobe scat;          // sampling weight = lobe(albedo) when cont
@@ -984,6 +985,7 @@ PT_DEV VertexOut shade_vertex(const SceneView& sc, const PathParams& pp, uint32_
     VertexOut out;
     out.cont = false;
     out.id = 0xFFFFFFFFu;
+    out.hot = 0u;
     out.emitted = false;
     out.w_emit = 0.0f;
     out.addL = false;
@@ -1020,6 +1022,7 @@ PT_DEV VertexOut shade_vertex(const SceneView& sc, const PathParams& pp, uint32_
     const f3 alb = load3(sc.albedo, id);
     const float4 mat = sc.mats[minfo & ~kLightFlag];
     out.id = id;
+    out.hot = f2u(tc.w);
     f3 e1 = sub3(v1, v0), e2 = sub3(v2, v0);
     f3 x = mk3((v0.x + h.b1 * e1.x) + h.b2 * e2.x, (v0.y + h.b1 * e1.y) + h.b2 * e2.y,
                (v0.z + h.b1 * e1.z) + h.b2 * e2.z);

@@ -48,6 +48,10 @@ struct LightEntry {
     uint32_t pad;
 };
 
+// triangles of largest area whose adjoint gradients are summed per
+// workgroup (many paths reach them: a ground plane, area lights)
+constexpr int kHotTris = 64;
+
 struct SceneView {
     const float4* __restrict__ nodes;
     const float4* __restrict__ tris;
@@ -61,6 +65,11 @@ struct SceneView {
     float area_total;
     float sky0, sky1, sky2;
     float cx, cy, cz;  // centre of the scene's bounding box (ray sort key)
+    // the largest triangles (input ids by slot): a triangle record's third
+    // word w holds its slot + 1 (0 = not one of them); the adjoint sums
+    // their gradients per workgroup before adding them to global memory
+    const uint32_t* __restrict__ hot_ids;
+    int32_t n_hot;
 };
 
 struct CamView {

@@ -36,6 +36,8 @@ SceneView host_view(const pt_ctx* c) {
     v.cx = c->bvh.center[0];
     v.cy = c->bvh.center[1];
     v.cz = c->bvh.center[2];
+    v.hot_ids = c->bvh.hot_ids.data();
+    v.n_hot = (int32_t)c->bvh.hot_ids.size();
     return v;
 }
 
@@ -208,6 +210,7 @@ int32_t emu_backward(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32_t 
         void add(float* p, float v) {
             if (v != 0.0f) *p += v;
         }
+        void add_tri(uint32_t, int, int, float* p, float v) { add(p, v); }
         void add_light(uint32_t, int, float* p, float v) { add(p, v); }
     } acc;
     SceneView sc = host_view(c);

@@ -185,3 +185,30 @@ def test_light_cdf_matches_oracle():
     for w in words:
         j_lib = int(np.searchsorted(lights[:, 1], np.uint32(w), side="left"))
         assert j_lib == S.pick_light(int(w))
+
+
+@pytest.mark.parametrize("which", ["procedural", "soup", "degenerate"])
+def test_largest_triangles_marked(which):
+    # the triangle records mark the 64 triangles of largest area (ties to
+    # the smaller input id, zero area never) with their slot + 1 in the
+    # last word; the adjoint sums those triangles' gradients per workgroup
+    if which == "procedural":
+        scene, _ = scenes.procedural(seed=3, n_objects=30)
+    elif which == "soup":
+        scene = scenes.random_soup(5, 40, emissive_frac=0.2)
+    else:
+        from tests._parity import degenerate_scene
+        scene, _ = degenerate_scene()
+    ctx = ptmi.Context(scene, device=-1)
+    _, tris, _ = ctx.host_bvh()
+    P = scene["positions"].astype(np.float64)[scene["indices"]]
+    c = np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0])
+    a2 = (c * c).sum(1)
+    order = sorted((i for i in range(len(a2)) if a2[i] > 0), key=lambda i: (-a2[i], i))[:64]
+    ids = tris[:, 3].view(np.uint32)
+    slot = np.zeros(len(a2), np.int64)
+    slot[ids] = tris[:, 11].view(np.uint32)
+    expect = np.zeros(len(a2), np.int64)
+    for k, i in enumerate(order):
+        expect[i] = k + 1
+    assert np.array_equal(slot, expect)
