@@ -328,3 +328,6 @@ def test_halton_sampler_vs_oracle():
     ws, wsb = R.workspace(R.args(spp=1))
     out = torch.empty((61, 97, 3), dtype=torch.float32, device="cuda")
     assert ptmi.lib().pt_render_frame(R.h, ctypes.byref(a), out.data_ptr(), None, ws, wsb, R._stream()) == -1
+    a = R.args(spp=1)
+    a.tail_spread = 2  # 0 or 1 only
+    assert ptmi.lib().pt_render_frame(R.h, ctypes.byref(a), out.data_ptr(), None, ws, wsb, R._stream()) == -1
