@@ -160,7 +160,10 @@ typedef struct {
  * tail_spread: 1 = the hybrid tail spreads its queue over as many waves as
  * the device holds at once (partly filled waves, more latency hidden: faster
  * when a frame runs alone), 0 = full waves (fewer instructions: faster with
- * frames in flight); same image bit for bit. */
+ * frames in flight); same image bit for bit.
+ * mega_waves: the megakernel's occupancy, 4 (0 = default) or 5 waves per
+ * SIMD (more registers spilled: slower frame by frame, faster with frames in
+ * flight); same image bit for bit. */
 typedef struct {
     int32_t spp, max_depth;
     uint64_t seed;
@@ -176,6 +179,7 @@ typedef struct {
     int32_t tail_bounce;
     int32_t sampler;
     int32_t tail_spread;
+    int32_t mega_waves;
 } pt_render_args;
 
 /* Library version (major * 10000 + minor * 100 + patch). */

@@ -20,7 +20,7 @@ FRAME_SPACE = {
     "wave": {"block": [64, 128, 256], "grid_mult": [4, 8, 16], "stack_lds": [8, 16],
              "sort_threshold": [None, 1 << 16], "ray_sort": [False, True],
              "tail_threshold": [0, 1 << 16, 1 << 18, 1 << 19, 1 << 20]},
-    "mega": {"block": [64, 128, 256], "grid_mult": [2, 4, 8, 16], "stack_lds": [8, 16]},
+    "mega": {"block": [64, 128, 256], "grid_mult": [2, 4, 8, 16], "stack_lds": [8, 16], "mega_waves": [4, 5]},
 }
 # tried after the other wave parameters are chosen (0 = off)
 TAIL_BOUNCES = [0, 2, 3, 4, 5, 6]

@@ -167,6 +167,8 @@ pt_status check_args(const pt_ctx* c, const pt_render_args* a) {
     if (a->tail_bounce < 0 || a->tail_bounce > a->max_depth)
         return fail(PT_EINVAL, "tail_bounce must be in [0, max_depth]");
     if (a->tail_spread != 0 && a->tail_spread != 1) return fail(PT_EINVAL, "tail_spread must be 0 or 1");
+    if (a->mega_waves != 0 && a->mega_waves != 4 && a->mega_waves != 5)
+        return fail(PT_EINVAL, "mega_waves must be 0, 4 or 5");
     if (a->sampler != PT_SAMPLER_PHILOX && a->sampler != PT_SAMPLER_HALTON)
         return fail(PT_EINVAL, "sampler must be PT_SAMPLER_PHILOX or PT_SAMPLER_HALTON");
     if (a->mode != PT_MODE_MEGA && a->mode != PT_MODE_WAVE) return fail(PT_EINVAL, "unknown mode");
@@ -237,7 +239,7 @@ pt_status enqueue_stages(pt_ctx* c, const pt_render_args* a, const Launch& L, co
         PT_HIP(launch_init_counts(s, counts, w.ncounts, 0u), "init counters");
         // counters: [0] extension rays, [1] shadow rays, [2] overflow flag, [4..5] the
         // megakernel's 64-bit pixel cursor
-        PT_HIP(timed(c, prof, 5, s, [&] { return launch_mega(L.lds, count, grid, block, s, c->view, c->cam, pp, img, acc, ovf, L.gcap, counts, trav); }), "megakernel");
+        PT_HIP(timed(c, prof, 5, s, [&] { return launch_mega(L.lds, count, a->mega_waves == 5 ? 5 : 4, grid, block, s, c->view, c->cam, pp, img, acc, ovf, L.gcap, counts, trav); }), "megakernel");
     } else {
         WaveBufs wb{};
         for (int q = 0; q < 2; ++q) {

@@ -49,7 +49,8 @@ constexpr uint32_t kRefill = 16;
 // stats: [0] extension rays, [1] shadow rays, [2] overflow flag; trav:
 // node visits, triangle tests
 // count: traversal kernels also count node visits and triangle tests
-hipError_t launch_mega(int lds, bool count, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
+// waves: the megakernel's occupancy, 4 or 5 waves per SIMD
+hipError_t launch_mega(int lds, bool count, int waves, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
                        const CamView& cam, const PathParams& pp, float* img, float* acc, uint2* ovf, int gcap,
                        uint32_t* stats, unsigned long long* trav);
 hipError_t launch_init_counts(hipStream_t s, uint32_t* counts, int n, uint32_t first);

@@ -46,8 +46,8 @@ constexpr uint32_t kMegaChunk = 64u;
 
 // four waves per SIMD instead of the three the register count would give:
 // a few spilled registers cost less than the lost latency hiding
-template <int LDS, bool COUNT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_mega(SceneView sc, CamView cam, PathParams pp, float* __restrict__ img,
+template <int LDS, bool COUNT, int WAVES>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) k_mega(SceneView sc, CamView cam, PathParams pp, float* __restrict__ img,
                                               float* __restrict__ acc, uint2* __restrict__ ovf, int gcap,
                                               uint32_t* __restrict__ stats, unsigned long long* __restrict__ trav) {
     extern __shared__ __align__(8) uint32_t smem[];
@@ -448,11 +448,15 @@ __global__ void __launch_bounds__(256) k_accumulate(CamView cam, PathParams pp, 
 
 static size_t stack_lds_bytes(int lds, int block) { return trav_stack_lds_bytes(lds, block); }
 
-hipError_t launch_mega(int lds, bool count, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
+hipError_t launch_mega(int lds, bool count, int waves, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
                        const CamView& cam, const PathParams& pp, float* img, float* acc, uint2* ovf, int gcap,
                        uint32_t* stats, unsigned long long* trav) {
     size_t sm = stack_lds_bytes(lds, block.x);
-#define L(N, C) hipLaunchKernelGGL((k_mega<N, C>), grid, block, sm, s, sc, cam, pp, img, acc, ovf, gcap, stats, trav);
+#define L(N, C)                                                                                                      \
+    if (waves == 5)                                                                                                  \
+        hipLaunchKernelGGL((k_mega<N, C, 5>), grid, block, sm, s, sc, cam, pp, img, acc, ovf, gcap, stats, trav);    \
+    else                                                                                                             \
+        hipLaunchKernelGGL((k_mega<N, C, 4>), grid, block, sm, s, sc, cam, pp, img, acc, ovf, gcap, stats, trav);
 #define X(N) PT_DISPATCH(N, L)
     PT_STACK_CASES(X)
 #undef X

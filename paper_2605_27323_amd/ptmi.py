@@ -60,7 +60,8 @@ class RenderArgs(C.Structure):
                 ("job", C.c_uint32), ("nee", C.c_int32), ("rr_start", C.c_int32), ("mode", C.c_int32),
                 ("flags", C.c_int32), ("block", C.c_int32), ("grid_mult", C.c_int32),
                 ("sort_threshold", C.c_uint32), ("stack_lds", C.c_int32), ("tail_threshold", C.c_uint32),
-                ("tail_bounce", C.c_int32), ("sampler", C.c_int32), ("tail_spread", C.c_int32)]
+                ("tail_bounce", C.c_int32), ("sampler", C.c_int32), ("tail_spread", C.c_int32),
+                ("mega_waves", C.c_int32)]
 
 
 NSTAGES = 9
@@ -240,14 +241,14 @@ class Renderer(Context):
 
     def args(self, spp=1, max_depth=5, seed=0, frame=0, job=0, nee=True, rr_start=-1, mode="wave", flags=0,
              block=0, grid_mult=0, sort_threshold=0, stack_lds=0, tail_threshold=0, tail_bounce=0,
-             sampler="philox", tail_spread=False):
+             sampler="philox", tail_spread=False, mega_waves=0):
         m = MODE_WAVE if mode in ("wave", MODE_WAVE) else MODE_MEGA
         if sampler not in ("philox", "halton", SAMPLER_PHILOX, SAMPLER_HALTON):
             raise ValueError(f"unknown sampler {sampler!r} (philox or halton)")
         smp = SAMPLER_HALTON if sampler in ("halton", SAMPLER_HALTON) else SAMPLER_PHILOX
         return RenderArgs(int(spp), int(max_depth), int(seed), int(frame), int(job), int(bool(nee)), int(rr_start), m,
                           int(flags), int(block), int(grid_mult), int(sort_threshold), int(stack_lds),
-                          int(tail_threshold), int(tail_bounce), smp, int(bool(tail_spread)))
+                          int(tail_threshold), int(tail_bounce), smp, int(bool(tail_spread)), int(mega_waves))
 
     def workspace(self, a):
         need = C.c_uint64()

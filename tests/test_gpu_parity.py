@@ -177,6 +177,7 @@ def test_no_compaction_and_launch_shapes_bit_identical():
             R.render(mode="wave", block=64, grid_mult=1, **cfg),
             R.render(mode="wave", block=256, grid_mult=3, **cfg),
             R.render(mode="mega", block=64, grid_mult=2, **cfg),
+            R.render(mode="mega", mega_waves=5, **cfg),
             R.render(mode="wave", flags=ptmi.FLAG_SORT_MATERIAL, **cfg),
             R.render(mode="wave", flags=ptmi.FLAG_SORT_MATERIAL, sort_threshold=1500, **cfg),
             R.render(mode="wave", flags=ptmi.FLAG_SORT_MATERIAL, block=64, grid_mult=1, **cfg),
