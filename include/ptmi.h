@@ -248,9 +248,12 @@ pt_status pt_render_frames(pt_ctx* ctx, const pt_render_args* args, int32_t n_fr
  * d_emission (float[nt*3] device, input triangle order) the gradient of
  * sum_p sum_c d_image[p][c] * I[p][c] for the fixed-sample estimator defined
  * by (seed, frame, spp, job).  Each path is replayed twice from its random
- * numbers (radiance first, then gradients), nothing is stored per path.
- * PT_EINVAL if Russian roulette is on (its survival probability depends on
- * the albedo). */
+ * numbers: a first pass over all paths keeps only each path's radiance (16
+ * bytes per path in the workspace), a second pass replays them again and
+ * adds the gradients; no vertex is stored.  workspace: at least
+ * pt_workspace_size bytes for these args with mode PT_MODE_MEGA (or
+ * PT_MODE_WAVE, which is larger).  PT_EINVAL if Russian roulette is on (its
+ * survival probability depends on the albedo). */
 pt_status pt_render_backward(pt_ctx* ctx, const pt_render_args* args, const float* d_image,
                              float* d_albedo, float* d_emission, void* workspace,
                              uint64_t workspace_bytes, void* stream);

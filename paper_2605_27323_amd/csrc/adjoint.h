@@ -21,75 +21,103 @@
 
 namespace ptmi {
 
+// Replay B of one path as resumable steps, one path vertex per step, from
+// the path's radiance Ltot (replay A), so that a kernel can hand a lane
+// whose path has ended the next path while the others go on.
+struct AdjRun {
+    PathRun pr;  // ray, throughput and radiance gathered so far
+    f3 Ltot;     // radiance of the whole path
+    f3 delta;    // dLoss/dI(pixel) / spp
+    uint32_t pix, sample;
+};
+
+PT_DEV void adjoint_b_begin(const CamView& cam, const PathParams& pp, uint32_t pix, uint32_t sample, f3 delta,
+                            f3 Ltot, AdjRun& ar) {
+    path_begin(cam, pp, pix, sample, ar.pr);
+    ar.Ltot = Ltot;
+    ar.delta = delta;
+    ar.pix = pix;
+    ar.sample = sample;
+}
+
+// One vertex of replay B; returns false when the path is finished.
+template <int LDS, class Acc, bool COUNT = false>
+PT_DEV bool adjoint_b_step(const SceneView& sc, const PathParams& pp, AdjRun& ar, float* __restrict__ g_alb,
+                           float* __restrict__ g_emi, TravStack<LDS, COUNT>& st, Acc& acc) {
+    const f3 delta = ar.delta, Ltot = ar.Ltot;
+    const uint32_t pix = ar.pix, sample = ar.sample;
+    const int k = ar.pr.k;
+    const f3 o = ar.pr.o, d = ar.pr.d;
+    PathState& ps = ar.pr.ps;
+    Ray ray = make_ray(o, d);
+    Hit h = closest_hit<LDS>(sc, ray, INFINITY, st);
+    const f3 beta = ps.beta;
+    ShadowReq sh;
+    VertexOut vo = shade_vertex(sc, pp, pix, sample, k, d, h, ps, sh);
+    add_radiance(ps, vo);
+    if (vo.id == 0xFFFFFFFFu) return false;  // escaped: the sky is not a parameter
+    const uint32_t id = vo.id;
+    if (vo.emitted) {
+        acc.add_tri(vo.hot, 1, 0, g_emi + 3 * (size_t)id + 0, delta.x * (beta.x * vo.w_emit));
+        acc.add_tri(vo.hot, 1, 1, g_emi + 3 * (size_t)id + 1, delta.y * (beta.y * vo.w_emit));
+        acc.add_tri(vo.hot, 1, 2, g_emi + 3 * (size_t)id + 2, delta.z * (beta.z * vo.w_emit));
+    }
+    // the albedo gradient of this vertex: light-sample and continuation
+    // terms summed here, one accumulation per channel
+    float ga[3] = {0.0f, 0.0f, 0.0f};
+    if (sh.valid) {
+        Ray sr = make_ray(sh.o, sh.d);
+        if (!any_hit<LDS>(sc, sr, kShadowTmax, st)) {
+            ps.L = mk3(ps.L.x + sh.contrib.x, ps.L.y + sh.contrib.y, ps.L.z + sh.contrib.z);
+            const f3 rho = load3(sc.albedo, id);
+            const f3 Le = load3(sc.emission, sh.light_id);
+            const float der = lobe_der(sh.lobe);
+            const uint32_t lid = sh.light_id;
+            acc.add_light(sh.light_idx, 0, g_emi + 3 * (size_t)lid + 0,
+                          delta.x * (beta.x * (lobe_value(sh.lobe, rho.x) * sh.G)));
+            acc.add_light(sh.light_idx, 1, g_emi + 3 * (size_t)lid + 1,
+                          delta.y * (beta.y * (lobe_value(sh.lobe, rho.y) * sh.G)));
+            acc.add_light(sh.light_idx, 2, g_emi + 3 * (size_t)lid + 2,
+                          delta.z * (beta.z * (lobe_value(sh.lobe, rho.z) * sh.G)));
+            if (der != 0.0f) {
+                ga[0] = delta.x * (beta.x * ((der * sh.G) * Le.x));
+                ga[1] = delta.y * (beta.y * ((der * sh.G) * Le.y));
+                ga[2] = delta.z * (beta.z * ((der * sh.G) * Le.z));
+            }
+        }
+    }
+    const bool cont = vo.cont;
+    if (cont) {
+        const float der = lobe_der(vo.scat);
+        if (der != 0.0f) {
+            const f3 rho = load3(sc.albedo, id);
+            const float W[3] = {lobe_value(vo.scat, rho.x), lobe_value(vo.scat, rho.y), lobe_value(vo.scat, rho.z)};
+            const float post[3] = {Ltot.x - ps.L.x, Ltot.y - ps.L.y, Ltot.z - ps.L.z};
+            const float dl[3] = {delta.x, delta.y, delta.z};
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                if (W[c] != 0.0f) ga[c] += dl[c] * (post[c] * (der / W[c]));
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc.add_tri(vo.hot, 0, c, g_alb + 3 * (size_t)id + c, ga[c]);
+    if (!cont) return false;
+    ar.pr.o = vo.o;
+    ar.pr.d = vo.d;
+    ++ar.pr.k;
+    return true;
+}
+
+// The whole path: replay A, then replay B vertex by vertex.
 template <int LDS, class Acc, bool COUNT = false>
 PT_DEV void adjoint_path(const SceneView& sc, const CamView& cam, const PathParams& pp, uint32_t pix, uint32_t sample,
                          f3 delta, float* __restrict__ g_alb, float* __restrict__ g_emi, TravStack<LDS, COUNT>& st,
                          Acc& acc) {
     uint32_t ne = 0, ns = 0;
     const f3 Ltot = trace_path<LDS>(sc, cam, pp, pix, sample, st, ne, ns);
-    f3 o, d;
-    camera_sample(cam, pp, pix, sample, o, d);
-    PathState ps;
-    ps.beta = mk3(1.f, 1.f, 1.f);
-    ps.L = mk3(0.f, 0.f, 0.f);
-    ps.p_prev = 0.f;
-    ps.prev_smooth = 0;
-    for (int k = 1;; ++k) {
-        Ray ray = make_ray(o, d);
-        Hit h = closest_hit<LDS>(sc, ray, INFINITY, st);
-        const f3 beta = ps.beta;
-        ShadowReq sh;
-        VertexOut vo = shade_vertex(sc, pp, pix, sample, k, d, h, ps, sh);
-        add_radiance(ps, vo);
-        if (vo.id == 0xFFFFFFFFu) break;  // escaped: the sky is not a parameter
-        const uint32_t id = vo.id;
-        if (vo.emitted) {
-            acc.add_tri(vo.hot, 1, 0, g_emi + 3 * (size_t)id + 0, delta.x * (beta.x * vo.w_emit));
-            acc.add_tri(vo.hot, 1, 1, g_emi + 3 * (size_t)id + 1, delta.y * (beta.y * vo.w_emit));
-            acc.add_tri(vo.hot, 1, 2, g_emi + 3 * (size_t)id + 2, delta.z * (beta.z * vo.w_emit));
-        }
-        // the albedo gradient of this vertex: light-sample and continuation
-        // terms summed here, one accumulation per channel
-        float ga[3] = {0.0f, 0.0f, 0.0f};
-        if (sh.valid) {
-            Ray sr = make_ray(sh.o, sh.d);
-            if (!any_hit<LDS>(sc, sr, kShadowTmax, st)) {
-                ps.L = mk3(ps.L.x + sh.contrib.x, ps.L.y + sh.contrib.y, ps.L.z + sh.contrib.z);
-                const f3 rho = load3(sc.albedo, id);
-                const f3 Le = load3(sc.emission, sh.light_id);
-                const float der = lobe_der(sh.lobe);
-                const uint32_t lid = sh.light_id;
-                acc.add_light(sh.light_idx, 0, g_emi + 3 * (size_t)lid + 0,
-                              delta.x * (beta.x * (lobe_value(sh.lobe, rho.x) * sh.G)));
-                acc.add_light(sh.light_idx, 1, g_emi + 3 * (size_t)lid + 1,
-                              delta.y * (beta.y * (lobe_value(sh.lobe, rho.y) * sh.G)));
-                acc.add_light(sh.light_idx, 2, g_emi + 3 * (size_t)lid + 2,
-                              delta.z * (beta.z * (lobe_value(sh.lobe, rho.z) * sh.G)));
-                if (der != 0.0f) {
-                    ga[0] = delta.x * (beta.x * ((der * sh.G) * Le.x));
-                    ga[1] = delta.y * (beta.y * ((der * sh.G) * Le.y));
-                    ga[2] = delta.z * (beta.z * ((der * sh.G) * Le.z));
-                }
-            }
-        }
-        const bool cont = vo.cont;
-        if (cont) {
-            const float der = lobe_der(vo.scat);
-            if (der != 0.0f) {
-                const f3 rho = load3(sc.albedo, id);
-                const float W[3] = {lobe_value(vo.scat, rho.x), lobe_value(vo.scat, rho.y), lobe_value(vo.scat, rho.z)};
-                const float post[3] = {Ltot.x - ps.L.x, Ltot.y - ps.L.y, Ltot.z - ps.L.z};
-                const float dl[3] = {delta.x, delta.y, delta.z};
-#pragma unroll
-                for (int c = 0; c < 3; ++c)
-                    if (W[c] != 0.0f) ga[c] += dl[c] * (post[c] * (der / W[c]));
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) acc.add_tri(vo.hot, 0, c, g_alb + 3 * (size_t)id + c, ga[c]);
-        if (!cont) break;
-        o = vo.o;
-        d = vo.d;
+    AdjRun ar;
+    adjoint_b_begin(cam, pp, pix, sample, delta, Ltot, ar);
+    while (adjoint_b_step<LDS>(sc, pp, ar, g_alb, g_emi, st, acc)) {
     }
 }
 

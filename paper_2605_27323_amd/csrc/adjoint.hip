@@ -39,13 +39,73 @@ struct AtomicAcc {
 
 }  // namespace
 
-// four waves per SIMD (128 registers, some spilled) instead of the two that
-// the register count would give: −40 % backward time
+// Replay A of every path: its radiance, into Lpath[path].  One loop trip =
+// one path vertex; a lane whose path is done takes the next path of its
+// wave's chunk, a wave whose chunk is used up takes the next 64 paths from
+// cursor[0].
+template <int LDS>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_adjoint_radiance(
+    SceneView sc, CamView cam, PathParams pp, float4* __restrict__ Lpath, unsigned long long* __restrict__ cursor,
+    uint2* __restrict__ ovf, int gcap, uint32_t* __restrict__ stats) {
+    extern __shared__ __align__(8) uint32_t smem[];
+    const uint32_t nlanes = gridDim.x * blockDim.x;
+    const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
+    TravStack<LDS> st =
+        make_trav_stack<LDS>(reinterpret_cast<uint2*>(smem) + threadIdx.x, (int)blockDim.x, ovf, gtid, (int)nlanes, gcap);
+    const uint32_t npaths = (uint32_t)cam.W * (uint32_t)cam.H * (uint32_t)pp.spp;
+    uint32_t next = 0, end = 0;  // wave-uniform
+    bool drained = false;        // wave-uniform
+    bool live = false;
+    uint32_t path = 0, pix = 0, sample = 0, ne = 0, ns = 0;
+    PathRun pr;
+    while (true) {
+        const uint64_t idle = __ballot(!live);
+        if (idle != 0ull && !drained) {
+            if (next >= end) {
+                unsigned long long base = 0ull;
+                if (lane_id() == 0) base = atomicAdd(cursor, 64ull);
+                base = wave_broadcast_u64(base);
+                if (base >= (unsigned long long)npaths) {
+                    drained = true;
+                } else {
+                    next = (uint32_t)base;
+                    end = (uint32_t)min(base + 64ull, (unsigned long long)npaths);
+                }
+            }
+            if (!drained) {
+                if (!live) {
+                    const uint32_t p = next + rank_in(idle);
+                    if (p < end) {
+                        path = p;
+                        pix = p / (uint32_t)pp.spp;
+                        sample = pp.frame * (uint32_t)pp.spp + (p - pix * (uint32_t)pp.spp);
+                        path_begin(cam, pp, pix, sample, pr);
+                        live = true;
+                    }
+                }
+                next = min(next + (uint32_t)__popcll(idle), end);
+            }
+        }
+        if (__ballot(live) == 0ull) {
+            if (drained) break;
+            continue;
+        }
+        if (!live) continue;
+        if (path_vertex<LDS>(sc, pp, pix, sample, pr, st, ne, ns)) continue;
+        Lpath[path] = make_float4(pr.ps.L.x, pr.ps.L.y, pr.ps.L.z, 0.f);
+        live = false;
+    }
+    if (st.overflow) atomicOr(&stats[2], 1u);
+}
+
+// Replay B of every path, one vertex per loop trip with the same hand-out
+// of paths (cursor[1]), from the radiance replay A left in Lpath.
 template <int LDS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_adjoint(SceneView sc, CamView cam, PathParams pp,
-                                                 const float* __restrict__ d_img, float* __restrict__ g_alb,
+                                                 const float* __restrict__ d_img, const float4* __restrict__ Lpath,
+                                                 unsigned long long* __restrict__ cursor, float* __restrict__ g_alb,
                                                  float* __restrict__ g_emi, uint2* __restrict__ ovf, int gcap,
-                                                 uint32_t* __restrict__ stats, unsigned long long* __restrict__ trav) {
+                                                 uint32_t* __restrict__ stats) {
     extern __shared__ __align__(8) uint32_t smem[];
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -63,24 +123,47 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     __syncthreads();
     const uint32_t npaths = (uint32_t)cam.W * (uint32_t)cam.H * (uint32_t)pp.spp;
     const float fs = (float)pp.spp;
-    // a wave takes 64 paths at a time from the cursor, so waves whose paths
-    // were short take more of them and all finish together
-    unsigned long long* cursor = reinterpret_cast<unsigned long long*>(stats + 4);
+    uint32_t next = 0, end = 0;  // wave-uniform
+    bool drained = false;        // wave-uniform
+    bool live = false;
+    AdjRun ar;
     while (true) {
-        unsigned long long base = 0ull;
-        if (lane_id() == 0) base = atomicAdd(cursor, 64ull);
-        base = wave_broadcast_u64(base);
-        if (base >= (unsigned long long)npaths) break;
-        const uint32_t p = (uint32_t)base + lane_id();
-        if (p < npaths) {
-            const uint32_t pix = p / (uint32_t)pp.spp;
-            const uint32_t s = p - pix * (uint32_t)pp.spp;
-            const f3 delta =
-                mk3(d_img[3 * (size_t)pix] / fs, d_img[3 * (size_t)pix + 1] / fs, d_img[3 * (size_t)pix + 2] / fs);
-            adjoint_path<LDS>(sc, cam, pp, pix, pp.frame * (uint32_t)pp.spp + s, delta, g_alb, g_emi, st, acc);
+        const uint64_t idle = __ballot(!live);
+        if (idle != 0ull && !drained) {
+            if (next >= end) {
+                unsigned long long base = 0ull;
+                if (lane_id() == 0) base = atomicAdd(cursor + 1, 64ull);
+                base = wave_broadcast_u64(base);
+                if (base >= (unsigned long long)npaths) {
+                    drained = true;
+                } else {
+                    next = (uint32_t)base;
+                    end = (uint32_t)min(base + 64ull, (unsigned long long)npaths);
+                }
+            }
+            if (!drained) {
+                if (!live) {
+                    const uint32_t p = next + rank_in(idle);
+                    if (p < end) {
+                        const uint32_t pix = p / (uint32_t)pp.spp;
+                        const uint32_t s = p - pix * (uint32_t)pp.spp;
+                        const f3 delta = mk3(d_img[3 * (size_t)pix] / fs, d_img[3 * (size_t)pix + 1] / fs,
+                                             d_img[3 * (size_t)pix + 2] / fs);
+                        adjoint_b_begin(cam, pp, pix, pp.frame * (uint32_t)pp.spp + s, delta, xyz(Lpath[p]), ar);
+                        live = true;
+                    }
+                }
+                next = min(next + (uint32_t)__popcll(idle), end);
+            }
         }
+        if (__ballot(live) == 0ull) {
+            if (drained) break;
+            continue;
+        }
+        if (!live) continue;
+        if (!adjoint_b_step<LDS>(sc, pp, ar, g_alb, g_emi, st, acc)) live = false;
     }
-    // every thread of the block is here: add the block's light sums
+    // every thread of the block is here: add the block's sums
     __syncthreads();
     for (uint32_t j = threadIdx.x; j < 3 * acc.n_lds; j += blockDim.x) {
         const float v = light_g[j];
@@ -96,12 +179,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 }
 
 hipError_t launch_adjoint(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const CamView& cam,
-                          const PathParams& pp, const float* d_img, float* g_alb, float* g_emi, uint2* ovf, int gcap,
-                          uint32_t* stats, unsigned long long* trav) {
+                          const PathParams& pp, const float* d_img, float4* Lpath, unsigned long long* cursor,
+                          float* g_alb, float* g_emi, uint2* ovf, int gcap, uint32_t* stats) {
     size_t sm = trav_stack_lds_bytes(lds, (int)block.x);
 #define X(N)                                                                                                  \
     if (lds == N) {                                                                                           \
-        hipLaunchKernelGGL(k_adjoint<N>, grid, block, sm, s, sc, cam, pp, d_img, g_alb, g_emi, ovf, gcap, stats, trav); \
+        hipLaunchKernelGGL(k_adjoint_radiance<N>, grid, block, sm, s, sc, cam, pp, Lpath, cursor, ovf, gcap, stats); \
+        hipError_t e = hipGetLastError();                                                                     \
+        if (e != hipSuccess) return e;                                                                        \
+        hipLaunchKernelGGL(k_adjoint<N>, grid, block, sm, s, sc, cam, pp, d_img, Lpath, cursor, g_alb, g_emi, ovf, \
+                           gcap, stats);                                                                      \
         return hipGetLastError();                                                                             \
     }
     X(8) X(16) X(24) X(32)

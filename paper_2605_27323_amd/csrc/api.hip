@@ -121,7 +121,7 @@ pt_status launch_config(const pt_ctx* c, const pt_render_args* a, Launch& L) {
 }
 
 struct WsLayout {
-    size_t counts, trav, ovf, wave[11], sort_key, perm, hist, total;
+    size_t counts, trav, ovf, adj, wave[11], sort_key, perm, hist, total;
     int ncounts;
 };
 constexpr int kTravWords = 16;  // 8 u64 traversal work counters
@@ -140,6 +140,9 @@ WsLayout layout(const pt_ctx* c, const pt_render_args* a, const Launch& L) {
     off = align_up(off + sizeof(uint32_t) * kTravWords);
     w.ovf = off;
     off = align_up(off + sizeof(uint2) * (size_t)L.gcap * L.nlanes);
+    // megakernel layout: also the adjoint's two path cursors and per-path radiance
+    w.adj = off;
+    if (a->mode == PT_MODE_MEGA) off = align_up(off + kAlign + sizeof(float4) * npaths);
     for (int i = 0; i < 11; ++i) {
         w.wave[i] = off;
         if (a->mode == PT_MODE_WAVE) off = align_up(off + sizeof(float4) * npaths);
@@ -659,9 +662,12 @@ pt_status pt_render_backward(pt_ctx* c, const pt_render_args* a, const float* d_
     c->event_next = 0;
     PT_HIP(launch_init_counts(s, counts, w.ncounts, 0u), "init counters");
     PT_HIP(launch_init_counts(s, reinterpret_cast<uint32_t*>(trav), kTravWords, 0u), "init work counters");
+    unsigned long long* cursor = reinterpret_cast<unsigned long long*>(base + w.adj);
+    float4* Lpath = reinterpret_cast<float4*>(base + w.adj + kAlign);
+    PT_HIP(launch_init_counts(s, reinterpret_cast<uint32_t*>(cursor), 4, 0u), "init path cursors");
     PT_HIP(timed(c, prof, 7, s, [&] {
-               return launch_adjoint(L.lds, dim3(L.grid), dim3(L.block), s, c->view, c->cam, pp, d_image, d_albedo,
-                                     d_emission, ovf, L.gcap, counts, trav);
+               return launch_adjoint(L.lds, dim3(L.grid), dim3(L.block), s, c->view, c->cam, pp, d_image, Lpath, cursor,
+                                     d_albedo, d_emission, ovf, L.gcap, counts);
            }),
            "adjoint");
     remember_frame(c, a, counts, w.ncounts, 2, false);

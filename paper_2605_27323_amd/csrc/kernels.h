@@ -76,9 +76,11 @@ hipError_t launch_sort(dim3 grid, dim3 block, hipStream_t s, const SceneView& sc
                        uint32_t threshold, int key_kind);
 hipError_t launch_shadow(int lds, bool count, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
                          const WaveBufs& wb, int b, uint2* ovf, int gcap);
+// the adjoint: replay A of every path into Lpath (one float4 per path),
+// then replay B; cursor: two u64 path cursors, zero on entry
 hipError_t launch_adjoint(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const CamView& cam,
-                          const PathParams& pp, const float* d_img, float* g_alb, float* g_emi, uint2* ovf, int gcap,
-                          uint32_t* stats, unsigned long long* trav);
+                          const PathParams& pp, const float* d_img, float4* Lpath, unsigned long long* cursor,
+                          float* g_alb, float* g_emi, uint2* ovf, int gcap, uint32_t* stats);
 hipError_t launch_accumulate(dim3 grid, dim3 block, hipStream_t s, const CamView& cam, const PathParams& pp,
                              const float4* L, float* img, float* acc);
 // img = I, running average acc updated for frame `frame` (npix pixels)
