@@ -1,6 +1,7 @@
-// Adjoint kernel of libptmi: one thread per camera path sample, two replays
-// of the path from its random numbers, gradients added with hardware fp32
-// atomics (see adjoint.h for the algorithm).
+// Adjoint kernels of libptmi: replay A of every camera path sample (its
+// radiance, kept per path), then replay B from the same random numbers,
+// gradients added with hardware fp32 atomics (see adjoint.h for the
+// algorithm).
 #include "adjoint.h"
 #include "wave.h"
 #include "kernels.h"
