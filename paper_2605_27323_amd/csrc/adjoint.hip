@@ -43,9 +43,9 @@ struct AtomicAcc {
 // Replay A of every path: its radiance, into Lpath[path].  One loop trip =
 // one path vertex; a lane whose path is done takes the next path of its
 // wave's chunk, a wave whose chunk is used up takes the next 64 paths from
-// cursor[0].
+// cursor[0].  Five waves per SIMD, as the megakernel.
 template <int LDS>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_adjoint_radiance(
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k_adjoint_radiance(
     SceneView sc, CamView cam, PathParams pp, float4* __restrict__ Lpath, unsigned long long* __restrict__ cursor,
     uint2* __restrict__ ovf, int gcap, uint32_t* __restrict__ stats) {
     extern __shared__ __align__(8) uint32_t smem[];
