@@ -71,7 +71,8 @@ def lib():
     L.orc_bsdf_sample.argtypes = [C.c_int32, C.c_float, C.c_float, f32p, f32p, f32p, C.c_float, C.c_float,
                                   C.c_float, f32p, f32p, C.POINTER(C.c_float)]
     L.orc_sample_triangle.argtypes = [f32p, f32p, f32p, C.c_float, C.c_float, f32p]
-    L.orc_offset.argtypes = [f32p, f32p, f32p]
+    L.orc_offset.argtypes = [f32p, f32p, f32p, f32p]
+    L.orc_frame.argtypes = [f32p, f32p, f32p]
     L.orc_pick_light.restype = C.c_int32
     L.orc_pick_light.argtypes = [C.c_void_p, C.c_uint32]
     L.orc_unif.restype = C.c_float
@@ -252,7 +253,16 @@ def sample_triangle(v0, v1, v2, u1, u2):
     return out
 
 
-def offset(p, n):
+def frame(n):
+    """Tangent and bitangent of the BSDF frame around the unit normal n."""
+    t = np.zeros(3, np.float32)
+    b = np.zeros(3, np.float32)
+    lib().orc_frame(_f32(n), t, b)
+    return t, b
+
+
+def offset(p, n, tri):
+    """p moved off the plane of triangle tri (3 vertices) along the unit n."""
     out = np.zeros(3, np.float32)
-    lib().orc_offset(_f32(p), _f32(n), out)
+    lib().orc_offset(_f32(p), _f32(n), _f32(tri).reshape(-1), out)
     return out

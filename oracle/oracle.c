@@ -660,27 +660,30 @@ int32_t orc_anyhit(const orc_scene* s, int32_t n, const float* o, const float* d
 /* ------------------------------------------------------------------------ */
 /* geometry helpers                                                          */
 /* ------------------------------------------------------------------------ */
-/* Offset of a surface point off its plane along n (Waechter and Binder,
- * Ray Tracing Gems ch. 6, 2019): move each coordinate by int(256 n) ulps,
- * or by n / 65536 when the coordinate is within 1/32 of zero. */
-static v3 offset_point(v3 p, v3 n)
+/* Offset of a surface point off its plane along n: o = p + (2^-15 m) n per
+ * coordinate, m the largest coordinate magnitude of the triangle the point
+ * lies on (at least 2^-7).  The offset follows the scale idea of Waechter and
+ * Binder (Ray Tracing Gems ch. 6, 2019: about 256 ulps of the coordinates),
+ * but measures it on the triangle rather than on the point: the hit point and
+ * the next ray's intersection test with the same triangle carry rounding
+ * errors of a few ulps of the triangle's vertex coordinates, which on a large
+ * triangle near a coordinate plane (a ground plane at y = 0) exceed a step
+ * measured on the point's own small coordinates. */
+static float tri_extent(const float* p)
 {
-    float pp[3] = {p.x, p.y, p.z}, nn[3] = {n.x, n.y, n.z}, out[3];
-    for (int a = 0; a < 3; ++a) {
-        int32_t of = (int32_t)(256.0f * nn[a]);
-        int32_t bits;
-        memcpy(&bits, &pp[a], 4);
-        bits = bits + (pp[a] < 0.0f ? -of : of);
-        float moved;
-        memcpy(&moved, &bits, 4);
-        out[a] = fabsf(pp[a]) < 0x1p-5f ? pp[a] + 0x1p-16f * nn[a] : moved;
-    }
-    return V(out[0], out[1], out[2]);
+    float m = 0x1p-7f;
+    for (int i = 0; i < 9; ++i) m = fabsf(p[i]) > m ? fabsf(p[i]) : m;
+    return m;
+}
+static v3 offset_point(v3 p, v3 n, float m)
+{
+    float dl = 0x1p-15f * m;
+    return V(p.x + dl * n.x, p.y + dl * n.y, p.z + dl * n.z);
 }
 
-void orc_offset(const float p[3], const float n[3], float out[3])
+void orc_offset(const float p[3], const float n[3], const float tri[9], float out[3])
 {
-    vstore(out, offset_point(vload(p), vload(n)));
+    vstore(out, offset_point(vload(p), vload(n), tri_extent(tri)));
 }
 
 /* Uniform point on a triangle: b1 = sqrt(u1)(1-u2), b2 = sqrt(u1) u2,
@@ -723,6 +726,12 @@ static frame_t make_frame(v3 n)
     f.b = V(b, sign + n.y * n.y * a, -n.y);
     f.n = n;
     return f;
+}
+void orc_frame(const float n[3], float t[3], float b[3])
+{
+    frame_t f = make_frame(vload(n));
+    vstore(t, f.t);
+    vstore(b, f.b);
 }
 static v3 to_local(const frame_t* f, v3 w) { return V(vdot(f->t, w), vdot(f->b, w), vdot(f->n, w)); }
 static v3 to_world(const frame_t* f, v3 l)
@@ -1048,8 +1057,8 @@ static v3 trace_path(const pt_args* a, int pix, uint32_t sample, int* frag, vrec
                         float G = (cos_x * wmis) / pl;
                         const float* Le = s->emission + 3 * (size_t)lt;
                         v3 C = V((f.x * Le[0]) * G, (f.y * Le[1]) * G, (f.z * Le[2]) * G);
-                        v3 so = offset_point(x, vdot(ng, wl) > 0.0f ? ng : vneg(ng));
-                        v3 sy = offset_point(y, ny);
+                        v3 so = offset_point(x, vdot(ng, wl) > 0.0f ? ng : vneg(ng), tri_extent(tp));
+                        v3 sy = offset_point(y, ny, tri_extent(lp));
                         ray_t sr;
                         ray_setup(&sr, so, vsub(sy, so));
                         if (!occluded(s, &sr, SHADOW_TMAX, a->use_bvh, frag)) {
@@ -1081,7 +1090,7 @@ static v3 trace_path(const pt_args* a, int pix, uint32_t sample, int* frag, vrec
         if (vr) { vr->scat = 1; vr->scat_lobe = lb; }
         v3 wi = to_world(&fr, wi_l);
         v3 no = vdot(ng, wi) > 0.0f ? ng : vneg(ng);
-        ray_setup(&r, offset_point(x, no), wi);
+        ray_setup(&r, offset_point(x, no, tri_extent(tp)), wi);
         p_prev = pb;
         prev_smooth = type != ORC_DIELECTRIC;
     }

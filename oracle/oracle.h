@@ -111,11 +111,15 @@ int32_t orc_bsdf_sample(int32_t type, float rough, float ior, const float alb[3]
                         const float n[3], const float wo[3], float u4, float u5, float u6,
                         float wi[3], float weight[3], float* pdf);
 
+/* Local frame of the BSDFs around the unit normal n (Duff et al., JCGT 2017):
+ * tangent t and bitangent b, so that (t, b, n) is right-handed. */
+void orc_frame(const float n[3], float t[3], float b[3]);
 /* Uniform point on a triangle from (u1, u2); out = point. */
 void orc_sample_triangle(const float v0[3], const float v1[3], const float v2[3], float u1,
                          float u2, float out[3]);
-/* Self-intersection offset of p along n. */
-void orc_offset(const float p[3], const float n[3], float out[3]);
+/* Self-intersection offset of p along n; tri = the 9 vertex coordinates of
+ * the triangle p lies on (the offset scales with their magnitude). */
+void orc_offset(const float p[3], const float n[3], const float tri[9], float out[3]);
 /* Light pick: index of the light chosen by raw word w (-1 if no lights). */
 int32_t orc_pick_light(const orc_scene* s, uint32_t w);
 /* u32 -> [0,1) conversion used for every uniform variate. */

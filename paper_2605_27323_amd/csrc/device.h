@@ -675,17 +675,23 @@ PT_DEV bool any_hit(const SceneView& sc, const Ray& r, float tmax, TravStack<LDS
 // ---------------------------------------------------------------------------
 // geometry helpers
 // ---------------------------------------------------------------------------
-// Self-intersection offset (Waechter and Binder, Ray Tracing Gems ch. 6):
-// move each coordinate by int(256 n) ulps, or by n / 65536 near zero.
-PT_DEV float offset_coord(float p, float n) {
-    int of = (int)(256.0f * n);
-    int bits = (int)f2u(p);
-    bits = bits + (p < 0.0f ? -of : of);
-    float moved = u2f((uint32_t)bits);
-    return fabsf(p) < 0x1p-5f ? p + 0x1p-16f * n : moved;
+// Self-intersection offset: p + (2^-15 m) n per coordinate, m the largest
+// coordinate magnitude of the triangle p lies on (at least 2^-7).  The scale
+// is that of Waechter and Binder (Ray Tracing Gems ch. 6: about 256 ulps),
+// measured on the triangle: the hit point and the next intersection test
+// with the same triangle err by a few ulps of its vertex coordinates, which
+// on a large triangle near a coordinate plane exceed a step measured on the
+// point's own small coordinates.
+PT_DEV float tri_extent(f3 v0, f3 v1, f3 v2) {
+    const float c[9] = {v0.x, v0.y, v0.z, v1.x, v1.y, v1.z, v2.x, v2.y, v2.z};
+    float m = 0x1p-7f;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) m = fabsf(c[i]) > m ? fabsf(c[i]) : m;
+    return m;
 }
-PT_DEV f3 offset_point(f3 p, f3 n) {
-    return mk3(offset_coord(p.x, n.x), offset_coord(p.y, n.y), offset_coord(p.z, n.z));
+PT_DEV f3 offset_point(f3 p, f3 n, float m) {
+    const float dl = 0x1p-15f * m;
+    return mk3(p.x + dl * n.x, p.y + dl * n.y, p.z + dl * n.z);
 }
 
 PT_DEV f3 tri_normal(f3 v0, f3 v1, f3 v2) {
@@ -1074,8 +1080,8 @@ PT_DEV VertexOut shade_vertex(const SceneView& sc, const PathParams& pp, uint32_
                     uint32_t lid = f2u(la.w);
                     sh.C = mk3((f.x * Le_l.x) * G, (f.y * Le_l.y) * G, (f.z * Le_l.z) * G);
                     sh.contrib = mk3(ps.beta.x * sh.C.x, ps.beta.y * sh.C.y, ps.beta.z * sh.C.z);
-                    sh.o = offset_point(x, dot3(ng, wl) > 0.0f ? ng : neg3(ng));
-                    f3 sy = offset_point(y, ny);
+                    sh.o = offset_point(x, dot3(ng, wl) > 0.0f ? ng : neg3(ng), tri_extent(v0, v1, v2));
+                    f3 sy = offset_point(y, ny, tri_extent(xyz(la), xyz(lb4), xyz(lc4)));
                     sh.d = sub3(sy, sh.o);
                     sh.valid = true;
                     sh.light_id = lid;
@@ -1104,7 +1110,7 @@ PT_DEV VertexOut shade_vertex(const SceneView& sc, const PathParams& pp, uint32_
     }
     f3 wi = to_world(fr, wi_l);
     f3 no = dot3(ng, wi) > 0.0f ? ng : neg3(ng);
-    out.o = offset_point(x, no);
+    out.o = offset_point(x, no, tri_extent(v0, v1, v2));
     out.d = wi;
     out.cont = true;
     out.scat = lb;

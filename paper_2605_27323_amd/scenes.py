@@ -159,7 +159,9 @@ def _tri_params(nt, alb, emi, mat):
 # --------------------------------------------------------------------------
 # Cornell-style room: 5 walls, two boxes, one quad light (36 triangles)
 # --------------------------------------------------------------------------
-def cornell():
+def cornell(tall_box=None):
+    """tall_box: None (white Lambertian) or (roughness, ior) to make the
+    tall box a rough dielectric (material 1)."""
     white = (0.73, 0.73, 0.73)
     red = (0.63, 0.06, 0.05)
     green = (0.14, 0.45, 0.09)
@@ -180,12 +182,15 @@ def cornell():
     # left wall x=-1 facing +x (red), right wall x=+1 facing -x (green)
     add(*quad((-1, 0, -1), (-1, 2, -1), (-1, 2, 1), (-1, 0, 1)), red)
     add(*quad((1, 0, -1), (1, 0, 1), (1, 2, 1), (1, 2, -1)), green)
-    add(*box_mesh((-0.7, 0.0, -0.7), (-0.1, 1.2, -0.1), 1), white)
+    add(*box_mesh((-0.7, 0.0, -0.7), (-0.1, 1.2, -0.1), 1), white, mat=0 if tall_box is None else 1)
     add(*box_mesh((0.1, 0.0, -0.2), (0.7, 0.6, 0.4), 1), white)
     # light at y=1.999 facing -y
     add(*quad((-0.25, 1.999, -0.25), (0.25, 1.999, -0.25), (0.25, 1.999, 0.25), (-0.25, 1.999, 0.25)),
         (0.0, 0.0, 0.0), (15.0, 15.0, 15.0))
-    scene = _pack(P, I, M, A, E, [(LAMBERT, 1.0, 1.5, 0.0)])
+    mats = [(LAMBERT, 1.0, 1.5, 0.0)]
+    if tall_box is not None:
+        mats.append((DIELECTRIC, float(tall_box[0]), float(tall_box[1]), 0.0))
+    scene = _pack(P, I, M, A, E, mats)
     cam = dict(eye=(0.0, 1.0, 3.6), target=(0.0, 1.0, 0.0), up=(0.0, 1.0, 0.0),
                vfov_deg=40.0, width=128, height=128)
     return scene, cam
@@ -211,6 +216,39 @@ def plane_under_sky(albedo=0.6, sky=1.0, half=1.0, width=16, height=16, height_c
     scene = _pack([pos], [idx], [m], [a], [e], [(LAMBERT, 1.0, 1.5, 0.0)], sky=(sky,) * 3)
     cam = dict(eye=(0.0, height_cam, 0.0), target=(0.0, 0.0, 0.0), up=(0.0, 0.0, 1.0),
                vfov_deg=60.0, width=width, height=height)
+    return scene, cam
+
+
+def slab_over_plane(ior=1.5, rough=0.0, albedo=0.5, sky=1.0, half=1000.0, slab=(1.0, 2.0), width=16,
+                    height=16, vfov_deg=2.0):
+    """Diffuse square (half-width `half`) at y=0 facing +y under a closed
+    dielectric slab (a box spanning the same square, y in `slab`, outward
+    normals) and a constant sky; camera at y = 10 looking straight down
+    through a narrow field of view."""
+    p0, i0 = quad((-half, 0, -half), (-half, 0, half), (half, 0, half), (half, 0, -half))
+    p1, i1 = box_mesh((-half, slab[0], -half), (half, slab[1], half), 1)
+    m0, a0, e0 = _tri_params(2, (albedo,) * 3, (0, 0, 0), 0)
+    m1, a1, e1 = _tri_params(i1.shape[0], (0, 0, 0), (0, 0, 0), 1)
+    scene = _pack([p0, p1], [i0, i1], [m0, m1], [a0, a1], [e0, e1],
+                  [(LAMBERT, 1.0, 1.5, 0.0), (DIELECTRIC, rough, ior, 0.0)], sky=(sky,) * 3)
+    cam = dict(eye=(0.0, 10.0, 0.0), target=(0.0, 0.0, 0.0), up=(0.0, 0.0, 1.0),
+               vfov_deg=vfov_deg, width=width, height=height)
+    return scene, cam
+
+
+def emitter_in_slab(ior=1.5, rough=0.0, le=2.0, half=8.0, width=16, height=16):
+    """Upward-facing emissive square (y = 1.5, half-width `half`, albedo 0)
+    inside a closed dielectric slab (y in [1, 2], same extent, outward
+    normals); black sky; camera at y = 10 looking straight down through a
+    2-degree field of view."""
+    p0, i0 = quad((-half, 1.5, -half), (-half, 1.5, half), (half, 1.5, half), (half, 1.5, -half))
+    p1, i1 = box_mesh((-half, 1.0, -half), (half, 2.0, half), 1)
+    m0, a0, e0 = _tri_params(2, (0, 0, 0), (le,) * 3, 0)
+    m1, a1, e1 = _tri_params(i1.shape[0], (0, 0, 0), (0, 0, 0), 1)
+    scene = _pack([p0, p1], [i0, i1], [m0, m1], [a0, a1], [e0, e1],
+                  [(LAMBERT, 1.0, 1.5, 0.0), (DIELECTRIC, rough, ior, 0.0)])
+    cam = dict(eye=(0.0, 10.0, 0.0), target=(0.0, 0.0, 0.0), up=(0.0, 0.0, 1.0),
+               vfov_deg=2.0, width=width, height=height)
     return scene, cam
 
 

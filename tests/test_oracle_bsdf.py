@@ -238,17 +238,35 @@ def test_light_pick_area_proportional():
 
 
 def test_offset_moves_to_normal_side():
+    # o = p + 2^-15 m n, m = the triangle's largest coordinate magnitude
     rng = np.random.default_rng(7)
     for _ in range(500):
-        p = rng.uniform(-100, 100, 3).astype(np.float32)
+        tri = rng.uniform(-100, 100, (3, 3)).astype(np.float32) * np.float32(10.0 ** rng.uniform(-3, 1))
+        b = rng.dirichlet([1, 1, 1])
+        p = (b @ tri.astype(np.float64)).astype(np.float32)
         if rng.uniform() < 0.2:
-            p[rng.integers(0, 3)] = np.float32(rng.uniform(-0.01, 0.01))
+            p[rng.integers(0, 3)] = np.float32(0.0)
         nvec = rng.normal(size=3)
         nvec = (nvec / np.linalg.norm(nvec)).astype(np.float32)
-        q = oracle.offset(p, nvec)
+        q = oracle.offset(p, nvec, tri)
+        m = max(float(np.abs(tri).max()), 2.0 ** -7)
         dlt = q.astype(np.float64) - p
         assert np.dot(dlt, nvec) > 0
-        assert np.abs(dlt).max() <= 1e-4 * max(1.0, np.abs(p).max())
+        # each coordinate moves by 2^-15 m n_c, up to the rounding of the sum
+        ulp = np.spacing(np.abs(q).astype(np.float32)).astype(np.float64)
+        assert (np.abs(dlt - 2.0 ** -15 * m * nvec) <= ulp + 1e-30).all(), (dlt, m, nvec)
+
+
+def test_offset_clears_large_triangle_near_coordinate_plane():
+    # a ground quad of half-width 1000 at y = 0: the continuation ray leaving
+    # a hit near the origin upward never hits the quad again (a step of a
+    # fixed size near zero, below the rounding of the 1000-scale vertices,
+    # did about 1 time in 8)
+    scene, cam = scenes.plane_under_sky(albedo=0.5, sky=1.0, half=1000.0, width=16, height=16)
+    cam = dict(cam, vfov_deg=2.0)
+    S = oracle.Scene(scene)
+    _, _, ps = S.render(cam, spp=256, max_depth=3, seed=1, per_sample=True)
+    assert (ps == np.float32(0.5)).all()
 
 
 def test_camera_centre_and_fov():
