@@ -198,7 +198,7 @@ pt_status pt_load_scene(pt_ctx* ctx, const pt_scene_desc* scene);
 
 /* CPU build of the acceleration structure (paper Sec. 3 builds BLAS/TLAS
  * through the driver; here a binned-SAH binary BVH collapsed to a 4-wide
- * BVH with 128-byte nodes), the leaf-order triangle array and the
+ * BVH with 80-byte nodes), the leaf-order triangle array and the
  * area-proportional light CDF.  Synchronous, host only. */
 pt_status pt_build_bvh(pt_ctx* ctx, const pt_bvh_opts* opts, pt_bvh_info* info);
 
@@ -250,10 +250,12 @@ pt_status pt_render_frames(pt_ctx* ctx, const pt_render_args* args, int32_t n_fr
  * by (seed, frame, spp, job).  Each path is replayed twice from its random
  * numbers: a first pass over all paths keeps only each path's radiance (16
  * bytes per path in the workspace), a second pass replays them again and
- * adds the gradients; no vertex is stored.  workspace: at least
- * pt_workspace_size bytes for these args with mode PT_MODE_MEGA (or
- * PT_MODE_WAVE, which is larger).  PT_EINVAL if Russian roulette is on (its
- * survival probability depends on the albedo). */
+ * adds the gradients; no vertex is stored.  args->mode is ignored.
+ * workspace: at least pt_backward_workspace_size bytes (path cursors, the
+ * per-path radiance, the traversal stack overflow area), 256-byte aligned.
+ * PT_EINVAL if Russian roulette is on (its survival probability depends on
+ * the albedo). */
+pt_status pt_backward_workspace_size(pt_ctx* ctx, const pt_render_args* args, uint64_t* bytes);
 pt_status pt_render_backward(pt_ctx* ctx, const pt_render_args* args, const float* d_image,
                              float* d_albedo, float* d_emission, void* workspace,
                              uint64_t workspace_bytes, void* stream);
@@ -275,7 +277,8 @@ pt_status pt_render_backward(pt_ctx* ctx, const pt_render_args* args, const floa
  *     hybrid tail, megakernel), filled when the frame ran with
  *     PT_FLAG_COUNT_WORK (else 0).
  *   extension_rays, shadow_rays: rays traced by the frame (wavefront stages
- *   and hybrid tail, or megakernel, or adjoint replays).
+ *   and hybrid tail, or megakernel; for the adjoint the rays of the paths,
+ *   which replay A and replay B each trace once).
  * PT_EOVERFLOW if a traversal stack overflowed during the frame. */
 #define PT_NSTAGES 9
 typedef struct {

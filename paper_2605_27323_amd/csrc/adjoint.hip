@@ -96,6 +96,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k
         Lpath[path] = make_float4(pr.ps.L.x, pr.ps.L.y, pr.ps.L.z, 0.f);
         live = false;
     }
+    // the rays of the paths (replay B traces the same ones again): one
+    // atomic per wave for the whole kernel
+    for (int off = 32; off > 0; off >>= 1) {
+        ne += __shfl_xor(ne, off);
+        ns += __shfl_xor(ns, off);
+    }
+    if (lane_id() == 0 && (ne | ns)) {
+        atomicAdd(&stats[0], ne);
+        atomicAdd(&stats[1], ns);
+    }
     if (st.overflow) atomicOr(&stats[2], 1u);
 }
 

@@ -126,8 +126,9 @@ struct WsLayout {
 };
 constexpr int kTravWords = 16;  // 8 u64 traversal work counters
 
-// workspace: counters | traversal overflow stack | wavefront state
-WsLayout layout(const pt_ctx* c, const pt_render_args* a, const Launch& L) {
+// workspace: counters | traversal overflow stack | adjoint path cursors and
+// radiance (backward only) | wavefront state (wavefront only)
+WsLayout layout(const pt_ctx* c, const pt_render_args* a, const Launch& L, bool backward = false) {
     WsLayout w{};
     const size_t npaths = (size_t)c->cam.W * c->cam.H * a->spp;
     // [0, D+1] live paths per bounce, [D+2, 2D+2] shadow rays per bounce,
@@ -140,19 +141,20 @@ WsLayout layout(const pt_ctx* c, const pt_render_args* a, const Launch& L) {
     off = align_up(off + sizeof(uint32_t) * kTravWords);
     w.ovf = off;
     off = align_up(off + sizeof(uint2) * (size_t)L.gcap * L.nlanes);
-    // megakernel layout: also the adjoint's two path cursors and per-path radiance
+    // the adjoint's two path cursors and per-path radiance
     w.adj = off;
-    if (a->mode == PT_MODE_MEGA) off = align_up(off + kAlign + sizeof(float4) * npaths);
+    if (backward) off = align_up(off + kAlign + sizeof(float4) * npaths);
+    const bool wave = !backward && a->mode == PT_MODE_WAVE;
     for (int i = 0; i < 11; ++i) {
         w.wave[i] = off;
-        if (a->mode == PT_MODE_WAVE) off = align_up(off + sizeof(float4) * npaths);
+        if (wave) off = align_up(off + sizeof(float4) * npaths);
     }
     w.sort_key = off;
-    if (a->mode == PT_MODE_WAVE) off = align_up(off + sizeof(uint32_t) * npaths);
+    if (wave) off = align_up(off + sizeof(uint32_t) * npaths);
     w.perm = off;
-    if (a->mode == PT_MODE_WAVE) off = align_up(off + sizeof(uint32_t) * npaths);
+    if (wave) off = align_up(off + sizeof(uint32_t) * npaths);
     w.hist = off;
-    if (a->mode == PT_MODE_WAVE) off = align_up(off + sizeof(uint32_t) * (2 * kSortBins + 1));
+    if (wave) off = align_up(off + sizeof(uint32_t) * (2 * kSortBins + 1));
     w.total = off;
     return w;
 }
@@ -541,6 +543,18 @@ pt_status pt_workspace_size(pt_ctx* c, const pt_render_args* a, uint64_t* bytes)
     return PT_OK;
 }
 
+pt_status pt_backward_workspace_size(pt_ctx* c, const pt_render_args* a, uint64_t* bytes) {
+    if (!c || !a || !bytes) return fail(PT_EINVAL, "null argument");
+    if (!c->built) return fail(PT_ESTATE, "BVH not built");
+    if (!c->cam_set) return fail(PT_ESTATE, "camera not set");
+    if (a->spp < 1 || a->max_depth < 0 || a->max_depth > 1000) return fail(PT_EINVAL, "bad spp or max_depth");
+    Launch L;
+    pt_status st = launch_config(c, a, L);
+    if (st) return st;
+    *bytes = layout(c, a, L, true).total;
+    return PT_OK;
+}
+
 pt_status pt_render_frame(pt_ctx* c, const pt_render_args* a, float* img, float* acc, void* ws, uint64_t ws_bytes,
                           void* stream) {
     pt_status st = check_args(c, a);
@@ -643,13 +657,11 @@ pt_status pt_render_backward(pt_ctx* c, const pt_render_args* a, const float* d_
     if (!d_image || !d_albedo || !d_emission) return fail(PT_EINVAL, "null gradient buffer");
     if (!ws) return fail(PT_EINVAL, "null workspace");
     if ((reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return fail(PT_EINVAL, "workspace must be 256-byte aligned");
-    pt_render_args am = *a;
-    am.mode = PT_MODE_MEGA;
     Launch L;
-    st = launch_config(c, &am, L);
+    st = launch_config(c, a, L);
     if (st) return st;
-    WsLayout w = layout(c, &am, L);
-    if (ws_bytes < w.total) return fail(PT_ENOMEM, "workspace too small (pt_workspace_size)");
+    WsLayout w = layout(c, a, L, true);
+    if (ws_bytes < w.total) return fail(PT_ENOMEM, "workspace too small (pt_backward_workspace_size)");
     PT_HIP(hipSetDevice(c->device), "hipSetDevice");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     char* base = static_cast<char*>(ws);
@@ -704,9 +716,11 @@ pt_status pt_frame_stats_get(pt_ctx* c, pt_frame_stats* out) {
         out->stage_items[k] = (int64_t)npaths;
         out->node_visits[k] = (int64_t)tv[0];
         out->tri_tests[k] = (int64_t)tv[1];
-        // path state lives in registers: only the image (megakernel) or
-        // the image adjoint (read once per pixel) touches memory
-        out->stage_bytes[k] = (double)npix * (c->last_kind == 0 ? img_bytes : 12.0);
+        // path state lives in registers: the megakernel writes the image
+        // (and updates the running average); the adjoint writes each path's
+        // radiance in replay A and reads it and its pixel's image adjoint in
+        // replay B (16 W + 16 R + 12 R per path)
+        out->stage_bytes[k] = c->last_kind == 0 ? (double)npix * img_bytes : 44.0 * (double)npaths;
         if (h[2]) return fail(PT_EOVERFLOW, "traversal stack overflow");
         return PT_OK;
     }

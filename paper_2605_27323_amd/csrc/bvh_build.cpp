@@ -1,5 +1,5 @@
 // Host-side scene packing for libptmi: binned-SAH binary BVH collapsed to a
-// 4-wide BVH with 128-byte nodes, triangles reordered to leaf order, and the
+// 4-wide BVH with 80-byte nodes (binary16 child boxes), triangles reordered to leaf order, and the
 // area-proportional light CDF.  The paper builds its acceleration
 // structures through the Vulkan driver (Sec. 3); this is the software
 // counterpart for traversal on the compute units.

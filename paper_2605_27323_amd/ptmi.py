@@ -106,6 +106,7 @@ SIGNATURES = {
     "pt_frames_workspace_size": (C.c_int32, [C.c_void_p, C.POINTER(RenderArgs), C.POINTER(C.c_uint64)]),
     "pt_render_frames": (C.c_int32, [C.c_void_p, C.POINTER(RenderArgs), C.c_int32, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_uint64, C.c_void_p]),
+    "pt_backward_workspace_size": (C.c_int32, [C.c_void_p, C.POINTER(RenderArgs), C.POINTER(C.c_uint64)]),
     "pt_render_backward": (C.c_int32, [C.c_void_p, C.POINTER(RenderArgs), C.c_void_p, C.c_void_p, C.c_void_p,
                                        C.c_void_p, C.c_uint64, C.c_void_p]),
     "pt_frame_stats_get": (C.c_int32, [C.c_void_p, C.POINTER(FrameStats)]),
@@ -250,9 +251,10 @@ class Renderer(Context):
                           int(flags), int(block), int(grid_mult), int(sort_threshold), int(stack_lds),
                           int(tail_threshold), int(tail_bounce), smp, int(bool(tail_spread)), int(mega_waves))
 
-    def workspace(self, a):
+    def workspace(self, a, backward=False):
         need = C.c_uint64()
-        check(lib().pt_workspace_size(self.h, C.byref(a), C.byref(need)))
+        size = lib().pt_backward_workspace_size if backward else lib().pt_workspace_size
+        check(size(self.h, C.byref(a), C.byref(need)))
         if need.value > self._ws_bytes:
             self._ws = None
             self._ws, self._ws_ptr = _aligned_empty(need.value, self.torch_device)
@@ -299,7 +301,7 @@ class Renderer(Context):
     def backward(self, d_image, d_albedo, d_emission, **kw):
         """Accumulate the adjoint into d_albedo / d_emission (nt x 3 tensors)."""
         a = self.args(**kw)
-        ws, wsb = self.workspace(a)
+        ws, wsb = self.workspace(a, backward=True)
         d_image = d_image.contiguous()
         check(lib().pt_render_backward(self.h, C.byref(a), d_image.data_ptr(), d_albedo.data_ptr(),
                                        d_emission.data_ptr(), ws, wsb, self._stream()))

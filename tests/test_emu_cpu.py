@@ -175,14 +175,18 @@ def test_adjoint_matches_oracle(which):
 
 @pytest.mark.parametrize("capacity", [64, 333, 100000])
 def test_batch_pool_equals_standalone(capacity):
-    jobs = []
+    jobs, scenes_ = [], []
     for j, (seed, n, w, h, spp) in enumerate([(1000, 8, 33, 21, 2), (1001, 20, 16, 16, 3), (1002, 3, 40, 8, 1)]):
         s, c = scenes.procedural(seed=seed, n_objects=n, width=w, height=h)
         jobs.append((emu.Emu(s, c), dict(spp=spp, max_depth=6, rr_start=3, seed=5, frame=1)))
+        scenes_.append((s, c))
     imgs, it = emu.render_batch([e for e, _ in jobs], [kw for _, kw in jobs], capacity, shuffle=capacity)
     for j, (e, kw) in enumerate(jobs):
         ref, _ = e.mega(job=j, **kw)
         assert np.array_equal(imgs[j].view(np.uint32), ref.view(np.uint32))
+        # the oracle's image of job j (the job index keys its random numbers)
+        o, frag = oracle.Scene(scenes_[j][0]).render(scenes_[j][1], job=j, **kw)
+        assert_parity(imgs[j], o, frag, what=f"pool job {j}")
 
 
 def test_far_camera():

@@ -19,7 +19,7 @@ import pytest
 
 import oracle
 from paper_2605_27323_amd import scenes
-from tests._parity import assert_parity
+from tests._parity import assert_parity, oracle_image
 
 pytestmark = pytest.mark.gpu
 
@@ -92,12 +92,13 @@ def test_adjoint_full_size_sampled_pixels():
 
 def test_batch_full_size_sampled_jobs():
     specs = scenes.batch_jobs(seed=4, n_jobs=64)
-    Rs, args = [], []
+    Rs, args, sc_all = [], [], []
     for j, sp in enumerate(specs):
         sc, cam = scenes.procedural(seed=sp["scene_seed"], n_objects=sp["n_objects"], width=sp["width"],
                                     height=sp["height"])
         Rs.append(ptmi.Renderer(sc, cam))
         args.append(dict(spp=sp["spp"], max_depth=8, rr_start=3, nee=True, seed=0, job=j))
+        sc_all.append((sc, cam) if j in (7, 31, 63) else None)
     log("batch 64 jobs", sum(R.nt for R in Rs), "triangles")
     imgs, ms, res = ptmi.render_batch(Rs, args, pool_capacity=1 << 22, block=256, grid_mult=8, stack_lds=8)
     torch.cuda.synchronize()
@@ -109,3 +110,11 @@ def test_batch_full_size_sampled_jobs():
         ref = Rs[j].render(mode="wave", **args[j], **WAVE).cpu().numpy()
         assert np.array_equal(imgs[j].cpu().numpy().view(np.uint32), ref.view(np.uint32)), j
     log("jobs compared:", pick)
+    # against the oracle: 1024 sampled pixels of jobs 7, 31 and 63 (job != 0
+    # keys their random numbers)
+    for j in (7, 31, 63):
+        sc, cam = sc_all[j]
+        px = scenes.pixel_subset(cam["width"], cam["height"], 1024, seed=1234 + j)
+        ref, frag, _ = oracle_image(sc, cam, pixels=px, **args[j])
+        got = imgs[j].cpu().numpy().reshape(-1, 3)[px]
+        assert_parity(got, ref, frag, what=f"batch job {j} ({Rs[j].nt} triangles) vs oracle")
