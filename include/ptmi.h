@@ -227,6 +227,23 @@ pt_status pt_render_frame(pt_ctx* ctx, const pt_render_args* args, float* image_
                           float* accum_inout, void* workspace, uint64_t workspace_bytes,
                           void* stream);
 
+/* For callers that cannot allocate device memory or pass a workspace (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): pt_render_frame with the megakernel (args->mode must be
+ * PT_MODE_MEGA, else PT_EUNSUPPORTED; PT_FLAG_PROFILE is PT_EINVAL), whose
+ * counters, pixel cursor and traversal stack overflow area live in a scratch
+ * array of 64 MiB that the library holds on each GPU it runs on (looked up
+ * by pt_create) until the process ends.  The caller passes the image and the
+ * optional running average as in pt_render_frame; the call allocates
+ * nothing.  PT_ENOMEM if the frame's launch configuration needs more scratch
+ * than that (the traversal stack overflow area grows with grid_mult x block
+ * x (BVH stack entries - stack_lds) x 8 bytes).  Every call on a GPU shares
+ * that GPU's array and leaves its contents behind (pt_frame_stats_get reads
+ * the last call's counters): calls that overlap on one GPU, from any
+ * context, race.  The image equals pt_render_frame's bit for bit. */
+pt_status pt_render_frame_noalloc(pt_ctx* ctx, const pt_render_args* args, float* image_out, float* accum_inout,
+                                  void* stream);
+
 /* Progressive rendering with three frames in flight: frames args->frame,
  * ..., args->frame + n_frames - 1, each exactly as pt_render_frame renders
  * it.  A frame's stages run on one of three internal streams of the context

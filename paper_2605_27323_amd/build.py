@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libptmi.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("PTMI_ARCH", "gfx950")
 
-SOURCES = ["api.hip", "kernels.hip", "adjoint.hip", "batch.hip", "bvh_build.cpp"]
+SOURCES = ["api.hip", "kernels.hip", "adjoint.hip", "batch.hip", "noalloc.hip", "bvh_build.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-mcode-object-version=5",

@@ -10,6 +10,7 @@
 #include "batch.h"
 #include "bvh_build.h"
 #include "kernels.h"
+#include "noalloc.h"
 
 using namespace ptmi;
 
@@ -358,6 +359,13 @@ pt_status pt_create(pt_ctx** out, int32_t device) {
         c->num_cu = prop.multiProcessorCount;
         c->lds_per_block = prop.sharedMemPerBlock;
         c->device = device;
+        // the device address of this GPU's scratch array (the allocation-free
+        // entry point's memory), looked up once per device
+        e = noalloc_scratch_init(device);
+        if (e != hipSuccess) {
+            delete c;
+            return hip_fail(e, "device scratch address");
+        }
     }
     *out = c;
     return PT_OK;
@@ -580,6 +588,30 @@ pt_status pt_render_frame(pt_ctx* c, const pt_render_args* a, float* img, float*
         PT_HIP(timed(c, prof, 4, s, [&] { return launch_accumulate(dim3(L.grid), dim3(L.block), s, c->cam, pp, Lbuf, img, acc); }), "accumulate");
     }
     return PT_OK;
+}
+
+pt_status pt_render_frame_noalloc(pt_ctx* c, const pt_render_args* a, float* img, float* acc, void* stream) {
+    pt_status st = check_args(c, a);
+    if (st) return st;
+    if (!img) return fail(PT_EINVAL, "null image");
+    if (a->mode != PT_MODE_MEGA) return fail(PT_EUNSUPPORTED, "pt_render_frame_noalloc renders with PT_MODE_MEGA only");
+    if (a->flags & PT_FLAG_PROFILE) return fail(PT_EINVAL, "PT_FLAG_PROFILE creates events; not in pt_render_frame_noalloc");
+    Launch L;
+    st = launch_config(c, a, L);
+    if (st) return st;
+    const WsLayout w = layout(c, a, L);
+    if (w.total > kNoAllocScratchBytes)
+        return fail(PT_ENOMEM, "the frame needs " + std::to_string(w.total) + " bytes of device scratch, more than the " +
+                                   std::to_string(kNoAllocScratchBytes) +
+                                   " the library holds per GPU: lower grid_mult or block, or raise stack_lds");
+    void* ptr = noalloc_scratch(c->device);
+    if (!ptr) return fail(PT_ESTATE, "no device scratch address for this device");
+    PT_HIP(hipSetDevice(c->device), "hipSetDevice");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    c->timers.clear();
+    c->event_next = 0;
+    const float4* Lbuf = nullptr;
+    return enqueue_stages(c, a, L, w, static_cast<char*>(ptr), s, img, acc, false, &Lbuf);
 }
 
 pt_status pt_frames_workspace_size(pt_ctx* c, const pt_render_args* a, uint64_t* bytes) {

@@ -103,6 +103,7 @@ SIGNATURES = {
     "pt_workspace_size": (C.c_int32, [C.c_void_p, C.POINTER(RenderArgs), C.POINTER(C.c_uint64)]),
     "pt_render_frame": (C.c_int32, [C.c_void_p, C.POINTER(RenderArgs), C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_uint64, C.c_void_p]),
+    "pt_render_frame_noalloc": (C.c_int32, [C.c_void_p, C.POINTER(RenderArgs), C.c_void_p, C.c_void_p, C.c_void_p]),
     "pt_frames_workspace_size": (C.c_int32, [C.c_void_p, C.POINTER(RenderArgs), C.POINTER(C.c_uint64)]),
     "pt_render_frames": (C.c_int32, [C.c_void_p, C.POINTER(RenderArgs), C.c_int32, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_uint64, C.c_void_p]),
@@ -274,6 +275,21 @@ class Renderer(Context):
             assert accum.is_contiguous() and accum.numel() == out.numel()
             acc_ptr = accum.data_ptr()
         check(lib().pt_render_frame(self.h, C.byref(a), out.data_ptr(), acc_ptr, ws, wsb, self._stream()))
+        return out
+
+    def render_noalloc(self, out=None, accum=None, **kw):
+        """Megakernel frame through pt_render_frame_noalloc (no workspace: the
+        library's own per-GPU scratch); returns the image tensor."""
+        import torch
+        a = self.args(**dict(kw, mode="mega"))
+        if out is None:
+            out = torch.empty((self.height, self.width, 3), dtype=torch.float32, device=self.torch_device)
+        assert out.is_contiguous() and out.dtype == torch.float32 and out.numel() == self.height * self.width * 3
+        acc_ptr = None
+        if accum is not None:
+            assert accum.is_contiguous() and accum.numel() == out.numel()
+            acc_ptr = accum.data_ptr()
+        check(lib().pt_render_frame_noalloc(self.h, C.byref(a), out.data_ptr(), acc_ptr, self._stream()))
         return out
 
     def render_frames(self, n_frames, out=None, accum=None, **kw):
