@@ -8,10 +8,20 @@ depth 6, roulette off.
 One step = one frame of the wavefront pipeline (raygen, extend, shade,
 shadow, accumulate over all bounces).  Inputs are resident in device memory
 before timing starts.  Prints one JSON line.
+
+Besides the headline (the wavefront with the hybrid tail, three frames in
+flight) the line carries: the pure wavefront (every bounce a separate
+extend / shade / shadow launch over compacted queues) and the megakernel,
+frame by frame and in flight; compaction against no compaction at depth 8
+and 16; the roofline of every traversal kernel, of the megakernel and of
+both adjoint kernels; short runs of the divergence workload (10M triangles,
+64 material ids) and of the batched workload (64 jobs); and the oracle
+timed on the host cores.
 """
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -19,52 +29,65 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP32_VECTOR_PEAK_TFLOPS = 157.3
-# algorithmic flops of one BVH4 node visit (four slab tests of 26 flops:
-# 6 subtractions, 6 multiplications, 12 min/max, slack multiply, compare)
-# and of one watertight triangle test (51 flops on its full path)
-FLOPS_PER_NODE = 104
-FLOPS_PER_TRI = 51
-# autotuner result on MI355X for the 1M-triangle 1080p workload
-FIXED_PARAMS = {"wave": {"block": 256, "grid_mult": 8, "stack_lds": 8, "tail_threshold": 1 << 18, "tail_bounce": 4},
-                "mega": {"block": 256, "grid_mult": 4, "stack_lds": 8}}
+# fp32 vector peak: 256 CUs x 2.4 GHz x 64 lanes x 2 flops (one wave64 fused
+# multiply-add per CU and cycle) = 78.6 TFLOP/s; packed FP32 (or dual issue)
+# doubles it to 157.3, but this build disables packed FP32, so 78.6 is the
+# reachable ceiling
+FP32_PEAK_TFLOPS = 78.6
+FP32_PEAK_PACKED_TFLOPS = 157.3
+# algorithmic flops of traversal: a BVH4 node visit tests four child boxes
+# (20 flops each: six plane distances of one fused multiply-add, three
+# maxima, three minima, the slack multiply and the compare), a watertight
+# ray/triangle test 40 (9 subtractions, 12 for the shear, 9 for the edge
+# functions, 2 for the determinant, 8 for the scaled depth and the division)
+FLOPS_PER_NODE = 80
+FLOPS_PER_TRI = 40
+# the launch parameters the autotuner chose on MI355X for the wavefront with
+# three frames in flight and for the megakernel; the stage profile, the
+# rooflines and the committed rocprofv3 profiles use them (bench.py --fixed)
+FIXED_PARAMS = {"wave": {"block": 256, "grid_mult": 4, "stack_lds": 8, "tail_threshold": 1 << 18, "tail_bounce": 3},
+                "mega": {"block": 256, "grid_mult": 4, "stack_lds": 8, "mega_waves": 5}}
+# the pure wavefront: no hybrid tail, every bounce in separate stage launches
+PURE = {"tail_threshold": 0, "tail_bounce": 0, "tail_spread": False}
 # launch parameters of the divergence workload (4 spp, depth 16)
 DIVERGENCE_PARAMS = {"wave": {"block": 256, "grid_mult": 8, "stack_lds": 8, "tail_threshold": 1 << 18, "tail_bounce": 6},
                      "mega": {"block": 256, "grid_mult": 4, "stack_lds": 8}}
+# batch options the autotuner chose for the 64-job workload
+BATCH_OPTS = {"pool_capacity": 1 << 23, "block": 256, "grid_mult": 8, "stack_lds": 8, "pools": 3}
 W, H, SPP, DEPTH, RR = 1920, 1080, 1, 8, 3
+PROFILE = "procedural1M_1080p"
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic(kernel, field="hbm_bytes_per_dispatch"):
-    """HBM bytes per dispatch of `kernel` (or another recorded field) from the
-    committed rocprofv3 counter summary, or None when the kernel sources
-    changed since it was taken."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", "k_extend_procedural1M_1080p.json")
-    if not os.path.exists(path):
-        return None
-    prof = json.load(open(path))
-    h = hashlib.sha256()
-    for f in ["device.h", "wavefront.h", "wave.h", "kernels.hip", "kernels.h", "ptmi_internal.h"]:
-        h.update(open(os.path.join(ROOT, "paper_2605_27323_amd", "csrc", f), "rb").read())
-    if h.hexdigest()[:16] != prof["source_hash"]:
-        return None
-    k = prof["kernels"].get(kernel)
-    return k.get(field) if k else None
+def host_cpu():
+    """CPU model and core counts of this host (the oracle's baseline runs here)."""
+    model = platform.processor() or ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"model": model, "nproc": aff, "cpu_count": os.cpu_count(),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
 
 
 def cpu_baseline(scene, cam, budget_s=12.0, single_s=3.0):
-    """The oracle (plain C, all host threads) on whole frames 0, 1, 2, ...
-    of the benchmark workload, split in 262144-pixel chunks, until the time
-    budget is spent."""
+    """The oracle (plain C, all host threads this process may use, at most
+    16: the host share of one GPU on the MI355X boxes, whose harness sets
+    OMP_NUM_THREADS=16) on whole frames 0, 1, 2, ... of the benchmark
+    workload, split in 262144-pixel chunks, until the time budget is spent;
+    and on one thread."""
     import numpy as np
 
     import oracle
-    # the cores this process may use, at most 16 (the host share of one GPU)
-    threads = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()))
+    cpu = host_cpu()
+    threads = max(1, min(16, cpu["nproc"]))
     t0 = time.perf_counter()
     S = oracle.Scene(scene)
     build_s = time.perf_counter() - t0
@@ -87,6 +110,8 @@ def cpu_baseline(scene, cam, budget_s=12.0, single_s=3.0):
     return {"value": done * SPP / dt, "unit": "path-samples/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} paths = {done / npix:.2f} frames of the {W}x{H} 1-spp workload (frames 0..{frame}), "
                       f"{dt:.1f} s render on {threads} threads, BVH build {build_s:.1f} s excluded",
+            "host": cpu,
+            "threads_note": "threads = the CPUs this process may use, capped at 16 (the host share of one GPU)",
             "single_thread": {"value": done1 * SPP / dt1, "sample": f"first {done1} paths of frame 0, {dt1:.1f} s"}}
 
 
@@ -107,6 +132,81 @@ def copy_ceiling(torch):
     return {"value": 2 * (1 << 30) / dt / 1e9, "unit": "GB/s", "bytes_per_copy": 2 * (1 << 30)}
 
 
+def time_frames(torch, R, img, k, first, in_flight, **kw):
+    """Seconds for k frames (first .. first + k - 1), frame by frame or with
+    three in flight, after the caller's warm-up."""
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    if in_flight:
+        R.render_frames(k, out=img, frame=first, **kw)
+    else:
+        for i in range(k):
+            R.render(out=img, frame=first + i, **kw)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t
+
+
+def schedule_run(torch, R, img, params, steps, warmup, kw, mode):
+    """Frame-by-frame and in-flight rates of one schedule."""
+    out = {"params": params}
+    for name, infl in [("frame_by_frame", False), ("frames_in_flight", True)]:
+        p = params[name]
+        time_frames(torch, R, img, max(1, warmup), 0, infl, mode=mode, **kw, **p)
+        dt = time_frames(torch, R, img, steps, warmup, infl, mode=mode, **kw, **p)
+        out[name] = {"ms_per_step": dt * 1e3 / steps, "value": W * H * SPP * steps / dt}
+    return out
+
+
+def profiled_frames(R, img, ptmi, mode, params, k, first, kw):
+    """k frames with per-stage HIP-event timing, then the same k frames with
+    the work-counting kernels: stage times, launches, items, algorithmic
+    state bytes, rays, node visits and triangle tests (summed)."""
+    acc = {"stage_ms": {}, "launches": {}, "items": {}, "bytes": {}, "node_visits": {}, "tri_tests": {},
+           "extension_rays": 0, "shadow_rays": 0, "frames": k}
+    for flag, keys in [(ptmi.FLAG_PROFILE, ("stage_ms", "launches", "items", "bytes")),
+                       (ptmi.FLAG_COUNT_WORK, ("node_visits", "tri_tests"))]:
+        for i in range(k):
+            p = dict(params)
+            p["flags"] = p.get("flags", 0) | flag
+            R.render(out=img, mode=mode, frame=first + i, **kw, **p)
+            st = R.stats()
+            for key in keys:
+                for s, v in st[key].items():
+                    acc[key][s] = acc[key].get(s, 0) + v
+            if flag == ptmi.FLAG_PROFILE:
+                acc["extension_rays"] += st["extension_rays"]
+                acc["shadow_rays"] += st["shadow_rays"]
+    return acc
+
+
+def roofline_entry(kernel, launches, ms, state_bytes, nodes, tris, prof, copy_gbs):
+    """Roofline figures of one kernel from its summed event times, launches,
+    algorithmic state bytes and traversal work, with the measured HBM
+    traffic and counters of the committed profile (None when stale)."""
+    avg_ms = ms / launches
+    e = {"kernel": kernel, "launches": launches, "avg_launch_ms": avg_ms}
+    per_bytes = state_bytes / launches
+    gbs = per_bytes / (avg_ms * 1e-3) / 1e9
+    e["state"] = {"bytes_per_launch": per_bytes, "achieved_gbs": gbs, "frac_hbm_peak": gbs / HBM_PEAK_GBS,
+                  "frac_copy_ceiling": gbs / copy_gbs if copy_gbs else None}
+    if nodes is not None:
+        per_flops = (FLOPS_PER_NODE * nodes + FLOPS_PER_TRI * tris) / launches
+        tf = per_flops / (avg_ms * 1e-3) / 1e12
+        e["alu"] = {"flops_per_launch": per_flops, "node_visits_per_launch": nodes / launches,
+                    "tri_tests_per_launch": tris / launches, "achieved_tflops": tf,
+                    "frac_fp32_peak": tf / FP32_PEAK_TFLOPS, "frac_fp32_packed_peak": tf / FP32_PEAK_PACKED_TFLOPS}
+    k = (prof or {}).get("kernels", {}).get(kernel)
+    if k:
+        traffic = k.get("hbm_bytes_per_dispatch")
+        e["measured"] = {"hbm_bytes_per_dispatch": traffic,
+                         "hbm_gbs": traffic / (avg_ms * 1e-3) / 1e9 if traffic else None,
+                         "traffic_over_state": traffic / per_bytes if traffic and per_bytes else None,
+                         "profile_avg_us": k.get("avg_us"), "valu_per_cu_cycle": k.get("valu_per_cu_cycle"),
+                         "l2_hit_rate": k.get("l2_hit_rate"), "waves_per_simd": k.get("waves_per_simd"),
+                         "vgpr": k.get("vgpr"), "lds": k.get("lds"), "scratch": k.get("scratch")}
+    return e
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,7 +214,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--mode", default="both", choices=["both", "wave", "mega"])
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the divergence and batched workload summaries and the compaction ablation")
+    ap.add_argument("--schedules", default="wave_hybrid,wave_pure,mega",
+                    help="comma-separated schedules to run: wave_hybrid, wave_pure, mega")
     ap.add_argument("--no-tune", action="store_true", help="default launch parameters instead of the autotuner")
     ap.add_argument("--fixed", action="store_true",
                     help="launch parameters the autotuner chose on MI355X for this workload, without tuning "
@@ -143,15 +246,16 @@ def main():
               f"note, not a measured configuration", file=sys.stderr, flush=True)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
-    from paper_2605_27323_amd import autotune, ptmi, scenes
+    from paper_2605_27323_amd import autotune, profiles, ptmi, scenes
 
     if args.batch:
-        return batch_bench(args)
+        print(json.dumps(batch_bench(args, torch, ptmi, scenes, autotune)), flush=True)
+        return
     if args.divergence:
-        return divergence_bench(args)
+        print(json.dumps(divergence_bench(args, torch, ptmi, scenes)), flush=True)
+        return
     t0 = time.perf_counter()
     scene, cam = scenes.procedural(seed=2, n_objects=2000, width=W, height=H)
     nt = scene["indices"].shape[0]
@@ -160,143 +264,117 @@ def main():
         f"built in {R.info.build_seconds:.2f} s (setup {time.perf_counter() - t0:.1f} s)")
     kw = dict(spp=SPP, max_depth=DEPTH, rr_start=RR, nee=True, seed=0)
     img = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
-    modes = ["wave", "mega"] if args.mode == "both" else [args.mode]
-    tuned = {m: {} for m in modes}
-    if args.params:
-        given = json.loads(args.params)
-        tuned = {m: dict(given.get(m, FIXED_PARAMS[m])) for m in modes}
-    elif args.fixed:
-        tuned = {m: dict(FIXED_PARAMS[m]) for m in modes}
-    elif not args.no_tune:
-        for mode in modes:
-            t = time.perf_counter()
-            tuned[mode] = autotune.tune_frame(R, mode=mode, cache=None, log=log, **kw)
-            log(f"autotune {mode}: {tuned[mode]} ({time.perf_counter() - t:.1f} s)")
+    schedules = [x for x in args.schedules.split(",") if x]
+    if not schedules or any(x not in ("wave_hybrid", "wave_pure", "mega") for x in schedules):
+        raise SystemExit(f"unknown schedule list {args.schedules!r}")
+    modes = (["wave"] if any(x.startswith("wave") for x in schedules) else []) + (["mega"] if "mega" in schedules else [])
 
-    def run(mode, k, first, flags=0):
-        p = dict(tuned[mode])
-        p["flags"] = p.get("flags", 0) | flags
-        for i in range(k):
-            R.render(out=img, mode=mode, frame=first + i, **kw, **p)
-
-    res = {}
+    # launch parameters per schedule, frame by frame and three frames in flight
+    tuned = {}
     for mode in modes:
-        run(mode, args.warmup, 0)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        run(mode, args.steps, args.warmup)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t
-        res[mode] = dict(seconds=dt, ms=dt * 1e3 / args.steps, value=W * H * SPP * args.steps / dt)
-        log(f"{mode}: {res[mode]['ms']:.3f} ms/frame, {res[mode]['value'] / 1e6:.1f} M path-samples/s")
-    # the same frames with three in flight (pt_render_frames): one frame's
-    # last, short bounces overlap the next frame's first ones
-    inflight = {}
-    tuned_inflight = {m: dict(tuned[m]) for m in modes}
-    if not args.fixed and not args.no_tune and not args.params:
-        for mode in modes:
-            t = time.perf_counter()
-            tuned_inflight[mode] = autotune.tune_frame(R, mode=mode, cache=None, log=log, in_flight=True, **kw)
-            log(f"autotune {mode}, three frames in flight: {tuned_inflight[mode]} ({time.perf_counter() - t:.1f} s)")
-    for mode in modes:
-        p = dict(tuned_inflight[mode])
-        R.render_frames(args.warmup, out=img, mode=mode, frame=0, **kw, **p)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        R.render_frames(args.steps, out=img, mode=mode, frame=args.warmup, **kw, **p)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t
-        inflight[mode] = dict(ms_per_step=dt * 1e3 / args.steps, value=W * H * SPP * args.steps / dt)
-        log(f"{mode}, three frames in flight: {inflight[mode]['ms_per_step']:.3f} ms/frame, "
-            f"{inflight[mode]['value'] / 1e6:.1f} M path-samples/s")
-
-    stage_ms, launches, items, nbytes, nodes, tris = {}, {}, {}, {}, {}, {}
-    rays = [0, 0]
-    roofline, state_floor, frame_stage_ms = None, None, {}
-    ext_rays_per_frame = sh_rays_per_frame = 0.0
-    # stage profile and work counts at the fixed launch parameters, the ones
-    # the committed rocprofv3 profiles were taken with (bench.py --fixed), so
-    # that the roofline's mean launch time is comparable with them
-    prof_params = dict(tuned["wave"]) if (args.params and "wave" in tuned) else dict(FIXED_PARAMS["wave"])
-
-    def run_prof(first, flags):
-        p = dict(prof_params)
-        p["flags"] = p.get("flags", 0) | flags
-        R.render(out=img, mode="wave", frame=first, **kw, **p)
-
-    if "wave" in modes:
-        # per-stage times with HIP events on the render stream, over the same
-        # number of frames, plus ray counts, work items and algorithmic bytes
-        for i in range(args.steps):
-            run_prof(args.warmup + i, ptmi.FLAG_PROFILE)
-            st = R.stats()
-            for k, v in st["stage_ms"].items():
-                stage_ms[k] = stage_ms.get(k, 0.0) + v
-                launches[k] = launches.get(k, 0) + st["launches"][k]
-            for k, v in st["items"].items():
-                items[k] = items.get(k, 0) + v
-                nbytes[k] = nbytes.get(k, 0.0) + st["bytes"][k]
-            rays[0] += st["extension_rays"]
-            rays[1] += st["shadow_rays"]
-        # the same frames again with the work-counting kernels (node visits and
-        # triangle tests; a separate, slower build, so not timed)
-        for i in range(args.steps):
-            run_prof(args.warmup + i, ptmi.FLAG_COUNT_WORK)
-            st = R.stats()
-            for k, v in st["node_visits"].items():
-                nodes[k] = nodes.get(k, 0) + v
-            for k, v in st["tri_tests"].items():
-                tris[k] = tris.get(k, 0) + v
-        frame_stage_ms = {k: v / args.steps for k, v in stage_ms.items()}
-        log("wavefront stage ms/frame: " + ", ".join(f"{k} {v:.3f}" for k, v in frame_stage_ms.items()))
-        ext_rays_per_frame = rays[0] / args.steps
-        sh_rays_per_frame = rays[1] / args.steps
-        # roofline of the stage kernel with the largest share of the frame.
-        # Traversal kernels (extend, shadow, tail) are bound by vector ALU issue:
-        # achieved = algorithmic flops per launch (FLOPS_PER_NODE per BVH node
-        # visit, FLOPS_PER_TRI per triangle test, counted on the device) over the
-        # mean launch time, against the fp32 vector peak.  The streaming stages
-        # use their algorithmic path-state bytes against the HBM peak.
-        dom = max(stage_ms, key=stage_ms.get)
-        lds = prof_params.get("stack_lds", 16)
-        kname = {"extend": f"ptmi::k_extend<{lds}, false>", "shade": "ptmi::k_shade",
-                 "shadow": f"ptmi::k_shadow<{lds}, false>", "tail": f"ptmi::k_shade_tail<{lds}, false>",
-                 "raygen": "ptmi::k_raygen", "accumulate": "ptmi::k_accumulate", "sort": "ptmi::k_sort_*"}[dom]
-        dom_avg_ms = stage_ms[dom] / launches[dom]
-        per_launch_bytes = nbytes.get(dom, 0.0) / launches[dom]
-        state_gbs = per_launch_bytes / (dom_avg_ms * 1e-3) / 1e9
-        common = {"kernel": kname, "traffic": measured_traffic(kname), "avg_launch_ms": dom_avg_ms,
-                  "launches_per_frame": launches[dom] / args.steps, "items_per_frame": items.get(dom, 0) / args.steps,
-                  "stage_share": stage_ms[dom] / sum(stage_ms.values()), "state_bytes_per_launch": per_launch_bytes,
-                  "state_gbs": state_gbs, "launch_params": prof_params}
-        if dom in ("extend", "shadow", "tail"):
-            flops = FLOPS_PER_NODE * nodes.get(dom, 0) + FLOPS_PER_TRI * tris.get(dom, 0)
-            per_launch_flops = flops / launches[dom]
-            achieved = per_launch_flops / (dom_avg_ms * 1e-3) / 1e12
-            roofline = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                        "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "flops_per_launch": per_launch_flops,
-                        # wave64 VALU instructions issued per CU cycle (1.0 = the non-packed issue limit)
-                        "valu_issue_per_cu_cycle": measured_traffic(kname, "valu_per_cu_cycle"),
-                        "l2_hit_rate": measured_traffic(kname, "l2_hit_rate"),
-                        "node_visits_per_frame": nodes.get(dom, 0) / args.steps,
-                        "tri_tests_per_frame": tris.get(dom, 0) / args.steps, **common}
+        if args.params:
+            given = json.loads(args.params)
+            p = dict(given.get(mode, FIXED_PARAMS[mode]))
+            tuned[mode] = {"frame_by_frame": p, "frames_in_flight": p}
+        elif args.fixed:
+            tuned[mode] = {"frame_by_frame": dict(FIXED_PARAMS[mode]), "frames_in_flight": dict(FIXED_PARAMS[mode])}
+        elif args.no_tune:
+            tuned[mode] = {"frame_by_frame": {}, "frames_in_flight": {}}
         else:
-            roofline = {"bound": "hbm", "achieved": state_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": state_gbs / HBM_PEAK_GBS, "bytes_per_launch": per_launch_bytes, **common}
-        state_bytes = sum(nbytes.values()) / args.steps
-        state_floor = {"bytes_per_frame": state_bytes,
-                       "frac_of_frame": (state_bytes / (res["wave"]["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS)
-                       if "wave" in res else None}
+            tuned[mode] = {}
+            for name, infl in [("frame_by_frame", False), ("frames_in_flight", True)]:
+                t = time.perf_counter()
+                tuned[mode][name] = autotune.tune_frame(R, mode=mode, cache=None, log=log, in_flight=infl, **kw)
+                log(f"autotune {mode} {name}: {tuned[mode][name]} ({time.perf_counter() - t:.1f} s)")
 
-    head = "wave" if "wave" in inflight else "mega"
+    sched = {}
+    if "wave_hybrid" in schedules:
+        sched["wave_hybrid"] = schedule_run(torch, R, img, tuned["wave"], args.steps, args.warmup, kw, "wave")
+    if "wave_pure" in schedules:
+        pure = {n: dict(p, **PURE) for n, p in tuned["wave"].items()}
+        sched["wave_pure"] = schedule_run(torch, R, img, pure, args.steps, args.warmup, kw, "wave")
+    if "mega" in modes:
+        sched["mega"] = schedule_run(torch, R, img, tuned["mega"], args.steps, args.warmup, kw, "mega")
+    for s, v in sched.items():
+        log(f"{s}: {v['frame_by_frame']['ms_per_step']:.3f} ms/frame, in flight "
+            f"{v['frames_in_flight']['ms_per_step']:.3f} ms/frame")
+
+    copy = copy_ceiling(torch)
+    copy_gbs = copy["value"]
+    prof = profiles.load(PROFILE)
+    out_roof = {}
+    frame_stage_ms = {}
+    wave_sum = {}
+    k = min(args.steps, 16)
+    if "wave" in modes:
+        # stage profile at the fixed launch parameters (those of the committed
+        # rocprofv3 profiles), frame by frame on the render stream
+        for name, params in [("hybrid", FIXED_PARAMS["wave"]), ("pure", dict(FIXED_PARAMS["wave"], **PURE))]:
+            if f"wave_{name}" not in schedules:
+                continue
+            acc = profiled_frames(R, img, ptmi, "wave", params, k, args.warmup, kw)
+            frame_stage_ms[name] = {s: v / k for s, v in acc["stage_ms"].items()}
+            log(f"wavefront ({name}) stage ms/frame: " +
+                ", ".join(f"{s} {v:.3f}" for s, v in frame_stage_ms[name].items()))
+            lds = params.get("stack_lds", 8)
+            kname = {"extend": f"ptmi::k_extend<{lds}, false>", "shadow": f"ptmi::k_shadow<{lds}, false>",
+                     "tail": f"ptmi::k_shade_tail<{lds}, false>", "shade": "ptmi::k_shade"}
+            for st in ["extend", "shadow", "shade", "tail"]:
+                if st not in acc["launches"]:
+                    continue
+                trav = st in ("extend", "shadow", "tail")
+                out_roof[f"{st}_{name}"] = roofline_entry(
+                    kname[st], acc["launches"][st], acc["stage_ms"][st], acc["bytes"].get(st, 0.0),
+                    acc["node_visits"].get(st, 0) if trav else None, acc["tri_tests"].get(st, 0) if trav else None,
+                    prof if name == "hybrid" else None, copy_gbs)
+            wave_sum[name] = {
+                "rays": {"extension": acc["extension_rays"] / k, "shadow": acc["shadow_rays"] / k},
+                "dominant": max(acc["stage_ms"], key=acc["stage_ms"].get),
+                "share": {s: v / sum(acc["stage_ms"].values()) for s, v in acc["stage_ms"].items()},
+                "items": {s: v / k for s, v in acc["items"].items()},
+                "nodes": {s: v / k for s, v in acc["node_visits"].items()},
+                "tris": {s: v / k for s, v in acc["tri_tests"].items()},
+                "state_bytes": sum(acc["bytes"].values()) / k}
+    if "mega" in modes:
+        acc = profiled_frames(R, img, ptmi, "mega", FIXED_PARAMS["mega"], k, args.warmup, kw)
+        waves = FIXED_PARAMS["mega"].get("mega_waves", 4)
+        out_roof["mega"] = roofline_entry(
+            f"ptmi::k_mega<{FIXED_PARAMS['mega']['stack_lds']}, false, {waves}>", acc["launches"]["mega"],
+            acc["stage_ms"]["mega"], acc["bytes"]["mega"], acc["node_visits"]["mega"], acc["tri_tests"]["mega"],
+            prof, copy_gbs)
+
+    out_adj = None
+    if not args.no_adjoint:
+        out_adj = adjoint_bench(ptmi, scene, torch, args, prof, copy_gbs, out_roof)
+
+    head = "wave_hybrid" if "wave_hybrid" in sched else ("wave_pure" if "wave_pure" in sched else "mega")
+    hv = sched[head]["frames_in_flight"]
+    roofline = None
+    hname = {"wave_hybrid": "hybrid", "wave_pure": "pure"}.get(head)
+    ws = wave_sum.get(hname)
+    rays = ws["rays"] if ws else None
+    if ws and f"extend_{hname}" in out_roof:
+        # the dominant kernel of the headline frame: the extension rays'
+        # traversal, against the HBM peak on its algorithmic state bytes
+        # (48 B per ray: read the ray, write the hit)
+        r = out_roof[f"extend_{hname}"]
+        roofline = {"bound": "hbm", "achieved": r["state"]["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": r["state"]["frac_hbm_peak"],
+                    "traffic": (r.get("measured") or {}).get("hbm_bytes_per_dispatch"),
+                    "kernel": r["kernel"], "avg_launch_ms": r["avg_launch_ms"],
+                    "launches_per_frame": r["launches"] / k, "bytes_per_launch": r["state"]["bytes_per_launch"],
+                    "frac_copy_ceiling": r["state"]["frac_copy_ceiling"], "alu": r.get("alu"),
+                    "measured": r.get("measured"), "stage_share": ws["share"].get("extend"),
+                    "dominant_stage": ws["dominant"],
+                    "launch_params": dict(FIXED_PARAMS["wave"], **(PURE if hname == "pure" else {}))}
     out = {
         "metric": "path samples/s wavefront vs megakernel @1080p, 1M tris; adjoint samples/s",
-        "value": inflight[head]["value"],
+        "value": hv["value"],
         "unit": "path-samples/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": inflight[head]["ms_per_step"],
+        "ms_per_step": hv["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -304,46 +382,78 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"procedural scene {nt} triangles (1000 icospheres + 1000 tessellated boxes, "
                                f"ground, 16 quad lights), {W}x{H}, {SPP} spp/frame, max depth {DEPTH}, "
-                               f"roulette from {RR}, light sampling on; {head} schedule, progressive frames with "
-                               f"three in flight (bit-identical to frame by frame)",
+                               f"roulette from {RR}, light sampling on; "
+                               + ({"wave_pure": "pure wavefront schedule (separate extend / shade / shadow "
+                                               "launches over compacted queues at every bounce)",
+                                  "mega": "megakernel"}.get(head) or "wavefront schedule with the hybrid tail (separate extend / shade / shadow "
+                                  "launches over compacted queues while they are long, the paths still live at "
+                                  "the tail bounce finished megakernel-style in one launch)"
+                                  ) +
+                               ", progressive frames with three in flight (bit-identical to frame by frame)",
                    "width": W, "height": H, "spp": SPP, "max_depth": DEPTH, "triangles": nt},
-        "schedules": {m: {"frames_in_flight": inflight[m], "frame_by_frame": {"value": res[m]["value"],
-                                                                                 "ms_per_step": res[m]["ms"]}}
-                      for m in modes},
-        "wave_over_mega": ({"frames_in_flight": inflight["wave"]["value"] / inflight["mega"]["value"],
-                            "frame_by_frame": res["wave"]["value"] / res["mega"]["value"]} if len(res) == 2 else None),
-        "rays_per_s": ((ext_rays_per_frame + sh_rays_per_frame) / (inflight["wave"]["ms_per_step"] * 1e-3))
-                      if "wave" in inflight else None,
-        "rays_per_frame": {"extension": ext_rays_per_frame, "shadow": sh_rays_per_frame},
+        "schedules": sched,
+        "wave_over_mega": ({s: {n: sched["mega"][n]["ms_per_step"] / sched[s][n]["ms_per_step"]
+                                for n in ("frame_by_frame", "frames_in_flight")}
+                            for s in ("wave_pure", "wave_hybrid") if s in sched} if "mega" in sched else None),
+        "rays_per_s": ((rays["extension"] + rays["shadow"]) / (hv["ms_per_step"] * 1e-3)) if rays else None,
+        "rays_per_frame": rays,
         "stage_ms_per_frame": frame_stage_ms,
-        "launch_params": {"frame_by_frame": tuned, "frames_in_flight": tuned_inflight},
         "roofline": roofline,
-        "state_traffic": state_floor,
-        "stage_items_per_frame": {k: v / args.steps for k, v in items.items()},
-        "node_visits_per_frame": {k: v / args.steps for k, v in nodes.items()},
-        "tri_tests_per_frame": {k: v / args.steps for k, v in tris.items()},
+        "rooflines": out_roof,
+        "state_traffic": ({"bytes_per_frame": ws["state_bytes"],
+                           "frac_hbm_peak_at_headline": ws["state_bytes"] / (hv["ms_per_step"] * 1e-3) / 1e9 /
+                           HBM_PEAK_GBS} if ws else None),
+        "wavefront_work_per_frame": {n: {"items": v["items"], "node_visits": v["nodes"], "tri_tests": v["tris"],
+                                         "rays": v["rays"], "stage_share": v["share"]} for n, v in wave_sum.items()},
+        "hbm_copy_ceiling": copy,
+        "profile": {"name": PROFILE, "current": prof is not None},
         "paper_context": "paper reports ~16% (1.138x by its table) wavefront over megakernel on an RTX 3060 Ti "
                          "with RT cores, A Beautiful Game scene",
     }
-
-    out["hbm_copy_ceiling"] = copy_ceiling(torch)
-    if not args.no_adjoint:
-        out["adjoint"] = adjoint_bench(ptmi, scenes, scene, torch, args)
-
+    if out_adj:
+        out["adjoint"] = out_adj
+    if not args.no_extra and "wave" in modes:
+        out["compaction"] = compaction_bench(torch, R, img, ptmi, kw, tuned["wave"]["frame_by_frame"])
+    if not args.no_extra:
+        del R
+        torch.cuda.empty_cache()
+        out["divergence"] = divergence_bench(args, torch, ptmi, scenes, frames=2, summary=True)
+        torch.cuda.empty_cache()
+        out["batch"] = batch_bench(args, torch, ptmi, scenes, None, runs=2, summary=True)
     if not args.no_cpu:
         log("oracle CPU baseline ...")
         out["cpu_baseline"] = cpu_baseline(scene, cam)
     print(json.dumps(out), flush=True)
 
 
-def batch_bench(args):
+def compaction_bench(torch, R, img, ptmi, kw, params, k=6):
+    """Pure wavefront with compaction (live paths packed into the next queue
+    after every bounce) against no compaction (every path slot dispatched
+    every bounce, finished ones skipped), at depth 8 and 16 (paper Sec. 3.1:
+    the gain grows with the maximum depth)."""
+    res = {}
+    base = dict(params, **PURE)
+    base.pop("flags", None)
+    for depth in (DEPTH, 16):
+        r = {}
+        for name, flags in [("compacted", 0), ("no_compaction", ptmi.FLAG_NO_COMPACT)]:
+            p = dict(base, flags=flags)
+            a = dict(kw, max_depth=depth)
+            time_frames(torch, R, img, 1, 0, False, mode="wave", **a, **p)
+            dt = time_frames(torch, R, img, k, 1, False, mode="wave", **a, **p)
+            r[name] = {"ms_per_frame": dt * 1e3 / k}
+        r["gain"] = r["no_compaction"]["ms_per_frame"] / r["compacted"]["ms_per_frame"]
+        res[f"depth{depth}"] = r
+        log(f"compaction depth {depth}: {r['compacted']['ms_per_frame']:.3f} ms vs "
+            f"{r['no_compaction']['ms_per_frame']:.3f} ms without ({r['gain']:.2f}x)")
+    return res
+
+
+def batch_bench(args, torch, ptmi, scenes, autotune, runs=None, summary=False):
     """64 jobs: per job a procedural scene of T triangles (T log-uniform in
     [1e4, 2e6]), a resolution from {256^2, 512^2, 1024^2, 1920x1080}, 1..8
     spp, depth 8, roulette from 3; all in one batched persistent wavefront."""
     import numpy as np
-    import torch
-
-    from paper_2605_27323_amd import autotune, ptmi, scenes
     t0 = time.perf_counter()
     specs = scenes.batch_jobs(seed=4, n_jobs=64)
     Rs, job_args = [], []
@@ -356,37 +466,42 @@ def batch_bench(args):
         job_args.append(dict(spp=sp["spp"], max_depth=DEPTH, rr_start=RR, nee=True, seed=0, job=j))
     total = sum(R.width * R.height * a["spp"] for R, a in zip(Rs, job_args))
     log(f"batch: {len(Rs)} jobs, {ntri} triangles, {total} path samples (setup {time.perf_counter() - t0:.1f} s)")
-    opts = {} if args.no_tune else autotune.tune_batch(Rs, job_args, cache=None, log=log)
+    if autotune is not None and not args.no_tune and not args.fixed:
+        opts = autotune.tune_batch(Rs, job_args, cache=None, log=log)
+    else:
+        opts = dict(BATCH_OPTS)
     log(f"batch options {opts}")
-    ws = None
     _, _, r = ptmi.render_batch(Rs, job_args, **opts)
     ws = r["workspace"]
-    runs = []
-    for _ in range(max(1, args.steps // 16)):
+    res = []
+    for _ in range(runs or max(1, args.steps // 16)):
         _, ms, r = ptmi.render_batch(Rs, job_args, workspace=ws, **opts)
-        runs.append((r["seconds"], ms))
-    sec = min(t for t, _ in runs)
-    ms = [m for t, m in runs if t == sec][0]
-    out = {"metric": "batched path samples/s (64 jobs)", "value": total / sec, "unit": "path-samples/s",
-           "n_gpus": 1, "steps": len(runs), "warmup": 1, "ms_per_step": sec * 1e3, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": f"64 jobs, {ntri} triangles in total, {total} path samples, depth {DEPTH}, "
-                                  f"roulette from {RR}, one batched persistent wavefront with a hipGraph loop",
-                      "triangles": ntri, "path_samples": total},
-           "job_latency_ms": {"p50": float(np.percentile(ms, 50)), "p99": float(np.percentile(ms, 99)),
-                              "max": float(np.max(ms))},
-           "iterations": r["iterations"], "graph_launches": r["launches"], "batch_options": opts}
-    print(json.dumps(out), flush=True)
+        res.append((r["seconds"], ms, r))
+    sec = min(t for t, _, _ in res)
+    ms, r = [(m, rr) for t, m, rr in res if t == sec][0]
+    lat = {"p50": float(np.percentile(ms, 50)), "p99": float(np.percentile(ms, 99)), "max": float(np.max(ms))}
+    log(f"batch: {sec * 1e3:.1f} ms, {total / sec / 1e6:.1f} M path-samples/s, latency {lat}")
+    body = {"value": total / sec, "unit": "path-samples/s", "ms": sec * 1e3, "job_latency_ms": lat,
+            "iterations": r["iterations"], "graph_launches": r["launches"], "batch_options": opts,
+            "runs": len(res), "triangles": ntri, "path_samples": total,
+            "workload": f"64 jobs, {ntri} triangles in total, {total} path samples, depth {DEPTH}, roulette from "
+                        f"{RR}, batched persistent wavefront with a hipGraph loop"}
+    if summary:
+        return body
+    return {"metric": "batched path samples/s (64 jobs)", "value": total / sec, "unit": "path-samples/s",
+            "n_gpus": 1, "steps": len(res), "warmup": 1, "ms_per_step": sec * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": body["workload"], "triangles": ntri, "path_samples": total},
+            "job_latency_ms": lat, "iterations": r["iterations"], "graph_launches": r["launches"],
+            "batch_options": opts}
 
 
-def divergence_bench(args):
+def divergence_bench(args, torch, ptmi, scenes, frames=None, summary=False):
     """~10M triangles, 64 material ids (Lambertian, conductor, rough
     dielectric, emissive), 1920x1080, 4 spp, depth 16, roulette from 3:
-    megakernel, wavefront, wavefront with the material sort, the ray sort,
-    and the wavefront and megakernel with three frames in flight."""
-    import torch
-
-    from paper_2605_27323_amd import ptmi, scenes
+    megakernel, wavefront (hybrid and pure), wavefront with the material
+    sort and with the ray sort, and the hybrid wavefront and the megakernel
+    with three frames in flight."""
     t0 = time.perf_counter()
     scene, cam = scenes.procedural(seed=3, n_objects=20000, width=W, height=H, material_mode="divergence")
     nt = scene["indices"].shape[0]
@@ -395,48 +510,49 @@ def divergence_bench(args):
     kw = dict(spp=4, max_depth=16, rr_start=3, nee=True, seed=0)
     img = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
     res = {}
-    k = max(2, args.steps // 8)
+    k = frames or max(2, args.steps // 8)
     given = json.loads(args.params) if args.params else {}
     wave = dict(given.get("wave", DIVERGENCE_PARAMS["wave"]))
     mega = dict(given.get("mega", DIVERGENCE_PARAMS["mega"]))
+
     def sorted_by(flag):
         return dict(wave, mode="wave", flags=wave.get("flags", 0) | flag,
                     sort_threshold=wave.get("sort_threshold", 1 << 16))
 
-    runs = [("mega", dict(mode="mega", **mega)), ("wave", dict(mode="wave", **wave)),
-            ("wave_material_sort", sorted_by(ptmi.FLAG_SORT_MATERIAL)),
-            ("wave_ray_sort", sorted_by(ptmi.FLAG_SORT_RAYS))]
+    runs = [("mega", dict(mode="mega", **mega)), ("wave_hybrid", dict(mode="wave", **wave)),
+            ("wave_pure", dict(dict(mode="wave", **wave), **PURE)),
+            ("wave_hybrid_material_sort", sorted_by(ptmi.FLAG_SORT_MATERIAL)),
+            ("wave_hybrid_ray_sort", sorted_by(ptmi.FLAG_SORT_RAYS))]
     for name, extra in runs:
-        R.render(out=img, frame=0, **kw, **extra)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for i in range(k):
-            R.render(out=img, frame=1 + i, **kw, **extra)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t) / k
+        time_frames(torch, R, img, 1, 0, False, **kw, **extra)
+        dt = time_frames(torch, R, img, k, 1, False, **kw, **extra) / k
         res[name] = {"ms_per_frame": dt * 1e3, "path_samples_per_s": W * H * 4 / dt}
-        log(f"{name}: {dt * 1e3:.2f} ms/frame")
-    for name, extra in [("mega_in_flight", dict(mode="mega", **mega)), ("wave_in_flight", dict(mode="wave", **wave))]:
-        R.render_frames(2, out=img, frame=0, **kw, **extra)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        R.render_frames(k, out=img, frame=2, **kw, **extra)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t) / k
+        log(f"divergence {name}: {dt * 1e3:.2f} ms/frame")
+    for name, extra in [("mega_in_flight", dict(mode="mega", **mega)),
+                        ("wave_hybrid_in_flight", dict(mode="wave", **wave))]:
+        time_frames(torch, R, img, 2, 0, True, **kw, **extra)
+        dt = time_frames(torch, R, img, max(k, 3), 2, True, **kw, **extra) / max(k, 3)
         res[name] = {"ms_per_frame": dt * 1e3, "path_samples_per_s": W * H * 4 / dt}
-        log(f"{name}: {dt * 1e3:.2f} ms/frame")
+        log(f"divergence {name}: {dt * 1e3:.2f} ms/frame")
     best = max((r for r in res if r.startswith("wave")), key=lambda r: res[r]["path_samples_per_s"])
-    out = {"metric": "path samples/s, divergence workload", "value": res[best]["path_samples_per_s"],
-           "unit": "path-samples/s", "n_gpus": 1, "steps": k, "warmup": 1,
-           "ms_per_step": res[best]["ms_per_frame"], "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": f"procedural {nt} triangles, 64 material ids, {W}x{H}, 4 spp, depth 16, "
-                                  f"roulette from 3; best wavefront schedule: {best}"}, "schedules": res}
-    print(json.dumps(out), flush=True)
+    workload = f"procedural {nt} triangles, 64 material ids, {W}x{H}, 4 spp, depth 16, roulette from 3"
+    if summary:
+        return {"workload": workload, "frames_per_run": k, "schedules": res, "best_wavefront": best,
+                "wave_over_mega_frame_by_frame": res["mega"]["ms_per_frame"] / res["wave_hybrid"]["ms_per_frame"],
+                "launch_params": {"wave": wave, "mega": mega}}
+    return {"metric": "path samples/s, divergence workload", "value": res[best]["path_samples_per_s"],
+            "unit": "path-samples/s", "n_gpus": 1, "steps": k, "warmup": 1,
+            "ms_per_step": res[best]["ms_per_frame"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"{workload}; best wavefront schedule: {best}"}, "schedules": res}
 
 
-def adjoint_bench(ptmi, scenes, scene, torch, args):
-    """Backward (path replay) of the 512x512, 8 spp, depth 6 frame."""
+def adjoint_bench(ptmi, scene, torch, args, prof, copy_gbs, roof):
+    """Backward (path replay) of the 512x512, 8 spp, depth 6 frame: adjoint
+    samples/s, and the rooflines of its two kernels (replay A keeps each
+    path's radiance, replay B adds the gradients).  Both replays trace the
+    rays of the forward megakernel frame with the same arguments, so their
+    node visits and triangle tests are those of that frame."""
     cam = dict(eye=(0.0, 50.0, -130.0), target=(0.0, 40.0, 0.0), up=(0.0, 1.0, 0.0), vfov_deg=50.0,
                width=512, height=512)
     try:
@@ -455,7 +571,28 @@ def adjoint_bench(ptmi, scenes, scene, torch, args):
         dt = time.perf_counter() - t
         n = 512 * 512 * 8 * k
         log(f"adjoint: {dt * 1e3 / k:.3f} ms per backward, {n / dt / 1e6:.1f} M samples/s")
+        # per-kernel event times
+        ms = {"adjoint": 0.0, "adjoint_radiance": 0.0}
+        by = {"adjoint": 0.0, "adjoint_radiance": 0.0}
+        for i in range(k):
+            R.backward(d_img, ga, ge, frame=i, flags=ptmi.FLAG_PROFILE, **kw)
+            st = R.stats()
+            for s in ms:
+                ms[s] += st["stage_ms"][s]
+                by[s] += st["bytes"][s]
+        nodes = tris = 0
+        img = torch.empty((512, 512, 3), dtype=torch.float32, device="cuda")
+        for i in range(k):
+            R.render(out=img, mode="mega", frame=i, flags=ptmi.FLAG_COUNT_WORK, **kw)
+            st = R.stats()
+            nodes += st["node_visits"]["mega"]
+            tris += st["tri_tests"]["mega"]
+        roof["adjoint_radiance"] = roofline_entry("ptmi::k_adjoint_radiance<8>", k, ms["adjoint_radiance"],
+                                                  by["adjoint_radiance"], nodes, tris, prof, copy_gbs)
+        roof["adjoint"] = roofline_entry("ptmi::k_adjoint<8>", k, ms["adjoint"], by["adjoint"], nodes, tris, prof,
+                                         copy_gbs)
         return {"value": n / dt, "unit": "adjoint samples/s", "ms_per_backward": dt * 1e3 / k,
+                "ms_per_kernel": {s: v / k for s, v in ms.items()},
                 "config": "same scene, 512x512, 8 spp, max depth 6, roulette off"}
     except ptmi.PtError as e:
         log(f"adjoint unavailable: {e}")

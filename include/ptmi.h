@@ -279,7 +279,8 @@ pt_status pt_render_backward(pt_ctx* ctx, const pt_render_args* args, const floa
 
 /* Statistics of the last frame rendered (synchronises the stream).
  * Stages (index k): 0 raygen, 1 extend, 2 shade, 3 shadow, 4 accumulate,
- * 5 megakernel, 6 sort, 7 adjoint, 8 hybrid tail.
+ * 5 megakernel, 6 sort, 7 adjoint replay B (gradients), 8 hybrid tail,
+ * 9 adjoint replay A (path radiance).
  *   stage_ms[k], launches[k]: HIP-event time and launch count per stage,
  *     filled only when the frame ran with PT_FLAG_PROFILE (else 0).
  *   stage_items[k]: work items the stage's launches processed (paths for
@@ -297,7 +298,7 @@ pt_status pt_render_backward(pt_ctx* ctx, const pt_render_args* args, const floa
  *   and hybrid tail, or megakernel; for the adjoint the rays of the paths,
  *   which replay A and replay B each trace once).
  * PT_EOVERFLOW if a traversal stack overflowed during the frame. */
-#define PT_NSTAGES 9
+#define PT_NSTAGES 10
 typedef struct {
     double stage_ms[PT_NSTAGES];
     int64_t launches[PT_NSTAGES];

@@ -189,15 +189,26 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     if (st.overflow) atomicOr(&stats[2], 1u);
 }
 
-hipError_t launch_adjoint(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const CamView& cam,
-                          const PathParams& pp, const float* d_img, float4* Lpath, unsigned long long* cursor,
-                          float* g_alb, float* g_emi, uint2* ovf, int gcap, uint32_t* stats) {
+hipError_t launch_adjoint_radiance(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
+                                   const CamView& cam, const PathParams& pp, float4* Lpath,
+                                   unsigned long long* cursor, uint2* ovf, int gcap, uint32_t* stats) {
     size_t sm = trav_stack_lds_bytes(lds, (int)block.x);
 #define X(N)                                                                                                  \
     if (lds == N) {                                                                                           \
         hipLaunchKernelGGL(k_adjoint_radiance<N>, grid, block, sm, s, sc, cam, pp, Lpath, cursor, ovf, gcap, stats); \
-        hipError_t e = hipGetLastError();                                                                     \
-        if (e != hipSuccess) return e;                                                                        \
+        return hipGetLastError();                                                                             \
+    }
+    X(8) X(16) X(24) X(32)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_adjoint(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const CamView& cam,
+                          const PathParams& pp, const float* d_img, const float4* Lpath, unsigned long long* cursor,
+                          float* g_alb, float* g_emi, uint2* ovf, int gcap, uint32_t* stats) {
+    size_t sm = trav_stack_lds_bytes(lds, (int)block.x);
+#define X(N)                                                                                                  \
+    if (lds == N) {                                                                                           \
         hipLaunchKernelGGL(k_adjoint<N>, grid, block, sm, s, sc, cam, pp, d_img, Lpath, cursor, g_alb, g_emi, ovf, \
                            gcap, stats);                                                                      \
         return hipGetLastError();                                                                             \

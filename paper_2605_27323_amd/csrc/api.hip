@@ -709,11 +709,16 @@ pt_status pt_render_backward(pt_ctx* c, const pt_render_args* a, const float* d_
     unsigned long long* cursor = reinterpret_cast<unsigned long long*>(base + w.adj);
     float4* Lpath = reinterpret_cast<float4*>(base + w.adj + kAlign);
     PT_HIP(launch_init_counts(s, reinterpret_cast<uint32_t*>(cursor), 4, 0u), "init path cursors");
+    PT_HIP(timed(c, prof, 9, s, [&] {
+               return launch_adjoint_radiance(L.lds, dim3(L.grid), dim3(L.block), s, c->view, c->cam, pp, Lpath, cursor,
+                                              ovf, L.gcap, counts);
+           }),
+           "adjoint replay A");
     PT_HIP(timed(c, prof, 7, s, [&] {
                return launch_adjoint(L.lds, dim3(L.grid), dim3(L.block), s, c->view, c->cam, pp, d_image, Lpath, cursor,
                                      d_albedo, d_emission, ovf, L.gcap, counts);
            }),
-           "adjoint");
+           "adjoint replay B");
     remember_frame(c, a, counts, w.ncounts, 2, false);
     c->last_trav = trav;
     return PT_OK;
@@ -750,9 +755,13 @@ pt_status pt_frame_stats_get(pt_ctx* c, pt_frame_stats* out) {
         out->tri_tests[k] = (int64_t)tv[1];
         // path state lives in registers: the megakernel writes the image
         // (and updates the running average); the adjoint writes each path's
-        // radiance in replay A and reads it and its pixel's image adjoint in
-        // replay B (16 W + 16 R + 12 R per path)
-        out->stage_bytes[k] = c->last_kind == 0 ? (double)npix * img_bytes : 44.0 * (double)npaths;
+        // radiance in replay A (16 B) and reads it and its pixel's image
+        // adjoint in replay B (16 + 12 B)
+        out->stage_bytes[k] = c->last_kind == 0 ? (double)npix * img_bytes : 28.0 * (double)npaths;
+        if (c->last_kind == 2) {
+            out->stage_items[9] = (int64_t)npaths;
+            out->stage_bytes[9] = 16.0 * (double)npaths;
+        }
         if (h[2]) return fail(PT_EOVERFLOW, "traversal stack overflow");
         return PT_OK;
     }

@@ -76,10 +76,13 @@ hipError_t launch_sort(dim3 grid, dim3 block, hipStream_t s, const SceneView& sc
                        uint32_t threshold, int key_kind);
 hipError_t launch_shadow(int lds, bool count, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
                          const WaveBufs& wb, int b, uint2* ovf, int gcap);
-// the adjoint: replay A of every path into Lpath (one float4 per path),
-// then replay B; cursor: two u64 path cursors, zero on entry
+// the adjoint: replay A of every path into Lpath (one float4 per path;
+// cursor[0], zero on entry), then replay B (cursor[1], zero on entry)
+hipError_t launch_adjoint_radiance(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
+                                   const CamView& cam, const PathParams& pp, float4* Lpath,
+                                   unsigned long long* cursor, uint2* ovf, int gcap, uint32_t* stats);
 hipError_t launch_adjoint(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const CamView& cam,
-                          const PathParams& pp, const float* d_img, float4* Lpath, unsigned long long* cursor,
+                          const PathParams& pp, const float* d_img, const float4* Lpath, unsigned long long* cursor,
                           float* g_alb, float* g_emi, uint2* ovf, int gcap, uint32_t* stats);
 hipError_t launch_accumulate(dim3 grid, dim3 block, hipStream_t s, const CamView& cam, const PathParams& pp,
                              const float4* L, float* img, float* acc);

@@ -19,7 +19,8 @@ PT_OK, PT_EINVAL, PT_ENOMEM, PT_EHIP, PT_ESTATE, PT_EOVERFLOW, PT_EUNSUPPORTED =
 MODE_MEGA, MODE_WAVE = 0, 1
 FLAG_PROFILE, FLAG_NO_COMPACT, FLAG_SORT_MATERIAL, FLAG_COUNT_WORK, FLAG_SORT_RAYS = 1, 2, 4, 8, 16
 SAMPLER_PHILOX, SAMPLER_HALTON = 0, 1
-STAGES = ["raygen", "extend", "shade", "shadow", "accumulate", "mega", "sort", "adjoint", "tail"]
+STAGES = ["raygen", "extend", "shade", "shadow", "accumulate", "mega", "sort", "adjoint", "tail",
+          "adjoint_radiance"]
 
 
 class PtError(RuntimeError):
@@ -64,7 +65,7 @@ class RenderArgs(C.Structure):
                 ("mega_waves", C.c_int32)]
 
 
-NSTAGES = 9
+NSTAGES = 10
 
 
 class FrameStats(C.Structure):

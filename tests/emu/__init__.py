@@ -16,7 +16,7 @@ def build():
     from paper_2605_27323_amd import build as B
     csrc = os.path.join(ROOT, "paper_2605_27323_amd", "csrc")
     srcs = [os.path.join(HERE, "emu.hip"), os.path.join(csrc, "kernels.hip"), os.path.join(csrc, "bvh_build.cpp")]
-    for extra in ("adjoint.hip", "batch.hip"):
+    for extra in ("adjoint.hip", "batch.hip", "noalloc.hip"):
         p = os.path.join(csrc, extra)
         if os.path.exists(p):
             srcs.append(p)
@@ -30,6 +30,8 @@ def _stale():
     if not os.path.exists(LIB):
         return True
     t = os.path.getmtime(LIB)
+    if os.path.getmtime(os.path.abspath(__file__)) > t:
+        return True
     dirs = [HERE, os.path.join(ROOT, "paper_2605_27323_amd", "csrc"), os.path.join(ROOT, "include")]
     for d in dirs:
         for f in os.listdir(d):
