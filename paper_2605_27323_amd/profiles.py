@@ -194,6 +194,8 @@ def markdown(p):
           f"{p['copy_kib']:.0f} KiB (`__amd_rocclr_copyBuffer`): FETCH_SIZE reads {_f(p['copy_fetch_kib'], '{:.1f}')}"
           f" KiB (scale {_f(p['fetch_scale'], '{:.4f}')}), WRITE_SIZE {_f(p['copy_write_kib'], '{:.1f}')} KiB "
           f"(scale {_f(p['write_scale'], '{:.4f}')}).", "",
+          "VGPR and SGPR are rocprofv3's VGPR_Count and SGPR_Count of the dispatch (the VGPR count is reported in "
+          "units of two registers on this device: the megakernel at four waves per SIMD holds 128 VGPRs and shows 64). "
           "Waves/SIMD = 4 x SQ_WAVE_CYCLES / (GRBM_GUI_ACTIVE / 8 XCDs x 1024 SIMDs): mean resident waves per SIMD "
           "over the dispatch. VALU/CU-cycle = SQ_INSTS_VALU / (GRBM_GUI_ACTIVE / 8 x 256 CUs): wave64 VALU "
           "instructions issued per CU and cycle (1.0 = the issue limit without packed FP32). L2 hit = "
