@@ -63,8 +63,11 @@ enum {
     PT_FLAG_SORT_MATERIAL = 4, /* wavefront: counting-sort each shade queue by material type */
     PT_FLAG_COUNT_WORK = 8,    /* traversal kernels count BVH node visits and triangle tests
                                   (pt_frame_stats); a separate kernel build, slower */
-    PT_FLAG_SORT_RAYS = 16     /* wavefront: counting-sort each extend queue by ray direction octant and
+    PT_FLAG_SORT_RAYS = 16,    /* wavefront: counting-sort each extend queue by ray direction octant and
                                   origin side of the scene centre (coherent waves) */
+    PT_FLAG_XCD_LOCAL = 32     /* each of the eight XCDs (own L2 each) takes one contiguous part of the
+                                  extend / shadow queues, and the megakernel's waves on an XCD take their
+                                  pixels from one band of rows first; same image bit for bit */
 };
 
 typedef struct pt_ctx pt_ctx;

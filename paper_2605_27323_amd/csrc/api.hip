@@ -134,7 +134,8 @@ WsLayout layout(const pt_ctx* c, const pt_render_args* a, const Launch& L, bool 
     const size_t npaths = (size_t)c->cam.W * c->cam.H * a->spp;
     // [0, D+1] live paths per bounce, [D+2, 2D+2] shadow rays per bounce,
     // [2D+3, 2D+4] rays traced by the hybrid tail, [2D+5] overflow flag
-    w.ncounts = 2 * a->max_depth + 6;
+    // (the megakernel's eight band cursors, u64, take words 8 .. 23)
+    w.ncounts = std::max(2 * a->max_depth + 6, 24);
     size_t off = 0;
     w.counts = off;
     off = align_up(off + sizeof(uint32_t) * w.ncounts);
@@ -166,7 +167,8 @@ pt_status check_args(const pt_ctx* c, const pt_render_args* a) {
     if (c->device < 0) return fail(PT_ESTATE, "host-only context cannot render");
     if (!c->bound) return fail(PT_ESTATE, "scene not bound (pt_bind_scene)");
     if (!c->cam_set) return fail(PT_ESTATE, "camera not set (pt_set_camera)");
-    if (a->flags & ~(PT_FLAG_PROFILE | PT_FLAG_NO_COMPACT | PT_FLAG_SORT_MATERIAL | PT_FLAG_COUNT_WORK | PT_FLAG_SORT_RAYS))
+    if (a->flags & ~(PT_FLAG_PROFILE | PT_FLAG_NO_COMPACT | PT_FLAG_SORT_MATERIAL | PT_FLAG_COUNT_WORK | PT_FLAG_SORT_RAYS |
+                     PT_FLAG_XCD_LOCAL))
         return fail(PT_EINVAL, "unknown flag");
     if (a->spp < 1 || a->spp > 65536) return fail(PT_EINVAL, "spp must be in [1, 65536]");
     if (a->max_depth < 0 || a->max_depth > 1000) return fail(PT_EINVAL, "max_depth must be in [0, 1000]");
@@ -239,13 +241,14 @@ pt_status enqueue_stages(pt_ctx* c, const pt_render_args* a, const Launch& L, co
     PathParams pp{a->spp, a->max_depth, a->nee ? 1 : 0, a->rr_start, a->seed, a->frame, a->job, a->sampler};
     dim3 grid(L.grid), block(L.block);
     const bool count = (a->flags & PT_FLAG_COUNT_WORK) != 0;
+    const int xcd = (a->flags & PT_FLAG_XCD_LOCAL) ? 1 : 0;
     PT_HIP(launch_init_counts(s, reinterpret_cast<uint32_t*>(trav), kTravWords, 0u), "init work counters");
     const uint32_t npaths = (uint32_t)c->cam.W * c->cam.H * a->spp;
     if (a->mode == PT_MODE_MEGA) {
         PT_HIP(launch_init_counts(s, counts, w.ncounts, 0u), "init counters");
         // counters: [0] extension rays, [1] shadow rays, [2] overflow flag, [4..5] the
         // megakernel's 64-bit pixel cursor
-        PT_HIP(timed(c, prof, 5, s, [&] { return launch_mega(L.lds, count, a->mega_waves == 5 ? 5 : 4, grid, block, s, c->view, c->cam, pp, img, acc, ovf, L.gcap, counts, trav); }), "megakernel");
+        PT_HIP(timed(c, prof, 5, s, [&] { return launch_mega(L.lds, count, a->mega_waves == 5 ? 5 : 4, grid, block, s, c->view, c->cam, pp, img, acc, ovf, L.gcap, counts, trav, xcd); }), "megakernel");
     } else {
         WaveBufs wb{};
         for (int q = 0; q < 2; ++q) {
@@ -276,7 +279,7 @@ pt_status enqueue_stages(pt_ctx* c, const pt_render_args* a, const Launch& L, co
         for (int b = 0; b <= a->max_depth; ++b) {
             if (rsort)
                 PT_HIP(timed(c, prof, 6, s, [&] { return launch_sort(grid, block, s, c->view, wb, b, a->sort_threshold, 1); }), "ray sort");
-            PT_HIP(timed(c, prof, 1, s, [&] { return launch_extend(L.lds, count, grid, block, s, c->view, wb, b, ovf, L.gcap, rsort); }), "extend");
+            PT_HIP(timed(c, prof, 1, s, [&] { return launch_extend(L.lds, count, grid, block, s, c->view, wb, b, ovf, L.gcap, rsort, xcd); }), "extend");
             if (sort)
                 PT_HIP(timed(c, prof, 6, s, [&] { return launch_sort(grid, block, s, c->view, wb, b, a->sort_threshold, 0); }), "sort");
             // at bounce tail_bounce the hybrid tail takes whatever is left
@@ -292,7 +295,7 @@ pt_status enqueue_stages(pt_ctx* c, const pt_render_args* a, const Launch& L, co
                        "hybrid tail");
             if (last) break;
             if (b < a->max_depth && a->nee)
-                PT_HIP(timed(c, prof, 3, s, [&] { return launch_shadow(L.lds, count, grid, block, s, c->view, wb, b, ovf, L.gcap); }), "shadow");
+                PT_HIP(timed(c, prof, 3, s, [&] { return launch_shadow(L.lds, count, grid, block, s, c->view, wb, b, ovf, L.gcap, xcd); }), "shadow");
         }
         *Lbuf = wb.L;
     }

@@ -52,13 +52,13 @@ constexpr uint32_t kRefill = 16;
 // waves: the megakernel's occupancy, 4 or 5 waves per SIMD
 hipError_t launch_mega(int lds, bool count, int waves, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
                        const CamView& cam, const PathParams& pp, float* img, float* acc, uint2* ovf, int gcap,
-                       uint32_t* stats, unsigned long long* trav);
+                       uint32_t* stats, unsigned long long* trav, int xcd_local);
 hipError_t launch_init_counts(hipStream_t s, uint32_t* counts, int n, uint32_t first);
 hipError_t launch_raygen(dim3 grid, dim3 block, hipStream_t s, const CamView& cam, const PathParams& pp,
                          const WaveBufs& wb);
 // sorted: a ray sort of queue b precedes (its permutation orders the work)
 hipError_t launch_extend(int lds, bool count, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
-                         const WaveBufs& wb, int b, uint2* ovf, int gcap, int sorted);
+                         const WaveBufs& wb, int b, uint2* ovf, int gcap, int sorted, int xcd_local);
 // tail > 0 (compacted queues only): a queue with fewer than `tail` paths is
 // skipped here and finished in place by launch_tail
 hipError_t launch_shade(dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const PathParams& pp,
@@ -75,7 +75,7 @@ hipError_t launch_tail(int lds, bool count, dim3 grid, dim3 block, hipStream_t s
 hipError_t launch_sort(dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const WaveBufs& wb, int b,
                        uint32_t threshold, int key_kind);
 hipError_t launch_shadow(int lds, bool count, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
-                         const WaveBufs& wb, int b, uint2* ovf, int gcap);
+                         const WaveBufs& wb, int b, uint2* ovf, int gcap, int xcd_local);
 // the adjoint: replay A of every path into Lpath (one float4 per path;
 // cursor[0], zero on entry), then replay B (cursor[1], zero on entry)
 hipError_t launch_adjoint_radiance(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,

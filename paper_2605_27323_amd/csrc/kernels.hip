@@ -49,7 +49,8 @@ constexpr uint32_t kMegaChunk = 64u;
 template <int LDS, bool COUNT, int WAVES>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) k_mega(SceneView sc, CamView cam, PathParams pp, float* __restrict__ img,
                                               float* __restrict__ acc, uint2* __restrict__ ovf, int gcap,
-                                              uint32_t* __restrict__ stats, unsigned long long* __restrict__ trav) {
+                                              uint32_t* __restrict__ stats, unsigned long long* __restrict__ trav,
+                                              int xcd_local) {
     extern __shared__ __align__(8) uint32_t smem[];
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -65,9 +66,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES)
     // kMegaChunk pixels from a global cursor (one atomic per chunk), so
     // lanes and waves stay busy until the frame is drained.  A pixel's
     // samples still run in order on one lane, so its sum is the same.
+    // With xcd_local the frame's pixels are split into eight bands of rows,
+    // one cursor each (stats + 8 ...); the waves of XCD x (workgroups b with
+    // b mod 8 = x) take chunks from band x first, so neighbouring pixels
+    // share that XCD's L2, and then help with the other bands in turn.
     unsigned long long* cursor = reinterpret_cast<unsigned long long*>(stats + 4);
+    const uint32_t nbands = xcd_local ? 8u : 1u;
+    const uint32_t band_px = (npix + nbands - 1u) / nbands;
+    uint32_t band = xcd_local ? (blockIdx.x & 7u) : 0u, bands_left = nbands;  // wave-uniform
     uint32_t next = 0, end = 0;  // this wave's chunk (wave-uniform)
-    bool drained = false;        // the cursor has passed the last pixel (wave-uniform)
+    bool drained = false;        // every band's cursor has passed its last pixel (wave-uniform)
     bool live = false;
     uint32_t pix = 0, s = 0;
     f3 sum = mk3(0.f, 0.f, 0.f);
@@ -76,15 +84,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES)
     while (true) {
         const uint64_t idle = __ballot(!live);
         if (idle != 0ull && !drained) {
-            if (next >= end) {
+            while (next >= end && !drained) {
+                const uint32_t lo = band * band_px, hi = min(lo + band_px, npix);
                 unsigned long long base = 0ull;
-                if (lane_id() == 0) base = atomicAdd(cursor, (unsigned long long)kMegaChunk);
-                base = wave_broadcast_u64(base);
-                if (base >= (unsigned long long)npix) {
-                    drained = true;
+                if (lane_id() == 0) base = atomicAdd(cursor + (xcd_local ? 2u + band : 0u), (unsigned long long)kMegaChunk);
+                base = wave_broadcast_u64(base) + lo;
+                if (base >= (unsigned long long)hi) {
+                    // this band is done: the next one, until all are
+                    if (--bands_left == 0u) drained = true;
+                    band = band + 1u == nbands ? 0u : band + 1u;
                 } else {
                     next = (uint32_t)base;
-                    end = (uint32_t)min(base + (unsigned long long)kMegaChunk, (unsigned long long)npix);
+                    end = (uint32_t)min(base + (unsigned long long)kMegaChunk, (unsigned long long)hi);
                 }
             }
             if (!drained) {
@@ -211,7 +222,7 @@ __global__ void __launch_bounds__(256) k_raygen(CamView cam, PathParams pp, Wave
 
 template <int LDS, bool COUNT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k_extend(SceneView sc, WaveBufs wb, int b, uint2* __restrict__ ovf, int gcap,
-                                                uint32_t refill, int sorted) {
+                                                uint32_t refill, int sorted, int xcd_local) {
     extern __shared__ __align__(8) uint32_t smem[];
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -220,7 +231,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
     // with a ray sort this bounce, position i of the queue is slot perm[i]
     const uint32_t* perm = (sorted && wb.hist[2 * kSortBins]) ? wb.perm : nullptr;
     uint32_t next, end;
-    wave_chunk(wb.counts[b], next, end);
+    wave_chunk(wb.counts[b], next, end, xcd_local);
     bool live = false;
     uint32_t item = 0, ref = 0;
     Ray ray;
@@ -308,13 +319,13 @@ __global__ void __launch_bounds__(256) k_shade(SceneView sc, PathParams pp, Wave
 
 template <int LDS, bool COUNT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k_shadow(SceneView sc, WaveBufs wb, int b, uint2* __restrict__ ovf, int gcap,
-                                                uint32_t refill) {
+                                                uint32_t refill, int xcd_local) {
     extern __shared__ __align__(8) uint32_t smem[];
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
     TravStack<LDS, COUNT> st = make_stack<LDS, COUNT>(smem, ovf, gcap, gtid, nlanes);
     uint32_t next, end;
-    wave_chunk(wb.counts[wb.sh_base + b], next, end);
+    wave_chunk(wb.counts[wb.sh_base + b], next, end, xcd_local);
     bool live = false;
     uint32_t item = 0, ref = 0;
     Ray ray;
@@ -450,13 +461,15 @@ static size_t stack_lds_bytes(int lds, int block) { return trav_stack_lds_bytes(
 
 hipError_t launch_mega(int lds, bool count, int waves, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
                        const CamView& cam, const PathParams& pp, float* img, float* acc, uint2* ovf, int gcap,
-                       uint32_t* stats, unsigned long long* trav) {
+                       uint32_t* stats, unsigned long long* trav, int xcd_local) {
     size_t sm = stack_lds_bytes(lds, block.x);
 #define L(N, C)                                                                                                      \
     if (waves == 5)                                                                                                  \
-        hipLaunchKernelGGL((k_mega<N, C, 5>), grid, block, sm, s, sc, cam, pp, img, acc, ovf, gcap, stats, trav);    \
+        hipLaunchKernelGGL((k_mega<N, C, 5>), grid, block, sm, s, sc, cam, pp, img, acc, ovf, gcap, stats, trav,     \
+                           xcd_local);                                                                               \
     else                                                                                                             \
-        hipLaunchKernelGGL((k_mega<N, C, 4>), grid, block, sm, s, sc, cam, pp, img, acc, ovf, gcap, stats, trav);
+        hipLaunchKernelGGL((k_mega<N, C, 4>), grid, block, sm, s, sc, cam, pp, img, acc, ovf, gcap, stats, trav,     \
+                           xcd_local);
 #define X(N) PT_DISPATCH(N, L)
     PT_STACK_CASES(X)
 #undef X
@@ -476,9 +489,9 @@ hipError_t launch_raygen(dim3 grid, dim3 block, hipStream_t s, const CamView& ca
 }
 
 hipError_t launch_extend(int lds, bool count, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
-                         const WaveBufs& wb, int b, uint2* ovf, int gcap, int sorted) {
+                         const WaveBufs& wb, int b, uint2* ovf, int gcap, int sorted, int xcd_local) {
     size_t sm = stack_lds_bytes(lds, block.x);
-#define L(N, C) hipLaunchKernelGGL((k_extend<N, C>), grid, block, sm, s, sc, wb, b, ovf, gcap, kRefill, sorted);
+#define L(N, C) hipLaunchKernelGGL((k_extend<N, C>), grid, block, sm, s, sc, wb, b, ovf, gcap, kRefill, sorted, xcd_local);
 #define X(N) PT_DISPATCH(N, L)
     PT_STACK_CASES(X)
 #undef X
@@ -518,9 +531,9 @@ hipError_t launch_sort(dim3 grid, dim3 block, hipStream_t s, const SceneView& sc
 }
 
 hipError_t launch_shadow(int lds, bool count, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
-                         const WaveBufs& wb, int b, uint2* ovf, int gcap) {
+                         const WaveBufs& wb, int b, uint2* ovf, int gcap, int xcd_local) {
     size_t sm = stack_lds_bytes(lds, block.x);
-#define L(N, C) hipLaunchKernelGGL((k_shadow<N, C>), grid, block, sm, s, sc, wb, b, ovf, gcap, kRefill);
+#define L(N, C) hipLaunchKernelGGL((k_shadow<N, C>), grid, block, sm, s, sc, wb, b, ovf, gcap, kRefill, xcd_local);
 #define X(N) PT_DISPATCH(N, L)
     PT_STACK_CASES(X)
 #undef X

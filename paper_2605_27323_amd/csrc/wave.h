@@ -40,11 +40,23 @@ __device__ __forceinline__ unsigned long long wave_broadcast_u64(unsigned long l
     return ((unsigned long long)hi << 32) | lo;
 }
 
+// Workgroup order in which consecutive parts of a queue are handed out.
+// The dispatcher places workgroup b on XCD b mod 8 (each XCD has its own
+// L2); with xcd_local the order b' = (b mod 8) * (G / 8) + b / 8 gives every
+// XCD one contiguous eighth of the queue, so that neighbouring rays (close
+// pixels, similar directions) share an L2 instead of being spread over all
+// eight.  Grids that are not a multiple of 8 keep launch order.
+__device__ __forceinline__ uint32_t block_order(int xcd_local) {
+    const uint32_t b = blockIdx.x;
+    if (!xcd_local || (gridDim.x & 7u) != 0u) return b;
+    return (b & 7u) * (gridDim.x >> 3) + (b >> 3);
+}
+
 // The contiguous chunk [next, end) of a queue of `count` entries owned by
-// this wave in a persistent kernel (waves of the grid in launch order).
-__device__ __forceinline__ void wave_chunk(uint32_t count, uint32_t& next, uint32_t& end) {
+// this wave in a persistent kernel (waves in block_order).
+__device__ __forceinline__ void wave_chunk(uint32_t count, uint32_t& next, uint32_t& end, int xcd_local = 0) {
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t wave = (block_order(xcd_local) * blockDim.x + threadIdx.x) >> 6;
     const uint32_t chunk = (uint32_t)(((uint64_t)count + nwaves - 1) / nwaves);
     next = (uint32_t)min((uint64_t)wave * chunk, (uint64_t)count);
     end = (uint32_t)min((uint64_t)next + chunk, (uint64_t)count);

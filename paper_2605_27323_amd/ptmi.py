@@ -18,6 +18,7 @@ LIB_PATH = os.environ.get("PTMI_LIB") or os.path.join(HERE, "libptmi.so")
 PT_OK, PT_EINVAL, PT_ENOMEM, PT_EHIP, PT_ESTATE, PT_EOVERFLOW, PT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 MODE_MEGA, MODE_WAVE = 0, 1
 FLAG_PROFILE, FLAG_NO_COMPACT, FLAG_SORT_MATERIAL, FLAG_COUNT_WORK, FLAG_SORT_RAYS = 1, 2, 4, 8, 16
+FLAG_XCD_LOCAL = 32
 SAMPLER_PHILOX, SAMPLER_HALTON = 0, 1
 STAGES = ["raygen", "extend", "shade", "shadow", "accumulate", "mega", "sort", "adjoint", "tail",
           "adjoint_radiance"]

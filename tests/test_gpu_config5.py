@@ -1,0 +1,90 @@
+"""The differentiable-rendering protocol at its configured size: the
+procedural 1.02M-triangle scene at 512x512, 8 spp, depth 6, roulette off,
+light sampling on; per-triangle albedos of the target perturbed by
+N(0, 0.05) and clipped to [0.02, 0.95]; L2 image loss; 200 Adam steps on
+the albedos from the unperturbed ones, gradients from the path-replay
+adjoint with random numbers independent of the forward frame's."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_27323_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2605_27323_amd import ptmi  # noqa: E402
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+CAM = dict(eye=(0.0, 50.0, -130.0), target=(0.0, 40.0, 0.0), up=(0.0, 1.0, 0.0), vfov_deg=50.0, width=512,
+           height=512)
+
+
+def primary_counts(scene, cam, spp):
+    """Primary-hit samples per triangle, from the oracle's closest hits of the
+    pixel-centre rays (times spp)."""
+    c = oracle.camera(cam)
+    W, H = cam["width"], cam["height"]
+    px, py = np.meshgrid(np.arange(W), np.arange(H))
+    sx = ((px + 0.5) / W * 2 - 1).astype(np.float32).reshape(-1, 1)
+    sy = (1 - (py + 0.5) / H * 2).astype(np.float32).reshape(-1, 1)
+    d = sx * c[3:6] + sy * c[6:9] + c[9:12]
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    o = np.repeat(c[None, :3], len(d), 0)
+    _, prim, _, _ = oracle.Scene(scene).closest(o, d.astype(np.float32))
+    return np.bincount(prim[prim >= 0], minlength=scene["indices"].shape[0]) * spp
+
+
+def test_config5_adam_recovers_albedos():
+    scene, _ = scenes.procedural(seed=2, n_objects=2000, width=512, height=512)
+    base = scene["albedo"].copy()
+    light = (scene["emission"] > 0).any(1)
+    true_alb = scenes.perturb_albedo(base, seed=5, sigma=0.05)
+    true_alb[light] = 0.0
+    R = ptmi.Renderer(scene, CAM)
+    kw = dict(spp=8, max_depth=6, rr_start=-1, nee=True, mode="mega")
+    R.albedo.copy_(torch.from_numpy(true_alb).cuda())
+    target = torch.zeros((512, 512, 3), device="cuda")
+    n_t = 64  # target = mean of 64 frames of 8 spp (512 spp)
+    for f in range(n_t):
+        target += R.render(seed=777, frame=f, **kw)
+    target /= n_t
+    alb = torch.from_numpy(base.copy()).cuda().requires_grad_(True)
+    mask = torch.from_numpy(~light).cuda()[:, None].float()
+    steps = 200
+    opt = torch.optim.Adam([alb], lr=1e-2)
+    sched = torch.optim.lr_scheduler.CosineAnnealingLR(opt, T_max=steps, eta_min=1e-3)
+    seen = np.nonzero((primary_counts(scene, CAM, 8) >= 64) & ~light)[0]
+    tt = torch.from_numpy(true_alb[seen]).cuda()
+    idx = torch.from_numpy(seen).cuda()
+    curve = []
+    for step in range(steps):
+        opt.zero_grad()
+        R.albedo.copy_(alb.detach())
+        I = R.render(seed=2 * step, **kw)
+        d_img = (2.0 / I.numel()) * (I - target)
+        ga = torch.zeros_like(R.albedo)
+        ge = torch.zeros_like(R.emission)
+        R.backward(d_img.contiguous(), ga, ge, seed=2 * step + 1, **kw)
+        alb.grad = ga * mask
+        opt.step()
+        sched.step()
+        with torch.no_grad():
+            alb.clamp_(0.02, 0.95)
+            alb[torch.from_numpy(light).cuda()] = 0.0
+        if step % 20 == 0 or step == steps - 1:
+            e = float((alb.detach()[idx] - tt).abs().mean())
+            curve.append((step, e))
+            log("step", step, "loss", float(((I - target) ** 2).mean()), "albedo error", e)
+    e0 = float(np.abs(base[seen] - true_alb[seen]).mean())
+    e1 = curve[-1][1]
+    log("triangles with >= 64 primary samples:", len(seen), "error", e0, "->", e1, "ratio", e0 / e1)
+    assert len(seen) > 1000
+    assert e1 <= e0 / 5, (e0, e1, curve)

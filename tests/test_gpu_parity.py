@@ -193,6 +193,10 @@ def test_no_compaction_and_launch_shapes_bit_identical():
             R.render(mode="wave", tail_bounce=2, tail_spread=True, **cfg),
             R.render(mode="wave", tail_threshold=1 << 30, tail_spread=True, block=64, grid_mult=1, **cfg),
             R.render(mode="wave", tail_threshold=500, tail_spread=True, flags=ptmi.FLAG_SORT_MATERIAL, **cfg),
+            R.render(mode="wave", flags=ptmi.FLAG_XCD_LOCAL, **cfg),
+            R.render(mode="wave", flags=ptmi.FLAG_XCD_LOCAL, block=64, grid_mult=3, tail_bounce=3, **cfg),
+            R.render(mode="mega", flags=ptmi.FLAG_XCD_LOCAL, **cfg),
+            R.render(mode="mega", flags=ptmi.FLAG_XCD_LOCAL, block=128, grid_mult=1, mega_waves=5, **cfg),
             R.render(mode="wave", **cfg)]
     # the image does not depend on the BVH either: leaves of up to 4 and 8 triangles
     for ml in (4, 8):
