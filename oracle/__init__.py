@@ -61,7 +61,10 @@ def lib():
     L.orc_radical_inverse.restype = C.c_float
     L.orc_radical_inverse.argtypes = [C.c_uint32, C.c_int32]
     L.orc_halton_jitter.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, f32p]
-    L.orc_closest.argtypes = [C.c_void_p, C.c_int32, f32p, f32p, C.c_float, C.c_int32, f32p, i32p, f32p, f32p]
+    L.orc_closest.argtypes = [C.c_void_p, C.c_int32, f32p, f32p, C.c_float, C.c_int32, f32p, i32p, f32p, f32p,
+                              C.c_void_p]
+    L.orc_scene_set_instances.restype = C.c_int32
+    L.orc_scene_set_instances.argtypes = [C.c_void_p, C.c_int32, i32p, i32p, C.c_int32, i32p, f32p, f32p]
     L.orc_anyhit.argtypes = [C.c_void_p, C.c_int32, f32p, f32p, C.c_float, C.c_int32, u8p]
     L.orc_tri_test.restype = C.c_int32
     L.orc_tri_test.argtypes = [f32p, f32p, f32p, f32p, f32p, C.POINTER(C.c_float), C.POINTER(C.c_float),
@@ -108,7 +111,11 @@ def unif(w):
 class Scene:
     """Oracle-side scene (own triangle copy, own light CDF, own BVH)."""
 
-    def __init__(self, scene, bvh=True):
+    def __init__(self, scene, bvh=True, instances=None):
+        """instances (optional): a two-level scene, dict of mesh_first,
+        mesh_count (int32 [n_meshes]), inst_mesh (int32 [n_inst]), o2w and
+        w2o (float32 [n_inst, 12], 3x4 row-major); the scene's triangles are
+        then the meshes, in object space."""
         L = lib()
         pos = _f32(scene["positions"]).reshape(-1)
         idx = np.ascontiguousarray(scene["indices"], np.int32).reshape(-1)
@@ -121,6 +128,15 @@ class Scene:
         if not self.ptr:
             raise ValueError("oracle rejected the scene")
         self.has_bvh = bool(bvh)
+        if instances is not None:
+            i = instances
+            rc = L.orc_scene_set_instances(self.ptr, len(i["mesh_first"]),
+                                           np.ascontiguousarray(i["mesh_first"], np.int32),
+                                           np.ascontiguousarray(i["mesh_count"], np.int32), len(i["inst_mesh"]),
+                                           np.ascontiguousarray(i["inst_mesh"], np.int32),
+                                           _f32(i["o2w"]).reshape(-1), _f32(i["w2o"]).reshape(-1))
+            if rc != 0:
+                raise ValueError("oracle rejected the instances")
 
     def __del__(self):
         if getattr(self, "ptr", None):
@@ -191,7 +207,7 @@ class Scene:
             raise ValueError(f"orc_backward failed ({rc})")
         return ga.reshape(-1, 3), ge.reshape(-1, 3), aa.reshape(-1, 3), ae.reshape(-1, 3)
 
-    def closest(self, o, d, tmax=np.inf, mode=1):
+    def closest(self, o, d, tmax=np.inf, mode=1, with_inst=False):
         o = _f32(o).reshape(-1)
         d = _f32(d).reshape(-1)
         n = o.size // 3
@@ -199,7 +215,10 @@ class Scene:
         prim = np.zeros(n, np.int32)
         b1 = np.zeros(n, np.float32)
         b2 = np.zeros(n, np.float32)
-        lib().orc_closest(self.ptr, n, o, d, float(tmax), int(mode), t, prim, b1, b2)
+        inst = np.zeros(n, np.int32)
+        lib().orc_closest(self.ptr, n, o, d, float(tmax), int(mode), t, prim, b1, b2, inst.ctypes.data)
+        if with_inst:
+            return t, prim, b1, b2, inst
         return t, prim, b1, b2
 
     def anyhit(self, o, d, tmax, mode=1):

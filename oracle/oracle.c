@@ -166,7 +166,43 @@ struct orc_scene {
     onode* nodes;
     int32_t nnodes, depth;
     int32_t* order;
+    /* two-level scene: ninst > 0 places meshes (ranges of the triangles, in
+     * object space) by affine maps; the triangles alone are then no longer
+     * world geometry.  o2w, w2o: 12 floats per instance (3x4, row-major). */
+    int32_t nmesh, ninst;
+    int32_t *mesh_first, *mesh_count, *mesh_root;
+    int32_t* inst_mesh;
+    float *o2w, *w2o;
+    int32_t* light_inst; /* instance of each light */
 };
+
+/* Affine map by a 3x4 row-major matrix M (row r: linear part M[4r..4r+2],
+ * translation M[4r+3]), in this order: ((M0 x + M1 y) + M2 z) + M3.  The
+ * direction map drops the translation. */
+static v3 xform_point(const float* M, v3 p)
+{
+    return V(((M[0] * p.x + M[1] * p.y) + M[2] * p.z) + M[3], ((M[4] * p.x + M[5] * p.y) + M[6] * p.z) + M[7],
+             ((M[8] * p.x + M[9] * p.y) + M[10] * p.z) + M[11]);
+}
+static v3 xform_dir(const float* M, v3 d)
+{
+    return V((M[0] * d.x + M[1] * d.y) + M[2] * d.z, (M[4] * d.x + M[5] * d.y) + M[6] * d.z,
+             (M[8] * d.x + M[9] * d.y) + M[10] * d.z);
+}
+
+/* World-space vertices (9 floats) of triangle tri, placed by instance inst
+ * (the triangle itself in a flat scene): out, or the triangle's own array. */
+static const float* world_tri(const orc_scene* s, int32_t inst, int32_t tri, float out[9])
+{
+    const float* p = s->v + 9 * (size_t)tri;
+    if (s->ninst == 0) return p;
+    const float* M = s->o2w + 12 * (size_t)inst;
+    for (int k = 0; k < 3; ++k) {
+        v3 w = xform_point(M, V(p[3 * k], p[3 * k + 1], p[3 * k + 2]));
+        out[3 * k] = w.x; out[3 * k + 1] = w.y; out[3 * k + 2] = w.z;
+    }
+    return out;
+}
 
 static int finite3(const float* p) { return isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]); }
 
@@ -174,18 +210,32 @@ static int finite3(const float* p) { return isfinite(p[0]) && isfinite(p[1]) && 
  * CDF: fp64 prefix sums of the areas 0.5 |(v1-v0) x (v2-v0)| in triangle
  * order, quantised as floor(cum/total * 2^32), the last entry forced to
  * 2^32-1.  A raw word w selects the first light j with w <= cdf[j]. */
+/* In a two-level scene the light set is every (instance, emissive triangle of
+ * its mesh) pair, in instance order, with the areas of the world-space
+ * triangles (world_tri). */
 static void build_lights(orc_scene* s)
 {
+    free(s->light_tri); free(s->light_cdf); free(s->light_inst);
     s->nl = 0;
-    for (int i = 0; i < s->nt; ++i) s->nl += s->is_light[i];
+    const int ninst = s->ninst > 0 ? s->ninst : 1;
+    for (int q = 0; q < ninst; ++q) {
+        int first = s->ninst > 0 ? s->mesh_first[s->inst_mesh[q]] : 0;
+        int count = s->ninst > 0 ? s->mesh_count[s->inst_mesh[q]] : s->nt;
+        for (int i = first; i < first + count; ++i) s->nl += s->is_light[i];
+    }
     s->light_tri = (int32_t*)malloc(sizeof(int32_t) * (s->nl ? s->nl : 1));
+    s->light_inst = (int32_t*)malloc(sizeof(int32_t) * (s->nl ? s->nl : 1));
     s->light_cdf = (uint32_t*)malloc(sizeof(uint32_t) * (s->nl ? s->nl : 1));
     double* cum = (double*)malloc(sizeof(double) * (s->nl ? s->nl : 1));
     double acc = 0.0;
     int j = 0;
-    for (int i = 0; i < s->nt; ++i) {
+    for (int q = 0; q < ninst; ++q) {
+      int first = s->ninst > 0 ? s->mesh_first[s->inst_mesh[q]] : 0;
+      int count = s->ninst > 0 ? s->mesh_count[s->inst_mesh[q]] : s->nt;
+      for (int i = first; i < first + count; ++i) {
         if (!s->is_light[i]) continue;
-        const float* t = s->v + 9 * (size_t)i;
+        float tw[9];
+        const float* t = world_tri(s, q, i, tw);
         double e1x = (double)t[3] - (double)t[0], e1y = (double)t[4] - (double)t[1],
                e1z = (double)t[5] - (double)t[2];
         double e2x = (double)t[6] - (double)t[0], e2y = (double)t[7] - (double)t[1],
@@ -195,7 +245,9 @@ static void build_lights(orc_scene* s)
         acc += area;
         cum[j] = acc;
         s->light_tri[j] = i;
+        s->light_inst[j] = s->ninst > 0 ? q : 0;
         ++j;
+      }
     }
     s->area_total = (float)acc;
     for (j = 0; j < s->nl; ++j) {
@@ -296,16 +348,25 @@ static int bvh_build_rec(orc_scene* s, int first, int count, int depth, float pa
 
 static void build_bvh(orc_scene* s)
 {
+    free(s->order); free(s->nodes);
     s->order = (int32_t*)malloc(sizeof(int32_t) * (s->nt ? s->nt : 1));
     for (int i = 0; i < s->nt; ++i) s->order[i] = i;
     s->nodes = (onode*)malloc(sizeof(onode) * (size_t)(2 * (s->nt ? s->nt : 1)));
     s->nnodes = 0;
     s->depth = 0;
     if (s->nt == 0) return;
-    float m = 0.0f;
-    for (size_t i = 0; i < (size_t)s->nt * 9; ++i)
-        if (fabsf(s->v[i]) > m) m = fabsf(s->v[i]);
-    bvh_build_rec(s, 0, s->nt, 0, m * 0x1p-18f);
+    /* one BVH over all triangles (flat scene), or one per mesh in object
+     * space (two-level scene), each padded by 2^-18 of its own largest
+     * coordinate */
+    const int nb = s->ninst > 0 ? s->nmesh : 1;
+    for (int b = 0; b < nb; ++b) {
+        int first = s->ninst > 0 ? s->mesh_first[b] : 0, count = s->ninst > 0 ? s->mesh_count[b] : s->nt;
+        float m = 0.0f;
+        for (size_t i = 9 * (size_t)first; i < 9 * (size_t)(first + count); ++i)
+            if (fabsf(s->v[i]) > m) m = fabsf(s->v[i]);
+        int root = count > 0 ? bvh_build_rec(s, first, count, 0, m * 0x1p-18f) : -1;
+        if (s->ninst > 0) s->mesh_root[b] = root;
+    }
 }
 
 orc_scene* orc_scene_create(int32_t nv, const float* pos, int32_t nt, const int32_t* idx,
@@ -368,7 +429,40 @@ void orc_scene_destroy(orc_scene* s)
     if (!s) return;
     free(s->v); free(s->tri_mat); free(s->mats); free(s->albedo); free(s->emission);
     free(s->is_light); free(s->light_tri); free(s->light_cdf); free(s->nodes); free(s->order);
+    free(s->mesh_first); free(s->mesh_count); free(s->mesh_root); free(s->inst_mesh); free(s->o2w); free(s->w2o);
+    free(s->light_inst);
     free(s);
+}
+
+int32_t orc_scene_set_instances(orc_scene* s, int32_t n_meshes, const int32_t* mesh_first,
+                                const int32_t* mesh_count, int32_t n_inst, const int32_t* inst_mesh,
+                                const float* o2w, const float* w2o)
+{
+    if (n_meshes < 1 || n_inst < 1) return -1;
+    for (int m = 0; m < n_meshes; ++m)
+        if (mesh_first[m] < 0 || mesh_count[m] < 0 || (int64_t)mesh_first[m] + mesh_count[m] > s->nt) return -1;
+    for (int q = 0; q < n_inst; ++q) {
+        if (inst_mesh[q] < 0 || inst_mesh[q] >= n_meshes) return -1;
+        for (int k = 0; k < 12; ++k)
+            if (!isfinite(o2w[12 * (size_t)q + k]) || !isfinite(w2o[12 * (size_t)q + k])) return -1;
+    }
+    int had_bvh = s->nodes != NULL;
+    s->nmesh = n_meshes;
+    s->ninst = n_inst;
+    s->mesh_first = (int32_t*)malloc(sizeof(int32_t) * n_meshes);
+    s->mesh_count = (int32_t*)malloc(sizeof(int32_t) * n_meshes);
+    s->mesh_root = (int32_t*)malloc(sizeof(int32_t) * n_meshes);
+    memcpy(s->mesh_first, mesh_first, sizeof(int32_t) * n_meshes);
+    memcpy(s->mesh_count, mesh_count, sizeof(int32_t) * n_meshes);
+    s->inst_mesh = (int32_t*)malloc(sizeof(int32_t) * n_inst);
+    memcpy(s->inst_mesh, inst_mesh, sizeof(int32_t) * n_inst);
+    s->o2w = (float*)malloc(sizeof(float) * 12 * (size_t)n_inst);
+    s->w2o = (float*)malloc(sizeof(float) * 12 * (size_t)n_inst);
+    memcpy(s->o2w, o2w, sizeof(float) * 12 * (size_t)n_inst);
+    memcpy(s->w2o, w2o, sizeof(float) * 12 * (size_t)n_inst);
+    build_lights(s);
+    if (had_bvh) build_bvh(s);
+    return 0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -503,16 +597,19 @@ int32_t orc_tri_test(const float o[3], const float d[3], const float v0[3], cons
 typedef struct {
     float t, b1, b2;
     int32_t prim;
+    int32_t inst; /* instance of the hit (0 in a flat scene) */
     float margin; /* smallest barycentric of the current best hit */
     float tie_t;  /* largest t of the closest pair of near-equal hits seen */
     float miss_t; /* smallest plane distance of a near-missed triangle */
 } hit_t;
 
-/* Candidate update with the (t, id) lexicographic order.  For the fragility
- * flags it also remembers near-ties (relative 2^-20) between distinct
- * triangles and near-misses (within 1e-6 barycentric of an edge); they are
- * judged against the final closest hit in closest(). */
-static void consider(const orc_scene* s, const ray_t* r, int tri, float tmax, hit_t* h)
+/* Candidate update with the (t, instance, id) lexicographic order (instance
+ * 0 in a flat scene).  For the fragility flags it also remembers near-ties
+ * (relative 2^-20) between distinct triangles and near-misses (within 1e-6
+ * barycentric of an edge); they are judged against the final closest hit in
+ * closest().  r is the ray in the triangle's own space (object space of the
+ * instance), whose parameter t is the world ray's. */
+static void consider(const orc_scene* s, const ray_t* r, int tri, int inst, float tmax, hit_t* h)
 {
     float t, b1, b2, m;
     int ok = tri_test(r, s->v + 9 * (size_t)tri, &t, &b1, &b2, &m);
@@ -525,9 +622,18 @@ static void consider(const orc_scene* s, const ray_t* r, int tri, float tmax, hi
         float hi = t > h->t ? t : h->t;
         if (hi < h->tie_t) h->tie_t = hi;
     }
-    if (t < h->t || (t == h->t && tri < h->prim)) {
-        h->t = t; h->b1 = b1; h->b2 = b2; h->prim = tri; h->margin = m;
+    if (t < h->t || (t == h->t && (inst < h->inst || (inst == h->inst && tri < h->prim)))) {
+        h->t = t; h->b1 = b1; h->b2 = b2; h->prim = tri; h->inst = inst; h->margin = m;
     }
+}
+
+/* The ray in the object space of instance q: origin and direction mapped by
+ * its world-to-object matrix (xform_point, xform_dir), not renormalised, so
+ * that a point at parameter t is the image of the world ray's point at t. */
+static void object_ray(const orc_scene* s, int q, const ray_t* r, ray_t* ro)
+{
+    const float* M = s->w2o + 12 * (size_t)q;
+    ray_setup(ro, xform_point(M, r->o), xform_dir(M, r->d));
 }
 
 /* Conservative slab test: entry <= exit * (1 + 2^-16), entry clamped at 0
@@ -552,36 +658,50 @@ static int box_test(const onode* nd, const ray_t* r, float tlim, float* tnear)
     return t0 <= t1 * (1.0f + 0x1p-16f);
 }
 
-static void bvh_closest_rec(const orc_scene* s, int ni, const ray_t* r, float tmax, hit_t* h)
+static void bvh_closest_rec(const orc_scene* s, int ni, const ray_t* r, int inst, float tmax, hit_t* h)
 {
     const onode* nd = &s->nodes[ni];
     float tn;
     float lim = h->prim >= 0 ? h->t : tmax;
     if (!box_test(nd, r, lim, &tn)) return;
     if (nd->count > 0) {
-        for (int i = nd->first; i < nd->first + nd->count; ++i) consider(s, r, s->order[i], tmax, h);
+        for (int i = nd->first; i < nd->first + nd->count; ++i) consider(s, r, s->order[i], inst, tmax, h);
         return;
     }
     float tl = INFINITY, tr = INFINITY;
     int hl = box_test(&s->nodes[nd->left], r, lim, &tl);
     int hr = box_test(&s->nodes[nd->right], r, lim, &tr);
     if (hl && hr && tr < tl) {
-        bvh_closest_rec(s, nd->right, r, tmax, h);
-        bvh_closest_rec(s, nd->left, r, tmax, h);
+        bvh_closest_rec(s, nd->right, r, inst, tmax, h);
+        bvh_closest_rec(s, nd->left, r, inst, tmax, h);
     } else {
-        if (hl) bvh_closest_rec(s, nd->left, r, tmax, h);
-        if (hr) bvh_closest_rec(s, nd->right, r, tmax, h);
+        if (hl) bvh_closest_rec(s, nd->left, r, inst, tmax, h);
+        if (hr) bvh_closest_rec(s, nd->right, r, inst, tmax, h);
     }
 }
 
 static void closest(const orc_scene* s, const ray_t* r, float tmax, int use_bvh, hit_t* h, int* frag)
 {
-    h->t = tmax; h->b1 = 0.0f; h->b2 = 0.0f; h->prim = -1;
+    h->t = tmax; h->b1 = 0.0f; h->b2 = 0.0f; h->prim = -1; h->inst = 0;
     h->margin = 1.0f; h->tie_t = INFINITY; h->miss_t = INFINITY;
     if (s->nt == 0) return;
-    if (use_bvh && s->nodes) bvh_closest_rec(s, 0, r, tmax, h);
-    else
-        for (int i = 0; i < s->nt; ++i) consider(s, r, i, tmax, h);
+    if (s->ninst > 0) {
+        /* every instance, in its object space (no world-space culling: the
+         * result cannot depend on instance boxes) */
+        for (int q = 0; q < s->ninst; ++q) {
+            const int m = s->inst_mesh[q];
+            if (s->mesh_count[m] == 0) continue;
+            ray_t ro;
+            object_ray(s, q, r, &ro);
+            if (use_bvh && s->nodes) bvh_closest_rec(s, s->mesh_root[m], &ro, q, tmax, h);
+            else
+                for (int i = s->mesh_first[m]; i < s->mesh_first[m] + s->mesh_count[m]; ++i) consider(s, &ro, i, q, tmax, h);
+        }
+    } else if (use_bvh && s->nodes) {
+        bvh_closest_rec(s, 0, r, 0, tmax, h);
+    } else {
+        for (int i = 0; i < s->nt; ++i) consider(s, r, i, 0, tmax, h);
+    }
     if (!frag) return;
     if (h->prim >= 0) {
         float lim = h->t * (1.0f + 0x1p-20f);
@@ -627,6 +747,21 @@ static int bvh_any_rec(const orc_scene* s, int ni, const ray_t* r, float tmax, i
 static int occluded(const orc_scene* s, const ray_t* r, float tmax, int use_bvh, int* frag)
 {
     if (s->nt == 0) return 0;
+    if (s->ninst > 0) {
+        for (int q = 0; q < s->ninst; ++q) {
+            const int m = s->inst_mesh[q];
+            if (s->mesh_count[m] == 0) continue;
+            ray_t ro;
+            object_ray(s, q, r, &ro);
+            if (use_bvh && s->nodes) {
+                if (bvh_any_rec(s, s->mesh_root[m], &ro, tmax, frag)) return 1;
+            } else {
+                for (int i = s->mesh_first[m]; i < s->mesh_first[m] + s->mesh_count[m]; ++i)
+                    if (any_tri(s, &ro, i, tmax, frag)) return 1;
+            }
+        }
+        return 0;
+    }
     if (use_bvh && s->nodes) return bvh_any_rec(s, 0, r, tmax, frag);
     for (int i = 0; i < s->nt; ++i)
         if (any_tri(s, r, i, tmax, frag)) return 1;
@@ -634,7 +769,7 @@ static int occluded(const orc_scene* s, const ray_t* r, float tmax, int use_bvh,
 }
 
 int32_t orc_closest(const orc_scene* s, int32_t n, const float* o, const float* d, float tmax,
-                    int32_t mode, float* t, int32_t* prim, float* b1, float* b2)
+                    int32_t mode, float* t, int32_t* prim, float* b1, float* b2, int32_t* inst)
 {
     for (int i = 0; i < n; ++i) {
         ray_t r;
@@ -642,6 +777,7 @@ int32_t orc_closest(const orc_scene* s, int32_t n, const float* o, const float* 
         hit_t h;
         closest(s, &r, tmax, mode, &h, NULL);
         t[i] = h.t; prim[i] = h.prim; b1[i] = h.b1; b2[i] = h.b2;
+        if (inst) inst[i] = h.prim >= 0 ? h.inst : -1;
     }
     return 0;
 }
@@ -989,7 +1125,8 @@ static v3 trace_path(const pt_args* a, int pix, uint32_t sample, int* frag, vrec
             L = V(L.x + beta.x * s->sky[0], L.y + beta.y * s->sky[1], L.z + beta.z * s->sky[2]);
             break;
         }
-        const float* tp = s->v + 9 * (size_t)h.prim;
+        float tw[9];
+        const float* tp = world_tri(s, h.inst, h.prim, tw);
         v3 v0 = vload(tp), e1 = vsub(vload(tp + 3), v0), e2 = vsub(vload(tp + 6), v0);
         v3 x = V((v0.x + h.b1 * e1.x) + h.b2 * e2.x, (v0.y + h.b1 * e1.y) + h.b2 * e2.y,
                  (v0.z + h.b1 * e1.z) + h.b2 * e2.z);
@@ -1036,7 +1173,8 @@ static v3 trace_path(const pt_args* a, int pix, uint32_t sample, int* frag, vrec
                 if (hi - w[0] < 4096u || (j > 0 && w[0] - lo < 4096u)) *frag |= FR_THRESH;
             }
             int lt = s->light_tri[j];
-            const float* lp = s->v + 9 * (size_t)lt;
+            float lw[9];
+            const float* lp = world_tri(s, s->light_inst[j], lt, lw);
             v3 y = tri_point(lp, orc_unif(w[1]), orc_unif(w[2]));
             v3 ny = tri_normal(lp);
             v3 dv = vsub(y, x);

@@ -46,6 +46,24 @@ void orc_scene_destroy(orc_scene* s);
  * at creation (triangles with some emission channel > 0). */
 void orc_scene_set_params(orc_scene* s, const float* albedo, const float* emission);
 int32_t orc_scene_num_lights(const orc_scene* s);
+/* Two-level scene (paper Sec. 2.3 and 3: a top-level structure over
+ * instances of bottom-level meshes).  Mesh m is the triangle range
+ * [mesh_first[m], mesh_first[m] + mesh_count[m]) of the scene, in object
+ * space; instance q places mesh inst_mesh[q] in the world by the affine map
+ * o2w[12q .. 12q + 11] (3x4 row-major: row r = linear row r, translation r),
+ * and w2o (same layout) maps world rays into its object space.  From then on
+ * the world is the instances: a ray is tested against each instance's mesh
+ * with the object-space ray ((M0 x + M1 y) + M2 z) + M3 per row, direction
+ * without translation, not renormalised, so t is the world ray's parameter;
+ * the closest hit is the smallest t, ties to the smaller instance and then
+ * the smaller triangle; shading, light sampling and areas use the world-space
+ * vertices o2w(v) in the same arithmetic; per-triangle parameters (material,
+ * albedo, emission) are shared by all instances of a mesh; the light set is
+ * every (instance, emissive triangle) pair.  Returns 0, or -1 on invalid
+ * input (out-of-range ranges or indices, non-finite matrices). */
+int32_t orc_scene_set_instances(orc_scene* s, int32_t n_meshes, const int32_t* mesh_first,
+                                const int32_t* mesh_count, int32_t n_inst, const int32_t* inst_mesh,
+                                const float* o2w, const float* w2o);
 /* BVH statistics: node count and maximum depth (0 if no BVH). */
 void orc_scene_bvh_stats(const orc_scene* s, int32_t* nodes, int32_t* depth);
 
@@ -90,9 +108,10 @@ float orc_radical_inverse(uint32_t n, int32_t base);
 void orc_halton_jitter(uint64_t seed, uint32_t pixel, uint32_t sample, uint32_t job, float out[2]);
 
 /* Closest hit (mode 0 brute force, 1 BVH) for n rays o[3n], d[3n] with
- * t in (0, tmax).  prim = -1 on a miss. */
+ * t in (0, tmax).  prim = -1 on a miss; inst (may be NULL) receives the
+ * instance of the hit in a two-level scene (0 in a flat one, -1 on a miss). */
 int32_t orc_closest(const orc_scene* s, int32_t n, const float* o, const float* d, float tmax,
-                    int32_t mode, float* t, int32_t* prim, float* b1, float* b2);
+                    int32_t mode, float* t, int32_t* prim, float* b1, float* b2, int32_t* inst);
 /* Any hit in (0, tmax): occluded[i] = 0/1. */
 int32_t orc_anyhit(const orc_scene* s, int32_t n, const float* o, const float* d, float tmax,
                    int32_t mode, uint8_t* occluded);

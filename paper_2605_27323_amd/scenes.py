@@ -361,6 +361,124 @@ def procedural(seed=2, n_objects=2000, width=1920, height=1080, material_mode="l
     return scene, cam
 
 
+# --------------------------------------------------------------------------
+# Two-level scenes: meshes (ranges of the triangle list, object space) placed
+# by instances (3x4 row-major object-to-world maps and their inverses)
+# --------------------------------------------------------------------------
+def affine(rot, scale, trans):
+    """(o2w, w2o) as float32 [12] arrays for x -> scale * rot @ x + trans
+    (rot orthonormal), the inverse computed in binary64 and rounded once."""
+    rot = np.asarray(rot, np.float64)
+    trans = np.asarray(trans, np.float64)
+    A = scale * rot
+    Ai = rot.T / scale
+    o2w = np.concatenate([A, trans[:, None]], 1)
+    w2o = np.concatenate([Ai, (-Ai @ trans)[:, None]], 1)
+    return o2w.astype(np.float32).reshape(12), w2o.astype(np.float32).reshape(12)
+
+
+def random_rotation(rng):
+    """Uniform random rotation (quaternion with normal components)."""
+    q = rng.normal(size=4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+                     [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+                     [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
+
+
+def split_into_instances(scene, parts):
+    """A flat scene as a two-level one: its triangles cut into `parts`
+    consecutive meshes, each placed once by the identity."""
+    nt = scene["indices"].shape[0]
+    cuts = np.linspace(0, nt, parts + 1).round().astype(np.int64)
+    eye = np.array([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0], np.float32)
+    return {"mesh_first": cuts[:-1].astype(np.int32), "mesh_count": np.diff(cuts).astype(np.int32),
+            "inst_mesh": np.arange(parts, dtype=np.int32), "o2w": np.tile(eye, (parts, 1)),
+            "w2o": np.tile(eye, (parts, 1))}
+
+
+def instanced_procedural(seed=6, n_instances=4000, n_meshes=32, width=1920, height=1080, ground_albedo=0.5,
+                         light_le=20.0):
+    """A scene of shared meshes: n_meshes object meshes (icospheres of level
+    2-4 and tessellated boxes, unit size, each with its own material) placed
+    n_instances times with random rotations, scales log-uniform in [0.1, 5]
+    and centres uniform in [-50,50] x [0,100] x [-50,50]; a 400 x 400 ground
+    quad (one instance) and a 10 x 10 downward quad light placed 16 times on a
+    4 x 4 grid at y = 120 (the procedural scene's layout).  Materials per
+    mesh: 50% Lambertian (albedo U[0.1,0.9]^3), 50% GGX conductor (F0
+    U[0.1,0.9]^3, roughness U[0.05,0.8]).  Returns (scene, instances, cam)."""
+    rng = np.random.default_rng(seed)
+    P, I, M, A, E = [], [], [], [], []
+    materials = [(LAMBERT, 1.0, 1.5, 0.0)]
+    first, count = [], []
+    nt = 0
+
+    def add(pos, idx, mat, alb, emi):
+        nonlocal nt
+        P.append(pos); I.append(idx)
+        m, a, e = _tri_params(idx.shape[0], alb, emi, mat)
+        M.append(m); A.append(a); E.append(e)
+        first.append(nt); count.append(idx.shape[0])
+        nt += idx.shape[0]
+
+    for k in range(n_meshes):
+        if k % 2 == 0:
+            pos, idx = icosphere_unit(int(rng.integers(2, 5)))
+        else:
+            pos, idx = box_mesh(-rng.uniform(0.5, 1.0, 3), rng.uniform(0.5, 1.0, 3), int(rng.integers(2, 6)))
+        alb = rng.uniform(0.1, 0.9, size=3)
+        if rng.uniform() < 0.5:
+            mat = 0
+        else:
+            materials.append((CONDUCTOR, float(rng.uniform(0.05, 0.8)), 1.5, 0.0))
+            mat = len(materials) - 1
+        add(pos, idx, mat, alb, np.zeros(3))
+    gp, gi = quad((-200, 0, -200), (-200, 0, 200), (200, 0, 200), (200, 0, -200))
+    add(gp, gi, 0, (ground_albedo,) * 3, (0, 0, 0))
+    lp, li = quad((-5, 0, -5), (5, 0, -5), (5, 0, 5), (-5, 0, 5))
+    add(lp, li, 0, (0, 0, 0), (light_le,) * 3)
+    ground, light = n_meshes, n_meshes + 1
+    inst_mesh, o2w, w2o = [], [], []
+    for q in range(n_instances):
+        a, b = affine(random_rotation(rng), float(np.exp(rng.uniform(np.log(0.1), np.log(5.0)))),
+                      (rng.uniform(-50, 50), rng.uniform(0, 100), rng.uniform(-50, 50)))
+        inst_mesh.append(int(rng.integers(0, n_meshes))); o2w.append(a); w2o.append(b)
+    a, b = affine(np.eye(3), 1.0, (0, 0, 0))
+    inst_mesh.append(ground); o2w.append(a); w2o.append(b)
+    for gx in np.linspace(-45, 45, 4):
+        for gz in np.linspace(-45, 45, 4):
+            a, b = affine(np.eye(3), 1.0, (gx, 120.0, gz))
+            inst_mesh.append(light); o2w.append(a); w2o.append(b)
+    scene = _pack(P, I, M, A, E, materials)
+    inst = {"mesh_first": np.array(first, np.int32), "mesh_count": np.array(count, np.int32),
+            "inst_mesh": np.array(inst_mesh, np.int32), "o2w": np.array(o2w, np.float32),
+            "w2o": np.array(w2o, np.float32)}
+    cam = dict(eye=(0.0, 50.0, -130.0), target=(0.0, 40.0, 0.0), up=(0.0, 1.0, 0.0),
+               vfov_deg=50.0, width=width, height=height)
+    return scene, inst, cam
+
+
+def flatten_instances(scene, inst):
+    """The world-space flat scene of a two-level one (every instance's
+    triangles mapped by its o2w in binary64, rounded once; per-triangle
+    parameters copied), for size and speed comparisons."""
+    pos = scene["positions"].astype(np.float64)
+    idx = scene["indices"]
+    P, I, M, A, E = [], [], [], [], []
+    for q, m in enumerate(inst["inst_mesh"]):
+        f, n = int(inst["mesh_first"][m]), int(inst["mesh_count"][m])
+        if n == 0:
+            continue
+        T = inst["o2w"][q].astype(np.float64).reshape(3, 4)
+        tri = idx[f:f + n]
+        v = pos[tri.reshape(-1)] @ T[:, :3].T + T[:, 3]
+        P.append(v)
+        I.append(np.arange(3 * n, dtype=np.int32).reshape(n, 3))
+        M.append(scene["tri_mat"][f:f + n]); A.append(scene["albedo"][f:f + n]); E.append(scene["emission"][f:f + n])
+    return _pack(P, I, M, A, E, scene["materials"], sky=scene["sky"])
+
+
 def random_soup(seed, n_tris, extent=1.0, emissive_frac=0.1, materials=None):
     """Random triangle soup in [-extent, extent]^3 (tiny scenes for
     intersection and parity tests), with shared edges from a small vertex
