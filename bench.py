@@ -317,8 +317,8 @@ def main():
             log(f"wavefront ({name}) stage ms/frame: " +
                 ", ".join(f"{s} {v:.3f}" for s, v in frame_stage_ms[name].items()))
             lds = params.get("stack_lds", 8)
-            kname = {"extend": f"ptmi::k_extend<{lds}, false>", "shadow": f"ptmi::k_shadow<{lds}, false>",
-                     "tail": f"ptmi::k_shade_tail<{lds}, false>", "shade": "ptmi::k_shade"}
+            kname = {"extend": f"ptmi::k_extend<{lds}, false, false>", "shadow": f"ptmi::k_shadow<{lds}, false, false>",
+                     "tail": f"ptmi::k_shade_tail<{lds}, false, false>", "shade": "ptmi::k_shade<false>"}
             for st in ["extend", "shadow", "shade", "tail"]:
                 if st not in acc["launches"]:
                     continue
@@ -339,7 +339,7 @@ def main():
         acc = profiled_frames(R, img, ptmi, "mega", FIXED_PARAMS["mega"], k, args.warmup, kw)
         waves = FIXED_PARAMS["mega"].get("mega_waves", 4)
         out_roof["mega"] = roofline_entry(
-            f"ptmi::k_mega<{FIXED_PARAMS['mega']['stack_lds']}, false, {waves}>", acc["launches"]["mega"],
+            f"ptmi::k_mega<{FIXED_PARAMS['mega']['stack_lds']}, false, {waves}, false>", acc["launches"]["mega"],
             acc["stage_ms"]["mega"], acc["bytes"]["mega"], acc["node_visits"]["mega"], acc["tri_tests"]["mega"],
             prof, copy_gbs)
 
@@ -417,6 +417,8 @@ def main():
     if not args.no_extra:
         del R
         torch.cuda.empty_cache()
+        out["instancing"] = instancing_bench(args, torch, ptmi, scenes)
+        torch.cuda.empty_cache()
         out["divergence"] = divergence_bench(args, torch, ptmi, scenes, frames=2, summary=True)
         torch.cuda.empty_cache()
         out["batch"] = batch_bench(args, torch, ptmi, scenes, None, runs=2, summary=True)
@@ -446,6 +448,36 @@ def compaction_bench(torch, R, img, ptmi, kw, params, k=6):
         res[f"depth{depth}"] = r
         log(f"compaction depth {depth}: {r['compacted']['ms_per_frame']:.3f} ms vs "
             f"{r['no_compaction']['ms_per_frame']:.3f} ms without ({r['gain']:.2f}x)")
+    return res
+
+
+def instancing_bench(args, torch, ptmi, scenes, k=8):
+    """Two-level scene (4016 instances of 34 shared meshes, ~1M instanced
+    triangles, the procedural scene's layout) against its flattened copy:
+    device bytes of the acceleration structure and triangles, and ms per
+    frame of the hybrid wavefront and the megakernel, frame by frame."""
+    sc, inst, cam = scenes.instanced_procedural(seed=6, width=W, height=H)
+    flat = scenes.flatten_instances(sc, inst)
+    kw = dict(spp=SPP, max_depth=DEPTH, rr_start=RR, nee=True, seed=0)
+    img = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+    res = {}
+    for name, R in [("instanced", ptmi.Renderer(sc, cam, instances=inst)), ("flattened", ptmi.Renderer(flat, cam))]:
+        i = R.info
+        r = {"triangles": R.nt, "instances": i.instance_count, "node_bytes": i.node_bytes, "tri_bytes": i.tri_bytes,
+             "instance_bytes": i.instance_bytes, "build_s": i.build_seconds,
+             "device_bytes": i.node_bytes + i.tri_bytes + i.instance_bytes + i.light_bytes}
+        for mode, p in [("wave_hybrid", dict(FIXED_PARAMS["wave"], mode="wave")),
+                        ("mega", dict(FIXED_PARAMS["mega"], mode="mega"))]:
+            time_frames(torch, R, img, 2, 0, False, **kw, **p)
+            r[f"{mode}_ms_per_frame"] = time_frames(torch, R, img, k, 2, False, **kw, **p) * 1e3 / k
+        res[name] = r
+        log(f"{name}: {r}")
+        del R
+    res["memory_ratio"] = res["flattened"]["device_bytes"] / res["instanced"]["device_bytes"]
+    res["time_ratio_wave"] = res["instanced"]["wave_hybrid_ms_per_frame"] / res["flattened"]["wave_hybrid_ms_per_frame"]
+    res["workload"] = (f"{len(inst['inst_mesh'])} instances of {len(inst['mesh_first'])} meshes "
+                       f"({sc['indices'].shape[0]} unique triangles), {W}x{H}, {SPP} spp, depth {DEPTH}, roulette "
+                       f"from {RR}; flattened = every instance's triangles in world space")
     return res
 
 

@@ -92,6 +92,36 @@ typedef struct {
     float sky[3];
 } pt_scene_desc;
 
+/* Two-level scene (paper Sec. 2.3 and 3: a top-level acceleration structure
+ * over instances of per-mesh bottom-level structures).  Mesh m is the range
+ * [mesh_first[m], mesh_first[m] + mesh_count[m]) of the loaded triangles
+ * (object space; ranges may not overlap); instance q places mesh
+ * inst_mesh[q] in the world by the affine map o2w[12 q .. 12 q + 11] (3x4
+ * row-major: row r = three linear coefficients, then the translation) and
+ * w2o (same layout) maps world rays into its object space.  The world is
+ * then the instances: a ray is tested against an instance's mesh with the
+ * object-space ray ((M0 x + M1 y) + M2 z) + M3 per row (direction without
+ * translation, not renormalised, so t is the world ray's parameter); the
+ * closest hit is the smallest t, ties to the smaller instance, then the
+ * smaller triangle; shading, light sampling and light areas use the world
+ * vertices o2w(v) in the same arithmetic; material, albedo and emission are
+ * per mesh triangle and shared by the instances; the light set is every
+ * (instance, emissive triangle) pair.  Call after pt_load_scene and before
+ * pt_build_bvh; n_instances = 0 (or a NULL desc) returns to a flat scene.
+ * The adjoint and the batched launch take flat scenes only
+ * (PT_EUNSUPPORTED).  PT_EINVAL on out-of-range or overlapping ranges,
+ * indices or non-finite matrices. */
+typedef struct {
+    int32_t n_meshes;
+    const int32_t* mesh_first;
+    const int32_t* mesh_count;
+    int32_t n_instances;
+    const int32_t* inst_mesh;
+    const float* o2w;
+    const float* w2o;
+} pt_instances_desc;
+pt_status pt_set_instances(pt_ctx* ctx, const pt_instances_desc* instances);
+
 /* BVH build options (NULL = defaults). */
 typedef struct {
     int32_t max_leaf;  /* triangles per leaf, 1..8 (0 = default 1: one triangle per leaf
@@ -106,6 +136,7 @@ typedef struct {
     int64_t light_count, light_bytes;/* 16 B per light (leaf-order index, CDF word, input index, 0),
                                         then the input ids of the 64 largest triangles */
     int64_t material_bytes;          /* 16 B per material */
+    int64_t instance_count, instance_bytes; /* two-level scenes: 112 B per instance record */
     int32_t depth;                   /* BVH4 levels */
     int32_t stack_entries;           /* traversal stack entries needed */
     double build_seconds;
@@ -125,6 +156,7 @@ typedef struct {
     float* albedo;
     float* emission;
     int32_t upload_params;
+    void* instances;  /* instance records (two-level scenes; may be NULL for a flat scene) */
 } pt_scene_buffers;
 
 /* Pinhole camera: eye, target, up, vertical field of view (degrees),

@@ -62,6 +62,7 @@ struct pt_ctx {
     std::vector<int32_t> tri_mat;
     float sky[3] = {0, 0, 0};
     BuildResult bvh;
+    InstanceSet inst;  // two-level scene (no instances: flat)
     SceneView view{};
     CamView cam{};
     // profiling
@@ -327,6 +328,8 @@ SceneView make_view(const pt_ctx* c, const pt_scene_buffers* b) {
     v.cz = c->bvh.center[2];
     v.hot_ids = reinterpret_cast<const uint32_t*>(static_cast<const char*>(b->lights) + hot_ids_offset(c));
     v.n_hot = (int32_t)c->bvh.hot_ids.size();
+    v.insts = c->bvh.insts.empty() ? nullptr : reinterpret_cast<const float4*>(b->instances);
+    v.n_inst = (int32_t)(c->bvh.insts.size() / kInstRecord);
     return v;
 }
 
@@ -430,7 +433,43 @@ pt_status pt_load_scene(pt_ctx* c, const pt_scene_desc* s) {
         if (!std::isfinite(v) || v < 0.f) return fail(PT_EINVAL, "emission must be finite and >= 0");
     c->mats.assign(s->materials, s->materials + 4 * (size_t)s->nm);
     std::memcpy(c->sky, s->sky, sizeof c->sky);
+    c->inst = InstanceSet{};
     c->loaded = true;
+    c->built = false;
+    c->bound = false;
+    return PT_OK;
+}
+
+pt_status pt_set_instances(pt_ctx* c, const pt_instances_desc* d) {
+    if (!c) return fail(PT_EINVAL, "null context");
+    if (!c->loaded) return fail(PT_ESTATE, "no scene loaded");
+    InstanceSet is;
+    if (d && d->n_instances > 0) {
+        if (d->n_meshes < 1 || !d->mesh_first || !d->mesh_count || !d->inst_mesh || !d->o2w || !d->w2o)
+            return fail(PT_EINVAL, "null instance array");
+        if ((int64_t)d->n_instances > (int64_t)kLeafFirstMask) return fail(PT_EINVAL, "too many instances");
+        std::vector<std::pair<int32_t, int32_t>> ranges;
+        for (int m = 0; m < d->n_meshes; ++m) {
+            const int32_t f = d->mesh_first[m], n = d->mesh_count[m];
+            if (f < 0 || n < 0 || (int64_t)f + n > c->nt) return fail(PT_EINVAL, "mesh range out of range");
+            if (n > 0) ranges.emplace_back(f, n);
+        }
+        std::sort(ranges.begin(), ranges.end());
+        for (size_t k = 1; k < ranges.size(); ++k)
+            if (ranges[k - 1].first + ranges[k - 1].second > ranges[k].first) return fail(PT_EINVAL, "mesh ranges overlap");
+        for (int q = 0; q < d->n_instances; ++q) {
+            if (d->inst_mesh[q] < 0 || d->inst_mesh[q] >= d->n_meshes) return fail(PT_EINVAL, "instance mesh out of range");
+            for (int k = 0; k < 12; ++k)
+                if (!std::isfinite(d->o2w[12 * (size_t)q + k]) || !std::isfinite(d->w2o[12 * (size_t)q + k]))
+                    return fail(PT_EINVAL, "non-finite instance matrix");
+        }
+        is.mesh_first.assign(d->mesh_first, d->mesh_first + d->n_meshes);
+        is.mesh_count.assign(d->mesh_count, d->mesh_count + d->n_meshes);
+        is.inst_mesh.assign(d->inst_mesh, d->inst_mesh + d->n_instances);
+        is.o2w.assign(d->o2w, d->o2w + 12 * (size_t)d->n_instances);
+        is.w2o.assign(d->w2o, d->w2o + 12 * (size_t)d->n_instances);
+    }
+    c->inst = std::move(is);
     c->built = false;
     c->bound = false;
     return PT_OK;
@@ -444,7 +483,9 @@ pt_status pt_build_bvh(pt_ctx* c, const pt_bvh_opts* o, pt_bvh_info* info) {
     if (max_leaf > kMaxLeaf) return fail(PT_EINVAL, "max_leaf must be <= 8");
     auto t0 = std::chrono::steady_clock::now();
     try {
-        c->bvh = build_scene(c->tri_v, c->tri_mat, c->emission, max_leaf, threads);
+        c->bvh = c->inst.inst_mesh.empty()
+                     ? build_scene(c->tri_v, c->tri_mat, c->emission, max_leaf, threads)
+                     : build_instanced(c->tri_v, c->tri_mat, c->emission, c->inst, max_leaf, threads);
     } catch (const std::exception& e) {
         return fail(PT_ENOMEM, std::string("BVH build failed: ") + e.what());
     }
@@ -459,6 +500,8 @@ pt_status pt_build_bvh(pt_ctx* c, const pt_bvh_opts* o, pt_bvh_info* info) {
         info->light_bytes = (int64_t)(std::max<size_t>(1, c->bvh.lights.size()) * sizeof(LightEntry) +
                                       sizeof(LightEntry) * (size_t)((kHotTris + 3) / 4));
         info->material_bytes = (int64_t)(c->mats.size() * sizeof(float));
+        info->instance_count = (int64_t)(c->bvh.insts.size() / kInstRecord);
+        info->instance_bytes = (int64_t)(c->bvh.insts.size() * sizeof(float4));
         info->depth = c->bvh.depth;
         info->stack_entries = c->bvh.stack_entries;
         info->build_seconds = secs;
@@ -484,6 +527,8 @@ pt_status pt_bind_scene(pt_ctx* c, const pt_scene_buffers* b, void* stream) {
     for (const void* p : ptrs)
         if (!p || (reinterpret_cast<uintptr_t>(p) % kAlign) != 0) return fail(PT_EINVAL, "scene buffers must be non-null and 256-byte aligned");
     if (c->nt > 0 && (!b->albedo || !b->emission)) return fail(PT_EINVAL, "null albedo/emission");
+    if (!c->bvh.insts.empty() && (!b->instances || (reinterpret_cast<uintptr_t>(b->instances) % kAlign) != 0))
+        return fail(PT_EINVAL, "a two-level scene needs a 256-byte aligned instance buffer");
     PT_HIP(hipSetDevice(c->device), "hipSetDevice");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     PT_HIP(hipMemcpyAsync(b->nodes, c->bvh.nodes.data(), c->bvh.nodes.size() * sizeof(Node4), hipMemcpyHostToDevice, s), "upload nodes");
@@ -496,6 +541,10 @@ pt_status pt_bind_scene(pt_ctx* c, const pt_scene_buffers* b, void* stream) {
                               c->bvh.hot_ids.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s),
                "upload hot triangle ids");
     PT_HIP(hipMemcpyAsync(b->materials, c->mats.data(), c->mats.size() * sizeof(float), hipMemcpyHostToDevice, s), "upload materials");
+    if (!c->bvh.insts.empty())
+        PT_HIP(hipMemcpyAsync(b->instances, c->bvh.insts.data(), c->bvh.insts.size() * sizeof(float4),
+                              hipMemcpyHostToDevice, s),
+               "upload instances");
     if (b->upload_params && c->nt > 0) {
         PT_HIP(hipMemcpyAsync(b->albedo, c->albedo.data(), c->albedo.size() * sizeof(float), hipMemcpyHostToDevice, s), "upload albedo");
         PT_HIP(hipMemcpyAsync(b->emission, c->emission.data(), c->emission.size() * sizeof(float), hipMemcpyHostToDevice, s), "upload emission");
@@ -689,6 +738,7 @@ pt_status pt_render_backward(pt_ctx* c, const pt_render_args* a, const float* d_
     pt_status st = check_args(c, a);
     if (st) return st;
     if (a->rr_start >= 0) return fail(PT_EINVAL, "the adjoint needs Russian roulette off (rr_start < 0)");
+    if (c->view.n_inst > 0) return fail(PT_EUNSUPPORTED, "the adjoint takes flat scenes only");
     if (!d_image || !d_albedo || !d_emission) return fail(PT_EINVAL, "null gradient buffer");
     if (!ws) return fail(PT_EINVAL, "null workspace");
     if ((reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return fail(PT_EINVAL, "workspace must be 256-byte aligned");
@@ -843,6 +893,7 @@ pt_status plan_batch(const pt_job* jobs, const std::vector<int>& members, const 
         pt_status st = check_args(jb.ctx, &jb.args);
         if (st) return st;
         if (!jb.image_out) return fail(PT_EINVAL, "null job image");
+        if (jb.ctx->view.n_inst > 0) return fail(PT_EUNSUPPORTED, "the batched launch takes flat scenes only");
         if (P.device < 0) {
             P.device = jb.ctx->device;
             P.num_cu = jb.ctx->num_cu;

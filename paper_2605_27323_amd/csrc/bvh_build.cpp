@@ -11,6 +11,7 @@
 #include <cstring>
 #include <deque>
 #include <future>
+#include <limits>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -49,9 +50,11 @@ class BinaryBuilder {
     BinaryBuilder(const std::vector<PrimInfo>& info, std::vector<int32_t>& order, int max_leaf, int threads)
         : info_(info), order_(order), max_leaf_(max_leaf), budget_(threads > 1 ? threads - 1 : 0) {}
 
-    BNode* build() {
+    BNode* build() { return build(0, (int32_t)order_.size()); }
+    // over order[first, first + count) only
+    BNode* build(int32_t first, int32_t count) {
         arenas_.emplace_back(new Arena());
-        return rec(0, (int32_t)order_.size(), arenas_.back().get());
+        return rec(first, count, arenas_.back().get());
     }
 
    private:
@@ -444,6 +447,218 @@ BuildResult build_scene(const std::vector<float>& tri_v, const std::vector<int32
             r.lights[j].cdf = w;
             r.lights[j].id = ids[j];
             r.lights[j].pad = 0u;
+        }
+    }
+    return r;
+}
+
+void xform_tri(const float* M, const float* v, float* out) {
+    for (int k = 0; k < 3; ++k) {
+        const float x = v[3 * k], y = v[3 * k + 1], z = v[3 * k + 2];
+        for (int r = 0; r < 3; ++r) out[3 * k + r] = ((M[4 * r] * x + M[4 * r + 1] * y) + M[4 * r + 2] * z) + M[4 * r + 3];
+    }
+}
+
+namespace {
+
+// A binary subtree collapsed into nodes[idx] (and nodes appended for its
+// internal children); a single leaf is wrapped in a node with one child.
+// Returns the depth in BVH4 levels.
+int emit_tree(std::vector<Node4>& nodes, uint32_t idx, BNode* root, float pad) {
+    Collapser col{nodes, pad};
+    if (Collapser::is_leaf(root)) {
+        float lo[4][3] = {}, hi[4][3] = {};
+        const uint32_t ref[4] = {root->count > 0 ? Collapser::leaf_ref(root) : kEmptyRef, kEmptyRef, kEmptyRef,
+                                 kEmptyRef};
+        if (root->count > 0) col.child_box(root, lo[0], hi[0]);
+        quantize_node(nodes[idx], lo, hi, ref);
+        return 1;
+    }
+    col.emit(idx, root, 1);
+    return col.depth;
+}
+
+double tri_area(const float* p) {
+    double ax = (double)p[3] - (double)p[0], ay = (double)p[4] - (double)p[1], az = (double)p[5] - (double)p[2];
+    double bx = (double)p[6] - (double)p[0], by = (double)p[7] - (double)p[1], bz = (double)p[8] - (double)p[2];
+    double cx = ay * bz - az * by, cy = az * bx - ax * bz, cz = ax * by - ay * bx;
+    return 0.5 * std::sqrt(cx * cx + cy * cy + cz * cz);
+}
+
+}  // namespace
+
+BuildResult build_instanced(const std::vector<float>& tri_v, const std::vector<int32_t>& tri_mat,
+                            const std::vector<float>& emission, const InstanceSet& is, int max_leaf, int threads) {
+    BuildResult r;
+    const int32_t nt = (int32_t)tri_mat.size();
+    const int nmesh = (int)is.mesh_first.size(), ninst = (int)is.inst_mesh.size();
+    max_leaf = std::max(1, std::min(kMaxLeaf, max_leaf));
+    if (threads <= 0) threads = (int)std::max(1u, std::thread::hardware_concurrency());
+
+    std::vector<PrimInfo> info(nt);
+    for (int32_t i = 0; i < nt; ++i) {
+        const float* p = &tri_v[9 * (size_t)i];
+        for (int a = 0; a < 3; ++a) {
+            float lo = std::min(p[a], std::min(p[3 + a], p[6 + a]));
+            float hi = std::max(p[a], std::max(p[3 + a], p[6 + a]));
+            info[i].lo[a] = lo;
+            info[i].hi[a] = hi;
+            info[i].c[a] = 0.5f * (lo + hi);
+        }
+    }
+    // leaf order: each mesh's triangles reordered within its own range
+    std::vector<int32_t> order(nt);
+    for (int32_t i = 0; i < nt; ++i) order[i] = i;
+    r.nodes.emplace_back();  // node 0: the top-level root
+    std::vector<uint32_t> mesh_root(nmesh, kEmptyRef);
+    std::vector<double> mlo(3 * (size_t)nmesh), mhi(3 * (size_t)nmesh);
+    int blas_depth = 0;
+    for (int m = 0; m < nmesh; ++m) {
+        const int32_t first = is.mesh_first[m], count = is.mesh_count[m];
+        if (count == 0) continue;
+        // object-space boxes padded by 2^-18 of the mesh's largest coordinate
+        // (the flat scene's rule, per mesh)
+        float M = 0.f;
+        for (int32_t i = first; i < first + count; ++i)
+            for (int a = 0; a < 3; ++a) M = std::max(M, std::max(std::fabs(info[i].lo[a]), std::fabs(info[i].hi[a])));
+        const float pad = M * 0x1p-18f;
+        BinaryBuilder bb(info, order, max_leaf, threads);
+        BNode* root = bb.build(first, count);
+        const uint32_t idx = (uint32_t)r.nodes.size();
+        r.nodes.emplace_back();
+        blas_depth = std::max(blas_depth, emit_tree(r.nodes, idx, root, pad));
+        mesh_root[m] = idx;
+        for (int a = 0; a < 3; ++a) {
+            mlo[3 * m + a] = (double)std::nextafter(root->lo[a] - pad, -INFINITY);
+            mhi[3 * m + a] = (double)std::nextafter(root->hi[a] + pad, INFINITY);
+        }
+    }
+    // top level over the world boxes of the instances of non-empty meshes:
+    // the eight corners of the mesh's padded box mapped by o2w in binary64,
+    // then widened by 2^-12 of (extent + largest coordinate magnitude), which
+    // covers the difference between the world ray and the rounded
+    // object-space ray of an instance (a few ulps of the coordinates times
+    // the transform's condition number) for rays within a few hundred scene
+    // sizes
+    std::vector<PrimInfo> iinfo(ninst);
+    std::vector<int32_t> iorder;
+    constexpr double kInf = std::numeric_limits<double>::infinity();
+    double wlo[3] = {kInf, kInf, kInf}, whi[3] = {-kInf, -kInf, -kInf};
+    for (int q = 0; q < ninst; ++q) {
+        const int m = is.inst_mesh[q];
+        if (mesh_root[m] == kEmptyRef) continue;
+        const float* M = &is.o2w[12 * (size_t)q];
+        double lo[3] = {kInf, kInf, kInf}, hi[3] = {-kInf, -kInf, -kInf};
+        for (int c = 0; c < 8; ++c) {
+            const double p[3] = {(c & 1) ? mhi[3 * m] : mlo[3 * m], (c & 2) ? mhi[3 * m + 1] : mlo[3 * m + 1],
+                                 (c & 4) ? mhi[3 * m + 2] : mlo[3 * m + 2]};
+            for (int a = 0; a < 3; ++a) {
+                const double w = (double)M[4 * a] * p[0] + (double)M[4 * a + 1] * p[1] + (double)M[4 * a + 2] * p[2] +
+                                 (double)M[4 * a + 3];
+                lo[a] = std::min(lo[a], w);
+                hi[a] = std::max(hi[a], w);
+            }
+        }
+        double ext = 0.0, mag = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            ext = std::max(ext, hi[a] - lo[a]);
+            mag = std::max(mag, std::max(std::fabs(lo[a]), std::fabs(hi[a])));
+        }
+        const double pad = std::ldexp(ext + mag, -12);
+        for (int a = 0; a < 3; ++a) {
+            iinfo[q].lo[a] = std::nextafter((float)(lo[a] - pad), -INFINITY);
+            iinfo[q].hi[a] = std::nextafter((float)(hi[a] + pad), INFINITY);
+            iinfo[q].c[a] = 0.5f * (iinfo[q].lo[a] + iinfo[q].hi[a]);
+            wlo[a] = std::min(wlo[a], (double)iinfo[q].lo[a]);
+            whi[a] = std::max(whi[a], (double)iinfo[q].hi[a]);
+        }
+        iorder.push_back(q);
+    }
+    int tlas_depth = 1;
+    if (iorder.empty()) {
+        const float lo[4][3] = {}, hi[4][3] = {};
+        const uint32_t ref[4] = {kEmptyRef, kEmptyRef, kEmptyRef, kEmptyRef};
+        quantize_node(r.nodes[0], lo, hi, ref);
+    } else {
+        BinaryBuilder tb(iinfo, iorder, 1, threads);
+        BNode* root = tb.build();
+        tlas_depth = emit_tree(r.nodes, 0, root, 0.f);
+        for (int a = 0; a < 3; ++a) {
+            r.center[a] = (float)(0.5 * (wlo[a] + whi[a]));
+            r.max_coord = std::max(r.max_coord, (float)std::max(std::fabs(wlo[a]), std::fabs(whi[a])));
+        }
+    }
+    r.depth = tlas_depth + blas_depth;
+    // top-level entries, the return marker, then the mesh's entries
+    r.stack_entries = 3 * (tlas_depth + blas_depth) + 2;
+
+    // instance records in top-level leaf order
+    std::vector<uint32_t> rec_of(ninst, 0xFFFFFFFFu);
+    r.insts.resize((size_t)kInstRecord * iorder.size());
+    for (size_t pos = 0; pos < iorder.size(); ++pos) {
+        const int q = iorder[pos];
+        rec_of[q] = (uint32_t)pos;
+        float4* rec = &r.insts[(size_t)kInstRecord * pos];
+        const float* W = &is.w2o[12 * (size_t)q];
+        const float* O = &is.o2w[12 * (size_t)q];
+        for (int row = 0; row < 3; ++row) {
+            rec[row] = make_float4(W[4 * row], W[4 * row + 1], W[4 * row + 2], W[4 * row + 3]);
+            rec[3 + row] = make_float4(O[4 * row], O[4 * row + 1], O[4 * row + 2], O[4 * row + 3]);
+        }
+        const uint32_t root = mesh_root[is.inst_mesh[q]], qq = (uint32_t)q;
+        float froot, fq;
+        std::memcpy(&froot, &root, 4);
+        std::memcpy(&fq, &qq, 4);
+        rec[6] = make_float4(froot, fq, 0.f, 0.f);
+    }
+
+    // triangles in leaf order
+    std::vector<uint8_t> is_light(nt);
+    for (int32_t i = 0; i < nt; ++i) {
+        const float* e = &emission[3 * (size_t)i];
+        is_light[i] = (e[0] > 0.f || e[1] > 0.f || e[2] > 0.f);
+    }
+    r.tris.resize(3 * (size_t)nt);
+    std::vector<uint32_t> leaf_pos(nt);
+    for (int32_t j = 0; j < nt; ++j) {
+        const int32_t t = order[j];
+        leaf_pos[t] = (uint32_t)j;
+        const float* p = &tri_v[9 * (size_t)t];
+        const uint32_t id = (uint32_t)t, mi = (uint32_t)tri_mat[t] | (is_light[t] ? kLightFlag : 0u);
+        float fid, fmi;
+        std::memcpy(&fid, &id, 4);
+        std::memcpy(&fmi, &mi, 4);
+        r.tris[3 * (size_t)j + 0] = make_float4(p[0], p[1], p[2], fid);
+        r.tris[3 * (size_t)j + 1] = make_float4(p[3], p[4], p[5], fmi);
+        r.tris[3 * (size_t)j + 2] = make_float4(p[6], p[7], p[8], 0.f);
+    }
+
+    // lights: every (instance, emissive triangle) in instance order, areas of
+    // the world-space triangles in binary64
+    std::vector<double> cum;
+    std::vector<LightEntry> ent;
+    double acc = 0.0;
+    for (int q = 0; q < ninst; ++q) {
+        const int m = is.inst_mesh[q];
+        for (int32_t i = is.mesh_first[m]; i < is.mesh_first[m] + is.mesh_count[m]; ++i) {
+            if (!is_light[i]) continue;
+            float w[9];
+            xform_tri(&is.o2w[12 * (size_t)q], &tri_v[9 * (size_t)i], w);
+            acc += tri_area(w);
+            cum.push_back(acc);
+            ent.push_back(LightEntry{leaf_pos[i], 0u, (uint32_t)i, rec_of[q]});
+        }
+    }
+    r.area_total = (float)acc;
+    if (acc > 0.0) {
+        r.lights = ent;
+        for (size_t j = 0; j < ent.size(); ++j) {
+            if (j + 1 == ent.size()) {
+                r.lights[j].cdf = 0xFFFFFFFFu;
+            } else {
+                double q = std::floor(cum[j] / acc * 4294967296.0);
+                r.lights[j].cdf = q > 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)q;
+            }
         }
     }
     return r;

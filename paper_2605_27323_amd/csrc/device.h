@@ -398,6 +398,8 @@ struct Hit {
     float det;
     uint32_t tri;   // leaf-order index, ~0u on a miss
     uint32_t id;    // input id (tie-break)
+    uint32_t inst;  // two-level scenes: instance record of the hit
+    uint32_t iid;   // and its input index (tie-break before id)
 };
 
 PT_DEV void hit_finish(Hit& h) {
@@ -670,6 +672,255 @@ PT_DEV bool any_hit(const SceneView& sc, const Ray& r, float tmax, TravStack<LDS
     while (any_step<LDS>(sc, r, tmax, ref, st, occluded)) {
     }
     return occluded;
+}
+
+// ---------------------------------------------------------------------------
+// two-level traversal (paper Sec. 2.3 and 3: a top-level structure over
+// instances of per-mesh bottom-level structures)
+// ---------------------------------------------------------------------------
+// Affine map by a 3x4 matrix given as three float4 rows (linear part xyz,
+// translation w): ((r.x x + r.y y) + r.z z) + r.w per row; directions drop
+// the translation.
+PT_DEV f3 xform_point(float4 r0, float4 r1, float4 r2, f3 p) {
+    return mk3(((r0.x * p.x + r0.y * p.y) + r0.z * p.z) + r0.w, ((r1.x * p.x + r1.y * p.y) + r1.z * p.z) + r1.w,
+               ((r2.x * p.x + r2.y * p.y) + r2.z * p.z) + r2.w);
+}
+PT_DEV f3 xform_dir(float4 r0, float4 r1, float4 r2, f3 d) {
+    return mk3((r0.x * d.x + r0.y * d.y) + r0.z * d.z, (r1.x * d.x + r1.y * d.y) + r1.z * d.z,
+               (r2.x * d.x + r2.y * d.y) + r2.z * d.z);
+}
+
+// The ray of a two-level traversal.  At a top-level leaf the active Ray
+// becomes the instance's object-space ray (origin and direction mapped by
+// its world-to-object rows, not renormalised, so a point at parameter t is
+// the image of the world ray's point at t and distances stay comparable
+// across instances) and a marker entry is pushed; popping the marker
+// restores the world ray kept here.
+struct InstTrav {
+    f3 o, d;       // the world ray
+    uint32_t rec;  // instance record while inside a mesh
+    uint32_t iid;  // its input index
+    bool obj;      // inside a mesh
+};
+
+PT_DEV void inst_begin(f3 o, f3 d, InstTrav& it) {
+    it.o = o;
+    it.d = d;
+    it.rec = 0u;
+    it.iid = 0u;
+    it.obj = false;
+}
+
+// Enter the instance of top-level leaf `ref`: object-space ray, marker, the
+// mesh's root as the next reference.  False for a reference outside the
+// instance records.
+template <int LDS, bool COUNT>
+PT_DEV bool inst_enter(const SceneView& sc, Ray& r, InstTrav& it, uint32_t& ref, TravStack<LDS, COUNT>& st) {
+    const uint32_t rec = ref & kLeafFirstMask;
+    if (rec >= (uint32_t)sc.n_inst) return false;
+    const float4* ip = sc.insts + (size_t)rec * kInstRecord;
+    const float4 w0 = ip[0], w1 = ip[1], w2 = ip[2], meta = ip[6];
+    r = make_ray(xform_point(w0, w1, w2, it.o), xform_dir(w0, w1, w2, it.d));
+    it.obj = true;
+    it.rec = rec;
+    it.iid = f2u(meta.y);
+    st.push(kInstMarker, 0.0f);
+    ref = f2u(meta.x);
+    return true;
+}
+
+// closest_step over a two-level scene; closest-hit key (t, input instance,
+// input triangle)
+template <int LDS, bool COUNT = false>
+PT_DEV bool closest_step_inst(const SceneView& sc, Ray& r, InstTrav& it, float tmax, Hit& h, uint32_t& ref,
+                              TravStack<LDS, COUNT>& st) {
+    if (!(ref & kLeafBit)) {
+        if (ref < (uint32_t)sc.n_nodes) {
+            if constexpr (COUNT) ++st.nodes;
+            float4 q[5];
+            load_node(sc.nodes, ref, q);
+            float tn[4];
+            unsigned m = slab4_q(r, q, h.t, tn);
+            if (m) {
+                uint32_t rr[4];
+                float tt[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    bool hit = (m >> c) & 1u;
+                    const float cref = c == 0 ? q[4].x : (c == 1 ? q[4].y : (c == 2 ? q[4].z : q[4].w));
+                    rr[c] = hit ? f2u(cref) : kEmptyRef;
+                    tt[c] = hit ? tn[c] : INFINITY;
+                }
+                sort4(rr, tt);
+                st.push3(make_uint2(rr[3], f2u(tt[3])), rr[3] != kEmptyRef, make_uint2(rr[2], f2u(tt[2])),
+                         rr[2] != kEmptyRef, make_uint2(rr[1], f2u(tt[1])), rr[1] != kEmptyRef);
+                ref = rr[0];
+                return true;
+            }
+        }
+    } else if (!it.obj) {
+        if (inst_enter<LDS, COUNT>(sc, r, it, ref, st)) return true;
+    } else {
+        uint32_t first = ref & kLeafFirstMask;
+        uint32_t cnt = ((ref >> kLeafCountShift) & 15u) + 1u;
+        if (first + cnt <= (uint32_t)sc.nt) {
+            if constexpr (COUNT) st.tris += cnt;
+            for (uint32_t i = first; i < first + cnt; ++i) {
+                const float4* tp = sc.tris + (size_t)i * 3;
+                float4 a = tp[0], b = tp[1], c = tp[2];
+                float t, vn, wn, dn;
+                if (tri_test(r, xyz(a), xyz(b), xyz(c), t, vn, wn, dn) && t < tmax) {
+                    uint32_t id = f2u(a.w);
+                    if (t < h.t || (t == h.t && (it.iid < h.iid || (it.iid == h.iid && id < h.id)))) {
+                        h.t = t;
+                        h.b1 = vn;
+                        h.b2 = wn;
+                        h.det = dn;
+                        h.tri = i;
+                        h.id = id;
+                        h.inst = it.rec;
+                        h.iid = it.iid;
+                    }
+                }
+            }
+        }
+    }
+    while (st.sp > 0) {
+        float t;
+        st.pop(ref, t);
+        if (ref == kInstMarker) {
+            r = make_ray(it.o, it.d);
+            it.obj = false;
+            continue;
+        }
+        if (t <= h.t * kBoxSlack) return true;
+    }
+    return false;
+}
+
+template <int LDS, bool COUNT = false>
+PT_DEV void closest_begin_inst(f3 o, f3 d, float tmax, Ray& r, InstTrav& it, Hit& h, uint32_t& ref,
+                               TravStack<LDS, COUNT>& st) {
+    closest_begin<LDS>(tmax, h, ref, st);
+    h.inst = 0u;
+    h.iid = 0xFFFFFFFFu;
+    inst_begin(o, d, it);
+    r = make_ray(o, d);
+}
+
+// any_step over a two-level scene
+template <int LDS, bool COUNT = false>
+PT_DEV bool any_step_inst(const SceneView& sc, Ray& r, InstTrav& it, float tmax, uint32_t& ref,
+                          TravStack<LDS, COUNT>& st, bool& occluded) {
+    if (!(ref & kLeafBit)) {
+        if (ref < (uint32_t)sc.n_nodes) {
+            if constexpr (COUNT) ++st.nodes;
+            float4 q[5];
+            load_node(sc.nodes, ref, q);
+            float tn[4];
+            unsigned m = slab4_q(r, q, tmax, tn);
+            if (m) {
+                const uint32_t cr[4] = {f2u(q[4].x), f2u(q[4].y), f2u(q[4].z), f2u(q[4].w)};
+                const uint32_t last = 31u - (uint32_t)__builtin_clz(m);
+                st.push3(make_uint2(cr[0], f2u(tn[0])), (m & 1u) && last > 0u, make_uint2(cr[1], f2u(tn[1])),
+                         ((m >> 1) & 1u) && last > 1u, make_uint2(cr[2], f2u(tn[2])), ((m >> 2) & 1u) && last > 2u);
+                ref = last == 0u ? cr[0] : (last == 1u ? cr[1] : (last == 2u ? cr[2] : cr[3]));
+                return true;
+            }
+        }
+    } else if (!it.obj) {
+        if (inst_enter<LDS, COUNT>(sc, r, it, ref, st)) return true;
+    } else {
+        uint32_t first = ref & kLeafFirstMask;
+        uint32_t cnt = ((ref >> kLeafCountShift) & 15u) + 1u;
+        if (first + cnt <= (uint32_t)sc.nt) {
+            for (uint32_t i = first; i < first + cnt; ++i) {
+                if constexpr (COUNT) ++st.tris;
+                const float4* tp = sc.tris + (size_t)i * 3;
+                float4 a = tp[0], b = tp[1], c = tp[2];
+                float t, vn, wn, dn;
+                if (tri_test(r, xyz(a), xyz(b), xyz(c), t, vn, wn, dn) && t < tmax) {
+                    occluded = true;
+                    return false;
+                }
+            }
+        }
+    }
+    while (st.sp > 0) {
+        float t;
+        st.pop(ref, t);
+        if (ref == kInstMarker) {
+            r = make_ray(it.o, it.d);
+            it.obj = false;
+            continue;
+        }
+        return true;
+    }
+    return false;
+}
+
+// Closest hit and any hit in (0, tmax) of the world ray (o, d): the flat
+// traversal, or with INST the two-level one
+template <int LDS, bool COUNT = false, bool INST = false>
+PT_DEV Hit closest_hit_t(const SceneView& sc, f3 o, f3 d, float tmax, TravStack<LDS, COUNT>& st) {
+    if constexpr (INST) {
+        Hit h;
+        Ray r;
+        InstTrav it;
+        uint32_t ref;
+        closest_begin_inst<LDS>(o, d, tmax, r, it, h, ref, st);
+        while (closest_step_inst<LDS>(sc, r, it, tmax, h, ref, st)) {
+        }
+        hit_finish(h);
+        return h;
+    } else {
+        return closest_hit<LDS>(sc, make_ray(o, d), tmax, st);
+    }
+}
+template <int LDS, bool COUNT = false, bool INST = false>
+PT_DEV bool any_hit_t(const SceneView& sc, f3 o, f3 d, float tmax, TravStack<LDS, COUNT>& st) {
+    if constexpr (INST) {
+        Ray r = make_ray(o, d);
+        InstTrav it;
+        inst_begin(o, d, it);
+        uint32_t ref;
+        any_begin<LDS>(ref, st);
+        bool occluded = false;
+        while (any_step_inst<LDS>(sc, r, it, tmax, ref, st, occluded)) {
+        }
+        return occluded;
+    } else {
+        return any_hit<LDS>(sc, make_ray(o, d), tmax, st);
+    }
+}
+
+// World-space vertices of the hit triangle: the record's vertices, mapped by
+// the object-to-world rows of instance record `rec` in a two-level scene
+PT_DEV void inst_vertices(const SceneView& sc, uint32_t rec, float4& a, float4& b, float4& c) {
+    const float4* ip = sc.insts + (size_t)rec * kInstRecord;
+    const float4 o0 = ip[3], o1 = ip[4], o2 = ip[5];
+    const f3 wa = xform_point(o0, o1, o2, xyz(a)), wb = xform_point(o0, o1, o2, xyz(b)),
+             wc = xform_point(o0, o1, o2, xyz(c));
+    a = make_float4(wa.x, wa.y, wa.z, a.w);
+    b = make_float4(wb.x, wb.y, wb.z, b.w);
+    c = make_float4(wc.x, wc.y, wc.z, c.w);
+}
+
+// hit_barycentrics in a two-level scene: the same test in the object space
+// of the hit's instance record h.inst, with the object-space ray of the
+// traversal
+PT_DEV void hit_barycentrics_inst(const SceneView& sc, f3 o, f3 d, Hit& h) {
+    h.b1 = 0.0f;
+    h.b2 = 0.0f;
+    if (h.tri >= (uint32_t)sc.nt || h.inst >= (uint32_t)sc.n_inst) return;
+    const float4* ip = sc.insts + (size_t)h.inst * kInstRecord;
+    const float4 w0 = ip[0], w1 = ip[1], w2 = ip[2];
+    Ray r;
+    r.o = xform_point(w0, w1, w2, o);
+    set_shear(r, xform_dir(w0, w1, w2, d));
+    const float4* tp = sc.tris + (size_t)h.tri * 3;
+    float t;
+    tri_intersect(r, xyz(tp[0]), xyz(tp[1]), xyz(tp[2]), t, h.b1, h.b2);
 }
 
 // ---------------------------------------------------------------------------
@@ -985,6 +1236,11 @@ PT_DEV f3 load3(const float* __restrict__ p, uint32_t i) {
 // them is waited for; only the per-triangle albedo, emission and material
 // wait for the hit triangle.  Values fetched this way are used under the
 // same conditions as before, so the arithmetic is unchanged.
+//
+// INST (two-level scene): the hit triangle's vertices are mapped to world
+// space by its instance record's object-to-world rows, and so are the
+// sampled light's (its instance record is the light table's last word).
+template <bool INST = false>
 PT_DEV VertexOut shade_vertex(const SceneView& sc, const PathParams& pp, uint32_t pixel, uint32_t sample, int k,
                               f3 rd, const Hit& h, PathState& ps, ShadowReq& sh,
                               const LightCache& lc = no_light_cache()) {
@@ -1002,7 +1258,8 @@ PT_DEV VertexOut shade_vertex(const SceneView& sc, const PathParams& pp, uint32_
         return out;
     }
     const float4* tp = sc.tris + (size_t)h.tri * 3;
-    const float4 ta = tp[0], tb = tp[1], tc = tp[2];
+    float4 ta = tp[0], tb = tp[1], tc = tp[2];
+    if constexpr (INST) inst_vertices(sc, h.inst, ta, tb, tc);
     const bool more = k != pp.D + 1;
     Rng8 rn;
     float4 la, lb4, lc4;
@@ -1020,6 +1277,7 @@ PT_DEV VertexOut shade_vertex(const SceneView& sc, const PathParams& pp, uint32_
         lb4 = lp[1];
         lc4 = lp[2];
         Le_l = load3(sc.emission, lid);
+        if constexpr (INST) inst_vertices(sc, sc.lights[j].pad, la, lb4, lc4);
     }
     f3 v0 = xyz(ta), v1 = xyz(tb), v2 = xyz(tc);
     uint32_t id = f2u(ta.w);
@@ -1139,20 +1397,18 @@ PT_DEV void path_begin(const CamView& cam, const PathParams& pp, uint32_t pix, u
     pr.k = 1;
 }
 
-template <int LDS, bool COUNT = false>
+template <int LDS, bool COUNT = false, bool INST = false>
 PT_DEV bool path_vertex(const SceneView& sc, const PathParams& pp, uint32_t pix, uint32_t sample, PathRun& pr,
                         TravStack<LDS, COUNT>& st, uint32_t& n_ext, uint32_t& n_sh,
                         const LightCache& lc = no_light_cache()) {
-    Ray ray = make_ray(pr.o, pr.d);
-    Hit h = closest_hit<LDS>(sc, ray, INFINITY, st);
+    Hit h = closest_hit_t<LDS, COUNT, INST>(sc, pr.o, pr.d, INFINITY, st);
     ++n_ext;
     ShadowReq sh;
-    VertexOut vo = shade_vertex(sc, pp, pix, sample, pr.k, pr.d, h, pr.ps, sh, lc);
+    VertexOut vo = shade_vertex<INST>(sc, pp, pix, sample, pr.k, pr.d, h, pr.ps, sh, lc);
     add_radiance(pr.ps, vo);
     if (sh.valid) {
         ++n_sh;
-        Ray sr = make_ray(sh.o, sh.d);
-        if (!any_hit<LDS>(sc, sr, kShadowTmax, st))
+        if (!any_hit_t<LDS, COUNT, INST>(sc, sh.o, sh.d, kShadowTmax, st))
             pr.ps.L = mk3(pr.ps.L.x + sh.contrib.x, pr.ps.L.y + sh.contrib.y, pr.ps.L.z + sh.contrib.z);
     }
     if (!vo.cont) return false;
@@ -1163,12 +1419,12 @@ PT_DEV bool path_vertex(const SceneView& sc, const PathParams& pp, uint32_t pix,
 }
 
 // One complete camera path: its radiance.
-template <int LDS, bool COUNT = false>
+template <int LDS, bool COUNT = false, bool INST = false>
 PT_DEV f3 trace_path(const SceneView& sc, const CamView& cam, const PathParams& pp, uint32_t pix, uint32_t sample,
                      TravStack<LDS, COUNT>& st, uint32_t& n_ext, uint32_t& n_sh, const LightCache& lc = no_light_cache()) {
     PathRun pr;
     path_begin(cam, pp, pix, sample, pr);
-    while (path_vertex<LDS>(sc, pp, pix, sample, pr, st, n_ext, n_sh, lc)) {
+    while (path_vertex<LDS, COUNT, INST>(sc, pp, pix, sample, pr, st, n_ext, n_sh, lc)) {
     }
     return pr.ps.L;
 }

@@ -46,7 +46,7 @@ constexpr uint32_t kMegaChunk = 64u;
 
 // four waves per SIMD instead of the three the register count would give:
 // a few spilled registers cost less than the lost latency hiding
-template <int LDS, bool COUNT, int WAVES>
+template <int LDS, bool COUNT, int WAVES, bool INST>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) k_mega(SceneView sc, CamView cam, PathParams pp, float* __restrict__ img,
                                               float* __restrict__ acc, uint2* __restrict__ ovf, int gcap,
                                               uint32_t* __restrict__ stats, unsigned long long* __restrict__ trav,
@@ -121,7 +121,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES)
             path_begin(cam, pp, pix, sample, pr);
             started = true;
         }
-        if (path_vertex<LDS>(sc, pp, pix, sample, pr, st, n_ext, n_sh, lc)) continue;
+        if (path_vertex<LDS, COUNT, INST>(sc, pp, pix, sample, pr, st, n_ext, n_sh, lc)) continue;
         started = false;
         sum = s == 0 ? pr.ps.L : add3(sum, pr.ps.L);
         if (++s == (uint32_t)pp.spp) {
@@ -160,7 +160,7 @@ __global__ void k_init_counts(uint32_t* __restrict__ counts, int n, uint32_t fir
 // Limited to 128 VGPRs (4 waves per SIMD, a few spilled registers): at 148
 // it ran 3 waves per SIMD and kept the next frame's stage kernels off the
 // compute units while it finished the last bounces.
-template <int LDS, bool COUNT>
+template <int LDS, bool COUNT, bool INST>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_shade_tail(SceneView sc, PathParams pp, WaveBufs wb, int b, int sorted,
                                                     uint32_t tail, uint2* __restrict__ ovf, int gcap,
                                                     uint32_t spread) {
@@ -188,8 +188,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         VertexOut vo;
         ShadowReq sh;
         PathState ps;
-        const uint32_t path = shade_item(sc, pp, wb, b, i, vo, sh, ps, perm, lc, true);
-        finish_path<LDS>(sc, pp, wb, path, b + 1, vo, sh, ps, st, n_ext, n_sh, lc);
+        const uint32_t path = shade_item<INST>(sc, pp, wb, b, i, vo, sh, ps, perm, lc, true);
+        finish_path<LDS, COUNT, INST>(sc, pp, wb, path, b + 1, vo, sh, ps, st, n_ext, n_sh, lc);
     }
     // every lane of the wave is here: reduce the ray counts across it
     for (int off = 32; off > 0; off >>= 1) {
@@ -220,7 +220,7 @@ __global__ void __launch_bounds__(256) k_raygen(CamView cam, PathParams pp, Wave
 // when at least `refill` of them are idle (or all are); the chunk cursor is
 // wave-uniform, so no atomics are needed.
 
-template <int LDS, bool COUNT>
+template <int LDS, bool COUNT, bool INST>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k_extend(SceneView sc, WaveBufs wb, int b, uint2* __restrict__ ovf, int gcap,
                                                 uint32_t refill, int sorted, int xcd_local) {
     extern __shared__ __align__(8) uint32_t smem[];
@@ -236,6 +236,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
     uint32_t item = 0, ref = 0;
     Ray ray;
     Hit h;
+    InstTrav it;
     while (true) {
         const uint64_t idle = __ballot(!live);
         const uint32_t nidle = (uint32_t)__popcll(idle);
@@ -247,8 +248,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
                     const float4 o4 = wb.ray_o[cur][i];
                     if (f2u(o4.w) != kDeadPath) {  // dead slots (no compaction) need no hit
                         const float4 d4 = wb.ray_d[cur][i];
-                        ray = make_ray(xyz(o4), xyz(d4));
-                        closest_begin<LDS>(INFINITY, h, ref, st);
+                        if constexpr (INST) {
+                            closest_begin_inst<LDS>(xyz(o4), xyz(d4), INFINITY, ray, it, h, ref, st);
+                        } else {
+                            ray = make_ray(xyz(o4), xyz(d4));
+                            closest_begin<LDS>(INFINITY, h, ref, st);
+                        }
                         item = i;
                         live = true;
                     }
@@ -260,9 +265,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
             if (next < end) continue;
             break;
         }
-        if (live && !closest_step<LDS>(sc, ray, INFINITY, h, ref, st)) {
-            wb.hit[item] = make_float4(h.t, 0.f, 0.f, u2f(h.tri));
-            live = false;
+        if constexpr (INST) {
+            if (live && !closest_step_inst<LDS>(sc, ray, it, INFINITY, h, ref, st)) {
+                wb.hit[item] = make_float4(h.t, u2f(h.inst), 0.f, u2f(h.tri));
+                live = false;
+            }
+        } else {
+            if (live && !closest_step<LDS>(sc, ray, INFINITY, h, ref, st)) {
+                wb.hit[item] = make_float4(h.t, 0.f, 0.f, u2f(h.tri));
+                live = false;
+            }
         }
     }
     if constexpr (COUNT) {
@@ -272,6 +284,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
     if (st.overflow) atomicOr(&wb.counts[wb.err_slot], 1u);
 }
 
+template <bool INST>
 __global__ void __launch_bounds__(256) k_shade(SceneView sc, PathParams pp, WaveBufs wb, int b, int compact,
                                                int sorted, uint32_t tail) {
     const uint32_t nlanes = gridDim.x * blockDim.x;
@@ -301,7 +314,7 @@ __global__ void __launch_bounds__(256) k_shade(SceneView sc, PathParams pp, Wave
         vo.cont = false;
         sh.valid = false;
         uint32_t path = kDeadPath;
-        if (i < count) path = shade_item(sc, pp, wb, b, i, vo, sh, ps, perm, lc);
+        if (i < count) path = shade_item<INST>(sc, pp, wb, b, i, vo, sh, ps, perm, lc);
         const uint64_t mk = compact ? __ballot(vo.cont) : 0ull;
         const uint64_t ms = __ballot(sh.valid);
         uint32_t jc, js;
@@ -317,7 +330,7 @@ __global__ void __launch_bounds__(256) k_shade(SceneView sc, PathParams pp, Wave
     }
 }
 
-template <int LDS, bool COUNT>
+template <int LDS, bool COUNT, bool INST>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k_shadow(SceneView sc, WaveBufs wb, int b, uint2* __restrict__ ovf, int gcap,
                                                 uint32_t refill, int xcd_local) {
     extern __shared__ __align__(8) uint32_t smem[];
@@ -329,6 +342,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
     bool live = false;
     uint32_t item = 0, ref = 0;
     Ray ray;
+    InstTrav it;
     while (true) {
         const uint64_t idle = __ballot(!live);
         const uint32_t nidle = (uint32_t)__popcll(idle);
@@ -337,6 +351,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
                 const uint32_t i = next + rank_in(idle);
                 if (i < end) {
                     ray = make_ray(xyz(wb.sh_o[i]), xyz(wb.sh_d[i]));
+                    if constexpr (INST) inst_begin(ray.o, ray.d, it);
                     any_begin<LDS>(ref, st);
                     item = i;
                     live = true;
@@ -350,7 +365,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
         }
         if (live) {
             bool occluded = false;
-            if (!any_step<LDS>(sc, ray, kShadowTmax, ref, st, occluded)) {
+            bool more;
+            if constexpr (INST) more = any_step_inst<LDS>(sc, ray, it, kShadowTmax, ref, st, occluded);
+            else more = any_step<LDS>(sc, ray, kShadowTmax, ref, st, occluded);
+            if (!more) {
                 live = false;
                 if (!occluded) shadow_add(wb, item);
             }
@@ -454,7 +472,12 @@ __global__ void __launch_bounds__(256) k_accumulate(CamView cam, PathParams pp, 
 // instantiate a traversal kernel for the LDS stack depth and the work-counting flag
 #define PT_DISPATCH(N, launch) \
     if (lds == N) {            \
-        if (count) launch(N, true) else launch(N, false) return hipGetLastError(); \
+        if (sc.n_inst > 0) {   \
+            if (count) launch(N, true, true) else launch(N, false, true)   \
+        } else {               \
+            if (count) launch(N, true, false) else launch(N, false, false) \
+        }                      \
+        return hipGetLastError(); \
     }
 
 static size_t stack_lds_bytes(int lds, int block) { return trav_stack_lds_bytes(lds, block); }
@@ -463,12 +486,12 @@ hipError_t launch_mega(int lds, bool count, int waves, dim3 grid, dim3 block, hi
                        const CamView& cam, const PathParams& pp, float* img, float* acc, uint2* ovf, int gcap,
                        uint32_t* stats, unsigned long long* trav, int xcd_local) {
     size_t sm = stack_lds_bytes(lds, block.x);
-#define L(N, C)                                                                                                      \
+#define L(N, C, I)                                                                                                   \
     if (waves == 5)                                                                                                  \
-        hipLaunchKernelGGL((k_mega<N, C, 5>), grid, block, sm, s, sc, cam, pp, img, acc, ovf, gcap, stats, trav,     \
+        hipLaunchKernelGGL((k_mega<N, C, 5, I>), grid, block, sm, s, sc, cam, pp, img, acc, ovf, gcap, stats, trav,  \
                            xcd_local);                                                                               \
     else                                                                                                             \
-        hipLaunchKernelGGL((k_mega<N, C, 4>), grid, block, sm, s, sc, cam, pp, img, acc, ovf, gcap, stats, trav,     \
+        hipLaunchKernelGGL((k_mega<N, C, 4, I>), grid, block, sm, s, sc, cam, pp, img, acc, ovf, gcap, stats, trav,  \
                            xcd_local);
 #define X(N) PT_DISPATCH(N, L)
     PT_STACK_CASES(X)
@@ -491,7 +514,7 @@ hipError_t launch_raygen(dim3 grid, dim3 block, hipStream_t s, const CamView& ca
 hipError_t launch_extend(int lds, bool count, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
                          const WaveBufs& wb, int b, uint2* ovf, int gcap, int sorted, int xcd_local) {
     size_t sm = stack_lds_bytes(lds, block.x);
-#define L(N, C) hipLaunchKernelGGL((k_extend<N, C>), grid, block, sm, s, sc, wb, b, ovf, gcap, kRefill, sorted, xcd_local);
+#define L(N, C, I) hipLaunchKernelGGL((k_extend<N, C, I>), grid, block, sm, s, sc, wb, b, ovf, gcap, kRefill, sorted, xcd_local);
 #define X(N) PT_DISPATCH(N, L)
     PT_STACK_CASES(X)
 #undef X
@@ -501,7 +524,10 @@ hipError_t launch_extend(int lds, bool count, dim3 grid, dim3 block, hipStream_t
 
 hipError_t launch_shade(dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const PathParams& pp,
                         const WaveBufs& wb, int b, int compact, int sorted, uint32_t tail) {
-    hipLaunchKernelGGL(k_shade, grid, block, 0, s, sc, pp, wb, b, compact, sorted, compact ? tail : 0u);
+    if (sc.n_inst > 0)
+        hipLaunchKernelGGL(k_shade<true>, grid, block, 0, s, sc, pp, wb, b, compact, sorted, compact ? tail : 0u);
+    else
+        hipLaunchKernelGGL(k_shade<false>, grid, block, 0, s, sc, pp, wb, b, compact, sorted, compact ? tail : 0u);
     return hipGetLastError();
 }
 
@@ -510,7 +536,7 @@ hipError_t launch_tail(int lds, bool count, dim3 grid, dim3 block, hipStream_t s
                        int gcap, uint32_t resident_waves) {
     const size_t sm = stack_lds_bytes(lds, block.x);
     const uint32_t spread = resident_waves ? std::max(1u, std::min(grid.x * block.x / 64u, resident_waves)) : 0u;
-#define L(N, C) hipLaunchKernelGGL((k_shade_tail<N, C>), grid, block, sm, s, sc, pp, wb, b, sorted, tail, ovf, gcap, spread);
+#define L(N, C, I) hipLaunchKernelGGL((k_shade_tail<N, C, I>), grid, block, sm, s, sc, pp, wb, b, sorted, tail, ovf, gcap, spread);
 #define X(N) PT_DISPATCH(N, L)
     PT_STACK_CASES(X)
 #undef X
@@ -533,7 +559,7 @@ hipError_t launch_sort(dim3 grid, dim3 block, hipStream_t s, const SceneView& sc
 hipError_t launch_shadow(int lds, bool count, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
                          const WaveBufs& wb, int b, uint2* ovf, int gcap, int xcd_local) {
     size_t sm = stack_lds_bytes(lds, block.x);
-#define L(N, C) hipLaunchKernelGGL((k_shadow<N, C>), grid, block, sm, s, sc, wb, b, ovf, gcap, kRefill, xcd_local);
+#define L(N, C, I) hipLaunchKernelGGL((k_shadow<N, C, I>), grid, block, sm, s, sc, wb, b, ovf, gcap, kRefill, xcd_local);
 #define X(N) PT_DISPATCH(N, L)
     PT_STACK_CASES(X)
 #undef X

@@ -52,6 +52,17 @@ struct LightEntry {
 // workgroup (many paths reach them: a ground plane, area lights)
 constexpr int kHotTris = 64;
 
+// Instance record of a two-level scene, kInstRecord float4 (112 bytes), in
+// the top-level BVH's leaf order: rows 0-2 the world-to-object map (3x4,
+// row-major, a float4 per row), rows 3-5 the object-to-world map, row 6 =
+// (root node of the instance's mesh, input instance index, 0, 0) as bits.
+// A top-level leaf reference holds the record index (one instance per leaf).
+// In a two-level scene the light table's last word is the light's record.
+constexpr int kInstRecord = 7;
+// traversal stack entry that marks the return from an instance's mesh to
+// the top level (never a node or leaf reference of a valid scene)
+constexpr uint32_t kInstMarker = 0xFFFFFFFEu;
+
 struct SceneView {
     const float4* __restrict__ nodes;
     const float4* __restrict__ tris;
@@ -70,6 +81,10 @@ struct SceneView {
     // their gradients per workgroup before adding them to global memory
     const uint32_t* __restrict__ hot_ids;
     int32_t n_hot;
+    // two-level scene: instance records (kInstRecord float4 each), count;
+    // n_inst = 0 for a flat scene
+    const float4* __restrict__ insts;
+    int32_t n_inst;
 };
 
 struct CamView {

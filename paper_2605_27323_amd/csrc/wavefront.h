@@ -38,14 +38,14 @@ PT_DEV void raygen_item(const CamView& cam, const PathParams& pp, const WaveBufs
     wb.L[p] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
-// closest hit of queue slot i of bounce b
-template <int LDS, bool COUNT = false>
+// closest hit of queue slot i of bounce b: the hit record is (t, instance
+// record in a two-level scene, 0, leaf-order triangle)
+template <int LDS, bool COUNT = false, bool INST = false>
 PT_DEV void extend_item(const SceneView& sc, const WaveBufs& wb, int b, uint32_t i, TravStack<LDS, COUNT>& st) {
     float4 o4 = wb.ray_o[b & 1][i], d4 = wb.ray_d[b & 1][i];
     if (f2u(o4.w) == kDeadPath) return;
-    Ray ray = make_ray(xyz(o4), xyz(d4));
-    Hit h = closest_hit<LDS>(sc, ray, INFINITY, st);
-    wb.hit[i] = make_float4(h.t, 0.f, 0.f, u2f(h.tri));
+    Hit h = closest_hit_t<LDS, COUNT, INST>(sc, xyz(o4), xyz(d4), INFINITY, st);
+    wb.hit[i] = make_float4(h.t, INST ? u2f(h.inst) : 0.f, 0.f, u2f(h.tri));
 }
 
 // 6-bit sort key of a hit: material type in bits 4-5, low bits of the
@@ -72,6 +72,7 @@ PT_DEV uint32_t ray_key(const SceneView& sc, const float4& o4, const float4& d4)
 // radiance L[path] is read only where this vertex adds to it, and updated
 // in place; with for_tail it is always read into ps.L (plus this vertex's
 // term) for finish_path, which stores it at the path's end.
+template <bool INST = false>
 PT_DEV uint32_t shade_item(const SceneView& sc, const PathParams& pp, const WaveBufs& wb, int b, uint32_t i,
                            VertexOut& vo, ShadowReq& sh, PathState& ps, const uint32_t* __restrict__ perm = nullptr,
                            const LightCache& lc = no_light_cache(), bool for_tail = false) {
@@ -99,8 +100,13 @@ PT_DEV uint32_t shade_item(const SceneView& sc, const PathParams& pp, const Wave
     h.t = h4.x;
     h.tri = f2u(h4.w);
     h.id = 0;
-    hit_barycentrics(sc, xyz(o4), xyz(d4), h);
-    vo = shade_vertex(sc, pp, pix, sample, b + 1, xyz(d4), h, ps, sh, lc);
+    if constexpr (INST) {
+        h.inst = f2u(h4.y);
+        hit_barycentrics_inst(sc, xyz(o4), xyz(d4), h);
+    } else {
+        hit_barycentrics(sc, xyz(o4), xyz(d4), h);
+    }
+    vo = shade_vertex<INST>(sc, pp, pix, sample, b + 1, xyz(d4), h, ps, sh, lc);
     if (for_tail) {
         ps.L = xyz(wb.L[path]);
         add_radiance(ps, vo);
@@ -117,7 +123,7 @@ PT_DEV uint32_t shade_item(const SceneView& sc, const PathParams& pp, const Wave
 // vertices) and store its final radiance.  Used when a bounce's queue is too
 // short to keep the wavefront stages busy.
 // n_ext / n_sh count the extension and shadow rays traced here.
-template <int LDS, bool COUNT = false>
+template <int LDS, bool COUNT = false, bool INST = false>
 PT_DEV void finish_path(const SceneView& sc, const PathParams& pp, const WaveBufs& wb, uint32_t path, int k,
                         VertexOut vo, ShadowReq sh, PathState& ps, TravStack<LDS, COUNT>& st, uint32_t& n_ext,
                         uint32_t& n_sh, const LightCache& lc = no_light_cache()) {
@@ -127,17 +133,15 @@ PT_DEV void finish_path(const SceneView& sc, const PathParams& pp, const WaveBuf
     while (true) {
         if (sh.valid) {
             ++n_sh;
-            Ray sr = make_ray(sh.o, sh.d);
-            if (!any_hit<LDS>(sc, sr, kShadowTmax, st))
+            if (!any_hit_t<LDS, COUNT, INST>(sc, sh.o, sh.d, kShadowTmax, st))
                 ps.L = mk3(ps.L.x + sh.contrib.x, ps.L.y + sh.contrib.y, ps.L.z + sh.contrib.z);
         }
         if (!vo.cont) break;
         ++k;
         ++n_ext;
         const f3 d = vo.d;
-        Ray ray = make_ray(vo.o, d);
-        Hit h = closest_hit<LDS>(sc, ray, INFINITY, st);
-        vo = shade_vertex(sc, pp, pix, sample, k, d, h, ps, sh, lc);
+        Hit h = closest_hit_t<LDS, COUNT, INST>(sc, vo.o, d, INFINITY, st);
+        vo = shade_vertex<INST>(sc, pp, pix, sample, k, d, h, ps, sh, lc);
         add_radiance(ps, vo);
     }
     wb.L[path] = make_float4(ps.L.x, ps.L.y, ps.L.z, 0.f);
@@ -169,11 +173,10 @@ PT_DEV void shadow_add(const WaveBufs& wb, uint32_t i) {
 }
 
 // light-sample segment i: add beta * C to its path when unoccluded
-template <int LDS, bool COUNT = false>
+template <int LDS, bool COUNT = false, bool INST = false>
 PT_DEV void shadow_item(const SceneView& sc, const WaveBufs& wb, uint32_t i, TravStack<LDS, COUNT>& st) {
     float4 o4 = wb.sh_o[i], d4 = wb.sh_d[i];
-    Ray ray = make_ray(xyz(o4), xyz(d4));
-    if (!any_hit<LDS>(sc, ray, kShadowTmax, st)) shadow_add(wb, i);
+    if (!any_hit_t<LDS, COUNT, INST>(sc, xyz(o4), xyz(d4), kShadowTmax, st)) shadow_add(wb, i);
 }
 
 // per-pixel mean over its spp paths, summed in sample order

@@ -44,12 +44,19 @@ class BvhOpts(C.Structure):
 class BvhInfo(C.Structure):
     _fields_ = [("node_count", C.c_int64), ("node_bytes", C.c_int64), ("tri_bytes", C.c_int64),
                 ("light_count", C.c_int64), ("light_bytes", C.c_int64), ("material_bytes", C.c_int64),
+                ("instance_count", C.c_int64), ("instance_bytes", C.c_int64),
                 ("depth", C.c_int32), ("stack_entries", C.c_int32), ("build_seconds", C.c_double)]
+
+
+class InstancesDesc(C.Structure):
+    _fields_ = [("n_meshes", C.c_int32), ("mesh_first", C.c_void_p), ("mesh_count", C.c_void_p),
+                ("n_instances", C.c_int32), ("inst_mesh", C.c_void_p), ("o2w", C.c_void_p), ("w2o", C.c_void_p)]
 
 
 class SceneBuffers(C.Structure):
     _fields_ = [("nodes", C.c_void_p), ("tris", C.c_void_p), ("lights", C.c_void_p), ("materials", C.c_void_p),
-                ("albedo", C.c_void_p), ("emission", C.c_void_p), ("upload_params", C.c_int32)]
+                ("albedo", C.c_void_p), ("emission", C.c_void_p), ("upload_params", C.c_int32),
+                ("instances", C.c_void_p)]
 
 
 class Camera(C.Structure):
@@ -98,6 +105,7 @@ SIGNATURES = {
     "pt_create": (C.c_int32, [C.POINTER(C.c_void_p), C.c_int32]),
     "pt_destroy": (C.c_int32, [C.c_void_p]),
     "pt_load_scene": (C.c_int32, [C.c_void_p, C.POINTER(SceneDesc)]),
+    "pt_set_instances": (C.c_int32, [C.c_void_p, C.POINTER(InstancesDesc)]),
     "pt_build_bvh": (C.c_int32, [C.c_void_p, C.POINTER(BvhOpts), C.POINTER(BvhInfo)]),
     "pt_get_bvh": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pt_bind_scene": (C.c_int32, [C.c_void_p, C.POINTER(SceneBuffers), C.c_void_p]),
@@ -151,7 +159,11 @@ def _host(a, dtype):
 class Context:
     """A library context with a loaded scene and its built BVH (host side)."""
 
-    def __init__(self, scene, device=0, max_leaf=0, threads=0):
+    def __init__(self, scene, device=0, max_leaf=0, threads=0, instances=None):
+        """instances (optional): a two-level scene, dict of mesh_first,
+        mesh_count (int32 [n_meshes]), inst_mesh (int32 [n_inst]), o2w and
+        w2o (float32 [n_inst, 12], 3x4 row-major); the scene's triangles are
+        then the meshes, in object space."""
         L = lib()
         h = C.c_void_p()
         check(L.pt_create(C.byref(h), int(device)))
@@ -159,6 +171,13 @@ class Context:
         self.device = device
         self._keep = []
         self.load(scene)
+        if instances is not None:
+            i = {k: _host(instances[k], np.int32) for k in ("mesh_first", "mesh_count", "inst_mesh")}
+            i.update({k: _host(instances[k], np.float32) for k in ("o2w", "w2o")})
+            d = InstancesDesc(i["mesh_first"].size, i["mesh_first"].ctypes.data, i["mesh_count"].ctypes.data,
+                              i["inst_mesh"].size, i["inst_mesh"].ctypes.data, i["o2w"].ctypes.data,
+                              i["w2o"].ctypes.data)
+            check(L.pt_set_instances(self.h, C.byref(d)))
         opts = BvhOpts(max_leaf, threads)
         self.info = BvhInfo()
         check(L.pt_build_bvh(self.h, C.byref(opts), C.byref(self.info)))
@@ -210,22 +229,22 @@ def _aligned_empty(nbytes, device):
 class Renderer(Context):
     """Scene bound to device buffers (torch tensors), plus a workspace."""
 
-    def __init__(self, scene, camera=None, device=0, max_leaf=0, threads=0):
+    def __init__(self, scene, camera=None, device=0, max_leaf=0, threads=0, instances=None):
         import torch
-        super().__init__(scene, device=device, max_leaf=max_leaf, threads=threads)
+        super().__init__(scene, device=device, max_leaf=max_leaf, threads=threads, instances=instances)
         self.torch_device = torch.device("cuda", device)
         i = self.info
         self._bufs = {}
         ptrs = {}
         for name, nbytes in [("nodes", i.node_bytes), ("tris", i.tri_bytes), ("lights", i.light_bytes),
-                             ("materials", i.material_bytes)]:
+                             ("materials", i.material_bytes), ("instances", i.instance_bytes)]:
             t, p = _aligned_empty(nbytes, self.torch_device)
             self._bufs[name] = t
             ptrs[name] = p
         self.albedo = torch.zeros((max(self.nt, 1), 3), dtype=torch.float32, device=self.torch_device)
         self.emission = torch.zeros((max(self.nt, 1), 3), dtype=torch.float32, device=self.torch_device)
         sb = SceneBuffers(ptrs["nodes"], ptrs["tris"], ptrs["lights"], ptrs["materials"],
-                          self.albedo.data_ptr(), self.emission.data_ptr(), 1)
+                          self.albedo.data_ptr(), self.emission.data_ptr(), 1, ptrs["instances"])
         check(lib().pt_bind_scene(self.h, C.byref(sb), self._stream()))
         self._ws = None
         self._ws_ptr = 0

@@ -74,7 +74,7 @@ def lib():
 class Emu:
     """Host-only library context (emulator build) with a scene and camera."""
 
-    def __init__(self, scene, cam, max_leaf=0):
+    def __init__(self, scene, cam, max_leaf=0, instances=None):
         from paper_2605_27323_amd import ptmi
         L = lib()
         h = C.c_void_p()
@@ -87,6 +87,14 @@ class Emu:
                            keep["materials"].ctypes.data, keep["albedo"].ctypes.data, keep["emission"].ctypes.data,
                            (C.c_float * 3)(*np.asarray(keep["sky"], np.float32).tolist()))
         assert L.pt_load_scene(h, C.byref(d)) == 0, L.pt_last_error()
+        if instances is not None:
+            ik = {k: np.ascontiguousarray(instances[k], np.int32) for k in ("mesh_first", "mesh_count", "inst_mesh")}
+            ik.update({k: np.ascontiguousarray(instances[k], np.float32) for k in ("o2w", "w2o")})
+            self._keep_inst = ik
+            idesc = ptmi.InstancesDesc(ik["mesh_first"].size, ik["mesh_first"].ctypes.data, ik["mesh_count"].ctypes.data,
+                                       ik["inst_mesh"].size, ik["inst_mesh"].ctypes.data, ik["o2w"].ctypes.data,
+                                       ik["w2o"].ctypes.data)
+            assert L.pt_set_instances(h, C.byref(idesc)) == 0, L.pt_last_error()
         info = ptmi.BvhInfo()
         opts = ptmi.BvhOpts(int(max_leaf), 0)
         assert L.pt_build_bvh(h, C.byref(opts), C.byref(info)) == 0

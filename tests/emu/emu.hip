@@ -38,6 +38,8 @@ SceneView host_view(const pt_ctx* c) {
     v.cz = c->bvh.center[2];
     v.hot_ids = c->bvh.hot_ids.data();
     v.n_hot = (int32_t)c->bvh.hot_ids.size();
+    v.insts = c->bvh.insts.empty() ? nullptr : c->bvh.insts.data();
+    v.n_inst = (int32_t)(c->bvh.insts.size() / kInstRecord);
     return v;
 }
 
@@ -50,15 +52,10 @@ struct HostStack {
     explicit HostStack(int gcap) : gbl(std::max(gcap, 1)) { st = make_trav_stack<kL>(l, 1, gbl.data(), 0u, 1, gcap); }
 };
 
-}  // namespace
-
-extern "C" {
-
-// Megakernel body for the listed pixels: out[n*3].  rays[2] = extension
-// and shadow ray counts.  Returns 0, or 1 if a traversal stack overflowed.
-int32_t emu_render_mega(pt_ctx* c, const int32_t* pixels, int32_t n, int32_t spp, int32_t D, uint64_t seed,
-                        uint32_t frame, uint32_t job, int32_t nee, int32_t rr_start, float* out, uint64_t* rays,
-                        int32_t sampler) {
+template <bool INST>
+int32_t render_mega(pt_ctx* c, const int32_t* pixels, int32_t n, int32_t spp, int32_t D, uint64_t seed,
+                    uint32_t frame, uint32_t job, int32_t nee, int32_t rr_start, float* out, uint64_t* rays,
+                    int32_t sampler) {
     SceneView sc = host_view(c);
     PathParams pp{spp, D, nee ? 1 : 0, rr_start, seed, frame, job, sampler};
     HostStack hs(std::max(0, c->bvh.stack_entries - kL));
@@ -68,7 +65,7 @@ int32_t emu_render_mega(pt_ctx* c, const int32_t* pixels, int32_t n, int32_t spp
         uint32_t e = 0, s = 0;
         f3 sum = mk3(0.f, 0.f, 0.f);
         for (int k = 0; k < spp; ++k) {
-            f3 L = trace_path<kL>(sc, c->cam, pp, pix, frame * (uint32_t)spp + (uint32_t)k, hs.st, e, s);
+            f3 L = trace_path<kL, false, INST>(sc, c->cam, pp, pix, frame * (uint32_t)spp + (uint32_t)k, hs.st, e, s);
             sum = k == 0 ? L : add3(sum, L);
         }
         const float fs = (float)spp;
@@ -83,6 +80,19 @@ int32_t emu_render_mega(pt_ctx* c, const int32_t* pixels, int32_t n, int32_t spp
     return hs.st.overflow ? 1 : 0;
 }
 
+}  // namespace
+
+extern "C" {
+
+// Megakernel body for the listed pixels: out[n*3].  rays[2] = extension
+// and shadow ray counts.  Returns 0, or 1 if a traversal stack overflowed.
+int32_t emu_render_mega(pt_ctx* c, const int32_t* pixels, int32_t n, int32_t spp, int32_t D, uint64_t seed,
+                        uint32_t frame, uint32_t job, int32_t nee, int32_t rr_start, float* out, uint64_t* rays,
+                        int32_t sampler) {
+    return c->bvh.insts.empty() ? render_mega<false>(c, pixels, n, spp, D, seed, frame, job, nee, rr_start, out, rays, sampler)
+                                : render_mega<true>(c, pixels, n, spp, D, seed, frame, job, nee, rr_start, out, rays, sampler);
+}
+
 // Closest hit of the library's traversal for n rays o[3n], d[3n] in
 // (0, inf): t, input triangle id (-1 on a miss), barycentrics.  Returns 1
 // if a traversal stack overflowed.
@@ -91,8 +101,9 @@ int32_t emu_closest(pt_ctx* c, int32_t n, const float* o, const float* d, float*
     SceneView sc = host_view(c);
     HostStack hs(std::max(0, c->bvh.stack_entries - kL));
     for (int32_t i = 0; i < n; ++i) {
-        const Ray r = make_ray(mk3(o[3 * i], o[3 * i + 1], o[3 * i + 2]), mk3(d[3 * i], d[3 * i + 1], d[3 * i + 2]));
-        const Hit h = closest_hit<kL>(sc, r, INFINITY, hs.st);
+        const f3 oo = mk3(o[3 * i], o[3 * i + 1], o[3 * i + 2]), dd = mk3(d[3 * i], d[3 * i + 1], d[3 * i + 2]);
+        const Hit h = sc.n_inst > 0 ? closest_hit_t<kL, false, true>(sc, oo, dd, INFINITY, hs.st)
+                                    : closest_hit<kL>(sc, make_ray(oo, dd), INFINITY, hs.st);
         t[i] = h.t;
         id[i] = h.tri == 0xFFFFFFFFu ? -1 : (int32_t)h.id;
         b1[i] = h.b1;
@@ -101,11 +112,14 @@ int32_t emu_closest(pt_ctx* c, int32_t n, const float* o, const float* d, float*
     return hs.st.overflow ? 1 : 0;
 }
 
-// Wavefront over the whole image: img[W*H*3]; shuffle_seed != 0 permutes
-// every continuation and shadow queue.  compact = 0 keeps dead slots.
-int32_t emu_render_wave(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32_t frame, uint32_t job, int32_t nee,
-                        int32_t rr_start, int32_t compact, uint64_t shuffle_seed, int32_t sort, uint32_t tail,
-                        float* img, uint64_t* rays, int32_t sampler) {
+}  // extern "C"
+
+namespace {
+
+template <bool INST>
+int32_t render_wave(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32_t frame, uint32_t job, int32_t nee,
+                    int32_t rr_start, int32_t compact, uint64_t shuffle_seed, int32_t sort, uint32_t tail,
+                    float* img, uint64_t* rays, int32_t sampler) {
     SceneView sc = host_view(c);
     PathParams pp{spp, D, nee ? 1 : 0, rr_start, seed, frame, job, sampler};
     const uint32_t npaths = (uint32_t)c->cam.W * c->cam.H * (uint32_t)spp;
@@ -134,7 +148,7 @@ int32_t emu_render_wave(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32
     uint64_t ne = 0, ns = 0;
     for (int b = 0; b <= D; ++b) {
         const uint32_t count = counts[b];
-        for (uint32_t i = 0; i < count; ++i) extend_item<kL>(sc, wb, b, i, hs.st);
+        for (uint32_t i = 0; i < count; ++i) extend_item<kL, false, INST>(sc, wb, b, i, hs.st);
         const int nxt = (b & 1) ^ 1;
         // material sort: counting sort of the slots by key (ties in slot order)
         std::vector<uint32_t> perm;
@@ -155,12 +169,12 @@ int32_t emu_render_wave(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32
             VertexOut vo;
             ShadowReq sh;
             PathState ps;
-            uint32_t path = shade_item(sc, pp, wb, b, i, vo, sh, ps, sort ? perm.data() : nullptr, no_light_cache(),
-                                       finish);
+            uint32_t path = shade_item<INST>(sc, pp, wb, b, i, vo, sh, ps, sort ? perm.data() : nullptr,
+                                             no_light_cache(), finish);
             if (path != kDeadPath) ++ne;
             if (finish) {
                 uint32_t te = 0, ts = 0;
-                finish_path<kL>(sc, pp, wb, path, b + 1, vo, sh, ps, hs.st, te, ts);
+                finish_path<kL, false, INST>(sc, pp, wb, path, b + 1, vo, sh, ps, hs.st, te, ts);
                 ne += te;
                 ns += ts;
                 continue;
@@ -192,7 +206,7 @@ int32_t emu_render_wave(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32
                 for (uint32_t i = 0; i < nsh; ++i) buf[f][i] = tmp[ps[i]];
             }
         }
-        for (uint32_t i = 0; i < nsh; ++i) shadow_item<kL>(sc, wb, i, hs.st);
+        for (uint32_t i = 0; i < nsh; ++i) shadow_item<kL, false, INST>(sc, wb, i, hs.st);
         ns += nsh;
     }
     const uint32_t npix = (uint32_t)c->cam.W * c->cam.H;
@@ -200,6 +214,22 @@ int32_t emu_render_wave(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32
     rays[0] = ne;
     rays[1] = ns;
     return hs.st.overflow ? 1 : 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Wavefront over the whole image: img[W*H*3]; shuffle_seed != 0 permutes
+// every continuation and shadow queue.  compact = 0 keeps dead slots.
+int32_t emu_render_wave(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32_t frame, uint32_t job, int32_t nee,
+                        int32_t rr_start, int32_t compact, uint64_t shuffle_seed, int32_t sort, uint32_t tail,
+                        float* img, uint64_t* rays, int32_t sampler) {
+    return c->bvh.insts.empty()
+               ? render_wave<false>(c, spp, D, seed, frame, job, nee, rr_start, compact, shuffle_seed, sort, tail, img,
+                                    rays, sampler)
+               : render_wave<true>(c, spp, D, seed, frame, job, nee, rr_start, compact, shuffle_seed, sort, tail, img,
+                                   rays, sampler);
 }
 
 // Path-replay adjoint over the whole image (sequential binary32 adds):
