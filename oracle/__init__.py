@@ -69,10 +69,16 @@ def lib():
     L.orc_tri_test.restype = C.c_int32
     L.orc_tri_test.argtypes = [f32p, f32p, f32p, f32p, f32p, C.POINTER(C.c_float), C.POINTER(C.c_float),
                                C.POINTER(C.c_float)]
-    L.orc_bsdf_eval.argtypes = [C.c_int32, C.c_float, f32p, f32p, f32p, f32p, f32p, C.POINTER(C.c_float)]
+    L.orc_bsdf_eval.argtypes = [C.c_int32, C.c_float, C.c_float, C.c_float, f32p, f32p, f32p, f32p, f32p,
+                                C.POINTER(C.c_float)]
     L.orc_bsdf_sample.restype = C.c_int32
-    L.orc_bsdf_sample.argtypes = [C.c_int32, C.c_float, C.c_float, f32p, f32p, f32p, C.c_float, C.c_float,
-                                  C.c_float, f32p, f32p, C.POINTER(C.c_float)]
+    L.orc_bsdf_sample.argtypes = [C.c_int32, C.c_float, C.c_float, C.c_float, f32p, f32p, f32p, C.c_float,
+                                  C.c_float, C.c_float, f32p, f32p, C.POINTER(C.c_float)]
+    L.orc_scene_set_attributes.restype = C.c_int32
+    L.orc_scene_set_attributes.argtypes = [C.c_void_p, C.c_int32, i32p, C.c_void_p, C.c_void_p]
+    L.orc_shading_normal.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_float, C.c_float, f32p]
+    L.orc_texture.restype = C.c_float
+    L.orc_texture.argtypes = [C.c_void_p, C.c_int32, C.c_float, C.c_float, C.c_float]
     L.orc_sample_triangle.argtypes = [f32p, f32p, f32p, C.c_float, C.c_float, f32p]
     L.orc_offset.argtypes = [f32p, f32p, f32p, f32p]
     L.orc_frame.argtypes = [f32p, f32p, f32p]
@@ -128,6 +134,16 @@ class Scene:
         if not self.ptr:
             raise ValueError("oracle rejected the scene")
         self.has_bvh = bool(bvh)
+        nrm, uvs = scene.get("normals"), scene.get("uvs")
+        if nrm is not None or uvs is not None:
+            self._nrm = None if nrm is None else _f32(nrm).reshape(-1)
+            self._uvs = None if uvs is None else _f32(uvs).reshape(-1)
+            rc = L.orc_scene_set_attributes(
+                self.ptr, pos.size // 3, idx,
+                None if self._nrm is None else self._nrm.ctypes.data_as(C.c_void_p),
+                None if self._uvs is None else self._uvs.ctypes.data_as(C.c_void_p))
+            if rc != 0:
+                raise ValueError("oracle rejected the vertex attributes")
         if instances is not None:
             i = instances
             rc = L.orc_scene_set_instances(self.ptr, len(i["mesh_first"]),
@@ -157,6 +173,16 @@ class Scene:
 
     def pick_light(self, w):
         return lib().orc_pick_light(self.ptr, int(w))
+
+    def shading_normal(self, tri, b1, b2, inst=0):
+        """Shading normal of triangle tri (of instance inst) at (b1, b2)."""
+        out = np.zeros(3, np.float32)
+        lib().orc_shading_normal(self.ptr, int(inst), int(tri), float(b1), float(b2), out)
+        return out
+
+    def texture(self, tri, b1, b2, freq):
+        """Checker factor of the albedo at (b1, b2) of triangle tri."""
+        return lib().orc_texture(self.ptr, int(tri), float(b1), float(b2), float(freq))
 
     def render(self, cam, pixels=None, spp=1, max_depth=5, seed=0, frame=0, job=0, nee=True,
                rr_start=-1, use_bvh=None, threads=None, per_sample=False, sampler=0):
@@ -250,19 +276,20 @@ def tri_test(o, d, v0, v1, v2):
     return bool(hit), t.value, b1.value, b2.value
 
 
-def bsdf_eval(mtype, rough, alb, n, wo, wi):
+def bsdf_eval(mtype, rough, alb, n, wo, wi, ior=1.5, tex=1.0):
     f = np.zeros(3, np.float32)
     pdf = C.c_float()
-    lib().orc_bsdf_eval(int(mtype), float(rough), _f32(alb), _f32(n), _f32(wo), _f32(wi), f, C.byref(pdf))
+    lib().orc_bsdf_eval(int(mtype), float(rough), float(ior), float(tex), _f32(alb), _f32(n), _f32(wo), _f32(wi),
+                        f, C.byref(pdf))
     return f, pdf.value
 
 
-def bsdf_sample(mtype, rough, ior, alb, n, wo, u4, u5, u6):
+def bsdf_sample(mtype, rough, ior, alb, n, wo, u4, u5, u6, tex=1.0):
     wi = np.zeros(3, np.float32)
     w = np.zeros(3, np.float32)
     pdf = C.c_float()
-    ok = lib().orc_bsdf_sample(int(mtype), float(rough), float(ior), _f32(alb), _f32(n), _f32(wo), float(u4),
-                               float(u5), float(u6), wi, w, C.byref(pdf))
+    ok = lib().orc_bsdf_sample(int(mtype), float(rough), float(ior), float(tex), _f32(alb), _f32(n), _f32(wo),
+                               float(u4), float(u5), float(u6), wi, w, C.byref(pdf))
     return bool(ok), wi, w, pdf.value
 
 

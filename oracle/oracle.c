@@ -174,6 +174,10 @@ struct orc_scene {
     int32_t* inst_mesh;
     float *o2w, *w2o;
     int32_t* light_inst; /* instance of each light */
+    /* vertex attributes per triangle corner (NULL when absent): normals
+     * nt * 9 (n0, n1, n2), texture coordinates nt * 6 (uv0, uv1, uv2) */
+    float* nrm;
+    float* uv;
 };
 
 /* Affine map by a 3x4 row-major matrix M (row r: linear part M[4r..4r+2],
@@ -431,6 +435,7 @@ void orc_scene_destroy(orc_scene* s)
     free(s->is_light); free(s->light_tri); free(s->light_cdf); free(s->nodes); free(s->order);
     free(s->mesh_first); free(s->mesh_count); free(s->mesh_root); free(s->inst_mesh); free(s->o2w); free(s->w2o);
     free(s->light_inst);
+    free(s->nrm); free(s->uv);
     free(s);
 }
 
@@ -462,6 +467,36 @@ int32_t orc_scene_set_instances(orc_scene* s, int32_t n_meshes, const int32_t* m
     memcpy(s->w2o, w2o, sizeof(float) * 12 * (size_t)n_inst);
     build_lights(s);
     if (had_bvh) build_bvh(s);
+    return 0;
+}
+
+int32_t orc_scene_set_attributes(orc_scene* s, int32_t nv, const int32_t* idx, const float* normals,
+                                 const float* uvs)
+{
+    for (int i = 0; i < s->nt; ++i)
+        for (int k = 0; k < 3; ++k)
+            if (idx[3 * (size_t)i + k] < 0 || idx[3 * (size_t)i + k] >= nv) return -1;
+    for (int i = 0; i < nv; ++i) {
+        if (normals && !finite3(normals + 3 * (size_t)i)) return -1;
+        if (uvs && !(isfinite(uvs[2 * (size_t)i]) && isfinite(uvs[2 * (size_t)i + 1]))) return -1;
+    }
+    free(s->nrm); free(s->uv);
+    s->nrm = NULL; s->uv = NULL;
+    size_t nt = (size_t)(s->nt ? s->nt : 1);
+    if (normals) {
+        s->nrm = (float*)malloc(sizeof(float) * 9 * nt);
+        for (int i = 0; i < s->nt; ++i)
+            for (int k = 0; k < 3; ++k)
+                for (int a = 0; a < 3; ++a)
+                    s->nrm[9 * (size_t)i + 3 * k + a] = normals[3 * (size_t)idx[3 * (size_t)i + k] + a];
+    }
+    if (uvs) {
+        s->uv = (float*)malloc(sizeof(float) * 6 * nt);
+        for (int i = 0; i < s->nt; ++i)
+            for (int k = 0; k < 3; ++k)
+                for (int a = 0; a < 2; ++a)
+                    s->uv[6 * (size_t)i + 2 * k + a] = uvs[2 * (size_t)idx[3 * (size_t)i + k] + a];
+    }
     return 0;
 }
 
@@ -876,6 +911,61 @@ static v3 to_world(const frame_t* f, v3 l)
              (f->t.z * l.x + f->b.z * l.y) + f->n.z * l.z);
 }
 
+/* ------------------------------------------------------------------------ */
+/* vertex attributes at a hit (paper Sec. 2.3: the shading stage rebuilds    */
+/* the hit's attributes from the triangle and its barycentrics)              */
+/* Reading: weights (w0, b1, b2) with w0 = (1 - b1) - b2 for (v0, v1, v2),   */
+/* the sum ((w0 a0 + b1 a1) + b2 a2) per component.                          */
+/* ------------------------------------------------------------------------ */
+static float interp3(float a0, float a1, float a2, float w0, float b1, float b2)
+{
+    return (w0 * a0 + b1 * a1) + b2 * a2;
+}
+
+/* Shading normal: the interpolated vertex normal; in a two-level scene it is
+ * an object-space normal and maps by the inverse transpose of the
+ * instance's object-to-world map, i.e. by the columns of w2o's linear part;
+ * normalised once; turned to the side of the geometric normal ng (vertex
+ * normals and winding may disagree); ng itself when the scene has no
+ * normals or the interpolant is zero or not finite. */
+static v3 shading_normal(const orc_scene* s, int32_t inst, int32_t tri, float b1, float b2, v3 ng)
+{
+    if (!s->nrm) return ng;
+    const float* n = s->nrm + 9 * (size_t)tri;
+    float w0 = (1.0f - b1) - b2;
+    v3 m = V(interp3(n[0], n[3], n[6], w0, b1, b2), interp3(n[1], n[4], n[7], w0, b1, b2),
+             interp3(n[2], n[5], n[8], w0, b1, b2));
+    if (s->ninst > 0) {
+        const float* M = s->w2o + 12 * (size_t)inst;
+        m = V((M[0] * m.x + M[4] * m.y) + M[8] * m.z, (M[1] * m.x + M[5] * m.y) + M[9] * m.z,
+              (M[2] * m.x + M[6] * m.y) + M[10] * m.z);
+    }
+    float l2 = vdot(m, m);
+    if (!(l2 > 0.0f && l2 <= FLT_MAX)) return ng;
+    v3 ns = vnorm(m);
+    return vdot(ns, ng) < 0.0f ? vneg(ns) : ns;
+}
+
+/* Checker texture of the albedo (a synthetic stand-in for the paper's
+ * base-colour textures): cell (floor(u f), floor(v f)); the factor is
+ * CHECKER_DARK on cells whose two indices differ in parity, else 1.  Parity
+ * of floor(x): floor(x)/2 is an integer or a half, both exact in binary32. */
+#define CHECKER_DARK 0.25f
+static int odd_cell(float x)
+{
+    float f = floorf(x);
+    float h = f * 0.5f;
+    return floorf(h) != h;
+}
+static float texture(const orc_scene* s, int32_t tri, float b1, float b2, float freq)
+{
+    if (!s->uv || !(freq > 0.0f)) return 1.0f;
+    const float* q = s->uv + 6 * (size_t)tri;
+    float w0 = (1.0f - b1) - b2;
+    float u = interp3(q[0], q[2], q[4], w0, b1, b2), v = interp3(q[1], q[3], q[5], w0, b1, b2);
+    return odd_cell(u * freq) != odd_cell(v * freq) ? CHECKER_DARK : 1.0f;
+}
+
 /* cos and sin of 2 pi u, evaluated in binary64 and rounded to binary32. */
 static void cos_sin_2pi(float u, float* c, float* s)
 {
@@ -930,21 +1020,58 @@ static float pow5(float m) { return ((m * m) * (m * m)) * m; }
 typedef struct {
     int type;
     float m5; /* Schlick (1 - cos)^5 (conductor) */
-    float k;  /* conductor: D G2 / (4 cos_o cos_i) in f = F k; dielectric: weight */
+    float k;  /* Lambert: f = albedo k; conductor: D G2 / (4 cos_o cos_i) in f = F k;
+                 dielectric: weight; coated: the base's factor in f = albedo k + b */
+    float b;  /* coated: the coat's specular term (albedo-free) */
 } lobe_t;
+
+/* Coated material (a two-lobe subset of a layered model such as OpenPBR's
+ * coat over a base; reading, the paper names the layered model but not its
+ * evaluation): a GGX dielectric coat of index ior over a Lambertian base,
+ *   f = F(wo.h) D G2 / (4 cos_o cos_i) + (1 - F(cos_o)) (1 - F(cos_i)) albedo / pi
+ * with F the exact unpolarised Fresnel reflectance of the coat (its
+ * specular reflection, Walter et al. 2007) and the base seen through two
+ * coat crossings at the macro-surface angles (no interreflection between
+ * the layers).  Symmetric in (wo, wi).  Sampling takes the coat's visible
+ * normals with probability F(cos_o) (u4 < F(cos_o)), else the base's cosine
+ * lobe; the pdf is the mixture of the two, and the weight f cos_i / pdf. */
+static float fresnel_dielectric(float ci, float eta);
+static void eval_coat(float rough, float ior, float tex, v3 alb, v3 wo, v3 wi, v3* f, float* pdf, lobe_t* lb)
+{
+    float alpha = ggx_alpha(rough), a2 = alpha * alpha;
+    v3 h = vnorm(vadd(wo, wi));
+    float D = ggx_D(h, a2);
+    float lo = ggx_lambda(wo, a2), li = ggx_lambda(wi, a2);
+    float G1 = 1.0f / (1.0f + lo);
+    float G2 = 1.0f / ((1.0f + lo) + li);
+    float Fh = fresnel_dielectric(vdot(wo, h), ior);
+    float fs = ((Fh * D) * G2) / ((4.0f * wo.z) * wi.z);
+    float Fo = fresnel_dielectric(wo.z, ior), Fi = fresnel_dielectric(wi.z, ior);
+    float kd = (((1.0f - Fo) * (1.0f - Fi)) * tex) * INV_PI_F;
+    *f = V(alb.x * kd + fs, alb.y * kd + fs, alb.z * kd + fs);
+    *pdf = Fo * ((G1 * D) / (4.0f * wo.z)) + (1.0f - Fo) * (wi.z * INV_PI_F);
+    lb->k = kd;
+    lb->b = fs;
+}
 
 /* Evaluate f and the solid-angle pdf for an opaque material (Lambert or
  * conductor) with wo, wi in the local frame of the normal on wo's side. */
-static void eval_opaque(int type, float rough, v3 alb, v3 wo, v3 wi, v3* f, float* pdf, lobe_t* lb)
+static void eval_opaque(int type, float rough, float ior, float tex, v3 alb, v3 wo, v3 wi, v3* f, float* pdf,
+                        lobe_t* lb)
 {
     *f = V(0.0f, 0.0f, 0.0f);
     *pdf = 0.0f;
-    lb->type = type; lb->m5 = 0.0f; lb->k = 0.0f;
+    lb->type = type; lb->m5 = 0.0f; lb->k = 0.0f; lb->b = 0.0f;
     if (wi.z <= 0.0f || wo.z <= 0.0f) return;
     if (type == ORC_LAMBERT) {
-        *f = V(alb.x * INV_PI_F, alb.y * INV_PI_F, alb.z * INV_PI_F);
+        float k = tex * INV_PI_F;
+        *f = V(alb.x * k, alb.y * k, alb.z * k);
         *pdf = wi.z * INV_PI_F;
-        lb->k = INV_PI_F;
+        lb->k = k;
+        return;
+    }
+    if (type == ORC_COATED) {
+        eval_coat(rough, ior, tex, alb, wo, wi, f, pdf, lb);
         return;
     }
     float alpha = ggx_alpha(rough), a2 = alpha * alpha;
@@ -976,23 +1103,54 @@ static float fresnel_dielectric(float ci, float eta)
 /* Sample a direction.  wo is in the local frame (z = normal on the side the
  * sampling happens: wo side for opaque, the side of wo for the dielectric).
  * Returns 0 if rejected.  weight = f |cos| / pdf. */
-static int sample_local(int type, float rough, float ior, int entering, v3 alb, v3 wo, float u4,
+/* cosine-weighted direction about +z from (u5, u6) */
+static v3 cosine_dir(float u5, float u6)
+{
+    float r = sqrtf(u5), c, s;
+    cos_sin_2pi(u6, &c, &s);
+    float z2 = 1.0f - u5;
+    return V(r * c, r * s, sqrtf(z2 > 0.0f ? z2 : 0.0f));
+}
+
+static int sample_local(int type, float rough, float ior, float tex, int entering, v3 alb, v3 wo, float u4,
                         float u5, float u6, v3* wi, v3* weight, float* pdf, lobe_t* lb, int* frag)
 {
-    lb->type = type; lb->m5 = 0.0f; lb->k = 0.0f;
+    lb->type = type; lb->m5 = 0.0f; lb->k = 0.0f; lb->b = 0.0f;
     if (type == ORC_LAMBERT) {
-        float r = sqrtf(u5), c, s;
-        cos_sin_2pi(u6, &c, &s);
-        float z2 = 1.0f - u5;
-        *wi = V(r * c, r * s, sqrtf(z2 > 0.0f ? z2 : 0.0f));
-        *weight = alb;
+        *wi = cosine_dir(u5, u6);
+        *weight = V(alb.x * tex, alb.y * tex, alb.z * tex);
         *pdf = wi->z * INV_PI_F;
-        lb->k = 1.0f;
+        lb->k = tex;
         return 1;
     }
     if (wo.z <= 0.0f) return 0;
     if (frag && wo.z < FRAG_EPS) *frag |= FR_GRAZE;
     float alpha = ggx_alpha(rough), a2 = alpha * alpha;
+    if (type == ORC_COATED) {
+        float Fo = fresnel_dielectric(wo.z, ior);
+        if (frag && fabsf(u4 - Fo) < 0x1p-20f) *frag |= FR_THRESH;
+        v3 w;
+        if (u4 < Fo) {
+            v3 m = ggx_vndf(wo, alpha, u5, u6);
+            float com = vdot(wo, m);
+            w = V((2.0f * com) * m.x - wo.x, (2.0f * com) * m.y - wo.y, (2.0f * com) * m.z - wo.z);
+        } else {
+            w = cosine_dir(u5, u6);
+        }
+        if (frag && fabsf(w.z) < FRAG_EPS) *frag |= FR_GRAZE;
+        if (w.z <= 0.0f) return 0;
+        v3 f;
+        float p;
+        eval_coat(rough, ior, tex, alb, wo, w, &f, &p, lb);
+        if (!(p > 0.0f)) return 0;
+        float sc = w.z / p;
+        lb->k = lb->k * sc;
+        lb->b = lb->b * sc;
+        *wi = w;
+        *weight = V(alb.x * lb->k + lb->b, alb.y * lb->k + lb->b, alb.z * lb->k + lb->b);
+        *pdf = p;
+        return 1;
+    }
     v3 m = ggx_vndf(wo, alpha, u5, u6);
     float com = vdot(wo, m);
     float lo = ggx_lambda(wo, a2);
@@ -1043,17 +1201,18 @@ static int sample_local(int type, float rough, float ior, int entering, v3 alb, 
     return 1;
 }
 
-void orc_bsdf_eval(int32_t type, float rough, const float alb[3], const float n[3],
+void orc_bsdf_eval(int32_t type, float rough, float ior, float tex, const float alb[3], const float n[3],
                    const float wo[3], const float wi[3], float f[3], float* pdf)
 {
     frame_t fr = make_frame(vload(n));
     v3 ff;
     lobe_t lb;
-    eval_opaque(type, rough, vload(alb), to_local(&fr, vload(wo)), to_local(&fr, vload(wi)), &ff, pdf, &lb);
+    eval_opaque(type, rough, ior, tex, vload(alb), to_local(&fr, vload(wo)), to_local(&fr, vload(wi)), &ff, pdf,
+                &lb);
     vstore(f, ff);
 }
 
-int32_t orc_bsdf_sample(int32_t type, float rough, float ior, const float alb[3],
+int32_t orc_bsdf_sample(int32_t type, float rough, float ior, float tex, const float alb[3],
                         const float n[3], const float wo[3], float u4, float u5, float u6,
                         float wi[3], float weight[3], float* pdf)
 {
@@ -1066,12 +1225,24 @@ int32_t orc_bsdf_sample(int32_t type, float rough, float ior, const float alb[3]
     frame_t fr = make_frame(nn);
     v3 w, W;
     lobe_t lb;
-    int ok = sample_local(type, rough, ior, entering, vload(alb), to_local(&fr, vload(wo)), u4, u5, u6,
+    int ok = sample_local(type, rough, ior, tex, entering, vload(alb), to_local(&fr, vload(wo)), u4, u5, u6,
                           &w, &W, pdf, &lb, NULL);
     vstore(wi, ok ? to_world(&fr, w) : V(0.0f, 0.0f, 0.0f));
     vstore(weight, ok ? W : V(0.0f, 0.0f, 0.0f));
     if (!ok) *pdf = 0.0f;
     return ok;
+}
+
+void orc_shading_normal(const orc_scene* s, int32_t inst, int32_t tri, float b1, float b2, float out[3])
+{
+    float tw[9];
+    const float* tp = world_tri(s, inst, tri, tw);
+    vstore(out, shading_normal(s, inst, tri, b1, b2, tri_normal(tp)));
+}
+
+float orc_texture(const orc_scene* s, int32_t tri, float b1, float b2, float freq)
+{
+    return texture(s, tri, b1, b2, freq);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1155,16 +1326,29 @@ static v3 trace_path(const pt_args* a, int pix, uint32_t sample, int* frag, vrec
         int type = (int)mat[0];
         float rough = mat[1], ior = mat[2];
         v3 alb = vload(s->albedo + 3 * (size_t)h.prim);
+        float tex = (type == ORC_LAMBERT || type == ORC_COATED) ? texture(s, h.prim, h.b1, h.b2, mat[3]) : 1.0f;
+        /* BSDF frame: the shading normal turned to wo's side of the surface
+         * (the geometric normal when the scene has no vertex normals) */
+        v3 ns = shading_normal(s, h.inst, h.prim, h.b1, h.b2, ng);
         int entering = 1;
-        v3 n;
+        v3 n, ngf;
         if (type == ORC_DIELECTRIC) {
             entering = cos_e > 0.0f;
-            n = entering ? ng : vneg(ng);
+            n = entering ? ns : vneg(ns);
+            ngf = entering ? ng : vneg(ng);
         } else {
-            n = cos_e > 0.0f ? ng : vneg(ng);
+            n = cos_e > 0.0f ? ns : vneg(ns);
+            ngf = cos_e > 0.0f ? ng : vneg(ng);
         }
         frame_t fr = make_frame(n);
         v3 wo_l = to_local(&fr, wo);
+        /* shading normals (reading): a vertex seen from below its shading
+         * horizon scatters nothing; a light or continuation direction must
+         * also lie on the geometric side its lobe implies (reflection: wo's
+         * side, transmission: the other), so that no light leaks through
+         * the surface */
+        if (frag && s->nrm && fabsf(wo_l.z) < FRAG_EPS) *frag |= FR_GRAZE;
+        if (s->nrm && wo_l.z <= 0.0f) break;
         /* next-event estimation at opaque vertices */
         if (a->nee && s->nl > 0 && type != ORC_DIELECTRIC) {
             int j = orc_pick_light(s, w[0]);
@@ -1184,11 +1368,17 @@ static v3 trace_path(const pt_args* a, int pix, uint32_t sample, int* frag, vrec
                 float cos_y = -vdot(ny, wl);
                 float cos_x = vdot(n, wl);
                 if (frag && ((cos_y != 0.0f && fabsf(cos_y) < FRAG_EPS) || (cos_x != 0.0f && fabsf(cos_x) < FRAG_EPS))) *frag |= FR_GRAZE;
-                if (cos_y > 0.0f && cos_x > 0.0f) {
+                int side = 1;
+                if (s->nrm) {
+                    float cg = vdot(ngf, wl);
+                    if (frag && fabsf(cg) < FRAG_EPS) *frag |= FR_GRAZE;
+                    side = cg > 0.0f;
+                }
+                if (cos_y > 0.0f && cos_x > 0.0f && side) {
                     v3 f;
                     float pb;
                     lobe_t lb;
-                    eval_opaque(type, rough, alb, wo_l, to_local(&fr, wl), &f, &pb, &lb);
+                    eval_opaque(type, rough, ior, tex, alb, wo_l, to_local(&fr, wl), &f, &pb, &lb);
                     float pl = d2 / (s->area_total * cos_y);
                     if (lb.k > 0.0f && pl > 0.0f) {
                         float wmis = (pl * pl) / (pl * pl + pb * pb);
@@ -1211,11 +1401,17 @@ static v3 trace_path(const pt_args* a, int pix, uint32_t sample, int* frag, vrec
         v3 wi_l, W;
         float pb;
         lobe_t lb;
-        int ok = sample_local(type, rough, ior, entering, alb, wo_l, orc_unif(w[4]), orc_unif(w[5]),
+        int ok = sample_local(type, rough, ior, tex, entering, alb, wo_l, orc_unif(w[4]), orc_unif(w[5]),
                               orc_unif(w[6]), &wi_l, &W, &pb, &lb, frag);
         if (!ok) break;
         if (W.x == 0.0f && W.y == 0.0f && W.z == 0.0f) break;
         if (type != ORC_DIELECTRIC && !(pb > 0.0f)) break;
+        v3 wi = to_world(&fr, wi_l);
+        if (s->nrm) {
+            float cg = vdot(ngf, wi);
+            if (frag && fabsf(cg) < FRAG_EPS) *frag |= FR_GRAZE;
+            if (wi_l.z > 0.0f ? !(cg > 0.0f) : !(cg < 0.0f)) break;
+        }
         beta = V(beta.x * W.x, beta.y * W.y, beta.z * W.z);
         if (a->rr_start >= 0 && k >= a->rr_start) {
             float q = maxc(beta);
@@ -1226,7 +1422,6 @@ static v3 trace_path(const pt_args* a, int pix, uint32_t sample, int* frag, vrec
             beta = V(beta.x / q, beta.y / q, beta.z / q);
         }
         if (vr) { vr->scat = 1; vr->scat_lobe = lb; }
-        v3 wi = to_world(&fr, wi_l);
         v3 no = vdot(ng, wi) > 0.0f ? ng : vneg(ng);
         ray_setup(&r, offset_point(x, no, tri_extent(tp)), wi);
         p_prev = pb;
@@ -1320,11 +1515,12 @@ static double lobe_val(const lobe_t* lb, double rho)
 {
     if (lb->type == ORC_LAMBERT) return rho * (double)lb->k;
     if (lb->type == ORC_CONDUCTOR) return (rho + (1.0 - rho) * (double)lb->m5) * (double)lb->k;
+    if (lb->type == ORC_COATED) return rho * (double)lb->k + (double)lb->b;
     return (double)lb->k;
 }
 static double lobe_der(const lobe_t* lb)
 {
-    if (lb->type == ORC_LAMBERT) return (double)lb->k;
+    if (lb->type == ORC_LAMBERT || lb->type == ORC_COATED) return (double)lb->k;
     if (lb->type == ORC_CONDUCTOR) return (1.0 - (double)lb->m5) * (double)lb->k;
     return 0.0;
 }

@@ -31,8 +31,12 @@ extern "C" {
 
 typedef struct orc_scene orc_scene;
 
-/* Material types of the material table (type, roughness, ior, unused). */
-enum { ORC_LAMBERT = 0, ORC_CONDUCTOR = 1, ORC_DIELECTRIC = 2 };
+/* Material types of the material table (type, roughness, ior, checker
+ * frequency).  ORC_COATED: a dielectric coat (GGX roughness, ior) over a
+ * Lambertian base of the triangle's albedo.  The checker frequency (> 0)
+ * textures the albedo of Lambertian and coated materials through the
+ * vertex texture coordinates (orc_scene_set_attributes); 0 = untextured. */
+enum { ORC_LAMBERT = 0, ORC_CONDUCTOR = 1, ORC_DIELECTRIC = 2, ORC_COATED = 3 };
 
 /* Build a scene from indexed triangles.  Arrays are copied.  build_bvh != 0
  * also builds the oracle's own binary BVH (object-median splits).
@@ -64,6 +68,28 @@ int32_t orc_scene_num_lights(const orc_scene* s);
 int32_t orc_scene_set_instances(orc_scene* s, int32_t n_meshes, const int32_t* mesh_first,
                                 const int32_t* mesh_count, int32_t n_inst, const int32_t* inst_mesh,
                                 const float* o2w, const float* w2o);
+/* Vertex attributes (paper Sec. 2.3: the shading stage interpolates the
+ * hit triangle's vertex attributes).  normals (nv*3, may be NULL) and uvs
+ * (nv*2, may be NULL) are per vertex, taken through idx (nt*3, the scene's
+ * indices; in a two-level scene they are in object space).  The shading
+ * normal at barycentrics (b1, b2) is the interpolation
+ * ((w0 n0 + b1 n1) + b2 n2), w0 = (1 - b1) - b2, mapped to world space by
+ * the columns of w2o's linear part in a two-level scene, normalised, and
+ * turned to the geometric normal's side; a zero or non-finite interpolant
+ * falls back to the geometric normal.  Texture: the checker factor of
+ * orc_texture.  Returns 0, or -1 on a non-finite value or an index out of
+ * range. */
+int32_t orc_scene_set_attributes(orc_scene* s, int32_t nv, const int32_t* idx, const float* normals,
+                                 const float* uvs);
+/* Shading normal of triangle tri (instance inst in a two-level scene) at
+ * barycentrics (b1, b2), before it is turned towards the outgoing
+ * direction; the geometric normal when the scene has no normals. */
+void orc_shading_normal(const orc_scene* s, int32_t inst, int32_t tri, float b1, float b2, float out[3]);
+/* Albedo factor of the checker texture of frequency freq at (b1, b2) of
+ * triangle tri: with (u, v) interpolated like the normals, 1/4 where
+ * floor(u freq) + floor(v freq) is odd, else 1 (1 without texture
+ * coordinates or with freq <= 0). */
+float orc_texture(const orc_scene* s, int32_t tri, float b1, float b2, float freq);
 /* BVH statistics: node count and maximum depth (0 if no BVH). */
 void orc_scene_bvh_stats(const orc_scene* s, int32_t* nodes, int32_t* depth);
 
@@ -121,12 +147,13 @@ int32_t orc_tri_test(const float o[3], const float d[3], const float v0[3], cons
                      const float v2[3], float* t, float* b1, float* b2);
 
 /* BSDF pieces, for pins.  n is the unit surface normal on the side of wo
- * (for the dielectric: the outside normal).  eval writes f[3] and *pdf
+ * (for the dielectric: the outside normal); tex is the texture factor of
+ * the albedo (Lambertian and coated base).  eval writes f[3] and *pdf
  * (solid angle).  sample writes wi, the weight f|n.wi|/pdf and *pdf and
  * returns 0 when the sample is rejected. */
-void orc_bsdf_eval(int32_t type, float rough, const float alb[3], const float n[3],
+void orc_bsdf_eval(int32_t type, float rough, float ior, float tex, const float alb[3], const float n[3],
                    const float wo[3], const float wi[3], float f[3], float* pdf);
-int32_t orc_bsdf_sample(int32_t type, float rough, float ior, const float alb[3],
+int32_t orc_bsdf_sample(int32_t type, float rough, float ior, float tex, const float alb[3],
                         const float n[3], const float wo[3], float u4, float u5, float u6,
                         float wi[3], float weight[3], float* pdf);
 

@@ -12,6 +12,14 @@ A scene is a dict of NumPy arrays:
     albedo     float32 [nt, 3]
     emission   float32 [nt, 3]   one-sided, front face only
     sky        float32 [3]       constant radiance of escaped rays
+and optionally per-vertex attributes:
+    normals    float32 [nv, 3]   shading normals (zero rows: flat shading)
+    uvs        float32 [nv, 2]   texture coordinates (for the checker
+                                 texture of materials whose 4th entry, the
+                                 checker frequency, is > 0)
+Material types: LAMBERT, CONDUCTOR, DIELECTRIC, COATED (a GGX dielectric
+coat of the material's roughness and ior over a Lambertian base of the
+triangle's albedo).
 A camera is a dict {eye, target, up, vfov_deg, width, height}.
 
 The paper's own benchmark asset is not available; the procedural scenes
@@ -25,6 +33,7 @@ import numpy as np
 LAMBERT = 0
 CONDUCTOR = 1
 DIELECTRIC = 2
+COATED = 3
 
 
 def _pack(pos_list, idx_list, mat_list, alb_list, emi_list, materials, sky=(0.0, 0.0, 0.0)):
@@ -249,6 +258,99 @@ def emitter_in_slab(ior=1.5, rough=0.0, le=2.0, half=8.0, width=16, height=16):
                   [(LAMBERT, 1.0, 1.5, 0.0), (DIELECTRIC, rough, ior, 0.0)])
     cam = dict(eye=(0.0, 10.0, 0.0), target=(0.0, 0.0, 0.0), up=(0.0, 0.0, 1.0),
                vfov_deg=2.0, width=width, height=height)
+    return scene, cam
+
+
+def tilted_normal_plane(alpha_deg=30.0, albedo=0.6, sky=1.0, half=1000.0, width=8, height=8):
+    """Square at y = 0 facing +y whose four vertex normals all equal
+    (sin a, cos a, 0): shading normals tilted by a from the geometric
+    normal.  Constant sky; camera at y = 10 looking straight down through a
+    2-degree field of view."""
+    pos, idx = quad((-half, 0, -half), (-half, 0, half), (half, 0, half), (half, 0, -half))
+    m, a, e = _tri_params(2, (albedo,) * 3, (0, 0, 0), 0)
+    scene = _pack([pos], [idx], [m], [a], [e], [(LAMBERT, 1.0, 1.5, 0.0)], sky=(sky,) * 3)
+    al = np.radians(alpha_deg)
+    scene["normals"] = np.tile(np.array([np.sin(al), np.cos(al), 0.0], np.float32), (4, 1))
+    cam = dict(eye=(0.0, 10.0, 0.0), target=(0.0, 0.0, 0.0), up=(0.0, 0.0, 1.0),
+               vfov_deg=2.0, width=width, height=height)
+    return scene, cam
+
+
+def coated_plane(ior=1.5, rough=0.0, base=0.0, sky=1.0, theta_deg=45.0, half=1000.0, width=8, height=8,
+                 vfov_deg=0.5):
+    """Coated square at y = 0 facing +y (base albedo `base`) under a constant
+    sky, seen at `theta_deg` from its normal from 10 units away through a
+    narrow field of view."""
+    pos, idx = quad((-half, 0, -half), (-half, 0, half), (half, 0, half), (half, 0, -half))
+    m, a, e = _tri_params(2, (base,) * 3, (0, 0, 0), 0)
+    scene = _pack([pos], [idx], [m], [a], [e], [(COATED, rough, ior, 0.0)], sky=(sky,) * 3)
+    th = np.radians(theta_deg)
+    cam = dict(eye=(0.0, 10.0 * np.cos(th), -10.0 * np.sin(th)), target=(0.0, 0.0, 0.0), up=(0.0, 1.0, 0.0),
+               vfov_deg=vfov_deg, width=width, height=height)
+    return scene, cam
+
+
+def checker_plane(freq=4.0, albedo=0.8, sky=1.0, half=1.0, uv_offset=(0.13, 0.37), width=32, height=32):
+    """Square at y = 0 facing +y, texture coordinates (x, z) + uv_offset at
+    its corners, Lambertian with a checker texture of frequency `freq`;
+    constant sky; camera at y = 3 looking straight down (the square fills
+    the middle of the view)."""
+    pos, idx = quad((-half, 0, -half), (-half, 0, half), (half, 0, half), (half, 0, -half))
+    m, a, e = _tri_params(2, (albedo,) * 3, (0, 0, 0), 0)
+    scene = _pack([pos], [idx], [m], [a], [e], [(LAMBERT, 1.0, 1.5, float(freq))], sky=(sky,) * 3)
+    scene["uvs"] = (pos[:, [0, 2]] + np.asarray(uv_offset)).astype(np.float32)
+    cam = dict(eye=(0.0, 3.0, 0.0), target=(0.0, 0.0, 0.0), up=(0.0, 0.0, 1.0),
+               vfov_deg=40.0, width=width, height=height)
+    return scene, cam
+
+
+def with_attributes(scene, normals=None, uvs=None):
+    """A copy of a scene with vertex attributes added (zero normals and
+    zero texture coordinates where not given)."""
+    out = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in scene.items()}
+    nv = scene["positions"].shape[0]
+    out["normals"] = np.zeros((nv, 3), np.float32) if normals is None else np.asarray(normals, np.float32)
+    out["uvs"] = np.zeros((nv, 2), np.float32) if uvs is None else np.asarray(uvs, np.float32)
+    return out
+
+
+def cornell_attributes(coat=(0.2, 1.5), freq=6.0):
+    """Cornell room with shading attributes: the tall box replaced by a
+    smooth-shaded level-3 icosphere with a coat (roughness, ior) over a
+    white base, the short box a coated box with flat shading (zero vertex
+    normals), a checker-textured floor (texture coordinates (x, z) + 0.1,
+    frequency `freq`), the walls flat and untextured."""
+    white = (0.73, 0.73, 0.73)
+    red = (0.63, 0.06, 0.05)
+    green = (0.14, 0.45, 0.09)
+    P, I, M, A, E, N, U = [], [], [], [], [], [], []
+
+    def add(pos, idx, alb, emi=(0, 0, 0), mat=0, nrm=None, uv=None):
+        P.append(pos)
+        I.append(idx)
+        m, a, e = _tri_params(idx.shape[0], alb, emi, mat)
+        M.append(m); A.append(a); E.append(e)
+        N.append(np.zeros((pos.shape[0], 3)) if nrm is None else nrm)
+        U.append(np.zeros((pos.shape[0], 2)) if uv is None else uv)
+
+    fp, fi = quad((-1, 0, -1), (-1, 0, 1), (1, 0, 1), (1, 0, -1))
+    add(fp, fi, white, mat=2, uv=fp[:, [0, 2]] + 0.1)
+    add(*quad((-1, 2, -1), (1, 2, -1), (1, 2, 1), (-1, 2, 1)), white)
+    add(*quad((-1, 0, -1), (1, 0, -1), (1, 2, -1), (-1, 2, -1)), white)
+    add(*quad((-1, 0, -1), (-1, 2, -1), (-1, 2, 1), (-1, 0, 1)), red)
+    add(*quad((1, 0, -1), (1, 0, 1), (1, 2, 1), (1, 2, -1)), green)
+    up, ui = icosphere_unit(3)
+    add(np.array([-0.4, 0.42, -0.4]) + 0.4 * up, ui, (0.9, 0.9, 0.9), mat=1, nrm=up)
+    add(*box_mesh((0.1, 0.0, -0.2), (0.7, 0.6, 0.4), 1), (0.2, 0.4, 0.8), mat=1)
+    add(*quad((-0.25, 1.999, -0.25), (0.25, 1.999, -0.25), (0.25, 1.999, 0.25), (-0.25, 1.999, 0.25)),
+        (0.0, 0.0, 0.0), (15.0, 15.0, 15.0))
+    mats = [(LAMBERT, 1.0, 1.5, 0.0), (COATED, float(coat[0]), float(coat[1]), 0.0),
+            (LAMBERT, 1.0, 1.5, float(freq))]
+    scene = _pack(P, I, M, A, E, mats)
+    scene["normals"] = np.concatenate(N).astype(np.float32)
+    scene["uvs"] = np.concatenate(U).astype(np.float32)
+    cam = dict(eye=(0.0, 1.0, 3.6), target=(0.0, 1.0, 0.0), up=(0.0, 1.0, 0.0),
+               vfov_deg=40.0, width=128, height=128)
     return scene, cam
 
 

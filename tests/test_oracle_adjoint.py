@@ -47,12 +47,18 @@ def _scene_with_conductor():
     return scene, dict(cam, width=20, height=20)
 
 
-@pytest.mark.parametrize("which", ["lambert", "conductor"])
+@pytest.mark.parametrize("which", ["lambert", "conductor", "attributes"])
 def test_gradient_vs_central_differences(which):
+    """attributes: smooth-shaded coated sphere, coated box, checker-textured
+    floor (the coat's lobe choice depends on Fresnel only, not on the
+    albedo, so the estimator stays a polynomial in the albedos)."""
     scene, cam = scenes.cornell()
     cam = dict(cam, width=20, height=20)
     if which == "conductor":
         scene, cam = _scene_with_conductor()
+    if which == "attributes":
+        scene, cam = scenes.cornell_attributes(coat=(0.3, 1.5))
+        cam = dict(cam, width=20, height=20)
     S = oracle.Scene(scene)
     rng = np.random.default_rng(3)
     npix = cam["width"] * cam["height"]
@@ -63,8 +69,15 @@ def test_gradient_vs_central_differences(which):
     emi0 = scene["emission"].copy()
     h = 1e-2
     checked = 0
-    # albedo: the triangles with the largest gradients, all channels
-    for t in np.argsort(-np.abs(ga).sum(1))[:6]:
+    # albedo: the triangles with the largest gradients (the two largest of
+    # each material), all channels
+    mag = np.abs(ga).sum(1)
+    cand = []
+    for m in np.unique(scene["tri_mat"]):
+        idx = np.nonzero(scene["tri_mat"] == m)[0]
+        cand += list(idx[np.argsort(-mag[idx])[:2]])
+    mats_checked = set()
+    for t in sorted(set(cand) | set(np.argsort(-mag)[:6])):
         for c in range(3):
             if abs(ga[t, c]) < 1e-3:
                 continue
@@ -75,10 +88,12 @@ def test_gradient_vs_central_differences(which):
             fd = (lp - lm) / (2 * h)
             assert abs(fd - ga[t, c]) <= 1e-2 * abs(ga[t, c]), (t, c, fd, ga[t, c])
             checked += 1
+            mats_checked.add(int(scene["tri_mat"][t]))
     S.set_params(alb0, emi0)
     assert checked >= 6
+    assert mats_checked == set(np.unique(scene["tri_mat"]).tolist()), mats_checked
     # emission of the light (linear: any step is exact up to binary32 rounding)
-    for t in [34, 35]:
+    for t in np.nonzero(emi0.any(1))[0]:
         for c in range(3):
             ep = emi0.copy(); ep[t, c] += 1.0
             S.set_params(alb0, ep); lp = loss_of(S, cam, dimg, **kw)
