@@ -50,7 +50,14 @@ enum {
     PT_EUNSUPPORTED = -6 /* option not supported */
 };
 
-enum { PT_LAMBERT = 0, PT_CONDUCTOR = 1, PT_DIELECTRIC = 2 };
+/* Material types.  PT_COATED (paper Sec. 3: a two-lobe subset of a layered
+ * material such as OpenPBR's coat over a base): a GGX dielectric coat of the
+ * material's roughness and ior over a Lambertian base of the triangle's
+ * albedo, f = F(wo.h) D G2 / (4 cos_o cos_i) + (1 - F(cos_o)) (1 - F(cos_i))
+ * albedo / pi with F the exact unpolarised Fresnel reflectance; sampled by
+ * the coat's visible normals with probability F(cos_o), else the base's
+ * cosine lobe. */
+enum { PT_LAMBERT = 0, PT_CONDUCTOR = 1, PT_DIELECTRIC = 2, PT_COATED = 3 };
 enum { PT_MODE_MEGA = 0, PT_MODE_WAVE = 1 };
 
 /* Camera samplers (pt_render_args.sampler). */
@@ -75,7 +82,9 @@ typedef struct pt_ctx pt_ctx;
 /* Triangle scene (paper Sec. 3: scene data packed on the CPU).
  * positions  float[nv*3]; indices int32[nt*3], counter-clockwise (v0,v1,v2)
  * faces the front; tri_material int32[nt] indexes materials float[nm*4]
- * = (type, roughness, ior, unused); albedo and emission float[nt*3] per
+ * = (type, roughness, ior, checker frequency): the frequency (>= 0; 0 =
+ * none) textures the albedo of Lambertian and coated materials through the
+ * vertex texture coordinates of pt_set_attributes; albedo and emission float[nt*3] per
  * triangle (emission is one-sided, front face only); sky float[3] is the
  * radiance of escaped rays.  Triangles with some emission channel > 0 at
  * load time form the fixed light set of next-event estimation (picked in
@@ -122,6 +131,31 @@ typedef struct {
 } pt_instances_desc;
 pt_status pt_set_instances(pt_ctx* ctx, const pt_instances_desc* instances);
 
+/* Vertex attributes (paper Sec. 2.3: the shading stage interpolates the
+ * hit triangle's vertex normals and texture coordinates).  nv must equal
+ * the loaded scene's vertex count; normals float[nv*3] and uvs float[nv*2]
+ * (either may be NULL) are indexed by the scene's triangle indices (object
+ * space in a two-level scene).  Interpolation at barycentrics (b1, b2):
+ * ((w0 a0 + b1 a1) + b2 a2) with w0 = (1 - b1) - b2.  Shading normal: the
+ * interpolated normal, mapped by the columns of w2o's linear part in a
+ * two-level scene, normalised and turned to the geometric normal's side
+ * (the geometric normal if the interpolant is zero or not finite).  With
+ * normals, the BSDF frame is the shading normal turned to the outgoing
+ * direction's side; a vertex whose outgoing direction is below its shading
+ * horizon scatters nothing, and light and continuation directions on the
+ * wrong geometric side for their lobe (reflection: the outgoing side,
+ * transmission: the other) are dropped.  Checker texture: with (u, v)
+ * interpolated, the albedo is scaled by 1/4 where floor(u f) + floor(v f)
+ * is odd (f the material's checker frequency).  Call after pt_load_scene
+ * (which clears them) and before pt_build_bvh; NULL desc or both arrays
+ * NULL removes them.  PT_EINVAL on a count mismatch or non-finite value. */
+typedef struct {
+    int32_t nv;
+    const float* normals;
+    const float* uvs;
+} pt_attributes_desc;
+pt_status pt_set_attributes(pt_ctx* ctx, const pt_attributes_desc* attributes);
+
 /* BVH build options (NULL = defaults). */
 typedef struct {
     int32_t max_leaf;  /* triangles per leaf, 1..8 (0 = default 1: one triangle per leaf
@@ -137,6 +171,7 @@ typedef struct {
                                         then the input ids of the 64 largest triangles */
     int64_t material_bytes;          /* 16 B per material */
     int64_t instance_count, instance_bytes; /* two-level scenes: 112 B per instance record */
+    int64_t attribute_bytes;         /* vertex attributes: 64 B per triangle, leaf order (0 without) */
     int32_t depth;                   /* BVH4 levels */
     int32_t stack_entries;           /* traversal stack entries needed */
     double build_seconds;
@@ -157,6 +192,7 @@ typedef struct {
     float* emission;
     int32_t upload_params;
     void* instances;  /* instance records (two-level scenes; may be NULL for a flat scene) */
+    void* attributes; /* vertex attribute records (may be NULL without attributes) */
 } pt_scene_buffers;
 
 /* Pinhole camera: eye, target, up, vertical field of view (degrees),

@@ -40,8 +40,9 @@ PT_DEV void adjoint_b_begin(const CamView& cam, const PathParams& pp, uint32_t p
     ar.sample = sample;
 }
 
-// One vertex of replay B; returns false when the path is finished.
-template <int LDS, class Acc, bool COUNT = false>
+// One vertex of replay B; returns false when the path is finished.  ATTR:
+// the scene may have vertex attributes (see shade_vertex).
+template <int LDS, bool ATTR = false, class Acc, bool COUNT = false>
 PT_DEV bool adjoint_b_step(const SceneView& sc, const PathParams& pp, AdjRun& ar, float* __restrict__ g_alb,
                            float* __restrict__ g_emi, TravStack<LDS, COUNT>& st, Acc& acc) {
     const f3 delta = ar.delta, Ltot = ar.Ltot;
@@ -53,7 +54,7 @@ PT_DEV bool adjoint_b_step(const SceneView& sc, const PathParams& pp, AdjRun& ar
     Hit h = closest_hit<LDS>(sc, ray, INFINITY, st);
     const f3 beta = ps.beta;
     ShadowReq sh;
-    VertexOut vo = shade_vertex(sc, pp, pix, sample, k, d, h, ps, sh);
+    VertexOut vo = shade_vertex<false, ATTR>(sc, pp, pix, sample, k, d, h, ps, sh);
     add_radiance(ps, vo);
     if (vo.id == 0xFFFFFFFFu) return false;  // escaped: the sky is not a parameter
     const uint32_t id = vo.id;
@@ -109,15 +110,15 @@ PT_DEV bool adjoint_b_step(const SceneView& sc, const PathParams& pp, AdjRun& ar
 }
 
 // The whole path: replay A, then replay B vertex by vertex.
-template <int LDS, class Acc, bool COUNT = false>
+template <int LDS, bool ATTR = false, class Acc, bool COUNT = false>
 PT_DEV void adjoint_path(const SceneView& sc, const CamView& cam, const PathParams& pp, uint32_t pix, uint32_t sample,
                          f3 delta, float* __restrict__ g_alb, float* __restrict__ g_emi, TravStack<LDS, COUNT>& st,
                          Acc& acc) {
     uint32_t ne = 0, ns = 0;
-    const f3 Ltot = trace_path<LDS>(sc, cam, pp, pix, sample, st, ne, ns);
+    const f3 Ltot = trace_path<LDS, COUNT, false, ATTR>(sc, cam, pp, pix, sample, st, ne, ns);
     AdjRun ar;
     adjoint_b_begin(cam, pp, pix, sample, delta, Ltot, ar);
-    while (adjoint_b_step<LDS>(sc, pp, ar, g_alb, g_emi, st, acc)) {
+    while (adjoint_b_step<LDS, ATTR>(sc, pp, ar, g_alb, g_emi, st, acc)) {
     }
 }
 

@@ -44,7 +44,7 @@ struct AtomicAcc {
 // one path vertex; a lane whose path is done takes the next path of its
 // wave's chunk, a wave whose chunk is used up takes the next 64 paths from
 // cursor[0].  Five waves per SIMD, as the megakernel.
-template <int LDS>
+template <int LDS, bool ATTR>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k_adjoint_radiance(
     SceneView sc, CamView cam, PathParams pp, float4* __restrict__ Lpath, unsigned long long* __restrict__ cursor,
     uint2* __restrict__ ovf, int gcap, uint32_t* __restrict__ stats) {
@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k
             continue;
         }
         if (!live) continue;
-        if (path_vertex<LDS>(sc, pp, pix, sample, pr, st, ne, ns)) continue;
+        if (path_vertex<LDS, false, false, ATTR>(sc, pp, pix, sample, pr, st, ne, ns)) continue;
         Lpath[path] = make_float4(pr.ps.L.x, pr.ps.L.y, pr.ps.L.z, 0.f);
         live = false;
     }
@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k
 
 // Replay B of every path, one vertex per loop trip with the same hand-out
 // of paths (cursor[1]), from the radiance replay A left in Lpath.
-template <int LDS>
+template <int LDS, bool ATTR>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_adjoint(SceneView sc, CamView cam, PathParams pp,
                                                  const float* __restrict__ d_img, const float4* __restrict__ Lpath,
                                                  unsigned long long* __restrict__ cursor, float* __restrict__ g_alb,
@@ -172,7 +172,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
             continue;
         }
         if (!live) continue;
-        if (!adjoint_b_step<LDS>(sc, pp, ar, g_alb, g_emi, st, acc)) live = false;
+        if (!adjoint_b_step<LDS, ATTR>(sc, pp, ar, g_alb, g_emi, st, acc)) live = false;
     }
     // every thread of the block is here: add the block's sums
     __syncthreads();
@@ -195,7 +195,12 @@ hipError_t launch_adjoint_radiance(int lds, dim3 grid, dim3 block, hipStream_t s
     size_t sm = trav_stack_lds_bytes(lds, (int)block.x);
 #define X(N)                                                                                                  \
     if (lds == N) {                                                                                           \
-        hipLaunchKernelGGL(k_adjoint_radiance<N>, grid, block, sm, s, sc, cam, pp, Lpath, cursor, ovf, gcap, stats); \
+        if (sc.attr_flags)                                                                                    \
+            hipLaunchKernelGGL((k_adjoint_radiance<N, true>), grid, block, sm, s, sc, cam, pp, Lpath, cursor, ovf, \
+                               gcap, stats);                                                                  \
+        else                                                                                                  \
+            hipLaunchKernelGGL((k_adjoint_radiance<N, false>), grid, block, sm, s, sc, cam, pp, Lpath, cursor, ovf, \
+                               gcap, stats);                                                                  \
         return hipGetLastError();                                                                             \
     }
     X(8) X(16) X(24) X(32)
@@ -209,8 +214,12 @@ hipError_t launch_adjoint(int lds, dim3 grid, dim3 block, hipStream_t s, const S
     size_t sm = trav_stack_lds_bytes(lds, (int)block.x);
 #define X(N)                                                                                                  \
     if (lds == N) {                                                                                           \
-        hipLaunchKernelGGL(k_adjoint<N>, grid, block, sm, s, sc, cam, pp, d_img, Lpath, cursor, g_alb, g_emi, ovf, \
-                           gcap, stats);                                                                      \
+        if (sc.attr_flags)                                                                                    \
+            hipLaunchKernelGGL((k_adjoint<N, true>), grid, block, sm, s, sc, cam, pp, d_img, Lpath, cursor, g_alb, \
+                               g_emi, ovf, gcap, stats);                                                      \
+        else                                                                                                  \
+            hipLaunchKernelGGL((k_adjoint<N, false>), grid, block, sm, s, sc, cam, pp, d_img, Lpath, cursor, g_alb, \
+                               g_emi, ovf, gcap, stats);                                                      \
         return hipGetLastError();                                                                             \
     }
     X(8) X(16) X(24) X(32)

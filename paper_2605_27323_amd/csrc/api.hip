@@ -63,6 +63,13 @@ struct pt_ctx {
     float sky[3] = {0, 0, 0};
     BuildResult bvh;
     InstanceSet inst;  // two-level scene (no instances: flat)
+    // vertex attributes per triangle corner (input order; empty = none):
+    // normals nt * 9, texture coordinates nt * 6; attr_leaf: the device
+    // records in leaf order (kAttrRecord float4 per triangle)
+    int32_t nv = 0;
+    std::vector<int32_t> tri_idx;
+    std::vector<float> attr_n, attr_uv;
+    std::vector<float4> attr_leaf;
     SceneView view{};
     CamView cam{};
     // profiling
@@ -330,6 +337,8 @@ SceneView make_view(const pt_ctx* c, const pt_scene_buffers* b) {
     v.n_hot = (int32_t)c->bvh.hot_ids.size();
     v.insts = c->bvh.insts.empty() ? nullptr : reinterpret_cast<const float4*>(b->instances);
     v.n_inst = (int32_t)(c->bvh.insts.size() / kInstRecord);
+    v.attrs = c->attr_leaf.empty() ? nullptr : reinterpret_cast<const float4*>(b->attributes);
+    v.attr_flags = c->attr_leaf.empty() ? 0 : ((c->attr_n.empty() ? 0 : kAttrNormals) | (c->attr_uv.empty() ? 0 : kAttrUV));
     return v;
 }
 
@@ -409,9 +418,10 @@ pt_status pt_load_scene(pt_ctx* c, const pt_scene_desc* s) {
     for (int i = 0; i < s->nm; ++i) {
         const float* m = s->materials + 4 * i;
         int t = (int)m[0];
-        if ((float)t != m[0] || t < PT_LAMBERT || t > PT_DIELECTRIC) return fail(PT_EINVAL, "unknown material type");
+        if ((float)t != m[0] || t < PT_LAMBERT || t > PT_COATED) return fail(PT_EINVAL, "unknown material type");
         if (!(m[1] >= 0.f && m[1] <= 1.f)) return fail(PT_EINVAL, "roughness must be in [0, 1]");
-        if (t == PT_DIELECTRIC && !(m[2] > 0.f && std::isfinite(m[2]))) return fail(PT_EINVAL, "bad ior");
+        if ((t == PT_DIELECTRIC || t == PT_COATED) && !(m[2] > 0.f && std::isfinite(m[2]))) return fail(PT_EINVAL, "bad ior");
+        if (!(m[3] >= 0.f && std::isfinite(m[3]))) return fail(PT_EINVAL, "checker frequency must be finite and >= 0");
     }
     c->nt = s->nt;
     c->nm = s->nm;
@@ -434,6 +444,11 @@ pt_status pt_load_scene(pt_ctx* c, const pt_scene_desc* s) {
     c->mats.assign(s->materials, s->materials + 4 * (size_t)s->nm);
     std::memcpy(c->sky, s->sky, sizeof c->sky);
     c->inst = InstanceSet{};
+    c->nv = s->nv;
+    c->tri_idx.assign(s->indices, s->indices + 3 * (size_t)s->nt);
+    c->attr_n.clear();
+    c->attr_uv.clear();
+    c->attr_leaf.clear();
     c->loaded = true;
     c->built = false;
     c->bound = false;
@@ -475,6 +490,37 @@ pt_status pt_set_instances(pt_ctx* c, const pt_instances_desc* d) {
     return PT_OK;
 }
 
+pt_status pt_set_attributes(pt_ctx* c, const pt_attributes_desc* d) {
+    if (!c) return fail(PT_EINVAL, "null context");
+    if (!c->loaded) return fail(PT_ESTATE, "no scene loaded");
+    std::vector<float> an, au;
+    if (d && (d->normals || d->uvs)) {
+        if (d->nv != c->nv) return fail(PT_EINVAL, "attribute count differs from the scene's vertex count");
+        for (int64_t i = 0; d->normals && i < 3 * (int64_t)d->nv; ++i)
+            if (!std::isfinite(d->normals[i])) return fail(PT_EINVAL, "non-finite vertex normal");
+        for (int64_t i = 0; d->uvs && i < 2 * (int64_t)d->nv; ++i)
+            if (!std::isfinite(d->uvs[i])) return fail(PT_EINVAL, "non-finite texture coordinate");
+        if (d->normals) {
+            an.resize(9 * (size_t)c->nt);
+            for (size_t i = 0; i < (size_t)c->nt; ++i)
+                for (int k = 0; k < 3; ++k)
+                    for (int a = 0; a < 3; ++a) an[9 * i + 3 * k + a] = d->normals[3 * (size_t)c->tri_idx[3 * i + k] + a];
+        }
+        if (d->uvs) {
+            au.resize(6 * (size_t)c->nt);
+            for (size_t i = 0; i < (size_t)c->nt; ++i)
+                for (int k = 0; k < 3; ++k)
+                    for (int a = 0; a < 2; ++a) au[6 * i + 2 * k + a] = d->uvs[2 * (size_t)c->tri_idx[3 * i + k] + a];
+        }
+    }
+    c->attr_n = std::move(an);
+    c->attr_uv = std::move(au);
+    c->attr_leaf.clear();
+    c->built = false;
+    c->bound = false;
+    return PT_OK;
+}
+
 pt_status pt_build_bvh(pt_ctx* c, const pt_bvh_opts* o, pt_bvh_info* info) {
     if (!c) return fail(PT_EINVAL, "null context");
     if (!c->loaded) return fail(PT_ESTATE, "no scene loaded");
@@ -489,6 +535,24 @@ pt_status pt_build_bvh(pt_ctx* c, const pt_bvh_opts* o, pt_bvh_info* info) {
     } catch (const std::exception& e) {
         return fail(PT_ENOMEM, std::string("BVH build failed: ") + e.what());
     }
+    // attribute records in leaf order, keyed by each triangle record's input id
+    c->attr_leaf.clear();
+    if (!c->attr_n.empty() || !c->attr_uv.empty()) {
+        const size_t n = c->bvh.tris.size() / 3;
+        c->attr_leaf.assign(kAttrRecord * n, make_float4(0.f, 0.f, 0.f, 0.f));
+        for (size_t j = 0; j < n; ++j) {
+            uint32_t id;
+            std::memcpy(&id, &c->bvh.tris[3 * j].w, sizeof id);
+            float nn[9] = {}, uv[6] = {};
+            if (!c->attr_n.empty()) std::memcpy(nn, &c->attr_n[9 * (size_t)id], sizeof nn);
+            if (!c->attr_uv.empty()) std::memcpy(uv, &c->attr_uv[6 * (size_t)id], sizeof uv);
+            float4* r = &c->attr_leaf[kAttrRecord * j];
+            r[0] = make_float4(nn[0], nn[1], nn[2], uv[0]);
+            r[1] = make_float4(nn[3], nn[4], nn[5], uv[1]);
+            r[2] = make_float4(nn[6], nn[7], nn[8], uv[2]);
+            r[3] = make_float4(uv[3], uv[4], uv[5], 0.f);
+        }
+    }
     double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     c->built = true;
     c->bound = false;
@@ -502,6 +566,7 @@ pt_status pt_build_bvh(pt_ctx* c, const pt_bvh_opts* o, pt_bvh_info* info) {
         info->material_bytes = (int64_t)(c->mats.size() * sizeof(float));
         info->instance_count = (int64_t)(c->bvh.insts.size() / kInstRecord);
         info->instance_bytes = (int64_t)(c->bvh.insts.size() * sizeof(float4));
+        info->attribute_bytes = (int64_t)(c->attr_leaf.size() * sizeof(float4));
         info->depth = c->bvh.depth;
         info->stack_entries = c->bvh.stack_entries;
         info->build_seconds = secs;
@@ -529,6 +594,8 @@ pt_status pt_bind_scene(pt_ctx* c, const pt_scene_buffers* b, void* stream) {
     if (c->nt > 0 && (!b->albedo || !b->emission)) return fail(PT_EINVAL, "null albedo/emission");
     if (!c->bvh.insts.empty() && (!b->instances || (reinterpret_cast<uintptr_t>(b->instances) % kAlign) != 0))
         return fail(PT_EINVAL, "a two-level scene needs a 256-byte aligned instance buffer");
+    if (!c->attr_leaf.empty() && (!b->attributes || (reinterpret_cast<uintptr_t>(b->attributes) % kAlign) != 0))
+        return fail(PT_EINVAL, "vertex attributes need a 256-byte aligned attribute buffer");
     PT_HIP(hipSetDevice(c->device), "hipSetDevice");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     PT_HIP(hipMemcpyAsync(b->nodes, c->bvh.nodes.data(), c->bvh.nodes.size() * sizeof(Node4), hipMemcpyHostToDevice, s), "upload nodes");
@@ -545,6 +612,10 @@ pt_status pt_bind_scene(pt_ctx* c, const pt_scene_buffers* b, void* stream) {
         PT_HIP(hipMemcpyAsync(b->instances, c->bvh.insts.data(), c->bvh.insts.size() * sizeof(float4),
                               hipMemcpyHostToDevice, s),
                "upload instances");
+    if (!c->attr_leaf.empty())
+        PT_HIP(hipMemcpyAsync(b->attributes, c->attr_leaf.data(), c->attr_leaf.size() * sizeof(float4),
+                              hipMemcpyHostToDevice, s),
+               "upload vertex attributes");
     if (b->upload_params && c->nt > 0) {
         PT_HIP(hipMemcpyAsync(b->albedo, c->albedo.data(), c->albedo.size() * sizeof(float), hipMemcpyHostToDevice, s), "upload albedo");
         PT_HIP(hipMemcpyAsync(b->emission, c->emission.data(), c->emission.size() * sizeof(float), hipMemcpyHostToDevice, s), "upload emission");
@@ -878,6 +949,7 @@ struct BatchPlan {
     Launch L{};
     uint32_t capacity = 0;
     int iters_per_graph = 8, use_graph = 1;
+    bool attr = false;  // some job's scene has vertex attributes
     // workspace offsets
     size_t o_jobs = 0, o_ctl = 0, o_rem = 0, o_ts = 0, o_pool = 0, o_L = 0, o_ovf = 0, total_bytes = 0;
 };
@@ -903,6 +975,7 @@ pt_status plan_batch(const pt_job* jobs, const std::vector<int>& members, const 
         }
         JobDesc& d = P.jobs[j];
         d.sc = jb.ctx->view;
+        P.attr = P.attr || d.sc.attr_flags != 0;
         d.cam = jb.ctx->cam;
         d.pp = PathParams{jb.args.spp, jb.args.max_depth, jb.args.nee ? 1 : 0, jb.args.rr_start, jb.args.seed,
                           jb.args.frame, jb.args.job, jb.args.sampler};
@@ -1094,7 +1167,7 @@ pt_status pt_render_batch(const pt_job* jobs, int32_t n, const pt_batch_opts* o,
             PT_HIP(hipStreamBeginCapture(p.s, hipStreamCaptureModeThreadLocal), "begin capture");
             hipError_t ce = hipSuccess;
             for (int it = 0; it < P.iters_per_graph && ce == hipSuccess; ++it)
-                ce = launch_batch_iteration(P.L.lds, grid, block, p.s, p.bb, it & 1, ovf, P.L.gcap);
+                ce = launch_batch_iteration(P.L.lds, grid, block, p.s, p.bb, it & 1, ovf, P.L.gcap, P.attr);
             hipError_t ee = hipStreamEndCapture(p.s, &p.g);
             if (ce != hipSuccess) return hip_fail(ce, "capture launches");
             if (ee != hipSuccess) return hip_fail(ee, "end capture");
@@ -1112,7 +1185,8 @@ pt_status pt_render_batch(const pt_job* jobs, int32_t n, const pt_batch_opts* o,
         } else {
             uint2* ovf = reinterpret_cast<uint2*>(base + offs[k] + P.o_ovf);
             for (int it = 0; it < 2; ++it)
-                PT_HIP(launch_batch_iteration(P.L.lds, dim3(P.L.grid), dim3(P.L.block), p.s, p.bb, it & 1, ovf, P.L.gcap),
+                PT_HIP(launch_batch_iteration(P.L.lds, dim3(P.L.grid), dim3(P.L.block), p.s, p.bb, it & 1, ovf, P.L.gcap,
+                                              P.attr),
                        "batch iteration");
             p.iters += 2;
         }

@@ -114,7 +114,8 @@ PT_DEV void batch_extend_item(const BatchBufs& bb, int q, uint32_t i, TravStack<
 
 // shade slot i of queue q; returns true if the path finished here (the
 // caller decrements its job's counter); vo / sh / ps / meta describe what
-// to enqueue
+// to enqueue.  ATTR: some job's scene has vertex attributes.
+template <bool ATTR = false>
 PT_DEV bool batch_shade_item(const BatchBufs& bb, int q, uint32_t i, VertexOut& vo, ShadowReq& sh, PathState& ps,
                              uint32_t& g, uint32_t& meta) {
     const float4 o4 = bb.ray_o[q][i], d4 = bb.ray_d[q][i], p4 = bb.pst[q][i], h4 = bb.hit[i];
@@ -135,7 +136,7 @@ PT_DEV bool batch_shade_item(const BatchBufs& bb, int q, uint32_t i, VertexOut& 
     h.tri = f2u(h4.w);
     h.id = 0;
     hit_barycentrics(jd.sc, xyz(o4), xyz(d4), h);
-    vo = shade_vertex(jd.sc, jd.pp, pix, sample, (int)k, xyz(d4), h, ps, sh);
+    vo = shade_vertex<false, ATTR>(jd.sc, jd.pp, pix, sample, (int)k, xyz(d4), h, ps, sh);
     if (vo.addL) {  // the radiance is read only where this vertex adds to it
         ps.L = xyz(bb.L[g]);
         add_radiance(ps, vo);

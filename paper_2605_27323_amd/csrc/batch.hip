@@ -110,6 +110,7 @@ k_batch_extend(BatchBufs bb, int q, uint2* __restrict__ ovf, int gcap) {
 
 // slots of the next queue and of the shadow queue reserved once per block
 // and trip (see k_shade)
+template <bool ATTR>
 __global__ void __launch_bounds__(256) k_batch_shade(BatchBufs bb, int q) {
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t count = bb.ctl->count;
@@ -124,7 +125,7 @@ __global__ void __launch_bounds__(256) k_batch_shade(BatchBufs bb, int q) {
         sh.valid = false;
         uint32_t g = 0, meta = 0;
         bool finished = false;
-        if (i < count) finished = batch_shade_item(bb, q, i, vo, sh, ps, g, meta);
+        if (i < count) finished = batch_shade_item<ATTR>(bb, q, i, vo, sh, ps, g, meta);
         jobs_finished(bb, finished, meta >> 24);
         const uint64_t mk = __ballot(vo.cont), ms = __ballot(sh.valid);
         uint32_t jc, js;
@@ -195,14 +196,17 @@ hipError_t launch_batch_init(hipStream_t s, const BatchBufs& bb, uint32_t total)
 
 // one iteration of the pool on queue parity q
 hipError_t launch_batch_iteration(int lds, dim3 grid, dim3 block, hipStream_t s, const BatchBufs& bb, int q,
-                                  uint2* ovf, int gcap) {
+                                  uint2* ovf, int gcap, bool attr) {
     const size_t sm = trav_stack_lds_bytes(lds, (int)block.x);
     hipLaunchKernelGGL(k_batch_sched, dim3(1), dim3(64), 0, s, bb, q);
     hipLaunchKernelGGL(k_batch_regen, grid, block, 0, s, bb, q);
 #define X(N)                                                                              \
     if (lds == N) {                                                                       \
         hipLaunchKernelGGL(k_batch_extend<N>, grid, block, sm, s, bb, q, ovf, gcap);      \
-        hipLaunchKernelGGL(k_batch_shade, grid, block, 0, s, bb, q);                      \
+        if (attr)                                                                         \
+            hipLaunchKernelGGL(k_batch_shade<true>, grid, block, 0, s, bb, q);            \
+        else                                                                              \
+            hipLaunchKernelGGL(k_batch_shade<false>, grid, block, 0, s, bb, q);           \
         hipLaunchKernelGGL(k_batch_shadow<N>, grid, block, sm, s, bb, ovf, gcap);         \
         return hipGetLastError();                                                         \
     }

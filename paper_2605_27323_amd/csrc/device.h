@@ -980,6 +980,57 @@ PT_DEV f3 to_world(const Frame& f, f3 l) {
 }
 
 // ---------------------------------------------------------------------------
+// vertex attributes at a hit (paper Sec. 2.3: the shading stage rebuilds the
+// hit's attributes from its triangle and barycentrics): weights
+// (w0, b1, b2), w0 = (1 - b1) - b2, summed as ((w0 a0 + b1 a1) + b2 a2)
+// ---------------------------------------------------------------------------
+PT_DEV float interp3(float a0, float a1, float a2, float w0, float b1, float b2) {
+    return (w0 * a0 + b1 * a1) + b2 * a2;
+}
+
+// Shading normal of hit h: the interpolated vertex normal (object space in a
+// two-level scene, mapped by the inverse transpose of the instance's
+// object-to-world map = the columns of its world-to-object rows),
+// normalised once and turned to the side of the geometric normal ng; ng
+// itself when the interpolant is zero or not finite.
+template <bool INST>
+PT_DEV f3 shading_normal(const SceneView& sc, const Hit& h, f3 ng) {
+    const float4* ap = sc.attrs + (size_t)h.tri * kAttrRecord;
+    const float4 a0 = ap[0], a1 = ap[1], a2 = ap[2];
+    const float w0 = (1.0f - h.b1) - h.b2;
+    f3 m = mk3(interp3(a0.x, a1.x, a2.x, w0, h.b1, h.b2), interp3(a0.y, a1.y, a2.y, w0, h.b1, h.b2),
+               interp3(a0.z, a1.z, a2.z, w0, h.b1, h.b2));
+    if constexpr (INST) {
+        const float4* ip = sc.insts + (size_t)h.inst * kInstRecord;
+        const float4 r0 = ip[0], r1 = ip[1], r2 = ip[2];
+        m = mk3((r0.x * m.x + r1.x * m.y) + r2.x * m.z, (r0.y * m.x + r1.y * m.y) + r2.y * m.z,
+                (r0.z * m.x + r1.z * m.y) + r2.z * m.z);
+    }
+    const float l2 = dot3(m, m);
+    if (!(l2 > 0.0f && l2 <= 3.40282347e38f)) return ng;
+    const f3 ns = normalize3(m);
+    return dot3(ns, ng) < 0.0f ? neg3(ns) : ns;
+}
+
+// Checker texture of the albedo: cell (floor(u f), floor(v f)) of the
+// interpolated texture coordinates; the factor is 1/4 where the two cell
+// indices differ in parity, else 1.  Parity of floor(x): floor(x) / 2 is an
+// integer or a half, both exact in binary32.
+constexpr float kCheckerDark = 0.25f;
+PT_DEV bool odd_cell(float x) {
+    const float f = floorf(x);
+    const float hf = f * 0.5f;
+    return floorf(hf) != hf;
+}
+PT_DEV float checker(const SceneView& sc, const Hit& h, float freq) {
+    const float4* ap = sc.attrs + (size_t)h.tri * kAttrRecord;
+    const float4 a0 = ap[0], a1 = ap[1], a2 = ap[2], a3 = ap[3];
+    const float w0 = (1.0f - h.b1) - h.b2;
+    const float u = interp3(a0.w, a2.w, a3.y, w0, h.b1, h.b2), v = interp3(a1.w, a3.x, a3.z, w0, h.b1, h.b2);
+    return odd_cell(u * freq) != odd_cell(v * freq) ? kCheckerDark : 1.0f;
+}
+
+// ---------------------------------------------------------------------------
 // materials
 // ---------------------------------------------------------------------------
 PT_DEV float ggx_alpha(float rough) {
@@ -1016,8 +1067,10 @@ PT_DEV f3 ggx_vndf(f3 wo, float alpha, float u5, float u6) {
 PT_DEV float pow5(float m) { return ((m * m) * (m * m)) * m; }
 
 // Albedo-free factors of a lobe, kept for the adjoint: f (or the sampling
-// weight) = Lambert: albedo * k; conductor: (albedo + (1 - albedo) m5) * k;
-// dielectric: k, untinted.
+// weight) = Lambert: albedo * k (k holds the texture factor); conductor:
+// (albedo + (1 - albedo) m5) * k; dielectric: k, untinted; coated:
+// albedo * k + m5 (k: the base seen through the coat, m5: the coat's
+// specular term).
 struct Lobe {
     int type;
     float m5, k;
@@ -1027,17 +1080,50 @@ struct Lobe {
 PT_DEV float lobe_value(const Lobe& lb, float rho) {
     if (lb.type == PT_LAMBERT) return rho * lb.k;
     if (lb.type == PT_CONDUCTOR) return (rho + (1.0f - rho) * lb.m5) * lb.k;
+    if (lb.type == PT_COATED) return rho * lb.k + lb.m5;
     return lb.k;
 }
 PT_DEV float lobe_der(const Lobe& lb) {
-    if (lb.type == PT_LAMBERT) return lb.k;
+    if (lb.type == PT_LAMBERT || lb.type == PT_COATED) return lb.k;
     if (lb.type == PT_CONDUCTOR) return (1.0f - lb.m5) * lb.k;
     return 0.0f;
 }
 
+PT_DEV float fresnel_dielectric(float ci, float eta);
+
+// Coated material: a GGX dielectric coat of index ior over a Lambertian base,
+// f = F(wo.h) D G2 / (4 cos_o cos_i) + (1 - F(cos_o)) (1 - F(cos_i)) tex
+// albedo / pi, pdf = F(cos_o) G1 D / (4 cos_o) + (1 - F(cos_o)) cos_i / pi
+// (the mixture the sampler draws from).  wo, wi above the surface.
+PT_DEV void eval_coat(float rough, float ior, float tex, f3 alb, f3 wo, f3 wi, f3& f, float& pdf, Lobe& lb) {
+    const float alpha = ggx_alpha(rough), a2 = alpha * alpha;
+    const f3 h = normalize3(add3(wo, wi));
+    const float D = ggx_D(h, a2);
+    const float lo = ggx_lambda(wo, a2), li = ggx_lambda(wi, a2);
+    const float G1 = 1.0f / (1.0f + lo);
+    const float G2 = 1.0f / ((1.0f + lo) + li);
+    const float Fh = fresnel_dielectric(dot3(wo, h), ior);
+    const float fs = ((Fh * D) * G2) / ((4.0f * wo.z) * wi.z);
+    const float Fo = fresnel_dielectric(wo.z, ior), Fi = fresnel_dielectric(wi.z, ior);
+    const float kd = (((1.0f - Fo) * (1.0f - Fi)) * tex) * kInvPi;
+    f = mk3(alb.x * kd + fs, alb.y * kd + fs, alb.z * kd + fs);
+    pdf = Fo * ((G1 * D) / (4.0f * wo.z)) + (1.0f - Fo) * (wi.z * kInvPi);
+    lb.k = kd;
+    lb.m5 = fs;
+}
+
+// cosine-weighted direction about +z
+PT_DEV f3 cosine_dir(float u5, float u6) {
+    float r = sqrtf(u5), c, s;
+    cos_sin_2pi(u6, c, s);
+    float z2 = 1.0f - u5;
+    return mk3(r * c, r * s, sqrtf(z2 > 0.0f ? z2 : 0.0f));
+}
+
 // f and the solid-angle pdf of an opaque material, wo and wi in the local
 // frame of the normal on wo's side.
-PT_DEV void eval_opaque(int type, float rough, f3 alb, f3 wo, f3 wi, f3& f, float& pdf, Lobe& lb) {
+PT_DEV void eval_opaque(int type, float rough, float ior, float tex, f3 alb, f3 wo, f3 wi, f3& f, float& pdf,
+                        Lobe& lb) {
     f = mk3(0.0f, 0.0f, 0.0f);
     pdf = 0.0f;
     lb.type = type;
@@ -1045,9 +1131,14 @@ PT_DEV void eval_opaque(int type, float rough, f3 alb, f3 wo, f3 wi, f3& f, floa
     lb.k = 0.0f;
     if (wi.z <= 0.0f || wo.z <= 0.0f) return;
     if (type == PT_LAMBERT) {
-        f = mk3(alb.x * kInvPi, alb.y * kInvPi, alb.z * kInvPi);
+        const float k = tex * kInvPi;
+        f = mk3(alb.x * k, alb.y * k, alb.z * k);
         pdf = wi.z * kInvPi;
-        lb.k = kInvPi;
+        lb.k = k;
+        return;
+    }
+    if (type == PT_COATED) {
+        eval_coat(rough, ior, tex, alb, wo, wi, f, pdf, lb);
         return;
     }
     float alpha = ggx_alpha(rough), a2 = alpha * alpha;
@@ -1075,23 +1166,45 @@ PT_DEV float fresnel_dielectric(float ci, float eta) {
 }
 
 // Sample a continuation direction in the local frame; false = rejected.
-PT_DEV bool sample_local(int type, float rough, float ior, bool entering, f3 alb, f3 wo, float u4, float u5,
-                         float u6, f3& wi, f3& weight, float& pdf, Lobe& lb) {
+PT_DEV bool sample_local(int type, float rough, float ior, float tex, bool entering, f3 alb, f3 wo, float u4,
+                         float u5, float u6, f3& wi, f3& weight, float& pdf, Lobe& lb) {
     lb.type = type;
     lb.m5 = 0.0f;
     lb.k = 0.0f;
     if (type == PT_LAMBERT) {
-        float r = sqrtf(u5), c, s;
-        cos_sin_2pi(u6, c, s);
-        float z2 = 1.0f - u5;
-        wi = mk3(r * c, r * s, sqrtf(z2 > 0.0f ? z2 : 0.0f));
-        weight = alb;
+        wi = cosine_dir(u5, u6);
+        weight = mk3(alb.x * tex, alb.y * tex, alb.z * tex);
         pdf = wi.z * kInvPi;
-        lb.k = 1.0f;
+        lb.k = tex;
         return true;
     }
     if (wo.z <= 0.0f) return false;
     float alpha = ggx_alpha(rough), a2 = alpha * alpha;
+    if (type == PT_COATED) {
+        // the coat's visible normals with probability F(cos_o), else the
+        // base's cosine lobe; weight f cos_i / (mixture pdf)
+        const float Fo = fresnel_dielectric(wo.z, ior);
+        f3 w;
+        if (u4 < Fo) {
+            const f3 m = ggx_vndf(wo, alpha, u5, u6);
+            const float com = dot3(wo, m);
+            w = mk3((2.0f * com) * m.x - wo.x, (2.0f * com) * m.y - wo.y, (2.0f * com) * m.z - wo.z);
+        } else {
+            w = cosine_dir(u5, u6);
+        }
+        if (w.z <= 0.0f) return false;
+        f3 f;
+        float p;
+        eval_coat(rough, ior, tex, alb, wo, w, f, p, lb);
+        if (!(p > 0.0f)) return false;
+        const float sc = w.z / p;
+        lb.k = lb.k * sc;
+        lb.m5 = lb.m5 * sc;
+        wi = w;
+        weight = mk3(alb.x * lb.k + lb.m5, alb.y * lb.k + lb.m5, alb.z * lb.k + lb.m5);
+        pdf = p;
+        return true;
+    }
     f3 m = ggx_vndf(wo, alpha, u5, u6);
     float com = dot3(wo, m);
     float lo = ggx_lambda(wo, a2);
@@ -1240,7 +1353,10 @@ PT_DEV f3 load3(const float* __restrict__ p, uint32_t i) {
 // INST (two-level scene): the hit triangle's vertices are mapped to world
 // space by its instance record's object-to-world rows, and so are the
 // sampled light's (its instance record is the light table's last word).
-template <bool INST = false>
+// ATTR: the scene may have vertex attributes (shading normals, texture
+// coordinates); without it the attribute code is compiled out, so scenes
+// without attributes keep the smaller register budget.
+template <bool INST = false, bool ATTR = false>
 PT_DEV VertexOut shade_vertex(const SceneView& sc, const PathParams& pp, uint32_t pixel, uint32_t sample, int k,
                               f3 rd, const Hit& h, PathState& ps, ShadowReq& sh,
                               const LightCache& lc = no_light_cache()) {
@@ -1307,16 +1423,29 @@ PT_DEV VertexOut shade_vertex(const SceneView& sc, const PathParams& pp, uint32_
     if (!more) return out;
     int type = (int)mat.x;
     float rough = mat.y, ior = mat.z;
+    // vertex attributes: the shading normal (the BSDF frame) and the
+    // checker factor of the albedo
+    const bool nrm = ATTR && (sc.attr_flags & kAttrNormals) != 0;
+    float tex = 1.0f;
+    if (ATTR && (sc.attr_flags & kAttrUV) && (type == PT_LAMBERT || type == PT_COATED) && mat.w > 0.0f)
+        tex = checker(sc, h, mat.w);
+    const f3 ns = nrm ? shading_normal<INST>(sc, h, ng) : ng;
     bool entering = true;
-    f3 n;
+    f3 n, ngf;
     if (type == PT_DIELECTRIC) {
         entering = cos_e > 0.0f;
-        n = entering ? ng : neg3(ng);
+        n = entering ? ns : neg3(ns);
+        ngf = entering ? ng : neg3(ng);
     } else {
-        n = cos_e > 0.0f ? ng : neg3(ng);
+        n = cos_e > 0.0f ? ns : neg3(ns);
+        ngf = cos_e > 0.0f ? ng : neg3(ng);
     }
     Frame fr = make_frame(n);
     f3 wo_l = to_local(fr, wo);
+    // with shading normals: nothing scatters from below the shading
+    // horizon, and directions on the wrong geometric side for their lobe
+    // are dropped (no light leaks through the surface)
+    if (nrm && wo_l.z <= 0.0f) return out;
     if (nee && type != PT_DIELECTRIC) {
         f3 y = tri_point(xyz(la), xyz(lb4), xyz(lc4), unif(rn.w[1]), unif(rn.w[2]));
         f3 ny = tri_normal(xyz(la), xyz(lb4), xyz(lc4));
@@ -1326,11 +1455,11 @@ PT_DEV VertexOut shade_vertex(const SceneView& sc, const PathParams& pp, uint32_
             f3 wl = scl3(dv, 1.0f / sqrtf(d2));
             float cos_y = -dot3(ny, wl);
             float cos_x = dot3(n, wl);
-            if (cos_y > 0.0f && cos_x > 0.0f) {
+            if (cos_y > 0.0f && cos_x > 0.0f && (!nrm || dot3(ngf, wl) > 0.0f)) {
                 f3 f;
                 float pb;
                 Lobe lob;
-                eval_opaque(type, rough, alb, wo_l, to_local(fr, wl), f, pb, lob);
+                eval_opaque(type, rough, ior, tex, alb, wo_l, to_local(fr, wl), f, pb, lob);
                 float pl = d2 / (sc.area_total * cos_y);
                 if (lob.k > 0.0f && pl > 0.0f) {
                     float wmis = (pl * pl) / (pl * pl + pb * pb);
@@ -1353,11 +1482,16 @@ PT_DEV VertexOut shade_vertex(const SceneView& sc, const PathParams& pp, uint32_
     f3 wi_l, W;
     float pb;
     Lobe lb;
-    bool ok = sample_local(type, rough, ior, entering, alb, wo_l, unif(rn.w[4]), unif(rn.w[5]), unif(rn.w[6]), wi_l,
-                           W, pb, lb);
+    bool ok = sample_local(type, rough, ior, tex, entering, alb, wo_l, unif(rn.w[4]), unif(rn.w[5]), unif(rn.w[6]),
+                           wi_l, W, pb, lb);
     if (!ok) return out;
     if (W.x == 0.0f && W.y == 0.0f && W.z == 0.0f) return out;
     if (type != PT_DIELECTRIC && !(pb > 0.0f)) return out;
+    f3 wi = to_world(fr, wi_l);
+    if (nrm) {
+        const float cg = dot3(ngf, wi);
+        if (wi_l.z > 0.0f ? !(cg > 0.0f) : !(cg < 0.0f)) return out;
+    }
     ps.beta = mk3(ps.beta.x * W.x, ps.beta.y * W.y, ps.beta.z * W.z);
     if (pp.rr_start >= 0 && k >= pp.rr_start) {
         float q = max3c(ps.beta);
@@ -1366,7 +1500,6 @@ PT_DEV VertexOut shade_vertex(const SceneView& sc, const PathParams& pp, uint32_
         if (u7 >= q) return out;
         ps.beta = mk3(ps.beta.x / q, ps.beta.y / q, ps.beta.z / q);
     }
-    f3 wi = to_world(fr, wi_l);
     f3 no = dot3(ng, wi) > 0.0f ? ng : neg3(ng);
     out.o = offset_point(x, no, tri_extent(v0, v1, v2));
     out.d = wi;
@@ -1397,14 +1530,14 @@ PT_DEV void path_begin(const CamView& cam, const PathParams& pp, uint32_t pix, u
     pr.k = 1;
 }
 
-template <int LDS, bool COUNT = false, bool INST = false>
+template <int LDS, bool COUNT = false, bool INST = false, bool ATTR = false>
 PT_DEV bool path_vertex(const SceneView& sc, const PathParams& pp, uint32_t pix, uint32_t sample, PathRun& pr,
                         TravStack<LDS, COUNT>& st, uint32_t& n_ext, uint32_t& n_sh,
                         const LightCache& lc = no_light_cache()) {
     Hit h = closest_hit_t<LDS, COUNT, INST>(sc, pr.o, pr.d, INFINITY, st);
     ++n_ext;
     ShadowReq sh;
-    VertexOut vo = shade_vertex<INST>(sc, pp, pix, sample, pr.k, pr.d, h, pr.ps, sh, lc);
+    VertexOut vo = shade_vertex<INST, ATTR>(sc, pp, pix, sample, pr.k, pr.d, h, pr.ps, sh, lc);
     add_radiance(pr.ps, vo);
     if (sh.valid) {
         ++n_sh;
@@ -1419,12 +1552,12 @@ PT_DEV bool path_vertex(const SceneView& sc, const PathParams& pp, uint32_t pix,
 }
 
 // One complete camera path: its radiance.
-template <int LDS, bool COUNT = false, bool INST = false>
+template <int LDS, bool COUNT = false, bool INST = false, bool ATTR = false>
 PT_DEV f3 trace_path(const SceneView& sc, const CamView& cam, const PathParams& pp, uint32_t pix, uint32_t sample,
                      TravStack<LDS, COUNT>& st, uint32_t& n_ext, uint32_t& n_sh, const LightCache& lc = no_light_cache()) {
     PathRun pr;
     path_begin(cam, pp, pix, sample, pr);
-    while (path_vertex<LDS, COUNT, INST>(sc, pp, pix, sample, pr, st, n_ext, n_sh, lc)) {
+    while (path_vertex<LDS, COUNT, INST, ATTR>(sc, pp, pix, sample, pr, st, n_ext, n_sh, lc)) {
     }
     return pr.ps.L;
 }

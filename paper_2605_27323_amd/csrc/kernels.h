@@ -93,7 +93,7 @@ hipError_t launch_average(dim3 grid, dim3 block, hipStream_t s, const float* I, 
 struct BatchBufs;
 hipError_t launch_batch_init(hipStream_t s, const BatchBufs& bb, uint32_t total);
 hipError_t launch_batch_iteration(int lds, dim3 grid, dim3 block, hipStream_t s, const BatchBufs& bb, int q,
-                                  uint2* ovf, int gcap);
+                                  uint2* ovf, int gcap, bool attr);
 hipError_t launch_batch_accumulate(dim3 grid, dim3 block, hipStream_t s, const BatchBufs& bb, uint32_t total_pix);
 
 }  // namespace ptmi

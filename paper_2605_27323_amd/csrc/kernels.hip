@@ -46,7 +46,7 @@ constexpr uint32_t kMegaChunk = 64u;
 
 // four waves per SIMD instead of the three the register count would give:
 // a few spilled registers cost less than the lost latency hiding
-template <int LDS, bool COUNT, int WAVES, bool INST>
+template <int LDS, bool COUNT, int WAVES, bool INST, bool ATTR>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) k_mega(SceneView sc, CamView cam, PathParams pp, float* __restrict__ img,
                                               float* __restrict__ acc, uint2* __restrict__ ovf, int gcap,
                                               uint32_t* __restrict__ stats, unsigned long long* __restrict__ trav,
@@ -121,7 +121,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES)
             path_begin(cam, pp, pix, sample, pr);
             started = true;
         }
-        if (path_vertex<LDS, COUNT, INST>(sc, pp, pix, sample, pr, st, n_ext, n_sh, lc)) continue;
+        if (path_vertex<LDS, COUNT, INST, ATTR>(sc, pp, pix, sample, pr, st, n_ext, n_sh, lc)) continue;
         started = false;
         sum = s == 0 ? pr.ps.L : add3(sum, pr.ps.L);
         if (++s == (uint32_t)pp.spp) {
@@ -160,7 +160,7 @@ __global__ void k_init_counts(uint32_t* __restrict__ counts, int n, uint32_t fir
 // Limited to 128 VGPRs (4 waves per SIMD, a few spilled registers): at 148
 // it ran 3 waves per SIMD and kept the next frame's stage kernels off the
 // compute units while it finished the last bounces.
-template <int LDS, bool COUNT, bool INST>
+template <int LDS, bool COUNT, bool INST, bool ATTR>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_shade_tail(SceneView sc, PathParams pp, WaveBufs wb, int b, int sorted,
                                                     uint32_t tail, uint2* __restrict__ ovf, int gcap,
                                                     uint32_t spread) {
@@ -188,8 +188,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         VertexOut vo;
         ShadowReq sh;
         PathState ps;
-        const uint32_t path = shade_item<INST>(sc, pp, wb, b, i, vo, sh, ps, perm, lc, true);
-        finish_path<LDS, COUNT, INST>(sc, pp, wb, path, b + 1, vo, sh, ps, st, n_ext, n_sh, lc);
+        const uint32_t path = shade_item<INST, ATTR>(sc, pp, wb, b, i, vo, sh, ps, perm, lc, true);
+        finish_path<LDS, COUNT, INST, ATTR>(sc, pp, wb, path, b + 1, vo, sh, ps, st, n_ext, n_sh, lc);
     }
     // every lane of the wave is here: reduce the ray counts across it
     for (int off = 32; off > 0; off >>= 1) {
@@ -284,7 +284,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
     if (st.overflow) atomicOr(&wb.counts[wb.err_slot], 1u);
 }
 
-template <bool INST>
+template <bool INST, bool ATTR>
 __global__ void __launch_bounds__(256) k_shade(SceneView sc, PathParams pp, WaveBufs wb, int b, int compact,
                                                int sorted, uint32_t tail) {
     const uint32_t nlanes = gridDim.x * blockDim.x;
@@ -314,7 +314,7 @@ __global__ void __launch_bounds__(256) k_shade(SceneView sc, PathParams pp, Wave
         vo.cont = false;
         sh.valid = false;
         uint32_t path = kDeadPath;
-        if (i < count) path = shade_item<INST>(sc, pp, wb, b, i, vo, sh, ps, perm, lc);
+        if (i < count) path = shade_item<INST, ATTR>(sc, pp, wb, b, i, vo, sh, ps, perm, lc);
         const uint64_t mk = compact ? __ballot(vo.cont) : 0ull;
         const uint64_t ms = __ballot(sh.valid);
         uint32_t jc, js;
@@ -469,7 +469,8 @@ __global__ void __launch_bounds__(256) k_accumulate(CamView cam, PathParams pp, 
 // launchers
 // ---------------------------------------------------------------------------
 #define PT_STACK_CASES(X) X(8) X(16) X(24) X(32)
-// instantiate a traversal kernel for the LDS stack depth and the work-counting flag
+// instantiate a traversal kernel for the LDS stack depth, the work-counting
+// flag and the scene kind (flat / two-level)
 #define PT_DISPATCH(N, launch) \
     if (lds == N) {            \
         if (sc.n_inst > 0) {   \
@@ -480,20 +481,36 @@ __global__ void __launch_bounds__(256) k_accumulate(CamView cam, PathParams pp, 
         return hipGetLastError(); \
     }
 
+// the same for kernels that shade, which also take the attribute flag
+#define PT_DISPATCH_SHADE(N, launch)                                                \
+    if (lds == N) {                                                                 \
+        const bool inst = sc.n_inst > 0, attr = sc.attr_flags != 0;                 \
+        if (inst && attr) {                                                         \
+            if (count) launch(N, true, true, true) else launch(N, false, true, true)   \
+        } else if (inst) {                                                          \
+            if (count) launch(N, true, true, false) else launch(N, false, true, false) \
+        } else if (attr) {                                                          \
+            if (count) launch(N, true, false, true) else launch(N, false, false, true) \
+        } else {                                                                    \
+            if (count) launch(N, true, false, false) else launch(N, false, false, false) \
+        }                                                                           \
+        return hipGetLastError();                                                   \
+    }
+
 static size_t stack_lds_bytes(int lds, int block) { return trav_stack_lds_bytes(lds, block); }
 
 hipError_t launch_mega(int lds, bool count, int waves, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
                        const CamView& cam, const PathParams& pp, float* img, float* acc, uint2* ovf, int gcap,
                        uint32_t* stats, unsigned long long* trav, int xcd_local) {
     size_t sm = stack_lds_bytes(lds, block.x);
-#define L(N, C, I)                                                                                                   \
+#define L(N, C, I, A)                                                                                                \
     if (waves == 5)                                                                                                  \
-        hipLaunchKernelGGL((k_mega<N, C, 5, I>), grid, block, sm, s, sc, cam, pp, img, acc, ovf, gcap, stats, trav,  \
-                           xcd_local);                                                                               \
+        hipLaunchKernelGGL((k_mega<N, C, 5, I, A>), grid, block, sm, s, sc, cam, pp, img, acc, ovf, gcap, stats,     \
+                           trav, xcd_local);                                                                         \
     else                                                                                                             \
-        hipLaunchKernelGGL((k_mega<N, C, 4, I>), grid, block, sm, s, sc, cam, pp, img, acc, ovf, gcap, stats, trav,  \
-                           xcd_local);
-#define X(N) PT_DISPATCH(N, L)
+        hipLaunchKernelGGL((k_mega<N, C, 4, I, A>), grid, block, sm, s, sc, cam, pp, img, acc, ovf, gcap, stats,     \
+                           trav, xcd_local);
+#define X(N) PT_DISPATCH_SHADE(N, L)
     PT_STACK_CASES(X)
 #undef X
 #undef L
@@ -524,10 +541,15 @@ hipError_t launch_extend(int lds, bool count, dim3 grid, dim3 block, hipStream_t
 
 hipError_t launch_shade(dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const PathParams& pp,
                         const WaveBufs& wb, int b, int compact, int sorted, uint32_t tail) {
-    if (sc.n_inst > 0)
-        hipLaunchKernelGGL(k_shade<true>, grid, block, 0, s, sc, pp, wb, b, compact, sorted, compact ? tail : 0u);
+    const uint32_t t = compact ? tail : 0u;
+    if (sc.n_inst > 0 && sc.attr_flags)
+        hipLaunchKernelGGL((k_shade<true, true>), grid, block, 0, s, sc, pp, wb, b, compact, sorted, t);
+    else if (sc.n_inst > 0)
+        hipLaunchKernelGGL((k_shade<true, false>), grid, block, 0, s, sc, pp, wb, b, compact, sorted, t);
+    else if (sc.attr_flags)
+        hipLaunchKernelGGL((k_shade<false, true>), grid, block, 0, s, sc, pp, wb, b, compact, sorted, t);
     else
-        hipLaunchKernelGGL(k_shade<false>, grid, block, 0, s, sc, pp, wb, b, compact, sorted, compact ? tail : 0u);
+        hipLaunchKernelGGL((k_shade<false, false>), grid, block, 0, s, sc, pp, wb, b, compact, sorted, t);
     return hipGetLastError();
 }
 
@@ -536,8 +558,8 @@ hipError_t launch_tail(int lds, bool count, dim3 grid, dim3 block, hipStream_t s
                        int gcap, uint32_t resident_waves) {
     const size_t sm = stack_lds_bytes(lds, block.x);
     const uint32_t spread = resident_waves ? std::max(1u, std::min(grid.x * block.x / 64u, resident_waves)) : 0u;
-#define L(N, C, I) hipLaunchKernelGGL((k_shade_tail<N, C, I>), grid, block, sm, s, sc, pp, wb, b, sorted, tail, ovf, gcap, spread);
-#define X(N) PT_DISPATCH(N, L)
+#define L(N, C, I, A) hipLaunchKernelGGL((k_shade_tail<N, C, I, A>), grid, block, sm, s, sc, pp, wb, b, sorted, tail, ovf, gcap, spread);
+#define X(N) PT_DISPATCH_SHADE(N, L)
     PT_STACK_CASES(X)
 #undef X
 #undef L

@@ -63,6 +63,14 @@ constexpr int kInstRecord = 7;
 // the top level (never a node or leaf reference of a valid scene)
 constexpr uint32_t kInstMarker = 0xFFFFFFFEu;
 
+// Vertex attribute record of a triangle, kAttrRecord float4 (64 bytes), in
+// leaf order like the triangle records: (n0.xyz, u0), (n1.xyz, v0),
+// (n2.xyz, u1), (v1, u2, v2, 0).  SceneView::attr_flags says which of the
+// two kinds the scene has.
+constexpr int kAttrRecord = 4;
+constexpr int32_t kAttrNormals = 1;
+constexpr int32_t kAttrUV = 2;
+
 struct SceneView {
     const float4* __restrict__ nodes;
     const float4* __restrict__ tris;
@@ -85,6 +93,10 @@ struct SceneView {
     // n_inst = 0 for a flat scene
     const float4* __restrict__ insts;
     int32_t n_inst;
+    // vertex attributes (kAttrRecord float4 per triangle, leaf order) and
+    // which kinds are present (kAttrNormals | kAttrUV; 0 = none)
+    const float4* __restrict__ attrs;
+    int32_t attr_flags;
 };
 
 struct CamView {

@@ -72,7 +72,7 @@ PT_DEV uint32_t ray_key(const SceneView& sc, const float4& o4, const float4& d4)
 // radiance L[path] is read only where this vertex adds to it, and updated
 // in place; with for_tail it is always read into ps.L (plus this vertex's
 // term) for finish_path, which stores it at the path's end.
-template <bool INST = false>
+template <bool INST = false, bool ATTR = false>
 PT_DEV uint32_t shade_item(const SceneView& sc, const PathParams& pp, const WaveBufs& wb, int b, uint32_t i,
                            VertexOut& vo, ShadowReq& sh, PathState& ps, const uint32_t* __restrict__ perm = nullptr,
                            const LightCache& lc = no_light_cache(), bool for_tail = false) {
@@ -106,7 +106,7 @@ PT_DEV uint32_t shade_item(const SceneView& sc, const PathParams& pp, const Wave
     } else {
         hit_barycentrics(sc, xyz(o4), xyz(d4), h);
     }
-    vo = shade_vertex<INST>(sc, pp, pix, sample, b + 1, xyz(d4), h, ps, sh, lc);
+    vo = shade_vertex<INST, ATTR>(sc, pp, pix, sample, b + 1, xyz(d4), h, ps, sh, lc);
     if (for_tail) {
         ps.L = xyz(wb.L[path]);
         add_radiance(ps, vo);
@@ -123,7 +123,7 @@ PT_DEV uint32_t shade_item(const SceneView& sc, const PathParams& pp, const Wave
 // vertices) and store its final radiance.  Used when a bounce's queue is too
 // short to keep the wavefront stages busy.
 // n_ext / n_sh count the extension and shadow rays traced here.
-template <int LDS, bool COUNT = false, bool INST = false>
+template <int LDS, bool COUNT = false, bool INST = false, bool ATTR = false>
 PT_DEV void finish_path(const SceneView& sc, const PathParams& pp, const WaveBufs& wb, uint32_t path, int k,
                         VertexOut vo, ShadowReq sh, PathState& ps, TravStack<LDS, COUNT>& st, uint32_t& n_ext,
                         uint32_t& n_sh, const LightCache& lc = no_light_cache()) {
@@ -141,7 +141,7 @@ PT_DEV void finish_path(const SceneView& sc, const PathParams& pp, const WaveBuf
         ++n_ext;
         const f3 d = vo.d;
         Hit h = closest_hit_t<LDS, COUNT, INST>(sc, vo.o, d, INFINITY, st);
-        vo = shade_vertex<INST>(sc, pp, pix, sample, k, d, h, ps, sh, lc);
+        vo = shade_vertex<INST, ATTR>(sc, pp, pix, sample, k, d, h, ps, sh, lc);
         add_radiance(ps, vo);
     }
     wb.L[path] = make_float4(ps.L.x, ps.L.y, ps.L.z, 0.f);

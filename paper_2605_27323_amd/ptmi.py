@@ -44,7 +44,7 @@ class BvhOpts(C.Structure):
 class BvhInfo(C.Structure):
     _fields_ = [("node_count", C.c_int64), ("node_bytes", C.c_int64), ("tri_bytes", C.c_int64),
                 ("light_count", C.c_int64), ("light_bytes", C.c_int64), ("material_bytes", C.c_int64),
-                ("instance_count", C.c_int64), ("instance_bytes", C.c_int64),
+                ("instance_count", C.c_int64), ("instance_bytes", C.c_int64), ("attribute_bytes", C.c_int64),
                 ("depth", C.c_int32), ("stack_entries", C.c_int32), ("build_seconds", C.c_double)]
 
 
@@ -53,10 +53,14 @@ class InstancesDesc(C.Structure):
                 ("n_instances", C.c_int32), ("inst_mesh", C.c_void_p), ("o2w", C.c_void_p), ("w2o", C.c_void_p)]
 
 
+class AttributesDesc(C.Structure):
+    _fields_ = [("nv", C.c_int32), ("normals", C.c_void_p), ("uvs", C.c_void_p)]
+
+
 class SceneBuffers(C.Structure):
     _fields_ = [("nodes", C.c_void_p), ("tris", C.c_void_p), ("lights", C.c_void_p), ("materials", C.c_void_p),
                 ("albedo", C.c_void_p), ("emission", C.c_void_p), ("upload_params", C.c_int32),
-                ("instances", C.c_void_p)]
+                ("instances", C.c_void_p), ("attributes", C.c_void_p)]
 
 
 class Camera(C.Structure):
@@ -106,6 +110,7 @@ SIGNATURES = {
     "pt_destroy": (C.c_int32, [C.c_void_p]),
     "pt_load_scene": (C.c_int32, [C.c_void_p, C.POINTER(SceneDesc)]),
     "pt_set_instances": (C.c_int32, [C.c_void_p, C.POINTER(InstancesDesc)]),
+    "pt_set_attributes": (C.c_int32, [C.c_void_p, C.POINTER(AttributesDesc)]),
     "pt_build_bvh": (C.c_int32, [C.c_void_p, C.POINTER(BvhOpts), C.POINTER(BvhInfo)]),
     "pt_get_bvh": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pt_bind_scene": (C.c_int32, [C.c_void_p, C.POINTER(SceneBuffers), C.c_void_p]),
@@ -194,6 +199,13 @@ class Context:
         d = SceneDesc(pos.size // 3, self.nt, mats.size // 4, pos.ctypes.data, idx.ctypes.data, tm.ctypes.data,
                       mats.ctypes.data, alb.ctypes.data, emi.ctypes.data, (C.c_float * 3)(*sky.tolist()))
         check(lib().pt_load_scene(self.h, C.byref(d)))
+        nrm, uvs = scene.get("normals"), scene.get("uvs")
+        if nrm is not None or uvs is not None:
+            nrm = None if nrm is None else _host(nrm, np.float32)
+            uvs = None if uvs is None else _host(uvs, np.float32)
+            a = AttributesDesc(pos.size // 3, None if nrm is None else nrm.ctypes.data,
+                               None if uvs is None else uvs.ctypes.data)
+            check(lib().pt_set_attributes(self.h, C.byref(a)))
         self.albedo0 = alb.reshape(-1, 3)
         self.emission0 = emi.reshape(-1, 3)
 
@@ -237,14 +249,16 @@ class Renderer(Context):
         self._bufs = {}
         ptrs = {}
         for name, nbytes in [("nodes", i.node_bytes), ("tris", i.tri_bytes), ("lights", i.light_bytes),
-                             ("materials", i.material_bytes), ("instances", i.instance_bytes)]:
+                             ("materials", i.material_bytes), ("instances", i.instance_bytes),
+                             ("attributes", i.attribute_bytes)]:
             t, p = _aligned_empty(nbytes, self.torch_device)
             self._bufs[name] = t
             ptrs[name] = p
         self.albedo = torch.zeros((max(self.nt, 1), 3), dtype=torch.float32, device=self.torch_device)
         self.emission = torch.zeros((max(self.nt, 1), 3), dtype=torch.float32, device=self.torch_device)
         sb = SceneBuffers(ptrs["nodes"], ptrs["tris"], ptrs["lights"], ptrs["materials"],
-                          self.albedo.data_ptr(), self.emission.data_ptr(), 1, ptrs["instances"])
+                          self.albedo.data_ptr(), self.emission.data_ptr(), 1, ptrs["instances"],
+                          ptrs["attributes"])
         check(lib().pt_bind_scene(self.h, C.byref(sb), self._stream()))
         self._ws = None
         self._ws_ptr = 0

@@ -373,7 +373,7 @@ def plane_under_light(albedo=0.5, le=4.0, light_half=0.5, light_h=1.0, half=4.0,
 # Procedural scenes: icospheres + tessellated boxes on a ground plane
 # --------------------------------------------------------------------------
 def procedural(seed=2, n_objects=2000, width=1920, height=1080, material_mode="lambert_conductor",
-               n_material_ids=64, ground_albedo=0.5, light_le=20.0):
+               n_material_ids=64, ground_albedo=0.5, light_le=20.0, attributes=False):
     """Half icospheres (level 3 or 4: 320 or 1280 faces), half boxes with an
     n x n grid per face (n in {3,4,5}: 108..300 triangles): expected
     1000 triangles per object on average.  Centres uniform in
@@ -387,8 +387,20 @@ def procedural(seed=2, n_objects=2000, width=1920, height=1080, material_mode="l
           ids in the first quarter are Lambertian, second conductor, third
           rough dielectric (ior U[1.3,1.8]), last quarter emissive Lambertian
           (albedo 0, emission 5 * U[0.2,1]^3).
+
+    attributes=True adds shading attributes without changing the geometry:
+    icospheres get their radial vertex normals (smooth shading), boxes zero
+    normals (flat shading); every mesh gets texture coordinates (icospheres
+    longitude/latitude, boxes (x + z, y) / scale, the ground (x, z) / 10);
+    half of the Lambertian meshes a checker texture (frequency 2, 4 or 8,
+    the ground 1) and half of the conductors become coated (coat roughness
+    U[0, 0.5], ior U[1.3, 1.8]) over a base of the same albedo.  These
+    choices come from a second generator (seed + 1000), so the scene's
+    geometry and albedos equal those of attributes=False.
     """
     rng = np.random.default_rng(seed)
+    rng2 = np.random.default_rng(seed + 1000)
+    NRM, UV = [], []
     n_ico = n_objects // 2
     n_box = n_objects - n_ico
     P, I, M, A, E = [], [], [], [], []
@@ -416,10 +428,16 @@ def procedural(seed=2, n_objects=2000, width=1920, height=1080, material_mode="l
             return mid + 1, mat_alb[mid], mat_emi[mid]
         if rng.uniform() < 0.5:
             alb = rng.uniform(0.1, 0.9, size=3)
+            if attributes and rng2.uniform() < 0.5:
+                materials.append((LAMBERT, 1.0, 1.5, float(rng2.choice([2.0, 4.0, 8.0]))))
+                return len(materials) - 1, alb, np.zeros(3)
             return 0, alb, np.zeros(3)
         alb = rng.uniform(0.1, 0.9, size=3)
         rough = float(rng.uniform(0.05, 0.8))
-        materials.append((CONDUCTOR, rough, 1.5, 0.0))
+        if attributes and rng2.uniform() < 0.5:
+            materials.append((COATED, float(rng2.uniform(0.0, 0.5)), float(rng2.uniform(1.3, 1.8)), 0.0))
+        else:
+            materials.append((CONDUCTOR, rough, 1.5, 0.0))
         return len(materials) - 1, alb, np.zeros(3)
 
     centres = np.stack([rng.uniform(-50, 50, n_objects), rng.uniform(0, 100, n_objects),
@@ -435,10 +453,15 @@ def procedural(seed=2, n_objects=2000, width=1920, height=1080, material_mode="l
             up, ui = icosphere_unit(lvl)
             pos = c + s * up
             idx = ui
+            NRM.append(up)
+            UV.append(np.stack([np.arctan2(up[:, 2], up[:, 0]) / (2 * np.pi) + 0.5,
+                                np.arccos(np.clip(up[:, 1], -1, 1)) / np.pi], 1))
         else:
             n = int(rng.integers(3, 6))
             ext = s * rng.uniform(0.5, 1.0, size=3)
             pos, idx = box_mesh(c - ext, c + ext, n)
+            NRM.append(np.zeros_like(pos))
+            UV.append(np.stack([(pos[:, 0] + pos[:, 2]) / s, pos[:, 1] / s], 1))
         mat, alb, emi = obj_material()
         P.append(pos)
         I.append(idx)
@@ -449,15 +472,24 @@ def procedural(seed=2, n_objects=2000, width=1920, height=1080, material_mode="l
 
     # ground
     gp, gi = quad((-200, 0, -200), (-200, 0, 200), (200, 0, 200), (200, 0, -200))
-    m, a, e = _tri_params(2, (ground_albedo,) * 3, (0, 0, 0), 0)
+    gmat = 0
+    if attributes:
+        materials.append((LAMBERT, 1.0, 1.5, 1.0))
+        gmat = len(materials) - 1
+    m, a, e = _tri_params(2, (ground_albedo,) * 3, (0, 0, 0), gmat)
     P.append(gp); I.append(gi); M.append(m); A.append(a); E.append(e)
+    NRM.append(np.zeros_like(gp)); UV.append(gp[:, [0, 2]] / 10.0)
     # 16 lights: 4 x 4 grid of 10 x 10 quads over [-45,45]^2 at y=120, facing -y
     for gx in np.linspace(-45, 45, 4):
         for gz in np.linspace(-45, 45, 4):
             lp, li = quad((gx - 5, 120, gz - 5), (gx + 5, 120, gz - 5), (gx + 5, 120, gz + 5), (gx - 5, 120, gz + 5))
             m, a, e = _tri_params(2, (0, 0, 0), (light_le,) * 3, 0)
             P.append(lp); I.append(li); M.append(m); A.append(a); E.append(e)
+            NRM.append(np.zeros_like(lp)); UV.append(np.zeros((4, 2)))
     scene = _pack(P, I, M, A, E, materials)
+    if attributes:
+        scene["normals"] = np.ascontiguousarray(np.concatenate(NRM).astype(np.float32))
+        scene["uvs"] = np.ascontiguousarray(np.concatenate(UV).astype(np.float32))
     cam = dict(eye=(0.0, 50.0, -130.0), target=(0.0, 40.0, 0.0), up=(0.0, 1.0, 0.0),
                vfov_deg=50.0, width=width, height=height)
     return scene, cam
@@ -501,7 +533,7 @@ def split_into_instances(scene, parts):
 
 
 def instanced_procedural(seed=6, n_instances=4000, n_meshes=32, width=1920, height=1080, ground_albedo=0.5,
-                         light_le=20.0):
+                         light_le=20.0, attributes=False):
     """A scene of shared meshes: n_meshes object meshes (icospheres of level
     2-4 and tessellated boxes, unit size, each with its own material) placed
     n_instances times with random rotations, scales log-uniform in [0.1, 5]
@@ -509,16 +541,23 @@ def instanced_procedural(seed=6, n_instances=4000, n_meshes=32, width=1920, heig
     quad (one instance) and a 10 x 10 downward quad light placed 16 times on a
     4 x 4 grid at y = 120 (the procedural scene's layout).  Materials per
     mesh: 50% Lambertian (albedo U[0.1,0.9]^3), 50% GGX conductor (F0
-    U[0.1,0.9]^3, roughness U[0.05,0.8]).  Returns (scene, instances, cam)."""
+    U[0.1,0.9]^3, roughness U[0.05,0.8]).  attributes=True adds object-space
+    vertex normals and texture coordinates, checker textures and coats as in
+    procedural (from a second generator: same geometry and placements).
+    Returns (scene, instances, cam)."""
     rng = np.random.default_rng(seed)
+    rng2 = np.random.default_rng(seed + 1000)
     P, I, M, A, E = [], [], [], [], []
+    NRM, UV = [], []
     materials = [(LAMBERT, 1.0, 1.5, 0.0)]
     first, count = [], []
     nt = 0
 
-    def add(pos, idx, mat, alb, emi):
+    def add(pos, idx, mat, alb, emi, nrm=None, uv=None):
         nonlocal nt
         P.append(pos); I.append(idx)
+        NRM.append(np.zeros_like(pos) if nrm is None else nrm)
+        UV.append(np.zeros((pos.shape[0], 2)) if uv is None else uv)
         m, a, e = _tri_params(idx.shape[0], alb, emi, mat)
         M.append(m); A.append(a); E.append(e)
         first.append(nt); count.append(idx.shape[0])
@@ -527,17 +566,33 @@ def instanced_procedural(seed=6, n_instances=4000, n_meshes=32, width=1920, heig
     for k in range(n_meshes):
         if k % 2 == 0:
             pos, idx = icosphere_unit(int(rng.integers(2, 5)))
+            nrm = pos
+            uv = np.stack([np.arctan2(pos[:, 2], pos[:, 0]) / (2 * np.pi) + 0.5,
+                           np.arccos(np.clip(pos[:, 1], -1, 1)) / np.pi], 1)
         else:
             pos, idx = box_mesh(-rng.uniform(0.5, 1.0, 3), rng.uniform(0.5, 1.0, 3), int(rng.integers(2, 6)))
+            nrm = None
+            uv = np.stack([pos[:, 0] + pos[:, 2], pos[:, 1]], 1)
         alb = rng.uniform(0.1, 0.9, size=3)
         if rng.uniform() < 0.5:
             mat = 0
+            if attributes and rng2.uniform() < 0.5:
+                materials.append((LAMBERT, 1.0, 1.5, float(rng2.choice([2.0, 4.0, 8.0]))))
+                mat = len(materials) - 1
         else:
-            materials.append((CONDUCTOR, float(rng.uniform(0.05, 0.8)), 1.5, 0.0))
+            rough = float(rng.uniform(0.05, 0.8))
+            if attributes and rng2.uniform() < 0.5:
+                materials.append((COATED, float(rng2.uniform(0.0, 0.5)), float(rng2.uniform(1.3, 1.8)), 0.0))
+            else:
+                materials.append((CONDUCTOR, rough, 1.5, 0.0))
             mat = len(materials) - 1
-        add(pos, idx, mat, alb, np.zeros(3))
+        add(pos, idx, mat, alb, np.zeros(3), nrm, uv)
     gp, gi = quad((-200, 0, -200), (-200, 0, 200), (200, 0, 200), (200, 0, -200))
-    add(gp, gi, 0, (ground_albedo,) * 3, (0, 0, 0))
+    gmat = 0
+    if attributes:
+        materials.append((LAMBERT, 1.0, 1.5, 1.0))
+        gmat = len(materials) - 1
+    add(gp, gi, gmat, (ground_albedo,) * 3, (0, 0, 0), None, gp[:, [0, 2]] / 10.0)
     lp, li = quad((-5, 0, -5), (5, 0, -5), (5, 0, 5), (-5, 0, 5))
     add(lp, li, 0, (0, 0, 0), (light_le,) * 3)
     ground, light = n_meshes, n_meshes + 1
@@ -553,6 +608,9 @@ def instanced_procedural(seed=6, n_instances=4000, n_meshes=32, width=1920, heig
             a, b = affine(np.eye(3), 1.0, (gx, 120.0, gz))
             inst_mesh.append(light); o2w.append(a); w2o.append(b)
     scene = _pack(P, I, M, A, E, materials)
+    if attributes:
+        scene["normals"] = np.ascontiguousarray(np.concatenate(NRM).astype(np.float32))
+        scene["uvs"] = np.ascontiguousarray(np.concatenate(UV).astype(np.float32))
     inst = {"mesh_first": np.array(first, np.int32), "mesh_count": np.array(count, np.int32),
             "inst_mesh": np.array(inst_mesh, np.int32), "o2w": np.array(o2w, np.float32),
             "w2o": np.array(w2o, np.float32)}

@@ -81,12 +81,20 @@ class Emu:
         assert L.pt_create(C.byref(h), -1) == 0
         self.h = h
         keep = {k: np.ascontiguousarray(v) for k, v in scene.items()}
+        for k in ("normals", "uvs"):
+            if k in keep:
+                keep[k] = np.ascontiguousarray(keep[k], np.float32)
         self._keep = keep
         d = ptmi.SceneDesc(keep["positions"].shape[0], keep["indices"].shape[0], keep["materials"].shape[0],
                            keep["positions"].ctypes.data, keep["indices"].ctypes.data, keep["tri_mat"].ctypes.data,
                            keep["materials"].ctypes.data, keep["albedo"].ctypes.data, keep["emission"].ctypes.data,
                            (C.c_float * 3)(*np.asarray(keep["sky"], np.float32).tolist()))
         assert L.pt_load_scene(h, C.byref(d)) == 0, L.pt_last_error()
+        if "normals" in keep or "uvs" in keep:
+            a = ptmi.AttributesDesc(keep["positions"].shape[0],
+                                    keep["normals"].ctypes.data if "normals" in keep else None,
+                                    keep["uvs"].ctypes.data if "uvs" in keep else None)
+            assert L.pt_set_attributes(h, C.byref(a)) == 0, L.pt_last_error()
         if instances is not None:
             ik = {k: np.ascontiguousarray(instances[k], np.int32) for k in ("mesh_first", "mesh_count", "inst_mesh")}
             ik.update({k: np.ascontiguousarray(instances[k], np.float32) for k in ("o2w", "w2o")})

@@ -40,8 +40,12 @@ SceneView host_view(const pt_ctx* c) {
     v.n_hot = (int32_t)c->bvh.hot_ids.size();
     v.insts = c->bvh.insts.empty() ? nullptr : c->bvh.insts.data();
     v.n_inst = (int32_t)(c->bvh.insts.size() / kInstRecord);
+    v.attrs = c->attr_leaf.empty() ? nullptr : c->attr_leaf.data();
+    v.attr_flags = c->attr_leaf.empty() ? 0 : ((c->attr_n.empty() ? 0 : kAttrNormals) | (c->attr_uv.empty() ? 0 : kAttrUV));
     return v;
 }
+
+bool has_attrs(const pt_ctx* c) { return !c->attr_leaf.empty(); }
 
 constexpr int kL = 16;
 
@@ -52,7 +56,7 @@ struct HostStack {
     explicit HostStack(int gcap) : gbl(std::max(gcap, 1)) { st = make_trav_stack<kL>(l, 1, gbl.data(), 0u, 1, gcap); }
 };
 
-template <bool INST>
+template <bool INST, bool ATTR>
 int32_t render_mega(pt_ctx* c, const int32_t* pixels, int32_t n, int32_t spp, int32_t D, uint64_t seed,
                     uint32_t frame, uint32_t job, int32_t nee, int32_t rr_start, float* out, uint64_t* rays,
                     int32_t sampler) {
@@ -65,7 +69,8 @@ int32_t render_mega(pt_ctx* c, const int32_t* pixels, int32_t n, int32_t spp, in
         uint32_t e = 0, s = 0;
         f3 sum = mk3(0.f, 0.f, 0.f);
         for (int k = 0; k < spp; ++k) {
-            f3 L = trace_path<kL, false, INST>(sc, c->cam, pp, pix, frame * (uint32_t)spp + (uint32_t)k, hs.st, e, s);
+            f3 L = trace_path<kL, false, INST, ATTR>(sc, c->cam, pp, pix, frame * (uint32_t)spp + (uint32_t)k, hs.st, e,
+                                                    s);
             sum = k == 0 ? L : add3(sum, L);
         }
         const float fs = (float)spp;
@@ -89,8 +94,12 @@ extern "C" {
 int32_t emu_render_mega(pt_ctx* c, const int32_t* pixels, int32_t n, int32_t spp, int32_t D, uint64_t seed,
                         uint32_t frame, uint32_t job, int32_t nee, int32_t rr_start, float* out, uint64_t* rays,
                         int32_t sampler) {
-    return c->bvh.insts.empty() ? render_mega<false>(c, pixels, n, spp, D, seed, frame, job, nee, rr_start, out, rays, sampler)
-                                : render_mega<true>(c, pixels, n, spp, D, seed, frame, job, nee, rr_start, out, rays, sampler);
+    // the kernel variant the library would launch for this scene
+#define RM(I, A) render_mega<I, A>(c, pixels, n, spp, D, seed, frame, job, nee, rr_start, out, rays, sampler)
+    const bool inst = !c->bvh.insts.empty();
+    if (has_attrs(c)) return inst ? RM(true, true) : RM(false, true);
+    return inst ? RM(true, false) : RM(false, false);
+#undef RM
 }
 
 // Closest hit of the library's traversal for n rays o[3n], d[3n] in
@@ -116,7 +125,7 @@ int32_t emu_closest(pt_ctx* c, int32_t n, const float* o, const float* d, float*
 
 namespace {
 
-template <bool INST>
+template <bool INST, bool ATTR>
 int32_t render_wave(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32_t frame, uint32_t job, int32_t nee,
                     int32_t rr_start, int32_t compact, uint64_t shuffle_seed, int32_t sort, uint32_t tail,
                     float* img, uint64_t* rays, int32_t sampler) {
@@ -169,12 +178,12 @@ int32_t render_wave(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32_t f
             VertexOut vo;
             ShadowReq sh;
             PathState ps;
-            uint32_t path = shade_item<INST>(sc, pp, wb, b, i, vo, sh, ps, sort ? perm.data() : nullptr,
+            uint32_t path = shade_item<INST, ATTR>(sc, pp, wb, b, i, vo, sh, ps, sort ? perm.data() : nullptr,
                                              no_light_cache(), finish);
             if (path != kDeadPath) ++ne;
             if (finish) {
                 uint32_t te = 0, ts = 0;
-                finish_path<kL, false, INST>(sc, pp, wb, path, b + 1, vo, sh, ps, hs.st, te, ts);
+                finish_path<kL, false, INST, ATTR>(sc, pp, wb, path, b + 1, vo, sh, ps, hs.st, te, ts);
                 ne += te;
                 ns += ts;
                 continue;
@@ -225,11 +234,12 @@ extern "C" {
 int32_t emu_render_wave(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32_t frame, uint32_t job, int32_t nee,
                         int32_t rr_start, int32_t compact, uint64_t shuffle_seed, int32_t sort, uint32_t tail,
                         float* img, uint64_t* rays, int32_t sampler) {
-    return c->bvh.insts.empty()
-               ? render_wave<false>(c, spp, D, seed, frame, job, nee, rr_start, compact, shuffle_seed, sort, tail, img,
-                                    rays, sampler)
-               : render_wave<true>(c, spp, D, seed, frame, job, nee, rr_start, compact, shuffle_seed, sort, tail, img,
-                                   rays, sampler);
+#define RW(I, A) \
+    render_wave<I, A>(c, spp, D, seed, frame, job, nee, rr_start, compact, shuffle_seed, sort, tail, img, rays, sampler)
+    const bool inst = !c->bvh.insts.empty();
+    if (has_attrs(c)) return inst ? RW(true, true) : RW(false, true);
+    return inst ? RW(true, false) : RW(false, false);
+#undef RW
 }
 
 // Path-replay adjoint over the whole image (sequential binary32 adds):
@@ -251,7 +261,10 @@ int32_t emu_backward(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32_t 
     for (uint32_t p = 0; p < npaths; ++p) {
         const uint32_t pix = p / (uint32_t)spp, s = p - pix * (uint32_t)spp;
         f3 delta = mk3(d_img[3 * (size_t)pix] / fs, d_img[3 * (size_t)pix + 1] / fs, d_img[3 * (size_t)pix + 2] / fs);
-        adjoint_path<kL>(sc, c->cam, pp, pix, frame * (uint32_t)spp + s, delta, g_alb, g_emi, hs.st, acc);
+        if (has_attrs(c))
+            adjoint_path<kL, true>(sc, c->cam, pp, pix, frame * (uint32_t)spp + s, delta, g_alb, g_emi, hs.st, acc);
+        else
+            adjoint_path<kL, false>(sc, c->cam, pp, pix, frame * (uint32_t)spp + s, delta, g_alb, g_emi, hs.st, acc);
     }
     return hs.st.overflow ? 1 : 0;
 }
@@ -263,6 +276,8 @@ int64_t emu_render_batch(pt_ctx** ctxs, const pt_render_args* args, int32_t n, u
                          float* img) {
     std::vector<JobDesc> jobs(n);
     uint64_t total = 0, total_pix = 0;
+    bool any_attr = false;
+    for (int j = 0; j < n; ++j) any_attr = any_attr || has_attrs(ctxs[j]);
     int gcap = 0;
     for (int j = 0; j < n; ++j) {
         JobDesc& d = jobs[j];
@@ -314,7 +329,8 @@ int64_t emu_render_batch(pt_ctx** ctxs, const pt_render_args* args, int32_t n, u
             ShadowReq sh;
             PathState ps;
             uint32_t g = 0, meta = 0;
-            bool fin = batch_shade_item(bb, q, i, vo, sh, ps, g, meta);
+            bool fin = any_attr ? batch_shade_item<true>(bb, q, i, vo, sh, ps, g, meta)
+                                : batch_shade_item<false>(bb, q, i, vo, sh, ps, g, meta);
             if (fin && remaining[meta >> 24]-- == 0) return -1;
             if (vo.cont) {
                 if (ctl.live[q ^ 1] >= capacity) return -1;

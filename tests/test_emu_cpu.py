@@ -257,3 +257,76 @@ def test_identity_instances_equal_flat_scene():
     for parts in (1, 5):
         b, _ = emu.Emu(sc, cam, instances=scenes.split_into_instances(sc, parts)).mega(**cfg)
         assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), parts
+
+
+@pytest.mark.parametrize("cfg", [dict(spp=3, max_depth=6, rr_start=3, seed=4, frame=1),
+                                 dict(spp=2, max_depth=4, nee=False, seed=8)])
+def test_attributes_match_oracle(cfg):
+    # shading normals, checker texture and the coated material: the device
+    # shading code against the oracle; wavefront (shuffled, sorted, hybrid
+    # tail) = megakernel bit for bit
+    scene, cam = scenes.cornell_attributes(coat=(0.3, 1.5))
+    cam = dict(cam, width=40, height=32)
+    E, img, rays, nexact = _check(scene, cam, **cfg)
+    assert nexact >= 0.999 * img.shape[0]
+    for kw in (dict(shuffle=7), dict(sort=True, shuffle=2), dict(tail=300, shuffle=5)):
+        w, rw = E.wave(**kw, **cfg)
+        assert np.array_equal(w.view(np.uint32), img.view(np.uint32)), kw
+        assert (rw == rays).all()
+
+
+def test_procedural_attributes_match_oracle():
+    scene, cam = scenes.procedural(seed=21, n_objects=40, width=61, height=37, attributes=True)
+    assert (scene["materials"][:, 0] == scenes.COATED).any() and (scene["materials"][:, 3] > 0).any()
+    cfg = dict(spp=2, max_depth=8, rr_start=3, seed=7, frame=2)
+    E, img, rays, nexact = _check(scene, cam, **cfg)
+    assert nexact >= 0.999 * img.shape[0]
+    w, rw = E.wave(shuffle=9, tail=400, **cfg)
+    assert np.array_equal(w.view(np.uint32), img.view(np.uint32))
+    # without the attributes the same geometry renders differently
+    plain = {k: v for k, v in scene.items() if k not in ("normals", "uvs")}
+    p, _ = emu.Emu(plain, cam).mega(**cfg)
+    assert not np.array_equal(p, img)
+
+
+def test_instanced_attributes_match_oracle():
+    # smooth-shaded, textured and coated meshes placed by instances: object
+    # space normals mapped by the inverse transpose
+    sc, inst, cam = scenes.instanced_procedural(seed=9, n_instances=80, n_meshes=8, width=40, height=28,
+                                                attributes=True)
+    E = emu.Emu(sc, cam, instances=inst)
+    S = oracle.Scene(sc, instances=inst)
+    cfg = dict(spp=2, max_depth=6, rr_start=3, seed=5, frame=1)
+    img, rays = E.mega(**cfg)
+    o, frag = S.render(cam, **cfg)
+    nexact = assert_parity(img, o, frag, what="instanced attributes")
+    assert nexact >= 0.999 * img.shape[0]
+    w, rw = E.wave(shuffle=3, tail=200, **cfg)
+    assert np.array_equal(w.view(np.uint32), img.view(np.uint32)) and (rw == rays).all()
+
+
+def test_adjoint_with_attributes_matches_oracle():
+    scene, cam = scenes.cornell_attributes(coat=(0.3, 1.5))
+    cam = dict(cam, width=24, height=20)
+    E = emu.Emu(scene, cam)
+    rng = np.random.default_rng(1)
+    d = rng.normal(size=(cam["width"] * cam["height"], 3)).astype(np.float32)
+    ga, ge = E.backward(d, spp=2, max_depth=4, seed=3)
+    oa, oe, aa, ae = oracle.Scene(scene).backward(cam, d, spp=2, max_depth=4, seed=3)
+    for g, o, a in [(ga, oa, aa), (ge, oe, ae)]:
+        assert (np.abs(g - o) <= 1e-4 * a + 1e-7 * np.abs(o).max()).all()
+        assert np.linalg.norm(g - o) <= 1e-4 * np.linalg.norm(o)
+    # coated and textured triangles receive albedo gradients
+    assert np.abs(oa[scene["tri_mat"] == 1]).sum() > 0 and np.abs(oa[:2]).sum() > 0
+
+
+def test_batch_with_attribute_job_matches_oracle():
+    s0, c0 = scenes.cornell_attributes(coat=(0.2, 1.4))
+    c0 = dict(c0, width=20, height=16)
+    s1, c1 = scenes.procedural(seed=1001, n_objects=12, width=16, height=16)
+    jobs = [(emu.Emu(s0, c0), dict(spp=2, max_depth=5, rr_start=3, seed=5, frame=1)),
+            (emu.Emu(s1, c1), dict(spp=1, max_depth=5, rr_start=3, seed=6))]
+    imgs, _ = emu.render_batch([e for e, _ in jobs], [kw for _, kw in jobs], 200, shuffle=4)
+    for j, ((s, c), (e, kw)) in enumerate(zip([(s0, c0), (s1, c1)], jobs)):
+        o, frag = oracle.Scene(s).render(c, job=j, **kw)
+        assert_parity(imgs[j], o, frag, what=f"attribute batch job {j}")
