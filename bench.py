@@ -419,6 +419,8 @@ def main():
         torch.cuda.empty_cache()
         out["instancing"] = instancing_bench(args, torch, ptmi, scenes)
         torch.cuda.empty_cache()
+        out["attributes"] = attributes_bench(args, torch, ptmi, scenes)
+        torch.cuda.empty_cache()
         out["divergence"] = divergence_bench(args, torch, ptmi, scenes, frames=2, summary=True)
         torch.cuda.empty_cache()
         out["batch"] = batch_bench(args, torch, ptmi, scenes, None, runs=2, summary=True)
@@ -478,6 +480,34 @@ def instancing_bench(args, torch, ptmi, scenes, k=8):
     res["workload"] = (f"{len(inst['inst_mesh'])} instances of {len(inst['mesh_first'])} meshes "
                        f"({sc['indices'].shape[0]} unique triangles), {W}x{H}, {SPP} spp, depth {DEPTH}, roulette "
                        f"from {RR}; flattened = every instance's triangles in world space")
+    return res
+
+
+def attributes_bench(args, torch, ptmi, scenes, k=8):
+    """The benchmark geometry with shading attributes (smooth-shaded
+    icospheres, checker textures, half of the conductors coated) against the
+    same geometry without them: attribute bytes and ms per frame of the
+    hybrid wavefront and the megakernel, frame by frame."""
+    kw = dict(spp=SPP, max_depth=DEPTH, rr_start=RR, nee=True, seed=0)
+    img = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+    res = {}
+    for name, attr in [("attributes", True), ("plain", False)]:
+        scene, cam = scenes.procedural(seed=2, n_objects=2000, width=W, height=H, attributes=attr)
+        R = ptmi.Renderer(scene, cam, max_leaf=args.max_leaf)
+        r = {"attribute_bytes": R.info.attribute_bytes,
+             "coated_materials": int((scene["materials"][:, 0] == scenes.COATED).sum()),
+             "textured_materials": int((scene["materials"][:, 3] > 0).sum())}
+        for mode, p in [("wave_hybrid", dict(FIXED_PARAMS["wave"], mode="wave")),
+                        ("mega", dict(FIXED_PARAMS["mega"], mode="mega"))]:
+            time_frames(torch, R, img, 2, 0, False, **kw, **p)
+            r[f"{mode}_ms_per_frame"] = time_frames(torch, R, img, k, 2, False, **kw, **p) * 1e3 / k
+        res[name] = r
+        log(f"{name}: {r}")
+        del R
+    res["time_ratio_wave"] = res["attributes"]["wave_hybrid_ms_per_frame"] / res["plain"]["wave_hybrid_ms_per_frame"]
+    res["time_ratio_mega"] = res["attributes"]["mega_ms_per_frame"] / res["plain"]["mega_ms_per_frame"]
+    res["workload"] = (f"procedural scene (1019958 triangles) with and without shading attributes, {W}x{H}, {SPP} "
+                       f"spp, depth {DEPTH}, roulette from {RR}")
     return res
 
 

@@ -17,15 +17,18 @@ import time
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ptmi_autotune.json")
 
 FRAME_SPACE = {
-    "wave": {"block": [64, 128, 256], "grid_mult": [4, 8, 16], "stack_lds": [8, 16],
+    "wave": {"block": [64, 128, 256], "grid_mult": [4, 8, 16], "stack_lds": [8, 16, 24, 32],
              "sort_threshold": [None, 1 << 16], "ray_sort": [False, True],
              "tail_threshold": [0, 1 << 16, 1 << 18, 1 << 19, 1 << 20]},
-    "mega": {"block": [64, 128, 256], "grid_mult": [2, 4, 8, 16], "stack_lds": [8, 16], "mega_waves": [4, 5]},
+    "mega": {"block": [64, 128, 256], "grid_mult": [2, 4, 8, 16], "stack_lds": [8, 16, 24, 32],
+             "mega_waves": [4, 5]},
 }
 # tried after the other wave parameters are chosen (0 = off)
 TAIL_BOUNCES = [0, 2, 3, 4, 5, 6]
-BATCH_SPACE = {"pool_capacity": [1 << 21, 1 << 22, 1 << 23], "block": [128, 256], "grid_mult": [4, 8],
-               "stack_lds": [8, 16], "pools": [1, 2, 3]}
+# The batched launch has no sort or hybrid-tail stage, so its space is the
+# pool (capacity, count) and the launch shape.
+BATCH_SPACE = {"pool_capacity": [1 << 20, 1 << 21, 1 << 22, 1 << 23, 1 << 24], "block": [128, 256],
+               "grid_mult": [4, 8, 16], "stack_lds": [8, 16, 32], "pools": [1, 2, 3, 4]}
 
 
 def _bucket(x):
