@@ -318,7 +318,7 @@ def main():
                 ", ".join(f"{s} {v:.3f}" for s, v in frame_stage_ms[name].items()))
             lds = params.get("stack_lds", 8)
             kname = {"extend": f"ptmi::k_extend<{lds}, false, false>", "shadow": f"ptmi::k_shadow<{lds}, false, false>",
-                     "tail": f"ptmi::k_shade_tail<{lds}, false, false>", "shade": "ptmi::k_shade<false>"}
+                     "tail": f"ptmi::k_shade_tail<{lds}, false, false, false>", "shade": "ptmi::k_shade<false, false>"}
             for st in ["extend", "shadow", "shade", "tail"]:
                 if st not in acc["launches"]:
                     continue
@@ -339,7 +339,7 @@ def main():
         acc = profiled_frames(R, img, ptmi, "mega", FIXED_PARAMS["mega"], k, args.warmup, kw)
         waves = FIXED_PARAMS["mega"].get("mega_waves", 4)
         out_roof["mega"] = roofline_entry(
-            f"ptmi::k_mega<{FIXED_PARAMS['mega']['stack_lds']}, false, {waves}, false>", acc["launches"]["mega"],
+            f"ptmi::k_mega<{FIXED_PARAMS['mega']['stack_lds']}, false, {waves}, false, false>", acc["launches"]["mega"],
             acc["stage_ms"]["mega"], acc["bytes"]["mega"], acc["node_visits"]["mega"], acc["tri_tests"]["mega"],
             prof, copy_gbs)
 
@@ -649,9 +649,9 @@ def adjoint_bench(ptmi, scene, torch, args, prof, copy_gbs, roof):
             st = R.stats()
             nodes += st["node_visits"]["mega"]
             tris += st["tri_tests"]["mega"]
-        roof["adjoint_radiance"] = roofline_entry("ptmi::k_adjoint_radiance<8>", k, ms["adjoint_radiance"],
+        roof["adjoint_radiance"] = roofline_entry("ptmi::k_adjoint_radiance<8, false>", k, ms["adjoint_radiance"],
                                                   by["adjoint_radiance"], nodes, tris, prof, copy_gbs)
-        roof["adjoint"] = roofline_entry("ptmi::k_adjoint<8>", k, ms["adjoint"], by["adjoint"], nodes, tris, prof,
+        roof["adjoint"] = roofline_entry("ptmi::k_adjoint<8, false>", k, ms["adjoint"], by["adjoint"], nodes, tris, prof,
                                          copy_gbs)
         return {"value": n / dt, "unit": "adjoint samples/s", "ms_per_backward": dt * 1e3 / k,
                 "ms_per_kernel": {s: v / k for s, v in ms.items()},
