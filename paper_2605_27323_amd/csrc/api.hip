@@ -315,6 +315,15 @@ pt_status enqueue_stages(pt_ctx* c, const pt_render_args* a, const Launch& L, co
 // the largest triangles' ids follow the light table in the light buffer
 size_t hot_ids_offset(const pt_ctx* c) { return std::max<size_t>(1, c->bvh.lights.size()) * sizeof(LightEntry); }
 
+// which shading features the scene uses (kAttrNormals | kAttrUV | kAttrCoat);
+// nonzero selects the shading kernels' extended variant
+int32_t shading_flags(const pt_ctx* c) {
+    int32_t f = (c->attr_n.empty() ? 0 : kAttrNormals) | (c->attr_uv.empty() ? 0 : kAttrUV);
+    for (size_t i = 0; i < c->mats.size(); i += 4)
+        if ((int)c->mats[i] == PT_COATED) f |= kAttrCoat;
+    return f;
+}
+
 SceneView make_view(const pt_ctx* c, const pt_scene_buffers* b) {
     SceneView v{};
     v.nodes = reinterpret_cast<const float4*>(b->nodes);
@@ -338,7 +347,7 @@ SceneView make_view(const pt_ctx* c, const pt_scene_buffers* b) {
     v.insts = c->bvh.insts.empty() ? nullptr : reinterpret_cast<const float4*>(b->instances);
     v.n_inst = (int32_t)(c->bvh.insts.size() / kInstRecord);
     v.attrs = c->attr_leaf.empty() ? nullptr : reinterpret_cast<const float4*>(b->attributes);
-    v.attr_flags = c->attr_leaf.empty() ? 0 : ((c->attr_n.empty() ? 0 : kAttrNormals) | (c->attr_uv.empty() ? 0 : kAttrUV));
+    v.attr_flags = shading_flags(c);
     return v;
 }
 

@@ -1121,7 +1121,9 @@ PT_DEV f3 cosine_dir(float u5, float u6) {
 }
 
 // f and the solid-angle pdf of an opaque material, wo and wi in the local
-// frame of the normal on wo's side.
+// frame of the normal on wo's side.  EXT: the scene may hold coated
+// materials (else their case is compiled out).
+template <bool EXT = true>
 PT_DEV void eval_opaque(int type, float rough, float ior, float tex, f3 alb, f3 wo, f3 wi, f3& f, float& pdf,
                         Lobe& lb) {
     f = mk3(0.0f, 0.0f, 0.0f);
@@ -1137,7 +1139,7 @@ PT_DEV void eval_opaque(int type, float rough, float ior, float tex, f3 alb, f3 
         lb.k = k;
         return;
     }
-    if (type == PT_COATED) {
+    if (EXT && type == PT_COATED) {
         eval_coat(rough, ior, tex, alb, wo, wi, f, pdf, lb);
         return;
     }
@@ -1166,6 +1168,8 @@ PT_DEV float fresnel_dielectric(float ci, float eta) {
 }
 
 // Sample a continuation direction in the local frame; false = rejected.
+// EXT as for eval_opaque.
+template <bool EXT = true>
 PT_DEV bool sample_local(int type, float rough, float ior, float tex, bool entering, f3 alb, f3 wo, float u4,
                          float u5, float u6, f3& wi, f3& weight, float& pdf, Lobe& lb) {
     lb.type = type;
@@ -1180,7 +1184,7 @@ PT_DEV bool sample_local(int type, float rough, float ior, float tex, bool enter
     }
     if (wo.z <= 0.0f) return false;
     float alpha = ggx_alpha(rough), a2 = alpha * alpha;
-    if (type == PT_COATED) {
+    if (EXT && type == PT_COATED) {
         // the coat's visible normals with probability F(cos_o), else the
         // base's cosine lobe; weight f cos_i / (mixture pdf)
         const float Fo = fresnel_dielectric(wo.z, ior);
@@ -1354,8 +1358,8 @@ PT_DEV f3 load3(const float* __restrict__ p, uint32_t i) {
 // space by its instance record's object-to-world rows, and so are the
 // sampled light's (its instance record is the light table's last word).
 // ATTR: the scene may have vertex attributes (shading normals, texture
-// coordinates); without it the attribute code is compiled out, so scenes
-// without attributes keep the smaller register budget.
+// coordinates) or coated materials; without it that code is compiled out,
+// so scenes without them keep the smaller register budget.
 template <bool INST = false, bool ATTR = false>
 PT_DEV VertexOut shade_vertex(const SceneView& sc, const PathParams& pp, uint32_t pixel, uint32_t sample, int k,
                               f3 rd, const Hit& h, PathState& ps, ShadowReq& sh,
@@ -1459,7 +1463,7 @@ PT_DEV VertexOut shade_vertex(const SceneView& sc, const PathParams& pp, uint32_
                 f3 f;
                 float pb;
                 Lobe lob;
-                eval_opaque(type, rough, ior, tex, alb, wo_l, to_local(fr, wl), f, pb, lob);
+                eval_opaque<ATTR>(type, rough, ior, tex, alb, wo_l, to_local(fr, wl), f, pb, lob);
                 float pl = d2 / (sc.area_total * cos_y);
                 if (lob.k > 0.0f && pl > 0.0f) {
                     float wmis = (pl * pl) / (pl * pl + pb * pb);
@@ -1482,7 +1486,7 @@ PT_DEV VertexOut shade_vertex(const SceneView& sc, const PathParams& pp, uint32_
     f3 wi_l, W;
     float pb;
     Lobe lb;
-    bool ok = sample_local(type, rough, ior, tex, entering, alb, wo_l, unif(rn.w[4]), unif(rn.w[5]), unif(rn.w[6]),
+    bool ok = sample_local<ATTR>(type, rough, ior, tex, entering, alb, wo_l, unif(rn.w[4]), unif(rn.w[5]), unif(rn.w[6]),
                            wi_l, W, pb, lb);
     if (!ok) return out;
     if (W.x == 0.0f && W.y == 0.0f && W.z == 0.0f) return out;

@@ -70,6 +70,9 @@ constexpr uint32_t kInstMarker = 0xFFFFFFFEu;
 constexpr int kAttrRecord = 4;
 constexpr int32_t kAttrNormals = 1;
 constexpr int32_t kAttrUV = 2;
+// a material of the scene is coated: the shading kernels' extended variant
+// (the one that also handles attributes) is needed
+constexpr int32_t kAttrCoat = 4;
 
 struct SceneView {
     const float4* __restrict__ nodes;
@@ -89,13 +92,15 @@ struct SceneView {
     // their gradients per workgroup before adding them to global memory
     const uint32_t* __restrict__ hot_ids;
     int32_t n_hot;
-    // two-level scene: instance records (kInstRecord float4 each), count;
-    // n_inst = 0 for a flat scene
+    // two-level scene: instance records (kInstRecord float4 each) and their
+    // count (0 for a flat scene); vertex attributes (kAttrRecord float4 per
+    // triangle, leaf order) and which kinds are present (kAttrNormals |
+    // kAttrUV; 0 = none).  The two pointers precede the two counts so the
+    // struct has no padding: kernels that keep a scene per lane in
+    // registers (the batched traversal) fit their register budget.
     const float4* __restrict__ insts;
-    int32_t n_inst;
-    // vertex attributes (kAttrRecord float4 per triangle, leaf order) and
-    // which kinds are present (kAttrNormals | kAttrUV; 0 = none)
     const float4* __restrict__ attrs;
+    int32_t n_inst;
     int32_t attr_flags;
 };
 

@@ -41,11 +41,12 @@ SceneView host_view(const pt_ctx* c) {
     v.insts = c->bvh.insts.empty() ? nullptr : c->bvh.insts.data();
     v.n_inst = (int32_t)(c->bvh.insts.size() / kInstRecord);
     v.attrs = c->attr_leaf.empty() ? nullptr : c->attr_leaf.data();
-    v.attr_flags = c->attr_leaf.empty() ? 0 : ((c->attr_n.empty() ? 0 : kAttrNormals) | (c->attr_uv.empty() ? 0 : kAttrUV));
+    v.attr_flags = shading_flags(c);
     return v;
 }
 
-bool has_attrs(const pt_ctx* c) { return !c->attr_leaf.empty(); }
+// the shading variant the library would launch
+bool has_attrs(const pt_ctx* c) { return shading_flags(c) != 0; }
 
 constexpr int kL = 16;
 

@@ -330,3 +330,17 @@ def test_batch_with_attribute_job_matches_oracle():
     for j, ((s, c), (e, kw)) in enumerate(zip([(s0, c0), (s1, c1)], jobs)):
         o, frag = oracle.Scene(s).render(c, job=j, **kw)
         assert_parity(imgs[j], o, frag, what=f"attribute batch job {j}")
+
+
+def test_coat_without_attributes_matches_oracle():
+    # coated materials alone select the extended shading variant
+    scene, cam = scenes.cornell()
+    scene = {k: v.copy() for k, v in scene.items()}
+    scene["materials"] = np.array([[0, 1.0, 1.5, 0], [scenes.COATED, 0.2, 1.6, 0]], np.float32)
+    scene["tri_mat"][10:22] = 1
+    cam = dict(cam, width=40, height=32)
+    cfg = dict(spp=3, max_depth=6, rr_start=3, seed=4)
+    E, img, rays, nexact = _check(scene, cam, **cfg)
+    assert nexact >= 0.999 * img.shape[0]
+    w, rw = E.wave(shuffle=6, tail=300, **cfg)
+    assert np.array_equal(w.view(np.uint32), img.view(np.uint32))

@@ -111,3 +111,20 @@ def test_batch_with_attribute_job_matches_oracle():
     for j, ((s, c), kw) in enumerate(zip(((s0, c0), (s1, c1), (s2, c2)), args)):
         o, frag = oracle.Scene(s).render(c, job=j, **kw)
         assert_parity(imgs[j].cpu().numpy().reshape(-1, 3), o, frag, what=f"attribute batch job {j}")
+
+
+def test_coat_without_attributes_matches_oracle():
+    # coated materials alone select the extended shading kernels
+    scene, cam = scenes.cornell()
+    scene = {k: v.copy() for k, v in scene.items()}
+    scene["materials"] = np.array([[0, 1.0, 1.5, 0], [scenes.COATED, 0.2, 1.6, 0]], np.float32)
+    scene["tri_mat"][10:22] = 1
+    cam = dict(cam, width=64, height=48)
+    cfg = dict(spp=4, max_depth=6, rr_start=3, seed=4)
+    R = ptmi.Renderer(scene, cam)
+    mega = R.render(mode="mega", **cfg).cpu().numpy()
+    wave = R.render(mode="wave", tail_bounce=2, tail_threshold=500, **cfg).cpu().numpy()
+    assert np.array_equal(mega.view(np.uint32), wave.view(np.uint32))
+    o, frag = oracle.Scene(scene).render(cam, **cfg)
+    nexact = assert_parity(wave.reshape(-1, 3), o, frag, what="coat without attributes")
+    assert nexact >= 0.999 * o.shape[0]
