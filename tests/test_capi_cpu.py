@@ -212,3 +212,46 @@ def test_largest_triangles_marked(which):
     for k, i in enumerate(order):
         expect[i] = k + 1
     assert np.array_equal(slot, expect)
+
+
+def test_attributes_validated():
+    L = ptmi.lib()
+    h = C.c_void_p()
+    assert L.pt_create(C.byref(h), -1) == 0
+    scene, _ = scenes.cornell_attributes()
+    nv = scene["positions"].shape[0]
+    nrm = np.ascontiguousarray(scene["normals"])
+    uvs = np.ascontiguousarray(scene["uvs"])
+    a = ptmi.AttributesDesc(nv, nrm.ctypes.data, uvs.ctypes.data)
+    assert L.pt_set_attributes(h, C.byref(a)) == ptmi.PT_ESTATE  # no scene yet
+    d, keep = _desc(scene)
+    assert L.pt_load_scene(h, C.byref(d)) == 0
+    bad = ptmi.AttributesDesc(nv - 1, nrm.ctypes.data, None)
+    assert L.pt_set_attributes(h, C.byref(bad)) == ptmi.PT_EINVAL  # count mismatch
+    nan = nrm.copy()
+    nan[3, 1] = np.inf
+    bad = ptmi.AttributesDesc(nv, nan.ctypes.data, None)
+    assert L.pt_set_attributes(h, C.byref(bad)) == ptmi.PT_EINVAL
+    # a coat needs a finite ior > 0; the checker frequency must be finite and >= 0
+    for m in ([3, 0.2, 0.0, 0], [0, 1.0, 1.5, -1.0], [0, 1.0, 1.5, np.nan]):
+        b = {k: v.copy() for k, v in scene.items()}
+        b["materials"] = np.array([m], np.float32)
+        b["tri_mat"][:] = 0
+        db, kb = _desc(b)
+        assert L.pt_load_scene(h, C.byref(db)) == ptmi.PT_EINVAL, m
+    assert L.pt_load_scene(h, C.byref(d)) == 0
+    assert L.pt_set_attributes(h, C.byref(a)) == 0
+    info = ptmi.BvhInfo()
+    assert L.pt_build_bvh(h, None, C.byref(info)) == 0
+    nt = scene["indices"].shape[0]
+    assert info.attribute_bytes == 64 * nt
+    # one record per triangle record
+    tris = np.zeros((nt, 12), np.float32)
+    assert L.pt_get_bvh(h, None, tris.ctypes.data, None, None) == 0
+    ids = tris[:, 3].view(np.uint32)
+    assert sorted(ids.tolist()) == list(range(nt))
+    # NULL desc removes the attributes; the scene reports none
+    assert L.pt_set_attributes(h, None) == 0
+    assert L.pt_build_bvh(h, None, C.byref(info)) == 0
+    assert info.attribute_bytes == 0
+    assert L.pt_destroy(h) == 0
