@@ -166,7 +166,7 @@ typedef struct {
 /* Filled by pt_build_bvh: sizes of the device buffers of pt_scene_buffers. */
 typedef struct {
     int64_t node_count, node_bytes;  /* BVH4 nodes, 80 B each (half-precision child boxes) */
-    int64_t tri_bytes;               /* 48 B per triangle, leaf order */
+    int64_t tri_bytes;               /* 48 B per triangle, leaf order, plus 32 B of padding */
     int64_t light_count, light_bytes;/* 16 B per light (leaf-order index, CDF word, input index, 0),
                                         then the input ids of the 64 largest triangles */
     int64_t material_bytes;          /* 16 B per material */
@@ -273,7 +273,8 @@ pt_status pt_load_scene(pt_ctx* ctx, const pt_scene_desc* scene);
  * area-proportional light CDF.  Synchronous, host only. */
 pt_status pt_build_bvh(pt_ctx* ctx, const pt_bvh_opts* opts, pt_bvh_info* info);
 
-/* Host copies of the built buffers (each may be NULL), sizes as reported. */
+/* Host copies of the built buffers (each may be NULL), sizes as reported
+ * (the triangle array without its 32 B of padding: 48 B per triangle). */
 pt_status pt_get_bvh(pt_ctx* ctx, void* nodes, void* tris, void* lights, void* materials);
 
 /* Upload the built buffers into the caller's device buffers on `stream`

@@ -547,7 +547,7 @@ pt_status pt_build_bvh(pt_ctx* c, const pt_bvh_opts* o, pt_bvh_info* info) {
     // attribute records in leaf order, keyed by each triangle record's input id
     c->attr_leaf.clear();
     if (!c->attr_n.empty() || !c->attr_uv.empty()) {
-        const size_t n = c->bvh.tris.size() / 3;
+        const size_t n = (size_t)c->nt;
         c->attr_leaf.assign(kAttrRecord * n, make_float4(0.f, 0.f, 0.f, 0.f));
         for (size_t j = 0; j < n; ++j) {
             uint32_t id;
@@ -587,7 +587,7 @@ pt_status pt_get_bvh(pt_ctx* c, void* nodes, void* tris, void* lights, void* mat
     if (!c) return fail(PT_EINVAL, "null context");
     if (!c->built) return fail(PT_ESTATE, "BVH not built");
     if (nodes) std::memcpy(nodes, c->bvh.nodes.data(), c->bvh.nodes.size() * sizeof(Node4));
-    if (tris) std::memcpy(tris, c->bvh.tris.data(), c->bvh.tris.size() * sizeof(float4));
+    if (tris) std::memcpy(tris, c->bvh.tris.data(), 3 * (size_t)c->nt * sizeof(float4));
     if (lights) std::memcpy(lights, c->bvh.lights.data(), c->bvh.lights.size() * sizeof(LightEntry));
     if (materials) std::memcpy(materials, c->mats.data(), c->mats.size() * sizeof(float));
     return PT_OK;

@@ -369,8 +369,8 @@ BuildResult build_scene(const std::vector<float>& tri_v, const std::vector<int32
     }
     r.stack_entries = 3 * r.depth + 1;
 
-    // triangles in leaf order
-    r.tris.resize(3 * (size_t)nt);
+    // triangles in leaf order, then the padding
+    r.tris.assign(3 * (size_t)nt + kTriPad, make_float4(0.f, 0.f, 0.f, 0.f));
     std::vector<uint8_t> is_light(nt);
     for (int32_t i = 0; i < nt; ++i) {
         const float* e = &emission[3 * (size_t)i];
@@ -618,7 +618,7 @@ BuildResult build_instanced(const std::vector<float>& tri_v, const std::vector<i
         const float* e = &emission[3 * (size_t)i];
         is_light[i] = (e[0] > 0.f || e[1] > 0.f || e[2] > 0.f);
     }
-    r.tris.resize(3 * (size_t)nt);
+    r.tris.assign(3 * (size_t)nt + kTriPad, make_float4(0.f, 0.f, 0.f, 0.f));
     std::vector<uint32_t> leaf_pos(nt);
     for (int32_t j = 0; j < nt; ++j) {
         const int32_t t = order[j];

@@ -9,7 +9,7 @@ namespace ptmi {
 
 struct BuildResult {
     std::vector<Node4> nodes;
-    std::vector<float4> tris;        // 3 per triangle, leaf order
+    std::vector<float4> tris;        // 3 per triangle, leaf order, then kTriPad zero float4
     std::vector<float4> insts;       // two-level scenes: kInstRecord per instance, top-level leaf order
     std::vector<LightEntry> lights;  // input order of the light triangles
     std::vector<uint32_t> hot_ids;   // input ids of the largest triangles, by slot (at most kHotTris)

@@ -409,17 +409,6 @@ PT_DEV void hit_finish(Hit& h) {
     }
 }
 
-// load a node: q[0] = (origin, scale exponents), q[1..3] = the x, y, z
-// planes (binary16 pairs), q[4] = child references
-PT_DEV void load_node(const float4* __restrict__ nodes, uint32_t idx, float4 q[5]) {
-    const float4* p = nodes + (size_t)mul24(idx, 5u);
-    q[0] = p[0];
-    q[1] = p[1];
-    q[2] = p[2];
-    q[3] = p[3];
-    q[4] = p[4];
-}
-
 // plane offset c (0..3) of a word pair (w0: children 0, 1; w1: 2, 3) as float
 PT_DEV float half_of(uint32_t w0, uint32_t w1, int c) {
     const uint32_t w = c < 2 ? w0 : w1;
@@ -504,6 +493,23 @@ PT_DEV void sort4(uint32_t ref[4], float t[4]) {
     cswap(ref[1], t[1], ref[2], t[2]);
 }
 
+// One fetch per lane and traversal step: five float4 from the node (an
+// inner node) or from the leaf's first triangle record (a leaf: its three
+// float4, then two that are not used; the triangle array's padding keeps
+// the last record readable), issued by the same instructions for every
+// lane before any lane uses them.  A wave whose lanes are at inner nodes
+// and at leaves then waits for memory once per step, not once per branch.
+// `ok` = the reference is in range (else node 0 is read and ignored).
+PT_DEV void fetch_item(const SceneView& sc, uint32_t ref, bool ok, float4 q[5]) {
+    const uint32_t r = ok ? ref : 0u;
+    const float4* p = (r & kLeafBit) ? sc.tris + (size_t)(r & kLeafFirstMask) * 3 : sc.nodes + (size_t)mul24(r, 5u);
+    q[0] = p[0];
+    q[1] = p[1];
+    q[2] = p[2];
+    q[3] = p[3];
+    q[4] = p[4];
+}
+
 // Closest hit in (0, tmax): smallest t, ties to the smaller input id.
 // References outside the node or triangle arrays are skipped, so a damaged
 // BVH cannot make a lane read out of bounds.
@@ -530,11 +536,15 @@ PT_DEV void closest_begin(float tmax, Hit& h, uint32_t& ref, TravStack<LDS, COUN
 // still hold a closer hit.  Returns false when the traversal is finished.
 template <int LDS, bool COUNT = false>
 PT_DEV bool closest_step(const SceneView& sc, const Ray& r, float tmax, Hit& h, uint32_t& ref, TravStack<LDS, COUNT>& st) {
-    if (!(ref & kLeafBit)) {
-        if (ref < (uint32_t)sc.n_nodes) {
+    const bool leaf = (ref & kLeafBit) != 0;
+    const uint32_t first = ref & kLeafFirstMask;
+    const uint32_t cnt = ((ref >> kLeafCountShift) & 15u) + 1u;
+    const bool ok = leaf ? first + cnt <= (uint32_t)sc.nt : ref < (uint32_t)sc.n_nodes;
+    float4 q[5];
+    fetch_item(sc, ref, ok, q);
+    if (!leaf) {
+        if (ok) {
             if constexpr (COUNT) ++st.nodes;
-            float4 q[5];
-            load_node(sc.nodes, ref, q);
             float tn[4];
             unsigned m = slab4_q(r, q, h.t, tn);
             if (m) {
@@ -556,13 +566,16 @@ PT_DEV bool closest_step(const SceneView& sc, const Ray& r, float tmax, Hit& h, 
             }
         }
     } else {
-        uint32_t first = ref & kLeafFirstMask;
-        uint32_t cnt = ((ref >> kLeafCountShift) & 15u) + 1u;
-        if (first + cnt <= (uint32_t)sc.nt) {
+        if (ok) {
             if constexpr (COUNT) st.tris += cnt;
             for (uint32_t i = first; i < first + cnt; ++i) {
-                const float4* tp = sc.tris + (size_t)i * 3;
-                float4 a = tp[0], b = tp[1], c = tp[2];
+                float4 a = q[0], b = q[1], c = q[2];  // the first triangle came with the fetch
+                if (i != first) {
+                    const float4* tp = sc.tris + (size_t)i * 3;
+                    a = tp[0];
+                    b = tp[1];
+                    c = tp[2];
+                }
                 float t, vn, wn, dn;
                 if (tri_test(r, xyz(a), xyz(b), xyz(c), t, vn, wn, dn) && t < tmax) {
                     uint32_t id = f2u(a.w);
@@ -625,11 +638,15 @@ PT_DEV void any_begin(uint32_t& ref, TravStack<LDS, COUNT>& st) {
 template <int LDS, bool COUNT = false>
 PT_DEV bool any_step(const SceneView& sc, const Ray& r, float tmax, uint32_t& ref, TravStack<LDS, COUNT>& st,
                      bool& occluded) {
-    if (!(ref & kLeafBit)) {
-        if (ref < (uint32_t)sc.n_nodes) {
+    const bool leaf = (ref & kLeafBit) != 0;
+    const uint32_t first = ref & kLeafFirstMask;
+    const uint32_t cnt = ((ref >> kLeafCountShift) & 15u) + 1u;
+    const bool ok = leaf ? first + cnt <= (uint32_t)sc.nt : ref < (uint32_t)sc.n_nodes;
+    float4 q[5];
+    fetch_item(sc, ref, ok, q);
+    if (!leaf) {
+        if (ok) {
             if constexpr (COUNT) ++st.nodes;
-            float4 q[5];
-            load_node(sc.nodes, ref, q);
             float tn[4];
             unsigned m = slab4_q(r, q, tmax, tn);
             if (m) {
@@ -643,13 +660,16 @@ PT_DEV bool any_step(const SceneView& sc, const Ray& r, float tmax, uint32_t& re
             }
         }
     } else {
-        uint32_t first = ref & kLeafFirstMask;
-        uint32_t cnt = ((ref >> kLeafCountShift) & 15u) + 1u;
-        if (first + cnt <= (uint32_t)sc.nt) {
+        if (ok) {
             for (uint32_t i = first; i < first + cnt; ++i) {
                 if constexpr (COUNT) ++st.tris;
-                const float4* tp = sc.tris + (size_t)i * 3;
-                float4 a = tp[0], b = tp[1], c = tp[2];
+                float4 a = q[0], b = q[1], c = q[2];  // the first triangle came with the fetch
+                if (i != first) {
+                    const float4* tp = sc.tris + (size_t)i * 3;
+                    a = tp[0];
+                    b = tp[1];
+                    c = tp[2];
+                }
                 float t, vn, wn, dn;
                 if (tri_test(r, xyz(a), xyz(b), xyz(c), t, vn, wn, dn) && t < tmax) {
                     occluded = true;
@@ -734,11 +754,17 @@ PT_DEV bool inst_enter(const SceneView& sc, Ray& r, InstTrav& it, uint32_t& ref,
 template <int LDS, bool COUNT = false>
 PT_DEV bool closest_step_inst(const SceneView& sc, Ray& r, InstTrav& it, float tmax, Hit& h, uint32_t& ref,
                               TravStack<LDS, COUNT>& st) {
-    if (!(ref & kLeafBit)) {
-        if (ref < (uint32_t)sc.n_nodes) {
+    // one fetch as in closest_step (an instance leaf fetches its record in
+    // inst_enter instead)
+    const bool leaf = (ref & kLeafBit) != 0;
+    const uint32_t first = ref & kLeafFirstMask;
+    const uint32_t cnt = ((ref >> kLeafCountShift) & 15u) + 1u;
+    const bool ok = leaf ? it.obj && first + cnt <= (uint32_t)sc.nt : ref < (uint32_t)sc.n_nodes;
+    float4 q[5];
+    fetch_item(sc, ref, ok, q);
+    if (!leaf) {
+        if (ok) {
             if constexpr (COUNT) ++st.nodes;
-            float4 q[5];
-            load_node(sc.nodes, ref, q);
             float tn[4];
             unsigned m = slab4_q(r, q, h.t, tn);
             if (m) {
@@ -761,13 +787,16 @@ PT_DEV bool closest_step_inst(const SceneView& sc, Ray& r, InstTrav& it, float t
     } else if (!it.obj) {
         if (inst_enter<LDS, COUNT>(sc, r, it, ref, st)) return true;
     } else {
-        uint32_t first = ref & kLeafFirstMask;
-        uint32_t cnt = ((ref >> kLeafCountShift) & 15u) + 1u;
-        if (first + cnt <= (uint32_t)sc.nt) {
+        if (ok) {
             if constexpr (COUNT) st.tris += cnt;
             for (uint32_t i = first; i < first + cnt; ++i) {
-                const float4* tp = sc.tris + (size_t)i * 3;
-                float4 a = tp[0], b = tp[1], c = tp[2];
+                float4 a = q[0], b = q[1], c = q[2];  // the first triangle came with the fetch
+                if (i != first) {
+                    const float4* tp = sc.tris + (size_t)i * 3;
+                    a = tp[0];
+                    b = tp[1];
+                    c = tp[2];
+                }
                 float t, vn, wn, dn;
                 if (tri_test(r, xyz(a), xyz(b), xyz(c), t, vn, wn, dn) && t < tmax) {
                     uint32_t id = f2u(a.w);
@@ -812,11 +841,15 @@ PT_DEV void closest_begin_inst(f3 o, f3 d, float tmax, Ray& r, InstTrav& it, Hit
 template <int LDS, bool COUNT = false>
 PT_DEV bool any_step_inst(const SceneView& sc, Ray& r, InstTrav& it, float tmax, uint32_t& ref,
                           TravStack<LDS, COUNT>& st, bool& occluded) {
-    if (!(ref & kLeafBit)) {
-        if (ref < (uint32_t)sc.n_nodes) {
+    const bool leaf = (ref & kLeafBit) != 0;
+    const uint32_t first = ref & kLeafFirstMask;
+    const uint32_t cnt = ((ref >> kLeafCountShift) & 15u) + 1u;
+    const bool ok = leaf ? it.obj && first + cnt <= (uint32_t)sc.nt : ref < (uint32_t)sc.n_nodes;
+    float4 q[5];
+    fetch_item(sc, ref, ok, q);
+    if (!leaf) {
+        if (ok) {
             if constexpr (COUNT) ++st.nodes;
-            float4 q[5];
-            load_node(sc.nodes, ref, q);
             float tn[4];
             unsigned m = slab4_q(r, q, tmax, tn);
             if (m) {
@@ -831,13 +864,16 @@ PT_DEV bool any_step_inst(const SceneView& sc, Ray& r, InstTrav& it, float tmax,
     } else if (!it.obj) {
         if (inst_enter<LDS, COUNT>(sc, r, it, ref, st)) return true;
     } else {
-        uint32_t first = ref & kLeafFirstMask;
-        uint32_t cnt = ((ref >> kLeafCountShift) & 15u) + 1u;
-        if (first + cnt <= (uint32_t)sc.nt) {
+        if (ok) {
             for (uint32_t i = first; i < first + cnt; ++i) {
                 if constexpr (COUNT) ++st.tris;
-                const float4* tp = sc.tris + (size_t)i * 3;
-                float4 a = tp[0], b = tp[1], c = tp[2];
+                float4 a = q[0], b = q[1], c = q[2];  // the first triangle came with the fetch
+                if (i != first) {
+                    const float4* tp = sc.tris + (size_t)i * 3;
+                    a = tp[0];
+                    b = tp[1];
+                    c = tp[2];
+                }
                 float t, vn, wn, dn;
                 if (tri_test(r, xyz(a), xyz(b), xyz(c), t, vn, wn, dn) && t < tmax) {
                     occluded = true;

@@ -38,6 +38,9 @@ constexpr int64_t kMaxTris = int64_t(kLeafFirstMask) + 1;
 // Triangle in leaf order, 48 bytes: three float4 = (v0, input id bits),
 // (v1, material index | light flag bit 31), (v2, 0).
 constexpr uint32_t kLightFlag = 0x80000000u;
+// The triangle array ends with kTriPad zero float4 after the last record, so
+// a traversal step may read five float4 from any record (see fetch_item).
+constexpr int kTriPad = 2;
 
 // Light table entry, 16 bytes: leaf-order triangle index, the u32 CDF word,
 // the input triangle index (which addresses the emission array), zero.
