@@ -245,9 +245,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
                 const uint32_t pos = next + rank_in(idle);
                 if (pos < end) {
                     const uint32_t i = perm ? perm[pos] : pos;
+                    // both loads issued before either is used (one wait)
                     const float4 o4 = wb.ray_o[cur][i];
+                    const float4 d4 = wb.ray_d[cur][i];
                     if (f2u(o4.w) != kDeadPath) {  // dead slots (no compaction) need no hit
-                        const float4 d4 = wb.ray_d[cur][i];
                         if constexpr (INST) {
                             closest_begin_inst<LDS>(xyz(o4), xyz(d4), INFINITY, ray, it, h, ref, st);
                         } else {
