@@ -751,19 +751,22 @@ PT_DEV bool inst_enter(const SceneView& sc, Ray& r, InstTrav& it, uint32_t& ref,
 
 // closest_step over a two-level scene; closest-hit key (t, input instance,
 // input triangle)
-template <int LDS, bool COUNT = false>
+template <int LDS, bool COUNT = false, bool SPLIT = false>
 PT_DEV bool closest_step_inst(const SceneView& sc, Ray& r, InstTrav& it, float tmax, Hit& h, uint32_t& ref,
                               TravStack<LDS, COUNT>& st) {
     // one fetch as in closest_step (an instance leaf fetches its record in
-    // inst_enter instead)
+    // inst_enter instead); SPLIT: each branch fetches its own (the
+    // megakernel's two-level traversal, whose register budget the single
+    // fetch exceeds)
     const bool leaf = (ref & kLeafBit) != 0;
     const uint32_t first = ref & kLeafFirstMask;
     const uint32_t cnt = ((ref >> kLeafCountShift) & 15u) + 1u;
     const bool ok = leaf ? it.obj && first + cnt <= (uint32_t)sc.nt : ref < (uint32_t)sc.n_nodes;
     float4 q[5];
-    fetch_item(sc, ref, ok, q);
+    if constexpr (!SPLIT) fetch_item(sc, ref, ok, q);
     if (!leaf) {
         if (ok) {
+            if constexpr (SPLIT) fetch_item(sc, ref, true, q);
             if constexpr (COUNT) ++st.nodes;
             float tn[4];
             unsigned m = slab4_q(r, q, h.t, tn);
@@ -788,6 +791,7 @@ PT_DEV bool closest_step_inst(const SceneView& sc, Ray& r, InstTrav& it, float t
         if (inst_enter<LDS, COUNT>(sc, r, it, ref, st)) return true;
     } else {
         if (ok) {
+            if constexpr (SPLIT) fetch_item(sc, ref, true, q);
             if constexpr (COUNT) st.tris += cnt;
             for (uint32_t i = first; i < first + cnt; ++i) {
                 float4 a = q[0], b = q[1], c = q[2];  // the first triangle came with the fetch
@@ -838,7 +842,7 @@ PT_DEV void closest_begin_inst(f3 o, f3 d, float tmax, Ray& r, InstTrav& it, Hit
 }
 
 // any_step over a two-level scene
-template <int LDS, bool COUNT = false>
+template <int LDS, bool COUNT = false, bool SPLIT = false>
 PT_DEV bool any_step_inst(const SceneView& sc, Ray& r, InstTrav& it, float tmax, uint32_t& ref,
                           TravStack<LDS, COUNT>& st, bool& occluded) {
     const bool leaf = (ref & kLeafBit) != 0;
@@ -846,9 +850,10 @@ PT_DEV bool any_step_inst(const SceneView& sc, Ray& r, InstTrav& it, float tmax,
     const uint32_t cnt = ((ref >> kLeafCountShift) & 15u) + 1u;
     const bool ok = leaf ? it.obj && first + cnt <= (uint32_t)sc.nt : ref < (uint32_t)sc.n_nodes;
     float4 q[5];
-    fetch_item(sc, ref, ok, q);
+    if constexpr (!SPLIT) fetch_item(sc, ref, ok, q);
     if (!leaf) {
         if (ok) {
+            if constexpr (SPLIT) fetch_item(sc, ref, true, q);
             if constexpr (COUNT) ++st.nodes;
             float tn[4];
             unsigned m = slab4_q(r, q, tmax, tn);
@@ -865,6 +870,7 @@ PT_DEV bool any_step_inst(const SceneView& sc, Ray& r, InstTrav& it, float tmax,
         if (inst_enter<LDS, COUNT>(sc, r, it, ref, st)) return true;
     } else {
         if (ok) {
+            if constexpr (SPLIT) fetch_item(sc, ref, true, q);
             for (uint32_t i = first; i < first + cnt; ++i) {
                 if constexpr (COUNT) ++st.tris;
                 float4 a = q[0], b = q[1], c = q[2];  // the first triangle came with the fetch
@@ -905,7 +911,7 @@ PT_DEV Hit closest_hit_t(const SceneView& sc, f3 o, f3 d, float tmax, TravStack<
         InstTrav it;
         uint32_t ref;
         closest_begin_inst<LDS>(o, d, tmax, r, it, h, ref, st);
-        while (closest_step_inst<LDS>(sc, r, it, tmax, h, ref, st)) {
+        while (closest_step_inst<LDS, COUNT, true>(sc, r, it, tmax, h, ref, st)) {
         }
         hit_finish(h);
         return h;
@@ -922,7 +928,7 @@ PT_DEV bool any_hit_t(const SceneView& sc, f3 o, f3 d, float tmax, TravStack<LDS
         uint32_t ref;
         any_begin<LDS>(ref, st);
         bool occluded = false;
-        while (any_step_inst<LDS>(sc, r, it, tmax, ref, st, occluded)) {
+        while (any_step_inst<LDS, COUNT, true>(sc, r, it, tmax, ref, st, occluded)) {
         }
         return occluded;
     } else {
