@@ -110,8 +110,9 @@ k_batch_extend(BatchBufs bb, int q, uint2* __restrict__ ovf, int gcap) {
 
 // slots of the next queue and of the shadow queue reserved once per block
 // and trip (see k_shade)
+// four waves per SIMD, as k_shade (without attributes: 128 VGPRs, no spill)
 template <bool ATTR>
-__global__ void __launch_bounds__(256) k_batch_shade(BatchBufs bb, int q) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_batch_shade(BatchBufs bb, int q) {
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t count = bb.ctl->count;
     __shared__ BlockReserve br;

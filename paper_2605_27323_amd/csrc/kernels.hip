@@ -285,8 +285,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
     if (st.overflow) atomicOr(&wb.counts[wb.err_slot], 1u);
 }
 
+// Four waves per SIMD (at most 128 VGPRs, a few spilled): at the 137 it
+// needs otherwise it ran three, and the stage took 17 % longer.
 template <bool INST, bool ATTR>
-__global__ void __launch_bounds__(256) k_shade(SceneView sc, PathParams pp, WaveBufs wb, int b, int compact,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_shade(SceneView sc, PathParams pp, WaveBufs wb, int b, int compact,
                                                int sorted, uint32_t tail) {
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
