@@ -434,19 +434,23 @@ def compaction_bench(torch, R, img, ptmi, kw, params, k=6):
     """Pure wavefront with compaction (live paths packed into the next queue
     after every bounce) against no compaction (every path slot dispatched
     every bounce, finished ones skipped), at depth 8 and 16 (paper Sec. 3.1:
-    the gain grows with the maximum depth)."""
+    the gain grows with the maximum depth); and the paper's two-slot live
+    count with a promote kernel after every bounce against one counter per
+    bounce."""
     res = {}
     base = dict(params, **PURE)
     base.pop("flags", None)
     for depth in (DEPTH, 16):
         r = {}
-        for name, flags in [("compacted", 0), ("no_compaction", ptmi.FLAG_NO_COMPACT)]:
+        for name, flags in [("compacted", 0), ("no_compaction", ptmi.FLAG_NO_COMPACT),
+                            ("two_slot_promote", ptmi.FLAG_TWO_SLOT)]:
             p = dict(base, flags=flags)
             a = dict(kw, max_depth=depth)
             time_frames(torch, R, img, 1, 0, False, mode="wave", **a, **p)
             dt = time_frames(torch, R, img, k, 1, False, mode="wave", **a, **p)
             r[name] = {"ms_per_frame": dt * 1e3 / k}
         r["gain"] = r["no_compaction"]["ms_per_frame"] / r["compacted"]["ms_per_frame"]
+        r["two_slot_over_per_bounce"] = r["two_slot_promote"]["ms_per_frame"] / r["compacted"]["ms_per_frame"]
         res[f"depth{depth}"] = r
         log(f"compaction depth {depth}: {r['compacted']['ms_per_frame']:.3f} ms vs "
             f"{r['no_compaction']['ms_per_frame']:.3f} ms without ({r['gain']:.2f}x)")

@@ -72,9 +72,13 @@ enum {
                                   (pt_frame_stats); a separate kernel build, slower */
     PT_FLAG_SORT_RAYS = 16,    /* wavefront: counting-sort each extend queue by ray direction octant and
                                   origin side of the scene centre (coherent waves) */
-    PT_FLAG_XCD_LOCAL = 32     /* each of the eight XCDs (own L2 each) takes one contiguous part of the
+    PT_FLAG_XCD_LOCAL = 32,    /* each of the eight XCDs (own L2 each) takes one contiguous part of the
                                   extend / shadow queues, and the megakernel's waves on an XCD take their
                                   pixels from one band of rows first; same image bit for bit */
+    PT_FLAG_TWO_SLOT = 64      /* wavefront, ablation of paper Sec. 3.1: the live path count in a
+                                  two-slot buffer (current, next) that a one-thread promote kernel
+                                  moves over after every bounce, in place of one counter per bounce;
+                                  same image bit for bit */
 };
 
 typedef struct pt_ctx pt_ctx;
@@ -352,7 +356,8 @@ pt_status pt_render_backward(pt_ctx* ctx, const pt_render_args* args, const floa
 /* Statistics of the last frame rendered (synchronises the stream).
  * Stages (index k): 0 raygen, 1 extend, 2 shade, 3 shadow, 4 accumulate,
  * 5 megakernel, 6 sort, 7 adjoint replay B (gradients), 8 hybrid tail,
- * 9 adjoint replay A (path radiance).
+ * 9 adjoint replay A (path radiance), 10 promote (the two-slot count
+ * buffer of PT_FLAG_TWO_SLOT).
  *   stage_ms[k], launches[k]: HIP-event time and launch count per stage,
  *     filled only when the frame ran with PT_FLAG_PROFILE (else 0).
  *   stage_items[k]: work items the stage's launches processed (paths for
@@ -370,7 +375,7 @@ pt_status pt_render_backward(pt_ctx* ctx, const pt_render_args* args, const floa
  *   and hybrid tail, or megakernel; for the adjoint the rays of the paths,
  *   which replay A and replay B each trace once).
  * PT_EOVERFLOW if a traversal stack overflowed during the frame. */
-#define PT_NSTAGES 10
+#define PT_NSTAGES 11
 typedef struct {
     double stage_ms[PT_NSTAGES];
     int64_t launches[PT_NSTAGES];

@@ -89,6 +89,7 @@ struct pt_ctx {
     int last_spp = 1, last_nee = 1, last_compact = 1, last_sort = 0;
     uint32_t last_tail = 0, last_sort_threshold = 0;
     int last_tail_bounce = 0;
+    int64_t last_promotes = 0;  // promote launches of the last frame (PT_FLAG_TWO_SLOT)
     uint64_t last_npix = 0;
     bool last_acc = false;
     bool last_valid = false;
@@ -141,9 +142,10 @@ WsLayout layout(const pt_ctx* c, const pt_render_args* a, const Launch& L, bool 
     WsLayout w{};
     const size_t npaths = (size_t)c->cam.W * c->cam.H * a->spp;
     // [0, D+1] live paths per bounce, [D+2, 2D+2] shadow rays per bounce,
-    // [2D+3, 2D+4] rays traced by the hybrid tail, [2D+5] overflow flag
+    // [2D+3, 2D+4] rays traced by the hybrid tail, [2D+6, 2D+7] the
+    // two-slot count buffer (PT_FLAG_TWO_SLOT), the last word the overflow flag
     // (the megakernel's eight band cursors, u64, take words 8 .. 23)
-    w.ncounts = std::max(2 * a->max_depth + 6, 24);
+    w.ncounts = std::max(2 * a->max_depth + 9, 24);
     size_t off = 0;
     w.counts = off;
     off = align_up(off + sizeof(uint32_t) * w.ncounts);
@@ -176,7 +178,7 @@ pt_status check_args(const pt_ctx* c, const pt_render_args* a) {
     if (!c->bound) return fail(PT_ESTATE, "scene not bound (pt_bind_scene)");
     if (!c->cam_set) return fail(PT_ESTATE, "camera not set (pt_set_camera)");
     if (a->flags & ~(PT_FLAG_PROFILE | PT_FLAG_NO_COMPACT | PT_FLAG_SORT_MATERIAL | PT_FLAG_COUNT_WORK | PT_FLAG_SORT_RAYS |
-                     PT_FLAG_XCD_LOCAL))
+                     PT_FLAG_XCD_LOCAL | PT_FLAG_TWO_SLOT))
         return fail(PT_EINVAL, "unknown flag");
     if (a->spp < 1 || a->spp > 65536) return fail(PT_EINVAL, "spp must be in [1, 65536]");
     if (a->max_depth < 0 || a->max_depth > 1000) return fail(PT_EINVAL, "max_depth must be in [0, 1000]");
@@ -215,8 +217,10 @@ hipError_t timed(pt_ctx* c, bool prof, int stage, hipStream_t s, F fn) {
     return e;
 }
 
-void remember_frame(pt_ctx* c, const pt_render_args* a, uint32_t* counts, int ncounts, int kind, bool acc) {
+void remember_frame(pt_ctx* c, const pt_render_args* a, uint32_t* counts, int ncounts, int kind, bool acc,
+                    int64_t promotes = 0) {
     c->last_counts = counts;
+    c->last_promotes = promotes;
     c->last_ncounts = ncounts;
     c->last_D = a->max_depth;
     c->last_kind = kind;
@@ -257,6 +261,7 @@ pt_status enqueue_stages(pt_ctx* c, const pt_render_args* a, const Launch& L, co
         // counters: [0] extension rays, [1] shadow rays, [2] overflow flag, [4..5] the
         // megakernel's 64-bit pixel cursor
         PT_HIP(timed(c, prof, 5, s, [&] { return launch_mega(L.lds, count, a->mega_waves == 5 ? 5 : 4, grid, block, s, c->view, c->cam, pp, img, acc, ovf, L.gcap, counts, trav, xcd); }), "megakernel");
+        remember_frame(c, a, counts, w.ncounts, 0, acc != nullptr);
     } else {
         WaveBufs wb{};
         for (int q = 0; q < 2; ++q) {
@@ -274,6 +279,8 @@ pt_status enqueue_stages(pt_ctx* c, const pt_render_args* a, const Launch& L, co
         wb.sh_base = a->max_depth + 2;
         wb.tail_slot = 2 * a->max_depth + 3;
         wb.err_slot = w.ncounts - 1;
+        wb.two_slot = (a->flags & PT_FLAG_TWO_SLOT) ? 1 : 0;
+        wb.slot = 2 * a->max_depth + 6;
         wb.sort_key = reinterpret_cast<uint32_t*>(base + w.sort_key);
         wb.perm = reinterpret_cast<uint32_t*>(base + w.perm);
         wb.hist = reinterpret_cast<uint32_t*>(base + w.hist);
@@ -284,6 +291,11 @@ pt_status enqueue_stages(pt_ctx* c, const pt_render_args* a, const Launch& L, co
         PT_HIP(launch_init_counts(s, counts, w.ncounts, npaths), "init counters");
         if (sort || rsort) PT_HIP(launch_init_counts(s, wb.hist, 2 * kSortBins + 1, 0u), "init sort histogram");
         PT_HIP(timed(c, prof, 0, s, [&] { return launch_raygen(grid, block, s, c->cam, pp, wb); }), "raygen");
+        int64_t promotes = 0;
+        if (wb.two_slot) {
+            PT_HIP(timed(c, prof, 10, s, [&] { return launch_promote(s, wb, -1); }), "promote");
+            ++promotes;
+        }
         for (int b = 0; b <= a->max_depth; ++b) {
             if (rsort)
                 PT_HIP(timed(c, prof, 6, s, [&] { return launch_sort(grid, block, s, c->view, wb, b, a->sort_threshold, 1); }), "ray sort");
@@ -302,12 +314,16 @@ pt_status enqueue_stages(pt_ctx* c, const pt_render_args* a, const Launch& L, co
                        }),
                        "hybrid tail");
             if (last) break;
+            if (wb.two_slot) {
+                PT_HIP(timed(c, prof, 10, s, [&] { return launch_promote(s, wb, b); }), "promote");
+                ++promotes;
+            }
             if (b < a->max_depth && a->nee)
                 PT_HIP(timed(c, prof, 3, s, [&] { return launch_shadow(L.lds, count, grid, block, s, c->view, wb, b, ovf, L.gcap, xcd); }), "shadow");
         }
         *Lbuf = wb.L;
+        remember_frame(c, a, counts, w.ncounts, 1, acc != nullptr, promotes);
     }
-    remember_frame(c, a, counts, w.ncounts, a->mode == PT_MODE_WAVE ? 1 : 0, acc != nullptr);
     c->last_trav = trav;
     return PT_OK;
 }
@@ -939,6 +955,10 @@ pt_status pt_frame_stats_get(pt_ctx* c, pt_frame_stats* out) {
     out->stage_bytes[3] = 48.0 * (double)out->stage_items[3];
     out->stage_bytes[6] = 28.0 * (double)out->stage_items[6];
     out->stage_bytes[8] = 96.0 * (double)out->stage_items[8];
+    // promote launches of the two-slot count buffer: one word read, three
+    // written (16 B)
+    out->stage_items[10] = c->last_promotes;
+    out->stage_bytes[10] = 16.0 * (double)c->last_promotes;
     out->stage_items[4] = (int64_t)npix;
     out->stage_bytes[4] = (double)npix * (16.0 * c->last_spp + img_bytes);
     if (h[c->last_ncounts - 1]) return fail(PT_EOVERFLOW, "traversal stack overflow");

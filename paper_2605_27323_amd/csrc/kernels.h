@@ -28,6 +28,10 @@ struct WaveBufs {
     // [tail_slot + 1] extension and shadow rays traced by the hybrid tail,
     // [err_slot] traversal stack overflow flag
     uint32_t* counts;
+    // two_slot != 0 (the paper's two-slot count buffer, an ablation): the
+    // stage kernels read the live count from [slot] and add the next
+    // bounce's to [slot + 1]; k_promote moves it over between bounces
+    int two_slot, slot;
     // traversal work counters: node visits and triangle tests of the
     // extend [0, 1], shadow [2, 3] and hybrid-tail [4, 5] kernels
     unsigned long long* trav;
@@ -42,6 +46,14 @@ struct WaveBufs {
 };
 
 constexpr int kSortBins = 64;
+
+// the live count of bounce b and the next bounce's count
+__host__ __device__ inline uint32_t live_slot(const WaveBufs& wb, int b) {
+    return wb.two_slot ? (uint32_t)wb.slot : (uint32_t)b;
+}
+__host__ __device__ inline uint32_t next_slot(const WaveBufs& wb, int b) {
+    return wb.two_slot ? (uint32_t)wb.slot + 1u : (uint32_t)b + 1u;
+}
 // persistent traversal kernels refill a wave's idle lanes once this many
 // of its 64 lanes are idle
 constexpr uint32_t kRefill = 16;
@@ -53,6 +65,7 @@ constexpr uint32_t kRefill = 16;
 hipError_t launch_mega(int lds, bool count, int waves, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
                        const CamView& cam, const PathParams& pp, float* img, float* acc, uint2* ovf, int gcap,
                        uint32_t* stats, unsigned long long* trav, int xcd_local);
+hipError_t launch_promote(hipStream_t s, const WaveBufs& wb, int b);
 hipError_t launch_init_counts(hipStream_t s, uint32_t* counts, int n, uint32_t first);
 hipError_t launch_raygen(dim3 grid, dim3 block, hipStream_t s, const CamView& cam, const PathParams& pp,
                          const WaveBufs& wb);

@@ -155,6 +155,21 @@ __global__ void k_init_counts(uint32_t* __restrict__ counts, int n, uint32_t fir
     if (i < n) counts[i] = i == 0 ? first : 0u;
 }
 
+// The paper's two-slot count buffer (ablation): after a bounce, the next
+// bounce's live count moves from slot + 1 to slot, slot + 1 is cleared, and
+// the count is also kept at [b + 1] for the frame statistics.  b = -1 (the
+// frame start): the slot takes [0], the initial paths.
+__global__ void k_promote(WaveBufs wb, int b) {
+    uint32_t* c = wb.counts;
+    if (b < 0) {
+        c[wb.slot] = c[0];
+    } else {
+        c[b + 1] = c[wb.slot + 1];
+        c[wb.slot] = c[wb.slot + 1];
+    }
+    c[wb.slot + 1] = 0u;
+}
+
 // hybrid tail: a queue with fewer than `tail` paths is too short to keep
 // the stage kernels busy; each path is shaded and finished in place.
 // Limited to 128 VGPRs (4 waves per SIMD, a few spilled registers): at 148
@@ -164,7 +179,7 @@ template <int LDS, bool COUNT, bool INST, bool ATTR>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_shade_tail(SceneView sc, PathParams pp, WaveBufs wb, int b, int sorted,
                                                     uint32_t tail, uint2* __restrict__ ovf, int gcap,
                                                     uint32_t spread) {
-    const uint32_t count = wb.counts[b];
+    const uint32_t count = wb.counts[live_slot(wb, b)];
     if (!(count < tail) || count == 0u) return;
     extern __shared__ __align__(8) uint32_t smem[];
     __shared__ uint32_t light_buf[3 * kLdsLights];
@@ -231,7 +246,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
     // with a ray sort this bounce, position i of the queue is slot perm[i]
     const uint32_t* perm = (sorted && wb.hist[2 * kSortBins]) ? wb.perm : nullptr;
     uint32_t next, end;
-    wave_chunk(wb.counts[b], next, end, xcd_local);
+    wave_chunk(wb.counts[live_slot(wb, b)], next, end, xcd_local);
     bool live = false;
     uint32_t item = 0, ref = 0;
     Ray ray;
@@ -292,14 +307,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
                                                int sorted, uint32_t tail) {
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t count = wb.counts[b];
+    const uint32_t count = wb.counts[live_slot(wb, b)];
     if (compact && count < tail) return;  // k_shade_tail finishes this queue
     if (count == 0u) return;
     __shared__ uint32_t light_buf[3 * kLdsLights];
     const LightCache lc = stage_lights(sc, light_buf);
     const uint32_t* perm = (sorted && wb.hist[2 * kSortBins]) ? wb.perm : nullptr;
     const int nxt = (b & 1) ^ 1;
-    uint32_t* next_count = &wb.counts[b + 1];
+    uint32_t* next_count = &wb.counts[next_slot(wb, b)];
     uint32_t* sh_count = &wb.counts[wb.sh_base + b];
     if (!compact && gtid == 0 && count) atomicMax(next_count, count);
     // Queue slots are reserved once per block and trip, not once per wave:
@@ -400,7 +415,7 @@ __global__ void __launch_bounds__(256) k_average(const float* __restrict__ I, ui
 // origin side (extend queue)
 __global__ void __launch_bounds__(256) k_sort_hist(SceneView sc, WaveBufs wb, int b, uint32_t threshold, int key_kind) {
     __shared__ uint32_t h[kSortBins];
-    const uint32_t count = wb.counts[b];
+    const uint32_t count = wb.counts[live_slot(wb, b)];
     if (count < threshold) return;
     for (int t = threadIdx.x; t < kSortBins; t += blockDim.x) h[t] = 0u;
     __syncthreads();
@@ -421,7 +436,7 @@ __global__ void __launch_bounds__(256) k_sort_hist(SceneView sc, WaveBufs wb, in
 __global__ void k_sort_scan(WaveBufs wb, int b, uint32_t threshold) {
     __shared__ uint32_t v[kSortBins];
     const int t = threadIdx.x;
-    const bool active = wb.counts[b] >= threshold;
+    const bool active = wb.counts[live_slot(wb, b)] >= threshold;
     v[t] = active ? wb.hist[t] : 0u;
     __syncthreads();
     for (int off = 1; off < kSortBins; off <<= 1) {
@@ -439,7 +454,7 @@ __global__ void k_sort_scan(WaveBufs wb, int b, uint32_t threshold) {
 // per non-empty bin, then perm[offset + rank] = slot
 __global__ void __launch_bounds__(256) k_sort_scatter(WaveBufs wb, int b, uint32_t threshold) {
     __shared__ uint32_t cnt[kSortBins], base[kSortBins];
-    const uint32_t count = wb.counts[b];
+    const uint32_t count = wb.counts[live_slot(wb, b)];
     if (count < threshold) return;
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t c0 = blockIdx.x * blockDim.x; c0 < count; c0 += stride) {
@@ -518,6 +533,11 @@ hipError_t launch_mega(int lds, bool count, int waves, dim3 grid, dim3 block, hi
 #undef X
 #undef L
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_promote(hipStream_t s, const WaveBufs& wb, int b) {
+    hipLaunchKernelGGL(k_promote, dim3(1), dim3(1), 0, s, wb, b);
+    return hipGetLastError();
 }
 
 hipError_t launch_init_counts(hipStream_t s, uint32_t* counts, int n, uint32_t first) {

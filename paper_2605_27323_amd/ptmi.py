@@ -19,9 +19,10 @@ PT_OK, PT_EINVAL, PT_ENOMEM, PT_EHIP, PT_ESTATE, PT_EOVERFLOW, PT_EUNSUPPORTED =
 MODE_MEGA, MODE_WAVE = 0, 1
 FLAG_PROFILE, FLAG_NO_COMPACT, FLAG_SORT_MATERIAL, FLAG_COUNT_WORK, FLAG_SORT_RAYS = 1, 2, 4, 8, 16
 FLAG_XCD_LOCAL = 32
+FLAG_TWO_SLOT = 64
 SAMPLER_PHILOX, SAMPLER_HALTON = 0, 1
 STAGES = ["raygen", "extend", "shade", "shadow", "accumulate", "mega", "sort", "adjoint", "tail",
-          "adjoint_radiance"]
+          "adjoint_radiance", "promote"]
 
 
 class PtError(RuntimeError):
@@ -77,7 +78,7 @@ class RenderArgs(C.Structure):
                 ("mega_waves", C.c_int32)]
 
 
-NSTAGES = 10
+NSTAGES = 11
 
 
 class FrameStats(C.Structure):

@@ -336,3 +336,32 @@ def test_halton_sampler_vs_oracle():
     a = R.args(spp=1)
     a.tail_spread = 2  # 0 or 1 only
     assert ptmi.lib().pt_render_frame(R.h, ctypes.byref(a), out.data_ptr(), None, ws, wsb, R._stream()) == -1
+
+
+def test_two_slot_count_buffer_bit_identical():
+    # the paper's two-slot live count with a promote kernel between bounces
+    # (Sec. 3.1), as an ablation of the per-bounce counters: same image and
+    # ray counts in every wavefront configuration, one promote per bounce
+    scene, cam = scenes.procedural(seed=41, n_objects=30, width=64, height=40)
+    log("two-slot counts")
+    R = ptmi.Renderer(scene, cam)
+    cfg = dict(spp=2, max_depth=6, rr_start=2, seed=3)
+    T = ptmi.FLAG_TWO_SLOT
+    for kw in (dict(), dict(flags=ptmi.FLAG_NO_COMPACT), dict(flags=ptmi.FLAG_SORT_MATERIAL | ptmi.FLAG_SORT_RAYS),
+               dict(tail_threshold=700), dict(tail_bounce=3, tail_threshold=300), dict(block=64, grid_mult=1)):
+        flags = kw.pop("flags", 0)
+        ref = R.render(mode="wave", flags=flags, **kw, **cfg).cpu().numpy()
+        st_ref = R.stats()
+        img = R.render(mode="wave", flags=flags | T, **kw, **cfg).cpu().numpy()
+        st = R.stats()
+        assert np.array_equal(img.view(np.uint32), ref.view(np.uint32)), kw
+        assert st["extension_rays"] == st_ref["extension_rays"] and st["shadow_rays"] == st_ref["shadow_rays"], kw
+        assert st["items"].get("extend") == st_ref["items"].get("extend"), kw
+        assert st["items"]["promote"] >= 2 and "promote" not in st_ref["items"], kw
+    # frames in flight
+    out_a = torch.zeros((40, 64, 3), device="cuda")
+    out_b = torch.zeros((40, 64, 3), device="cuda")
+    R.render_frames(4, out=out_a, mode="wave", **cfg)
+    R.render_frames(4, out=out_b, mode="wave", flags=T, **cfg)
+    torch.cuda.synchronize()
+    assert torch.equal(out_a, out_b)
