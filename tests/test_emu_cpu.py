@@ -344,3 +344,21 @@ def test_coat_without_attributes_matches_oracle():
     assert nexact >= 0.999 * img.shape[0]
     w, rw = E.wave(shuffle=6, tail=300, **cfg)
     assert np.array_equal(w.view(np.uint32), img.view(np.uint32))
+
+
+def test_degenerate_triangles_with_attributes():
+    # zero-area triangles and random (some zero, some flipped, some huge)
+    # vertex normals and texture coordinates with coated and textured
+    # materials: finite images equal to the oracle's
+    from tests._parity import degenerate_scene
+    scene, cam = degenerate_scene(False)
+    rng = np.random.default_rng(17)
+    nv = scene["positions"].shape[0]
+    nrm = rng.normal(size=(nv, 3)) * rng.choice([0.0, 1e-3, 1.0, 1e6], size=(nv, 1))
+    scene = dict(scene, normals=nrm.astype(np.float32), uvs=rng.uniform(-50, 50, (nv, 2)).astype(np.float32))
+    scene["materials"] = np.array([[0, 1.0, 1.5, 3.0], [scenes.COATED, 0.3, 1.4, 2.0]], np.float32)
+    scene["tri_mat"] = (np.arange(scene["indices"].shape[0]) % 2).astype(np.int32)
+    E, img, rays, nexact = _check(scene, cam, spp=4, max_depth=5, seed=2)
+    assert np.isfinite(img).all() and nexact >= 0.999 * img.shape[0]
+    w, _ = E.wave(shuffle=5, spp=4, max_depth=5, seed=2)
+    assert np.array_equal(w.view(np.uint32), img.view(np.uint32))
