@@ -214,6 +214,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-replay", default="mega,wave",
+                    help="comma-separated schedules of the adjoint's radiance replay: mega, wave (profiled runs take "
+                         "mega alone, so that the wavefront kernels' averages are the forward frame's)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the divergence and batched workload summaries and the compaction ablation")
     ap.add_argument("--schedules", default="wave_hybrid,wave_pure,mega",
@@ -615,10 +618,12 @@ def divergence_bench(args, torch, ptmi, scenes, frames=None, summary=False):
 
 def adjoint_bench(ptmi, scene, torch, args, prof, copy_gbs, roof):
     """Backward (path replay) of the 512x512, 8 spp, depth 6 frame: adjoint
-    samples/s, and the rooflines of its two kernels (replay A keeps each
-    path's radiance, replay B adds the gradients).  Both replays trace the
-    rays of the forward megakernel frame with the same arguments, so their
-    node visits and triangle tests are those of that frame."""
+    samples/s with replay A (each path's radiance) run two ways, as the
+    megakernel-style kernel and as the wavefront stages (the same per-path
+    radiance bit for bit), and the rooflines of the adjoint kernels (replay
+    B adds the gradients).  The replays trace the rays of the forward
+    megakernel frame with the same arguments, so their node visits and
+    triangle tests are those of that frame."""
     cam = dict(eye=(0.0, 50.0, -130.0), target=(0.0, 40.0, 0.0), up=(0.0, 1.0, 0.0), vfov_deg=50.0,
                width=512, height=512)
     try:
@@ -627,25 +632,38 @@ def adjoint_bench(ptmi, scene, torch, args, prof, copy_gbs, roof):
         d_img = torch.ones((512, 512, 3), dtype=torch.float32, device="cuda")
         ga = torch.zeros_like(R.albedo)
         ge = torch.zeros_like(R.emission)
-        R.backward(d_img, ga, ge, **kw)
-        torch.cuda.synchronize()
         k = max(4, args.steps // 8)
-        t = time.perf_counter()
-        for i in range(k):
-            R.backward(d_img, ga, ge, frame=i, **kw)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t
         n = 512 * 512 * 8 * k
-        log(f"adjoint: {dt * 1e3 / k:.3f} ms per backward, {n / dt / 1e6:.1f} M samples/s")
-        # per-kernel event times
-        ms = {"adjoint": 0.0, "adjoint_radiance": 0.0}
-        by = {"adjoint": 0.0, "adjoint_radiance": 0.0}
-        for i in range(k):
-            R.backward(d_img, ga, ge, frame=i, flags=ptmi.FLAG_PROFILE, **kw)
-            st = R.stats()
-            for s in ms:
-                ms[s] += st["stage_ms"][s]
-                by[s] += st["bytes"][s]
+        variants = {"replay_a_megakernel": dict(FIXED_PARAMS["mega"], mode="mega"),
+                    "replay_a_wavefront": dict(FIXED_PARAMS["wave"], mode="wave")}
+        pick = args.adjoint_replay.split(",")
+        variants = {n: p for n, p in variants.items() if p["mode"] in pick}
+        res = {}
+        wave_stages = ("raygen", "extend", "shade", "shadow", "tail")
+        for name, p in variants.items():
+            R.backward(d_img, ga, ge, **kw, **p)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for i in range(k):
+                R.backward(d_img, ga, ge, frame=i, **kw, **p)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            # per-kernel event times
+            ms = {"replay_a": 0.0, "adjoint": 0.0}
+            by = {"adjoint_radiance": 0.0, "adjoint": 0.0}
+            for i in range(k):
+                R.backward(d_img, ga, ge, frame=i, flags=ptmi.FLAG_PROFILE, **kw, **p)
+                st = R.stats()
+                ms["adjoint"] += st["stage_ms"]["adjoint"]
+                by["adjoint"] += st["bytes"]["adjoint"]
+                if p["mode"] == "mega":
+                    ms["replay_a"] += st["stage_ms"]["adjoint_radiance"]
+                    by["adjoint_radiance"] += st["bytes"]["adjoint_radiance"]
+                else:
+                    ms["replay_a"] += sum(st["stage_ms"].get(x, 0.0) for x in wave_stages)
+            res[name] = {"value": n / dt, "ms_per_backward": dt * 1e3 / k,
+                         "ms_per_kernel": {x: v / k for x, v in ms.items()}, "_ms": ms, "_by": by}
+            log(f"adjoint ({name}): {dt * 1e3 / k:.3f} ms per backward, {n / dt / 1e6:.1f} M samples/s")
         nodes = tris = 0
         img = torch.empty((512, 512, 3), dtype=torch.float32, device="cuda")
         for i in range(k):
@@ -653,12 +671,19 @@ def adjoint_bench(ptmi, scene, torch, args, prof, copy_gbs, roof):
             st = R.stats()
             nodes += st["node_visits"]["mega"]
             tris += st["tri_tests"]["mega"]
-        roof["adjoint_radiance"] = roofline_entry("ptmi::k_adjoint_radiance<8, false>", k, ms["adjoint_radiance"],
-                                                  by["adjoint_radiance"], nodes, tris, prof, copy_gbs)
-        roof["adjoint"] = roofline_entry("ptmi::k_adjoint<8, false>", k, ms["adjoint"], by["adjoint"], nodes, tris, prof,
-                                         copy_gbs)
-        return {"value": n / dt, "unit": "adjoint samples/s", "ms_per_backward": dt * 1e3 / k,
-                "ms_per_kernel": {s: v / k for s, v in ms.items()},
+        if "replay_a_megakernel" in res:
+            mg = res["replay_a_megakernel"]
+            roof["adjoint_radiance"] = roofline_entry("ptmi::k_adjoint_radiance<8, false>", k, mg["_ms"]["replay_a"],
+                                                      mg["_by"]["adjoint_radiance"], nodes, tris, prof, copy_gbs)
+        best = min(res, key=lambda x: res[x]["ms_per_backward"])
+        roof["adjoint"] = roofline_entry("ptmi::k_adjoint<8, false>", k, res[best]["_ms"]["adjoint"],
+                                         res[best]["_by"]["adjoint"], nodes, tris, prof, copy_gbs)
+        for r in res.values():
+            r.pop("_ms")
+            r.pop("_by")
+        return {"value": res[best]["value"], "unit": "adjoint samples/s",
+                "ms_per_backward": res[best]["ms_per_backward"], "best": best, "variants": res,
+                "ms_per_kernel": res[best]["ms_per_kernel"],
                 "config": "same scene, 512x512, 8 spp, max depth 6, roulette off"}
     except ptmi.PtError as e:
         log(f"adjoint unavailable: {e}")

@@ -343,9 +343,14 @@ pt_status pt_render_frames(pt_ctx* ctx, const pt_render_args* args, int32_t n_fr
  * by (seed, frame, spp, job).  Each path is replayed twice from its random
  * numbers: a first pass over all paths keeps only each path's radiance (16
  * bytes per path in the workspace), a second pass replays them again and
- * adds the gradients; no vertex is stored.  args->mode is ignored.
+ * adds the gradients; no vertex is stored.  args->mode selects how the
+ * first pass runs: PT_MODE_MEGA as one megakernel-style kernel, PT_MODE_WAVE
+ * as the wavefront stages with the frame's wavefront options (hybrid tail,
+ * sorts), whose per-path radiance is the same bit for bit; the second pass
+ * is one kernel either way.
  * workspace: at least pt_backward_workspace_size bytes (path cursors, the
- * per-path radiance, the traversal stack overflow area), 256-byte aligned.
+ * per-path radiance, the wavefront buffers in PT_MODE_WAVE, the traversal
+ * stack overflow area), 256-byte aligned.
  * PT_EINVAL if Russian roulette is on (its survival probability depends on
  * the albedo). */
 pt_status pt_backward_workspace_size(pt_ctx* ctx, const pt_render_args* args, uint64_t* bytes);

@@ -41,10 +41,12 @@ PT_DEV void adjoint_b_begin(const CamView& cam, const PathParams& pp, uint32_t p
 }
 
 // One vertex of replay B; returns false when the path is finished.  ATTR:
-// the scene may have vertex attributes (see shade_vertex).
+// the scene may have vertex attributes (see shade_vertex).  The extension
+// and shadow rays it traces are counted in n_ext, n_sh.
 template <int LDS, bool ATTR = false, class Acc, bool COUNT = false>
 PT_DEV bool adjoint_b_step(const SceneView& sc, const PathParams& pp, AdjRun& ar, float* __restrict__ g_alb,
-                           float* __restrict__ g_emi, TravStack<LDS, COUNT>& st, Acc& acc) {
+                           float* __restrict__ g_emi, TravStack<LDS, COUNT>& st, Acc& acc, uint32_t& n_ext,
+                           uint32_t& n_sh) {
     const f3 delta = ar.delta, Ltot = ar.Ltot;
     const uint32_t pix = ar.pix, sample = ar.sample;
     const int k = ar.pr.k;
@@ -52,6 +54,7 @@ PT_DEV bool adjoint_b_step(const SceneView& sc, const PathParams& pp, AdjRun& ar
     PathState& ps = ar.pr.ps;
     Ray ray = make_ray(o, d);
     Hit h = closest_hit<LDS>(sc, ray, INFINITY, st);
+    ++n_ext;
     const f3 beta = ps.beta;
     ShadowReq sh;
     VertexOut vo = shade_vertex<false, ATTR>(sc, pp, pix, sample, k, d, h, ps, sh);
@@ -67,6 +70,7 @@ PT_DEV bool adjoint_b_step(const SceneView& sc, const PathParams& pp, AdjRun& ar
     // terms summed here, one accumulation per channel
     float ga[3] = {0.0f, 0.0f, 0.0f};
     if (sh.valid) {
+        ++n_sh;
         Ray sr = make_ray(sh.o, sh.d);
         if (!any_hit<LDS>(sc, sr, kShadowTmax, st)) {
             ps.L = mk3(ps.L.x + sh.contrib.x, ps.L.y + sh.contrib.y, ps.L.z + sh.contrib.z);
@@ -118,7 +122,8 @@ PT_DEV void adjoint_path(const SceneView& sc, const CamView& cam, const PathPara
     const f3 Ltot = trace_path<LDS, COUNT, false, ATTR>(sc, cam, pp, pix, sample, st, ne, ns);
     AdjRun ar;
     adjoint_b_begin(cam, pp, pix, sample, delta, Ltot, ar);
-    while (adjoint_b_step<LDS, ATTR>(sc, pp, ar, g_alb, g_emi, st, acc)) {
+    uint32_t be = 0, bs = 0;
+    while (adjoint_b_step<LDS, ATTR>(sc, pp, ar, g_alb, g_emi, st, acc, be, bs)) {
     }
 }
 

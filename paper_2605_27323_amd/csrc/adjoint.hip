@@ -116,7 +116,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
                                                  const float* __restrict__ d_img, const float4* __restrict__ Lpath,
                                                  unsigned long long* __restrict__ cursor, float* __restrict__ g_alb,
                                                  float* __restrict__ g_emi, uint2* __restrict__ ovf, int gcap,
-                                                 uint32_t* __restrict__ stats) {
+                                                 uint32_t* __restrict__ stats, int count_rays) {
     extern __shared__ __align__(8) uint32_t smem[];
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -138,6 +138,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     bool drained = false;        // wave-uniform
     bool live = false;
     AdjRun ar;
+    uint32_t ne = 0, ns = 0;
     while (true) {
         const uint64_t idle = __ballot(!live);
         if (idle != 0ull && !drained) {
@@ -172,7 +173,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
             continue;
         }
         if (!live) continue;
-        if (!adjoint_b_step<LDS, ATTR>(sc, pp, ar, g_alb, g_emi, st, acc)) live = false;
+        if (!adjoint_b_step<LDS, ATTR>(sc, pp, ar, g_alb, g_emi, st, acc, ne, ns)) live = false;
+    }
+    // with count_rays (replay A ran as the wavefront, which keeps its own
+    // counters) the paths' rays are counted here, one atomic per wave
+    if (count_rays) {
+        for (int off = 32; off > 0; off >>= 1) {
+            ne += __shfl_xor(ne, off);
+            ns += __shfl_xor(ns, off);
+        }
+        if (lane_id() == 0 && (ne | ns)) {
+            atomicAdd(&stats[0], ne);
+            atomicAdd(&stats[1], ns);
+        }
     }
     // every thread of the block is here: add the block's sums
     __syncthreads();
@@ -210,16 +223,16 @@ hipError_t launch_adjoint_radiance(int lds, dim3 grid, dim3 block, hipStream_t s
 
 hipError_t launch_adjoint(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const CamView& cam,
                           const PathParams& pp, const float* d_img, const float4* Lpath, unsigned long long* cursor,
-                          float* g_alb, float* g_emi, uint2* ovf, int gcap, uint32_t* stats) {
+                          float* g_alb, float* g_emi, uint2* ovf, int gcap, uint32_t* stats, int count_rays) {
     size_t sm = trav_stack_lds_bytes(lds, (int)block.x);
 #define X(N)                                                                                                  \
     if (lds == N) {                                                                                           \
         if (sc.attr_flags)                                                                                    \
             hipLaunchKernelGGL((k_adjoint<N, true>), grid, block, sm, s, sc, cam, pp, d_img, Lpath, cursor, g_alb, \
-                               g_emi, ovf, gcap, stats);                                                      \
+                               g_emi, ovf, gcap, stats, count_rays);                                                      \
         else                                                                                                  \
             hipLaunchKernelGGL((k_adjoint<N, false>), grid, block, sm, s, sc, cam, pp, d_img, Lpath, cursor, g_alb, \
-                               g_emi, ovf, gcap, stats);                                                      \
+                               g_emi, ovf, gcap, stats, count_rays);                                                      \
         return hipGetLastError();                                                                             \
     }
     X(8) X(16) X(24) X(32)

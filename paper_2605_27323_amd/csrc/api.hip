@@ -90,6 +90,8 @@ struct pt_ctx {
     uint32_t last_tail = 0, last_sort_threshold = 0;
     int last_tail_bounce = 0;
     int64_t last_promotes = 0;  // promote launches of the last frame (PT_FLAG_TWO_SLOT)
+    bool last_replay_wave = false;  // the last backward ran replay A as the wavefront
+    uint32_t* last_ovf_a = nullptr;  // then: the wavefront stages' overflow flag
     uint64_t last_npix = 0;
     bool last_acc = false;
     bool last_valid = false;
@@ -153,10 +155,13 @@ WsLayout layout(const pt_ctx* c, const pt_render_args* a, const Launch& L, bool 
     off = align_up(off + sizeof(uint32_t) * kTravWords);
     w.ovf = off;
     off = align_up(off + sizeof(uint2) * (size_t)L.gcap * L.nlanes);
-    // the adjoint's two path cursors and per-path radiance
+    // the adjoint's two path cursors and replay B's counters (one aligned
+    // block), then the per-path radiance when replay A runs as the
+    // megakernel-style kernel (as the wavefront it is the wavefront's
+    // per-path radiance buffer)
+    const bool wave = a->mode == PT_MODE_WAVE;
     w.adj = off;
-    if (backward) off = align_up(off + kAlign + sizeof(float4) * npaths);
-    const bool wave = !backward && a->mode == PT_MODE_WAVE;
+    if (backward) off = align_up(off + kAlign + (wave ? 0 : sizeof(float4) * npaths));
     for (int i = 0; i < 11; ++i) {
         w.wave[i] = off;
         if (wave) off = align_up(off + sizeof(float4) * npaths);
@@ -856,19 +861,34 @@ pt_status pt_render_backward(pt_ctx* c, const pt_render_args* a, const float* d_
     PT_HIP(launch_init_counts(s, counts, w.ncounts, 0u), "init counters");
     PT_HIP(launch_init_counts(s, reinterpret_cast<uint32_t*>(trav), kTravWords, 0u), "init work counters");
     unsigned long long* cursor = reinterpret_cast<unsigned long long*>(base + w.adj);
-    float4* Lpath = reinterpret_cast<float4*>(base + w.adj + kAlign);
-    PT_HIP(launch_init_counts(s, reinterpret_cast<uint32_t*>(cursor), 4, 0u), "init path cursors");
-    PT_HIP(timed(c, prof, 9, s, [&] {
-               return launch_adjoint_radiance(L.lds, dim3(L.grid), dim3(L.block), s, c->view, c->cam, pp, Lpath, cursor,
-                                              ovf, L.gcap, counts);
-           }),
-           "adjoint replay A");
+    const float4* Lpath = nullptr;
+    if (a->mode == PT_MODE_WAVE) {
+        // replay A by the wavefront stages (bit-identical per-path radiance;
+        // the hybrid tail and the other wavefront options apply), which
+        // leave each path's radiance in their per-path buffer; replay B
+        // counts its rays in the block after the cursors
+        PT_HIP(launch_init_counts(s, reinterpret_cast<uint32_t*>(cursor), 8, 0u), "init path cursors");
+        st = enqueue_stages(c, a, L, w, base, s, nullptr, nullptr, prof, &Lpath);
+        if (st) return st;
+        counts = reinterpret_cast<uint32_t*>(base + w.adj) + 4;
+    } else {
+        float4* Lp = reinterpret_cast<float4*>(base + w.adj + kAlign);
+        PT_HIP(launch_init_counts(s, reinterpret_cast<uint32_t*>(cursor), 4, 0u), "init path cursors");
+        PT_HIP(timed(c, prof, 9, s, [&] {
+                   return launch_adjoint_radiance(L.lds, dim3(L.grid), dim3(L.block), s, c->view, c->cam, pp, Lp,
+                                                  cursor, ovf, L.gcap, counts);
+               }),
+               "adjoint replay A");
+        Lpath = Lp;
+    }
     PT_HIP(timed(c, prof, 7, s, [&] {
                return launch_adjoint(L.lds, dim3(L.grid), dim3(L.block), s, c->view, c->cam, pp, d_image, Lpath, cursor,
-                                     d_albedo, d_emission, ovf, L.gcap, counts);
+                                     d_albedo, d_emission, ovf, L.gcap, counts, a->mode == PT_MODE_WAVE ? 1 : 0);
            }),
            "adjoint replay B");
-    remember_frame(c, a, counts, w.ncounts, 2, false);
+    remember_frame(c, a, counts, a->mode == PT_MODE_WAVE ? 4 : w.ncounts, 2, false);
+    c->last_replay_wave = a->mode == PT_MODE_WAVE;
+    c->last_ovf_a = reinterpret_cast<uint32_t*>(base + w.counts) + (w.ncounts - 1);
     c->last_trav = trav;
     return PT_OK;
 }
@@ -907,11 +927,16 @@ pt_status pt_frame_stats_get(pt_ctx* c, pt_frame_stats* out) {
         // radiance in replay A (16 B) and reads it and its pixel's image
         // adjoint in replay B (16 + 12 B)
         out->stage_bytes[k] = c->last_kind == 0 ? (double)npix * img_bytes : 28.0 * (double)npaths;
-        if (c->last_kind == 2) {
+        if (c->last_kind == 2 && !c->last_replay_wave) {
             out->stage_items[9] = (int64_t)npaths;
             out->stage_bytes[9] = 16.0 * (double)npaths;
         }
         if (h[2]) return fail(PT_EOVERFLOW, "traversal stack overflow");
+        if (c->last_kind == 2 && c->last_replay_wave) {
+            uint32_t fa = 0;
+            PT_HIP(hipMemcpy(&fa, c->last_ovf_a, sizeof fa, hipMemcpyDeviceToHost), "read counters");
+            if (fa) return fail(PT_EOVERFLOW, "traversal stack overflow");
+        }
         return PT_OK;
     }
     const int D = c->last_D;

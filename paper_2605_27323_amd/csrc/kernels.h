@@ -96,7 +96,7 @@ hipError_t launch_adjoint_radiance(int lds, dim3 grid, dim3 block, hipStream_t s
                                    unsigned long long* cursor, uint2* ovf, int gcap, uint32_t* stats);
 hipError_t launch_adjoint(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const CamView& cam,
                           const PathParams& pp, const float* d_img, const float4* Lpath, unsigned long long* cursor,
-                          float* g_alb, float* g_emi, uint2* ovf, int gcap, uint32_t* stats);
+                          float* g_alb, float* g_emi, uint2* ovf, int gcap, uint32_t* stats, int count_rays);
 hipError_t launch_accumulate(dim3 grid, dim3 block, hipStream_t s, const CamView& cam, const PathParams& pp,
                              const float4* L, float* img, float* acc);
 // img = I, running average acc updated for frame `frame` (npix pixels)

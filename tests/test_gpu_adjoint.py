@@ -192,3 +192,31 @@ def test_adjoint_halton_sampler_vs_oracle():
     ga, ge = ga.cpu().numpy()[:R.nt], ge.cpu().numpy()[:R.nt]
     oa, oe, aa, ae = oracle.Scene(scene).backward(cam, d, sampler=1, **kw)
     _grad_check(ga, ge, oa, oe, aa, ae)
+
+
+@pytest.mark.parametrize("mode", ["mega", "wave"])
+def test_adjoint_replay_schedules_match_oracle(mode):
+    # replay A as the megakernel-style kernel or as the wavefront stages
+    # (with the hybrid tail): the same per-path radiance, so both gradients
+    # match the oracle's to the atomics' rounding
+    scene, cam = scenes.procedural(seed=62, n_objects=30, width=72, height=48)
+    log("adjoint replay", mode)
+    R = ptmi.Renderer(scene, cam)
+    rng = np.random.default_rng(4)
+    n = cam["width"] * cam["height"]
+    d = rng.normal(size=(n, 3)).astype(np.float32)
+    kw = dict(spp=3, max_depth=5, seed=9, frame=2)
+    extra = dict(tail_threshold=500, tail_bounce=3) if mode == "wave" else {}
+    ga = torch.zeros_like(R.albedo)
+    ge = torch.zeros_like(R.emission)
+    R.backward(torch.from_numpy(d).cuda(), ga, ge, mode=mode, **kw, **extra)
+    st = R.stats()
+    # replay B traces the forward frame's rays again: the counts are those
+    # of the forward megakernel with the same arguments
+    R.render(mode="mega", **kw)
+    fst = R.stats()
+    assert st["extension_rays"] == fst["extension_rays"] > 0
+    assert st["shadow_rays"] == fst["shadow_rays"] > 0
+    ga, ge = ga.cpu().numpy()[:R.nt], ge.cpu().numpy()[:R.nt]
+    oa, oe, aa, ae = oracle.Scene(scene).backward(cam, d, **kw)
+    _grad_check(ga, ge, oa, oe, aa, ae)
