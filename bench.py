@@ -47,6 +47,11 @@ FLOPS_PER_TRI = 40
 # rooflines and the committed rocprofv3 profiles use them (bench.py --fixed)
 FIXED_PARAMS = {"wave": {"block": 256, "grid_mult": 4, "stack_lds": 8, "tail_threshold": 1 << 18, "tail_bounce": 3},
                 "mega": {"block": 256, "grid_mult": 4, "stack_lds": 8, "mega_waves": 5}}
+# launch parameters of the backward (512x512, 8 spp, depth 6; measured on
+# MI355X): the radiance replay as one kernel, or as the wavefront stages with
+# the hybrid tail from bounce 4
+ADJOINT_PARAMS = {"mega": {"block": 256, "grid_mult": 8, "stack_lds": 8},
+                  "wave": {"block": 256, "grid_mult": 8, "stack_lds": 8, "tail_threshold": 1 << 18, "tail_bounce": 4}}
 # the pure wavefront: no hybrid tail, every bounce in separate stage launches
 PURE = {"tail_threshold": 0, "tail_bounce": 0, "tail_spread": False}
 # launch parameters of the divergence workload (4 spp, depth 16)
@@ -214,9 +219,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--adjoint-replay", default="mega,wave",
-                    help="comma-separated schedules of the adjoint's radiance replay: mega, wave (profiled runs take "
-                         "mega alone, so that the wavefront kernels' averages are the forward frame's)")
+    ap.add_argument("--adjoint-replay", default="mega,wave,keep",
+                    help="comma-separated schedules of the adjoint's radiance replay: mega, wave, keep (mega keeping "
+                         "the intersections for the gradient replay); profiled runs take mega alone, so that the "
+                         "wavefront kernels' averages are the forward frame's")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the divergence and batched workload summaries and the compaction ablation")
     ap.add_argument("--schedules", default="wave_hybrid,wave_pure,mega",
@@ -634,25 +640,30 @@ def adjoint_bench(ptmi, scene, torch, args, prof, copy_gbs, roof):
         ge = torch.zeros_like(R.emission)
         k = max(4, args.steps // 8)
         n = 512 * 512 * 8 * k
-        variants = {"replay_a_megakernel": dict(FIXED_PARAMS["mega"], mode="mega"),
-                    "replay_a_wavefront": dict(FIXED_PARAMS["wave"], mode="wave")}
+        variants = {"replay_a_megakernel": dict(ADJOINT_PARAMS["mega"], mode="mega"),
+                    "replay_a_wavefront": dict(ADJOINT_PARAMS["wave"], mode="wave"),
+                    "replay_a_megakernel_keep_hits": dict(ADJOINT_PARAMS["mega"], mode="mega",
+                                                          flags=ptmi.FLAG_KEEP_HITS)}
         pick = args.adjoint_replay.split(",")
-        variants = {n: p for n, p in variants.items() if p["mode"] in pick}
+        variants = {n: p for n, p in variants.items()
+                    if (n.endswith("keep_hits") and "keep" in pick) or (not n.endswith("keep_hits") and p["mode"] in pick)}
         res = {}
         wave_stages = ("raygen", "extend", "shade", "shadow", "tail")
         for name, p in variants.items():
-            R.backward(d_img, ga, ge, **kw, **p)
+            fl = p.get("flags", 0)
+            p = {x: v for x, v in p.items() if x != "flags"}
+            R.backward(d_img, ga, ge, flags=fl, **kw, **p)
             torch.cuda.synchronize()
             t = time.perf_counter()
             for i in range(k):
-                R.backward(d_img, ga, ge, frame=i, **kw, **p)
+                R.backward(d_img, ga, ge, frame=i, flags=fl, **kw, **p)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t
             # per-kernel event times
             ms = {"replay_a": 0.0, "adjoint": 0.0}
             by = {"adjoint_radiance": 0.0, "adjoint": 0.0}
             for i in range(k):
-                R.backward(d_img, ga, ge, frame=i, flags=ptmi.FLAG_PROFILE, **kw, **p)
+                R.backward(d_img, ga, ge, frame=i, flags=ptmi.FLAG_PROFILE | fl, **kw, **p)
                 st = R.stats()
                 ms["adjoint"] += st["stage_ms"]["adjoint"]
                 by["adjoint"] += st["bytes"]["adjoint"]
@@ -661,7 +672,8 @@ def adjoint_bench(ptmi, scene, torch, args, prof, copy_gbs, roof):
                     by["adjoint_radiance"] += st["bytes"]["adjoint_radiance"]
                 else:
                     ms["replay_a"] += sum(st["stage_ms"].get(x, 0.0) for x in wave_stages)
-            res[name] = {"value": n / dt, "ms_per_backward": dt * 1e3 / k,
+            res[name] = {"value": n / dt, "ms_per_backward": dt * 1e3 / k, "keep_hits": fl != 0,
+                         "launch_params": {x: v for x, v in p.items() if x != "mode"},
                          "ms_per_kernel": {x: v / k for x, v in ms.items()}, "_ms": ms, "_by": by}
             log(f"adjoint ({name}): {dt * 1e3 / k:.3f} ms per backward, {n / dt / 1e6:.1f} M samples/s")
         nodes = tris = 0
@@ -673,11 +685,16 @@ def adjoint_bench(ptmi, scene, torch, args, prof, copy_gbs, roof):
             tris += st["tri_tests"]["mega"]
         if "replay_a_megakernel" in res:
             mg = res["replay_a_megakernel"]
-            roof["adjoint_radiance"] = roofline_entry("ptmi::k_adjoint_radiance<8, false>", k, mg["_ms"]["replay_a"],
-                                                      mg["_by"]["adjoint_radiance"], nodes, tris, prof, copy_gbs)
+            roof["adjoint_radiance"] = roofline_entry("ptmi::k_adjoint_radiance<8, false, false>", k,
+                                                      mg["_ms"]["replay_a"], mg["_by"]["adjoint_radiance"], nodes, tris,
+                                                      prof, copy_gbs)
         best = min(res, key=lambda x: res[x]["ms_per_backward"])
-        roof["adjoint"] = roofline_entry("ptmi::k_adjoint<8, false>", k, res[best]["_ms"]["adjoint"],
-                                         res[best]["_by"]["adjoint"], nodes, tris, prof, copy_gbs)
+        # the gradient replay of the fastest variant; reading kept
+        # intersections it traces nothing (no traversal work)
+        kb = res[best]["keep_hits"]
+        roof["adjoint"] = roofline_entry(f"ptmi::k_adjoint<8, false, {'true' if kb else 'false'}>", k,
+                                         res[best]["_ms"]["adjoint"], res[best]["_by"]["adjoint"],
+                                         None if kb else nodes, None if kb else tris, prof, copy_gbs)
         for r in res.values():
             r.pop("_ms")
             r.pop("_by")

@@ -75,10 +75,14 @@ enum {
     PT_FLAG_XCD_LOCAL = 32,    /* each of the eight XCDs (own L2 each) takes one contiguous part of the
                                   extend / shadow queues, and the megakernel's waves on an XCD take their
                                   pixels from one band of rows first; same image bit for bit */
-    PT_FLAG_TWO_SLOT = 64      /* wavefront, ablation of paper Sec. 3.1: the live path count in a
+    PT_FLAG_TWO_SLOT = 64,     /* wavefront, ablation of paper Sec. 3.1: the live path count in a
                                   two-slot buffer (current, next) that a one-thread promote kernel
                                   moves over after every bounce, in place of one counter per bounce;
                                   same image bit for bit */
+    PT_FLAG_KEEP_HITS = 128    /* backward, PT_MODE_MEGA: the first replay keeps every path vertex's
+                                  intersection and light-sample visibility (9 bytes per vertex and
+                                  path sample in the workspace) and the second reads them instead of
+                                  tracing the same rays again; same gradients */
 };
 
 typedef struct pt_ctx pt_ctx;

@@ -21,6 +21,47 @@
 
 namespace ptmi {
 
+// Intersections kept by replay A (optional): for vertex k (1-based) of path
+// p, at [(k - 1) * npaths + p], the hit of the ray that reached it (t, the
+// triangle's leaf-order index, ~0u for a miss) and whether its light
+// sample was traced and unoccluded (1) or not (0).  Replay B then reads
+// them instead of tracing the same rays again: the intersection is a pure
+// function of the ray and the scene, so the replay is the same.
+struct VertexRecs {
+    uint2* __restrict__ hit;
+    uint8_t* __restrict__ vis;
+    uint32_t npaths;
+};
+
+// One vertex of replay A that keeps its records: path_vertex of the
+// megakernel plus the two stores (the same radiance bit for bit).
+template <int LDS, bool ATTR = false, bool COUNT = false>
+PT_DEV bool adjoint_a_vertex(const SceneView& sc, const PathParams& pp, uint32_t pix, uint32_t sample, uint32_t path,
+                             PathRun& pr, TravStack<LDS, COUNT>& st, uint32_t& n_ext, uint32_t& n_sh,
+                             const VertexRecs& rec) {
+    Hit h = closest_hit<LDS>(sc, make_ray(pr.o, pr.d), INFINITY, st);
+    ++n_ext;
+    const size_t at = (size_t)(pr.k - 1) * rec.npaths + path;
+    rec.hit[at] = make_uint2(f2u(h.t), h.tri);
+    ShadowReq sh;
+    VertexOut vo = shade_vertex<false, ATTR>(sc, pp, pix, sample, pr.k, pr.d, h, pr.ps, sh);
+    add_radiance(pr.ps, vo);
+    uint8_t seen = 0;
+    if (sh.valid) {
+        ++n_sh;
+        if (!any_hit<LDS>(sc, make_ray(sh.o, sh.d), kShadowTmax, st)) {
+            pr.ps.L = mk3(pr.ps.L.x + sh.contrib.x, pr.ps.L.y + sh.contrib.y, pr.ps.L.z + sh.contrib.z);
+            seen = 1;
+        }
+    }
+    rec.vis[at] = seen;
+    if (!vo.cont) return false;
+    pr.o = vo.o;
+    pr.d = vo.d;
+    ++pr.k;
+    return true;
+}
+
 // Replay B of one path as resumable steps, one path vertex per step, from
 // the path's radiance Ltot (replay A), so that a kernel can hand a lane
 // whose path has ended the next path while the others go on.
@@ -29,32 +70,47 @@ struct AdjRun {
     f3 Ltot;     // radiance of the whole path
     f3 delta;    // dLoss/dI(pixel) / spp
     uint32_t pix, sample;
+    uint32_t path;  // index of the path sample (its records with STORED)
 };
 
 PT_DEV void adjoint_b_begin(const CamView& cam, const PathParams& pp, uint32_t pix, uint32_t sample, f3 delta,
-                            f3 Ltot, AdjRun& ar) {
+                            f3 Ltot, AdjRun& ar, uint32_t path = 0) {
     path_begin(cam, pp, pix, sample, ar.pr);
     ar.Ltot = Ltot;
     ar.delta = delta;
     ar.pix = pix;
     ar.sample = sample;
+    ar.path = path;
 }
 
 // One vertex of replay B; returns false when the path is finished.  ATTR:
 // the scene may have vertex attributes (see shade_vertex).  The extension
-// and shadow rays it traces are counted in n_ext, n_sh.
-template <int LDS, bool ATTR = false, class Acc, bool COUNT = false>
+// and shadow rays it traces are counted in n_ext, n_sh.  STORED: the
+// vertex's intersection and light-sample visibility come from replay A's
+// records (rec) and no ray is traced.
+template <int LDS, bool ATTR = false, class Acc, bool COUNT = false, bool STORED = false>
 PT_DEV bool adjoint_b_step(const SceneView& sc, const PathParams& pp, AdjRun& ar, float* __restrict__ g_alb,
                            float* __restrict__ g_emi, TravStack<LDS, COUNT>& st, Acc& acc, uint32_t& n_ext,
-                           uint32_t& n_sh) {
+                           uint32_t& n_sh, const VertexRecs& rec = VertexRecs{nullptr, nullptr, 0u}) {
     const f3 delta = ar.delta, Ltot = ar.Ltot;
     const uint32_t pix = ar.pix, sample = ar.sample;
     const int k = ar.pr.k;
     const f3 o = ar.pr.o, d = ar.pr.d;
     PathState& ps = ar.pr.ps;
-    Ray ray = make_ray(o, d);
-    Hit h = closest_hit<LDS>(sc, ray, INFINITY, st);
-    ++n_ext;
+    size_t at = 0;
+    Hit h;
+    if constexpr (STORED) {
+        at = (size_t)(k - 1) * rec.npaths + ar.path;
+        const uint2 r = rec.hit[at];
+        h.t = u2f(r.x);
+        h.tri = r.y;
+        h.id = 0;
+        hit_barycentrics(sc, o, d, h);
+    } else {
+        Ray ray = make_ray(o, d);
+        h = closest_hit<LDS>(sc, ray, INFINITY, st);
+        ++n_ext;
+    }
     const f3 beta = ps.beta;
     ShadowReq sh;
     VertexOut vo = shade_vertex<false, ATTR>(sc, pp, pix, sample, k, d, h, ps, sh);
@@ -70,9 +126,14 @@ PT_DEV bool adjoint_b_step(const SceneView& sc, const PathParams& pp, AdjRun& ar
     // terms summed here, one accumulation per channel
     float ga[3] = {0.0f, 0.0f, 0.0f};
     if (sh.valid) {
-        ++n_sh;
-        Ray sr = make_ray(sh.o, sh.d);
-        if (!any_hit<LDS>(sc, sr, kShadowTmax, st)) {
+        bool seen;
+        if constexpr (STORED) {
+            seen = rec.vis[at] != 0;
+        } else {
+            ++n_sh;
+            seen = !any_hit<LDS>(sc, make_ray(sh.o, sh.d), kShadowTmax, st);
+        }
+        if (seen) {
             ps.L = mk3(ps.L.x + sh.contrib.x, ps.L.y + sh.contrib.y, ps.L.z + sh.contrib.z);
             const f3 rho = load3(sc.albedo, id);
             const f3 Le = load3(sc.emission, sh.light_id);
@@ -113,14 +174,26 @@ PT_DEV bool adjoint_b_step(const SceneView& sc, const PathParams& pp, AdjRun& ar
     return true;
 }
 
-// The whole path: replay A, then replay B vertex by vertex.
+// The whole path: replay A, then replay B vertex by vertex.  With rec
+// (records of path `path`), replay A keeps its intersections there and
+// replay B reads them.
 template <int LDS, bool ATTR = false, class Acc, bool COUNT = false>
 PT_DEV void adjoint_path(const SceneView& sc, const CamView& cam, const PathParams& pp, uint32_t pix, uint32_t sample,
                          f3 delta, float* __restrict__ g_alb, float* __restrict__ g_emi, TravStack<LDS, COUNT>& st,
-                         Acc& acc) {
+                         Acc& acc, const VertexRecs* rec = nullptr, uint32_t path = 0) {
     uint32_t ne = 0, ns = 0;
-    const f3 Ltot = trace_path<LDS, COUNT, false, ATTR>(sc, cam, pp, pix, sample, st, ne, ns);
     AdjRun ar;
+    if (rec) {
+        PathRun pr;
+        path_begin(cam, pp, pix, sample, pr);
+        while (adjoint_a_vertex<LDS, ATTR>(sc, pp, pix, sample, path, pr, st, ne, ns, *rec)) {
+        }
+        adjoint_b_begin(cam, pp, pix, sample, delta, pr.ps.L, ar, path);
+        while (adjoint_b_step<LDS, ATTR, Acc, COUNT, true>(sc, pp, ar, g_alb, g_emi, st, acc, ne, ns, *rec)) {
+        }
+        return;
+    }
+    const f3 Ltot = trace_path<LDS, COUNT, false, ATTR>(sc, cam, pp, pix, sample, st, ne, ns);
     adjoint_b_begin(cam, pp, pix, sample, delta, Ltot, ar);
     uint32_t be = 0, bs = 0;
     while (adjoint_b_step<LDS, ATTR>(sc, pp, ar, g_alb, g_emi, st, acc, be, bs)) {

@@ -43,11 +43,12 @@ struct AtomicAcc {
 // Replay A of every path: its radiance, into Lpath[path].  One loop trip =
 // one path vertex; a lane whose path is done takes the next path of its
 // wave's chunk, a wave whose chunk is used up takes the next 64 paths from
-// cursor[0].  Five waves per SIMD, as the megakernel.
-template <int LDS, bool ATTR>
+// cursor[0].  Five waves per SIMD, as the megakernel.  STORE: every
+// vertex's intersection and light-sample visibility go to rec as well.
+template <int LDS, bool ATTR, bool STORE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k_adjoint_radiance(
     SceneView sc, CamView cam, PathParams pp, float4* __restrict__ Lpath, unsigned long long* __restrict__ cursor,
-    uint2* __restrict__ ovf, int gcap, uint32_t* __restrict__ stats) {
+    uint2* __restrict__ ovf, int gcap, uint32_t* __restrict__ stats, VertexRecs rec) {
     extern __shared__ __align__(8) uint32_t smem[];
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -92,7 +93,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k
             continue;
         }
         if (!live) continue;
-        if (path_vertex<LDS, false, false, ATTR>(sc, pp, pix, sample, pr, st, ne, ns)) continue;
+        if constexpr (STORE) {
+            if (adjoint_a_vertex<LDS, ATTR>(sc, pp, pix, sample, path, pr, st, ne, ns, rec)) continue;
+        } else {
+            if (path_vertex<LDS, false, false, ATTR>(sc, pp, pix, sample, pr, st, ne, ns)) continue;
+        }
         Lpath[path] = make_float4(pr.ps.L.x, pr.ps.L.y, pr.ps.L.z, 0.f);
         live = false;
     }
@@ -110,13 +115,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k
 }
 
 // Replay B of every path, one vertex per loop trip with the same hand-out
-// of paths (cursor[1]), from the radiance replay A left in Lpath.
-template <int LDS, bool ATTR>
+// of paths (cursor[1]), from the radiance replay A left in Lpath.  STORED:
+// from replay A's records too, tracing no ray.
+template <int LDS, bool ATTR, bool STORED>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_adjoint(SceneView sc, CamView cam, PathParams pp,
                                                  const float* __restrict__ d_img, const float4* __restrict__ Lpath,
                                                  unsigned long long* __restrict__ cursor, float* __restrict__ g_alb,
                                                  float* __restrict__ g_emi, uint2* __restrict__ ovf, int gcap,
-                                                 uint32_t* __restrict__ stats, int count_rays) {
+                                                 uint32_t* __restrict__ stats, int count_rays, VertexRecs rec) {
     extern __shared__ __align__(8) uint32_t smem[];
     const uint32_t nlanes = gridDim.x * blockDim.x;
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -161,7 +167,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
                         const uint32_t s = p - pix * (uint32_t)pp.spp;
                         const f3 delta = mk3(d_img[3 * (size_t)pix] / fs, d_img[3 * (size_t)pix + 1] / fs,
                                              d_img[3 * (size_t)pix + 2] / fs);
-                        adjoint_b_begin(cam, pp, pix, pp.frame * (uint32_t)pp.spp + s, delta, xyz(Lpath[p]), ar);
+                        adjoint_b_begin(cam, pp, pix, pp.frame * (uint32_t)pp.spp + s, delta, xyz(Lpath[p]), ar, p);
                         live = true;
                     }
                 }
@@ -173,7 +179,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
             continue;
         }
         if (!live) continue;
-        if (!adjoint_b_step<LDS, ATTR>(sc, pp, ar, g_alb, g_emi, st, acc, ne, ns)) live = false;
+        if (!adjoint_b_step<LDS, ATTR, AtomicAcc, false, STORED>(sc, pp, ar, g_alb, g_emi, st, acc, ne, ns, rec))
+            live = false;
     }
     // with count_rays (replay A ran as the wavefront, which keeps its own
     // counters) the paths' rays are counted here, one atomic per wave
@@ -204,39 +211,51 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 
 hipError_t launch_adjoint_radiance(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
                                    const CamView& cam, const PathParams& pp, float4* Lpath,
-                                   unsigned long long* cursor, uint2* ovf, int gcap, uint32_t* stats) {
+                                   unsigned long long* cursor, uint2* ovf, int gcap, uint32_t* stats,
+                                   const VertexRecs& rec) {
     size_t sm = trav_stack_lds_bytes(lds, (int)block.x);
-#define X(N)                                                                                                  \
-    if (lds == N) {                                                                                           \
-        if (sc.attr_flags)                                                                                    \
-            hipLaunchKernelGGL((k_adjoint_radiance<N, true>), grid, block, sm, s, sc, cam, pp, Lpath, cursor, ovf, \
-                               gcap, stats);                                                                  \
-        else                                                                                                  \
-            hipLaunchKernelGGL((k_adjoint_radiance<N, false>), grid, block, sm, s, sc, cam, pp, Lpath, cursor, ovf, \
-                               gcap, stats);                                                                  \
-        return hipGetLastError();                                                                             \
+#define K(N, A, S) \
+    hipLaunchKernelGGL((k_adjoint_radiance<N, A, S>), grid, block, sm, s, sc, cam, pp, Lpath, cursor, ovf, gcap, stats, rec)
+#define X(N)                                                  \
+    if (lds == N) {                                           \
+        if (rec.hit) {                                        \
+            if (sc.attr_flags) K(N, true, true);              \
+            else K(N, false, true);                           \
+        } else {                                              \
+            if (sc.attr_flags) K(N, true, false);             \
+            else K(N, false, false);                          \
+        }                                                     \
+        return hipGetLastError();                             \
     }
     X(8) X(16) X(24) X(32)
 #undef X
+#undef K
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_adjoint(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const CamView& cam,
                           const PathParams& pp, const float* d_img, const float4* Lpath, unsigned long long* cursor,
-                          float* g_alb, float* g_emi, uint2* ovf, int gcap, uint32_t* stats, int count_rays) {
-    size_t sm = trav_stack_lds_bytes(lds, (int)block.x);
-#define X(N)                                                                                                  \
-    if (lds == N) {                                                                                           \
-        if (sc.attr_flags)                                                                                    \
-            hipLaunchKernelGGL((k_adjoint<N, true>), grid, block, sm, s, sc, cam, pp, d_img, Lpath, cursor, g_alb, \
-                               g_emi, ovf, gcap, stats, count_rays);                                                      \
-        else                                                                                                  \
-            hipLaunchKernelGGL((k_adjoint<N, false>), grid, block, sm, s, sc, cam, pp, d_img, Lpath, cursor, g_alb, \
-                               g_emi, ovf, gcap, stats, count_rays);                                                      \
-        return hipGetLastError();                                                                             \
+                          float* g_alb, float* g_emi, uint2* ovf, int gcap, uint32_t* stats, int count_rays,
+                          const VertexRecs& rec) {
+    // with the records replay B traces nothing: no traversal stack in LDS
+    const size_t sm = rec.hit ? 0 : trav_stack_lds_bytes(lds, (int)block.x);
+#define K(N, A, S)                                                                                               \
+    hipLaunchKernelGGL((k_adjoint<N, A, S>), grid, block, sm, s, sc, cam, pp, d_img, Lpath, cursor, g_alb, g_emi, \
+                       ovf, gcap, stats, count_rays, rec)
+    if (rec.hit) {
+        if (sc.attr_flags) K(8, true, true);
+        else K(8, false, true);
+        return hipGetLastError();
+    }
+#define X(N)                                      \
+    if (lds == N) {                               \
+        if (sc.attr_flags) K(N, true, false);     \
+        else K(N, false, false);                  \
+        return hipGetLastError();                 \
     }
     X(8) X(16) X(24) X(32)
 #undef X
+#undef K
     return hipErrorInvalidValue;
 }
 

@@ -92,6 +92,7 @@ struct pt_ctx {
     int64_t last_promotes = 0;  // promote launches of the last frame (PT_FLAG_TWO_SLOT)
     bool last_replay_wave = false;  // the last backward ran replay A as the wavefront
     uint32_t* last_ovf_a = nullptr;  // then: the wavefront stages' overflow flag
+    bool last_keep_hits = false;     // the last backward kept replay A's intersections
     uint64_t last_npix = 0;
     bool last_acc = false;
     bool last_valid = false;
@@ -133,7 +134,7 @@ pt_status launch_config(const pt_ctx* c, const pt_render_args* a, Launch& L) {
 }
 
 struct WsLayout {
-    size_t counts, trav, ovf, adj, wave[11], sort_key, perm, hist, total;
+    size_t counts, trav, ovf, adj, rec_hit, rec_vis, wave[11], sort_key, perm, hist, total;
     int ncounts;
 };
 constexpr int kTravWords = 16;  // 8 u64 traversal work counters
@@ -162,6 +163,13 @@ WsLayout layout(const pt_ctx* c, const pt_render_args* a, const Launch& L, bool 
     const bool wave = a->mode == PT_MODE_WAVE;
     w.adj = off;
     if (backward) off = align_up(off + kAlign + (wave ? 0 : sizeof(float4) * npaths));
+    // PT_FLAG_KEEP_HITS: replay A's records, max_depth + 1 vertices per path
+    const bool keep = backward && (a->flags & PT_FLAG_KEEP_HITS) != 0;
+    const size_t nrec = npaths * ((size_t)std::max(a->max_depth, 0) + 1);
+    w.rec_hit = off;
+    if (keep) off = align_up(off + sizeof(uint2) * nrec);
+    w.rec_vis = off;
+    if (keep) off = align_up(off + nrec);
     for (int i = 0; i < 11; ++i) {
         w.wave[i] = off;
         if (wave) off = align_up(off + sizeof(float4) * npaths);
@@ -183,7 +191,7 @@ pt_status check_args(const pt_ctx* c, const pt_render_args* a) {
     if (!c->bound) return fail(PT_ESTATE, "scene not bound (pt_bind_scene)");
     if (!c->cam_set) return fail(PT_ESTATE, "camera not set (pt_set_camera)");
     if (a->flags & ~(PT_FLAG_PROFILE | PT_FLAG_NO_COMPACT | PT_FLAG_SORT_MATERIAL | PT_FLAG_COUNT_WORK | PT_FLAG_SORT_RAYS |
-                     PT_FLAG_XCD_LOCAL | PT_FLAG_TWO_SLOT))
+                     PT_FLAG_XCD_LOCAL | PT_FLAG_TWO_SLOT | PT_FLAG_KEEP_HITS))
         return fail(PT_EINVAL, "unknown flag");
     if (a->spp < 1 || a->spp > 65536) return fail(PT_EINVAL, "spp must be in [1, 65536]");
     if (a->max_depth < 0 || a->max_depth > 1000) return fail(PT_EINVAL, "max_depth must be in [0, 1000]");
@@ -843,6 +851,9 @@ pt_status pt_render_backward(pt_ctx* c, const pt_render_args* a, const float* d_
     if (!d_image || !d_albedo || !d_emission) return fail(PT_EINVAL, "null gradient buffer");
     if (!ws) return fail(PT_EINVAL, "null workspace");
     if ((reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return fail(PT_EINVAL, "workspace must be 256-byte aligned");
+    const bool keep = (a->flags & PT_FLAG_KEEP_HITS) != 0;
+    if (keep && a->mode != PT_MODE_MEGA)
+        return fail(PT_EUNSUPPORTED, "PT_FLAG_KEEP_HITS needs the megakernel-style first replay (PT_MODE_MEGA)");
     Launch L;
     st = launch_config(c, a, L);
     if (st) return st;
@@ -862,6 +873,9 @@ pt_status pt_render_backward(pt_ctx* c, const pt_render_args* a, const float* d_
     PT_HIP(launch_init_counts(s, reinterpret_cast<uint32_t*>(trav), kTravWords, 0u), "init work counters");
     unsigned long long* cursor = reinterpret_cast<unsigned long long*>(base + w.adj);
     const float4* Lpath = nullptr;
+    const VertexRecs rec{keep ? reinterpret_cast<uint2*>(base + w.rec_hit) : nullptr,
+                         keep ? reinterpret_cast<uint8_t*>(base + w.rec_vis) : nullptr,
+                         (uint32_t)((size_t)c->cam.W * c->cam.H * a->spp)};
     if (a->mode == PT_MODE_WAVE) {
         // replay A by the wavefront stages (bit-identical per-path radiance;
         // the hybrid tail and the other wavefront options apply), which
@@ -876,18 +890,19 @@ pt_status pt_render_backward(pt_ctx* c, const pt_render_args* a, const float* d_
         PT_HIP(launch_init_counts(s, reinterpret_cast<uint32_t*>(cursor), 4, 0u), "init path cursors");
         PT_HIP(timed(c, prof, 9, s, [&] {
                    return launch_adjoint_radiance(L.lds, dim3(L.grid), dim3(L.block), s, c->view, c->cam, pp, Lp,
-                                                  cursor, ovf, L.gcap, counts);
+                                                  cursor, ovf, L.gcap, counts, rec);
                }),
                "adjoint replay A");
         Lpath = Lp;
     }
     PT_HIP(timed(c, prof, 7, s, [&] {
                return launch_adjoint(L.lds, dim3(L.grid), dim3(L.block), s, c->view, c->cam, pp, d_image, Lpath, cursor,
-                                     d_albedo, d_emission, ovf, L.gcap, counts, a->mode == PT_MODE_WAVE ? 1 : 0);
+                                     d_albedo, d_emission, ovf, L.gcap, counts, a->mode == PT_MODE_WAVE ? 1 : 0, rec);
            }),
            "adjoint replay B");
     remember_frame(c, a, counts, a->mode == PT_MODE_WAVE ? 4 : w.ncounts, 2, false);
     c->last_replay_wave = a->mode == PT_MODE_WAVE;
+    c->last_keep_hits = keep;
     c->last_ovf_a = reinterpret_cast<uint32_t*>(base + w.counts) + (w.ncounts - 1);
     c->last_trav = trav;
     return PT_OK;
@@ -930,6 +945,12 @@ pt_status pt_frame_stats_get(pt_ctx* c, pt_frame_stats* out) {
         if (c->last_kind == 2 && !c->last_replay_wave) {
             out->stage_items[9] = (int64_t)npaths;
             out->stage_bytes[9] = 16.0 * (double)npaths;
+        }
+        if (c->last_kind == 2 && c->last_keep_hits) {
+            // the records: 9 bytes per path vertex (one per extension ray),
+            // written by replay A and read by replay B
+            out->stage_bytes[7] += 9.0 * (double)h[0];
+            out->stage_bytes[9] += 9.0 * (double)h[0];
         }
         if (h[2]) return fail(PT_EOVERFLOW, "traversal stack overflow");
         if (c->last_kind == 2 && c->last_replay_wave) {

@@ -2,6 +2,7 @@
 #pragma once
 #include "../../include/ptmi.h"
 #include "device.h"
+#include "adjoint.h"
 
 namespace ptmi {
 
@@ -90,13 +91,17 @@ hipError_t launch_sort(dim3 grid, dim3 block, hipStream_t s, const SceneView& sc
 hipError_t launch_shadow(int lds, bool count, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
                          const WaveBufs& wb, int b, uint2* ovf, int gcap, int xcd_local);
 // the adjoint: replay A of every path into Lpath (one float4 per path;
-// cursor[0], zero on entry), then replay B (cursor[1], zero on entry)
+// cursor[0], zero on entry), then replay B (cursor[1], zero on entry);
+// with rec.hit set replay A keeps every vertex's intersection and
+// light-sample visibility there and replay B reads them (no tracing)
 hipError_t launch_adjoint_radiance(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc,
                                    const CamView& cam, const PathParams& pp, float4* Lpath,
-                                   unsigned long long* cursor, uint2* ovf, int gcap, uint32_t* stats);
+                                   unsigned long long* cursor, uint2* ovf, int gcap, uint32_t* stats,
+                                   const VertexRecs& rec);
 hipError_t launch_adjoint(int lds, dim3 grid, dim3 block, hipStream_t s, const SceneView& sc, const CamView& cam,
                           const PathParams& pp, const float* d_img, const float4* Lpath, unsigned long long* cursor,
-                          float* g_alb, float* g_emi, uint2* ovf, int gcap, uint32_t* stats, int count_rays);
+                          float* g_alb, float* g_emi, uint2* ovf, int gcap, uint32_t* stats, int count_rays,
+                          const VertexRecs& rec);
 hipError_t launch_accumulate(dim3 grid, dim3 block, hipStream_t s, const CamView& cam, const PathParams& pp,
                              const float4* L, float* img, float* acc);
 // img = I, running average acc updated for frame `frame` (npix pixels)

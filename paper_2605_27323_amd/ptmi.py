@@ -20,6 +20,7 @@ MODE_MEGA, MODE_WAVE = 0, 1
 FLAG_PROFILE, FLAG_NO_COMPACT, FLAG_SORT_MATERIAL, FLAG_COUNT_WORK, FLAG_SORT_RAYS = 1, 2, 4, 8, 16
 FLAG_XCD_LOCAL = 32
 FLAG_TWO_SLOT = 64
+FLAG_KEEP_HITS = 128
 SAMPLER_PHILOX, SAMPLER_HALTON = 0, 1
 STAGES = ["raygen", "extend", "shade", "shadow", "accumulate", "mega", "sort", "adjoint", "tail",
           "adjoint_radiance", "promote"]

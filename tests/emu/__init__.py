@@ -62,7 +62,7 @@ def lib():
         L.emu_render_batch.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_uint32, C.c_uint64, C.c_void_p]
         L.emu_backward.restype = C.c_int32
         L.emu_backward.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int32,
-                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32]
         for name, (res, args) in ptmi.SIGNATURES.items():
             f = getattr(L, name)
             f.restype = res
@@ -145,13 +145,13 @@ class Emu:
         assert rc == 0
         return img, rays
 
-    def backward(self, d_image, spp=1, max_depth=5, seed=0, frame=0, job=0, nee=True, sampler=0):
+    def backward(self, d_image, spp=1, max_depth=5, seed=0, frame=0, job=0, nee=True, sampler=0, keep_hits=False):
         d_image = np.ascontiguousarray(d_image, np.float32).reshape(-1, 3)
         nt = self._keep["indices"].shape[0]
         ga = np.zeros((max(nt, 1), 3), np.float32)
         ge = np.zeros((max(nt, 1), 3), np.float32)
         rc = lib().emu_backward(self.h, spp, max_depth, seed, frame, job, int(bool(nee)), d_image.ctypes.data,
-                                ga.ctypes.data, ge.ctypes.data, int(sampler))
+                                ga.ctypes.data, ge.ctypes.data, int(sampler), int(bool(keep_hits)))
         assert rc == 0
         return ga[:nt], ge[:nt]
 

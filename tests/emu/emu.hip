@@ -244,9 +244,11 @@ int32_t emu_render_wave(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32
 }
 
 // Path-replay adjoint over the whole image (sequential binary32 adds):
-// g_alb, g_emi (nt*3) are accumulated into.
+// g_alb, g_emi (nt*3) are accumulated into.  keep_hits: replay A keeps
+// every vertex's intersection and light-sample visibility and replay B
+// reads them (the records of all paths, laid out as the GPU's).
 int32_t emu_backward(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32_t frame, uint32_t job, int32_t nee,
-                     const float* d_img, float* g_alb, float* g_emi, int32_t sampler) {
+                     const float* d_img, float* g_alb, float* g_emi, int32_t sampler, int32_t keep_hits) {
     struct HostAcc {
         void add(float* p, float v) {
             if (v != 0.0f) *p += v;
@@ -259,13 +261,20 @@ int32_t emu_backward(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32_t 
     HostStack hs(std::max(0, c->bvh.stack_entries - kL));
     const uint32_t npaths = (uint32_t)c->cam.W * c->cam.H * (uint32_t)spp;
     const float fs = (float)spp;
+    const size_t nrec = keep_hits ? (size_t)npaths * ((size_t)std::max(D, 0) + 1) : 0;
+    // records filled with a pattern, so that a read of a slot replay A did
+    // not write would show
+    std::vector<uint2> hits(nrec, make_uint2(0x7FC00001u, 0xFFFFFFFEu));
+    std::vector<uint8_t> vis(nrec, 0x5Au);
+    const VertexRecs rec{hits.data(), vis.data(), npaths};
     for (uint32_t p = 0; p < npaths; ++p) {
         const uint32_t pix = p / (uint32_t)spp, s = p - pix * (uint32_t)spp;
         f3 delta = mk3(d_img[3 * (size_t)pix] / fs, d_img[3 * (size_t)pix + 1] / fs, d_img[3 * (size_t)pix + 2] / fs);
+        const VertexRecs* r = keep_hits ? &rec : nullptr;
         if (has_attrs(c))
-            adjoint_path<kL, true>(sc, c->cam, pp, pix, frame * (uint32_t)spp + s, delta, g_alb, g_emi, hs.st, acc);
+            adjoint_path<kL, true>(sc, c->cam, pp, pix, frame * (uint32_t)spp + s, delta, g_alb, g_emi, hs.st, acc, r, p);
         else
-            adjoint_path<kL, false>(sc, c->cam, pp, pix, frame * (uint32_t)spp + s, delta, g_alb, g_emi, hs.st, acc);
+            adjoint_path<kL, false>(sc, c->cam, pp, pix, frame * (uint32_t)spp + s, delta, g_alb, g_emi, hs.st, acc, r, p);
     }
     return hs.st.overflow ? 1 : 0;
 }

@@ -320,6 +320,31 @@ def test_adjoint_with_attributes_matches_oracle():
     assert np.abs(oa[scene["tri_mat"] == 1]).sum() > 0 and np.abs(oa[:2]).sum() > 0
 
 
+@pytest.mark.parametrize("which", ["cornell_attributes", "procedural", "depth0"])
+def test_adjoint_keep_hits_bit_identical(which):
+    # replay B from replay A's kept intersections and visibilities (no
+    # tracing) adds the same terms in the same order: the gradients equal
+    # those of the tracing replay bit for bit, and the oracle's
+    kw = dict(spp=2, max_depth=4, seed=3, frame=1)
+    if which == "cornell_attributes":
+        scene, cam = scenes.cornell_attributes(coat=(0.3, 1.5))
+        cam = dict(cam, width=20, height=16)
+    else:
+        scene, cam = scenes.procedural(seed=71, n_objects=25, width=24, height=16)
+        if which == "depth0":
+            kw["max_depth"] = 0
+    E = emu.Emu(scene, cam)
+    d = np.random.default_rng(5).normal(size=(cam["width"] * cam["height"], 3)).astype(np.float32)
+    ga, ge = E.backward(d, **kw)
+    ka, ke = E.backward(d, keep_hits=True, **kw)
+    assert np.array_equal(ga.view(np.uint32), ka.view(np.uint32))
+    assert np.array_equal(ge.view(np.uint32), ke.view(np.uint32))
+    oa, oe, aa, ae = oracle.Scene(scene).backward(cam, d, **kw)
+    for g, o, a in [(ka, oa, aa), (ke, oe, ae)]:
+        assert (np.abs(g - o) <= 1e-4 * a + 1e-7 * np.abs(o).max()).all()
+    assert np.abs(oe).sum() > 0
+
+
 def test_batch_with_attribute_job_matches_oracle():
     s0, c0 = scenes.cornell_attributes(coat=(0.2, 1.4))
     c0 = dict(c0, width=20, height=16)

@@ -194,11 +194,12 @@ def test_adjoint_halton_sampler_vs_oracle():
     _grad_check(ga, ge, oa, oe, aa, ae)
 
 
-@pytest.mark.parametrize("mode", ["mega", "wave"])
+@pytest.mark.parametrize("mode", ["mega", "wave", "mega_keep_hits"])
 def test_adjoint_replay_schedules_match_oracle(mode):
     # replay A as the megakernel-style kernel or as the wavefront stages
-    # (with the hybrid tail): the same per-path radiance, so both gradients
-    # match the oracle's to the atomics' rounding
+    # (with the hybrid tail), or keeping its intersections for replay B:
+    # the same per-path radiance and the same terms, so all gradients match
+    # the oracle's to the atomics' rounding
     scene, cam = scenes.procedural(seed=62, n_objects=30, width=72, height=48)
     log("adjoint replay", mode)
     R = ptmi.Renderer(scene, cam)
@@ -206,10 +207,11 @@ def test_adjoint_replay_schedules_match_oracle(mode):
     n = cam["width"] * cam["height"]
     d = rng.normal(size=(n, 3)).astype(np.float32)
     kw = dict(spp=3, max_depth=5, seed=9, frame=2)
-    extra = dict(tail_threshold=500, tail_bounce=3) if mode == "wave" else {}
+    extra = {"wave": dict(mode="wave", tail_threshold=500, tail_bounce=3), "mega": dict(mode="mega"),
+             "mega_keep_hits": dict(mode="mega", flags=ptmi.FLAG_KEEP_HITS)}[mode]
     ga = torch.zeros_like(R.albedo)
     ge = torch.zeros_like(R.emission)
-    R.backward(torch.from_numpy(d).cuda(), ga, ge, mode=mode, **kw, **extra)
+    R.backward(torch.from_numpy(d).cuda(), ga, ge, **kw, **extra)
     st = R.stats()
     # replay B traces the forward frame's rays again: the counts are those
     # of the forward megakernel with the same arguments
@@ -220,3 +222,29 @@ def test_adjoint_replay_schedules_match_oracle(mode):
     ga, ge = ga.cpu().numpy()[:R.nt], ge.cpu().numpy()[:R.nt]
     oa, oe, aa, ae = oracle.Scene(scene).backward(cam, d, **kw)
     _grad_check(ga, ge, oa, oe, aa, ae)
+
+
+def test_adjoint_keep_hits_full_size_matches_tracing_replay():
+    # the benchmark's backward (1.02M triangles, 512x512, 8 spp, depth 6)
+    # with replay B reading replay A's records against replay B tracing
+    # again: the same terms, summed by atomics in another order
+    scene, _ = scenes.procedural(seed=2, n_objects=2000)
+    cam = dict(eye=(0.0, 50.0, -130.0), target=(0.0, 40.0, 0.0), up=(0.0, 1.0, 0.0), vfov_deg=50.0,
+               width=512, height=512)
+    R = ptmi.Renderer(scene, cam)
+    log("adjoint keep hits full size", R.nt)
+    d = torch.ones((512, 512, 3), dtype=torch.float32, device="cuda")
+    kw = dict(spp=8, max_depth=6, seed=0, frame=3, block=256, grid_mult=8, stack_lds=8, mode="mega")
+    out = []
+    for flags in (0, ptmi.FLAG_KEEP_HITS):
+        ga = torch.zeros_like(R.albedo)
+        ge = torch.zeros_like(R.emission)
+        R.backward(d, ga, ge, flags=flags, **kw)
+        st = R.stats()
+        out.append((ga.cpu().numpy()[:R.nt].astype(np.float64), ge.cpu().numpy()[:R.nt].astype(np.float64),
+                    st["extension_rays"], st["shadow_rays"]))
+    (a0, e0, n0, s0), (a1, e1, n1, s1) = out
+    assert n0 == n1 > 0 and s0 == s1 > 0
+    for g0, g1 in ((a0, a1), (e0, e1)):
+        assert np.abs(g0).sum() > 0
+        assert np.linalg.norm(g1 - g0) <= 1e-5 * np.linalg.norm(g0)
