@@ -220,9 +220,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-replay", default="mega,wave,keep",
-                    help="comma-separated schedules of the adjoint's radiance replay: mega, wave, keep (mega keeping "
-                         "the intersections for the gradient replay); profiled runs take mega alone, so that the "
-                         "wavefront kernels' averages are the forward frame's")
+                    help="comma-separated schedules of the adjoint's radiance replay: mega, wave, and keep (each "
+                         "also keeping the intersections for the gradient replay); profiled runs take mega,keep "
+                         "only, so that the wavefront kernels' averages are the forward frame's")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the divergence and batched workload summaries and the compaction ablation")
     ap.add_argument("--schedules", default="wave_hybrid,wave_pure,mega",
@@ -643,10 +643,12 @@ def adjoint_bench(ptmi, scene, torch, args, prof, copy_gbs, roof):
         variants = {"replay_a_megakernel": dict(ADJOINT_PARAMS["mega"], mode="mega"),
                     "replay_a_wavefront": dict(ADJOINT_PARAMS["wave"], mode="wave"),
                     "replay_a_megakernel_keep_hits": dict(ADJOINT_PARAMS["mega"], mode="mega",
-                                                          flags=ptmi.FLAG_KEEP_HITS)}
+                                                          flags=ptmi.FLAG_KEEP_HITS),
+                    "replay_a_wavefront_keep_hits": dict(ADJOINT_PARAMS["wave"], mode="wave",
+                                                         flags=ptmi.FLAG_KEEP_HITS)}
         pick = args.adjoint_replay.split(",")
         variants = {n: p for n, p in variants.items()
-                    if (n.endswith("keep_hits") and "keep" in pick) or (not n.endswith("keep_hits") and p["mode"] in pick)}
+                    if p["mode"] in pick and (("keep" in pick) or not n.endswith("keep_hits"))}
         res = {}
         wave_stages = ("raygen", "extend", "shade", "shadow", "tail")
         for name, p in variants.items():

@@ -79,10 +79,10 @@ enum {
                                   two-slot buffer (current, next) that a one-thread promote kernel
                                   moves over after every bounce, in place of one counter per bounce;
                                   same image bit for bit */
-    PT_FLAG_KEEP_HITS = 128    /* backward, PT_MODE_MEGA: the first replay keeps every path vertex's
-                                  intersection and light-sample visibility (9 bytes per vertex and
-                                  path sample in the workspace) and the second reads them instead of
-                                  tracing the same rays again; same gradients */
+    PT_FLAG_KEEP_HITS = 128    /* backward: the first replay keeps every path vertex's intersection
+                                  and light-sample visibility (9 bytes per vertex and path sample in
+                                  the workspace) and the second reads them instead of tracing the
+                                  same rays again; same gradients; ignored by forward renders */
 };
 
 typedef struct pt_ctx pt_ctx;
@@ -347,14 +347,18 @@ pt_status pt_render_frames(pt_ctx* ctx, const pt_render_args* args, int32_t n_fr
  * by (seed, frame, spp, job).  Each path is replayed twice from its random
  * numbers: a first pass over all paths keeps only each path's radiance (16
  * bytes per path in the workspace), a second pass replays them again and
- * adds the gradients; no vertex is stored.  args->mode selects how the
+ * adds the gradients; by default no vertex is stored.  args->mode selects how the
  * first pass runs: PT_MODE_MEGA as one megakernel-style kernel, PT_MODE_WAVE
  * as the wavefront stages with the frame's wavefront options (hybrid tail,
  * sorts), whose per-path radiance is the same bit for bit; the second pass
- * is one kernel either way.
+ * is one kernel either way.  With PT_FLAG_KEEP_HITS the first pass also
+ * keeps every vertex's intersection and light-sample visibility and the
+ * second traces no ray (same gradients, 9 bytes per path vertex of
+ * workspace).
  * workspace: at least pt_backward_workspace_size bytes (path cursors, the
- * per-path radiance, the wavefront buffers in PT_MODE_WAVE, the traversal
- * stack overflow area), 256-byte aligned.
+ * per-path radiance, the wavefront buffers in PT_MODE_WAVE, the kept
+ * records with PT_FLAG_KEEP_HITS, the traversal stack overflow area),
+ * 256-byte aligned.
  * PT_EINVAL if Russian roulette is on (its survival probability depends on
  * the albedo). */
 pt_status pt_backward_workspace_size(pt_ctx* ctx, const pt_render_args* args, uint64_t* bytes);

@@ -84,10 +84,10 @@ PT_DEV void adjoint_b_begin(const CamView& cam, const PathParams& pp, uint32_t p
 }
 
 // One vertex of replay B; returns false when the path is finished.  ATTR:
-// the scene may have vertex attributes (see shade_vertex).  The extension
-// and shadow rays it traces are counted in n_ext, n_sh.  STORED: the
+// the scene may have vertex attributes (see shade_vertex).  STORED: the
 // vertex's intersection and light-sample visibility come from replay A's
-// records (rec) and no ray is traced.
+// records (rec) and no ray is traced.  The vertex's extension and shadow
+// rays (traced here, or by replay A with STORED) are counted in n_ext, n_sh.
 template <int LDS, bool ATTR = false, class Acc, bool COUNT = false, bool STORED = false>
 PT_DEV bool adjoint_b_step(const SceneView& sc, const PathParams& pp, AdjRun& ar, float* __restrict__ g_alb,
                            float* __restrict__ g_emi, TravStack<LDS, COUNT>& st, Acc& acc, uint32_t& n_ext,
@@ -109,8 +109,8 @@ PT_DEV bool adjoint_b_step(const SceneView& sc, const PathParams& pp, AdjRun& ar
     } else {
         Ray ray = make_ray(o, d);
         h = closest_hit<LDS>(sc, ray, INFINITY, st);
-        ++n_ext;
     }
+    ++n_ext;
     const f3 beta = ps.beta;
     ShadowReq sh;
     VertexOut vo = shade_vertex<false, ATTR>(sc, pp, pix, sample, k, d, h, ps, sh);
@@ -127,12 +127,9 @@ PT_DEV bool adjoint_b_step(const SceneView& sc, const PathParams& pp, AdjRun& ar
     float ga[3] = {0.0f, 0.0f, 0.0f};
     if (sh.valid) {
         bool seen;
-        if constexpr (STORED) {
-            seen = rec.vis[at] != 0;
-        } else {
-            ++n_sh;
-            seen = !any_hit<LDS>(sc, make_ray(sh.o, sh.d), kShadowTmax, st);
-        }
+        ++n_sh;
+        if constexpr (STORED) seen = rec.vis[at] != 0;
+        else seen = !any_hit<LDS>(sc, make_ray(sh.o, sh.d), kShadowTmax, st);
         if (seen) {
             ps.L = mk3(ps.L.x + sh.contrib.x, ps.L.y + sh.contrib.y, ps.L.z + sh.contrib.z);
             const f3 rho = load3(sc.albedo, id);

@@ -116,9 +116,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k
 
 // Replay B of every path, one vertex per loop trip with the same hand-out
 // of paths (cursor[1]), from the radiance replay A left in Lpath.  STORED:
-// from replay A's records too, tracing no ray.
+// from replay A's records too, tracing no ray (no traversal stack, so its
+// register budget is set on its own).
+constexpr int kStoredWaves = 4;
+
 template <int LDS, bool ATTR, bool STORED>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_adjoint(SceneView sc, CamView cam, PathParams pp,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STORED ? kStoredWaves : 4))) k_adjoint(SceneView sc, CamView cam, PathParams pp,
                                                  const float* __restrict__ d_img, const float4* __restrict__ Lpath,
                                                  unsigned long long* __restrict__ cursor, float* __restrict__ g_alb,
                                                  float* __restrict__ g_emi, uint2* __restrict__ ovf, int gcap,
@@ -183,7 +186,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
             live = false;
     }
     // with count_rays (replay A ran as the wavefront, which keeps its own
-    // counters) the paths' rays are counted here, one atomic per wave
+    // counters) the paths' rays are counted here (traced here, or by
+    // replay A with its records), one atomic per wave
     if (count_rays) {
         for (int off = 32; off > 0; off >>= 1) {
             ne += __shfl_xor(ne, off);

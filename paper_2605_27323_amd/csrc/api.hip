@@ -259,7 +259,8 @@ size_t frame_slot_bytes(const pt_ctx* c, const WsLayout& w) {
 // radiance buffer is returned in *Lbuf): counters, then the megakernel
 // (writing img / acc) or raygen and the bounce stages.
 pt_status enqueue_stages(pt_ctx* c, const pt_render_args* a, const Launch& L, const WsLayout& w, char* base,
-                         hipStream_t s, float* img, float* acc, bool prof, const float4** Lbuf) {
+                         hipStream_t s, float* img, float* acc, bool prof, const float4** Lbuf,
+                         const VertexRecs* rec = nullptr) {
     uint32_t* counts = reinterpret_cast<uint32_t*>(base + w.counts);
     unsigned long long* trav = reinterpret_cast<unsigned long long*>(base + w.trav);
     uint2* ovf = reinterpret_cast<uint2*>(base + w.ovf);
@@ -297,6 +298,11 @@ pt_status enqueue_stages(pt_ctx* c, const pt_render_args* a, const Launch& L, co
         wb.sort_key = reinterpret_cast<uint32_t*>(base + w.sort_key);
         wb.perm = reinterpret_cast<uint32_t*>(base + w.perm);
         wb.hist = reinterpret_cast<uint32_t*>(base + w.hist);
+        if (rec) {
+            wb.rec_hit = rec->hit;
+            wb.rec_vis = rec->vis;
+            wb.rec_n = rec->npaths;
+        }
         const int compact = (a->flags & PT_FLAG_NO_COMPACT) ? 0 : 1;
         const int sort = (a->flags & PT_FLAG_SORT_MATERIAL) ? 1 : 0;
         const int rsort = (a->flags & PT_FLAG_SORT_RAYS) ? 1 : 0;
@@ -852,8 +858,6 @@ pt_status pt_render_backward(pt_ctx* c, const pt_render_args* a, const float* d_
     if (!ws) return fail(PT_EINVAL, "null workspace");
     if ((reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return fail(PT_EINVAL, "workspace must be 256-byte aligned");
     const bool keep = (a->flags & PT_FLAG_KEEP_HITS) != 0;
-    if (keep && a->mode != PT_MODE_MEGA)
-        return fail(PT_EUNSUPPORTED, "PT_FLAG_KEEP_HITS needs the megakernel-style first replay (PT_MODE_MEGA)");
     Launch L;
     st = launch_config(c, a, L);
     if (st) return st;
@@ -882,7 +886,7 @@ pt_status pt_render_backward(pt_ctx* c, const pt_render_args* a, const float* d_
         // leave each path's radiance in their per-path buffer; replay B
         // counts its rays in the block after the cursors
         PT_HIP(launch_init_counts(s, reinterpret_cast<uint32_t*>(cursor), 8, 0u), "init path cursors");
-        st = enqueue_stages(c, a, L, w, base, s, nullptr, nullptr, prof, &Lpath);
+        st = enqueue_stages(c, a, L, w, base, s, nullptr, nullptr, prof, &Lpath, keep ? &rec : nullptr);
         if (st) return st;
         counts = reinterpret_cast<uint32_t*>(base + w.adj) + 4;
     } else {

@@ -44,6 +44,13 @@ struct WaveBufs {
     uint32_t* sort_key;
     uint32_t* perm;
     uint32_t* hist;     // [64] counts, [64..127] running offsets, [128] sorted flag
+    // the adjoint's replay A with kept intersections (else null): vertex
+    // k of path p at [(k - 1) * rec_n + p], its hit written by the shade
+    // stage and the hybrid tail, its light-sample visibility by the shadow
+    // stage and the tail (see VertexRecs)
+    uint2* rec_hit;
+    uint8_t* rec_vis;
+    uint32_t rec_n;
 };
 
 constexpr int kSortBins = 64;

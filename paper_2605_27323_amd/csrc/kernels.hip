@@ -389,6 +389,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
             if (!more) {
                 live = false;
                 if (!occluded) shadow_add(wb, item);
+                shadow_record(wb, b, item, !occluded);
             }
         }
     }

@@ -106,6 +106,7 @@ PT_DEV uint32_t shade_item(const SceneView& sc, const PathParams& pp, const Wave
     } else {
         hit_barycentrics(sc, xyz(o4), xyz(d4), h);
     }
+    if (wb.rec_hit) wb.rec_hit[(size_t)b * wb.rec_n + path] = make_uint2(f2u(h.t), h.tri);
     vo = shade_vertex<INST, ATTR>(sc, pp, pix, sample, b + 1, xyz(d4), h, ps, sh, lc);
     if (for_tail) {
         ps.L = xyz(wb.L[path]);
@@ -133,14 +134,16 @@ PT_DEV void finish_path(const SceneView& sc, const PathParams& pp, const WaveBuf
     while (true) {
         if (sh.valid) {
             ++n_sh;
-            if (!any_hit_t<LDS, COUNT, INST>(sc, sh.o, sh.d, kShadowTmax, st))
-                ps.L = mk3(ps.L.x + sh.contrib.x, ps.L.y + sh.contrib.y, ps.L.z + sh.contrib.z);
+            const bool seen = !any_hit_t<LDS, COUNT, INST>(sc, sh.o, sh.d, kShadowTmax, st);
+            if (seen) ps.L = mk3(ps.L.x + sh.contrib.x, ps.L.y + sh.contrib.y, ps.L.z + sh.contrib.z);
+            if (wb.rec_vis) wb.rec_vis[(size_t)(k - 1) * wb.rec_n + path] = seen ? 1 : 0;
         }
         if (!vo.cont) break;
         ++k;
         ++n_ext;
         const f3 d = vo.d;
         Hit h = closest_hit_t<LDS, COUNT, INST>(sc, vo.o, d, INFINITY, st);
+        if (wb.rec_hit) wb.rec_hit[(size_t)(k - 1) * wb.rec_n + path] = make_uint2(f2u(h.t), h.tri);
         vo = shade_vertex<INST, ATTR>(sc, pp, pix, sample, k, d, h, ps, sh, lc);
         add_radiance(ps, vo);
     }
@@ -172,11 +175,20 @@ PT_DEV void shadow_add(const WaveBufs& wb, uint32_t i) {
     wb.L[path] = make_float4(l4.x + c4.x, l4.y + c4.y, l4.z + c4.z, 0.f);
 }
 
-// light-sample segment i: add beta * C to its path when unoccluded
+// the visibility of light-sample segment i of bounce b, for the adjoint's
+// kept records
+PT_DEV void shadow_record(const WaveBufs& wb, int b, uint32_t i, bool seen) {
+    if (wb.rec_vis) wb.rec_vis[(size_t)b * wb.rec_n + f2u(wb.sh_o[i].w)] = seen ? 1 : 0;
+}
+
+// light-sample segment i of bounce b: add beta * C to its path when
+// unoccluded
 template <int LDS, bool COUNT = false, bool INST = false>
-PT_DEV void shadow_item(const SceneView& sc, const WaveBufs& wb, uint32_t i, TravStack<LDS, COUNT>& st) {
+PT_DEV void shadow_item(const SceneView& sc, const WaveBufs& wb, int b, uint32_t i, TravStack<LDS, COUNT>& st) {
     float4 o4 = wb.sh_o[i], d4 = wb.sh_d[i];
-    if (!any_hit_t<LDS, COUNT, INST>(sc, xyz(o4), xyz(d4), kShadowTmax, st)) shadow_add(wb, i);
+    const bool seen = !any_hit_t<LDS, COUNT, INST>(sc, xyz(o4), xyz(d4), kShadowTmax, st);
+    if (seen) shadow_add(wb, i);
+    shadow_record(wb, b, i, seen);
 }
 
 // per-pixel mean over its spp paths, summed in sample order

@@ -151,7 +151,7 @@ class Emu:
         ga = np.zeros((max(nt, 1), 3), np.float32)
         ge = np.zeros((max(nt, 1), 3), np.float32)
         rc = lib().emu_backward(self.h, spp, max_depth, seed, frame, job, int(bool(nee)), d_image.ctypes.data,
-                                ga.ctypes.data, ge.ctypes.data, int(sampler), int(bool(keep_hits)))
+                                ga.ctypes.data, ge.ctypes.data, int(sampler), int(keep_hits))
         assert rc == 0
         return ga[:nt], ge[:nt]
 

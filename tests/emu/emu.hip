@@ -126,10 +126,13 @@ int32_t emu_closest(pt_ctx* c, int32_t n, const float* o, const float* d, float*
 
 namespace {
 
+// The wavefront over the image; with rec, replay A of the adjoint with kept
+// records (the path radiances then go to Lout).
 template <bool INST, bool ATTR>
 int32_t render_wave(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32_t frame, uint32_t job, int32_t nee,
                     int32_t rr_start, int32_t compact, uint64_t shuffle_seed, int32_t sort, uint32_t tail,
-                    float* img, uint64_t* rays, int32_t sampler) {
+                    float* img, uint64_t* rays, int32_t sampler, const VertexRecs* rec = nullptr,
+                    float4* Lout = nullptr) {
     SceneView sc = host_view(c);
     PathParams pp{spp, D, nee ? 1 : 0, rr_start, seed, frame, job, sampler};
     const uint32_t npaths = (uint32_t)c->cam.W * c->cam.H * (uint32_t)spp;
@@ -148,6 +151,11 @@ int32_t render_wave(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32_t f
     wb.sh_c = buf[9].data();
     wb.L = buf[10].data();
     wb.counts = counts.data();
+    if (rec) {
+        wb.rec_hit = rec->hit;
+        wb.rec_vis = rec->vis;
+        wb.rec_n = rec->npaths;
+    }
     wb.sh_base = D + 2;
     wb.tail_slot = 2 * D + 3;
     wb.err_slot = (int)counts.size() - 1;
@@ -216,11 +224,13 @@ int32_t render_wave(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32_t f
                 for (uint32_t i = 0; i < nsh; ++i) buf[f][i] = tmp[ps[i]];
             }
         }
-        for (uint32_t i = 0; i < nsh; ++i) shadow_item<kL, false, INST>(sc, wb, i, hs.st);
+        for (uint32_t i = 0; i < nsh; ++i) shadow_item<kL, false, INST>(sc, wb, b, i, hs.st);
         ns += nsh;
     }
     const uint32_t npix = (uint32_t)c->cam.W * c->cam.H;
-    for (uint32_t pix = 0; pix < npix; ++pix) accumulate_item(pp, wb.L, img, nullptr, pix);
+    if (Lout) std::copy(buf[10].begin(), buf[10].begin() + npaths, Lout);
+    if (img)
+        for (uint32_t pix = 0; pix < npix; ++pix) accumulate_item(pp, wb.L, img, nullptr, pix);
     rays[0] = ne;
     rays[1] = ns;
     return hs.st.overflow ? 1 : 0;
@@ -246,7 +256,10 @@ int32_t emu_render_wave(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32
 // Path-replay adjoint over the whole image (sequential binary32 adds):
 // g_alb, g_emi (nt*3) are accumulated into.  keep_hits: replay A keeps
 // every vertex's intersection and light-sample visibility and replay B
-// reads them (the records of all paths, laid out as the GPU's).
+// reads them (the records of all paths, laid out as the GPU's); 1: replay
+// A path by path (megakernel order), 2: replay A as the wavefront over all
+// paths first (queues shuffled), 3: as 2 with every path finished by the
+// hybrid tail from its first vertex on.
 int32_t emu_backward(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32_t frame, uint32_t job, int32_t nee,
                      const float* d_img, float* g_alb, float* g_emi, int32_t sampler, int32_t keep_hits) {
     struct HostAcc {
@@ -267,6 +280,32 @@ int32_t emu_backward(pt_ctx* c, int32_t spp, int32_t D, uint64_t seed, uint32_t 
     std::vector<uint2> hits(nrec, make_uint2(0x7FC00001u, 0xFFFFFFFEu));
     std::vector<uint8_t> vis(nrec, 0x5Au);
     const VertexRecs rec{hits.data(), vis.data(), npaths};
+    if (keep_hits >= 2) {
+        std::vector<float4> L(std::max<uint32_t>(npaths, 1));
+        uint64_t rays[2];
+        const uint32_t tail = keep_hits == 3 ? npaths + 1 : 0u;
+        const int32_t rc = has_attrs(c) ? render_wave<false, true>(c, spp, D, seed, frame, job, nee, -1, 1, 77, 0, tail,
+                                                                   nullptr, rays, sampler, &rec, L.data())
+                                        : render_wave<false, false>(c, spp, D, seed, frame, job, nee, -1, 1, 77, 0,
+                                                                    tail, nullptr, rays, sampler, &rec, L.data());
+        if (rc) return rc;
+        for (uint32_t p = 0; p < npaths; ++p) {
+            const uint32_t pix = p / (uint32_t)spp, s = p - pix * (uint32_t)spp;
+            f3 delta =
+                mk3(d_img[3 * (size_t)pix] / fs, d_img[3 * (size_t)pix + 1] / fs, d_img[3 * (size_t)pix + 2] / fs);
+            AdjRun ar;
+            adjoint_b_begin(c->cam, pp, pix, frame * (uint32_t)spp + s, delta, xyz(L[p]), ar, p);
+            uint32_t ne = 0, ns = 0;
+            if (has_attrs(c)) {
+                while (adjoint_b_step<kL, true, HostAcc, false, true>(sc, pp, ar, g_alb, g_emi, hs.st, acc, ne, ns, rec)) {
+                }
+            } else {
+                while (adjoint_b_step<kL, false, HostAcc, false, true>(sc, pp, ar, g_alb, g_emi, hs.st, acc, ne, ns, rec)) {
+                }
+            }
+        }
+        return hs.st.overflow ? 1 : 0;
+    }
     for (uint32_t p = 0; p < npaths; ++p) {
         const uint32_t pix = p / (uint32_t)spp, s = p - pix * (uint32_t)spp;
         f3 delta = mk3(d_img[3 * (size_t)pix] / fs, d_img[3 * (size_t)pix + 1] / fs, d_img[3 * (size_t)pix + 2] / fs);

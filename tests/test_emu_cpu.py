@@ -336,13 +336,17 @@ def test_adjoint_keep_hits_bit_identical(which):
     E = emu.Emu(scene, cam)
     d = np.random.default_rng(5).normal(size=(cam["width"] * cam["height"], 3)).astype(np.float32)
     ga, ge = E.backward(d, **kw)
-    ka, ke = E.backward(d, keep_hits=True, **kw)
-    assert np.array_equal(ga.view(np.uint32), ka.view(np.uint32))
-    assert np.array_equal(ge.view(np.uint32), ke.view(np.uint32))
     oa, oe, aa, ae = oracle.Scene(scene).backward(cam, d, **kw)
-    for g, o, a in [(ka, oa, aa), (ke, oe, ae)]:
-        assert (np.abs(g - o) <= 1e-4 * a + 1e-7 * np.abs(o).max()).all()
     assert np.abs(oe).sum() > 0
+    # 1: replay A path by path; 2: replay A as the wavefront (shuffled
+    # queues), its records written by the stage functions; 3: the same with
+    # every path finished by the hybrid tail
+    for keep in (1, 2, 3):
+        ka, ke = E.backward(d, keep_hits=keep, **kw)
+        assert np.array_equal(ga.view(np.uint32), ka.view(np.uint32)), keep
+        assert np.array_equal(ge.view(np.uint32), ke.view(np.uint32)), keep
+        for g, o, a in [(ka, oa, aa), (ke, oe, ae)]:
+            assert (np.abs(g - o) <= 1e-4 * a + 1e-7 * np.abs(o).max()).all()
 
 
 def test_batch_with_attribute_job_matches_oracle():

@@ -194,7 +194,7 @@ def test_adjoint_halton_sampler_vs_oracle():
     _grad_check(ga, ge, oa, oe, aa, ae)
 
 
-@pytest.mark.parametrize("mode", ["mega", "wave", "mega_keep_hits"])
+@pytest.mark.parametrize("mode", ["mega", "wave", "mega_keep_hits", "wave_keep_hits"])
 def test_adjoint_replay_schedules_match_oracle(mode):
     # replay A as the megakernel-style kernel or as the wavefront stages
     # (with the hybrid tail), or keeping its intersections for replay B:
@@ -208,7 +208,8 @@ def test_adjoint_replay_schedules_match_oracle(mode):
     d = rng.normal(size=(n, 3)).astype(np.float32)
     kw = dict(spp=3, max_depth=5, seed=9, frame=2)
     extra = {"wave": dict(mode="wave", tail_threshold=500, tail_bounce=3), "mega": dict(mode="mega"),
-             "mega_keep_hits": dict(mode="mega", flags=ptmi.FLAG_KEEP_HITS)}[mode]
+             "mega_keep_hits": dict(mode="mega", flags=ptmi.FLAG_KEEP_HITS),
+             "wave_keep_hits": dict(mode="wave", tail_threshold=500, tail_bounce=3, flags=ptmi.FLAG_KEEP_HITS)}[mode]
     ga = torch.zeros_like(R.albedo)
     ge = torch.zeros_like(R.emission)
     R.backward(torch.from_numpy(d).cuda(), ga, ge, **kw, **extra)
@@ -234,17 +235,22 @@ def test_adjoint_keep_hits_full_size_matches_tracing_replay():
     R = ptmi.Renderer(scene, cam)
     log("adjoint keep hits full size", R.nt)
     d = torch.ones((512, 512, 3), dtype=torch.float32, device="cuda")
-    kw = dict(spp=8, max_depth=6, seed=0, frame=3, block=256, grid_mult=8, stack_lds=8, mode="mega")
+    kw = dict(spp=8, max_depth=6, seed=0, frame=3, block=256, grid_mult=8, stack_lds=8)
     out = []
-    for flags in (0, ptmi.FLAG_KEEP_HITS):
+    # the tracing replay, then the kept records written by the megakernel-
+    # style replay A and by the wavefront stages with the hybrid tail
+    for flags, extra in ((0, dict(mode="mega")), (ptmi.FLAG_KEEP_HITS, dict(mode="mega")),
+                         (ptmi.FLAG_KEEP_HITS, dict(mode="wave", tail_threshold=1 << 18, tail_bounce=4))):
         ga = torch.zeros_like(R.albedo)
         ge = torch.zeros_like(R.emission)
-        R.backward(d, ga, ge, flags=flags, **kw)
+        R.backward(d, ga, ge, flags=flags, **kw, **extra)
         st = R.stats()
         out.append((ga.cpu().numpy()[:R.nt].astype(np.float64), ge.cpu().numpy()[:R.nt].astype(np.float64),
                     st["extension_rays"], st["shadow_rays"]))
-    (a0, e0, n0, s0), (a1, e1, n1, s1) = out
-    assert n0 == n1 > 0 and s0 == s1 > 0
-    for g0, g1 in ((a0, a1), (e0, e1)):
-        assert np.abs(g0).sum() > 0
-        assert np.linalg.norm(g1 - g0) <= 1e-5 * np.linalg.norm(g0)
+    a0, e0, n0, s0 = out[0]
+    assert n0 > 0 and s0 > 0
+    for a1, e1, n1, s1 in out[1:]:
+        assert n1 == n0 and s1 == s0
+        for g0, g1 in ((a0, a1), (e0, e1)):
+            assert np.abs(g0).sum() > 0
+            assert np.linalg.norm(g1 - g0) <= 1e-5 * np.linalg.norm(g0)
