@@ -255,3 +255,38 @@ def test_attributes_validated():
     assert L.pt_build_bvh(h, None, C.byref(info)) == 0
     assert info.attribute_bytes == 0
     assert L.pt_destroy(h) == 0
+
+
+def test_keep_hits_workspace_adds_vertex_records():
+    # PT_FLAG_KEEP_HITS reserves, per path sample and vertex (max_depth + 1
+    # of them), an 8-byte hit record and a 1-byte visibility, each region
+    # 256-byte aligned; forward workspaces do not change
+    L = ptmi.lib()
+    h = C.c_void_p()
+    assert L.pt_create(C.byref(h), -1) == 0
+    scene, cam = scenes.cornell()
+    d, keep = _desc(scene)
+    info = ptmi.BvhInfo()
+    assert L.pt_load_scene(h, C.byref(d)) == 0
+    assert L.pt_build_bvh(h, None, C.byref(info)) == 0
+    W, H = 33, 17
+    camd = ptmi.Camera((C.c_double * 3)(*cam["eye"]), (C.c_double * 3)(*cam["target"]), (C.c_double * 3)(*cam["up"]),
+                       float(cam["vfov_deg"]), W, H)
+    assert L.pt_set_camera(h, C.byref(camd)) == 0
+
+    def up(x):
+        return (x + 255) // 256 * 256
+
+    for mode in (ptmi.MODE_MEGA, ptmi.MODE_WAVE):
+        for spp, depth in ((3, 5), (1, 0), (2, 12)):
+            sizes = {}
+            for flags in (0, ptmi.FLAG_KEEP_HITS):
+                a = ptmi.RenderArgs(spp, depth, 0, 0, 0, 1, -1, mode, flags, 0, 0)
+                for fn, key in ((L.pt_backward_workspace_size, "b"), (L.pt_workspace_size, "f")):
+                    n = C.c_uint64()
+                    assert fn(h, C.byref(a), C.byref(n)) == 0
+                    sizes[(flags, key)] = n.value
+            nrec = W * H * spp * (depth + 1)
+            assert sizes[(ptmi.FLAG_KEEP_HITS, "b")] - sizes[(0, "b")] == up(8 * nrec) + up(nrec)
+            assert sizes[(ptmi.FLAG_KEEP_HITS, "f")] == sizes[(0, "f")]
+    assert L.pt_destroy(h) == 0
