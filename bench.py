@@ -25,6 +25,13 @@ import platform
 import sys
 import time
 
+# At least eight hardware queues for this process (HIP's default is four),
+# read when HIP first initialises: the library then keeps five frames in
+# flight, one stream each, plus the caller's stream, and a batch four pools,
+# without sharing queues.
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "4") or "4") < 8:
+    os.environ["GPU_MAX_HW_QUEUES"] = "8"
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -57,8 +64,9 @@ PURE = {"tail_threshold": 0, "tail_bounce": 0, "tail_spread": False}
 # launch parameters of the divergence workload (4 spp, depth 16)
 DIVERGENCE_PARAMS = {"wave": {"block": 256, "grid_mult": 8, "stack_lds": 8, "tail_threshold": 1 << 18, "tail_bounce": 6},
                      "mega": {"block": 256, "grid_mult": 4, "stack_lds": 8}}
-# batch options the autotuner chose for the 64-job workload
-BATCH_OPTS = {"pool_capacity": 1 << 23, "block": 256, "grid_mult": 8, "stack_lds": 8, "pools": 3}
+# batch options for the 64-job workload (measured on MI355X; four pools need
+# the eight hardware queues set above)
+BATCH_OPTS = {"pool_capacity": 1 << 23, "block": 256, "grid_mult": 8, "stack_lds": 8, "pools": 4}
 W, H, SPP, DEPTH, RR = 1920, 1080, 1, 8, 3
 PROFILE = "procedural1M_1080p"
 

@@ -324,18 +324,21 @@ pt_status pt_render_frame(pt_ctx* ctx, const pt_render_args* args, float* image_
 pt_status pt_render_frame_noalloc(pt_ctx* ctx, const pt_render_args* args, float* image_out, float* accum_inout,
                                   void* stream);
 
-/* Progressive rendering with three frames in flight: frames args->frame,
+/* Progressive rendering with F frames in flight: frames args->frame,
  * ..., args->frame + n_frames - 1, each exactly as pt_render_frame renders
- * it.  A frame's stages run on one of three internal streams of the context
- * (default priority, created on first use) while the two before it finish
- * on the others, so that the short last bounces of one frame overlap the
- * first bounces of the next; the per-frame accumulation runs on `stream` in
- * frame order.  Work enqueued on `stream` before the call precedes every
+ * it.  A frame's stages run on one of F internal streams of the context
+ * (default priority, created on first use) while the frames before it
+ * finish on the others, so that the short last bounces of one frame overlap
+ * the first bounces of the next; the per-frame accumulation runs on
+ * `stream` in frame order.  F is fixed when the context is created: one
+ * less than the hardware queues HIP gives the process (the environment
+ * variable GPU_MAX_HW_QUEUES, 4 when unset; it must be set before the
+ * process first uses HIP to take effect), between 3 and 5.  Work enqueued on `stream` before the call precedes every
  * frame; the call's results are complete when `stream` reaches its end.
  * image_out receives each frame's image in turn (the last one remains);
  * accum_inout (may be NULL) is updated as by n_frames calls of
  * pt_render_frame, bit for bit.  workspace: pt_frames_workspace_size bytes
- * (three frame slots), 256-byte aligned.  PT_EINVAL with PT_FLAG_PROFILE.
+ * (F frame slots), 256-byte aligned.  PT_EINVAL with PT_FLAG_PROFILE.
  * Calls that overlap on one context race. */
 pt_status pt_frames_workspace_size(pt_ctx* ctx, const pt_render_args* args, uint64_t* bytes);
 pt_status pt_render_frames(pt_ctx* ctx, const pt_render_args* args, int32_t n_frames, float* image_out,

@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <thread>
@@ -33,8 +34,17 @@ pt_status hip_fail(hipError_t e, const char* what) {
         if (e_ != hipSuccess) return hip_fail(e_, what); \
     } while (0)
 
-// frames in flight in pt_render_frames (internal streams and workspace slots)
-constexpr int kInFlight = 3;
+// frames in flight in pt_render_frames (internal streams and workspace
+// slots): one stream per frame plus the caller's, each on a hardware queue
+// of its own; HIP gives a process GPU_MAX_HW_QUEUES of them (4 unless the
+// environment says otherwise), so the count follows that setting, from 3
+// up to kMaxInFlight.  Sharing queues cost more than the extra frame gained.
+constexpr int kMaxInFlight = 5;
+int frames_in_flight_for_queues() {
+    const char* e = std::getenv("GPU_MAX_HW_QUEUES");
+    const int q = e && *e ? std::atoi(e) : 4;
+    return std::max(3, std::min(kMaxInFlight, q - 1));
+}
 constexpr int kDefaultBlock = 256;
 constexpr int kDefaultGridMult = 8;
 constexpr int kStackLds = 8;
@@ -81,8 +91,9 @@ struct pt_ctx {
     // frames in flight (pt_render_frames): internal streams and their
     // events, created on first use
     bool aux_ready = false;
-    hipStream_t aux[kInFlight] = {};
-    hipEvent_t ev_entry = nullptr, ev_stage[kInFlight] = {}, ev_acc[kInFlight] = {};
+    int in_flight = 3;  // frames in flight (set at creation)
+    hipStream_t aux[kMaxInFlight] = {};
+    hipEvent_t ev_entry = nullptr, ev_stage[kMaxInFlight] = {}, ev_acc[kMaxInFlight] = {};
     uint32_t* last_counts = nullptr;
     unsigned long long* last_trav = nullptr;
     int last_ncounts = 0, last_D = 0, last_kind = 0;  // kind: 0 megakernel, 1 wavefront, 2 adjoint
@@ -418,6 +429,7 @@ pt_status pt_create(pt_ctx** out, int32_t device) {
         c->num_cu = prop.multiProcessorCount;
         c->lds_per_block = prop.sharedMemPerBlock;
         c->device = device;
+        c->in_flight = frames_in_flight_for_queues();
         // the device address of this GPU's scratch array (the allocation-free
         // entry point's memory), looked up once per device
         e = noalloc_scratch_init(device);
@@ -436,7 +448,7 @@ pt_status pt_destroy(pt_ctx* c) {
         (void)hipSetDevice(c->device);
         for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
         if (c->aux_ready) {
-            for (int i = 0; i < kInFlight; ++i) {
+            for (int i = 0; i < c->in_flight; ++i) {
                 (void)hipStreamDestroy(c->aux[i]);
                 (void)hipEventDestroy(c->ev_stage[i]);
                 (void)hipEventDestroy(c->ev_acc[i]);
@@ -789,7 +801,7 @@ pt_status pt_frames_workspace_size(pt_ctx* c, const pt_render_args* a, uint64_t*
     Launch L;
     pt_status st = launch_config(c, a, L);
     if (st) return st;
-    *bytes = kInFlight * frame_slot_bytes(c, layout(c, a, L));
+    *bytes = (uint64_t)c->in_flight * frame_slot_bytes(c, layout(c, a, L));
     return PT_OK;
 }
 
@@ -808,10 +820,11 @@ pt_status pt_render_frames(pt_ctx* c, const pt_render_args* a, int32_t n_frames,
     if (st) return st;
     const WsLayout w = layout(c, a, L);
     const size_t slot = frame_slot_bytes(c, w);
-    if (ws_bytes < kInFlight * slot) return fail(PT_ENOMEM, "workspace too small (pt_frames_workspace_size)");
+    const int nf = c->in_flight;
+    if (ws_bytes < (uint64_t)nf * slot) return fail(PT_ENOMEM, "workspace too small (pt_frames_workspace_size)");
     PT_HIP(hipSetDevice(c->device), "hipSetDevice");
     if (!c->aux_ready) {
-        for (int i = 0; i < kInFlight; ++i) {
+        for (int i = 0; i < nf; ++i) {
             PT_HIP(hipStreamCreateWithFlags(&c->aux[i], hipStreamNonBlocking), "create stream");
             PT_HIP(hipEventCreateWithFlags(&c->ev_stage[i], hipEventDisableTiming), "create event");
             PT_HIP(hipEventCreateWithFlags(&c->ev_acc[i], hipEventDisableTiming), "create event");
@@ -825,10 +838,10 @@ pt_status pt_render_frames(pt_ctx* c, const pt_render_args* a, int32_t n_frames,
     // everything the caller enqueued before (scene, parameters, outputs)
     // precedes both internal streams
     PT_HIP(hipEventRecord(c->ev_entry, s), "record event");
-    for (int i = 0; i < kInFlight; ++i) PT_HIP(hipStreamWaitEvent(c->aux[i], c->ev_entry, 0), "stream wait");
+    for (int i = 0; i < nf; ++i) PT_HIP(hipStreamWaitEvent(c->aux[i], c->ev_entry, 0), "stream wait");
     const uint32_t npix = (uint32_t)c->cam.W * (uint32_t)c->cam.H;
     for (int32_t f = 0; f < n_frames; ++f) {
-        const int k = f % kInFlight;
+        const int k = f % nf;
         char* base = static_cast<char*>(ws) + k * slot;
         float* frame_img = reinterpret_cast<float*>(base + w.total);
         pt_render_args af = *a;
@@ -919,7 +932,7 @@ pt_status pt_frame_stats_get(pt_ctx* c, pt_frame_stats* out) {
     PT_HIP(hipSetDevice(c->device), "hipSetDevice");
     // frames in flight ran on the internal streams
     if (c->aux_ready)
-        for (int i = 0; i < kInFlight; ++i) PT_HIP(hipStreamSynchronize(c->aux[i]), "stream sync");
+        for (int i = 0; i < c->in_flight; ++i) PT_HIP(hipStreamSynchronize(c->aux[i]), "stream sync");
     for (const StageTimer& t : c->timers) {
         PT_HIP(hipEventSynchronize(t.b), "event sync");
         float ms = 0.f;

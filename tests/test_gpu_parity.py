@@ -275,28 +275,41 @@ def test_profile_stage_times():
     assert st["launches"]["extend"] == 3 and st["launches"]["tail"] == 1 and st["launches"]["shadow"] == 2
 
 
+def _frames_ws(R, **kw):
+    n = ctypes.c_uint64()
+    assert ptmi.lib().pt_frames_workspace_size(R.h, ctypes.byref(R.args(**kw)), ctypes.byref(n)) == 0
+    return n.value
+
+
+@pytest.mark.parametrize("queues", ["4", "8"])
 @pytest.mark.parametrize("mode", ["wave", "mega"])
-def test_frames_in_flight_match_sequential(mode):
-    """pt_render_frames (three frames in flight on internal streams) gives the
-    same running average and last image, bit for bit, as frame-by-frame
-    rendering."""
+def test_frames_in_flight_match_sequential(mode, queues, monkeypatch):
+    """pt_render_frames (three frames in flight on internal streams, five
+    when the process has eight hardware queues) gives the same running
+    average and last image, bit for bit, as frame-by-frame rendering."""
     scene, cam = scenes.procedural(seed=52, n_objects=30, width=64, height=40)
-    log(f"frames in flight {mode}")
-    R = ptmi.Renderer(scene, cam)
+    log(f"frames in flight {mode}, {queues} queues")
+    monkeypatch.setenv("GPU_MAX_HW_QUEUES", queues)
+    R = ptmi.Renderer(scene, cam)  # the count of frames in flight is fixed here
+    monkeypatch.setenv("GPU_MAX_HW_QUEUES", "4")
+    R4 = ptmi.Renderer(scene, cam)
     kw = dict(mode=mode, spp=2, max_depth=6, rr_start=3, tail_threshold=300 if mode == "wave" else 0,
               tail_bounce=4 if mode == "wave" else 0)
+    # three or five frame slots
+    assert _frames_ws(R, **kw) * 3 == _frames_ws(R4, **kw) * (5 if queues == "8" else 3)
     acc_seq = torch.zeros((40, 64, 3), dtype=torch.float32, device="cuda")
     for f in range(5):
         img_seq = R.render(accum=acc_seq, frame=3 + f, **kw).clone()
-    # continue the same running average both ways from frame 8
+    # continue the same running average both ways from frame 8, over more
+    # frames than there are slots
     acc_pipe = acc_seq.clone()
     acc_seq2 = acc_seq.clone()
-    for f in range(5):
+    for f in range(7):
         R.render(accum=acc_seq2, frame=8 + f, **kw)
-    img_pipe = R.render_frames(5, accum=acc_pipe, frame=8, **kw)
+    img_pipe = R.render_frames(7, accum=acc_pipe, frame=8, **kw)
     torch.cuda.synchronize()
     assert torch.equal(acc_pipe.view(torch.int32), acc_seq2.view(torch.int32))
-    img_last = R.render(frame=12, **kw)
+    img_last = R.render(frame=14, **kw)
     assert torch.equal(img_pipe.view(torch.int32), img_last.view(torch.int32))
     # one frame through the pipelined entry point equals a plain frame
     one = R.render_frames(1, frame=0, **kw).clone()
