@@ -9,7 +9,7 @@ One step = one frame of the wavefront pipeline (raygen, extend, shade,
 shadow, accumulate over all bounces).  Inputs are resident in device memory
 before timing starts.  Prints one JSON line.
 
-Besides the headline (the wavefront with the hybrid tail, three frames in
+Besides the headline (the wavefront with the hybrid tail, five frames in
 flight) the line carries: the pure wavefront (every bounce a separate
 extend / shade / shadow launch over compacted queues) and the megakernel,
 frame by frame and in flight; compaction against no compaction at depth 8
@@ -50,7 +50,8 @@ FP32_PEAK_PACKED_TFLOPS = 157.3
 FLOPS_PER_NODE = 80
 FLOPS_PER_TRI = 40
 # the launch parameters the autotuner chose on MI355X for the wavefront with
-# three frames in flight and for the megakernel; the stage profile, the
+# three frames in flight and for the megakernel (kept so that profiles stay
+# comparable across changes); the stage profile, the
 # rooflines and the committed rocprofv3 profiles use them (bench.py --fixed)
 FIXED_PARAMS = {"wave": {"block": 256, "grid_mult": 4, "stack_lds": 8, "tail_threshold": 1 << 18, "tail_bounce": 3},
                 "mega": {"block": 256, "grid_mult": 4, "stack_lds": 8, "mega_waves": 5}}
@@ -286,7 +287,7 @@ def main():
         raise SystemExit(f"unknown schedule list {args.schedules!r}")
     modes = (["wave"] if any(x.startswith("wave") for x in schedules) else []) + (["mega"] if "mega" in schedules else [])
 
-    # launch parameters per schedule, frame by frame and three frames in flight
+    # launch parameters per schedule, frame by frame and with frames in flight
     tuned = {}
     for mode in modes:
         if args.params:
@@ -584,7 +585,7 @@ def divergence_bench(args, torch, ptmi, scenes, frames=None, summary=False):
     dielectric, emissive), 1920x1080, 4 spp, depth 16, roulette from 3:
     megakernel, wavefront (hybrid and pure), wavefront with the material
     sort and with the ray sort, and the hybrid wavefront and the megakernel
-    with three frames in flight."""
+    with frames in flight."""
     t0 = time.perf_counter()
     scene, cam = scenes.procedural(seed=3, n_objects=20000, width=W, height=H, material_mode="divergence")
     nt = scene["indices"].shape[0]

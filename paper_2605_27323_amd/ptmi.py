@@ -330,8 +330,9 @@ class Renderer(Context):
         return out
 
     def render_frames(self, n_frames, out=None, accum=None, **kw):
-        """Render frames kw['frame'] .. + n_frames - 1 with three frames in flight
-        (pt_render_frames); returns the image tensor (the last frame's image)."""
+        """Render frames kw['frame'] .. + n_frames - 1 with frames in flight
+        (pt_render_frames: three, or five when the process has eight hardware
+        queues); returns the image tensor (the last frame's image)."""
         import torch
         a = self.args(**kw)
         if out is None:

@@ -4,7 +4,7 @@ benchmark times, on outputs the oracle computes one by one:
 * divergence workload (~10M triangles, 64 material ids with rough
   dielectrics and emitters, 1920x1080, 4 spp, depth 16, roulette from 3):
   sampled pixels of the megakernel and the wavefront (frame by frame, with
-  the material and ray sorts, three frames in flight) against the oracle;
+  the material and ray sorts, frames in flight) against the oracle;
 * adjoint workload (the 1M-triangle scene at 512x512, 8 spp, depth 6):
   the gradient of an image loss that weights sampled pixels only, against
   the oracle's binary64 adjoint over those pixels;

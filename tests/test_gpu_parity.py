@@ -116,7 +116,7 @@ def test_full_size_procedural_sampled_pixels():
         ref, frag = S.render(cam, pixels=px, **cfg)
         assert_parity(wave.reshape(-1, 3)[px], ref, frag, what=f"1M frame {frame}")
         # the launch configurations the benchmark times: frame by frame, and
-        # three frames in flight (the last frame of a run ending at `frame`)
+        # frames in flight (the last frame of a run ending at `frame`)
         tuned = R.render(mode="wave", block=256, grid_mult=8, stack_lds=8, tail_threshold=1 << 18, tail_bounce=4,
                          **cfg)
         assert np.array_equal(tuned.cpu().numpy().view(np.uint32), wave.view(np.uint32))
