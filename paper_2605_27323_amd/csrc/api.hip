@@ -94,6 +94,11 @@ struct pt_ctx {
     int in_flight = 3;  // frames in flight (set at creation)
     hipStream_t aux[kMaxInFlight] = {};
     hipEvent_t ev_entry = nullptr, ev_stage[kMaxInFlight] = {}, ev_acc[kMaxInFlight] = {};
+    // a single wavefront frame: the side stream that runs each bounce's
+    // shadow stage beside the next extend stage, and its fork / join events
+    // (two per bounce), created on first use
+    hipStream_t side = nullptr;
+    std::vector<hipEvent_t> side_ev;
     uint32_t* last_counts = nullptr;
     unsigned long long* last_trav = nullptr;
     int last_ncounts = 0, last_D = 0, last_kind = 0;  // kind: 0 megakernel, 1 wavefront, 2 adjoint
@@ -145,7 +150,7 @@ pt_status launch_config(const pt_ctx* c, const pt_render_args* a, Launch& L) {
 }
 
 struct WsLayout {
-    size_t counts, trav, ovf, adj, rec_hit, rec_vis, wave[11], sort_key, perm, hist, total;
+    size_t counts, trav, ovf, ovf2, adj, rec_hit, rec_vis, wave[11], sort_key, perm, hist, total;
     int ncounts;
 };
 constexpr int kTravWords = 16;  // 8 u64 traversal work counters
@@ -167,6 +172,11 @@ WsLayout layout(const pt_ctx* c, const pt_render_args* a, const Launch& L, bool 
     off = align_up(off + sizeof(uint32_t) * kTravWords);
     w.ovf = off;
     off = align_up(off + sizeof(uint2) * (size_t)L.gcap * L.nlanes);
+    // the wavefront's shadow stage runs beside the next extend stage (on the
+    // context's side stream) and spills its stacks to an area of its own
+    const bool wave_mode = a->mode == PT_MODE_WAVE;
+    w.ovf2 = off;
+    if (wave_mode) off = align_up(off + sizeof(uint2) * (size_t)L.gcap * L.nlanes);
     // the adjoint's two path cursors and replay B's counters (one aligned
     // block), then the per-path radiance when replay A runs as the
     // megakernel-style kernel (as the wavefront it is the wavefront's
@@ -269,9 +279,27 @@ size_t frame_slot_bytes(const pt_ctx* c, const WsLayout& w) {
 // Enqueue one frame on stream s, except the wavefront's accumulate (its
 // radiance buffer is returned in *Lbuf): counters, then the megakernel
 // (writing img / acc) or raygen and the bounce stages.
+// The side stream of a context and at least nev fork / join events.
+pt_status side_stream(pt_ctx* c, int nev, hipStream_t& out) {
+    if (!c->side) PT_HIP(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking), "create stream");
+    while ((int)c->side_ev.size() < nev) {
+        hipEvent_t e = nullptr;
+        PT_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming), "create event");
+        c->side_ev.push_back(e);
+    }
+    out = c->side;
+    return PT_OK;
+}
+
+// Enqueue one frame's kernels on stream s.  With s2 (the wavefront only),
+// each bounce's shadow stage runs on s2, beside the next bounce's extend
+// stage on s: they read and write disjoint buffers (the shadow records and
+// the path radiance, the next rays and their hits), and the next shade
+// stage, which adds to the radiance and overwrites the shadow records,
+// waits for it.  The image is the same bit for bit.
 pt_status enqueue_stages(pt_ctx* c, const pt_render_args* a, const Launch& L, const WsLayout& w, char* base,
                          hipStream_t s, float* img, float* acc, bool prof, const float4** Lbuf,
-                         const VertexRecs* rec = nullptr) {
+                         const VertexRecs* rec = nullptr, hipStream_t s2 = nullptr) {
     uint32_t* counts = reinterpret_cast<uint32_t*>(base + w.counts);
     unsigned long long* trav = reinterpret_cast<unsigned long long*>(base + w.trav);
     uint2* ovf = reinterpret_cast<uint2*>(base + w.ovf);
@@ -321,6 +349,9 @@ pt_status enqueue_stages(pt_ctx* c, const pt_render_args* a, const Launch& L, co
         PT_HIP(launch_init_counts(s, counts, w.ncounts, npaths), "init counters");
         if (sort || rsort) PT_HIP(launch_init_counts(s, wb.hist, 2 * kSortBins + 1, 0u), "init sort histogram");
         PT_HIP(timed(c, prof, 0, s, [&] { return launch_raygen(grid, block, s, c->cam, pp, wb); }), "raygen");
+        uint2* ovf2 = reinterpret_cast<uint2*>(base + w.ovf2);
+        const bool fork = s2 != nullptr && a->nee && compact;
+        int pend = -1;  // bounce whose shadow stage runs on s2, not yet joined
         int64_t promotes = 0;
         if (wb.two_slot) {
             PT_HIP(timed(c, prof, 10, s, [&] { return launch_promote(s, wb, -1); }), "promote");
@@ -336,6 +367,10 @@ pt_status enqueue_stages(pt_ctx* c, const pt_render_args* a, const Launch& L, co
             // (threshold above any queue size); later bounces have nothing
             const bool last = compact && a->tail_bounce > 0 && b == a->tail_bounce;
             const uint32_t tail = last ? 0xFFFFFFFFu : a->tail_threshold;
+            if (pend >= 0) {
+                PT_HIP(hipStreamWaitEvent(s, c->side_ev[2 * pend + 1], 0), "join shadow stage");
+                pend = -1;
+            }
             PT_HIP(timed(c, prof, 2, s, [&] { return launch_shade(grid, block, s, c->view, pp, wb, b, compact, sort, tail); }), "shade");
             if (compact && tail)
                 PT_HIP(timed(c, prof, 8, s, [&] {
@@ -348,9 +383,19 @@ pt_status enqueue_stages(pt_ctx* c, const pt_render_args* a, const Launch& L, co
                 PT_HIP(timed(c, prof, 10, s, [&] { return launch_promote(s, wb, b); }), "promote");
                 ++promotes;
             }
-            if (b < a->max_depth && a->nee)
-                PT_HIP(timed(c, prof, 3, s, [&] { return launch_shadow(L.lds, count, grid, block, s, c->view, wb, b, ovf, L.gcap, xcd); }), "shadow");
+            if (b < a->max_depth && a->nee) {
+                if (fork) {
+                    PT_HIP(hipEventRecord(c->side_ev[2 * b], s), "fork shadow stage");
+                    PT_HIP(hipStreamWaitEvent(s2, c->side_ev[2 * b], 0), "fork shadow stage");
+                    PT_HIP(timed(c, prof, 3, s2, [&] { return launch_shadow(L.lds, count, grid, block, s2, c->view, wb, b, ovf2, L.gcap, xcd); }), "shadow");
+                    PT_HIP(hipEventRecord(c->side_ev[2 * b + 1], s2), "join shadow stage");
+                    pend = b;
+                } else {
+                    PT_HIP(timed(c, prof, 3, s, [&] { return launch_shadow(L.lds, count, grid, block, s, c->view, wb, b, ovf, L.gcap, xcd); }), "shadow");
+                }
+            }
         }
+        if (pend >= 0) PT_HIP(hipStreamWaitEvent(s, c->side_ev[2 * pend + 1], 0), "join shadow stage");
         *Lbuf = wb.L;
         remember_frame(c, a, counts, w.ncounts, 1, acc != nullptr, promotes);
     }
@@ -455,6 +500,8 @@ pt_status pt_destroy(pt_ctx* c) {
             }
             (void)hipEventDestroy(c->ev_entry);
         }
+        for (hipEvent_t e : c->side_ev) (void)hipEventDestroy(e);
+        if (c->side) (void)hipStreamDestroy(c->side);
     }
     delete c;
     return PT_OK;
@@ -760,7 +807,12 @@ pt_status pt_render_frame(pt_ctx* c, const pt_render_args* a, float* img, float*
     c->timers.clear();
     c->event_next = 0;
     const float4* Lbuf = nullptr;
-    st = enqueue_stages(c, a, L, w, static_cast<char*>(ws), s, img, acc, prof, &Lbuf);
+    hipStream_t s2 = nullptr;
+    if (a->mode == PT_MODE_WAVE) {
+        st = side_stream(c, 2 * (a->max_depth + 1), s2);
+        if (st) return st;
+    }
+    st = enqueue_stages(c, a, L, w, static_cast<char*>(ws), s, img, acc, prof, &Lbuf, nullptr, s2);
     if (st) return st;
     if (a->mode == PT_MODE_WAVE) {
         PathParams pp{a->spp, a->max_depth, a->nee ? 1 : 0, a->rr_start, a->seed, a->frame, a->job, a->sampler};
@@ -899,7 +951,10 @@ pt_status pt_render_backward(pt_ctx* c, const pt_render_args* a, const float* d_
         // leave each path's radiance in their per-path buffer; replay B
         // counts its rays in the block after the cursors
         PT_HIP(launch_init_counts(s, reinterpret_cast<uint32_t*>(cursor), 8, 0u), "init path cursors");
-        st = enqueue_stages(c, a, L, w, base, s, nullptr, nullptr, prof, &Lpath, keep ? &rec : nullptr);
+        hipStream_t s2 = nullptr;
+        st = side_stream(c, 2 * (a->max_depth + 1), s2);
+        if (st) return st;
+        st = enqueue_stages(c, a, L, w, base, s, nullptr, nullptr, prof, &Lpath, keep ? &rec : nullptr, s2);
         if (st) return st;
         counts = reinterpret_cast<uint32_t*>(base + w.adj) + 4;
     } else {
@@ -933,6 +988,7 @@ pt_status pt_frame_stats_get(pt_ctx* c, pt_frame_stats* out) {
     // frames in flight ran on the internal streams
     if (c->aux_ready)
         for (int i = 0; i < c->in_flight; ++i) PT_HIP(hipStreamSynchronize(c->aux[i]), "stream sync");
+    if (c->side) PT_HIP(hipStreamSynchronize(c->side), "stream sync");
     for (const StageTimer& t : c->timers) {
         PT_HIP(hipEventSynchronize(t.b), "event sync");
         float ms = 0.f;
