@@ -294,7 +294,8 @@ pt_status pt_set_camera(pt_ctx* ctx, const pt_camera* camera);
 
 /* Device workspace (bytes) a render with these arguments needs, for the
  * camera currently set: wavefront path state, queues and counters, and
- * the traversal stack overflow area. */
+ * the traversal stack overflow area (two of them in PT_MODE_WAVE: the
+ * shadow stage has its own). */
 pt_status pt_workspace_size(pt_ctx* ctx, const pt_render_args* args, uint64_t* bytes);
 
 /* Render one frame (paper Sec. 2.2 megakernel / Sec. 2.3 wavefront).
@@ -302,7 +303,12 @@ pt_status pt_workspace_size(pt_ctx* ctx, const pt_render_args* args, uint64_t* b
  * accum_inout (may be NULL): float[H][W][3] device running average
  * (paper Sec. 2.3 accumulation): frame 0 stores the frame, frame n > 0
  * stores acc + (I - acc) / (n + 1).
- * workspace: device memory of at least pt_workspace_size bytes. */
+ * workspace: device memory of at least pt_workspace_size bytes.
+ * In PT_MODE_WAVE each bounce's shadow stage runs on an internal stream
+ * of the context (default priority, created on first use), forked from
+ * `stream` after the shade stage and joined before the next one; the
+ * call's results are complete when `stream` reaches its end, and the
+ * image is the same bit for bit as with every stage on `stream`. */
 pt_status pt_render_frame(pt_ctx* ctx, const pt_render_args* args, float* image_out,
                           float* accum_inout, void* workspace, uint64_t workspace_bytes,
                           void* stream);
