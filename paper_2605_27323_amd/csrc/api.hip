@@ -350,7 +350,7 @@ pt_status enqueue_stages(pt_ctx* c, const pt_render_args* a, const Launch& L, co
         if (sort || rsort) PT_HIP(launch_init_counts(s, wb.hist, 2 * kSortBins + 1, 0u), "init sort histogram");
         PT_HIP(timed(c, prof, 0, s, [&] { return launch_raygen(grid, block, s, c->cam, pp, wb); }), "raygen");
         uint2* ovf2 = reinterpret_cast<uint2*>(base + w.ovf2);
-        const bool fork = s2 != nullptr && a->nee && compact;
+        const bool fork = s2 != nullptr && a->nee;
         int pend = -1;  // bounce whose shadow stage runs on s2, not yet joined
         int64_t promotes = 0;
         if (wb.two_slot) {
