@@ -59,7 +59,12 @@ FIXED_PARAMS = {"wave": {"block": 256, "grid_mult": 4, "stack_lds": 8, "tail_thr
 # MI355X): the radiance replay as one kernel, or as the wavefront stages with
 # the hybrid tail from bounce 4
 ADJOINT_PARAMS = {"mega": {"block": 256, "grid_mult": 8, "stack_lds": 8},
-                  "wave": {"block": 256, "grid_mult": 8, "stack_lds": 8, "tail_threshold": 1 << 18, "tail_bounce": 4}}
+                  "wave": {"block": 256, "grid_mult": 8, "stack_lds": 8, "tail_threshold": 1 << 18, "tail_bounce": 4},
+                  # with kept intersections the first replay's extend and
+                  # shadow stages, which run side by side, do best on half
+                  # the lanes each (5.98 against 6.09 ms at grid_mult 8)
+                  "wave_keep": {"block": 256, "grid_mult": 4, "stack_lds": 8, "tail_threshold": 1 << 18,
+                                "tail_bounce": 4}}
 # the pure wavefront: no hybrid tail, every bounce in separate stage launches
 PURE = {"tail_threshold": 0, "tail_bounce": 0, "tail_spread": False}
 # launch parameters of the divergence workload (4 spp, depth 16)
@@ -653,7 +658,7 @@ def adjoint_bench(ptmi, scene, torch, args, prof, copy_gbs, roof):
                     "replay_a_wavefront": dict(ADJOINT_PARAMS["wave"], mode="wave"),
                     "replay_a_megakernel_keep_hits": dict(ADJOINT_PARAMS["mega"], mode="mega",
                                                           flags=ptmi.FLAG_KEEP_HITS),
-                    "replay_a_wavefront_keep_hits": dict(ADJOINT_PARAMS["wave"], mode="wave",
+                    "replay_a_wavefront_keep_hits": dict(ADJOINT_PARAMS["wave_keep"], mode="wave",
                                                          flags=ptmi.FLAG_KEEP_HITS)}
         pick = args.adjoint_replay.split(",")
         variants = {n: p for n, p in variants.items()
