@@ -9,7 +9,7 @@ One step = one frame of the wavefront pipeline (raygen, extend, shade,
 shadow, accumulate over all bounces).  Inputs are resident in device memory
 before timing starts.  Prints one JSON line.
 
-Besides the headline (the wavefront with the hybrid tail, five frames in
+Besides the headline (the wavefront with the hybrid tail, six frames in
 flight) the line carries: the pure wavefront (every bounce a separate
 extend / shade / shadow launch over compacted queues) and the megakernel,
 frame by frame and in flight; compaction against no compaction at depth 8
@@ -26,9 +26,9 @@ import sys
 import time
 
 # At least eight hardware queues for this process (HIP's default is four),
-# read when HIP first initialises: the library then keeps five frames in
-# flight, one stream each, plus the caller's stream, and a batch four pools,
-# without sharing queues.
+# read when HIP first initialises: the library then keeps six frames in
+# flight, one stream each, beside the caller's stream, and a batch four
+# pools, without sharing queues.
 if int(os.environ.get("GPU_MAX_HW_QUEUES", "4") or "4") < 8:
     os.environ["GPU_MAX_HW_QUEUES"] = "8"
 

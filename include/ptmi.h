@@ -336,10 +336,10 @@ pt_status pt_render_frame_noalloc(pt_ctx* ctx, const pt_render_args* args, float
  * (default priority, created on first use) while the frames before it
  * finish on the others, so that the short last bounces of one frame overlap
  * the first bounces of the next; the per-frame accumulation runs on
- * `stream` in frame order.  F is fixed when the context is created: one
+ * `stream` in frame order.  F is fixed when the context is created: two
  * less than the hardware queues HIP gives the process (the environment
  * variable GPU_MAX_HW_QUEUES, 4 when unset; it must be set before the
- * process first uses HIP to take effect), between 3 and 5.  Work enqueued on `stream` before the call precedes every
+ * process first uses HIP to take effect), between 3 and 6.  Work enqueued on `stream` before the call precedes every
  * frame; the call's results are complete when `stream` reaches its end.
  * image_out receives each frame's image in turn (the last one remains);
  * accum_inout (may be NULL) is updated as by n_frames calls of
