@@ -9,7 +9,7 @@ One step = one frame of the wavefront pipeline (raygen, extend, shade,
 shadow, accumulate over all bounces).  Inputs are resident in device memory
 before timing starts.  Prints one JSON line.
 
-Besides the headline (the wavefront with the hybrid tail, six frames in
+Besides the headline (the wavefront with the hybrid tail, eight frames in
 flight) the line carries: the pure wavefront (every bounce a separate
 extend / shade / shadow launch over compacted queues) and the megakernel,
 frame by frame and in flight; compaction against no compaction at depth 8
@@ -25,12 +25,12 @@ import platform
 import sys
 import time
 
-# At least eight hardware queues for this process (HIP's default is four),
-# read when HIP first initialises: the library then keeps six frames in
+# At least ten hardware queues for this process (HIP's default is four),
+# read when HIP first initialises: the library then keeps eight frames in
 # flight, one stream each, beside the caller's stream, and a batch four
 # pools, without sharing queues.
-if int(os.environ.get("GPU_MAX_HW_QUEUES", "4") or "4") < 8:
-    os.environ["GPU_MAX_HW_QUEUES"] = "8"
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "4") or "4") < 10:
+    os.environ["GPU_MAX_HW_QUEUES"] = "10"
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -71,7 +71,7 @@ PURE = {"tail_threshold": 0, "tail_bounce": 0, "tail_spread": False}
 DIVERGENCE_PARAMS = {"wave": {"block": 256, "grid_mult": 8, "stack_lds": 8, "tail_threshold": 1 << 18, "tail_bounce": 6},
                      "mega": {"block": 256, "grid_mult": 4, "stack_lds": 8}}
 # batch options for the 64-job workload (measured on MI355X; four pools need
-# the eight hardware queues set above)
+# more than the default four hardware queues, set above)
 BATCH_OPTS = {"pool_capacity": 1 << 23, "block": 256, "grid_mult": 8, "stack_lds": 8, "pools": 4}
 W, H, SPP, DEPTH, RR = 1920, 1080, 1, 8, 3
 PROFILE = "procedural1M_1080p"

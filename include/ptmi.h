@@ -339,7 +339,7 @@ pt_status pt_render_frame_noalloc(pt_ctx* ctx, const pt_render_args* args, float
  * `stream` in frame order.  F is fixed when the context is created: two
  * less than the hardware queues HIP gives the process (the environment
  * variable GPU_MAX_HW_QUEUES, 4 when unset; it must be set before the
- * process first uses HIP to take effect), between 3 and 6.  Work enqueued on `stream` before the call precedes every
+ * process first uses HIP to take effect), between 3 and 8.  Work enqueued on `stream` before the call precedes every
  * frame; the call's results are complete when `stream` reaches its end.
  * image_out receives each frame's image in turn (the last one remains);
  * accum_inout (may be NULL) is updated as by n_frames calls of

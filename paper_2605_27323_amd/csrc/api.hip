@@ -40,8 +40,8 @@ pt_status hip_fail(hipError_t e, const char* what) {
 // them (4 unless the environment says otherwise), so the count follows that
 // setting, from 3 up to kMaxInFlight.  Sharing queues cost more than the
 // extra frame gained (measured with eight queues: 5 frames 1.61, 6 frames
-// 1.59, 7 frames 1.80 ms per frame).
-constexpr int kMaxInFlight = 6;
+// 1.59, 7 frames 1.80 ms per frame; 8 frames with ten queues 1.57).
+constexpr int kMaxInFlight = 8;
 int frames_in_flight_for_queues() {
     const char* e = std::getenv("GPU_MAX_HW_QUEUES");
     const int q = e && *e ? std::atoi(e) : 4;
