@@ -331,8 +331,8 @@ class Renderer(Context):
 
     def render_frames(self, n_frames, out=None, accum=None, **kw):
         """Render frames kw['frame'] .. + n_frames - 1 with frames in flight
-        (pt_render_frames: three, or five when the process has eight hardware
-        queues); returns the image tensor (the last frame's image)."""
+        (pt_render_frames: three to eight, two less than the process's
+        hardware queues); returns the image tensor (the last frame's image)."""
         import torch
         a = self.args(**kw)
         if out is None:
