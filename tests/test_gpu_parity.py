@@ -281,12 +281,13 @@ def _frames_ws(R, **kw):
     return n.value
 
 
-@pytest.mark.parametrize("queues", ["4", "8"])
+@pytest.mark.parametrize("queues", ["4", "8", "10"])
 @pytest.mark.parametrize("mode", ["wave", "mega"])
 def test_frames_in_flight_match_sequential(mode, queues, monkeypatch):
     """pt_render_frames (three frames in flight on internal streams, six
-    when the process has eight hardware queues) gives the same running
-    average and last image, bit for bit, as frame-by-frame rendering."""
+    when the process has eight hardware queues, eight with ten) gives the
+    same running average and last image, bit for bit, as frame-by-frame
+    rendering."""
     scene, cam = scenes.procedural(seed=52, n_objects=30, width=64, height=40)
     log(f"frames in flight {mode}, {queues} queues")
     monkeypatch.setenv("GPU_MAX_HW_QUEUES", queues)
@@ -295,8 +296,8 @@ def test_frames_in_flight_match_sequential(mode, queues, monkeypatch):
     R4 = ptmi.Renderer(scene, cam)
     kw = dict(mode=mode, spp=2, max_depth=6, rr_start=3, tail_threshold=300 if mode == "wave" else 0,
               tail_bounce=4 if mode == "wave" else 0)
-    # three or six frame slots
-    assert _frames_ws(R, **kw) * 3 == _frames_ws(R4, **kw) * (6 if queues == "8" else 3)
+    # three, six or eight frame slots
+    assert _frames_ws(R, **kw) * 3 == _frames_ws(R4, **kw) * {"4": 3, "8": 6, "10": 8}[queues]
     acc_seq = torch.zeros((40, 64, 3), dtype=torch.float32, device="cuda")
     for f in range(5):
         img_seq = R.render(accum=acc_seq, frame=3 + f, **kw).clone()
@@ -304,12 +305,12 @@ def test_frames_in_flight_match_sequential(mode, queues, monkeypatch):
     # frames than there are slots
     acc_pipe = acc_seq.clone()
     acc_seq2 = acc_seq.clone()
-    for f in range(7):
+    for f in range(9):
         R.render(accum=acc_seq2, frame=8 + f, **kw)
-    img_pipe = R.render_frames(7, accum=acc_pipe, frame=8, **kw)
+    img_pipe = R.render_frames(9, accum=acc_pipe, frame=8, **kw)
     torch.cuda.synchronize()
     assert torch.equal(acc_pipe.view(torch.int32), acc_seq2.view(torch.int32))
-    img_last = R.render(frame=14, **kw)
+    img_last = R.render(frame=16, **kw)
     assert torch.equal(img_pipe.view(torch.int32), img_last.view(torch.int32))
     # one frame through the pipelined entry point equals a plain frame
     one = R.render_frames(1, frame=0, **kw).clone()
