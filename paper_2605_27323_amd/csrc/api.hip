@@ -278,9 +278,6 @@ size_t frame_slot_bytes(const pt_ctx* c, const WsLayout& w) {
     return align_up(w.total + sizeof(float) * 3 * (size_t)c->cam.W * (size_t)c->cam.H);
 }
 
-// Enqueue one frame on stream s, except the wavefront's accumulate (its
-// radiance buffer is returned in *Lbuf): counters, then the megakernel
-// (writing img / acc) or raygen and the bounce stages.
 // The side stream of a context and at least nev fork / join events.
 pt_status side_stream(pt_ctx* c, int nev, hipStream_t& out) {
     if (!c->side) PT_HIP(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking), "create stream");
@@ -293,11 +290,14 @@ pt_status side_stream(pt_ctx* c, int nev, hipStream_t& out) {
     return PT_OK;
 }
 
-// Enqueue one frame's kernels on stream s.  With s2 (the wavefront only),
-// each bounce's shadow stage runs on s2, beside the next bounce's extend
-// stage on s: they read and write disjoint buffers (the shadow records and
-// the path radiance, the next rays and their hits), and the next shade
-// stage, which adds to the radiance and overwrites the shadow records,
+// Enqueue one frame on stream s, except the wavefront's accumulate (its
+// radiance buffer is returned in *Lbuf): counters, then the megakernel
+// (writing img / acc) or raygen and the bounce stages.  With s2 (the
+// wavefront only), each bounce's shadow stage runs on s2, beside the next
+// bounce's extend stage on s: they read and write disjoint buffers (the
+// shadow records and the path radiance, the next rays and their hits), and
+// the next shade stage, which adds to the radiance and overwrites the
+// shadow records,
 // waits for it.  The image is the same bit for bit.
 pt_status enqueue_stages(pt_ctx* c, const pt_render_args* a, const Launch& L, const WsLayout& w, char* base,
                          hipStream_t s, float* img, float* acc, bool prof, const float4** Lbuf,
