@@ -390,6 +390,14 @@ def main():
                     "measured": r.get("measured"), "stage_share": ws["share"].get("extend"),
                     "dominant_stage": ws["dominant"],
                     "launch_params": dict(FIXED_PARAMS["wave"], **(PURE if hname == "pure" else {}))}
+    # frames the library keeps in flight: its frames workspace in frame slots
+    # (one wavefront workspace and one image each, 256-byte aligned)
+    import ctypes
+    a0 = R.args(mode="wave", spp=SPP, max_depth=DEPTH)
+    n1, nf = ctypes.c_uint64(), ctypes.c_uint64()
+    ptmi.lib().pt_workspace_size(R.h, ctypes.byref(a0), ctypes.byref(n1))
+    ptmi.lib().pt_frames_workspace_size(R.h, ctypes.byref(a0), ctypes.byref(nf))
+    in_flight = int(nf.value // (((n1.value + 12 * W * H) + 255) // 256 * 256))
     out = {
         "metric": "path samples/s wavefront vs megakernel @1080p, 1M tris; adjoint samples/s",
         "value": hv["value"],
@@ -412,8 +420,9 @@ def main():
                                   "launches over compacted queues while they are long, the paths still live at "
                                   "the tail bounce finished megakernel-style in one launch)"
                                   ) +
-                               ", progressive frames with three in flight (bit-identical to frame by frame)",
-                   "width": W, "height": H, "spp": SPP, "max_depth": DEPTH, "triangles": nt},
+                               f", progressive frames with {in_flight} in flight (bit-identical to frame by frame)",
+                   "width": W, "height": H, "spp": SPP, "max_depth": DEPTH, "triangles": nt,
+                   "frames_in_flight": in_flight},
         "schedules": sched,
         "wave_over_mega": ({s: {n: sched["mega"][n]["ms_per_step"] / sched[s][n]["ms_per_step"]
                                 for n in ("frame_by_frame", "frames_in_flight")}
