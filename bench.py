@@ -165,11 +165,18 @@ def time_frames(torch, R, img, k, first, in_flight, **kw):
     return time.perf_counter() - t
 
 
+# set by --serial-stages: wavefront frames rendered one by one run every
+# stage on the render stream (no shadow stage beside the extend stage)
+SERIAL_FLAGS = 0
+
+
 def schedule_run(torch, R, img, params, steps, warmup, kw, mode):
     """Frame-by-frame and in-flight rates of one schedule."""
     out = {"params": params}
     for name, infl in [("frame_by_frame", False), ("frames_in_flight", True)]:
         p = params[name]
+        if not infl and mode == "wave" and SERIAL_FLAGS:
+            p = dict(p, flags=p.get("flags", 0) | SERIAL_FLAGS)
         time_frames(torch, R, img, max(1, warmup), 0, infl, mode=mode, **kw, **p)
         dt = time_frames(torch, R, img, steps, warmup, infl, mode=mode, **kw, **p)
         out[name] = {"ms_per_step": dt * 1e3 / steps, "value": W * H * SPP * steps / dt}
@@ -179,14 +186,17 @@ def schedule_run(torch, R, img, params, steps, warmup, kw, mode):
 def profiled_frames(R, img, ptmi, mode, params, k, first, kw):
     """k frames with per-stage HIP-event timing, then the same k frames with
     the work-counting kernels: stage times, launches, items, algorithmic
-    state bytes, rays, node visits and triangle tests (summed)."""
+    state bytes, rays, node visits and triangle tests (summed).  Wavefront
+    stages run one after another (PT_FLAG_SERIAL_STAGES), so that each
+    kernel's event time is its own."""
     acc = {"stage_ms": {}, "launches": {}, "items": {}, "bytes": {}, "node_visits": {}, "tri_tests": {},
            "extension_rays": 0, "shadow_rays": 0, "frames": k}
+    serial = ptmi.FLAG_SERIAL_STAGES if mode == "wave" else 0
     for flag, keys in [(ptmi.FLAG_PROFILE, ("stage_ms", "launches", "items", "bytes")),
                        (ptmi.FLAG_COUNT_WORK, ("node_visits", "tri_tests"))]:
         for i in range(k):
             p = dict(params)
-            p["flags"] = p.get("flags", 0) | flag
+            p["flags"] = p.get("flags", 0) | flag | serial
             R.render(out=img, mode=mode, frame=first + i, **kw, **p)
             st = R.stats()
             for key in keys:
@@ -233,6 +243,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--serial-stages", action="store_true",
+                    help="wavefront frames rendered one by one run every stage on the render stream (profiled runs "
+                         "take this, so that the profile's kernel times match the rooflines' per-kernel ones)")
     ap.add_argument("--adjoint-replay", default="mega,wave,keep",
                     help="comma-separated schedules of the adjoint's radiance replay: mega, wave, and keep (each "
                          "also keeping the intersections for the gradient replay); profiled runs take mega,keep "
@@ -255,6 +268,7 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
+    global SERIAL_FLAGS
     if args.copy_probe:
         import torch
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -272,6 +286,8 @@ def main():
     import torch
 
     from paper_2605_27323_amd import autotune, profiles, ptmi, scenes
+    if args.serial_stages:
+        SERIAL_FLAGS = ptmi.FLAG_SERIAL_STAGES
 
     if args.batch:
         print(json.dumps(batch_bench(args, torch, ptmi, scenes, autotune)), flush=True)

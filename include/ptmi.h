@@ -79,10 +79,13 @@ enum {
                                   two-slot buffer (current, next) that a one-thread promote kernel
                                   moves over after every bounce, in place of one counter per bounce;
                                   same image bit for bit */
-    PT_FLAG_KEEP_HITS = 128    /* backward: the first replay keeps every path vertex's intersection
+    PT_FLAG_KEEP_HITS = 128,   /* backward: the first replay keeps every path vertex's intersection
                                   and light-sample visibility (9 bytes per vertex and path sample in
                                   the workspace) and the second reads them instead of tracing the
                                   same rays again; same gradients; ignored by forward renders */
+    PT_FLAG_SERIAL_STAGES = 256 /* wavefront frame or backward: every stage on `stream`, the shadow
+                                  stage not beside the next extend stage, so that each kernel's
+                                  event time is its own (per-kernel measurement); same results */
 };
 
 typedef struct pt_ctx pt_ctx;

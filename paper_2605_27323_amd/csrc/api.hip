@@ -214,7 +214,7 @@ pt_status check_args(const pt_ctx* c, const pt_render_args* a) {
     if (!c->bound) return fail(PT_ESTATE, "scene not bound (pt_bind_scene)");
     if (!c->cam_set) return fail(PT_ESTATE, "camera not set (pt_set_camera)");
     if (a->flags & ~(PT_FLAG_PROFILE | PT_FLAG_NO_COMPACT | PT_FLAG_SORT_MATERIAL | PT_FLAG_COUNT_WORK | PT_FLAG_SORT_RAYS |
-                     PT_FLAG_XCD_LOCAL | PT_FLAG_TWO_SLOT | PT_FLAG_KEEP_HITS))
+                     PT_FLAG_XCD_LOCAL | PT_FLAG_TWO_SLOT | PT_FLAG_KEEP_HITS | PT_FLAG_SERIAL_STAGES))
         return fail(PT_EINVAL, "unknown flag");
     if (a->spp < 1 || a->spp > 65536) return fail(PT_EINVAL, "spp must be in [1, 65536]");
     if (a->max_depth < 0 || a->max_depth > 1000) return fail(PT_EINVAL, "max_depth must be in [0, 1000]");
@@ -810,7 +810,7 @@ pt_status pt_render_frame(pt_ctx* c, const pt_render_args* a, float* img, float*
     c->event_next = 0;
     const float4* Lbuf = nullptr;
     hipStream_t s2 = nullptr;
-    if (a->mode == PT_MODE_WAVE) {
+    if (a->mode == PT_MODE_WAVE && !(a->flags & PT_FLAG_SERIAL_STAGES)) {
         st = side_stream(c, 2 * (a->max_depth + 1), s2);
         if (st) return st;
     }
@@ -954,8 +954,10 @@ pt_status pt_render_backward(pt_ctx* c, const pt_render_args* a, const float* d_
         // counts its rays in the block after the cursors
         PT_HIP(launch_init_counts(s, reinterpret_cast<uint32_t*>(cursor), 8, 0u), "init path cursors");
         hipStream_t s2 = nullptr;
-        st = side_stream(c, 2 * (a->max_depth + 1), s2);
-        if (st) return st;
+        if (!(a->flags & PT_FLAG_SERIAL_STAGES)) {
+            st = side_stream(c, 2 * (a->max_depth + 1), s2);
+            if (st) return st;
+        }
         st = enqueue_stages(c, a, L, w, base, s, nullptr, nullptr, prof, &Lpath, keep ? &rec : nullptr, s2);
         if (st) return st;
         counts = reinterpret_cast<uint32_t*>(base + w.adj) + 4;

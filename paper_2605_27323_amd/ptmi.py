@@ -21,6 +21,7 @@ FLAG_PROFILE, FLAG_NO_COMPACT, FLAG_SORT_MATERIAL, FLAG_COUNT_WORK, FLAG_SORT_RA
 FLAG_XCD_LOCAL = 32
 FLAG_TWO_SLOT = 64
 FLAG_KEEP_HITS = 128
+FLAG_SERIAL_STAGES = 256
 SAMPLER_PHILOX, SAMPLER_HALTON = 0, 1
 STAGES = ["raygen", "extend", "shade", "shadow", "accumulate", "mega", "sort", "adjoint", "tail",
           "adjoint_radiance", "promote"]

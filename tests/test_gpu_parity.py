@@ -379,3 +379,22 @@ def test_two_slot_count_buffer_bit_identical():
     R.render_frames(4, out=out_b, mode="wave", flags=T, **cfg)
     torch.cuda.synchronize()
     assert torch.equal(out_a, out_b)
+
+
+def test_serial_stages_bit_identical():
+    # every stage on the render stream (PT_FLAG_SERIAL_STAGES) against the
+    # shadow stage beside the next extend stage: same image and ray counts,
+    # with and without compaction and the hybrid tail
+    scene, cam = scenes.procedural(seed=43, n_objects=30, width=64, height=40)
+    log("serial stages")
+    R = ptmi.Renderer(scene, cam)
+    cfg = dict(spp=2, max_depth=6, rr_start=2, seed=5)
+    S = ptmi.FLAG_SERIAL_STAGES
+    for kw in (dict(), dict(flags=ptmi.FLAG_NO_COMPACT), dict(tail_bounce=3, tail_threshold=300)):
+        flags = kw.pop("flags", 0)
+        ref = R.render(mode="wave", flags=flags | S, **kw, **cfg).cpu().numpy()
+        st_ref = R.stats()
+        img = R.render(mode="wave", flags=flags, **kw, **cfg).cpu().numpy()
+        st = R.stats()
+        assert np.array_equal(img.view(np.uint32), ref.view(np.uint32)), kw
+        assert st["extension_rays"] == st_ref["extension_rays"] and st["shadow_rays"] == st_ref["shadow_rays"], kw
